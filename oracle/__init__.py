@@ -1,0 +1,289 @@
+"""CPU oracle for the 3DGS SH BC1/BC7 coding path -- TEST INFRASTRUCTURE ONLY.
+
+Plain, slow, obviously-correct reference implementation (``gsbc_oracle.c``)
+of every step of the path, wrapped for numpy.  Only the test suite, the smoke
+check and the CPU-baseline leg of the benchmark may import it; the GPU library
+never does, and this package imports nothing from the GPU library.
+
+Steps (see the C file for the definitions and paper sections):
+  band_range / pos_aabb / quantise   -- Q (Sec. V-A)
+  keys                               -- K (Sec. III-C, Fig. Bit4Scan)
+  sort                               -- S (Sec. III-C)
+  pack                               -- B (Fig. SetupD, Fig. ZigZagScan)
+  bc1_decode / bc7_decode            -- D1 / D2 (BC formats, Sec. III-B)
+  bc1_encode / bc7_encode            -- E1 / E2 (BTC, Sec. III-A)
+  rate_select / encode_auto          -- R (Sec. IV-B)
+  sh_basis / decode_eval             -- H (Sec. II colour equation), FP64
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+FMT_BC1 = 1
+FMT_BC7 = 7
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        _lib = ctypes.CDLL(_LIB_PATH)
+        u64, u32, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+        P = ctypes.c_void_p
+        sig = {
+            "ref_band_range": (None, [P, u64, P, P]),
+            "ref_pos_aabb": (None, [P, u64, P, P]),
+            "ref_quantise": (None, [P, u64, P, P, P]),
+            "ref_morton_rgb": (u32, [u32, u32, u32]),
+            "ref_morton3": (u32, [u32, u32, u32, u32]),
+            "ref_keys": (None, [P, P, u64, u32, P, P, P]),
+            "ref_sort": (None, [P, u64, P]),
+            "ref_zigzag_texel": (u32, [u32]),
+            "ref_pack": (None, [P, P, u64, P]),
+            "ref_bc1_decode_block": (None, [P, P]),
+            "ref_bc7_decode_block": (None, [P, P]),
+            "ref_bc1_encode_block": (u32, [P, u32, P]),
+            "ref_bc7_encode_block": (u32, [P, u32, P]),
+            "ref_bc7_candidate": (i32, [i32, P, P, P, P]),
+            "ref_init": (None, []),
+            "ref_bc1_encode": (None, [P, u64, u32, P, P]),
+            "ref_bc7_encode": (None, [P, u64, u32, P, P]),
+            "ref_bc1_decode": (None, [P, u64, P]),
+            "ref_bc7_decode": (None, [P, u64, P]),
+            "ref_rate_select": (i32, [P, P, P, P, ctypes.c_double, P]),
+            "ref_sh_basis": (None, [ctypes.c_double] * 3 + [P]),
+            "ref_decode_eval": (None, [P, P, P, P, P, P, u32, P, u64, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(_lib, name)
+            f.restype = res
+            f.argtypes = args
+    return _lib
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def set_threads(n):
+    """Threads used by the block-parallel loops (OpenMP)."""
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+    except OSError:
+        pass
+
+
+# ---------------------------------------------------------------- Q, K, S, B
+def band_range(sh):
+    sh = _c(sh, np.float32)
+    n = sh.shape[0]
+    vmin = np.empty(16, np.float32)
+    vmax = np.empty(16, np.float32)
+    _load().ref_band_range(_p(sh), n, _p(vmin), _p(vmax))
+    return vmin, vmax
+
+
+def pos_aabb(pos):
+    pos = _c(pos, np.float32)
+    lo = np.empty(3, np.float32)
+    hi = np.empty(3, np.float32)
+    _load().ref_pos_aabb(_p(pos), pos.shape[0], _p(lo), _p(hi))
+    return lo, hi
+
+
+def quantise(sh, vmin, vmax):
+    sh = _c(sh, np.float32)
+    q = np.empty((sh.shape[0], 16, 3), np.uint8)
+    _load().ref_quantise(_p(sh), sh.shape[0], _p(_c(vmin, np.float32)), _p(_c(vmax, np.float32)), _p(q))
+    return q
+
+
+def morton_rgb(r, g, b):
+    return int(_load().ref_morton_rgb(int(r), int(g), int(b)))
+
+
+def zigzag_texel(j):
+    return int(_load().ref_zigzag_texel(int(j)))
+
+
+def keys(pos, q, grid_bits, lo, hi):
+    pos = _c(pos, np.float32)
+    q = _c(q, np.uint8)
+    out = np.empty(pos.shape[0], np.uint64)
+    _load().ref_keys(_p(pos), _p(q), pos.shape[0], int(grid_bits), _p(_c(lo, np.float32)),
+                     _p(_c(hi, np.float32)), _p(out))
+    return out
+
+
+def sort(k):
+    k = _c(k, np.uint64)
+    perm = np.empty(k.shape[0], np.uint32)
+    _load().ref_sort(_p(k), k.shape[0], _p(perm))
+    return perm
+
+
+def pack(q, perm):
+    q = _c(q, np.uint8)
+    perm = _c(perm, np.uint32)
+    n = perm.shape[0]
+    nblk = (n + 15) // 16
+    tex = np.empty((16, nblk, 16, 4), np.uint8)
+    _load().ref_pack(_p(q), _p(perm), n, _p(tex))
+    return tex
+
+
+def reorder(pos, sh, grid_bits=3):
+    """Q + K + S + B.  Returns (perm, textures[16][nblk][16][4], vmin, vmax)."""
+    vmin, vmax = band_range(sh)
+    lo, hi = pos_aabb(pos)
+    q = quantise(sh, vmin, vmax)
+    k = keys(pos, q, grid_bits, lo, hi)
+    perm = sort(k)
+    return perm, pack(q, perm), vmin, vmax
+
+
+# ---------------------------------------------------------------- D, E
+def bc1_decode(blocks):
+    blocks = _c(blocks, np.uint8).reshape(-1, 8)
+    out = np.empty((blocks.shape[0], 16, 4), np.uint8)
+    _load().ref_bc1_decode(_p(blocks), blocks.shape[0], _p(out))
+    return out
+
+
+def bc7_decode(blocks):
+    blocks = _c(blocks, np.uint8).reshape(-1, 16)
+    out = np.empty((blocks.shape[0], 16, 4), np.uint8)
+    _load().ref_bc7_decode(_p(blocks), blocks.shape[0], _p(out))
+    return out
+
+
+def bc1_encode(tex, refine_steps=2):
+    """tex uint8[nblk][16][4] -> (blocks uint8[nblk][8], sse uint32[nblk])."""
+    tex = _c(tex, np.uint8).reshape(-1, 16, 4)
+    nb = tex.shape[0]
+    blocks = np.empty((nb, 8), np.uint8)
+    sse = np.empty(nb, np.uint32)
+    _load().ref_bc1_encode(_p(tex), nb, int(refine_steps), _p(blocks), _p(sse))
+    return blocks, sse
+
+
+def bc7_encode(tex, mode_mask=0xFF):
+    """tex uint8[nblk][16][4] -> (blocks uint8[nblk][16], sse uint32[nblk])."""
+    tex = _c(tex, np.uint8).reshape(-1, 16, 4)
+    nb = tex.shape[0]
+    blocks = np.empty((nb, 16), np.uint8)
+    sse = np.empty(nb, np.uint32)
+    _load().ref_bc7_encode(_p(tex), nb, int(mode_mask), _p(blocks), _p(sse))
+    return blocks, sse
+
+
+def bc7_candidate(ci):
+    m, p, r, s = (ctypes.c_int() for _ in range(4))
+    rc = _load().ref_bc7_candidate(int(ci), ctypes.byref(m), ctypes.byref(p), ctypes.byref(r), ctypes.byref(s))
+    if rc != 0:
+        raise IndexError(ci)
+    return m.value, p.value, r.value, s.value
+
+
+# ---------------------------------------------------------------- R
+def rate_select(sse1, sse7, vmin, vmax, rate):
+    """Per-band formats (uint8[16], 1 or 7) or None when the rate is infeasible."""
+    fmt = np.empty(16, np.uint8)
+    rc = _load().ref_rate_select(_p(_c(sse1, np.int64)), _p(_c(sse7, np.int64)),
+                                 _p(_c(vmin, np.float32)), _p(_c(vmax, np.float32)),
+                                 float(rate), _p(fmt))
+    return None if rc != 0 else fmt
+
+
+def stream_layout(fmt, nblk):
+    """Byte offset of each band stream in the concatenated payload (bands in order,
+    each stream 16-byte aligned) and the total payload size."""
+    off = np.zeros(16, np.uint64)
+    pos = 0
+    for b in range(16):
+        off[b] = pos
+        pos += nblk * (8 if int(fmt[b]) == FMT_BC1 else 16)
+        pos = (pos + 15) // 16 * 16
+    return off, pos
+
+
+def encode(tex, fmt, refine_steps=2, mode_mask=0xFF):
+    """Encode every band of tex[16][nblk][16][4] in the given per-band formats;
+    returns (payload uint8[], offsets uint64[16], sse int64[16])."""
+    tex = _c(tex, np.uint8)
+    nblk = tex.shape[1]
+    off, total = stream_layout(fmt, nblk)
+    payload = np.zeros(total, np.uint8)
+    sse = np.zeros(16, np.int64)
+    for b in range(16):
+        if int(fmt[b]) == FMT_BC1:
+            blk, s = bc1_encode(tex[b], refine_steps)
+        else:
+            blk, s = bc7_encode(tex[b], mode_mask)
+        o = int(off[b])
+        payload[o:o + blk.size] = blk.reshape(-1)
+        sse[b] = int(s.astype(np.int64).sum())
+    return payload, off, sse
+
+
+def encode_auto(tex, vmin, vmax, rate, refine_steps=2, mode_mask=0xFF):
+    """Rate-controlled encode: band 0 BC7; bands 1..15 encoded in both formats,
+    the k = 4R - 17 largest-gain bands kept in BC7.  Returns
+    (payload, offsets, formats) or None when infeasible."""
+    tex = _c(tex, np.uint8)
+    sse1 = np.zeros(16, np.int64)
+    sse7 = np.zeros(16, np.int64)
+    for b in range(1, 16):
+        sse1[b] = int(bc1_encode(tex[b], refine_steps)[1].astype(np.int64).sum())
+    for b in range(16):
+        sse7[b] = int(bc7_encode(tex[b], mode_mask)[1].astype(np.int64).sum())
+    fmt = rate_select(sse1, sse7, vmin, vmax, rate)
+    if fmt is None:
+        return None
+    payload, off, _ = encode(tex, fmt, refine_steps, mode_mask)
+    return payload, off, fmt
+
+
+def decode_stream(payload, off, fmt, nblk):
+    """Decode every band stream back to textures uint8[16][nblk][16][4]."""
+    out = np.empty((16, nblk, 16, 4), np.uint8)
+    for b in range(16):
+        o = int(off[b])
+        if int(fmt[b]) == FMT_BC1:
+            out[b] = bc1_decode(payload[o:o + nblk * 8])
+        else:
+            out[b] = bc7_decode(payload[o:o + nblk * 16])
+    return out
+
+
+# ---------------------------------------------------------------- H
+def sh_basis(d):
+    """FP64 real SH basis (16 values) at direction d (3-vector)."""
+    Y = np.empty(16, np.float64)
+    _load().ref_sh_basis(float(d[0]), float(d[1]), float(d[2]), _p(Y))
+    return Y
+
+
+def decode_eval(payload, off, fmt, vmin, vmax, dirs, slots, with_scale=True):
+    """FP64 decode_eval.  Returns out[V][M][3] (and scale[V][M][3])."""
+    payload = _c(payload, np.uint8)
+    dirs = _c(dirs, np.float32).reshape(-1, 3)
+    slots = _c(slots, np.uint32)
+    V, M = dirs.shape[0], slots.shape[0]
+    out = np.empty((V, M, 3), np.float64)
+    scale = np.empty((V, M, 3), np.float64) if with_scale else None
+    _load().ref_decode_eval(_p(payload), _p(_c(fmt, np.uint8)), _p(_c(off, np.uint64)),
+                            _p(_c(vmin, np.float32)), _p(_c(vmax, np.float32)), _p(dirs), V,
+                            _p(slots), M, _p(out), _p(scale) if scale is not None else None)
+    return (out, scale) if with_scale else out

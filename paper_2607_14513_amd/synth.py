@@ -1,0 +1,65 @@
+"""Seeded synthetic 3DGS scenes and view directions.
+
+Inputs only: nothing here computes any step of the coding path.  The same
+arrays feed the CPU oracle and the GPU library.
+
+Scene recipe (stands in for the real 3DGS scenes of the paper's experiments,
+which are not available):
+  * positions: ``clusters`` centres ~ U[0,1]^3; each primitive picks one
+    uniformly and adds U[-0.05, 0.05]^3;
+  * band 0 (DC) RGB: a ``comps``-component isotropic Gaussian mixture, means
+    ~ U[0,1]^3, sigma 0.05, equal weights, clipped to [0,1];
+  * bands k = 1..15: i.i.d. Laplace(0, 0.2 / (l+1)^2) per channel, where
+    l = floor(sqrt(k)) is the SH degree of the band;
+  * FP64 on the host, stored as FP32.
+View directions: normalised N(0, I_3) draws, FP32.
+"""
+import math
+
+import numpy as np
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def band_degree(k):
+    return int(math.isqrt(k))
+
+
+def make_scene(n, clusters=32, comps=64, seed=1):
+    """Returns (pos float32[n][3], sh float32[n][16][3])."""
+    rng = _rng(seed)
+    centres = rng.uniform(0.0, 1.0, (clusters, 3))
+    which = rng.integers(0, clusters, n)
+    pos = centres[which] + rng.uniform(-0.05, 0.05, (n, 3))
+    means = rng.uniform(0.0, 1.0, (comps, 3))
+    comp = rng.integers(0, comps, n)
+    sh = np.empty((n, 16, 3), np.float64)
+    sh[:, 0, :] = np.clip(means[comp] + rng.normal(0.0, 0.05, (n, 3)), 0.0, 1.0)
+    for k in range(1, 16):
+        scale = 0.2 / (band_degree(k) + 1) ** 2
+        sh[:, k, :] = rng.laplace(0.0, scale, (n, 3))
+    return pos.astype(np.float32), sh.astype(np.float32)
+
+
+def make_dirs(v, seed=1):
+    """float32[v][3] unit view directions."""
+    rng = _rng(seed + 7919)
+    d = rng.normal(0.0, 1.0, (v, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    return d.astype(np.float32)
+
+
+def batch_sizes(n_scenes=64, lo=50_000, hi=2_000_000, seed=4):
+    """Primitive counts drawn log-uniformly from [lo, hi] (rounded)."""
+    rng = _rng(seed)
+    return [int(round(math.exp(x))) for x in rng.uniform(math.log(lo), math.log(hi), n_scenes)]
+
+
+# The five workloads (sizes and seeds) the tests and the benchmark use.
+CONFIGS = {
+    "small": dict(n=65_536, clusters=32, comps=64, seed=1, dirs=64),
+    "mid": dict(n=1_048_576, clusters=32, comps=64, seed=2, dirs=64),
+    "large": dict(n=3_145_728, clusters=256, comps=256, seed=3, dirs=1024, rate=6.0),
+}
