@@ -50,8 +50,9 @@ EXPORT void ref_band_range(const float *sh, uint64_t n, float *vmin, float *vmax
                 if (x < lo) lo = x;
                 if (x > hi) hi = x;
             }
-        vmin[k] = lo;
-        vmax[k] = hi;
+        /* the endpoints are values: a zero is stored as +0 */
+        vmin[k] = lo == 0.0f ? 0.0f : lo;
+        vmax[k] = hi == 0.0f ? 0.0f : hi;
     }
 }
 
@@ -64,8 +65,8 @@ EXPORT void ref_pos_aabb(const float *pos, uint64_t n, float *lo, float *hi)
             if (x < a) a = x;
             if (x > b) b = x;
         }
-        lo[c] = a;
-        hi[c] = b;
+        lo[c] = a == 0.0f ? 0.0f : a;
+        hi[c] = b == 0.0f ? 0.0f : b;
     }
 }
 
