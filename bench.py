@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the SH BC1/BC7 coding path on one MI355X.
+
+One step = the whole path over one synthetic scene already resident in HBM:
+  reorder (range, keys, stable radix sort, gather + pack)
+  -> encode every band in BC1 and in BC7 and keep the 6 bits/texel choice
+  -> random-access decode + SH evaluation at 64 view directions.
+Workload: 1,048,576 primitives (32 position clusters, 64-component DC colour
+mixture, Laplacian higher bands; seed 2), i.e. 1,048,576 blocks per format.
+
+Prints one JSON line.  `value` = blocks encoded per step (both formats) /
+step time, in Mblocks/s.  Also reported:
+  roofline            BC7 encode (the dominant kernel): algorithmic integer
+                      lane-ops per launch / its average launch time (HIP
+                      events on the library's stream), against the VALU peak;
+  roofline_decode_eval  decode + SH evaluation of 3,145,728 primitives at
+                      1,024 directions: bytes written+read per launch / time,
+                      against 8 TB/s;
+  cpu_baseline        the CPU oracle on a bounded sample of the same step.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+VALU_PEAK = 256 * 4 * 16 * 2.4e9        # integer lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz
+HBM_PEAK = 8.0e12                        # bytes/s
+BC7_EVALS_PER_BLOCK = 129_024            # texel x palette distance evaluations of the BC7 search
+OPS_PER_EVAL = 8                         # 3 sub + 3 mul + 1 add chain + 1 min, per evaluation
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--rate", type=float, default=6.0)
+    ap.add_argument("--dirs", type=int, default=64)
+    ap.add_argument("--no-large", action="store_true", help="skip the 3,145,728-primitive decode_eval leg")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy first (for counter scaling)")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the path would shard by block ranges, see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2607_14513_amd import gsbc, synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.Stream(dev)
+    cfg = synth.CONFIGS["mid"]
+    n, V, rate = cfg["n"], args.dirs, args.rate
+    pos, sh = synth.make_scene(n, cfg["clusters"], cfg["comps"], cfg["seed"])
+    dirs = synth.make_dirs(V, seed=cfg["seed"])
+    nblk = (n + 15) // 16
+
+    with torch.cuda.stream(stream):
+        if args.copy_calibration:
+            a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+            a.fill_(1.0)
+            b = torch.empty_like(a)
+            b.copy_(a)
+            torch.cuda.synchronize()
+            del a, b
+        ctx = gsbc.Context(0, stream=stream)
+        pos_d = torch.from_numpy(pos).to(dev)
+        sh_d = torch.from_numpy(sh).to(dev)
+        dirs_d = torch.from_numpy(dirs).to(dev)
+        _, cap, _ = gsbc.query_sizes(n)
+        perm = torch.empty(n, dtype=torch.int32, device=dev)
+        tex = torch.empty((16, nblk, 16, 4), dtype=torch.uint8, device=dev)
+        blocks = torch.empty(cap, dtype=torch.uint8, device=dev)
+        out = torch.empty((V, n, 3), dtype=torch.float32, device=dev)
+        torch.cuda.synchronize()
+
+        def step(ev=None):
+            if ev:
+                ev[0].record(stream)
+            _, _, d = ctx.reorder(pos_d, sh_d, out=(perm, tex))
+            if ev:
+                ev[1].record(stream)
+            _, d2, _ = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=rate, blocks=blocks)
+            if ev:
+                ev[2].record(stream)
+            ctx.decode_eval(blocks, d2, dirs_d, out=out)
+            if ev:
+                ev[3].record(stream)
+            return d2
+
+        for _ in range(args.warmup):
+            d2 = step()
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            d2 = step(evs[i])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        stage = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])] for e in evs])
+        ms_step = wall * 1e3 / args.steps
+        blocks_per_step = 2 * 16 * nblk
+        value = blocks_per_step / (ms_step * 1e-3) / 1e6
+
+        # ---- dominant kernel: BC7 encode of all 16 bands (one launch), HIP events on the stream
+        d7 = d2.copy()
+        t7 = []
+        for i in range(max(3, args.steps)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.encode(tex, d7, fmt=gsbc.FMT_BC7, blocks=blocks)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t7.append(e0.elapsed_time(e1) * 1e-3)
+        t1 = []
+        for i in range(max(3, args.steps)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            ctx.encode(tex, d7, fmt=gsbc.FMT_BC1, blocks=blocks)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t1.append(e0.elapsed_time(e1) * 1e-3)
+        bc7_s = float(np.mean(t7))
+        bc7_blocks = 16 * nblk
+        bc7_ops = bc7_blocks * BC7_EVALS_PER_BLOCK * OPS_PER_EVAL
+        traffic = None
+        if os.path.exists(TRAFFIC):
+            tr = json.load(open(TRAFFIC))
+            traffic = tr.get("k_bc7_encode")
+        roof = {"kernel": "k_bc7_encode", "bound": "alu", "achieved": bc7_ops / bc7_s / 1e12,
+                "peak": VALU_PEAK / 1e12, "unit": "Tops/s", "frac": bc7_ops / bc7_s / VALU_PEAK,
+                "traffic": traffic, "launch_ms": bc7_s * 1e3,
+                "algorithmic_ops_per_block": BC7_EVALS_PER_BLOCK * OPS_PER_EVAL}
+
+        # ---- decode_eval on the 3,145,728-primitive scene at 1,024 directions
+        roof_de = None
+        if not args.no_large:
+            del out
+            torch.cuda.empty_cache()
+            c3 = synth.CONFIGS["large"]
+            pos3, sh3 = synth.make_scene(c3["n"], c3["clusters"], c3["comps"], c3["seed"])
+            dirs3 = torch.from_numpy(synth.make_dirs(c3["dirs"], seed=c3["seed"])).to(dev)
+            p3, t3, dd = ctx.reorder(torch.from_numpy(pos3).to(dev), torch.from_numpy(sh3).to(dev))
+            b3, dd2, _ = ctx.encode(t3, dd, fmt=gsbc.FMT_AUTO, rate=c3["rate"])
+            del t3, p3
+            out3 = torch.empty((c3["dirs"], c3["n"], 3), dtype=torch.float32, device=dev)
+            ctx.decode_eval(b3, dd2, dirs3, out=out3)
+            torch.cuda.synchronize()
+            tde = []
+            for i in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                ctx.decode_eval(b3, dd2, dirs3, out=out3)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                tde.append(e0.elapsed_time(e1) * 1e-3)
+            de_s = float(np.mean(tde))
+            de_bytes = c3["dirs"] * c3["n"] * 12 + dd2.payload_bytes + c3["dirs"] * 12
+            tr_de = None
+            if os.path.exists(TRAFFIC):
+                tr_de = json.load(open(TRAFFIC)).get("k_decode_eval")
+            roof_de = {"kernel": "k_decode_eval", "bound": "hbm", "achieved": de_bytes / de_s / 1e9,
+                       "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": de_bytes / de_s / HBM_PEAK,
+                       "traffic": tr_de, "launch_ms": de_s * 1e3,
+                       "workload": "3,145,728 primitives x 1,024 directions, 6 bits/texel"}
+            del out3, b3
+            torch.cuda.empty_cache()
+        ctx.close()
+
+    cpu = None if args.no_cpu else cpu_baseline(pos, sh, dirs, rate)
+    line = {
+        "metric": "Mblocks/s BC7 & BC1 encode; decode+SH-eval GB/s; p50/p99 served latency",
+        "value": round(value, 3), "unit": "Mblocks/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "1,048,576 primitives (32 clusters, 64-component DC mixture, seed 2): "
+                               "reorder + BC1 and BC7 encode of all 16 bands + 6 bits/texel band choice "
+                               "+ decode_eval at 64 directions",
+                   "n_prims": n, "blocks_per_format": 16 * nblk, "rate_bits_per_texel": rate, "dirs": V},
+        "stages_ms": {"reorder": round(float(stage[:, 0].mean()), 3),
+                      "encode_auto": round(float(stage[:, 1].mean()), 3),
+                      "decode_eval": round(float(stage[:, 2].mean()), 3)},
+        "bc7_encode_mblocks_s": round(bc7_blocks / bc7_s / 1e6, 3),
+        "bc1_encode_mblocks_s": round(16 * nblk / float(np.mean(t1)) / 1e6, 3),
+        "roofline": roof,
+        "roofline_decode_eval": roof_de,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line))
+
+
+def cpu_baseline(pos, sh, dirs, rate):
+    """The oracle, untuned, on a bounded sample of the step: full reorder, BC1
+    and BC7 on 8,192 sampled blocks each, decode_eval of 16,384 slots at all
+    directions; scaled to the whole step's Mblocks/s."""
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    O.set_threads(threads)
+    n = pos.shape[0]
+    nblk = (n + 15) // 16
+    t = time.perf_counter()
+    perm, tex, vmin, vmax = O.reorder(pos, sh)
+    t_reorder = time.perf_counter() - t
+    rng = np.random.default_rng(0)
+    S = 8192
+    bands = rng.integers(0, 16, S)
+    blks = rng.integers(0, nblk, S)
+    sample = tex[bands, blks]
+    O._load().ref_init()
+    t = time.perf_counter()
+    O.bc1_encode(sample)
+    t_bc1 = (time.perf_counter() - t) / S
+    t = time.perf_counter()
+    O.bc7_encode(sample)
+    t_bc7 = (time.perf_counter() - t) / S
+    fmt = np.array([7] + [1] * 15, np.uint8)
+    slots = np.sort(rng.choice(n, 16384, replace=False)).astype(np.uint32)
+    blk_ids = np.unique(slots // 16)
+    mini = tex[:, blk_ids]
+    payload, off, _ = O.encode(mini, fmt)
+    where = {int(b): i for i, b in enumerate(blk_ids)}
+    renum = np.array([16 * where[int(s) // 16] + int(s) % 16 for s in slots], np.uint32)
+    t = time.perf_counter()
+    O.decode_eval(payload, off, fmt, vmin, vmax, dirs, renum, with_scale=False)
+    t_de = (time.perf_counter() - t) / len(slots)
+    step = t_reorder + 16 * nblk * (t_bc1 + t_bc7) + n * t_de
+    return {"value": round(2 * 16 * nblk / step / 1e6, 6), "unit": "Mblocks/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"full reorder of {n} primitives ({t_reorder:.2f} s); BC1 and BC7 on {S} sampled "
+                      f"blocks ({t_bc1 * 1e3:.3f} / {t_bc7 * 1e3:.3f} ms per block); decode_eval of "
+                      f"{len(slots)} slots x {len(dirs)} directions; scaled to one step of "
+                      f"{2 * 16 * nblk} blocks ({step:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

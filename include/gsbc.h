@@ -1,0 +1,173 @@
+/*
+ * gsbc.h -- C ABI of the MI355X (gfx950) library that codes the spherical-
+ * harmonic (SH) colour of 3D Gaussian Splatting primitives into BC1/BC7
+ * texture blocks, and decodes and evaluates it.
+ *
+ * Method: A. Said, R. Rauwendaal, "Compression of 3D Gaussian Splatting Data
+ * Using GPU-friendly Graphics Texture Coding".
+ *   - primitives may be reordered freely; reordering by colour inside spatial
+ *     groups makes BTC blocks cheaper to code (Sec. I; Sec. III-C);
+ *   - the SH coefficients of one band of 16 primitives form one 4x4 texel
+ *     block (Sec. IV-B, Fig. SetupD), coded with a fixed number of bits per
+ *     block (Sec. III-A/B), one bitstream per band, and the number of bits
+ *     per primitive is varied by choosing a format per bitstream (Sec. IV-B);
+ *   - a block is found by multiplying its index by the block size, which
+ *     gives random access for parallel decoding (Sec. I);
+ *   - the view-dependent colour is c(d) = H w(d) (Sec. II).
+ *
+ * Conventions shared by every call
+ *   - Pointers named "device" are HIP device memory owned by the caller; the
+ *     library never frees them.  Pointers named "host" are host memory owned
+ *     by the caller.  Every size is an element count unless it says bytes.
+ *   - Calls enqueue work on the context's stream.  gsbc_reorder and
+ *     gsbc_encode also copy a few header values back and wait for the stream
+ *     before they return; the other calls return without waiting.  Device
+ *     faults surface as GSBC_E_DEVICE from the next call or from gsbc_sync.
+ *   - Every call returns a gsbc_status; on error the context keeps a message
+ *     (gsbc_last_error).  Argument errors are detected before any work is
+ *     enqueued and leave the outputs untouched.
+ *   - Outputs are in sorted-slot order: slot s holds primitive perm[s].
+ *   - One context per host thread.  Contexts share only read-only tables.
+ *   - Results do not depend on launch shapes: every encoder decision is
+ *     integer (or a fixed FP32 expression), ties break by a fixed order.
+ */
+#ifndef GSBC_H
+#define GSBC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSBC_API __attribute__((visibility("default")))
+
+typedef int32_t gsbc_status;
+
+enum {
+    GSBC_OK = 0,
+    GSBC_E_ARG = -1,         /* invalid argument (null pointer, bad size, bad enum) */
+    GSBC_E_UNSUPPORTED = -2, /* valid request the library does not implement */
+    GSBC_E_NOMEM = -3,       /* scratch allocation failed */
+    GSBC_E_INFEASIBLE = -4,  /* the rate target cannot be met exactly */
+    GSBC_E_DEVICE = -5,      /* a HIP call or kernel failed */
+    GSBC_E_BUFFER = -6       /* a caller buffer is too small (see gsbc_query_sizes) */
+};
+
+enum { GSBC_FMT_AUTO = 0, GSBC_FMT_BC1 = 1, GSBC_FMT_BC7 = 7 };
+
+typedef struct gsbc_ctx gsbc_ctx;
+
+typedef struct {
+    uint32_t grid_bits;      /* spatial chunk grid: 2^g cells per axis, 0..10 (default 3) */
+    uint32_t refine_steps;   /* BC1 endpoint refinement steps, 0..8 (default 2) */
+    uint32_t bc7_mode_mask;  /* BC7 modes searched, bit m = mode m, nonzero (default 0xFF) */
+} gsbc_params;
+
+/* Header of a coded scene: one bitstream per SH band (Sec. IV-A: typed
+ * bitstreams; the stream index selects the decoder). */
+typedef struct {
+    uint8_t format[16];          /* per band: GSBC_FMT_BC1 or GSBC_FMT_BC7 */
+    uint64_t offset[16];         /* byte offset of band k's stream in the payload (16-byte aligned) */
+    float vmin[16], vmax[16];    /* per-band quantiser range: q = rint((x - vmin) * 255/(vmax - vmin)) */
+    uint64_t n_prims;            /* N */
+    uint64_t n_pad;              /* N rounded up to a multiple of 16 */
+    uint64_t blocks_per_band;    /* n_pad / 16 */
+    uint64_t payload_bytes;      /* bytes of the concatenated band streams */
+} gsbc_stream_desc;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * enqueue on, or NULL for a stream the context creates (default priority,
+ * blocking: ordered with work on the legacy null stream).  The context owns
+ * its scratch arena and, if it made it, its stream. */
+GSBC_API gsbc_status gsbc_create(gsbc_ctx **out, int device, void *hip_stream);
+
+/* Wait for the stream, free the scratch arena, destroy the context. */
+GSBC_API gsbc_status gsbc_destroy(gsbc_ctx *ctx);
+
+/* Message of the last error on this context ("" if none).  The string is
+ * owned by the context and valid until its next call. */
+GSBC_API const char *gsbc_last_error(const gsbc_ctx *ctx);
+
+/* Wait for all work enqueued by this context. */
+GSBC_API gsbc_status gsbc_sync(gsbc_ctx *ctx);
+
+/* Fill `p` (host) with the defaults: grid_bits 3, refine_steps 2, mode mask 0xFF. */
+GSBC_API void gsbc_default_params(gsbc_params *p);
+
+/* Sizes in bytes for N primitives and V directions (any output may be NULL):
+ * textures: uint8[16][n_pad/16][16][4];  max_blocks: the payload when every
+ * band is BC7 (an upper bound for any format choice);  out: float[V][N][3]. */
+GSBC_API gsbc_status gsbc_query_sizes(uint64_t n, uint32_t n_dirs, uint64_t *textures_bytes,
+                             uint64_t *max_blocks_bytes, uint64_t *out_bytes);
+
+/* ---------------------------------------------------------------- calls */
+
+/* Reorder and pack (Sec. III-C and Sec. IV-B, Fig. SetupD; quantiser of
+ * Sec. V-A with a per-band min/max range).
+ *   pos     device float[n][3]      primitive centres
+ *   sh      device float[n][16][3]  SH colour coefficients (band-major per primitive)
+ *   n       1 .. 2^31-1 primitives
+ *   params  host, NULL for defaults (grid_bits is used)
+ *   perm    device uint32[n]        out: perm[s] = original index at slot s
+ *   textures device uint8[16][n_pad/16][16][4] out: band k, block b, texel
+ *           4y+x holds the 8-bit RGB (alpha 255) of slot 16b+j, j placed at
+ *           the 2-D zigzag position x = j0|j2<<1, y = j1|j3<<1; slots past n
+ *           repeat slot n-1
+ *   desc    host, out: vmin, vmax, n_prims, n_pad, blocks_per_band filled
+ * Keys: (Morton cell of the position on a 2^g grid over the bounding box) << 24
+ * | interleaved bits of the band-0 quantised R,G,B (R highest in each triple);
+ * stable ascending sort.  Inputs must be finite. */
+GSBC_API gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, uint64_t n,
+                         const gsbc_params *params, uint32_t *perm, uint8_t *textures,
+                         gsbc_stream_desc *desc);
+
+/* Encode every band (Sec. III-A BTC; Sec. IV-B per-bitstream formats).
+ *   textures device, layout of gsbc_reorder; desc host, in: n_prims, n_pad,
+ *            blocks_per_band, vmin, vmax; out: format, offset, payload_bytes
+ *   format   GSBC_FMT_BC1 or GSBC_FMT_BC7 for all bands, or GSBC_FMT_AUTO:
+ *            every band is coded in both formats, then band 0 is BC7 and of
+ *            bands 1..15 the k = 4*rate - 17 with the largest
+ *            (SSE_BC1 - SSE_BC7) * delta_k^2 are BC7 (lower band first on
+ *            ties), the rest BC1, so the mean is exactly `rate` bits per texel
+ *            (GSBC_E_INFEASIBLE if k is not an integer in 0..15), with
+ *            delta_k = (vmax_k - vmin_k)/255 in FP32; `rate` is ignored
+ *            otherwise
+ *   params   host, NULL for defaults (refine_steps, bc7_mode_mask are used)
+ *   blocks   device uint8[blocks_capacity] out: band k's blocks at offset[k],
+ *            8 bytes (BC1) or 16 bytes (BC7) each; GSBC_E_BUFFER if
+ *            blocks_capacity < payload size
+ *   band_sse host int64[2][16] or NULL, out: total RGB SSE of each band coded
+ *            in BC1 (row 0) and BC7 (row 1) over all n_pad slots, -1 where that
+ *            format was not coded */
+GSBC_API gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc *desc,
+                        int format, double rate, const gsbc_params *params, uint8_t *blocks,
+                        uint64_t blocks_capacity, int64_t *band_sse);
+
+/* Decode every band back to textures (layout of gsbc_reorder) -- BC1 and BC7
+ * decoders of the format definitions; BC1 interpolants rounded to nearest.
+ *   blocks device, desc host (filled by gsbc_encode), textures_out device. */
+GSBC_API gsbc_status gsbc_decode(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_desc *desc,
+                        uint8_t *textures_out);
+
+/* Random-access decode + SH evaluation (Sec. II colour equation; Sec. I
+ * random access).  For every direction v and listed slot j:
+ *   out[v][j][c] = sum_k Hhat_k[c] * Y_k(dir_v),
+ *   Hhat_k = vmin_k + qhat * (vmax_k - vmin_k)/255 with qhat the decoded texel,
+ *   Y_k the real SH basis of degree <= 3 (k = l^2 + l + m, 3DGS signs), FP32.
+ *   blocks   device payload; desc host (filled by gsbc_encode)
+ *   dirs     device float[n_dirs][3], used as given (no normalisation)
+ *   prim_idx device uint32[m] sorted-slot ids (< n_prims), or NULL for all
+ *            slots 0..n_prims-1 (then m must equal n_prims)
+ *   out      device float[n_dirs][m][3] */
+GSBC_API gsbc_status gsbc_decode_eval(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_desc *desc,
+                             const float *dirs, uint32_t n_dirs, const uint32_t *prim_idx,
+                             uint64_t m, float *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GSBC_H */

@@ -1,0 +1,79 @@
+// gsbc_internal.h -- host-side declarations shared by the library's
+// translation units: kernel launchers (one per kernel family) and the
+// per-band launch arguments.  Nothing here is part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gsbc {
+
+// Per-band stream description passed to kernels by value.
+struct BandArgs {
+    uint64_t offset[16];   // byte offset of each band stream in the payload
+    uint32_t format[16];   // 1 (BC1) or 7 (BC7)
+    float vmin[16];        // dequantisation: vmin + q * delta
+    float delta[16];
+};
+
+// Range / scale record produced on the device by the reorder prologue.
+struct RangeRec {
+    float vmin[16], vmax[16];   // per-band range
+    float scale[16];            // 255 / (vmax - vmin), 0 for a constant band
+    float lo[3], hi[3];         // position bounding box
+    float cell_scale[3];        // 2^g / (hi - lo), 0 for a flat axis
+    uint32_t pad;
+};
+
+// ---- reorder (reorder.hip)
+size_t reorder_scratch_bytes(uint64_t n, uint32_t grid_bits);
+hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_t grid_bits,
+                          uint32_t *perm, uint8_t *textures, void *scratch, RangeRec *range_dev,
+                          hipStream_t st);
+
+// ---- encoders (bc1_encode.hip, bc7_encode.hip)
+// Encode bands [band0, band0 + nbands) of textures[16][nblk][16][4]; band b's
+// blocks go to out + out_offset[b], block sse added into band_sse[b] (int64
+// atomics, order independent).
+struct EncodeArgs {
+    const uint8_t *textures;
+    uint64_t nblk;
+    uint32_t band0, nbands;
+    uint8_t *out;
+    uint64_t out_offset[16];
+    unsigned long long *band_sse;   // [16], may be null
+    uint32_t refine_steps;
+    uint32_t mode_mask;
+};
+hipError_t launch_bc1_encode(const EncodeArgs &a, hipStream_t st);
+hipError_t launch_bc7_encode(const EncodeArgs &a, hipStream_t st);
+hipError_t upload_bc1_tables(hipStream_t st);
+hipError_t upload_bc7_tables(int device, hipStream_t st);
+
+// ---- rate control (rate.hip)
+// sse1/sse7: [16] int64 band SSEs; writes format[16] and offsets[16] plus the
+// payload size into sel (device), then copies the chosen streams from the
+// two candidate payloads into `out`.
+struct RateSel {
+    uint32_t format[16];
+    uint64_t offset[16];
+    uint64_t payload_bytes;
+};
+hipError_t launch_rate_select(const unsigned long long *sse1, const unsigned long long *sse7,
+                              const BandArgs &b, uint32_t k, uint64_t nblk, RateSel *sel,
+                              hipStream_t st);
+// Copies each chosen band stream and zero-fills its alignment padding.
+hipError_t launch_copy_streams(const uint8_t *src1, const uint64_t *off1, const uint8_t *src7,
+                               const uint64_t *off7, const RateSel *sel, uint64_t nblk,
+                               uint8_t *out, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t st);
+
+// ---- decoders (decode.hip)
+hipError_t launch_decode(const uint8_t *blocks, const BandArgs &b, uint64_t nblk,
+                         uint8_t *textures, hipStream_t st);
+// Slots listed in prim_idx at or beyond n_prims give NaN outputs.
+hipError_t launch_decode_eval(const uint8_t *blocks, const BandArgs &b, uint64_t n_prims,
+                              const float *dirs, uint32_t n_dirs, const uint32_t *prim_idx,
+                              uint64_t m, float *out, float *basis_scratch, hipStream_t st);
+
+}  // namespace gsbc

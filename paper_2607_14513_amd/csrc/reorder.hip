@@ -1,0 +1,352 @@
+// reorder.hip -- colour/space reorder and block packing on gfx950.
+//
+//   range    per-band min/max of the SH coefficients and the position
+//            bounding box (Sec. V-A quantiser range; Sec. III-C spatial
+//            groups), one coalesced float4 pass with order-independent
+//            integer atomics on an order-preserving encoding of the floats;
+//   keys     (Morton cell of the position) << 24 | RGB bit interleave of the
+//            quantised band-0 colour (Sec. III-C, Fig. Bit4Scan);
+//   sort     stable LSD radix sort, 11-bit digits, per-wave tiles with
+//            LDS-local counters and wave-ballot ranking (stable by
+//            construction: a wave walks its tile in order);
+//   pack     gather each slot's 48 coefficients, quantise, and write band k
+//            of slot s to texel zigzag(s % 16) of block s / 16 (Fig. SetupD,
+//            Fig. ZigZagScan).
+#include "gsbc_internal.h"
+
+#include <algorithm>
+
+namespace gsbc {
+namespace {
+
+constexpr int kDigitBits = 11;
+constexpr int kDigits = 1 << kDigitBits;
+constexpr int kWaveItems = 64;                 // keys per lane per tile
+constexpr int kTile = 64 * kWaveItems;         // keys per wave tile
+constexpr int kRangeBlock = 384;               // multiple of 12 and 3
+
+__device__ __forceinline__ uint32_t ord_of(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float float_of(uint32_t u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+}
+
+// Spread the low 10 bits of x to every third bit.
+__device__ __forceinline__ uint32_t spread3(uint32_t x)
+{
+    x &= 0x3FF;
+    x = (x | (x << 16)) & 0x030000FF;
+    x = (x | (x << 8)) & 0x0300F00F;
+    x = (x | (x << 4)) & 0x030C30C3;
+    x = (x | (x << 2)) & 0x09249249;
+    return x;
+}
+
+// 8-bit code of coefficient x in a band with range start vmin and scale s.
+__device__ __forceinline__ uint32_t quant8(float x, float vmin, float s)
+{
+    float t = x - vmin;
+    float u = t * s;
+    int v = (int)rintf(u);
+    v = v < 0 ? 0 : v;
+    v = v > 255 ? 255 : v;
+    return (uint32_t)v;
+}
+
+// acc layout: [0..15] band min, [16..31] band max, [32..34] pos min, [35..37] pos max
+__global__ void k_range_init(uint32_t *acc)
+{
+    int t = threadIdx.x;
+    if (t < 38) acc[t] = (t < 16 || (t >= 32 && t < 35)) ? 0xFFFFFFFFu : 0u;
+}
+
+__global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4, const float *pos,
+                                                               uint64_t n, uint32_t *acc)
+{
+    __shared__ uint32_t s_acc[38];
+    if (threadIdx.x < 38) s_acc[threadIdx.x] = (threadIdx.x < 16 || (threadIdx.x >= 32 && threadIdx.x < 35)) ? 0xFFFFFFFFu : 0u;
+    __syncthreads();
+    const uint64_t T = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // float4 chunk j of a primitive holds floats 4j..4j+3 -> bands (4j+c)/3
+    const int j = (int)(t % 12);
+    const int bandA = (4 * j) / 3, bandB = (4 * j + 3) / 3;
+    float minA = INFINITY, maxA = -INFINITY, minB = INFINITY, maxB = -INFINITY;
+    const uint64_t nq = n * 12;
+    for (uint64_t q = t; q < nq; q += T) {
+        float4 v = sh4[q];
+        float f[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            if ((4 * j + c) / 3 == bandA) { minA = fminf(minA, f[c]); maxA = fmaxf(maxA, f[c]); }
+            else { minB = fminf(minB, f[c]); maxB = fmaxf(maxB, f[c]); }
+        }
+    }
+    const int axis = (int)(t % 3);
+    float pmin = INFINITY, pmax = -INFINITY;
+    for (uint64_t f = t; f < n * 3; f += T) {
+        float v = pos[f];
+        pmin = fminf(pmin, v);
+        pmax = fmaxf(pmax, v);
+    }
+    atomicMin(&s_acc[bandA], ord_of(minA));
+    atomicMax(&s_acc[16 + bandA], ord_of(maxA));
+    if (bandB != bandA) {
+        atomicMin(&s_acc[bandB], ord_of(minB));
+        atomicMax(&s_acc[16 + bandB], ord_of(maxB));
+    }
+    atomicMin(&s_acc[32 + axis], ord_of(pmin));
+    atomicMax(&s_acc[35 + axis], ord_of(pmax));
+    __syncthreads();
+    if (threadIdx.x < 38) {
+        int i = threadIdx.x;
+        if (i < 16 || (i >= 32 && i < 35)) atomicMin(&acc[i], s_acc[i]);
+        else atomicMax(&acc[i], s_acc[i]);
+    }
+}
+
+// Signed zero: the range endpoints are values, stored as +0 when zero.
+__device__ __forceinline__ float canon_zero(float x) { return x == 0.0f ? 0.0f : x; }
+
+__global__ void k_range_final(const uint32_t *acc, uint32_t grid_bits, RangeRec *r)
+{
+    int k = threadIdx.x;
+    if (k < 16) {
+        float lo = canon_zero(float_of(acc[k])), hi = canon_zero(float_of(acc[16 + k]));
+        r->vmin[k] = lo;
+        r->vmax[k] = hi;
+        float range = hi - lo;
+        r->scale[k] = range > 0.0f ? 255.0f / range : 0.0f;
+    }
+    if (k < 3) {
+        float lo = canon_zero(float_of(acc[32 + k])), hi = canon_zero(float_of(acc[35 + k]));
+        r->lo[k] = lo;
+        r->hi[k] = hi;
+        float ext = hi - lo;
+        r->cell_scale[k] = ext > 0.0f ? (float)(1u << grid_bits) / ext : 0.0f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_keys(const float *pos, const float *sh, uint64_t n,
+                                              uint32_t grid_bits, const RangeRec *r,
+                                              uint64_t *keys, uint32_t *vals)
+{
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t cmax = (1u << grid_bits) - 1u;
+    uint32_t cell[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        float t = pos[i * 3 + a] - r->lo[a];
+        float u = t * r->cell_scale[a];
+        uint32_t v = (uint32_t)floorf(u);
+        cell[a] = v < cmax ? v : cmax;
+    }
+    const float *dc = sh + i * 48;
+    uint32_t q0 = quant8(dc[0], r->vmin[0], r->scale[0]);
+    uint32_t q1 = quant8(dc[1], r->vmin[0], r->scale[0]);
+    uint32_t q2 = quant8(dc[2], r->vmin[0], r->scale[0]);
+    uint64_t chunk = spread3(cell[0]) | (spread3(cell[1]) << 1) | (spread3(cell[2]) << 2);
+    uint32_t colour = (spread3(q0) << 2) | (spread3(q1) << 1) | spread3(q2);
+    keys[i] = (chunk << 24) | colour;
+    vals[i] = (uint32_t)i;
+}
+
+// Digit counts of each wave tile; hist is tile-major: hist[tile][digit].
+__global__ __launch_bounds__(256) void k_radix_hist(const uint64_t *keys, uint64_t n, int shift,
+                                                    uint32_t ntiles, uint32_t *hist)
+{
+    __shared__ uint32_t cnt[4][kDigits];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int d = lane; d < kDigits; d += 64) cnt[w][d] = 0;
+    __syncthreads();
+    const uint32_t tile = blockIdx.x * 4 + w;
+    if (tile < ntiles) {
+        const uint64_t base = (uint64_t)tile * kTile;
+        for (int it = 0; it < kWaveItems; it++) {
+            uint64_t i = base + (uint64_t)it * 64 + lane;
+            if (i < n) atomicAdd(&cnt[w][(keys[i] >> shift) & (kDigits - 1)], 1u);
+        }
+    }
+    __syncthreads();
+    if (tile < ntiles)
+        for (int d = lane; d < kDigits; d += 64) hist[(uint64_t)tile * kDigits + d] = cnt[w][d];
+}
+
+// Exclusive prefix of each digit's column over the tiles; digit totals.
+__global__ __launch_bounds__(256) void k_radix_colscan(uint32_t *hist, uint32_t ntiles, uint32_t *total)
+{
+    const int d = blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= kDigits) return;
+    uint32_t run = 0;
+    for (uint32_t t = 0; t < ntiles; t++) {
+        uint32_t c = hist[(uint64_t)t * kDigits + d];
+        hist[(uint64_t)t * kDigits + d] = run;
+        run += c;
+    }
+    total[d] = run;
+}
+
+// Exclusive scan of the digit totals (one workgroup of 1024 threads).
+__global__ __launch_bounds__(1024) void k_radix_digitscan(uint32_t *total)
+{
+    __shared__ uint32_t s[kDigits];
+    const int t = threadIdx.x;
+    s[2 * t] = total[2 * t];
+    s[2 * t + 1] = total[2 * t + 1];
+    __syncthreads();
+    if (t == 0) {
+        uint32_t run = 0;
+        for (int d = 0; d < kDigits; d++) {
+            uint32_t c = s[d];
+            s[d] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    total[2 * t] = s[2 * t];
+    total[2 * t + 1] = s[2 * t + 1];
+}
+
+// Stable scatter: each wave walks its tile in order; lanes with equal digits
+// are ranked by lane id through ballots over the digit bits.
+__global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *keys_in, const uint32_t *vals_in,
+                                                       uint64_t n, int shift, uint32_t ntiles,
+                                                       const uint32_t *hist, const uint32_t *digit_base,
+                                                       uint64_t *keys_out, uint32_t *vals_out)
+{
+    __shared__ uint32_t ctr[4][kDigits];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t tile = blockIdx.x * 4 + w;
+    if (tile >= ntiles) return;   // whole wave leaves; no block barrier below
+    for (int d = lane; d < kDigits; d += 64)
+        ctr[w][d] = hist[(uint64_t)tile * kDigits + d] + digit_base[d];
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t base = (uint64_t)tile * kTile;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int it = 0; it < kWaveItems; it++) {
+        uint64_t i = base + (uint64_t)it * 64 + lane;
+        bool valid = i < n;
+        uint64_t key = valid ? keys_in[i] : 0;
+        uint32_t val = valid ? vals_in[i] : 0;
+        uint32_t d = (uint32_t)(key >> shift) & (kDigits - 1);
+        uint64_t peers = __ballot(valid);
+        if (peers == 0) break;
+#pragma unroll
+        for (int b = 0; b < kDigitBits; b++) {
+            uint64_t bal = __ballot((d >> b) & 1);
+            peers &= ((d >> b) & 1) ? bal : ~bal;
+        }
+        if (valid) {
+            uint32_t rank = (uint32_t)__popcll(peers & below);
+            uint32_t off = ctr[w][d] + rank;
+            keys_out[off] = key;
+            vals_out[off] = val;
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (valid && (peers & below) == 0) ctr[w][d] += (uint32_t)__popcll(peers);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Slot s -> block s/16, texel zigzag(s%16); 16 band texels per slot.
+__global__ __launch_bounds__(256) void k_gather_pack(const float *sh, const uint32_t *perm, uint64_t n,
+                                                     uint64_t nblk, const RangeRec *r, uint32_t *tex)
+{
+    uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nblk * 16) return;
+    uint32_t src = perm[s < n ? s : n - 1];
+    uint32_t j = (uint32_t)(s & 15);
+    uint32_t x = (j & 1u) | (((j >> 2) & 1u) << 1);
+    uint32_t y = ((j >> 1) & 1u) | (((j >> 3) & 1u) << 1);
+    uint64_t texel = (s >> 4) * 16 + 4 * y + x;
+    const float4 *p = reinterpret_cast<const float4 *>(sh + (uint64_t)src * 48);
+    float f[48];
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+        float4 v = p[c];
+        f[4 * c] = v.x; f[4 * c + 1] = v.y; f[4 * c + 2] = v.z; f[4 * c + 3] = v.w;
+    }
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        float vm = r->vmin[k], sc = r->scale[k];
+        uint32_t w = quant8(f[3 * k], vm, sc) | (quant8(f[3 * k + 1], vm, sc) << 8) |
+                     (quant8(f[3 * k + 2], vm, sc) << 16) | 0xFF000000u;
+        tex[(uint64_t)k * nblk * 16 + texel] = w;
+    }
+}
+
+struct Layout {
+    size_t acc, keys_a, keys_b, vals_a, vals_b, hist, total, bytes;
+};
+
+Layout layout(uint64_t n)
+{
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    uint64_t ntiles = (n + kTile - 1) / kTile;
+    Layout L;
+    size_t o = 0;
+    L.acc = o; o += al(64 * 4);
+    L.keys_a = o; o += al(n * 8);
+    L.keys_b = o; o += al(n * 8);
+    L.vals_a = o; o += al(n * 4);
+    L.vals_b = o; o += al(n * 4);
+    L.hist = o; o += al(ntiles * kDigits * 4);
+    L.total = o; o += al(kDigits * 4);
+    L.bytes = o;
+    return L;
+}
+
+}  // namespace
+
+size_t reorder_scratch_bytes(uint64_t n, uint32_t) { return layout(n).bytes; }
+
+hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_t grid_bits,
+                          uint32_t *perm, uint8_t *textures, void *scratch, RangeRec *range_dev,
+                          hipStream_t st)
+{
+    Layout L = layout(n);
+    char *s = static_cast<char *>(scratch);
+    uint32_t *acc = reinterpret_cast<uint32_t *>(s + L.acc);
+    uint64_t *ka = reinterpret_cast<uint64_t *>(s + L.keys_a), *kb = reinterpret_cast<uint64_t *>(s + L.keys_b);
+    uint32_t *va = reinterpret_cast<uint32_t *>(s + L.vals_a), *vb = reinterpret_cast<uint32_t *>(s + L.vals_b);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(s + L.hist), *total = reinterpret_cast<uint32_t *>(s + L.total);
+
+    hipLaunchKernelGGL(k_range_init, dim3(1), dim3(64), 0, st, acc);
+    uint64_t want = (n * 12 + kRangeBlock - 1) / kRangeBlock;
+    uint32_t nb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 2048);
+    hipLaunchKernelGGL(k_range_partial, dim3(nb), dim3(kRangeBlock), 0, st,
+                       reinterpret_cast<const float4 *>(sh), pos, n, acc);
+    hipLaunchKernelGGL(k_range_final, dim3(1), dim3(64), 0, st, acc, grid_bits, range_dev);
+    hipLaunchKernelGGL(k_keys, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, pos, sh, n,
+                       grid_bits, range_dev, ka, va);
+
+    const int key_bits = 24 + 3 * (int)grid_bits;
+    const int passes = (key_bits + kDigitBits - 1) / kDigitBits;
+    const uint32_t ntiles = (uint32_t)((n + kTile - 1) / kTile);
+    const uint32_t nblocks = (ntiles + 3) / 4;
+    uint64_t *kin = ka, *kout = kb;
+    uint32_t *vin = va, *vout = vb;
+    for (int p = 0; p < passes; p++) {
+        int shift = p * kDigitBits;
+        uint32_t *vdst = (p == passes - 1) ? perm : vout;
+        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(256), 0, st, kin, n, shift, ntiles, hist);
+        hipLaunchKernelGGL(k_radix_colscan, dim3(kDigits / 256), dim3(256), 0, st, hist, ntiles, total);
+        hipLaunchKernelGGL(k_radix_digitscan, dim3(1), dim3(1024), 0, st, total);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(256), 0, st, kin, vin, n, shift,
+                           ntiles, hist, total, kout, vdst);
+        std::swap(kin, kout);
+        vin = vdst;
+        vout = (vdst == va) ? vb : va;
+    }
+    uint64_t nblk = (n + 15) / 16;
+    hipLaunchKernelGGL(k_gather_pack, dim3((uint32_t)((nblk * 16 + 255) / 256)), dim3(256), 0, st,
+                       sh, perm, n, nblk, range_dev, reinterpret_cast<uint32_t *>(textures));
+    return hipGetLastError();
+}
+
+}  // namespace gsbc

@@ -1,0 +1,208 @@
+"""ctypes binding of libgsbc.so (include/gsbc.h) over torch device tensors.
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+The library must be built (``__graft_entry__.build()`` or
+``python paper_2607_14513_amd/csrc/build.py``); importing this module without
+it, or calling it without a GPU, raises -- there is no CPU fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgsbc.so")
+
+OK, E_ARG, E_UNSUPPORTED, E_NOMEM, E_INFEASIBLE, E_DEVICE, E_BUFFER = 0, -1, -2, -3, -4, -5, -6
+FMT_AUTO, FMT_BC1, FMT_BC7 = 0, 1, 7
+
+EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_default_params",
+            "gsbc_query_sizes", "gsbc_reorder", "gsbc_encode", "gsbc_decode", "gsbc_decode_eval")
+
+
+class GsbcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"gsbc status {status}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("grid_bits", ctypes.c_uint32), ("refine_steps", ctypes.c_uint32),
+                ("bc7_mode_mask", ctypes.c_uint32)]
+
+
+class StreamDesc(ctypes.Structure):
+    _fields_ = [("format", ctypes.c_uint8 * 16), ("offset", ctypes.c_uint64 * 16),
+                ("vmin", ctypes.c_float * 16), ("vmax", ctypes.c_float * 16),
+                ("n_prims", ctypes.c_uint64), ("n_pad", ctypes.c_uint64),
+                ("blocks_per_band", ctypes.c_uint64), ("payload_bytes", ctypes.c_uint64)]
+
+    def formats(self):
+        return np.array(list(self.format), np.uint8)
+
+    def offsets(self):
+        return np.array(list(self.offset), np.uint64)
+
+    def ranges(self):
+        return np.array(list(self.vmin), np.float32), np.array(list(self.vmax), np.float32)
+
+    def copy(self):
+        d = StreamDesc()
+        ctypes.memmove(ctypes.byref(d), ctypes.byref(self), ctypes.sizeof(StreamDesc))
+        return d
+
+
+_lib = None
+
+
+def load():
+    """Load libgsbc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        P, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32
+        lib.gsbc_create.argtypes = [ctypes.POINTER(P), ctypes.c_int, P]
+        lib.gsbc_destroy.argtypes = [P]
+        lib.gsbc_last_error.argtypes = [P]
+        lib.gsbc_last_error.restype = ctypes.c_char_p
+        lib.gsbc_sync.argtypes = [P]
+        lib.gsbc_default_params.argtypes = [ctypes.POINTER(Params)]
+        lib.gsbc_default_params.restype = None
+        lib.gsbc_query_sizes.argtypes = [u64, u32, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)]
+        lib.gsbc_reorder.argtypes = [P, P, P, u64, ctypes.POINTER(Params), P, P, ctypes.POINTER(StreamDesc)]
+        lib.gsbc_encode.argtypes = [P, P, ctypes.POINTER(StreamDesc), ctypes.c_int, ctypes.c_double,
+                                    ctypes.POINTER(Params), P, u64, P]
+        lib.gsbc_decode.argtypes = [P, P, ctypes.POINTER(StreamDesc), P]
+        lib.gsbc_decode_eval.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, u32, P, u64, P]
+        for name in EXPORTED:
+            if name not in ("gsbc_default_params", "gsbc_last_error"):
+                getattr(lib, name).restype = i32
+        _lib = lib
+    return _lib
+
+
+def default_params(**kw):
+    p = Params()
+    load().gsbc_default_params(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, int(v))
+    return p
+
+
+def query_sizes(n, n_dirs=0):
+    t, b, o = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    st = load().gsbc_query_sizes(int(n), int(n_dirs), ctypes.byref(t), ctypes.byref(b), ctypes.byref(o))
+    if st != OK:
+        raise GsbcError(st, "query_sizes")
+    return t.value, b.value, o.value
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_tensor(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    return t
+
+
+class Context:
+    """One library context: device, stream (torch's current stream by default)
+    and scratch arena."""
+
+    def __init__(self, device=0, stream=None):
+        lib = load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no HIP device: the library has no CPU path")
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = lib.gsbc_create(ctypes.byref(h), int(device), ctypes.c_void_p(stream.cuda_stream))
+        if st != OK:
+            raise GsbcError(st, "gsbc_create failed")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().gsbc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _check(self, st):
+        if st != OK:
+            raise GsbcError(st, load().gsbc_last_error(self._h).decode())
+
+    def sync(self):
+        self._check(load().gsbc_sync(self._h))
+
+    # ------------------------------------------------------------- calls
+    def reorder(self, pos, sh, params=None, out=None):
+        """pos float32[n][3], sh float32[n][16][3] on the device ->
+        (perm uint32-as-int32[n], textures uint8[16][nblk][16][4], desc)."""
+        _dev_tensor(pos, torch.float32, "pos")
+        _dev_tensor(sh, torch.float32, "sh")
+        n = pos.shape[0]
+        nblk = (n + 15) // 16
+        if out is None:
+            perm = torch.empty(n, dtype=torch.int32, device=self.device)
+            tex = torch.empty((16, nblk, 16, 4), dtype=torch.uint8, device=self.device)
+        else:
+            perm, tex = out
+        desc = StreamDesc()
+        p = params if params is not None else default_params()
+        self._check(load().gsbc_reorder(self._h, _ptr(pos), _ptr(sh), n, ctypes.byref(p), _ptr(perm),
+                                        _ptr(tex), ctypes.byref(desc)))
+        return perm, tex, desc
+
+    def encode(self, textures, desc, fmt=FMT_AUTO, rate=6.0, params=None, blocks=None, want_sse=False):
+        """Encode all bands -> (blocks uint8 device tensor, desc, band_sse int64[2][16] or None)."""
+        _dev_tensor(textures, torch.uint8, "textures")
+        desc = desc.copy()
+        if blocks is None:
+            _, cap, _ = query_sizes(desc.n_prims)
+            blocks = torch.empty(cap, dtype=torch.uint8, device=self.device)
+        sse = np.zeros(32, np.int64) if want_sse else None
+        p = params if params is not None else default_params()
+        self._check(load().gsbc_encode(self._h, _ptr(textures), ctypes.byref(desc), int(fmt), float(rate),
+                                       ctypes.byref(p), _ptr(blocks), blocks.numel(),
+                                       ctypes.c_void_p(sse.ctypes.data) if sse is not None else None))
+        return blocks, desc, (sse.reshape(2, 16) if sse is not None else None)
+
+    def decode(self, blocks, desc, out=None):
+        if out is None:
+            out = torch.empty((16, desc.blocks_per_band, 16, 4), dtype=torch.uint8, device=self.device)
+        self._check(load().gsbc_decode(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(out)))
+        return out
+
+    def decode_eval(self, blocks, desc, dirs, prim_idx=None, out=None):
+        """dirs float32[V][3] device; prim_idx int32[m] sorted-slot ids or None
+        -> out float32[V][m][3]."""
+        _dev_tensor(dirs, torch.float32, "dirs")
+        V = dirs.shape[0]
+        m = desc.n_prims if prim_idx is None else prim_idx.numel()
+        if prim_idx is not None:
+            _dev_tensor(prim_idx, torch.int32, "prim_idx")
+        if out is None:
+            out = torch.empty((V, m, 3), dtype=torch.float32, device=self.device)
+        self._check(load().gsbc_decode_eval(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(dirs), V,
+                                            _ptr(prim_idx), m, _ptr(out)))
+        return out

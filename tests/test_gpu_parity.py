@@ -1,0 +1,387 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Integer results (permutation, textures, bitstreams, decoded texels, format
+choice) must be bit-exact; SH colours must satisfy
+|c32 - c64| <= 1e-5 * sum_k |Hhat_k Y_k| per channel (the size of the terms of
+the FP32 dot product), against the oracle's FP64 evaluation.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from conftest import random_blocks, rgba, smooth_blocks
+from paper_2607_14513_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-5
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2607_14513_amd import gsbc
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ctx = gsbc.Context(0)
+    yield gsbc, ctx
+    ctx.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _desc_for(gsbc, n, fmt):
+    d = gsbc.StreamDesc()
+    nblk = (n + 15) // 16
+    d.n_prims, d.n_pad, d.blocks_per_band = n, nblk * 16, nblk
+    pos = 0
+    for k in range(16):
+        d.format[k] = fmt[k]
+        d.offset[k] = pos
+        pos += nblk * (8 if fmt[k] == 1 else 16)
+        pos = (pos + 15) // 16 * 16
+    d.payload_bytes = pos
+    for k in range(16):
+        d.vmin[k], d.vmax[k] = -1.0, 1.0
+    return d
+
+
+# ---------------------------------------------------------------- decode
+@pytest.mark.parametrize("fmt", [1, 7])
+def test_decode_random_blocks(G, fmt):
+    gsbc, ctx = G
+    n = 16 * 1001 - 5                       # ragged: 1001 blocks per band
+    d = _desc_for(gsbc, n, [fmt] * 16)
+    rng = np.random.default_rng(fmt)
+    payload = rng.integers(0, 256, d.payload_bytes, dtype=np.uint8)
+    if fmt == 7:
+        payload[::16][:50] = 0              # some reserved-mode blocks
+    say("decode random", fmt)
+    out = host(ctx.decode(dev(payload), d))
+    nblk = d.blocks_per_band
+    ref = O.decode_stream(payload, d.offsets(), d.formats(), nblk)
+    assert np.array_equal(out, ref)
+
+
+# ---------------------------------------------------------------- reorder
+@pytest.mark.parametrize("n,seed", [(1, 3), (15, 4), (17, 5), (1007, 6), (65_536, 1)])
+def test_reorder_bit_exact(G, n, seed):
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(n, seed=seed)
+    say("reorder", n)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    rperm, rtex, rvmin, rvmax = O.reorder(pos, sh)
+    vmin, vmax = d.ranges()
+    assert np.array_equal(vmin.view(np.uint32), rvmin.view(np.uint32))
+    assert np.array_equal(vmax.view(np.uint32), rvmax.view(np.uint32))
+    assert np.array_equal(host(perm).view(np.uint32), rperm)
+    assert np.array_equal(host(tex), rtex)
+    assert d.n_prims == n and d.n_pad == (n + 15) // 16 * 16
+
+
+@pytest.mark.parametrize("g", [0, 1, 5, 10])
+def test_reorder_grid_bits(G, g):
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(5000, seed=20 + g)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh), params=gsbc.default_params(grid_bits=g))
+    rperm, rtex, _, _ = O.reorder(pos, sh, grid_bits=g)
+    assert np.array_equal(host(perm).view(np.uint32), rperm)
+    assert np.array_equal(host(tex), rtex)
+
+
+def test_reorder_degenerate_inputs(G):
+    """All positions equal (flat box) and constant bands (zero range)."""
+    gsbc, ctx = G
+    n = 300
+    pos = np.zeros((n, 3), np.float32)
+    rng = np.random.default_rng(9)
+    sh = rng.normal(size=(n, 16, 3)).astype(np.float32)
+    sh[:, 3, :] = 0.125
+    sh[:, 0, :] = np.float32(-0.0)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    rperm, rtex, rvmin, rvmax = O.reorder(pos, sh)
+    assert np.array_equal(host(perm).view(np.uint32), rperm)
+    assert np.array_equal(host(tex), rtex)
+    assert np.array_equal(d.ranges()[0].view(np.uint32), rvmin.view(np.uint32))
+
+
+def test_reorder_full_size(G):
+    """1,048,576 primitives: permutation, ranges and textures bit-exact."""
+    gsbc, ctx = G
+    c = synth.CONFIGS["mid"]
+    pos, sh = synth.make_scene(c["n"], c["clusters"], c["comps"], c["seed"])
+    say("reorder full", c["n"])
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    rperm, rtex, rvmin, rvmax = O.reorder(pos, sh)
+    assert np.array_equal(host(perm).view(np.uint32), rperm)
+    assert np.array_equal(host(tex), rtex)
+
+
+# ---------------------------------------------------------------- encoders
+def _encode_bands(ctx, gsbc, tex_np, fmt, **kw):
+    n = tex_np.shape[1] * 16
+    d = _desc_for(gsbc, n, [fmt] * 16)
+    blocks, d2, sse = ctx.encode(dev(tex_np), d, fmt=fmt, params=gsbc.default_params(**kw), want_sse=True)
+    return host(blocks), d2, sse
+
+
+def _stack_bands(blocks_list):
+    """16 bands of [nblk][16][4] texels."""
+    return np.stack(blocks_list)
+
+
+@pytest.mark.parametrize("kind", ["scene", "smooth", "random", "constant"])
+def test_bc1_bit_exact(G, kind):
+    gsbc, ctx = G
+    if kind == "scene":
+        pos, sh = synth.make_scene(65_536, seed=1)
+        _, tex, _, _ = O.reorder(pos, sh)
+    elif kind == "smooth":
+        tex = _stack_bands([smooth_blocks(203, 100 + b, spread=1 + 2 * b) for b in range(16)])
+    elif kind == "random":
+        tex = _stack_bands([random_blocks(131, 200 + b) for b in range(16)])
+    else:
+        rng = np.random.default_rng(3)
+        cols = rng.integers(0, 256, (16, 77, 1, 3))
+        tex = rgba(np.repeat(cols, 16, axis=2))
+    say("bc1", kind, tex.shape)
+    blocks, d, sse = _encode_bands(ctx, gsbc, tex, 1)
+    offs = d.offsets()
+    nblk = tex.shape[1]
+    tot = np.zeros(16, np.int64)
+    for b in range(16):
+        rb, rs = O.bc1_encode(tex[b])
+        o = int(offs[b])
+        assert np.array_equal(blocks[o:o + nblk * 8].reshape(nblk, 8), rb), f"band {b}"
+        tot[b] = rs.astype(np.int64).sum()
+    assert np.array_equal(sse[0], tot)
+
+
+@pytest.mark.parametrize("steps", [0, 1, 5])
+def test_bc1_refine_steps(G, steps):
+    gsbc, ctx = G
+    tex = _stack_bands([smooth_blocks(40, 300 + b, spread=20) for b in range(16)])
+    blocks, d, _ = _encode_bands(ctx, gsbc, tex, 1, refine_steps=steps)
+    for b in range(16):
+        o = int(d.offsets()[b])
+        assert np.array_equal(blocks[o:o + 40 * 8].reshape(40, 8), O.bc1_encode(tex[b], steps)[0])
+
+
+@pytest.mark.parametrize("kind", ["scene", "smooth", "random", "constant"])
+def test_bc7_bit_exact(G, kind):
+    gsbc, ctx = G
+    if kind == "scene":
+        pos, sh = synth.make_scene(4096 + 37, seed=7)
+        _, tex, _, _ = O.reorder(pos, sh)
+    elif kind == "smooth":
+        tex = _stack_bands([smooth_blocks(23, 400 + b, spread=1 + 3 * b) for b in range(16)])
+    elif kind == "random":
+        tex = _stack_bands([random_blocks(9, 500 + b) for b in range(16)])
+    else:
+        rng = np.random.default_rng(4)
+        cols = rng.integers(0, 256, (16, 31, 1, 3))
+        cols[0, :16, 0, :] = np.arange(16)[:, None] * 17
+        tex = rgba(np.repeat(cols, 16, axis=2))
+    say("bc7", kind, tex.shape)
+    blocks, d, sse = _encode_bands(ctx, gsbc, tex, 7)
+    nblk = tex.shape[1]
+    tot = np.zeros(16, np.int64)
+    for b in range(16):
+        rb, rs = O.bc7_encode(tex[b])
+        o = int(d.offsets()[b])
+        assert np.array_equal(blocks[o:o + nblk * 16].reshape(nblk, 16), rb), f"band {b}"
+        tot[b] = rs.astype(np.int64).sum()
+    assert np.array_equal(sse[1], tot)
+
+
+@pytest.mark.parametrize("mask", [0x01, 0x02, 0x04, 0x08, 0x10, 0x20, 0x40, 0x80, 0x81, 0x30])
+def test_bc7_mode_masks(G, mask):
+    gsbc, ctx = G
+    tex = _stack_bands([smooth_blocks(8, 600 + b, spread=4 + 2 * b) for b in range(16)])
+    blocks, d, _ = _encode_bands(ctx, gsbc, tex, 7, bc7_mode_mask=mask)
+    for b in range(16):
+        o = int(d.offsets()[b])
+        assert np.array_equal(blocks[o:o + 8 * 16].reshape(8, 16), O.bc7_encode(tex[b], mask)[0])
+
+
+def test_encoders_full_size_sampled(G):
+    """1,048,576 primitives, all 16 bands in BC1 and in BC7 (1,048,576 blocks
+    per format) in the launch the benchmark times; sampled blocks against the
+    oracle, and each band's reported SSE against the GPU's own decode."""
+    gsbc, ctx = G
+    c = synth.CONFIGS["mid"]
+    pos, sh = synth.make_scene(c["n"], c["clusters"], c["comps"], c["seed"])
+    _, rtex, _, _ = O.reorder(pos, sh)
+    nblk = rtex.shape[1]
+    rng = np.random.default_rng(0)
+    pick = np.sort(rng.choice(nblk, 48, replace=False))
+    pick = np.concatenate([[0], pick, [nblk - 1]])
+    texd = dev(rtex)
+    for fmt in (1, 7):
+        say("full-size encode", fmt)
+        d = _desc_for(gsbc, nblk * 16, [fmt] * 16)
+        blocks, d, sse = ctx.encode(texd, d, fmt=fmt, want_sse=True)
+        hb = host(blocks)
+        bs = 8 if fmt == 1 else 16
+        for b in (0, 1, 5, 15):
+            o = int(d.offsets()[b])
+            stream = hb[o:o + nblk * bs].reshape(nblk, bs)
+            ref = O.bc1_encode(rtex[b][pick])[0] if fmt == 1 else O.bc7_encode(rtex[b][pick])[0]
+            assert np.array_equal(stream[pick], ref), f"band {b}"
+        dec = ctx.decode(blocks, d)
+        diff = dec[..., :3].to(torch.int64) - texd[..., :3].to(torch.int64)
+        err = (diff * diff).sum(dim=(1, 2, 3)).cpu().numpy()
+        assert np.array_equal(err, sse[0 if fmt == 1 else 1])
+
+
+# ---------------------------------------------------------------- rate control
+@pytest.mark.parametrize("rate", [4.25, 6.0, 8.0])
+def test_rate_auto_bit_exact(G, rate):
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(3000 + 9, seed=31)
+    _, rtex, vmin, vmax = O.reorder(pos, sh)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    say("rate", rate)
+    blocks, d2, sse = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=rate, want_sse=True)
+    ref = O.encode_auto(rtex, vmin, vmax, rate)
+    payload, off, fmt = ref
+    assert np.array_equal(d2.formats(), fmt)
+    assert np.array_equal(d2.offsets(), off)
+    assert d2.payload_bytes == payload.size
+    assert np.array_equal(host(blocks)[:payload.size], payload)
+    nblk = rtex.shape[1]
+    block_bits = sum(nblk * (64 if f == 1 else 128) for f in fmt)
+    assert block_bits == rate * 16 * (nblk * 16)
+
+
+def test_rate_infeasible_and_errors(G):
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(100, seed=2)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    for rate in (6.1, 4.0, 9.0):
+        with pytest.raises(gsbc.GsbcError) as e:
+            ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=rate)
+        assert e.value.status == gsbc.E_INFEASIBLE
+    with pytest.raises(gsbc.GsbcError) as e:
+        ctx.encode(tex, d, fmt=3)
+    assert e.value.status == gsbc.E_ARG
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(gsbc.GsbcError) as e:
+        ctx.encode(tex, d, fmt=gsbc.FMT_BC7, blocks=small)
+    assert e.value.status == gsbc.E_BUFFER
+    with pytest.raises(gsbc.GsbcError) as e:
+        ctx.encode(tex, d, fmt=gsbc.FMT_BC1, params=gsbc.default_params(bc7_mode_mask=0))
+    assert e.value.status == gsbc.E_ARG
+    bad = d.copy()
+    bad.n_pad = 7
+    with pytest.raises(gsbc.GsbcError) as e:
+        ctx.encode(tex, bad, fmt=gsbc.FMT_BC1)
+    assert e.value.status == gsbc.E_ARG
+
+
+# ---------------------------------------------------------------- decode_eval
+def _check_colours(out32, ref64, scale):
+    err = np.abs(out32.astype(np.float64) - ref64)
+    assert np.all(err <= REL_TOL * scale), float((err / np.maximum(scale, 1e-30)).max())
+
+
+def _oracle_payload_for_slots(rtex, fmt, slots):
+    """Oracle-encoded payload holding only the blocks the slots live in:
+    returns (payload, offsets, slots renumbered into that payload)."""
+    blk = np.unique(slots // 16)
+    where = {int(b): i for i, b in enumerate(blk)}
+    mini = rtex[:, blk]
+    payload, off, _ = O.encode(mini, fmt)
+    renum = np.array([16 * where[int(s) // 16] + int(s) % 16 for s in slots], np.uint32)
+    return payload, off, renum
+
+
+@pytest.mark.parametrize("n,V", [(65_536, 64), (1000 + 3, 1), (16, 7), (17, 200)])
+def test_decode_eval_all_slots(G, n, V):
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(n, seed=41)
+    dirs = synth.make_dirs(V, seed=41)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    fmt = np.array([7] + [1] * 15, np.uint8)
+    _, rtex, vmin, vmax = O.reorder(pos, sh)
+    payload, off, _ = O.encode(rtex, fmt)
+    blocks, d2, _ = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=4.25)     # k = 0: band 0 BC7, rest BC1
+    assert np.array_equal(d2.formats(), fmt)
+    assert np.array_equal(host(blocks)[:payload.size], payload)
+    say("decode_eval", n, V)
+    out = host(ctx.decode_eval(blocks, d2, dev(dirs)))
+    slots = np.arange(n, dtype=np.uint32)
+    ref, scale = O.decode_eval(payload, off, fmt, vmin, vmax, dirs, slots)
+    _check_colours(out, ref, scale)
+
+
+def test_decode_eval_prim_subset_and_bounds(G):
+    gsbc, ctx = G
+    n = 5000
+    pos, sh = synth.make_scene(n, seed=43)
+    dirs = synth.make_dirs(33, seed=43)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    blocks, d2, _ = ctx.encode(tex, d, fmt=gsbc.FMT_BC7)
+    idx = np.array([4999, 0, 17, 17, 2500, n, n + 100, 123], np.int32)     # two out-of-range ids
+    out = host(ctx.decode_eval(blocks, d2, dev(dirs), prim_idx=dev(idx)))
+    good = idx < n
+    assert np.isnan(out[:, ~good, :]).all()
+    _, rtex, vmin, vmax = O.reorder(pos, sh)
+    fmt = np.full(16, 7, np.uint8)
+    payload, off, renum = _oracle_payload_for_slots(rtex, fmt, idx[good].astype(np.uint32))
+    ref, scale = O.decode_eval(payload, off, fmt, vmin, vmax, dirs, renum)
+    _check_colours(out[:, good, :], ref, scale)
+    full = host(ctx.decode_eval(blocks, d2, dev(dirs)))
+    assert np.array_equal(full[:, idx[good], :], out[:, good, :])
+
+
+def test_decode_eval_large_sampled(G):
+    """3,145,728 primitives, 256 clusters, 1,024 view directions in one launch
+    (38.7 GB of output).  Band 0 BC7, bands 1..15 BC1 (rate 4.25, where the
+    format choice is fixed); sampled outputs against the FP64 oracle on
+    oracle-encoded blocks.  Then the 6 bits/texel choice: exactly 8 BC7
+    bands, exact payload, and the k largest gains of the reported SSEs."""
+    gsbc, ctx = G
+    c = synth.CONFIGS["large"]
+    pos, sh = synth.make_scene(c["n"], c["clusters"], c["comps"], c["seed"])
+    dirs = synth.make_dirs(c["dirs"], seed=c["seed"])
+    say("large reorder+encode")
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    blocks, d2, _ = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=4.25)
+    say("large decode_eval")
+    out = ctx.decode_eval(blocks, d2, dev(dirs))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    slots = np.unique(np.concatenate([[0, c["n"] - 1], rng.integers(0, c["n"], 300)])).astype(np.uint32)
+    vpick = np.unique(np.concatenate([[0, c["dirs"] - 1], rng.integers(0, c["dirs"], 60)]))
+    sub = out[torch.from_numpy(vpick).cuda()][:, torch.from_numpy(slots.astype(np.int64)).cuda(), :].cpu().numpy()
+    del out
+    torch.cuda.empty_cache()
+    _, rtex, vmin, vmax = O.reorder(pos, sh)
+    fmt = np.array([7] + [1] * 15, np.uint8)
+    payload, off, renum = _oracle_payload_for_slots(rtex, fmt, slots)
+    ref, scale = O.decode_eval(payload, off, fmt, vmin, vmax, dirs[vpick], renum)
+    _check_colours(sub, ref, scale)
+
+    say("large rate 6")
+    blocks6, d6, sse = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=c["rate"], want_sse=True)
+    f6 = d6.formats()
+    assert f6[0] == 7 and (f6 == 7).sum() == 8
+    nblk = d6.blocks_per_band
+    assert sum(nblk * (64 if f == 1 else 128) for f in f6) == 6 * 16 * 16 * nblk
+    delta = np.array([np.float32((d6.vmax[k] - d6.vmin[k]) / np.float32(255.0)) for k in range(16)], np.float64)
+    gain = (sse[0] - sse[1]).astype(np.float64) * delta * delta
+    order = sorted(range(1, 16), key=lambda k: (-gain[k], k))
+    assert set(np.nonzero(f6[1:] == 7)[0] + 1) == set(order[:7])
