@@ -153,17 +153,18 @@ __device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, int
     for (int a = 0; a < 3; a++)
 #pragma unroll
         for (int b = a; b < 3; b++) { C[a][b] = 16 * XX[a][b] - S[a] * S[b]; C[b][a] = C[a][b]; }
-    int j = 0;
-    if (C[1][1] > C[j][j]) j = 1;
-    if (C[2][2] > C[j][j]) j = 2;
-    int dmax = C[j][j];
+    // row of the largest diagonal entry (lowest index on ties), by selects
+    const int j = (C[1][1] > C[0][0]) ? ((C[2][2] > C[1][1]) ? 2 : 1) : ((C[2][2] > C[0][0]) ? 2 : 0);
+    const int dmax = j == 0 ? C[0][0] : (j == 1 ? C[1][1] : C[2][2]);
     int tsh = max(0, bitlen(dmax) - 14);
     int Cs[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
         for (int b = 0; b < 3; b++) Cs[a][b] = C[a][b] >> tsh;
-    int v[3] = {Cs[j][0], Cs[j][1], Cs[j][2]};
+    int v[3];
+#pragma unroll
+    for (int b = 0; b < 3; b++) v[b] = j == 0 ? Cs[0][b] : (j == 1 ? Cs[1][b] : Cs[2][b]);
 #pragma unroll
     for (int it = 0; it < 8; it++) {
         int u[3];

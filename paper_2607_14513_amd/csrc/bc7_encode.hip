@@ -29,12 +29,12 @@ namespace {
 constexpr int kBlock = 64;
 
 // ---- tables (device global memory, built on the host at first use)
-// nearest[cls][p][t]: code c minimising |value(c, p) - t| (lowest on ties),
-// cls = (cb - 4) * 2 + has_pbit.
+// nearest[cls][p][t]: code c minimising |value(c, p) - t| (lowest on ties)
+// in the low byte, value(c, p) in the high byte; cls = (cb - 4) * 2 + has_pbit.
 // sv[cls][p0 + 2 p1][slot][v]: single-value pair (c0 | c1 << 8 | err << 16)
 // whose interpolation at weight(nb, K) is nearest v; slot = nb offset + K.
 struct Tables {
-    const uint8_t *nearest;
+    const uint16_t *nearest;
     const uint32_t *sv;
 };
 constexpr int kSlots = 28;
@@ -73,8 +73,8 @@ __device__ __forceinline__ void fit_eval(const int (&x)[16][3], uint32_t mask, c
         int d0[3] = {0, 0, 0}, d1[3] = {0, 0, 0};
 #pragma unroll
         for (int c = 0; c < NCH; c++) {
-            f.c0[c] = T.nearest[(cls * 2 + p0) * 256 + elo[c]];
-            f.c1[c] = T.nearest[(cls * 2 + p1) * 256 + ehi[c]];
+            f.c0[c] = T.nearest[(cls * 2 + p0) * 256 + elo[c]] & 255;
+            f.c1[c] = T.nearest[(cls * 2 + p1) * 256 + ehi[c]] & 255;
             d0[c] = ep_value(f.c0[c], p0, CB, PB);
             d1[c] = ep_value(f.c1[c], p1, CB, PB);
         }
@@ -176,16 +176,17 @@ __device__ __forceinline__ void fit_subset(const int (&x)[16][3], uint32_t mask,
         C[1][1] = n * XX[3] - S[1] * S[1];
         C[1][2] = C[2][1] = n * XX[4] - S[1] * S[2];
         C[2][2] = n * XX[5] - S[2] * S[2];
-        int j = 0;
-        if (C[1][1] > C[j][j]) j = 1;
-        if (C[2][2] > C[j][j]) j = 2;
-        const int tsh = max(0, bitlen(C[j][j]) - 14);
+        // row of the largest diagonal entry (lowest index on ties), by selects
+        const int j = (C[1][1] > C[0][0]) ? ((C[2][2] > C[1][1]) ? 2 : 1) : ((C[2][2] > C[0][0]) ? 2 : 0);
+        const int tsh = max(0, bitlen(j == 0 ? C[0][0] : (j == 1 ? C[1][1] : C[2][2])) - 14);
         int Cs[3][3];
 #pragma unroll
         for (int a = 0; a < 3; a++)
 #pragma unroll
             for (int b = 0; b < 3; b++) Cs[a][b] = C[a][b] >> tsh;
-        int v[3] = {Cs[j][0], Cs[j][1], Cs[j][2]};
+        int v[3];
+#pragma unroll
+        for (int b = 0; b < 3; b++) v[b] = j == 0 ? Cs[0][b] : (j == 1 ? Cs[1][b] : Cs[2][b]);
 #pragma unroll
         for (int it = 0; it < 8; it++) {
             int u[3];
@@ -314,75 +315,365 @@ __device__ __forceinline__ void candidate(int ci, int &m, int &p, int &r, int &s
 }
 
 // ---- pass 1: SSE of every candidate, best key
-__device__ __forceinline__ void consider(uint32_t sse, int ci, uint32_t &best)
+//
+// Texels sit in LDS, one column per lane, as 4x-scaled packed values
+// (rg = 4R | 4G << 16, b = 4B), so one texel x palette-entry distance with
+// its index tie-break is five VALU ops:
+//   d  = rg - prg            (v_pk_sub_i16)
+//   db = b - pb              (v_sub_u32)
+//   k' = db*db + k           (v_mad_i32_i24)       = 16*dB^2 + k
+//   k' = d.x*d.x + d.y*d.y + k'  (v_dot2c_i32_i16)  = 16*SSE + k
+//   best = min(best, k')     (v_min_u32)
+// Subset masks are wave-uniform, so texel loops walk the set bits of the
+// mask with scalar control.  The principal axis and the extreme texels of a
+// subset depend only on the partition, so they are found once and shared by
+// every mode with that partition (2-subset: modes 1, 3, 7; 3-subset: modes 0
+// and 2; whole block: modes 4, 5 and 6).
+constexpr int kSearchWG = 256;
+constexpr int kQEntries = 10 * 2 * 256;
+
+struct SearchLds {
+    uint32_t rg[16][kSearchWG];
+    uint32_t b[16][kSearchWG];
+    uint16_t q[kQEntries];        // nearest-code table: code | value << 8
+};
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+// Texel i of this lane; rotation r puts 4*255 in channel r-1.
+__device__ __forceinline__ void texel(const SearchLds &S, int i, int rot, uint32_t &rg, int &b)
 {
-    uint32_t key = (sse << 9) | (uint32_t)ci;
-    best = key < best ? key : best;
+    rg = S.rg[i][threadIdx.x];
+    b = (int)S.b[i][threadIdx.x];
+    if (rot == 1) rg = (rg & 0xFFFF0000u) | 1020u;
+    else if (rot == 2) rg = (rg & 0xFFFFu) | (1020u << 16);
+    else if (rot == 3) b = 1020;
 }
 
-__device__ uint32_t search(const int (&x)[16][3], uint32_t mode_mask, const Tables &T)
+__device__ __forceinline__ void unpack(uint32_t rg, int b, int (&x)[3])
+{
+    x[0] = (int)((rg & 0xFFFFu) >> 2);
+    x[1] = (int)(rg >> 18);
+    x[2] = b >> 2;
+}
+
+// Per-subset data shared across modes: whether every member is the same
+// colour, and the two endpoint colours (texels of least and greatest
+// projection on the principal axis, or the common colour).
+struct Prep {
+    bool same;
+    int lo[3], hi[3];
+};
+
+__device__ __forceinline__ Prep prep_subset(const SearchLds &S, uint32_t mask, int rot)
+{
+    Prep P;
+    const int first = __ffs(mask) - 1;
+    uint32_t rg0;
+    int b0;
+    texel(S, first, rot, rg0, b0);
+    bool same = true;
+    int Sx[3] = {0, 0, 0}, XX[6] = {0, 0, 0, 0, 0, 0};
+    for (uint32_t m = mask; m; m &= m - 1) {
+        uint32_t rg;
+        int b;
+        texel(S, __ffs(m) - 1, rot, rg, b);
+        same &= (rg == rg0) && (b == b0);
+        int x[3];
+        unpack(rg, b, x);
+        Sx[0] += x[0]; Sx[1] += x[1]; Sx[2] += x[2];
+        XX[0] += x[0] * x[0]; XX[1] += x[0] * x[1]; XX[2] += x[0] * x[2];
+        XX[3] += x[1] * x[1]; XX[4] += x[1] * x[2]; XX[5] += x[2] * x[2];
+    }
+    P.same = same;
+    unpack(rg0, b0, P.lo);
+    P.hi[0] = P.lo[0]; P.hi[1] = P.lo[1]; P.hi[2] = P.lo[2];
+    if (same) return P;
+    const int n = __popc(mask);
+    int C[3][3];
+    C[0][0] = n * XX[0] - Sx[0] * Sx[0];
+    C[0][1] = C[1][0] = n * XX[1] - Sx[0] * Sx[1];
+    C[0][2] = C[2][0] = n * XX[2] - Sx[0] * Sx[2];
+    C[1][1] = n * XX[3] - Sx[1] * Sx[1];
+    C[1][2] = C[2][1] = n * XX[4] - Sx[1] * Sx[2];
+    C[2][2] = n * XX[5] - Sx[2] * Sx[2];
+    // row of the largest diagonal entry (lowest index on ties), by selects
+    const int j = (C[1][1] > C[0][0]) ? ((C[2][2] > C[1][1]) ? 2 : 1) : ((C[2][2] > C[0][0]) ? 2 : 0);
+    const int tsh = max(0, bitlen(j == 0 ? C[0][0] : (j == 1 ? C[1][1] : C[2][2])) - 14);
+    int Cs[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) Cs[a][c] = C[a][c] >> tsh;
+    int v[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) v[c] = j == 0 ? Cs[0][c] : (j == 1 ? Cs[1][c] : Cs[2][c]);
+#pragma unroll
+    for (int it = 0; it < 8; it++) {
+        int u[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) u[a] = Cs[a][0] * v[0] + Cs[a][1] * v[1] + Cs[a][2] * v[2];
+        int mx = max(abs(u[0]), max(abs(u[1]), abs(u[2])));
+        int sh = max(0, bitlen(mx) - 15);
+#pragma unroll
+        for (int a = 0; a < 3; a++) v[a] = u[a] >> sh;
+    }
+    if (v[0] == 0 && v[1] == 0 && v[2] == 0) v[0] = v[1] = v[2] = 1;
+    int plo = 0, phi = 0;
+    bool any = false;
+    for (uint32_t m = mask; m; m &= m - 1) {
+        uint32_t rg;
+        int b;
+        texel(S, __ffs(m) - 1, rot, rg, b);
+        int x[3];
+        unpack(rg, b, x);
+        int p = v[0] * x[0] + v[1] * x[1] + v[2] * x[2];
+        if (!any || p < plo) { plo = p; P.lo[0] = x[0]; P.lo[1] = x[1]; P.lo[2] = x[2]; }
+        if (!any || p > phi) { phi = p; P.hi[0] = x[0]; P.hi[1] = x[1]; P.hi[2] = x[2]; }
+        any = true;
+    }
+    return P;
+}
+
+// (c) for one endpoint pair: best p-bit combination's SSE and indices.
+template <int CB, int PB, int NB>
+__device__ __forceinline__ uint32_t eval_pair(const SearchLds &S, uint32_t mask, int rot, const int (&lo)[3],
+                                              const int (&hi)[3], uint64_t &idx_out)
+{
+    constexpr int NPC = PB == 2 ? 4 : PB == 1 ? 2 : 1;
+    constexpr int cls = cls_of(CB, PB);
+    uint32_t best_sse = 0xFFFFFFFFu;
+    uint64_t best_idx = 0;
+    for (int pc = 0; pc < NPC; pc++) {
+        const int p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
+        const int p1 = PB == 2 ? (pc >> 1) : PB == 1 ? pc : 0;
+        const uint16_t *q0 = S.q + (cls * 2 + p0) * 256, *q1 = S.q + (cls * 2 + p1) * 256;
+        int d0[3], d1[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) { d0[c] = q0[lo[c]] >> 8; d1[c] = q1[hi[c]] >> 8; }
+        uint32_t prg[1 << NB];
+        int pb[1 << NB];
+#pragma unroll
+        for (int k = 0; k < (1 << NB); k++) {
+            const int w = bc7_weight(NB, k);
+            int r = interp64(d0[0], d1[0], w), g = interp64(d0[1], d1[1], w), bb = interp64(d0[2], d1[2], w);
+            prg[k] = ((uint32_t)r << 2) | ((uint32_t)g << 18);
+            pb[k] = bb << 2;
+        }
+        uint32_t sse = 0;
+        uint64_t idx = 0;
+        for (uint32_t m = mask; m; m &= m - 1) {
+            const int i = __ffs(m) - 1;
+            uint32_t rg;
+            int b;
+            texel(S, i, rot, rg, b);
+            uint32_t best = 0xFFFFFFFFu;
+#pragma unroll
+            for (int k = 0; k < (1 << NB); k++) {
+                short2_t d = __builtin_bit_cast(short2_t, rg) - __builtin_bit_cast(short2_t, prg[k]);
+                int db = b - pb[k];
+                int key = __builtin_amdgcn_sdot2(d, d, __mul24(db, db) + k, false);
+                best = min(best, (uint32_t)key);
+            }
+            sse += best >> 4;
+            idx |= (uint64_t)(best & 15u) << (4 * i);
+        }
+        if (sse < best_sse) { best_sse = sse; best_idx = idx; }
+    }
+    idx_out = best_idx;
+    return best_sse;
+}
+
+// (d) least-squares endpoints for the chosen indices; false if singular.
+template <int NB>
+__device__ __forceinline__ bool ls_endpoints(const SearchLds &S, uint32_t mask, int rot, uint64_t idx,
+                                             int (&lo)[3], int (&hi)[3])
+{
+    int A = 0, B = 0, AB = 0, SA[3] = {0, 0, 0}, SB[3] = {0, 0, 0};
+    for (uint32_t m = mask; m; m &= m - 1) {
+        const int i = __ffs(m) - 1;
+        uint32_t rg;
+        int b;
+        texel(S, i, rot, rg, b);
+        int x[3];
+        unpack(rg, b, x);
+        const int k = (int)((idx >> (4 * i)) & 15);
+        const int w = bc7_weight(NB, k), a = 64 - w;
+        A += a * a; B += w * w; AB += a * w;
+#pragma unroll
+        for (int c = 0; c < 3; c++) { SA[c] += a * x[c]; SB[c] += w * x[c]; }
+    }
+    const double det = (double)A * (double)B - (double)AB * (double)AB;
+    if (det == 0.0) return false;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        // exact numerators (< 2^42); a correctly rounded quotient keeps the
+        // floor(x + 1/2) decision of the exact rational for |x| <= 256
+        double n0 = 64.0 * ((double)B * (double)SA[c] - (double)AB * (double)SB[c]);
+        double n1 = 64.0 * ((double)A * (double)SB[c] - (double)AB * (double)SA[c]);
+        double q0 = floor(n0 / det + 0.5), q1 = floor(n1 / det + 0.5);
+        lo[c] = q0 < 0.0 ? 0 : (q0 > 255.0 ? 255 : (int)q0);
+        hi[c] = q1 < 0.0 ? 0 : (q1 > 255.0 ? 255 : (int)q1);
+    }
+    return true;
+}
+
+// SSE of one colour subset fitted with precision (CB, PB) and NB-bit indices.
+template <int CB, int PB, int NB>
+__device__ __forceinline__ uint32_t fit_colour(const SearchLds &S, uint32_t mask, int rot, const Prep &P,
+                                               const uint32_t *sv)
+{
+    constexpr int NPC = PB == 2 ? 4 : PB == 1 ? 2 : 1;
+    constexpr int cls = cls_of(CB, PB);
+    if (P.same) {
+        uint32_t be = 0xFFFFFFFFu;
+        for (int pc = 0; pc < NPC; pc++) {
+            const int p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
+            const int p1 = PB == 2 ? (pc >> 1) : PB == 1 ? pc : 0;
+            for (int k = 0; k < (1 << NB); k++) {
+                const uint32_t *row = sv + ((uint64_t)(cls * 4 + p0 + 2 * p1) * kSlots + slot_of(NB, k)) * 256;
+                uint32_t e = 0;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    uint32_t er = row[P.lo[c]] >> 16;
+                    e += er * er;
+                }
+                be = min(be, e);
+            }
+        }
+        return be * (uint32_t)__popc(mask);
+    }
+    uint64_t idx;
+    uint32_t sse = eval_pair<CB, PB, NB>(S, mask, rot, P.lo, P.hi, idx);
+    int rlo[3], rhi[3];
+    if (ls_endpoints<NB>(S, mask, rot, idx, rlo, rhi)) {
+        uint64_t idx2;
+        sse = min(sse, eval_pair<CB, PB, NB>(S, mask, rot, rlo, rhi, idx2));
+    }
+    return sse;
+}
+
+// SSE of the scalar channel (modes 4, 5, rotation r > 0): 16 values of
+// channel r-1, precision AB bits (no p-bit), NB-bit indices.
+template <int AB, int NB>
+__device__ __forceinline__ uint32_t fit_scalar(const SearchLds &S, int rot, const uint32_t *sv)
+{
+    constexpr int cls = cls_of(AB, 0);
+    auto value = [&](int i) {
+        const uint32_t rg = S.rg[i][threadIdx.x];
+        const int b = (int)S.b[i][threadIdx.x];
+        return rot == 1 ? (int)((rg & 0xFFFFu) >> 2) : rot == 2 ? (int)(rg >> 18) : (b >> 2);
+    };
+    const int v0 = value(0);
+    int lo = v0, hi = v0;
+    bool same = true;
+    for (int i = 1; i < 16; i++) {
+        int v = value(i);
+        same &= v == v0;
+        lo = min(lo, v);
+        hi = max(hi, v);
+    }
+    if (same) {
+        uint32_t be = 0xFFFFFFFFu;
+        for (int k = 0; k < (1 << NB); k++) {
+            uint32_t er = sv[((uint64_t)(cls * 4) * kSlots + slot_of(NB, k)) * 256 + v0] >> 16;
+            be = min(be, er * er);
+        }
+        return be * 16u;
+    }
+    uint32_t best = 0xFFFFFFFFu;
+    int elo = lo, ehi = hi;
+    for (int pass = 0; pass < 2; pass++) {
+        const int d0 = S.q[cls * 2 * 256 + elo] >> 8, d1 = S.q[cls * 2 * 256 + ehi] >> 8;
+        int pal[1 << NB];
+#pragma unroll
+        for (int k = 0; k < (1 << NB); k++) pal[k] = interp64(d0, d1, bc7_weight(NB, k)) << 2;
+        uint32_t sse = 0;
+        int A = 0, B = 0, AB2 = 0, SA = 0, SB = 0;
+        for (int i = 0; i < 16; i++) {
+            const int x = value(i);
+            uint32_t kbest = 0xFFFFFFFFu;
+#pragma unroll
+            for (int k = 0; k < (1 << NB); k++) {
+                int d = (x << 2) - pal[k];
+                kbest = min(kbest, (uint32_t)(__mul24(d, d) + k));
+            }
+            sse += kbest >> 4;
+            const int w = bc7_weight(NB, (int)(kbest & 15u)), a = 64 - w;
+            A += a * a; B += w * w; AB2 += a * w; SA += a * x; SB += w * x;
+        }
+        best = min(best, sse);
+        if (pass == 1) break;
+        const double det = (double)A * (double)B - (double)AB2 * (double)AB2;
+        if (det == 0.0) break;
+        double n0 = 64.0 * ((double)B * (double)SA - (double)AB2 * (double)SB);
+        double n1 = 64.0 * ((double)A * (double)SB - (double)AB2 * (double)SA);
+        double q0 = floor(n0 / det + 0.5), q1 = floor(n1 / det + 0.5);
+        elo = q0 < 0.0 ? 0 : (q0 > 255.0 ? 255 : (int)q0);
+        ehi = q1 < 0.0 ? 0 : (q1 > 255.0 ? 255 : (int)q1);
+    }
+    return best;
+}
+
+__device__ __forceinline__ void consider(uint32_t sse, int ci, uint32_t &best)
+{
+    best = min(best, (sse << 9) | (uint32_t)ci);
+}
+
+// The candidates fall into three groups by partition shape; each group is
+// its own kernel (smaller register footprint), and the block's key is the
+// minimum over the groups.
+template <int GROUP>
+__device__ uint32_t search_group(const SearchLds &S, uint32_t mode_mask, const uint32_t *sv)
 {
     uint32_t best = 0xFFFFFFFFu;
-    Fit f;
-    if (mode_mask & 1)
-        for (int p = 0; p < 16; p++) {
-            uint32_t sse = 0;
-            for (int s = 0; s < 3; s++) { fit_subset<4, 2, 3, 3>(x, mask3(p, s), T, f); sse += f.sse; }
-            consider(sse, p, best);
-        }
-    if (mode_mask & 2)
-        for (int p = 0; p < 64; p++) {
-            uint32_t sse = 0;
-            for (int s = 0; s < 2; s++) { fit_subset<6, 1, 3, 3>(x, mask2(p, s), T, f); sse += f.sse; }
-            consider(sse, 16 + p, best);
-        }
-    if (mode_mask & 4)
-        for (int p = 0; p < 64; p++) {
-            uint32_t sse = 0;
-            for (int s = 0; s < 3; s++) { fit_subset<5, 0, 2, 3>(x, mask3(p, s), T, f); sse += f.sse; }
-            consider(sse, 80 + p, best);
-        }
-    if (mode_mask & 8)
-        for (int p = 0; p < 64; p++) {
-            uint32_t sse = 0;
-            for (int s = 0; s < 2; s++) { fit_subset<7, 2, 2, 3>(x, mask2(p, s), T, f); sse += f.sse; }
-            consider(sse, 144 + p, best);
-        }
-    if (mode_mask & 0x30) {
-        int t[16][3], sc[16][3];
-        for (int r = 0; r < 4; r++) {
-            rotate(x, r, t, sc);
-            if (mode_mask & 0x10) {
-                for (int sel = 0; sel < 2; sel++) {
-                    uint32_t sse;
-                    if (sel == 0) {
-                        fit_subset<5, 0, 2, 3>(t, 0xFFFF, T, f); sse = f.sse;
-                        fit_subset<6, 0, 3, 1>(sc, 0xFFFF, T, f); if (r) sse += f.sse;
-                    } else {
-                        fit_subset<5, 0, 3, 3>(t, 0xFFFF, T, f); sse = f.sse;
-                        fit_subset<6, 0, 2, 1>(sc, 0xFFFF, T, f); if (r) sse += f.sse;
-                    }
-                    consider(sse, 208 + 2 * r + sel, best);
+    if (GROUP == 0) {
+        // 2-subset partitions: modes 1, 3, 7
+        if (mode_mask & 0x8A)
+            for (int p = 0; p < 64; p++) {
+                const uint32_t m0 = mask2(p, 0), m1 = mask2(p, 1);
+                const Prep P0 = prep_subset(S, m0, 0), P1 = prep_subset(S, m1, 0);
+                if (mode_mask & 0x02)
+                    consider(fit_colour<6, 1, 3>(S, m0, 0, P0, sv) + fit_colour<6, 1, 3>(S, m1, 0, P1, sv), 16 + p, best);
+                if (mode_mask & 0x08)
+                    consider(fit_colour<7, 2, 2>(S, m0, 0, P0, sv) + fit_colour<7, 2, 2>(S, m1, 0, P1, sv), 144 + p, best);
+                if (mode_mask & 0x80)
+                    consider(fit_colour<5, 2, 2>(S, m0, 0, P0, sv) + fit_colour<5, 2, 2>(S, m1, 0, P1, sv), 221 + p, best);
+            }
+    } else if (GROUP == 1) {
+        // 3-subset partitions: mode 0 (partitions 0..15), mode 2
+        if (mode_mask & 0x05)
+            for (int p = 0; p < ((mode_mask & 0x04) ? 64 : 16); p++) {
+                const uint32_t m0 = mask3(p, 0), m1 = mask3(p, 1), m2 = mask3(p, 2);
+                const Prep P0 = prep_subset(S, m0, 0), P1 = prep_subset(S, m1, 0), P2 = prep_subset(S, m2, 0);
+                if ((mode_mask & 0x01) && p < 16)
+                    consider(fit_colour<4, 2, 3>(S, m0, 0, P0, sv) + fit_colour<4, 2, 3>(S, m1, 0, P1, sv) +
+                                 fit_colour<4, 2, 3>(S, m2, 0, P2, sv), p, best);
+                if (mode_mask & 0x04)
+                    consider(fit_colour<5, 0, 2>(S, m0, 0, P0, sv) + fit_colour<5, 0, 2>(S, m1, 0, P1, sv) +
+                                 fit_colour<5, 0, 2>(S, m2, 0, P2, sv), 80 + p, best);
+            }
+    } else {
+        // one subset: mode 6, and modes 4 / 5 for every rotation
+        if (mode_mask & 0x70)
+            for (int r = 0; r < 4; r++) {
+                if (r > 0 && !(mode_mask & 0x30)) break;
+                const Prep P = prep_subset(S, 0xFFFFu, r);
+                if (r == 0 && (mode_mask & 0x40)) consider(fit_colour<7, 2, 4>(S, 0xFFFFu, 0, P, sv), 220, best);
+                if (mode_mask & 0x10) {
+                    uint32_t s0 = fit_colour<5, 0, 2>(S, 0xFFFFu, r, P, sv);
+                    uint32_t s1 = fit_colour<5, 0, 3>(S, 0xFFFFu, r, P, sv);
+                    if (r) { s0 += fit_scalar<6, 3>(S, r, sv); s1 += fit_scalar<6, 2>(S, r, sv); }
+                    consider(s0, 208 + 2 * r, best);
+                    consider(s1, 209 + 2 * r, best);
+                }
+                if (mode_mask & 0x20) {
+                    uint32_t s5 = fit_colour<7, 0, 2>(S, 0xFFFFu, r, P, sv);
+                    if (r) s5 += fit_scalar<8, 2>(S, r, sv);
+                    consider(s5, 216 + r, best);
                 }
             }
-            if (mode_mask & 0x20) {
-                uint32_t sse;
-                fit_subset<7, 0, 2, 3>(t, 0xFFFF, T, f); sse = f.sse;
-                fit_subset<8, 0, 2, 1>(sc, 0xFFFF, T, f); if (r) sse += f.sse;
-                consider(sse, 216 + r, best);
-            }
-        }
     }
-    if (mode_mask & 0x40) {
-        fit_subset<7, 2, 4, 3>(x, 0xFFFF, T, f);
-        consider(f.sse, 220, best);
-    }
-    if (mode_mask & 0x80)
-        for (int p = 0; p < 64; p++) {
-            uint32_t sse = 0;
-            for (int s = 0; s < 2; s++) { fit_subset<5, 2, 2, 3>(x, mask2(p, s), T, f); sse += f.sse; }
-            consider(sse, 221 + p, best);
-        }
     return best;
 }
 
@@ -515,38 +806,74 @@ struct Bc7Launch {
     Tables T;
 };
 
-__global__ __launch_bounds__(kBlock) void k_bc7_encode(Bc7Launch L)
+__device__ __forceinline__ void load_block(const EncodeArgs &a, uint64_t g, uint32_t (&t)[16], uint32_t &band,
+                                           uint64_t &b)
+{
+    band = a.band0 + (uint32_t)(g / a.nblk);
+    b = g % a.nblk;
+    const uint4 *src = reinterpret_cast<const uint4 *>(a.textures + ((uint64_t)band * a.nblk + b) * 64);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        uint4 v = src[q];
+        t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
+    }
+}
+
+// Pass 1: the best key of every block over one candidate group, min-combined
+// into the first word of its output slot (group 0 writes it first).
+template <int GROUP>
+__global__ __launch_bounds__(kSearchWG) void k_bc7_search(Bc7Launch L)
+{
+    __shared__ SearchLds S;
+    const EncodeArgs &a = L.a;
+    for (int q = threadIdx.x; q < kQEntries / 2; q += kSearchWG)
+        reinterpret_cast<uint32_t *>(S.q)[q] = reinterpret_cast<const uint32_t *>(L.T.nearest)[q];
+    const uint64_t g = (uint64_t)blockIdx.x * kSearchWG + threadIdx.x;
+    const uint64_t total = (uint64_t)a.nbands * a.nblk;
+    uint32_t t[16] = {0};
+    uint32_t band = 0;
+    uint64_t b = 0;
+    if (g < total) load_block(a, g, t, band, b);
+#pragma unroll
+    for (int i = 0; i < 16; i++) {
+        S.rg[i][threadIdx.x] = ((t[i] & 255u) << 2) | (((t[i] >> 8) & 255u) << 18);
+        S.b[i][threadIdx.x] = ((t[i] >> 16) & 255u) << 2;
+    }
+    __syncthreads();
+    if (g >= total) return;
+    uint32_t key = search_group<GROUP>(S, a.mode_mask, L.T.sv);
+    uint32_t *slot = reinterpret_cast<uint32_t *>(a.out + a.out_offset[band] + b * 16);
+    *slot = GROUP == 0 ? key : min(key, *slot);
+}
+
+// Pass 2: re-fit each block's winning candidate and write its bits.
+__global__ __launch_bounds__(kBlock) void k_bc7_emit(Bc7Launch L)
 {
     const EncodeArgs &a = L.a;
     const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint64_t total = (uint64_t)a.nbands * a.nblk;
     if (g >= total) return;
-    const uint32_t band = a.band0 + (uint32_t)(g / a.nblk);
-    const uint64_t b = g % a.nblk;
-    const uint4 *src = reinterpret_cast<const uint4 *>(a.textures + ((uint64_t)band * a.nblk + b) * 64);
+    uint32_t t[16], band;
+    uint64_t b;
+    load_block(a, g, t, band, b);
     int x[16][3];
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        uint4 v = src[q];
-        uint32_t t[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int e = 0; e < 4; e++) {
-            x[4 * q + e][0] = t[e] & 255;
-            x[4 * q + e][1] = (t[e] >> 8) & 255;
-            x[4 * q + e][2] = (t[e] >> 16) & 255;
-        }
+    for (int i = 0; i < 16; i++) {
+        x[i][0] = t[i] & 255;
+        x[i][1] = (t[i] >> 8) & 255;
+        x[i][2] = (t[i] >> 16) & 255;
     }
-    uint32_t key = search(x, a.mode_mask, L.T);
+    uint8_t *slot = a.out + a.out_offset[band] + b * 16;
+    const uint32_t key = *reinterpret_cast<const uint32_t *>(slot);
     uint64_t lo, hi;
     emit(x, (int)(key & 511u), L.T, lo, hi);
-    ulonglong2 *dst = reinterpret_cast<ulonglong2 *>(a.out + a.out_offset[band] + b * 16);
-    *dst = make_ulonglong2(lo, hi);
+    *reinterpret_cast<ulonglong2 *>(slot) = make_ulonglong2(lo, hi);
     if (a.band_sse) atomicAdd(&a.band_sse[band], (unsigned long long)(key >> 9));
 }
 
 // ---- host-side table construction
 struct HostTables {
-    std::vector<uint8_t> nearest;   // [10][2][256]
+    std::vector<uint16_t> nearest;  // [10][2][256]
     std::vector<uint32_t> sv;       // [10][4][kSlots][256]
 };
 
@@ -558,7 +885,7 @@ void build_nearest(HostTables &H)
             for (int p = 0; p < 2; p++) {
                 if (!pb && p) continue;
                 const int nc = 1 << cb;
-                uint8_t *row = &H.nearest[(cls_of(cb, pb) * 2 + p) * 256];
+                uint16_t *row = &H.nearest[(cls_of(cb, pb) * 2 + p) * 256];
                 for (int t = 0; t < 256; t++) {
                     int bc = 0, bd = 1 << 30;
                     for (int c = 0; c < nc; c++) {
@@ -566,7 +893,7 @@ void build_nearest(HostTables &H)
                         d = d < 0 ? -d : d;
                         if (d < bd) { bd = d; bc = c; }
                     }
-                    row[t] = (uint8_t)bc;
+                    row[t] = (uint16_t)(bc | (ep_value(bc, p, cb, pb) << 8));
                 }
             }
 }
@@ -639,7 +966,7 @@ hipError_t upload_bc7_tables(int device, hipStream_t st)
     static HostTables H;
     static bool built = false;
     if (!built) { build_nearest(H); build_sv(H); built = true; }
-    size_t nb = H.nearest.size(), sb = H.sv.size() * 4;
+    size_t nb = H.nearest.size() * 2, sb = H.sv.size() * 4;
     void *p = nullptr;
     hipError_t e = hipMalloc(&p, nb + sb);
     if (e != hipSuccess) return e;
@@ -661,9 +988,13 @@ hipError_t launch_bc7_encode(const EncodeArgs &a, hipStream_t st)
     if (total == 0) return hipSuccess;
     Bc7Launch L;
     L.a = a;
-    L.T.nearest = static_cast<const uint8_t *>(g_tab[dev]);
-    L.T.sv = reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(g_tab[dev]) + 10 * 2 * 256);
-    hipLaunchKernelGGL(k_bc7_encode, dim3((uint32_t)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, L);
+    L.T.nearest = static_cast<const uint16_t *>(g_tab[dev]);
+    L.T.sv = reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(g_tab[dev]) + 10 * 2 * 256 * 2);
+    const dim3 sgrid((uint32_t)((total + kSearchWG - 1) / kSearchWG));
+    hipLaunchKernelGGL(k_bc7_search<0>, sgrid, dim3(kSearchWG), 0, st, L);
+    hipLaunchKernelGGL(k_bc7_search<1>, sgrid, dim3(kSearchWG), 0, st, L);
+    hipLaunchKernelGGL(k_bc7_search<2>, sgrid, dim3(kSearchWG), 0, st, L);
+    hipLaunchKernelGGL(k_bc7_emit, dim3((uint32_t)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, L);
     return hipGetLastError();
 }
 
