@@ -10,9 +10,10 @@ mixture, Laplacian higher bands; seed 2), i.e. 1,048,576 blocks per format.
 
 Prints one JSON line.  `value` = blocks encoded per step (both formats) /
 step time, in Mblocks/s.  Also reported:
-  roofline            BC7 encode (the dominant kernel): algorithmic integer
-                      lane-ops per launch / its average launch time (HIP
-                      events on the library's stream), against the VALU peak;
+  roofline            the step's dominant kernel (a BC7 search kernel):
+                      algorithmic integer ops per launch / its average launch
+                      time (HIP events the library records on its stream),
+                      against the VALU peak;
   roofline_decode_eval  decode + SH evaluation of 3,145,728 primitives at
                       1,024 directions: bytes written+read per launch / time,
                       against 8 TB/s;
@@ -31,8 +32,15 @@ sys.path.insert(0, ROOT)
 
 VALU_PEAK = 256 * 4 * 16 * 2.4e9        # integer lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz
 HBM_PEAK = 8.0e12                        # bytes/s
-BC7_EVALS_PER_BLOCK = 129_024            # texel x palette distance evaluations of the BC7 search
-OPS_PER_EVAL = 8                         # 3 sub + 3 mul + 1 add chain + 1 min, per evaluation
+OPS_PER_EVAL = 8                         # one texel x palette-entry distance: 3 sub, 3 mul, 2 add
+# Algorithmic work per block of the BC7 search kernels: texel x palette-entry
+# distance evaluations of the candidates each kernel covers (initial fit and
+# least-squares refit, every p-bit choice) x OPS_PER_EVAL.
+ALGO_OPS = {
+    "bc7_search_2subset": 3 * 32_768 * OPS_PER_EVAL,            # modes 1, 3, 7
+    "bc7_search_3subset": (16_384 + 8_192) * OPS_PER_EVAL,     # modes 0, 2
+    "bc7_search_1subset": (3_072 + 1_024 + 2_048) * OPS_PER_EVAL,  # modes 4, 5, 6
+}
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
@@ -118,35 +126,42 @@ def main():
         blocks_per_step = 2 * 16 * nblk
         value = blocks_per_step / (ms_step * 1e-3) / 1e6
 
-        # ---- dominant kernel: BC7 encode of all 16 bands (one launch), HIP events on the stream
-        d7 = d2.copy()
-        t7 = []
-        for i in range(max(3, args.steps)):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            ctx.encode(tex, d7, fmt=gsbc.FMT_BC7, blocks=blocks)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            t7.append(e0.elapsed_time(e1) * 1e-3)
-        t1 = []
-        for i in range(max(3, args.steps)):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            ctx.encode(tex, d7, fmt=gsbc.FMT_BC1, blocks=blocks)
-            e1.record(stream)
-            torch.cuda.synchronize()
-            t1.append(e0.elapsed_time(e1) * 1e-3)
-        bc7_s = float(np.mean(t7))
-        bc7_blocks = 16 * nblk
-        bc7_ops = bc7_blocks * BC7_EVALS_PER_BLOCK * OPS_PER_EVAL
+        # ---- per-kernel device times of the same step (HIP events the library
+        # records on its stream around every launch)
+        ctx.profile(True)
+        ctx.profile_read()
+        nprof = max(3, args.steps)
+        for _ in range(nprof):
+            step()
+        kern = ctx.profile_read()
+        ctx.profile(False)
+        per_step = {k: v[1] / nprof for k, v in kern.items()}
+        dom = max(per_step, key=per_step.get)
+        launches = kern[dom][0] / nprof
+        dom_s = per_step[dom] / launches * 1e-3                     # average launch, s
+        units = 16 * nblk                                           # blocks per launch
+        work = ALGO_OPS.get(dom)
         traffic = None
         if os.path.exists(TRAFFIC):
-            tr = json.load(open(TRAFFIC))
-            traffic = tr.get("k_bc7_encode")
-        roof = {"kernel": "k_bc7_encode", "bound": "alu", "achieved": bc7_ops / bc7_s / 1e12,
-                "peak": VALU_PEAK / 1e12, "unit": "Tops/s", "frac": bc7_ops / bc7_s / VALU_PEAK,
-                "traffic": traffic, "launch_ms": bc7_s * 1e3,
-                "algorithmic_ops_per_block": BC7_EVALS_PER_BLOCK * OPS_PER_EVAL}
+            traffic = json.load(open(TRAFFIC)).get(dom)
+        roof = {"kernel": dom, "bound": "alu", "achieved": work * units / dom_s / 1e12 if work else None,
+                "peak": VALU_PEAK / 1e12, "unit": "Tops/s",
+                "frac": work * units / dom_s / VALU_PEAK if work else None, "traffic": traffic,
+                "launch_ms": round(dom_s * 1e3, 4), "algorithmic_ops_per_block": work, "blocks_per_launch": units}
+
+        # ---- whole-format encode rates (every band in one format)
+        d7 = d2.copy()
+        rates = {}
+        for fmt, name in ((gsbc.FMT_BC7, "bc7"), (gsbc.FMT_BC1, "bc1")):
+            ts = []
+            for i in range(max(3, args.steps)):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                ctx.encode(tex, d7, fmt=fmt, blocks=blocks)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+            rates[name] = 16 * nblk / float(np.mean(ts)) / 1e6
 
         # ---- decode_eval on the 3,145,728-primitive scene at 1,024 directions
         roof_de = None
@@ -162,15 +177,23 @@ def main():
             out3 = torch.empty((c3["dirs"], c3["n"], 3), dtype=torch.float32, device=dev)
             ctx.decode_eval(b3, dd2, dirs3, out=out3)
             torch.cuda.synchronize()
-            tde = []
+            ctx.profile(True)
+            ctx.profile_read()
+            for i in range(3):
+                ctx.decode_eval(b3, dd2, dirs3, out=out3)
+            kd = ctx.profile_read()
+            ctx.profile(False)
+            de_s = kd["decode_eval"][1] / kd["decode_eval"][0] * 1e-3
+            # context: a plain device fill of the same output (write ceiling)
+            tf = []
             for i in range(3):
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record(stream)
-                ctx.decode_eval(b3, dd2, dirs3, out=out3)
+                out3.fill_(0.0)
                 e1.record(stream)
                 torch.cuda.synchronize()
-                tde.append(e0.elapsed_time(e1) * 1e-3)
-            de_s = float(np.mean(tde))
+                tf.append(e0.elapsed_time(e1) * 1e-3)
+            fill_gbps = out3.numel() * 4 / float(np.mean(tf)) / 1e9
             de_bytes = c3["dirs"] * c3["n"] * 12 + dd2.payload_bytes + c3["dirs"] * 12
             tr_de = None
             if os.path.exists(TRAFFIC):
@@ -178,7 +201,8 @@ def main():
             roof_de = {"kernel": "k_decode_eval", "bound": "hbm", "achieved": de_bytes / de_s / 1e9,
                        "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": de_bytes / de_s / HBM_PEAK,
                        "traffic": tr_de, "launch_ms": de_s * 1e3,
-                       "workload": "3,145,728 primitives x 1,024 directions, 6 bits/texel"}
+                       "workload": "3,145,728 primitives x 1,024 directions, 6 bits/texel",
+                       "plain_fill_gbps": round(fill_gbps, 1)}
             del out3, b3
             torch.cuda.empty_cache()
         ctx.close()
@@ -196,8 +220,9 @@ def main():
         "stages_ms": {"reorder": round(float(stage[:, 0].mean()), 3),
                       "encode_auto": round(float(stage[:, 1].mean()), 3),
                       "decode_eval": round(float(stage[:, 2].mean()), 3)},
-        "bc7_encode_mblocks_s": round(bc7_blocks / bc7_s / 1e6, 3),
-        "bc1_encode_mblocks_s": round(16 * nblk / float(np.mean(t1)) / 1e6, 3),
+        "bc7_encode_mblocks_s": round(rates["bc7"], 3),
+        "bc1_encode_mblocks_s": round(rates["bc1"], 3),
+        "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "roofline": roof,
         "roofline_decode_eval": roof_de,
         "cpu_baseline": cpu,

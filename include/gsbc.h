@@ -166,6 +166,21 @@ GSBC_API gsbc_status gsbc_decode_eval(gsbc_ctx *ctx, const uint8_t *blocks, cons
                              const float *dirs, uint32_t n_dirs, const uint32_t *prim_idx,
                              uint64_t m, float *out);
 
+/* ---------------------------------------------------------------- tracing */
+
+/* Kernel timing, a tracing aid.  While enabled, every kernel this context
+ * launches is bracketed by HIP events on the context's stream (so the times
+ * are device times of that stream).  gsbc_profile_read waits for the stream,
+ * then returns per kernel name (at most max_entries of them, in first-launch
+ * order) the number of launches and their total milliseconds since the
+ * previous read, and forgets them.
+ *   names   host char[max_entries][64] out (NUL-terminated kernel names)
+ *   counts  host uint32[max_entries] out;  ms  host double[max_entries] out
+ *   n_out   host out: number of entries written */
+GSBC_API gsbc_status gsbc_profile_enable(gsbc_ctx *ctx, int on);
+GSBC_API gsbc_status gsbc_profile_read(gsbc_ctx *ctx, uint32_t max_entries, char *names, uint32_t *counts,
+                                       double *ms, uint32_t *n_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,8 +12,10 @@
 
 #include <algorithm>
 #include <atomic>
+#include <vector>
 
 using namespace gsbc;
+
 
 struct gsbc_ctx {
     int device = 0;
@@ -24,9 +26,22 @@ struct gsbc_ctx {
     void *small = nullptr;          // fixed device block: range, selection, SSE sums, offsets
     void *pinned = nullptr;         // host staging for read-backs
     char err[512] = {0};
+    // kernel timing (gsbc_profile_enable)
+    bool profiling = false;
+    struct Rec { const char *name; size_t ev; };
+    std::vector<hipEvent_t> events;  // pairs: 2k start, 2k+1 end
+    std::vector<Rec> recs;
 };
 
 namespace {
+
+// The context whose call is running on this thread (for the timing hooks).
+thread_local gsbc_ctx *t_active = nullptr;
+
+struct ActiveGuard {
+    explicit ActiveGuard(gsbc_ctx *c) { t_active = c; }
+    ~ActiveGuard() { t_active = nullptr; }
+};
 
 // Device "small" block layout
 constexpr size_t kRangeOff = 0;                  // RangeRec
@@ -163,6 +178,31 @@ char *small_ptr(gsbc_ctx *ctx, size_t off) { return static_cast<char *>(ctx->sma
 
 }  // namespace
 
+namespace gsbc {
+
+void trace_begin(const char *kernel, hipStream_t st)
+{
+    gsbc_ctx *c = t_active;
+    if (!c || !c->profiling) return;
+    size_t k = c->recs.size();
+    while (c->events.size() < 2 * (k + 1)) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        c->events.push_back(e);
+    }
+    c->recs.push_back({kernel, 2 * k});
+    (void)hipEventRecord(c->events[2 * k], st);
+}
+
+void trace_end(hipStream_t st)
+{
+    gsbc_ctx *c = t_active;
+    if (!c || !c->profiling || c->recs.empty()) return;
+    (void)hipEventRecord(c->events[c->recs.back().ev + 1], st);
+}
+
+}  // namespace gsbc
+
 extern "C" {
 
 void gsbc_default_params(gsbc_params *p)
@@ -212,6 +252,7 @@ gsbc_status gsbc_destroy(gsbc_ctx *ctx)
     gsbc_status s = GSBC_OK;
     if (hipSetDevice(ctx->device) != hipSuccess) s = GSBC_E_DEVICE;
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) s = GSBC_E_DEVICE;
+    for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
     if (ctx->arena) (void)hipFree(ctx->arena);
     if (ctx->small) (void)hipFree(ctx->small);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -226,6 +267,7 @@ gsbc_status gsbc_sync(gsbc_ctx *ctx)
 {
     gsbc_status s = begin(ctx);
     if (s) return s;
+    ActiveGuard guard(ctx);
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
     return GSBC_OK;
 }
@@ -246,6 +288,7 @@ gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, uint6
 {
     gsbc_status s = begin(ctx);
     if (s) return s;
+    ActiveGuard guard(ctx);
     if (!pos || !sh || !perm || !textures || !desc) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
     if (n == 0 || n > 0x7FFFFFFFull) return fail(ctx, GSBC_E_ARG, "n = %llu not in 1..2^31-1", (unsigned long long)n);
     if ((reinterpret_cast<uintptr_t>(sh) & 15) || (reinterpret_cast<uintptr_t>(textures) & 15) ||
@@ -272,6 +315,7 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
 {
     gsbc_status s = begin(ctx);
     if (s) return s;
+    ActiveGuard guard(ctx);
     if (!textures || !blocks) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
     if ((reinterpret_cast<uintptr_t>(textures) & 15) || (reinterpret_cast<uintptr_t>(blocks) & 15))
         return fail(ctx, GSBC_E_ARG, "textures and blocks must be 16-byte aligned");
@@ -303,6 +347,8 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
         if (blocks_capacity < payload)
             return fail(ctx, GSBC_E_BUFFER, "blocks_capacity %llu < payload %llu bytes", (unsigned long long)blocks_capacity,
                         (unsigned long long)payload);
+        if ((s = ensure_arena(ctx, bc7_scratch_bytes(16 * nblk)))) return s;
+        a.keys = static_cast<uint32_t *>(ctx->arena);
         HIP_TRY(ctx, launch_fill_u64(sse1, 32, 0, ctx->stream), "clear");
         a.band0 = 0;
         a.nbands = 16;
@@ -320,8 +366,9 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
             return fail(ctx, GSBC_E_BUFFER, "blocks_capacity %llu < payload %llu bytes", (unsigned long long)blocks_capacity,
                         (unsigned long long)payload);
         const uint64_t s1 = align16(8 * nblk), s7 = 16 * nblk;
-        if ((s = ensure_arena(ctx, 16 * s1 + 16 * s7))) return s;
+        if ((s = ensure_arena(ctx, 16 * s1 + 16 * s7 + bc7_scratch_bytes(16 * nblk)))) return s;
         uint8_t *buf1 = static_cast<uint8_t *>(ctx->arena), *buf7 = buf1 + 16 * s1;
+        a.keys = reinterpret_cast<uint32_t *>(buf7 + 16 * s7);
         uint64_t off1[16], off7[16];
         for (int q = 0; q < 16; q++) { off1[q] = q * s1; off7[q] = q * s7; }
         uint64_t *doff1 = reinterpret_cast<uint64_t *>(small_ptr(ctx, kOff1Off));
@@ -374,6 +421,7 @@ gsbc_status gsbc_decode(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_
 {
     gsbc_status s = begin(ctx);
     if (s) return s;
+    ActiveGuard guard(ctx);
     if (!blocks || !textures_out) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
     if ((reinterpret_cast<uintptr_t>(blocks) & 15) || (reinterpret_cast<uintptr_t>(textures_out) & 15))
         return fail(ctx, GSBC_E_ARG, "blocks and textures_out must be 16-byte aligned");
@@ -387,6 +435,7 @@ gsbc_status gsbc_decode_eval(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_st
 {
     gsbc_status s = begin(ctx);
     if (s) return s;
+    ActiveGuard guard(ctx);
     if (!blocks || !dirs || !out) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
     if (reinterpret_cast<uintptr_t>(blocks) & 15) return fail(ctx, GSBC_E_ARG, "blocks must be 16-byte aligned");
     if ((reinterpret_cast<uintptr_t>(dirs) & 3) || (reinterpret_cast<uintptr_t>(out) & 3) ||
@@ -400,6 +449,42 @@ gsbc_status gsbc_decode_eval(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_st
     if ((s = ensure_arena(ctx, (size_t)n_dirs * 16 * sizeof(float)))) return s;
     HIP_TRY(ctx, launch_decode_eval(blocks, band_args(desc), desc->n_prims, dirs, n_dirs, prim_idx, m, out,
                                     static_cast<float *>(ctx->arena), ctx->stream), "decode_eval launch");
+    return GSBC_OK;
+}
+
+gsbc_status gsbc_profile_enable(gsbc_ctx *ctx, int on)
+{
+    gsbc_status s = begin(ctx);
+    if (s) return s;
+    ctx->profiling = on != 0;
+    return GSBC_OK;
+}
+
+gsbc_status gsbc_profile_read(gsbc_ctx *ctx, uint32_t max_entries, char *names, uint32_t *counts, double *ms,
+                              uint32_t *n_out)
+{
+    gsbc_status s = begin(ctx);
+    if (s) return s;
+    if (!n_out || (max_entries && (!names || !counts || !ms))) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
+    uint32_t n = 0;
+    for (const gsbc_ctx::Rec &r : ctx->recs) {
+        float t = 0.0f;
+        HIP_TRY(ctx, hipEventElapsedTime(&t, ctx->events[r.ev], ctx->events[r.ev + 1]), "hipEventElapsedTime");
+        uint32_t q = 0;
+        while (q < n && strncmp(names + 64 * q, r.name, 63) != 0) q++;
+        if (q == n) {
+            if (n == max_entries) continue;
+            snprintf(names + 64 * n, 64, "%s", r.name);
+            counts[n] = 0;
+            ms[n] = 0.0;
+            n++;
+        }
+        counts[q]++;
+        ms[q] += t;
+    }
+    ctx->recs.clear();
+    *n_out = n;
     return GSBC_OK;
 }
 

@@ -294,9 +294,10 @@ __device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, int
 __global__ __launch_bounds__(kBlock) void k_bc1_encode(EncodeArgs a)
 {
     __shared__ int sP[17 * 3 * kBlock];
-    const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const uint64_t g0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint64_t total = (uint64_t)a.nbands * a.nblk;
-    if (g >= total) return;
+    const bool live = g0 < total;
+    const uint64_t g = live ? g0 : total - 1;   // past-the-end lanes redo the last block, write nothing
     const uint32_t band = a.band0 + (uint32_t)(g / a.nblk);
     const uint64_t b = g % a.nblk;
     const uint4 *src = reinterpret_cast<const uint4 *>(a.textures + ((uint64_t)band * a.nblk + b) * 64);
@@ -308,10 +309,12 @@ __global__ __launch_bounds__(kBlock) void k_bc1_encode(EncodeArgs a)
     }
     uint32_t w0, w1, sse;
     encode_block(t, a.refine_steps, sP + threadIdx.x, w0, w1, sse);
-    uint2 *dst = reinterpret_cast<uint2 *>(a.out + a.out_offset[band] + b * 8);
-    *dst = make_uint2(w0, w1);
-    if (b == a.nblk - 1 && (a.nblk & 1)) dst[1] = make_uint2(0, 0);   // 16-byte stream alignment
-    if (a.band_sse) atomicAdd(&a.band_sse[band], (unsigned long long)sse);
+    if (live) {
+        uint2 *dst = reinterpret_cast<uint2 *>(a.out + a.out_offset[band] + b * 8);
+        *dst = make_uint2(w0, w1);
+        if (b == a.nblk - 1 && (a.nblk & 1)) dst[1] = make_uint2(0, 0);   // 16-byte stream alignment
+    }
+    if (a.band_sse) band_add(a.band_sse, band, sse, live);
 }
 
 // Host-side construction of the constant-colour tables: for each channel
@@ -364,7 +367,7 @@ hipError_t launch_bc1_encode(const EncodeArgs &a, hipStream_t st)
 {
     uint64_t total = (uint64_t)a.nbands * a.nblk;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bc1_encode, dim3((uint32_t)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a);
+    GSBC_LAUNCH("bc1_encode", k_bc1_encode, dim3((uint32_t)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a);
     return hipGetLastError();
 }
 

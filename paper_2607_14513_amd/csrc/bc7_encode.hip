@@ -26,8 +26,6 @@
 namespace gsbc {
 namespace {
 
-constexpr int kBlock = 64;
-
 // ---- tables (device global memory, built on the host at first use)
 // nearest[cls][p][t]: code c minimising |value(c, p) - t| (lowest on ties)
 // in the low byte, value(c, p) in the high byte; cls = (cb - 4) * 2 + has_pbit.
@@ -48,231 +46,6 @@ __host__ __device__ constexpr int ep_value(int code, int p, int cb, int pb)
 
 __device__ __forceinline__ int bitlen(int x) { return 32 - __clz(x); }
 
-// ---- one subset fit
-struct Fit {
-    int c0[3], c1[3];
-    int p0, p1;
-    uint32_t sse;
-    uint64_t idx;   // 4 bits per texel (members only)
-};
-
-template <int CB, int PB, int NB, int NCH>
-__device__ __forceinline__ void fit_eval(const int (&x)[16][3], uint32_t mask, const int (&elo)[3],
-                                         const int (&ehi)[3], const Tables &T, Fit &out)
-{
-    constexpr int NPC = PB == 2 ? 4 : PB == 1 ? 2 : 1;
-    constexpr int cls = cls_of(CB, PB);
-    out.sse = 0xFFFFFFFFu;
-#pragma unroll
-    for (int pc = 0; pc < NPC; pc++) {
-        const int p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
-        const int p1 = PB == 2 ? (pc >> 1) : PB == 1 ? pc : 0;
-        Fit f;
-        f.p0 = p0;
-        f.p1 = p1;
-        int d0[3] = {0, 0, 0}, d1[3] = {0, 0, 0};
-#pragma unroll
-        for (int c = 0; c < NCH; c++) {
-            f.c0[c] = T.nearest[(cls * 2 + p0) * 256 + elo[c]] & 255;
-            f.c1[c] = T.nearest[(cls * 2 + p1) * 256 + ehi[c]] & 255;
-            d0[c] = ep_value(f.c0[c], p0, CB, PB);
-            d1[c] = ep_value(f.c1[c], p1, CB, PB);
-        }
-        int pal[1 << NB][3];
-#pragma unroll
-        for (int k = 0; k < (1 << NB); k++)
-#pragma unroll
-            for (int c = 0; c < NCH; c++) pal[k][c] = interp64(d0[c], d1[c], bc7_weight(NB, k));
-        uint32_t sse = 0;
-        uint64_t idx = 0;
-#pragma unroll
-        for (int i = 0; i < 16; i++) {
-            if (!((mask >> i) & 1)) continue;
-            uint32_t best = 0xFFFFFFFFu;
-#pragma unroll
-            for (int k = 0; k < (1 << NB); k++) {
-                uint32_t d = 0;
-#pragma unroll
-                for (int c = 0; c < NCH; c++) {
-                    int e = x[i][c] - pal[k][c];
-                    d += (uint32_t)(e * e);
-                }
-                uint32_t key = (d << 4) | (uint32_t)k;   // d < 2^18; lowest index on ties
-                best = key < best ? key : best;
-            }
-            sse += best >> 4;
-            idx |= (uint64_t)(best & 15u) << (4 * i);
-        }
-        f.sse = sse;
-        f.idx = idx;
-        if (sse < out.sse) out = f;
-    }
-}
-
-template <int CB, int PB, int NB, int NCH>
-__device__ __forceinline__ void fit_subset(const int (&x)[16][3], uint32_t mask, const Tables &T, Fit &out)
-{
-    constexpr int NPC = PB == 2 ? 4 : PB == 1 ? 2 : 1;
-    constexpr int cls = cls_of(CB, PB);
-    const int first = __ffs(mask) - 1;
-    const int n = __popc(mask);
-    bool same = true;
-#pragma unroll
-    for (int i = 0; i < 16; i++)
-        if ((mask >> i) & 1)
-#pragma unroll
-            for (int c = 0; c < NCH; c++) same &= x[i][c] == x[first][c];
-    if (same) {
-        // (a) single value: best (p-bits, index) over per-channel tables
-        out.sse = 0xFFFFFFFFu;
-        int v[3] = {0, 0, 0};
-#pragma unroll
-        for (int c = 0; c < NCH; c++) v[c] = x[first][c];
-#pragma unroll
-        for (int pc = 0; pc < NPC; pc++) {
-            const int p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
-            const int p1 = PB == 2 ? (pc >> 1) : PB == 1 ? pc : 0;
-            for (int k = 0; k < (1 << NB); k++) {
-                const uint32_t *row = T.sv + ((uint64_t)(cls * 4 + p0 + 2 * p1) * kSlots + slot_of(NB, k)) * 256;
-                uint32_t e = 0;
-                uint32_t ent[3] = {0, 0, 0};
-#pragma unroll
-                for (int c = 0; c < NCH; c++) {
-                    ent[c] = row[v[c]];
-                    uint32_t er = ent[c] >> 16;
-                    e += er * er;
-                }
-                if (e < out.sse) {
-                    out.sse = e;
-                    out.p0 = p0;
-                    out.p1 = p1;
-#pragma unroll
-                    for (int c = 0; c < NCH; c++) { out.c0[c] = ent[c] & 255; out.c1[c] = (ent[c] >> 8) & 255; }
-                    uint64_t idx = 0;
-#pragma unroll
-                    for (int i = 0; i < 16; i++) idx |= (uint64_t)k << (4 * i);
-                    out.idx = idx;
-                }
-            }
-        }
-        out.sse *= (uint32_t)n;
-        return;
-    }
-    // (b) endpoints: least and greatest projection on the principal axis
-    int elo[3] = {0, 0, 0}, ehi[3] = {0, 0, 0};
-    if (NCH == 3) {
-        int S[3] = {0, 0, 0}, XX[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int i = 0; i < 16; i++) {
-            if (!((mask >> i) & 1)) continue;
-            S[0] += x[i][0]; S[1] += x[i][1]; S[2] += x[i][2];
-            XX[0] += x[i][0] * x[i][0]; XX[1] += x[i][0] * x[i][1]; XX[2] += x[i][0] * x[i][2];
-            XX[3] += x[i][1] * x[i][1]; XX[4] += x[i][1] * x[i][2]; XX[5] += x[i][2] * x[i][2];
-        }
-        int C[3][3];
-        C[0][0] = n * XX[0] - S[0] * S[0];
-        C[0][1] = C[1][0] = n * XX[1] - S[0] * S[1];
-        C[0][2] = C[2][0] = n * XX[2] - S[0] * S[2];
-        C[1][1] = n * XX[3] - S[1] * S[1];
-        C[1][2] = C[2][1] = n * XX[4] - S[1] * S[2];
-        C[2][2] = n * XX[5] - S[2] * S[2];
-        // row of the largest diagonal entry (lowest index on ties), by selects
-        const int j = (C[1][1] > C[0][0]) ? ((C[2][2] > C[1][1]) ? 2 : 1) : ((C[2][2] > C[0][0]) ? 2 : 0);
-        const int tsh = max(0, bitlen(j == 0 ? C[0][0] : (j == 1 ? C[1][1] : C[2][2])) - 14);
-        int Cs[3][3];
-#pragma unroll
-        for (int a = 0; a < 3; a++)
-#pragma unroll
-            for (int b = 0; b < 3; b++) Cs[a][b] = C[a][b] >> tsh;
-        int v[3];
-#pragma unroll
-        for (int b = 0; b < 3; b++) v[b] = j == 0 ? Cs[0][b] : (j == 1 ? Cs[1][b] : Cs[2][b]);
-#pragma unroll
-        for (int it = 0; it < 8; it++) {
-            int u[3];
-#pragma unroll
-            for (int a = 0; a < 3; a++) u[a] = Cs[a][0] * v[0] + Cs[a][1] * v[1] + Cs[a][2] * v[2];
-            int m = max(abs(u[0]), max(abs(u[1]), abs(u[2])));
-            int s = max(0, bitlen(m) - 15);
-#pragma unroll
-            for (int a = 0; a < 3; a++) v[a] = u[a] >> s;
-        }
-        if (v[0] == 0 && v[1] == 0 && v[2] == 0) v[0] = v[1] = v[2] = 1;
-        int plo = 0, phi = 0, ilo = first, ihi = first;
-        bool any = false;
-#pragma unroll
-        for (int i = 0; i < 16; i++) {
-            if (!((mask >> i) & 1)) continue;
-            int p = v[0] * x[i][0] + v[1] * x[i][1] + v[2] * x[i][2];
-            if (!any || p < plo) { plo = p; ilo = i; }
-            if (!any || p > phi) { phi = p; ihi = i; }
-            any = true;
-        }
-#pragma unroll
-        for (int c = 0; c < 3; c++) { elo[c] = x[ilo][c]; ehi[c] = x[ihi][c]; }
-    } else {
-        int lo = 255, hi = 0;
-#pragma unroll
-        for (int i = 0; i < 16; i++) {
-            if (!((mask >> i) & 1)) continue;
-            lo = min(lo, x[i][0]);
-            hi = max(hi, x[i][0]);
-        }
-        elo[0] = lo;
-        ehi[0] = hi;
-    }
-    // (c)
-    fit_eval<CB, PB, NB, NCH>(x, mask, elo, ehi, T, out);
-    // (d) one least-squares refit with the chosen indices
-    int A = 0, B = 0, AB = 0, SA[3] = {0, 0, 0}, SB[3] = {0, 0, 0};
-#pragma unroll
-    for (int i = 0; i < 16; i++) {
-        if (!((mask >> i) & 1)) continue;
-        int k = (int)((out.idx >> (4 * i)) & 15);
-        int b = bc7_weight(NB, k & ((1 << NB) - 1)), a = 64 - b;
-        A += a * a; B += b * b; AB += a * b;
-#pragma unroll
-        for (int c = 0; c < NCH; c++) { SA[c] += a * x[i][c]; SB[c] += b * x[i][c]; }
-    }
-    const int64_t det = (int64_t)A * B - (int64_t)AB * AB;
-    if (det == 0) return;
-    int rlo[3] = {0, 0, 0}, rhi[3] = {0, 0, 0};
-    const double ddet = (double)det;
-#pragma unroll
-    for (int c = 0; c < NCH; c++) {
-        int64_t n0 = 64 * ((int64_t)B * SA[c] - (int64_t)AB * SB[c]);
-        int64_t n1 = 64 * ((int64_t)A * SB[c] - (int64_t)AB * SA[c]);
-        // floor(n/det + 1/2): the double quotient is within 2^-45 of the exact
-        // value for any value in range, and a half-integer tie is exact
-        double q0 = floor((double)n0 / ddet + 0.5), q1 = floor((double)n1 / ddet + 0.5);
-        rlo[c] = q0 < 0.0 ? 0 : (q0 > 255.0 ? 255 : (int)q0);
-        rhi[c] = q1 < 0.0 ? 0 : (q1 > 255.0 ? 255 : (int)q1);
-    }
-    Fit g;
-    fit_eval<CB, PB, NB, NCH>(x, mask, rlo, rhi, T, g);
-    if (g.sse < out.sse) out = g;
-}
-
-// Anchor rule: the anchor texel's index must have its top bit clear.
-template <int NB, int NCH>
-__device__ __forceinline__ void anchor_fix(Fit &f, uint32_t mask, int anchor)
-{
-    int k = (int)((f.idx >> (4 * anchor)) & 15);
-    if (!(k >> (NB - 1))) return;
-#pragma unroll
-    for (int c = 0; c < NCH; c++) { int t = f.c0[c]; f.c0[c] = f.c1[c]; f.c1[c] = t; }
-    int t = f.p0; f.p0 = f.p1; f.p1 = t;
-    uint64_t idx = f.idx;
-#pragma unroll
-    for (int i = 0; i < 16; i++)
-        if ((mask >> i) & 1) {
-            uint64_t m = (uint64_t)15 << (4 * i);
-            uint64_t nk = (uint64_t)(((1 << NB) - 1) - (int)((idx >> (4 * i)) & 15));
-            idx = (idx & ~m) | (nk << (4 * i));
-        }
-    f.idx = idx;
-}
-
 // ---- candidate geometry
 __device__ __forceinline__ uint32_t mask3(int p, int s)
 {
@@ -285,19 +58,6 @@ __device__ __forceinline__ uint32_t mask2(int p, int s)
 {
     uint32_t w = kPart2[p];
     return s ? w : (~w & 0xFFFFu);
-}
-
-// Colour triple and scalar values for rotation r (modes 4, 5): rotation
-// moves channel r-1 to the scalar slot and leaves 255 in its place.
-__device__ __forceinline__ void rotate(const int (&x)[16][3], int r, int (&t)[16][3], int (&s)[16][3])
-{
-#pragma unroll
-    for (int i = 0; i < 16; i++) {
-#pragma unroll
-        for (int c = 0; c < 3; c++) t[i][c] = x[i][c];
-        s[i][0] = 255; s[i][1] = 0; s[i][2] = 0;
-        if (r) { s[i][0] = x[i][r - 1]; t[i][r - 1] = 255; }
-    }
 }
 
 // Candidate index -> (mode, partition, rotation, index selection)
@@ -314,34 +74,31 @@ __device__ __forceinline__ void candidate(int ci, int &m, int &p, int &r, int &s
     else { m = 7; p = ci - 221; }
 }
 
-// ---- pass 1: SSE of every candidate, best key
+// ---- texels in LDS
 //
 // Texels sit in LDS, one column per lane, as 4x-scaled packed values
 // (rg = 4R | 4G << 16, b = 4B), so one texel x palette-entry distance with
 // its index tie-break is five VALU ops:
-//   d  = rg - prg            (v_pk_sub_i16)
-//   db = b - pb              (v_sub_u32)
-//   k' = db*db + k           (v_mad_i32_i24)       = 16*dB^2 + k
-//   k' = d.x*d.x + d.y*d.y + k'  (v_dot2c_i32_i16)  = 16*SSE + k
-//   best = min(best, k')     (v_min_u32)
-// Subset masks are wave-uniform, so texel loops walk the set bits of the
-// mask with scalar control.  The principal axis and the extreme texels of a
-// subset depend only on the partition, so they are found once and shared by
-// every mode with that partition (2-subset: modes 1, 3, 7; 3-subset: modes 0
-// and 2; whole block: modes 4, 5 and 6).
-constexpr int kSearchWG = 256;
+//   d  = rg - prg                 (v_pk_sub_i16)
+//   db = b - pb                   (v_sub_u32)
+//   k' = db*db + k                (v_mad_i32_i24)    = 16*dB^2 + k
+//   k' = d.x*d.x + d.y*d.y + k'   (v_dot2c_i32_i16)  = 16*SSE + k
+//   best = min(best, k')          (v_min_u32)
+// In the search the subset masks are wave-uniform, so texel loops walk the
+// set bits of a mask with scalar control.
+constexpr int kWG = 256;
 constexpr int kQEntries = 10 * 2 * 256;
 
-struct SearchLds {
-    uint32_t rg[16][kSearchWG];
-    uint32_t b[16][kSearchWG];
+struct TexLds {
+    uint32_t rg[16][kWG];
+    uint32_t b[16][kWG];
     uint16_t q[kQEntries];        // nearest-code table: code | value << 8
 };
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
 // Texel i of this lane; rotation r puts 4*255 in channel r-1.
-__device__ __forceinline__ void texel(const SearchLds &S, int i, int rot, uint32_t &rg, int &b)
+__device__ __forceinline__ void texel(const TexLds &S, int i, int rot, uint32_t &rg, int &b)
 {
     rg = S.rg[i][threadIdx.x];
     b = (int)S.b[i][threadIdx.x];
@@ -365,7 +122,7 @@ struct Prep {
     int lo[3], hi[3];
 };
 
-__device__ __forceinline__ Prep prep_subset(const SearchLds &S, uint32_t mask, int rot)
+__device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int rot)
 {
     Prep P;
     const int first = __ffs(mask) - 1;
@@ -389,6 +146,7 @@ __device__ __forceinline__ Prep prep_subset(const SearchLds &S, uint32_t mask, i
     unpack(rg0, b0, P.lo);
     P.hi[0] = P.lo[0]; P.hi[1] = P.lo[1]; P.hi[2] = P.lo[2];
     if (same) return P;
+    // principal axis: integer power iteration on the exact covariance
     const int n = __popc(mask);
     int C[3][3];
     C[0][0] = n * XX[0] - Sx[0] * Sx[0];
@@ -435,22 +193,41 @@ __device__ __forceinline__ Prep prep_subset(const SearchLds &S, uint32_t mask, i
     return P;
 }
 
-// (c) for one endpoint pair: best p-bit combination's SSE and indices.
+// Result of fitting one endpoint pair to a subset.
+struct PairFit {
+    uint32_t sse;
+    uint64_t idx;      // 4 bits per texel (members only)
+    uint32_t c0, c1;   // endpoint codes, 8 bits per channel, R lowest
+    int p0, p1;
+};
+
+// (c) for one endpoint pair: quantise for every p-bit combination, index
+// every member by least SSE; keep the best combination (lowest on ties).
 template <int CB, int PB, int NB>
-__device__ __forceinline__ uint32_t eval_pair(const SearchLds &S, uint32_t mask, int rot, const int (&lo)[3],
-                                              const int (&hi)[3], uint64_t &idx_out)
+__device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int rot, const int (&lo)[3],
+                                             const int (&hi)[3])
 {
     constexpr int NPC = PB == 2 ? 4 : PB == 1 ? 2 : 1;
     constexpr int cls = cls_of(CB, PB);
-    uint32_t best_sse = 0xFFFFFFFFu;
-    uint64_t best_idx = 0;
+    PairFit best;
+    best.sse = 0xFFFFFFFFu;
+    best.idx = 0;
+    best.c0 = best.c1 = 0;
+    best.p0 = best.p1 = 0;
     for (int pc = 0; pc < NPC; pc++) {
         const int p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
         const int p1 = PB == 2 ? (pc >> 1) : PB == 1 ? pc : 0;
         const uint16_t *q0 = S.q + (cls * 2 + p0) * 256, *q1 = S.q + (cls * 2 + p1) * 256;
         int d0[3], d1[3];
+        uint32_t c0 = 0, c1 = 0;
 #pragma unroll
-        for (int c = 0; c < 3; c++) { d0[c] = q0[lo[c]] >> 8; d1[c] = q1[hi[c]] >> 8; }
+        for (int c = 0; c < 3; c++) {
+            const uint32_t e0 = q0[lo[c]], e1 = q1[hi[c]];
+            d0[c] = (int)(e0 >> 8);
+            d1[c] = (int)(e1 >> 8);
+            c0 |= (e0 & 255u) << (8 * c);
+            c1 |= (e1 & 255u) << (8 * c);
+        }
         uint32_t prg[1 << NB];
         int pb[1 << NB];
 #pragma unroll
@@ -467,27 +244,33 @@ __device__ __forceinline__ uint32_t eval_pair(const SearchLds &S, uint32_t mask,
             uint32_t rg;
             int b;
             texel(S, i, rot, rg, b);
-            uint32_t best = 0xFFFFFFFFu;
+            uint32_t kb = 0xFFFFFFFFu;
 #pragma unroll
             for (int k = 0; k < (1 << NB); k++) {
                 short2_t d = __builtin_bit_cast(short2_t, rg) - __builtin_bit_cast(short2_t, prg[k]);
                 int db = b - pb[k];
                 int key = __builtin_amdgcn_sdot2(d, d, __mul24(db, db) + k, false);
-                best = min(best, (uint32_t)key);
+                kb = min(kb, (uint32_t)key);
             }
-            sse += best >> 4;
-            idx |= (uint64_t)(best & 15u) << (4 * i);
+            sse += kb >> 4;
+            idx |= (uint64_t)(kb & 15u) << (4 * i);
         }
-        if (sse < best_sse) { best_sse = sse; best_idx = idx; }
+        if (sse < best.sse) {
+            best.sse = sse;
+            best.idx = idx;
+            best.c0 = c0;
+            best.c1 = c1;
+            best.p0 = p0;
+            best.p1 = p1;
+        }
     }
-    idx_out = best_idx;
-    return best_sse;
+    return best;
 }
 
 // (d) least-squares endpoints for the chosen indices; false if singular.
 template <int NB>
-__device__ __forceinline__ bool ls_endpoints(const SearchLds &S, uint32_t mask, int rot, uint64_t idx,
-                                             int (&lo)[3], int (&hi)[3])
+__device__ __forceinline__ bool ls_endpoints(const TexLds &S, uint32_t mask, int rot, uint64_t idx, int (&lo)[3],
+                                             int (&hi)[3])
 {
     int A = 0, B = 0, AB = 0, SA[3] = {0, 0, 0}, SB[3] = {0, 0, 0};
     for (uint32_t m = mask; m; m &= m - 1) {
@@ -507,8 +290,11 @@ __device__ __forceinline__ bool ls_endpoints(const SearchLds &S, uint32_t mask, 
     if (det == 0.0) return false;
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        // exact numerators (< 2^42); a correctly rounded quotient keeps the
-        // floor(x + 1/2) decision of the exact rational for |x| <= 256
+        // Exact numerators (< 2^42).  The quotient is correctly rounded, so
+        // floor(q + 1/2) takes the same decision as floor(n/det + 1/2) on the
+        // exact rational whenever the result is in range (|n/det| <= 256):
+        // a half-integer quotient is exact, and any other one is at least
+        // 1/(2 det) > 1e-10 away from a half-integer.
         double n0 = 64.0 * ((double)B * (double)SA[c] - (double)AB * (double)SB[c]);
         double n1 = 64.0 * ((double)A * (double)SB[c] - (double)AB * (double)SA[c]);
         double q0 = floor(n0 / det + 0.5), q1 = floor(n1 / det + 0.5);
@@ -518,51 +304,68 @@ __device__ __forceinline__ bool ls_endpoints(const SearchLds &S, uint32_t mask, 
     return true;
 }
 
-// SSE of one colour subset fitted with precision (CB, PB) and NB-bit indices.
+// Fit one colour subset with endpoint precision (CB, PB) and NB-bit indices.
 template <int CB, int PB, int NB>
-__device__ __forceinline__ uint32_t fit_colour(const SearchLds &S, uint32_t mask, int rot, const Prep &P,
-                                               const uint32_t *sv)
+__device__ __forceinline__ PairFit fit_colour(const TexLds &S, uint32_t mask, int rot, const Prep &P,
+                                              const uint32_t *sv)
 {
     constexpr int NPC = PB == 2 ? 4 : PB == 1 ? 2 : 1;
     constexpr int cls = cls_of(CB, PB);
     if (P.same) {
-        uint32_t be = 0xFFFFFFFFu;
+        // (a) single value: best (p-bits, index) from the per-channel tables
+        PairFit f;
+        f.sse = 0xFFFFFFFFu;
+        f.idx = 0;
+        f.c0 = f.c1 = 0;
+        f.p0 = f.p1 = 0;
         for (int pc = 0; pc < NPC; pc++) {
             const int p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
             const int p1 = PB == 2 ? (pc >> 1) : PB == 1 ? pc : 0;
             for (int k = 0; k < (1 << NB); k++) {
                 const uint32_t *row = sv + ((uint64_t)(cls * 4 + p0 + 2 * p1) * kSlots + slot_of(NB, k)) * 256;
-                uint32_t e = 0;
+                uint32_t e = 0, c0 = 0, c1 = 0;
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
-                    uint32_t er = row[P.lo[c]] >> 16;
+                    const uint32_t ent = row[P.lo[c]];
+                    const uint32_t er = ent >> 16;
                     e += er * er;
+                    c0 |= (ent & 255u) << (8 * c);
+                    c1 |= ((ent >> 8) & 255u) << (8 * c);
                 }
-                be = min(be, e);
+                if (e < f.sse) {
+                    f.sse = e;
+                    f.idx = (uint64_t)k * 0x1111111111111111ull;
+                    f.c0 = c0;
+                    f.c1 = c1;
+                    f.p0 = p0;
+                    f.p1 = p1;
+                }
             }
         }
-        return be * (uint32_t)__popc(mask);
+        f.sse *= (uint32_t)__popc(mask);
+        return f;
     }
-    uint64_t idx;
-    uint32_t sse = eval_pair<CB, PB, NB>(S, mask, rot, P.lo, P.hi, idx);
+    // (b) endpoints from the principal axis, (c) quantise and index,
+    // (d) one least-squares refit kept only if strictly better
+    PairFit f = eval_pair<CB, PB, NB>(S, mask, rot, P.lo, P.hi);
     int rlo[3], rhi[3];
-    if (ls_endpoints<NB>(S, mask, rot, idx, rlo, rhi)) {
-        uint64_t idx2;
-        sse = min(sse, eval_pair<CB, PB, NB>(S, mask, rot, rlo, rhi, idx2));
+    if (ls_endpoints<NB>(S, mask, rot, f.idx, rlo, rhi)) {
+        PairFit g = eval_pair<CB, PB, NB>(S, mask, rot, rlo, rhi);
+        if (g.sse < f.sse) f = g;
     }
-    return sse;
+    return f;
 }
 
-// SSE of the scalar channel (modes 4, 5, rotation r > 0): 16 values of
-// channel r-1, precision AB bits (no p-bit), NB-bit indices.
+// Scalar channel of modes 4 and 5: the 16 values of channel r-1 (rotation
+// r > 0) or the constant 255 (r = 0); precision AB bits, NB-bit indices.
 template <int AB, int NB>
-__device__ __forceinline__ uint32_t fit_scalar(const SearchLds &S, int rot, const uint32_t *sv)
+__device__ __forceinline__ PairFit fit_scalar(const TexLds &S, int rot, const uint32_t *sv)
 {
     constexpr int cls = cls_of(AB, 0);
     auto value = [&](int i) {
         const uint32_t rg = S.rg[i][threadIdx.x];
         const int b = (int)S.b[i][threadIdx.x];
-        return rot == 1 ? (int)((rg & 0xFFFFu) >> 2) : rot == 2 ? (int)(rg >> 18) : (b >> 2);
+        return rot == 0 ? 255 : rot == 1 ? (int)((rg & 0xFFFFu) >> 2) : rot == 2 ? (int)(rg >> 18) : (b >> 2);
     };
     const int v0 = value(0);
     int lo = v0, hi = v0;
@@ -573,36 +376,54 @@ __device__ __forceinline__ uint32_t fit_scalar(const SearchLds &S, int rot, cons
         lo = min(lo, v);
         hi = max(hi, v);
     }
+    PairFit best;
+    best.sse = 0xFFFFFFFFu;
+    best.idx = 0;
+    best.c0 = best.c1 = 0;
+    best.p0 = best.p1 = 0;
     if (same) {
-        uint32_t be = 0xFFFFFFFFu;
         for (int k = 0; k < (1 << NB); k++) {
-            uint32_t er = sv[((uint64_t)(cls * 4) * kSlots + slot_of(NB, k)) * 256 + v0] >> 16;
-            be = min(be, er * er);
+            const uint32_t ent = sv[((uint64_t)(cls * 4) * kSlots + slot_of(NB, k)) * 256 + v0];
+            const uint32_t er = ent >> 16;
+            if (er * er < best.sse) {
+                best.sse = er * er;
+                best.idx = (uint64_t)k * 0x1111111111111111ull;
+                best.c0 = ent & 255u;
+                best.c1 = (ent >> 8) & 255u;
+            }
         }
-        return be * 16u;
+        best.sse *= 16u;
+        return best;
     }
-    uint32_t best = 0xFFFFFFFFu;
     int elo = lo, ehi = hi;
     for (int pass = 0; pass < 2; pass++) {
-        const int d0 = S.q[cls * 2 * 256 + elo] >> 8, d1 = S.q[cls * 2 * 256 + ehi] >> 8;
+        const uint32_t e0 = S.q[cls * 2 * 256 + elo], e1 = S.q[cls * 2 * 256 + ehi];
+        const int d0 = (int)(e0 >> 8), d1 = (int)(e1 >> 8);
         int pal[1 << NB];
 #pragma unroll
         for (int k = 0; k < (1 << NB); k++) pal[k] = interp64(d0, d1, bc7_weight(NB, k)) << 2;
         uint32_t sse = 0;
+        uint64_t idx = 0;
         int A = 0, B = 0, AB2 = 0, SA = 0, SB = 0;
         for (int i = 0; i < 16; i++) {
             const int x = value(i);
-            uint32_t kbest = 0xFFFFFFFFu;
+            uint32_t kb = 0xFFFFFFFFu;
 #pragma unroll
             for (int k = 0; k < (1 << NB); k++) {
                 int d = (x << 2) - pal[k];
-                kbest = min(kbest, (uint32_t)(__mul24(d, d) + k));
+                kb = min(kb, (uint32_t)(__mul24(d, d) + k));
             }
-            sse += kbest >> 4;
-            const int w = bc7_weight(NB, (int)(kbest & 15u)), a = 64 - w;
+            sse += kb >> 4;
+            idx |= (uint64_t)(kb & 15u) << (4 * i);
+            const int w = bc7_weight(NB, (int)(kb & 15u)), a = 64 - w;
             A += a * a; B += w * w; AB2 += a * w; SA += a * x; SB += w * x;
         }
-        best = min(best, sse);
+        if (sse < best.sse) {
+            best.sse = sse;
+            best.idx = idx;
+            best.c0 = e0 & 255u;
+            best.c1 = e1 & 255u;
+        }
         if (pass == 1) break;
         const double det = (double)A * (double)B - (double)AB2 * (double)AB2;
         if (det == 0.0) break;
@@ -615,16 +436,33 @@ __device__ __forceinline__ uint32_t fit_scalar(const SearchLds &S, int rot, cons
     return best;
 }
 
+// (e) the anchor texel's index must have its top bit clear; otherwise swap
+// the endpoints (and p-bits) and mirror every member's index.
+template <int NB>
+__device__ __forceinline__ void anchor_fix(PairFit &f, uint32_t mask, int anchor)
+{
+    if (!((f.idx >> (4 * anchor + NB - 1)) & 1)) return;
+    uint32_t t = f.c0; f.c0 = f.c1; f.c1 = t;
+    int u = f.p0; f.p0 = f.p1; f.p1 = u;
+    uint64_t spread = 0;
+    for (uint32_t m = mask; m; m &= m - 1) spread |= (uint64_t)((1u << NB) - 1) << (4 * (__ffs(m) - 1));
+    f.idx ^= spread;   // k -> (2^NB - 1) - k on the members
+}
+
+// ---- pass 1: best key over one candidate group
+//
+// The principal axis and the extreme texels of a subset depend only on the
+// partition, so they are found once and shared by every mode with that
+// partition.  The candidates fall into three groups by partition shape; each
+// group is its own kernel (smaller register footprint), and the block's key
+// is the minimum over the groups.
 __device__ __forceinline__ void consider(uint32_t sse, int ci, uint32_t &best)
 {
     best = min(best, (sse << 9) | (uint32_t)ci);
 }
 
-// The candidates fall into three groups by partition shape; each group is
-// its own kernel (smaller register footprint), and the block's key is the
-// minimum over the groups.
 template <int GROUP>
-__device__ uint32_t search_group(const SearchLds &S, uint32_t mode_mask, const uint32_t *sv)
+__device__ uint32_t search_group(const TexLds &S, uint32_t mode_mask, const uint32_t *sv)
 {
     uint32_t best = 0xFFFFFFFFu;
     if (GROUP == 0) {
@@ -634,11 +472,14 @@ __device__ uint32_t search_group(const SearchLds &S, uint32_t mode_mask, const u
                 const uint32_t m0 = mask2(p, 0), m1 = mask2(p, 1);
                 const Prep P0 = prep_subset(S, m0, 0), P1 = prep_subset(S, m1, 0);
                 if (mode_mask & 0x02)
-                    consider(fit_colour<6, 1, 3>(S, m0, 0, P0, sv) + fit_colour<6, 1, 3>(S, m1, 0, P1, sv), 16 + p, best);
+                    consider(fit_colour<6, 1, 3>(S, m0, 0, P0, sv).sse + fit_colour<6, 1, 3>(S, m1, 0, P1, sv).sse,
+                             16 + p, best);
                 if (mode_mask & 0x08)
-                    consider(fit_colour<7, 2, 2>(S, m0, 0, P0, sv) + fit_colour<7, 2, 2>(S, m1, 0, P1, sv), 144 + p, best);
+                    consider(fit_colour<7, 2, 2>(S, m0, 0, P0, sv).sse + fit_colour<7, 2, 2>(S, m1, 0, P1, sv).sse,
+                             144 + p, best);
                 if (mode_mask & 0x80)
-                    consider(fit_colour<5, 2, 2>(S, m0, 0, P0, sv) + fit_colour<5, 2, 2>(S, m1, 0, P1, sv), 221 + p, best);
+                    consider(fit_colour<5, 2, 2>(S, m0, 0, P0, sv).sse + fit_colour<5, 2, 2>(S, m1, 0, P1, sv).sse,
+                             221 + p, best);
             }
     } else if (GROUP == 1) {
         // 3-subset partitions: mode 0 (partitions 0..15), mode 2
@@ -647,11 +488,11 @@ __device__ uint32_t search_group(const SearchLds &S, uint32_t mode_mask, const u
                 const uint32_t m0 = mask3(p, 0), m1 = mask3(p, 1), m2 = mask3(p, 2);
                 const Prep P0 = prep_subset(S, m0, 0), P1 = prep_subset(S, m1, 0), P2 = prep_subset(S, m2, 0);
                 if ((mode_mask & 0x01) && p < 16)
-                    consider(fit_colour<4, 2, 3>(S, m0, 0, P0, sv) + fit_colour<4, 2, 3>(S, m1, 0, P1, sv) +
-                                 fit_colour<4, 2, 3>(S, m2, 0, P2, sv), p, best);
+                    consider(fit_colour<4, 2, 3>(S, m0, 0, P0, sv).sse + fit_colour<4, 2, 3>(S, m1, 0, P1, sv).sse +
+                                 fit_colour<4, 2, 3>(S, m2, 0, P2, sv).sse, p, best);
                 if (mode_mask & 0x04)
-                    consider(fit_colour<5, 0, 2>(S, m0, 0, P0, sv) + fit_colour<5, 0, 2>(S, m1, 0, P1, sv) +
-                                 fit_colour<5, 0, 2>(S, m2, 0, P2, sv), 80 + p, best);
+                    consider(fit_colour<5, 0, 2>(S, m0, 0, P0, sv).sse + fit_colour<5, 0, 2>(S, m1, 0, P1, sv).sse +
+                                 fit_colour<5, 0, 2>(S, m2, 0, P2, sv).sse, 80 + p, best);
             }
     } else {
         // one subset: mode 6, and modes 4 / 5 for every rotation
@@ -659,17 +500,17 @@ __device__ uint32_t search_group(const SearchLds &S, uint32_t mode_mask, const u
             for (int r = 0; r < 4; r++) {
                 if (r > 0 && !(mode_mask & 0x30)) break;
                 const Prep P = prep_subset(S, 0xFFFFu, r);
-                if (r == 0 && (mode_mask & 0x40)) consider(fit_colour<7, 2, 4>(S, 0xFFFFu, 0, P, sv), 220, best);
+                if (r == 0 && (mode_mask & 0x40)) consider(fit_colour<7, 2, 4>(S, 0xFFFFu, 0, P, sv).sse, 220, best);
                 if (mode_mask & 0x10) {
-                    uint32_t s0 = fit_colour<5, 0, 2>(S, 0xFFFFu, r, P, sv);
-                    uint32_t s1 = fit_colour<5, 0, 3>(S, 0xFFFFu, r, P, sv);
-                    if (r) { s0 += fit_scalar<6, 3>(S, r, sv); s1 += fit_scalar<6, 2>(S, r, sv); }
+                    uint32_t s0 = fit_colour<5, 0, 2>(S, 0xFFFFu, r, P, sv).sse;
+                    uint32_t s1 = fit_colour<5, 0, 3>(S, 0xFFFFu, r, P, sv).sse;
+                    if (r) { s0 += fit_scalar<6, 3>(S, r, sv).sse; s1 += fit_scalar<6, 2>(S, r, sv).sse; }
                     consider(s0, 208 + 2 * r, best);
                     consider(s1, 209 + 2 * r, best);
                 }
                 if (mode_mask & 0x20) {
-                    uint32_t s5 = fit_colour<7, 0, 2>(S, 0xFFFFu, r, P, sv);
-                    if (r) s5 += fit_scalar<8, 2>(S, r, sv);
+                    uint32_t s5 = fit_colour<7, 0, 2>(S, 0xFFFFu, r, P, sv).sse;
+                    if (r) s5 += fit_scalar<8, 2>(S, r, sv).sse;
                     consider(s5, 216 + r, best);
                 }
             }
@@ -677,7 +518,7 @@ __device__ uint32_t search_group(const SearchLds &S, uint32_t mode_mask, const u
     return best;
 }
 
-// ---- pass 2: re-fit the winner and lay out its bits
+// ---- pass 2: re-fit the winner (same arithmetic) and lay out its bits
 struct Writer {
     uint64_t lo = 0, hi = 0;
     int pos = 0;
@@ -694,27 +535,28 @@ struct Writer {
 };
 
 template <int M, int CB, int PB, int NB>
-__device__ void emit_partitioned(const int (&x)[16][3], int p, const Tables &T, Writer &w)
+__device__ void emit_partitioned(const TexLds &S, int p, const uint32_t *sv, Writer &w)
 {
     constexpr Bc7Mode md = bc7_mode(M);
     constexpr int NS = md.ns;
-    Fit f[NS];
+    PairFit f[NS];
     uint32_t msk[NS];
     int anc[NS];
 #pragma unroll
     for (int s = 0; s < NS; s++) {
         msk[s] = NS == 3 ? mask3(p, s) : mask2(p, s);
         anc[s] = bc7_anchor(NS, p, s);
-        fit_subset<CB, PB, NB, 3>(x, msk[s], T, f[s]);
-        anchor_fix<NB, 3>(f[s], msk[s], anc[s]);
+        const Prep P = prep_subset(S, msk[s], 0);
+        f[s] = fit_colour<CB, PB, NB>(S, msk[s], 0, P, sv);
+        anchor_fix<NB>(f[s], msk[s], anc[s]);
     }
     w.put(1u << M, M + 1);
     w.put((uint32_t)p, md.partbits);
 #pragma unroll
     for (int c = 0; c < 3; c++)
 #pragma unroll
-        for (int s = 0; s < NS; s++) { w.put(f[s].c0[c], CB); w.put(f[s].c1[c], CB); }
-    if (md.ab)
+        for (int s = 0; s < NS; s++) { w.put(f[s].c0 >> (8 * c), CB); w.put(f[s].c1 >> (8 * c), CB); }
+    if (md.ab)   // alpha is not coded for these colour blocks: all-ones fields
 #pragma unroll
         for (int s = 0; s < NS; s++) { w.put((1u << md.ab) - 1, md.ab); w.put((1u << md.ab) - 1, md.ab); }
     if (PB == 2)
@@ -723,80 +565,77 @@ __device__ void emit_partitioned(const int (&x)[16][3], int p, const Tables &T, 
     else if (PB == 1)
 #pragma unroll
         for (int s = 0; s < NS; s++) w.put(f[s].p0, 1);
+    // members' indices live in their own subset's fit: merge them
+    uint64_t idx = 0;
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+        uint64_t sel = 0;
+        for (uint32_t m = msk[s]; m; m &= m - 1) sel |= (uint64_t)15 << (4 * (__ffs(m) - 1));
+        idx |= f[s].idx & sel;
+    }
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-        int s = 0;
-#pragma unroll
-        for (int q = 1; q < NS; q++) if ((msk[q] >> i) & 1) s = q;
         bool anchored = false;
 #pragma unroll
         for (int q = 0; q < NS; q++) anchored |= anc[q] == i;
-        uint64_t idx = f[0].idx;
-#pragma unroll
-        for (int q = 1; q < NS; q++) if (s == q) idx = f[q].idx;
         w.put((uint32_t)((idx >> (4 * i)) & 15), NB - (anchored ? 1 : 0));
     }
 }
 
 // Modes 4 and 5: one colour pair plus a scalar pair, rotation r.
 template <int M, int CB, int AB, int CNB, int SNB>
-__device__ void emit_rotated(const int (&x)[16][3], int r, int sel, const Tables &T, Writer &w)
+__device__ void emit_rotated(const TexLds &S, int r, int sel, const uint32_t *sv, Writer &w)
 {
-    int t[16][3], sc[16][3];
-    rotate(x, r, t, sc);
-    Fit fc, fs;
-    fit_subset<CB, 0, CNB, 3>(t, 0xFFFF, T, fc);
-    anchor_fix<CNB, 3>(fc, 0xFFFF, 0);
-    fit_subset<AB, 0, SNB, 1>(sc, 0xFFFF, T, fs);
-    anchor_fix<SNB, 1>(fs, 0xFFFF, 0);
+    const Prep P = prep_subset(S, 0xFFFFu, r);
+    PairFit fc = fit_colour<CB, 0, CNB>(S, 0xFFFFu, r, P, sv);
+    anchor_fix<CNB>(fc, 0xFFFFu, 0);
+    PairFit fs = fit_scalar<AB, SNB>(S, r, sv);
+    anchor_fix<SNB>(fs, 0xFFFFu, 0);
     w.put(1u << M, M + 1);
     w.put((uint32_t)r, 2);
     if (M == 4) w.put((uint32_t)sel, 1);
 #pragma unroll
-    for (int c = 0; c < 3; c++) { w.put(fc.c0[c], CB); w.put(fc.c1[c], CB); }
-    w.put(fs.c0[0], AB);
-    w.put(fs.c1[0], AB);
-    // primary index set first, then the secondary set; index selection 1
-    // stores the scalar indices in the primary set
-    const Fit &first = (M == 4 && sel) ? fs : fc;
-    const Fit &second = (M == 4 && sel) ? fc : fs;
-    constexpr int NB1 = (M == 4) ? 2 : 2, NB2 = (M == 4) ? 3 : 2;
+    for (int c = 0; c < 3; c++) { w.put(fc.c0 >> (8 * c), CB); w.put(fc.c1 >> (8 * c), CB); }
+    w.put(fs.c0, AB);
+    w.put(fs.c1, AB);
+    // primary index set (2 bits) first, then the secondary set; index
+    // selection 1 stores the scalar indices in the primary set
+    const uint64_t first = (M == 4 && sel) ? fs.idx : fc.idx;
+    const uint64_t second = (M == 4 && sel) ? fc.idx : fs.idx;
+    constexpr int NB1 = 2, NB2 = (M == 4) ? 3 : 2;
 #pragma unroll
-    for (int i = 0; i < 16; i++) w.put((uint32_t)((first.idx >> (4 * i)) & 15), NB1 - (i == 0));
+    for (int i = 0; i < 16; i++) w.put((uint32_t)((first >> (4 * i)) & 15), NB1 - (i == 0));
 #pragma unroll
-    for (int i = 0; i < 16; i++) w.put((uint32_t)((second.idx >> (4 * i)) & 15), NB2 - (i == 0));
+    for (int i = 0; i < 16; i++) w.put((uint32_t)((second >> (4 * i)) & 15), NB2 - (i == 0));
 }
 
-__device__ void emit(const int (&x)[16][3], int ci, const Tables &T, uint64_t &lo, uint64_t &hi)
+// Bits of a winning candidate of mode M.
+template <int M>
+__device__ __forceinline__ void emit(const TexLds &S, int ci, const uint32_t *sv, uint64_t &lo, uint64_t &hi)
 {
     int m, p, r, s;
     candidate(ci, m, p, r, s);
     Writer w;
-    switch (m) {
-    case 0: emit_partitioned<0, 4, 2, 3>(x, p, T, w); break;
-    case 1: emit_partitioned<1, 6, 1, 3>(x, p, T, w); break;
-    case 2: emit_partitioned<2, 5, 0, 2>(x, p, T, w); break;
-    case 3: emit_partitioned<3, 7, 2, 2>(x, p, T, w); break;
-    case 4:
-        if (s == 0) emit_rotated<4, 5, 6, 2, 3>(x, r, 0, T, w);
-        else emit_rotated<4, 5, 6, 3, 2>(x, r, 1, T, w);
-        break;
-    case 5: emit_rotated<5, 7, 8, 2, 2>(x, r, 0, T, w); break;
-    case 6: {
-        Fit f;
-        fit_subset<7, 2, 4, 3>(x, 0xFFFF, T, f);
-        anchor_fix<4, 3>(f, 0xFFFF, 0);
+    if (M == 0) emit_partitioned<0, 4, 2, 3>(S, p, sv, w);
+    else if (M == 1) emit_partitioned<1, 6, 1, 3>(S, p, sv, w);
+    else if (M == 2) emit_partitioned<2, 5, 0, 2>(S, p, sv, w);
+    else if (M == 3) emit_partitioned<3, 7, 2, 2>(S, p, sv, w);
+    else if (M == 4) {
+        if (s == 0) emit_rotated<4, 5, 6, 2, 3>(S, r, 0, sv, w);
+        else emit_rotated<4, 5, 6, 3, 2>(S, r, 1, sv, w);
+    } else if (M == 5) emit_rotated<5, 7, 8, 2, 2>(S, r, 0, sv, w);
+    else if (M == 6) {
+        const Prep P = prep_subset(S, 0xFFFFu, 0);
+        PairFit f = fit_colour<7, 2, 4>(S, 0xFFFFu, 0, P, sv);
+        anchor_fix<4>(f, 0xFFFFu, 0);
         w.put(1u << 6, 7);
 #pragma unroll
-        for (int c = 0; c < 3; c++) { w.put(f.c0[c], 7); w.put(f.c1[c], 7); }
-        w.put(127, 7); w.put(127, 7);
+        for (int c = 0; c < 3; c++) { w.put(f.c0 >> (8 * c), 7); w.put(f.c1 >> (8 * c), 7); }
+        w.put(127, 7); w.put(127, 7);   // alpha not coded: all-ones fields
         w.put(f.p0, 1); w.put(f.p1, 1);
 #pragma unroll
         for (int i = 0; i < 16; i++) w.put((uint32_t)((f.idx >> (4 * i)) & 15), 4 - (i == 0));
-        break;
-    }
-    default: emit_partitioned<7, 5, 2, 2>(x, p, T, w); break;
-    }
+    } else emit_partitioned<7, 5, 2, 2>(S, p, sv, w);
     lo = w.lo;
     hi = w.hi;
 }
@@ -806,69 +645,181 @@ struct Bc7Launch {
     Tables T;
 };
 
-__device__ __forceinline__ void load_block(const EncodeArgs &a, uint64_t g, uint32_t (&t)[16], uint32_t &band,
-                                           uint64_t &b)
+// Stage this workgroup's blocks in LDS (4x-scaled packed texels, one column
+// per lane) with the endpoint-quantisation table; returns false for lanes
+// past the last block (they still take part in the barrier).
+__device__ __forceinline__ bool stage_block(TexLds &S, const Bc7Launch &L, uint32_t &band, uint64_t &b)
 {
-    band = a.band0 + (uint32_t)(g / a.nblk);
-    b = g % a.nblk;
-    const uint4 *src = reinterpret_cast<const uint4 *>(a.textures + ((uint64_t)band * a.nblk + b) * 64);
-#pragma unroll
-    for (int q = 0; q < 4; q++) {
-        uint4 v = src[q];
-        t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
-    }
-}
-
-// Pass 1: the best key of every block over one candidate group, min-combined
-// into the first word of its output slot (group 0 writes it first).
-template <int GROUP>
-__global__ __launch_bounds__(kSearchWG) void k_bc7_search(Bc7Launch L)
-{
-    __shared__ SearchLds S;
     const EncodeArgs &a = L.a;
-    for (int q = threadIdx.x; q < kQEntries / 2; q += kSearchWG)
+    for (int q = threadIdx.x; q < kQEntries / 2; q += kWG)
         reinterpret_cast<uint32_t *>(S.q)[q] = reinterpret_cast<const uint32_t *>(L.T.nearest)[q];
-    const uint64_t g = (uint64_t)blockIdx.x * kSearchWG + threadIdx.x;
+    const uint64_t g = (uint64_t)blockIdx.x * kWG + threadIdx.x;
     const uint64_t total = (uint64_t)a.nbands * a.nblk;
-    uint32_t t[16] = {0};
-    uint32_t band = 0;
-    uint64_t b = 0;
-    if (g < total) load_block(a, g, t, band, b);
+    uint32_t t[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) t[i] = 0;
+    band = 0;
+    b = 0;
+    const bool live = g < total;
+    if (live) {
+        band = a.band0 + (uint32_t)(g / a.nblk);
+        b = g % a.nblk;
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.textures + ((uint64_t)band * a.nblk + b) * 64);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            uint4 v = src[q];
+            t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 16; i++) {
         S.rg[i][threadIdx.x] = ((t[i] & 255u) << 2) | (((t[i] >> 8) & 255u) << 18);
         S.b[i][threadIdx.x] = ((t[i] >> 16) & 255u) << 2;
     }
     __syncthreads();
-    if (g >= total) return;
-    uint32_t key = search_group<GROUP>(S, a.mode_mask, L.T.sv);
-    uint32_t *slot = reinterpret_cast<uint32_t *>(a.out + a.out_offset[band] + b * 16);
-    *slot = GROUP == 0 ? key : min(key, *slot);
+    return live;
 }
 
-// Pass 2: re-fit each block's winning candidate and write its bits.
-__global__ __launch_bounds__(kBlock) void k_bc7_emit(Bc7Launch L)
+// Pass 1: the best key of every block over one candidate group, min-combined
+// into the block's key word (group 0 writes it first).
+template <int GROUP>
+__global__ __launch_bounds__(kWG) void k_bc7_search(Bc7Launch L)
 {
-    const EncodeArgs &a = L.a;
-    const uint64_t g = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    const uint64_t total = (uint64_t)a.nbands * a.nblk;
-    if (g >= total) return;
-    uint32_t t[16], band;
+    __shared__ TexLds S;
+    uint32_t band;
     uint64_t b;
-    load_block(a, g, t, band, b);
-    int x[16][3];
+    const bool live = stage_block(S, L, band, b);
+    if (__ballot(live) == 0) return;
+    uint32_t key = live ? search_group<GROUP>(S, L.a.mode_mask, L.T.sv) : 0u;
+    uint32_t *slot = L.a.keys + (uint64_t)blockIdx.x * kWG + threadIdx.x;   // block g's key
+    if (live) {
+        if (GROUP > 0) key = min(key, *slot);
+        *slot = key;
+    }
+    // the last group holds each block's final key: its SSE is key >> 9
+    if (GROUP == 2 && L.a.band_sse) band_add(L.a.band_sse, band, key >> 9, live);
+}
+
+// Between the passes: bucket the blocks by the mode of their winner, so that
+// the emit kernel of each mode runs full waves of that mode.  Order inside a
+// bucket does not matter: every block is emitted independently.
+__device__ __forceinline__ int mode_of_candidate(int ci)
+{
+    return ci < 16 ? 0 : ci < 80 ? 1 : ci < 144 ? 2 : ci < 208 ? 3 : ci < 216 ? 4 : ci < 220 ? 5 : ci < 221 ? 6 : 7;
+}
+
+// Per-workgroup mode counts (LDS atomics), written to wgcount[wg][8].
+__global__ __launch_bounds__(kWG) void k_bc7_bucket_count(const uint32_t *keys, uint64_t total, uint32_t *wgcount)
+{
+    __shared__ uint32_t c[8];
+    if (threadIdx.x < 8) c[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t g = (uint64_t)blockIdx.x * kWG + threadIdx.x;
+    if (g < total) atomicAdd(&c[mode_of_candidate((int)(keys[g] & 511u))], 1u);
+    __syncthreads();
+    if (threadIdx.x < 8) wgcount[(uint64_t)blockIdx.x * 8 + threadIdx.x] = c[threadIdx.x];
+}
+
+// Exclusive scan of wgcount down each mode's column, then the buckets:
+// count[m] = bucket size, count[8 + m] = its first list slot.  One
+// workgroup: each thread sums a run of rows, the run totals are scanned in
+// LDS, and each thread rewrites its rows.
+__global__ __launch_bounds__(256) void k_bc7_bucket_scan(uint32_t *wgcount, uint32_t nwg, uint32_t *count)
+{
+    __shared__ uint32_t part[256][8];
+    __shared__ uint32_t tot[8];
+    const uint32_t t = threadIdx.x, per = (nwg + 255) / 256;
+    const uint32_t r0 = min(nwg, t * per), r1 = min(nwg, r0 + per);
+    uint32_t acc[8];
+#pragma unroll
+    for (int m = 0; m < 8; m++) acc[m] = 0;
+    for (uint32_t r = r0; r < r1; r++)
+#pragma unroll
+        for (int m = 0; m < 8; m++) acc[m] += wgcount[(uint64_t)r * 8 + m];
+#pragma unroll
+    for (int m = 0; m < 8; m++) part[t][m] = acc[m];
+    __syncthreads();
+    if (t < 8) {
+        uint32_t run = 0;
+        for (int u = 0; u < 256; u++) {
+            uint32_t v = part[u][t];
+            part[u][t] = run;
+            run += v;
+        }
+        tot[t] = run;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 8; m++) {
+        uint32_t run = part[t][m];
+        for (uint32_t r = r0; r < r1; r++) {
+            uint32_t v = wgcount[(uint64_t)r * 8 + m];
+            wgcount[(uint64_t)r * 8 + m] = run;
+            run += v;
+        }
+    }
+    if (t < 8) {
+        uint32_t start = 0;
+        for (uint32_t q = 0; q < t; q++) start += tot[q];
+        count[t] = tot[t];
+        count[8 + t] = start;
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_bc7_bucket_fill(const uint32_t *keys, uint64_t total, const uint32_t *wgoff,
+                                                         const uint32_t *count, uint32_t *list)
+{
+    __shared__ uint32_t c[8];
+    if (threadIdx.x < 8) c[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t g = (uint64_t)blockIdx.x * kWG + threadIdx.x;
+    if (g >= total) return;
+    const int m = mode_of_candidate((int)(keys[g] & 511u));
+    const uint32_t rank = atomicAdd(&c[m], 1u);
+    list[count[8 + m] + wgoff[(uint64_t)blockIdx.x * 8 + m] + rank] = (uint32_t)g;
+}
+
+// Pass 2: re-fit each block's winning candidate and write its bits; one
+// kernel per mode over that mode's bucket (small code, full waves).
+template <int M>
+__global__ __launch_bounds__(kWG) void k_bc7_emit(Bc7Launch L)
+{
+    __shared__ TexLds S;
+    const EncodeArgs &a = L.a;
+    const uint64_t total = (uint64_t)a.nbands * a.nblk;
+    const uint32_t *list = a.keys + total, *count = a.keys + 2 * total;
+    const uint32_t n = count[M], off = count[8 + M];
+    const uint64_t e = (uint64_t)blockIdx.x * kWG + threadIdx.x;
+    if ((uint64_t)blockIdx.x * kWG >= n) return;   // whole workgroup past the bucket
+    const bool live = e < n;
+    const uint64_t g = live ? list[off + e] : 0;
+    // stage the block in LDS (lanes past the bucket stage zeros)
+    for (int q = threadIdx.x; q < kQEntries / 2; q += kWG)
+        reinterpret_cast<uint32_t *>(S.q)[q] = reinterpret_cast<const uint32_t *>(L.T.nearest)[q];
+    uint32_t t[16];
+#pragma unroll
+    for (int i = 0; i < 16; i++) t[i] = 0;
+    const uint32_t band = a.band0 + (uint32_t)(g / a.nblk);
+    const uint64_t b = g % a.nblk;
+    if (live) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.textures + ((uint64_t)band * a.nblk + b) * 64);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            uint4 v = src[q];
+            t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-        x[i][0] = t[i] & 255;
-        x[i][1] = (t[i] >> 8) & 255;
-        x[i][2] = (t[i] >> 16) & 255;
+        S.rg[i][threadIdx.x] = ((t[i] & 255u) << 2) | (((t[i] >> 8) & 255u) << 18);
+        S.b[i][threadIdx.x] = ((t[i] >> 16) & 255u) << 2;
     }
-    uint8_t *slot = a.out + a.out_offset[band] + b * 16;
-    const uint32_t key = *reinterpret_cast<const uint32_t *>(slot);
+    __syncthreads();
+    if (!live) return;
+    const uint32_t key = a.keys[g];
     uint64_t lo, hi;
-    emit(x, (int)(key & 511u), L.T, lo, hi);
-    *reinterpret_cast<ulonglong2 *>(slot) = make_ulonglong2(lo, hi);
-    if (a.band_sse) atomicAdd(&a.band_sse[band], (unsigned long long)(key >> 9));
+    emit<M>(S, (int)(key & 511u), L.T.sv, lo, hi);
+    *reinterpret_cast<ulonglong2 *>(a.out + a.out_offset[band] + b * 16) = make_ulonglong2(lo, hi);
 }
 
 // ---- host-side table construction
@@ -990,11 +941,25 @@ hipError_t launch_bc7_encode(const EncodeArgs &a, hipStream_t st)
     L.a = a;
     L.T.nearest = static_cast<const uint16_t *>(g_tab[dev]);
     L.T.sv = reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(g_tab[dev]) + 10 * 2 * 256 * 2);
-    const dim3 sgrid((uint32_t)((total + kSearchWG - 1) / kSearchWG));
-    hipLaunchKernelGGL(k_bc7_search<0>, sgrid, dim3(kSearchWG), 0, st, L);
-    hipLaunchKernelGGL(k_bc7_search<1>, sgrid, dim3(kSearchWG), 0, st, L);
-    hipLaunchKernelGGL(k_bc7_search<2>, sgrid, dim3(kSearchWG), 0, st, L);
-    hipLaunchKernelGGL(k_bc7_emit, dim3((uint32_t)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, L);
+    const dim3 sgrid((uint32_t)((total + kWG - 1) / kWG));
+    GSBC_LAUNCH("bc7_search_2subset", k_bc7_search<0>, sgrid, dim3(kWG), 0, st, L);
+    GSBC_LAUNCH("bc7_search_3subset", k_bc7_search<1>, sgrid, dim3(kWG), 0, st, L);
+    GSBC_LAUNCH("bc7_search_1subset", k_bc7_search<2>, sgrid, dim3(kWG), 0, st, L);
+    // key scratch: keys[total] | list[total] | count[8] start[8] | wgcount[nwg][8]
+    uint32_t *count = a.keys + 2 * total, *wgcount = count + 16;
+    const uint32_t nwg = sgrid.x;
+    GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_count, sgrid, dim3(kWG), 0, st, a.keys, total, wgcount);
+    GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_scan, dim3(1), dim3(256), 0, st, wgcount, nwg, count);
+    GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_fill, sgrid, dim3(kWG), 0, st, a.keys, total, wgcount, count,
+                a.keys + total);
+    if (a.mode_mask & 0x01) GSBC_LAUNCH("bc7_emit_m0", k_bc7_emit<0>, sgrid, dim3(kWG), 0, st, L);
+    if (a.mode_mask & 0x02) GSBC_LAUNCH("bc7_emit_m1", k_bc7_emit<1>, sgrid, dim3(kWG), 0, st, L);
+    if (a.mode_mask & 0x04) GSBC_LAUNCH("bc7_emit_m2", k_bc7_emit<2>, sgrid, dim3(kWG), 0, st, L);
+    if (a.mode_mask & 0x08) GSBC_LAUNCH("bc7_emit_m3", k_bc7_emit<3>, sgrid, dim3(kWG), 0, st, L);
+    if (a.mode_mask & 0x10) GSBC_LAUNCH("bc7_emit_m4", k_bc7_emit<4>, sgrid, dim3(kWG), 0, st, L);
+    if (a.mode_mask & 0x20) GSBC_LAUNCH("bc7_emit_m5", k_bc7_emit<5>, sgrid, dim3(kWG), 0, st, L);
+    if (a.mode_mask & 0x40) GSBC_LAUNCH("bc7_emit_m6", k_bc7_emit<6>, sgrid, dim3(kWG), 0, st, L);
+    if (a.mode_mask & 0x80) GSBC_LAUNCH("bc7_emit_m7", k_bc7_emit<7>, sgrid, dim3(kWG), 0, st, L);
     return hipGetLastError();
 }
 

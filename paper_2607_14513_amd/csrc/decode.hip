@@ -130,7 +130,7 @@ hipError_t launch_decode(const uint8_t *blocks, const BandArgs &b, uint64_t nblk
                          hipStream_t st)
 {
     uint64_t total = 16 * nblk;
-    hipLaunchKernelGGL(k_decode, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, blocks, b, nblk,
+    GSBC_LAUNCH("decode", k_decode, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, blocks, b, nblk,
                        reinterpret_cast<uint32_t *>(textures));
     return hipGetLastError();
 }
@@ -140,9 +140,9 @@ hipError_t launch_decode_eval(const uint8_t *blocks, const BandArgs &b, uint64_t
                               float *basis, hipStream_t st)
 {
     if (m == 0 || n_dirs == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_sh_basis, dim3((n_dirs + 255) / 256), dim3(256), 0, st, dirs, n_dirs, basis);
+    GSBC_LAUNCH("sh_basis", k_sh_basis, dim3((n_dirs + 255) / 256), dim3(256), 0, st, dirs, n_dirs, basis);
     dim3 grid((uint32_t)((m + kEvalBlock - 1) / kEvalBlock), (n_dirs + kDirTile - 1) / kDirTile);
-    hipLaunchKernelGGL(k_decode_eval, grid, dim3(kEvalBlock), 0, st, blocks, b, prim_idx, m, n_prims, basis,
+    GSBC_LAUNCH("decode_eval", k_decode_eval, grid, dim3(kEvalBlock), 0, st, blocks, b, prim_idx, m, n_prims, basis,
                        n_dirs, out);
     return hipGetLastError();
 }

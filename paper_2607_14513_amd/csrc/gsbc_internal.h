@@ -8,6 +8,38 @@
 
 namespace gsbc {
 
+// Kernel timing hooks around each launch; no-ops unless the calling context
+// has profiling enabled (see gsbc_profile_enable).
+void trace_begin(const char *kernel, hipStream_t st);
+void trace_end(hipStream_t st);
+
+// Add v (one value per lane; lanes with live == false add nothing) into
+// sums[band].  Lanes of a wave usually share a band (consecutive blocks):
+// then the wave sums in registers and one lane issues the atomic; otherwise
+// each lane adds on its own.  Integer sums, so the result is independent of
+// the order.
+__device__ __forceinline__ void band_add(unsigned long long *sums, uint32_t band, uint32_t v, bool live)
+{
+    const uint32_t b0 = (uint32_t)__shfl((int)band, __ffsll((unsigned long long)__ballot(live)) - 1);
+    const bool uniform = __ballot(live && band != b0) == 0;
+    if (uniform) {
+        unsigned long long x = live ? v : 0;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if (live && (__ballot(live) & __lanemask_lt()) == 0) atomicAdd(&sums[band], x);
+    } else if (live) {
+        atomicAdd(&sums[band], (unsigned long long)v);
+    }
+}
+
+// Launch `kernel` bracketed by the timing hooks.
+#define GSBC_LAUNCH(name, kernel, grid, block, shmem, st, ...)              \
+    do {                                                                   \
+        ::gsbc::trace_begin(name, st);                                     \
+        hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__);   \
+        ::gsbc::trace_end(st);                                             \
+    } while (0)
+
 // Per-band stream description passed to kernels by value.
 struct BandArgs {
     uint64_t offset[16];   // byte offset of each band stream in the payload
@@ -44,7 +76,11 @@ struct EncodeArgs {
     unsigned long long *band_sse;   // [16], may be null
     uint32_t refine_steps;
     uint32_t mode_mask;
+    uint32_t *keys;                 // BC7 only: scratch of bc7_scratch_bytes(nbands * nblk)
 };
+// Scratch bytes the BC7 encoder needs for `blocks` blocks: a key and a
+// bucket-list word per block, plus per-mode counters.
+inline size_t bc7_scratch_bytes(uint64_t blocks) { return (size_t)blocks * 8 + 64 + ((blocks + 255) / 256) * 32; }
 hipError_t launch_bc1_encode(const EncodeArgs &a, hipStream_t st);
 hipError_t launch_bc7_encode(const EncodeArgs &a, hipStream_t st);
 hipError_t upload_bc1_tables(hipStream_t st);

@@ -68,7 +68,7 @@ __global__ void k_fill_u64(unsigned long long *p, uint64_t n, unsigned long long
 hipError_t launch_rate_select(const unsigned long long *sse1, const unsigned long long *sse7, const BandArgs &b,
                               uint32_t k, uint64_t nblk, RateSel *sel, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_rate_select, dim3(1), dim3(64), 0, st, sse1, sse7, b, k, nblk, sel);
+    GSBC_LAUNCH("rate_select", k_rate_select, dim3(1), dim3(64), 0, st, sse1, sse7, b, k, nblk, sel);
     return hipGetLastError();
 }
 
@@ -79,14 +79,14 @@ hipError_t launch_copy_streams(const uint8_t *src1, const uint64_t *off1, const 
     uint64_t words = nblk * 2;
     uint32_t gx = (uint32_t)((words + 255) / 256);
     gx = gx > 1024 ? 1024 : (gx == 0 ? 1 : gx);
-    hipLaunchKernelGGL(k_copy_streams, dim3(gx, 16), dim3(256), 0, st, src1, off1, src7, off7, sel, nblk, out);
+    GSBC_LAUNCH("copy_streams", k_copy_streams, dim3(gx, 16), dim3(256), 0, st, src1, off1, src7, off7, sel, nblk, out);
     return hipGetLastError();
 }
 
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t st)
 {
     if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+    GSBC_LAUNCH("fill", k_fill_u64, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
     return hipGetLastError();
 }
 

@@ -316,13 +316,13 @@ hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_
     uint32_t *va = reinterpret_cast<uint32_t *>(s + L.vals_a), *vb = reinterpret_cast<uint32_t *>(s + L.vals_b);
     uint32_t *hist = reinterpret_cast<uint32_t *>(s + L.hist), *total = reinterpret_cast<uint32_t *>(s + L.total);
 
-    hipLaunchKernelGGL(k_range_init, dim3(1), dim3(64), 0, st, acc);
+    GSBC_LAUNCH("range_init", k_range_init, dim3(1), dim3(64), 0, st, acc);
     uint64_t want = (n * 12 + kRangeBlock - 1) / kRangeBlock;
     uint32_t nb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 2048);
-    hipLaunchKernelGGL(k_range_partial, dim3(nb), dim3(kRangeBlock), 0, st,
+    GSBC_LAUNCH("range_partial", k_range_partial, dim3(nb), dim3(kRangeBlock), 0, st,
                        reinterpret_cast<const float4 *>(sh), pos, n, acc);
-    hipLaunchKernelGGL(k_range_final, dim3(1), dim3(64), 0, st, acc, grid_bits, range_dev);
-    hipLaunchKernelGGL(k_keys, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, pos, sh, n,
+    GSBC_LAUNCH("range_final", k_range_final, dim3(1), dim3(64), 0, st, acc, grid_bits, range_dev);
+    GSBC_LAUNCH("keys", k_keys, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, pos, sh, n,
                        grid_bits, range_dev, ka, va);
 
     const int key_bits = 24 + 3 * (int)grid_bits;
@@ -334,17 +334,17 @@ hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_
     for (int p = 0; p < passes; p++) {
         int shift = p * kDigitBits;
         uint32_t *vdst = (p == passes - 1) ? perm : vout;
-        hipLaunchKernelGGL(k_radix_hist, dim3(nblocks), dim3(256), 0, st, kin, n, shift, ntiles, hist);
-        hipLaunchKernelGGL(k_radix_colscan, dim3(kDigits / 256), dim3(256), 0, st, hist, ntiles, total);
-        hipLaunchKernelGGL(k_radix_digitscan, dim3(1), dim3(1024), 0, st, total);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(nblocks), dim3(256), 0, st, kin, vin, n, shift,
+        GSBC_LAUNCH("radix_hist", k_radix_hist, dim3(nblocks), dim3(256), 0, st, kin, n, shift, ntiles, hist);
+        GSBC_LAUNCH("radix_colscan", k_radix_colscan, dim3(kDigits / 256), dim3(256), 0, st, hist, ntiles, total);
+        GSBC_LAUNCH("radix_digitscan", k_radix_digitscan, dim3(1), dim3(1024), 0, st, total);
+        GSBC_LAUNCH("radix_scatter", k_radix_scatter, dim3(nblocks), dim3(256), 0, st, kin, vin, n, shift,
                            ntiles, hist, total, kout, vdst);
         std::swap(kin, kout);
         vin = vdst;
         vout = (vdst == va) ? vb : va;
     }
     uint64_t nblk = (n + 15) / 16;
-    hipLaunchKernelGGL(k_gather_pack, dim3((uint32_t)((nblk * 16 + 255) / 256)), dim3(256), 0, st,
+    GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((nblk * 16 + 255) / 256)), dim3(256), 0, st,
                        sh, perm, n, nblk, range_dev, reinterpret_cast<uint32_t *>(textures));
     return hipGetLastError();
 }

@@ -18,7 +18,8 @@ OK, E_ARG, E_UNSUPPORTED, E_NOMEM, E_INFEASIBLE, E_DEVICE, E_BUFFER = 0, -1, -2,
 FMT_AUTO, FMT_BC1, FMT_BC7 = 0, 1, 7
 
 EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_default_params",
-            "gsbc_query_sizes", "gsbc_reorder", "gsbc_encode", "gsbc_decode", "gsbc_decode_eval")
+            "gsbc_query_sizes", "gsbc_reorder", "gsbc_encode", "gsbc_decode", "gsbc_decode_eval",
+            "gsbc_profile_enable", "gsbc_profile_read")
 
 
 class GsbcError(RuntimeError):
@@ -77,6 +78,8 @@ def load():
                                     ctypes.POINTER(Params), P, u64, P]
         lib.gsbc_decode.argtypes = [P, P, ctypes.POINTER(StreamDesc), P]
         lib.gsbc_decode_eval.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, u32, P, u64, P]
+        lib.gsbc_profile_enable.argtypes = [P, ctypes.c_int]
+        lib.gsbc_profile_read.argtypes = [P, u32, P, P, P, ctypes.POINTER(u32)]
         for name in EXPORTED:
             if name not in ("gsbc_default_params", "gsbc_last_error"):
                 getattr(lib, name).restype = i32
@@ -153,6 +156,23 @@ class Context:
 
     def sync(self):
         self._check(load().gsbc_sync(self._h))
+
+    def profile(self, on=True):
+        """Bracket every kernel launch with HIP events on the context's stream."""
+        self._check(load().gsbc_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self, max_entries=64):
+        """{kernel name: (launches, total ms)} since the previous read."""
+        names = ctypes.create_string_buffer(64 * max_entries)
+        counts = (ctypes.c_uint32 * max_entries)()
+        ms = (ctypes.c_double * max_entries)()
+        n = ctypes.c_uint32()
+        self._check(load().gsbc_profile_read(self._h, max_entries, names, counts, ms, ctypes.byref(n)))
+        out = {}
+        for q in range(n.value):
+            name = names.raw[64 * q:64 * q + 64].split(b"\0")[0].decode()
+            out[name] = (int(counts[q]), float(ms[q]))
+        return out
 
     # ------------------------------------------------------------- calls
     def reorder(self, pos, sh, params=None, out=None):
