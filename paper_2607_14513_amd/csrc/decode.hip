@@ -3,10 +3,10 @@
 //   decode       every block of every band back to 8-bit RGBA texels;
 //   decode_eval  for each listed slot (one per lane): find its 16 band blocks
 //                by index x block size (random access, Sec. I), decode its
-//                texel from each, dequantise (vmin + q * delta), then for
-//                every view direction in the workgroup's tile evaluate
-//                c = sum_k Hhat_k Y_k(d) (Sec. II colour equation) with the
-//                basis of the direction held in scalar registers.
+//                texel from each, dequantise (vmin + q * delta); then
+//                c = sum_k Hhat_k Y_k(d) (Sec. II colour equation) for every
+//                direction, computed as a K = 16 matrix product on the
+//                matrix cores.
 #include "gsbc_internal.h"
 #include "bc_format.h"
 
@@ -14,7 +14,6 @@ namespace gsbc {
 namespace {
 
 constexpr int kEvalBlock = 256;
-constexpr int kDirTile = 128;
 
 __device__ __forceinline__ uint32_t zigzag_texel(uint32_t j)
 {
@@ -81,46 +80,105 @@ __global__ void k_sh_basis(const float *dirs, uint32_t n, float *basis)
     Y[15] = -c3a * x * (xx - 3.0f * yy);
 }
 
+// decode_eval as a contraction: out[v][3j+c] = sum_k Y[v][k] * H[j][k][c], a
+// (directions x 16) by (16 x 3m) product with K = 16.  A workgroup decodes 256
+// slots once (one lane each) into an LDS matrix Hm[k][3*slot + c], then its
+// four waves compute 16 x 16 output tiles with v_mfma_f32_16x16x4f32 (four
+// K-steps each), holding their B operands in registers across the direction
+// tiles.  Lane layout of that instruction: lane l supplies A[l%16][l/16] and
+// B[l/16][l%16] and receives D[4*(l/16) + r][l%16], r = 0..3.
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+constexpr int kSlots = 256;                 // slots per workgroup
+constexpr int kCols = 3 * kSlots;           // output floats per direction
+constexpr int kColTiles = kCols / 16;       // 48, 12 per wave
+constexpr int kDirChunk = 256;              // directions per workgroup (grid.y)
+
 __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *blocks, BandArgs b,
                                                             const uint32_t *prim_idx, uint64_t m,
                                                             uint64_t n_prims, const float *basis,
                                                             uint32_t n_dirs, float *out)
 {
-    const uint64_t j = (uint64_t)blockIdx.x * kEvalBlock + threadIdx.x;
-    if (j >= m) return;
-    const uint32_t s = prim_idx ? prim_idx[j] : (uint32_t)j;
-    const uint32_t v0 = blockIdx.y * kDirTile;
-    const uint32_t v1 = min(n_dirs, v0 + kDirTile);
-    if (s >= n_prims) {   // not a slot of this scene: NaN, no block access
-        for (uint32_t v = v0; v < v1; v++) {
-            float *o = out + ((uint64_t)v * m + j) * 3;
-            o[0] = o[1] = o[2] = __builtin_nanf("");
-        }
-        return;
-    }
-    const uint64_t blk = s >> 4;
-    const int texel = (int)zigzag_texel(s & 15u);
-    float H[16][3];
+    __shared__ float Hm[16][kCols];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const uint64_t j0 = (uint64_t)blockIdx.x * kSlots;
+    // ---- decode: lane t -> slot j0 + t
+    {
+        const uint64_t j = j0 + t;
+        float h[16][3];
+        if (j < m) {
+            const uint32_t s = prim_idx ? prim_idx[j] : (uint32_t)j;
+            if (s < n_prims) {
+                const uint64_t blk = s >> 4;
+                const int texel = (int)zigzag_texel(s & 15u);
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-        uint32_t px = band_texel(blocks, b, k, blk, texel);
-        H[k][0] = fmaf((float)(px & 255), b.delta[k], b.vmin[k]);
-        H[k][1] = fmaf((float)((px >> 8) & 255), b.delta[k], b.vmin[k]);
-        H[k][2] = fmaf((float)((px >> 16) & 255), b.delta[k], b.vmin[k]);
-    }
-    for (uint32_t v = v0; v < v1; v++) {
-        const float *Y = basis + 16 * (uint64_t)v;
-        float r = H[0][0] * Y[0], g = H[0][1] * Y[0], bl = H[0][2] * Y[0];
+                for (int k = 0; k < 16; k++) {
+                    uint32_t px = band_texel(blocks, b, k, blk, texel);
+                    h[k][0] = fmaf((float)(px & 255), b.delta[k], b.vmin[k]);
+                    h[k][1] = fmaf((float)((px >> 8) & 255), b.delta[k], b.vmin[k]);
+                    h[k][2] = fmaf((float)((px >> 16) & 255), b.delta[k], b.vmin[k]);
+                }
+            } else {   // not a slot of this scene: NaN colours, no block access
 #pragma unroll
-        for (int k = 1; k < 16; k++) {
-            r = fmaf(H[k][0], Y[k], r);
-            g = fmaf(H[k][1], Y[k], g);
-            bl = fmaf(H[k][2], Y[k], bl);
+                for (int k = 0; k < 16; k++) h[k][0] = h[k][1] = h[k][2] = __builtin_nanf("");
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 16; k++) h[k][0] = h[k][1] = h[k][2] = 0.0f;
         }
-        float *o = out + ((uint64_t)v * m + j) * 3;
-        __builtin_nontemporal_store(r, o);
-        __builtin_nontemporal_store(g, o + 1);
-        __builtin_nontemporal_store(bl, o + 2);
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            Hm[k][3 * t] = h[k][0];
+            Hm[k][3 * t + 1] = h[k][1];
+            Hm[k][3 * t + 2] = h[k][2];
+        }
+    }
+    __syncthreads();
+    // ---- B operands of this wave's 12 column tiles, held across directions
+    const int row = lane >> 4, col = lane & 15;
+    float bop[12][4];
+#pragma unroll
+    for (int q = 0; q < 12; q++) {
+        const int c0 = 16 * (wave * 12 + q);
+#pragma unroll
+        for (int s = 0; s < 4; s++) bop[q][s] = Hm[4 * s + row][c0 + col];
+    }
+    const uint64_t cols_valid = (m - j0 < (uint64_t)kSlots ? m - j0 : (uint64_t)kSlots) * 3;
+    const uint64_t row_stride = 3 * m;
+    const uint32_t wcol0 = 16 * 12 * wave;                  // this wave's first column
+    float *obase = out + 3 * j0 + wcol0;
+    // Hm is dead once every wave holds its B operands: its rows become each
+    // wave's staging area (16 rows x 192 columns), so results leave as whole
+    // row segments (each store instruction writes 256 contiguous bytes).
+    __syncthreads();
+    float(*stage)[192] = reinterpret_cast<float(*)[192]>(&Hm[0][0]) + 16 * wave;
+    const uint32_t v_end = min(n_dirs, (blockIdx.y + 1) * kDirChunk);
+    for (uint32_t v0 = blockIdx.y * kDirChunk; v0 < v_end; v0 += 16) {
+        // A operand: Y[v0 + col][4s + row]
+        float aop[4];
+        const uint32_t va = v0 + col;
+#pragma unroll
+        for (int s = 0; s < 4; s++) aop[s] = va < n_dirs ? basis[16 * (uint64_t)va + 4 * s + row] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < 12; q++) {
+            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int s = 0; s < 4; s++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[s], bop[q][s], acc, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; r++) stage[4 * row + r][16 * q + col] = acc[r];
+        }
+        // rows v0..v0+15, 192 floats each = 3 x 64 lanes
+#pragma unroll 4
+        for (int rr = 0; rr < 16; rr++) {
+            const uint32_t v = v0 + rr;
+            if (v >= v_end) break;
+            float *orow = obase + v * row_stride;
+#pragma unroll
+            for (int h = 0; h < 3; h++) {
+                const uint32_t c = 64 * h + lane;
+                const float x = stage[rr][c];
+                if (wcol0 + c < cols_valid) __builtin_nontemporal_store(x, orow + c);
+            }
+        }
     }
 }
 
@@ -141,7 +199,7 @@ hipError_t launch_decode_eval(const uint8_t *blocks, const BandArgs &b, uint64_t
 {
     if (m == 0 || n_dirs == 0) return hipSuccess;
     GSBC_LAUNCH("sh_basis", k_sh_basis, dim3((n_dirs + 255) / 256), dim3(256), 0, st, dirs, n_dirs, basis);
-    dim3 grid((uint32_t)((m + kEvalBlock - 1) / kEvalBlock), (n_dirs + kDirTile - 1) / kDirTile);
+    dim3 grid((uint32_t)((m + kSlots - 1) / kSlots), (n_dirs + kDirChunk - 1) / kDirChunk);
     GSBC_LAUNCH("decode_eval", k_decode_eval, grid, dim3(kEvalBlock), 0, st, blocks, b, prim_idx, m, n_prims, basis,
                        n_dirs, out);
     return hipGetLastError();
