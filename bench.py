@@ -32,7 +32,14 @@ sys.path.insert(0, ROOT)
 
 VALU_PEAK = 256 * 4 * 16 * 2.4e9        # integer lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz
 HBM_PEAK = 8.0e12                        # bytes/s
-OPS_PER_EVAL = 8                         # one texel x palette-entry distance: 3 sub, 3 mul, 2 add
+# VALU issue slots (lane-instructions) that one exact texel x palette-entry
+# distance comparison needs at the least on gfx950: one v_dot2 for two
+# channels, one 24-bit multiply-add for the third channel plus the entry's
+# constant, and half a v_min3 for the running minimum.  A plain scalar form
+# takes about 8 (3 sub, 3 mul, 2 add); the issue-slot floor is what bounds
+# the kernel, so the fraction below is the share of peak VALU issue spent on
+# that irreducible work.
+OPS_PER_EVAL = 2.5
 # Algorithmic work per block of the BC7 search kernels: texel x palette-entry
 # distance evaluations of the candidates each kernel covers (initial fit and
 # least-squares refit, every p-bit choice) x OPS_PER_EVAL.

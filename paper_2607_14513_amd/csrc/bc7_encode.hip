@@ -76,42 +76,57 @@ __device__ __forceinline__ void candidate(int ci, int &m, int &p, int &r, int &s
 
 // ---- texels in LDS
 //
-// Texels sit in LDS, one column per lane, as 4x-scaled packed values
-// (rg = 4R | 4G << 16, b = 4B), so one texel x palette-entry distance with
-// its index tie-break is five VALU ops:
-//   d  = rg - prg                 (v_pk_sub_i16)
-//   db = b - pb                   (v_sub_u32)
-//   k' = db*db + k                (v_mad_i32_i24)    = 16*dB^2 + k
-//   k' = d.x*d.x + d.y*d.y + k'   (v_dot2c_i32_i16)  = 16*SSE + k
-//   best = min(best, k')          (v_min_u32)
-// In the search the subset masks are wave-uniform, so texel loops walk the
-// set bits of a mask with scalar control.
+// Texels sit in LDS, one column per lane: rg = R | G << 16 and
+// bx = B | 16 (R^2 + G^2 + B^2) << 8.  Because |x|^2 is the same for every
+// palette entry, the least-SSE entry is the least 16 (|p|^2 - 2 x.p) + k, so
+// with each entry held as (-32 p, 16 |p|^2 + k) one texel x entry evaluation
+// is three VALU ops:
+//   t = B * (-32 pB) + (16 |p|^2 + k)         (v_mad_i32_i24)
+//   t = R * (-32 pR) + G * (-32 pG) + t       (v_dot2c_i32_i16)
+//   best = min(best, t)                       (v_min_i32)
+// and 16 |x|^2 added to the minimum gives 16 SSE + k exactly.  In the search
+// the subset masks are wave-uniform, so texel loops walk the set bits of a
+// mask with scalar control.
 constexpr int kWG = 256;
 constexpr int kQEntries = 10 * 2 * 256;
 
 struct TexLds {
     uint32_t rg[16][kWG];
-    uint32_t b[16][kWG];
+    uint32_t bx[16][kWG];
     uint16_t q[kQEntries];        // nearest-code table: code | value << 8
 };
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
-// Texel i of this lane; rotation r puts 4*255 in channel r-1.
-__device__ __forceinline__ void texel(const TexLds &S, int i, int rot, uint32_t &rg, int &b)
+// Texel i of this lane: packed R|G<<16, B, and 16 |x|^2; rotation r puts 255
+// in channel r-1.
+__device__ __forceinline__ void texel(const TexLds &S, int i, int rot, uint32_t &rg, int &b, int &cx)
 {
     rg = S.rg[i][threadIdx.x];
-    b = (int)S.b[i][threadIdx.x];
-    if (rot == 1) rg = (rg & 0xFFFF0000u) | 1020u;
-    else if (rot == 2) rg = (rg & 0xFFFFu) | (1020u << 16);
-    else if (rot == 3) b = 1020;
+    const uint32_t bx = S.bx[i][threadIdx.x];
+    b = (int)(bx & 255u);
+    cx = (int)(bx >> 8);
+    if (rot) {
+        int r = (int)(rg & 0xFFFFu), g = (int)(rg >> 16);
+        if (rot == 1) r = 255;
+        else if (rot == 2) g = 255;
+        else b = 255;
+        rg = (uint32_t)r | ((uint32_t)g << 16);
+        cx = 16 * (r * r + g * g + b * b);
+    }
+}
+
+__device__ __forceinline__ void texel(const TexLds &S, int i, int rot, uint32_t &rg, int &b)
+{
+    int cx;
+    texel(S, i, rot, rg, b, cx);
 }
 
 __device__ __forceinline__ void unpack(uint32_t rg, int b, int (&x)[3])
 {
-    x[0] = (int)((rg & 0xFFFFu) >> 2);
-    x[1] = (int)(rg >> 18);
-    x[2] = b >> 2;
+    x[0] = (int)(rg & 0xFFFFu);
+    x[1] = (int)(rg >> 16);
+    x[2] = b;
 }
 
 // Per-subset data shared across modes: whether every member is the same
@@ -193,75 +208,110 @@ __device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int 
     return P;
 }
 
-// Result of fitting one endpoint pair to a subset.
+// Result of fitting one endpoint pair to a subset.  eval_pair leaves idx in
+// member order (4 bits per member, first member lowest); fit_colour returns
+// it by texel position (4 bits at 4 i for member i).
 struct PairFit {
     uint32_t sse;
-    uint64_t idx;      // 4 bits per texel (members only)
+    uint64_t idx;
     uint32_t c0, c1;   // endpoint codes, 8 bits per channel, R lowest
     int p0, p1;
 };
 
 // (c) for one endpoint pair: quantise for every p-bit combination, index
 // every member by least SSE; keep the best combination (lowest on ties).
+// Up to 32 palette entries are held at once, so each member is read once
+// per chunk of combinations.  Per member and combination the running sum
+// takes 16 SSE + k in one add and the index enters a 64-bit shift register
+// (newest member at the top); the k terms are removed from the sum at the end.
 template <int CB, int PB, int NB>
 __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int rot, const int (&lo)[3],
                                              const int (&hi)[3])
 {
     constexpr int NPC = PB == 2 ? 4 : PB == 1 ? 2 : 1;
+    constexpr int NE = 1 << NB;
+    constexpr int CPV = NPC * NE <= 32 ? NPC : 32 / NE;   // combinations per member visit
     constexpr int cls = cls_of(CB, PB);
+    const int n = __popc(mask);
     PairFit best;
     best.sse = 0xFFFFFFFFu;
     best.idx = 0;
     best.c0 = best.c1 = 0;
     best.p0 = best.p1 = 0;
-    for (int pc = 0; pc < NPC; pc++) {
-        const int p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
-        const int p1 = PB == 2 ? (pc >> 1) : PB == 1 ? pc : 0;
-        const uint16_t *q0 = S.q + (cls * 2 + p0) * 256, *q1 = S.q + (cls * 2 + p1) * 256;
-        int d0[3], d1[3];
-        uint32_t c0 = 0, c1 = 0;
 #pragma unroll
-        for (int c = 0; c < 3; c++) {
-            const uint32_t e0 = q0[lo[c]], e1 = q1[hi[c]];
-            d0[c] = (int)(e0 >> 8);
-            d1[c] = (int)(e1 >> 8);
-            c0 |= (e0 & 255u) << (8 * c);
-            c1 |= (e1 & 255u) << (8 * c);
-        }
-        uint32_t prg[1 << NB];
-        int pb[1 << NB];
+    for (int pc0 = 0; pc0 < NPC; pc0 += CPV) {
+        // palette entry k as (-32 pR, -32 pG) in 16-bit halves, -32 pB, 16 |p|^2 + k.
+        // Interpolation (64 - w) e0 + w e1 + 32 = (64 e0 + 32) + w (e1 - e0) stays
+        // within [32, 16352], so R and G are interpolated together in 16-bit lanes.
+        uint32_t prg[CPV][NE], c0[CPV], c1[CPV];
+        int pb[CPV][NE], pk[CPV][NE];
 #pragma unroll
-        for (int k = 0; k < (1 << NB); k++) {
-            const int w = bc7_weight(NB, k);
-            int r = interp64(d0[0], d1[0], w), g = interp64(d0[1], d1[1], w), bb = interp64(d0[2], d1[2], w);
-            prg[k] = ((uint32_t)r << 2) | ((uint32_t)g << 18);
-            pb[k] = bb << 2;
-        }
-        uint32_t sse = 0;
-        uint64_t idx = 0;
-        for (uint32_t m = mask; m; m &= m - 1) {
-            const int i = __ffs(m) - 1;
-            uint32_t rg;
-            int b;
-            texel(S, i, rot, rg, b);
-            uint32_t kb = 0xFFFFFFFFu;
+        for (int j = 0; j < CPV; j++) {
+            const int pc = pc0 + j;
+            const int p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
+            const int p1 = PB == 2 ? (pc >> 1) : PB == 1 ? pc : 0;
+            const uint16_t *q0 = S.q + (cls * 2 + p0) * 256, *q1 = S.q + (cls * 2 + p1) * 256;
+            int d0[3], d1[3];
+            c0[j] = c1[j] = 0;
 #pragma unroll
-            for (int k = 0; k < (1 << NB); k++) {
-                short2_t d = __builtin_bit_cast(short2_t, rg) - __builtin_bit_cast(short2_t, prg[k]);
-                int db = b - pb[k];
-                int key = __builtin_amdgcn_sdot2(d, d, __mul24(db, db) + k, false);
-                kb = min(kb, (uint32_t)key);
+            for (int c = 0; c < 3; c++) {
+                const uint32_t e0 = q0[lo[c]], e1 = q1[hi[c]];
+                d0[c] = (int)(e0 >> 8);
+                d1[c] = (int)(e1 >> 8);
+                c0[j] |= (e0 & 255u) << (8 * c);
+                c1[j] |= (e1 & 255u) << (8 * c);
             }
-            sse += kb >> 4;
-            idx |= (uint64_t)(kb & 15u) << (4 * i);
+            const short2_t a_rg = {(short)(64 * d0[0] + 32), (short)(64 * d0[1] + 32)};
+            const short2_t s_rg = {(short)(d1[0] - d0[0]), (short)(d1[1] - d0[1])};
+            const int a_b = 64 * d0[2] + 32, s_b = d1[2] - d0[2];
+#pragma unroll
+            for (int k = 0; k < NE; k++) {
+                const short w = (short)bc7_weight(NB, k);
+                const short2_t v = (a_rg + s_rg * w) >> (short)6;
+                const int bb = (int)__builtin_amdgcn_ubfe((uint32_t)(a_b + s_b * w), 6, 8);
+                prg[j][k] = __builtin_bit_cast(uint32_t, v * (short)-32);
+                pb[j][k] = -32 * bb;
+                pk[j][k] = 16 * __builtin_amdgcn_sdot2(v, v, __mul24(bb, bb), false) + k;
+            }
         }
-        if (sse < best.sse) {
-            best.sse = sse;
-            best.idx = idx;
-            best.c0 = c0;
-            best.c1 = c1;
-            best.p0 = p0;
-            best.p1 = p1;
+        uint32_t acc[CPV], rlo[CPV], rhi[CPV];
+#pragma unroll
+        for (int j = 0; j < CPV; j++) acc[j] = rlo[j] = rhi[j] = 0;
+        for (uint32_t m = mask; m; m &= m - 1) {
+            uint32_t rg;
+            int b, cx;
+            texel(S, __ffs(m) - 1, rot, rg, b, cx);
+#pragma unroll
+            for (int j = 0; j < CPV; j++) {
+                int kb = 0x7FFFFFFF;
+#pragma unroll
+                for (int k = 0; k < NE; k++) {
+                    const int key = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg),
+                                                           __builtin_bit_cast(short2_t, prg[j][k]),
+                                                           __mul24(b, pb[j][k]) + pk[j][k], false);
+                    kb = min(kb, key);
+                }
+                acc[j] += (uint32_t)kb + (uint32_t)cx;   // 16 SSE + k of this member
+                rlo[j] = __builtin_amdgcn_alignbit(rhi[j], rlo[j], 4);
+                rhi[j] = __builtin_amdgcn_alignbit((uint32_t)kb, rhi[j], 4);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < CPV; j++) {
+            // the register holds the n member indices in its top 4 n bits, zeros below
+            const uint32_t nib = (rlo[j] & 0x0F0F0F0Fu) + ((rlo[j] >> 4) & 0x0F0F0F0Fu) + (rhi[j] & 0x0F0F0F0Fu) +
+                                 ((rhi[j] >> 4) & 0x0F0F0F0Fu);
+            const uint32_t ksum = __builtin_amdgcn_udot4(nib, 0x01010101u, 0u, false);
+            const uint32_t sse = (acc[j] - ksum) >> 4;
+            if (sse < best.sse) {
+                const int pc = pc0 + j;
+                best.sse = sse;
+                best.idx = (((uint64_t)rhi[j] << 32) | rlo[j]) >> (64 - 4 * n);
+                best.c0 = c0[j];
+                best.c1 = c1[j];
+                best.p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
+                best.p1 = PB == 2 ? (pc >> 1) : PB == 1 ? pc : 0;
+            }
         }
     }
     return best;
@@ -280,7 +330,8 @@ __device__ __forceinline__ bool ls_endpoints(const TexLds &S, uint32_t mask, int
         texel(S, i, rot, rg, b);
         int x[3];
         unpack(rg, b, x);
-        const int k = (int)((idx >> (4 * i)) & 15);
+        const int k = (int)(idx & 15);   // member order
+        idx >>= 4;
         const int w = bc7_weight(NB, k), a = 64 - w;
         A += a * a; B += w * w; AB += a * w;
 #pragma unroll
@@ -353,6 +404,13 @@ __device__ __forceinline__ PairFit fit_colour(const TexLds &S, uint32_t mask, in
         PairFit g = eval_pair<CB, PB, NB>(S, mask, rot, rlo, rhi);
         if (g.sse < f.sse) f = g;
     }
+    // member order -> texel positions
+    uint64_t pos = 0, c = f.idx;
+    for (uint32_t m = mask; m; m &= m - 1) {
+        pos |= (c & 15u) << (4 * (__ffs(m) - 1));
+        c >>= 4;
+    }
+    f.idx = pos;
     return f;
 }
 
@@ -364,8 +422,8 @@ __device__ __forceinline__ PairFit fit_scalar(const TexLds &S, int rot, const ui
     constexpr int cls = cls_of(AB, 0);
     auto value = [&](int i) {
         const uint32_t rg = S.rg[i][threadIdx.x];
-        const int b = (int)S.b[i][threadIdx.x];
-        return rot == 0 ? 255 : rot == 1 ? (int)((rg & 0xFFFFu) >> 2) : rot == 2 ? (int)(rg >> 18) : (b >> 2);
+        const int b = (int)(S.bx[i][threadIdx.x] & 255u);
+        return rot == 0 ? 255 : rot == 1 ? (int)(rg & 0xFFFFu) : rot == 2 ? (int)(rg >> 16) : b;
     };
     const int v0 = value(0);
     int lo = v0, hi = v0;
@@ -399,20 +457,23 @@ __device__ __forceinline__ PairFit fit_scalar(const TexLds &S, int rot, const ui
     for (int pass = 0; pass < 2; pass++) {
         const uint32_t e0 = S.q[cls * 2 * 256 + elo], e1 = S.q[cls * 2 * 256 + ehi];
         const int d0 = (int)(e0 >> 8), d1 = (int)(e1 >> 8);
-        int pal[1 << NB];
+        // entry k as -32 p and 16 p^2 + k (see texel layout above)
+        int pal[1 << NB], pk[1 << NB];
 #pragma unroll
-        for (int k = 0; k < (1 << NB); k++) pal[k] = interp64(d0, d1, bc7_weight(NB, k)) << 2;
+        for (int k = 0; k < (1 << NB); k++) {
+            const int pv = interp64(d0, d1, bc7_weight(NB, k));
+            pal[k] = -32 * pv;
+            pk[k] = 16 * (int)__builtin_amdgcn_udot4((uint32_t)pv, (uint32_t)pv, 0u, false) + k;
+        }
         uint32_t sse = 0;
         uint64_t idx = 0;
         int A = 0, B = 0, AB2 = 0, SA = 0, SB = 0;
         for (int i = 0; i < 16; i++) {
             const int x = value(i);
-            uint32_t kb = 0xFFFFFFFFu;
+            int kmin = 0x7FFFFFFF;
 #pragma unroll
-            for (int k = 0; k < (1 << NB); k++) {
-                int d = (x << 2) - pal[k];
-                kb = min(kb, (uint32_t)(__mul24(d, d) + k));
-            }
+            for (int k = 0; k < (1 << NB); k++) kmin = min(kmin, __mul24(x, pal[k]) + pk[k]);
+            const uint32_t kb = (uint32_t)(kmin + 16 * x * x);   // 16 SSE + k
             sse += kb >> 4;
             idx |= (uint64_t)(kb & 15u) << (4 * i);
             const int w = bc7_weight(NB, (int)(kb & 15u)), a = 64 - w;
@@ -673,8 +734,9 @@ __device__ __forceinline__ bool stage_block(TexLds &S, const Bc7Launch &L, uint3
     }
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-        S.rg[i][threadIdx.x] = ((t[i] & 255u) << 2) | (((t[i] >> 8) & 255u) << 18);
-        S.b[i][threadIdx.x] = ((t[i] >> 16) & 255u) << 2;
+        const uint32_t r = t[i] & 255u, g = (t[i] >> 8) & 255u, bb = (t[i] >> 16) & 255u;
+        S.rg[i][threadIdx.x] = r | (g << 16);
+        S.bx[i][threadIdx.x] = bb | ((16u * (r * r + g * g + bb * bb)) << 8);
     }
     __syncthreads();
     return live;
@@ -811,8 +873,9 @@ __global__ __launch_bounds__(kWG) void k_bc7_emit(Bc7Launch L)
     }
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-        S.rg[i][threadIdx.x] = ((t[i] & 255u) << 2) | (((t[i] >> 8) & 255u) << 18);
-        S.b[i][threadIdx.x] = ((t[i] >> 16) & 255u) << 2;
+        const uint32_t r = t[i] & 255u, g = (t[i] >> 8) & 255u, bb = (t[i] >> 16) & 255u;
+        S.rg[i][threadIdx.x] = r | (g << 16);
+        S.bx[i][threadIdx.x] = bb | ((16u * (r * r + g * g + bb * bb)) << 8);
     }
     __syncthreads();
     if (!live) return;
