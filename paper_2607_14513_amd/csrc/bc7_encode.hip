@@ -76,17 +76,20 @@ __device__ __forceinline__ void candidate(int ci, int &m, int &p, int &r, int &s
 
 // ---- texels in LDS
 //
-// Texels sit in LDS, one column per lane: rg = R | G << 16 and
-// bx = B | 16 (R^2 + G^2 + B^2) << 8.  Because |x|^2 is the same for every
-// palette entry, the least-SSE entry is the least 16 (|p|^2 - 2 x.p) + k, so
-// with each entry held as (-32 p, 16 |p|^2 + k) one texel x entry evaluation
-// is three VALU ops:
-//   t = B * (-32 pB) + (16 |p|^2 + k)         (v_mad_i32_i24)
-//   t = R * (-32 pR) + G * (-32 pG) + t       (v_dot2c_i32_i16)
-//   best = min(best, t)                       (v_min_i32)
-// and 16 |x|^2 added to the minimum gives 16 SSE + k exactly.  In the search
-// the subset masks are wave-uniform, so texel loops walk the set bits of a
-// mask with scalar control.
+// Texels sit in LDS, one column per lane: rg = 16 R | 16 G << 16 and
+// bx = B | 256 (R^2 + G^2 + B^2) (the low byte of the second term is zero).
+// Because |x|^2 is the same for every palette entry, the least-SSE entry is
+// the least 256 (|p|^2 - 2 x.p) + k, so with each entry held as
+// (-32 pR, -32 pG), -512 pB and 256 |p|^2 + k one texel x entry evaluation is
+// three VALU ops:
+//   t = B * (-512 pB) + (256 |p|^2 + k)            (v_mad_i32_i24)
+//   t = 16 R * (-32 pR) + 16 G * (-32 pG) + t      (v_dot2c_i32_i16)
+//   best = min(best, t)                            (v_min_i32)
+// and 256 |x|^2 added to the minimum gives 256 SSE + k exactly (all terms
+// stay within int32: |t| < 2^26).  Summed over at most 16 members the k
+// terms stay below 256, so the subset SSE is the sum shifted right by 8.
+// In the search the subset masks are wave-uniform, so texel loops walk the
+// set bits of a mask with scalar control.
 constexpr int kWG = 256;
 constexpr int kQEntries = 10 * 2 * 256;
 
@@ -98,21 +101,21 @@ struct TexLds {
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
-// Texel i of this lane: packed R|G<<16, B, and 16 |x|^2; rotation r puts 255
-// in channel r-1.
+// Texel i of this lane: packed 16 R | 16 G << 16, B, and 256 |x|^2;
+// rotation r puts 255 in channel r-1.
 __device__ __forceinline__ void texel(const TexLds &S, int i, int rot, uint32_t &rg, int &b, int &cx)
 {
     rg = S.rg[i][threadIdx.x];
     const uint32_t bx = S.bx[i][threadIdx.x];
     b = (int)(bx & 255u);
-    cx = (int)(bx >> 8);
+    cx = (int)(bx & ~255u);
     if (rot) {
-        int r = (int)(rg & 0xFFFFu), g = (int)(rg >> 16);
+        int r = (int)__builtin_amdgcn_ubfe(rg, 4, 8), g = (int)(rg >> 20);
         if (rot == 1) r = 255;
         else if (rot == 2) g = 255;
         else b = 255;
-        rg = (uint32_t)r | ((uint32_t)g << 16);
-        cx = 16 * (r * r + g * g + b * b);
+        rg = (uint32_t)(16 * r) | ((uint32_t)(16 * g) << 16);
+        cx = 256 * (r * r + g * g + b * b);
     }
 }
 
@@ -124,8 +127,8 @@ __device__ __forceinline__ void texel(const TexLds &S, int i, int rot, uint32_t 
 
 __device__ __forceinline__ void unpack(uint32_t rg, int b, int (&x)[3])
 {
-    x[0] = (int)(rg & 0xFFFFu);
-    x[1] = (int)(rg >> 16);
+    x[0] = (int)__builtin_amdgcn_ubfe(rg, 4, 8);
+    x[1] = (int)(rg >> 20);
     x[2] = b;
 }
 
@@ -162,14 +165,15 @@ __device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int 
     P.hi[0] = P.lo[0]; P.hi[1] = P.lo[1]; P.hi[2] = P.lo[2];
     if (same) return P;
     // principal axis: integer power iteration on the exact covariance
+    // n <= 16, XX < 2^21 and Sx < 2^12: 24-bit multiplies with exact products
     const int n = __popc(mask);
     int C[3][3];
-    C[0][0] = n * XX[0] - Sx[0] * Sx[0];
-    C[0][1] = C[1][0] = n * XX[1] - Sx[0] * Sx[1];
-    C[0][2] = C[2][0] = n * XX[2] - Sx[0] * Sx[2];
-    C[1][1] = n * XX[3] - Sx[1] * Sx[1];
-    C[1][2] = C[2][1] = n * XX[4] - Sx[1] * Sx[2];
-    C[2][2] = n * XX[5] - Sx[2] * Sx[2];
+    C[0][0] = __mul24(n, XX[0]) - __mul24(Sx[0], Sx[0]);
+    C[0][1] = C[1][0] = __mul24(n, XX[1]) - __mul24(Sx[0], Sx[1]);
+    C[0][2] = C[2][0] = __mul24(n, XX[2]) - __mul24(Sx[0], Sx[2]);
+    C[1][1] = __mul24(n, XX[3]) - __mul24(Sx[1], Sx[1]);
+    C[1][2] = C[2][1] = __mul24(n, XX[4]) - __mul24(Sx[1], Sx[2]);
+    C[2][2] = __mul24(n, XX[5]) - __mul24(Sx[2], Sx[2]);
     // row of the largest diagonal entry (lowest index on ties), by selects
     const int j = (C[1][1] > C[0][0]) ? ((C[2][2] > C[1][1]) ? 2 : 1) : ((C[2][2] > C[0][0]) ? 2 : 0);
     const int tsh = max(0, bitlen(j == 0 ? C[0][0] : (j == 1 ? C[1][1] : C[2][2])) - 14);
@@ -181,11 +185,22 @@ __device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int 
     int v[3];
 #pragma unroll
     for (int c = 0; c < 3; c++) v[c] = j == 0 ? Cs[0][c] : (j == 1 ? Cs[1][c] : Cs[2][c]);
+    // |Cs| <= 2^14 (the largest diagonal is below 2^14 and bounds every entry
+    // of the positive semi-definite C) and |v| <= 2^15, so the products are
+    // 16-bit dot products with exact 32-bit sums (|u| < 3 * 2^29).
+    short2_t c01[3], c2[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        c01[a] = short2_t{(short)Cs[a][0], (short)Cs[a][1]};
+        c2[a] = short2_t{(short)Cs[a][2], (short)0};
+    }
 #pragma unroll
     for (int it = 0; it < 8; it++) {
+        const short2_t v01 = {(short)v[0], (short)v[1]}, v2 = {(short)v[2], (short)0};
         int u[3];
 #pragma unroll
-        for (int a = 0; a < 3; a++) u[a] = Cs[a][0] * v[0] + Cs[a][1] * v[1] + Cs[a][2] * v[2];
+        for (int a = 0; a < 3; a++)
+            u[a] = __builtin_amdgcn_sdot2(c01[a], v01, __builtin_amdgcn_sdot2(c2[a], v2, 0, false), false);
         int mx = max(abs(u[0]), max(abs(u[1]), abs(u[2])));
         int sh = max(0, bitlen(mx) - 15);
 #pragma unroll
@@ -221,16 +236,17 @@ struct PairFit {
 // (c) for one endpoint pair: quantise for every p-bit combination, index
 // every member by least SSE; keep the best combination (lowest on ties).
 // Up to 32 palette entries are held at once, so each member is read once
-// per chunk of combinations.  Per member and combination the running sum
-// takes 16 SSE + k in one add and the index enters a 64-bit shift register
-// (newest member at the top); the k terms are removed from the sum at the end.
+// for all combinations (once per combination for 16-entry palettes).  Per member and combination the running sum
+// takes 256 SSE + k in one add and the index enters a 64-bit shift register
+// (newest member at the top; the register holds the n indices in its top
+// 4 n bits).
 template <int CB, int PB, int NB>
 __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int rot, const int (&lo)[3],
                                              const int (&hi)[3])
 {
     constexpr int NPC = PB == 2 ? 4 : PB == 1 ? 2 : 1;
     constexpr int NE = 1 << NB;
-    constexpr int CPV = NPC * NE <= 32 ? NPC : 32 / NE;   // combinations per member visit
+    constexpr int CPV = NPC * NE <= 32 ? NPC : 1;   // combinations per member visit
     constexpr int cls = cls_of(CB, PB);
     const int n = __popc(mask);
     PairFit best;
@@ -240,7 +256,7 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
     best.p0 = best.p1 = 0;
 #pragma unroll
     for (int pc0 = 0; pc0 < NPC; pc0 += CPV) {
-        // palette entry k as (-32 pR, -32 pG) in 16-bit halves, -32 pB, 16 |p|^2 + k.
+        // palette entry k as (-32 pR, -32 pG) in 16-bit halves, -512 pB, 256 |p|^2 + k.
         // Interpolation (64 - w) e0 + w e1 + 32 = (64 e0 + 32) + w (e1 - e0) stays
         // within [32, 16352], so R and G are interpolated together in 16-bit lanes.
         uint32_t prg[CPV][NE], c0[CPV], c1[CPV];
@@ -270,8 +286,8 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
                 const short2_t v = (a_rg + s_rg * w) >> (short)6;
                 const int bb = (int)__builtin_amdgcn_ubfe((uint32_t)(a_b + s_b * w), 6, 8);
                 prg[j][k] = __builtin_bit_cast(uint32_t, v * (short)-32);
-                pb[j][k] = -32 * bb;
-                pk[j][k] = 16 * __builtin_amdgcn_sdot2(v, v, __mul24(bb, bb), false) + k;
+                pb[j][k] = -512 * bb;
+                pk[j][k] = 256 * __builtin_amdgcn_sdot2(v, v, __mul24(bb, bb), false) + k;
             }
         }
         uint32_t acc[CPV], rlo[CPV], rhi[CPV];
@@ -291,18 +307,14 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
                                                            __mul24(b, pb[j][k]) + pk[j][k], false);
                     kb = min(kb, key);
                 }
-                acc[j] += (uint32_t)kb + (uint32_t)cx;   // 16 SSE + k of this member
+                acc[j] += (uint32_t)kb + (uint32_t)cx;   // 256 SSE + k of this member
                 rlo[j] = __builtin_amdgcn_alignbit(rhi[j], rlo[j], 4);
                 rhi[j] = __builtin_amdgcn_alignbit((uint32_t)kb, rhi[j], 4);
             }
         }
 #pragma unroll
         for (int j = 0; j < CPV; j++) {
-            // the register holds the n member indices in its top 4 n bits, zeros below
-            const uint32_t nib = (rlo[j] & 0x0F0F0F0Fu) + ((rlo[j] >> 4) & 0x0F0F0F0Fu) + (rhi[j] & 0x0F0F0F0Fu) +
-                                 ((rhi[j] >> 4) & 0x0F0F0F0Fu);
-            const uint32_t ksum = __builtin_amdgcn_udot4(nib, 0x01010101u, 0u, false);
-            const uint32_t sse = (acc[j] - ksum) >> 4;
+            const uint32_t sse = acc[j] >> 8;
             if (sse < best.sse) {
                 const int pc = pc0 + j;
                 best.sse = sse;
@@ -423,7 +435,7 @@ __device__ __forceinline__ PairFit fit_scalar(const TexLds &S, int rot, const ui
     auto value = [&](int i) {
         const uint32_t rg = S.rg[i][threadIdx.x];
         const int b = (int)(S.bx[i][threadIdx.x] & 255u);
-        return rot == 0 ? 255 : rot == 1 ? (int)(rg & 0xFFFFu) : rot == 2 ? (int)(rg >> 16) : b;
+        return rot == 0 ? 255 : rot == 1 ? (int)__builtin_amdgcn_ubfe(rg, 4, 8) : rot == 2 ? (int)(rg >> 20) : b;
     };
     const int v0 = value(0);
     int lo = v0, hi = v0;
@@ -735,8 +747,8 @@ __device__ __forceinline__ bool stage_block(TexLds &S, const Bc7Launch &L, uint3
 #pragma unroll
     for (int i = 0; i < 16; i++) {
         const uint32_t r = t[i] & 255u, g = (t[i] >> 8) & 255u, bb = (t[i] >> 16) & 255u;
-        S.rg[i][threadIdx.x] = r | (g << 16);
-        S.bx[i][threadIdx.x] = bb | ((16u * (r * r + g * g + bb * bb)) << 8);
+        S.rg[i][threadIdx.x] = (r << 4) | (g << 20);
+        S.bx[i][threadIdx.x] = bb | (256u * (r * r + g * g + bb * bb));
     }
     __syncthreads();
     return live;
@@ -874,8 +886,8 @@ __global__ __launch_bounds__(kWG) void k_bc7_emit(Bc7Launch L)
 #pragma unroll
     for (int i = 0; i < 16; i++) {
         const uint32_t r = t[i] & 255u, g = (t[i] >> 8) & 255u, bb = (t[i] >> 16) & 255u;
-        S.rg[i][threadIdx.x] = r | (g << 16);
-        S.bx[i][threadIdx.x] = bb | ((16u * (r * r + g * g + bb * bb)) << 8);
+        S.rg[i][threadIdx.x] = (r << 4) | (g << 20);
+        S.bx[i][threadIdx.x] = bb | (256u * (r * r + g * g + bb * bb));
     }
     __syncthreads();
     if (!live) return;
