@@ -7,8 +7,8 @@
 // normal-equation determinants are scalar, and each lane only evaluates its
 // own numerators, quantised endpoints and SSE.  Per-lane prefix sums of the
 // ordered texels live in LDS, one column per lane (conflict-free reads at a
-// uniform row).  Every decision is integer; ties take the first candidate in
-// the fixed enumeration order.
+// uniform row), and so does the nearest-code table.  Every decision is
+// integer; ties take the first candidate in the fixed enumeration order.
 //
 // Steps: constant block -> per-channel endpoint tables; otherwise principal
 // axis by integer power iteration, texels ordered by projection, every
@@ -25,12 +25,24 @@ namespace {
 
 constexpr int kBlock = 128;   // lanes per workgroup
 
-// Constant-colour endpoint tables per channel width (0: 5 bits, 1: 6 bits).
+// Constant-colour endpoint tables per channel width (0: 5 bits, 1: 6 bits),
+// and the nearest-code table of the cluster fit: code[w][h] is the number of
+// codes c < max with E(c) + E(c+1) < h.
 struct Bc1Tables {
     uint8_t a4[2][256], b4[2][256], e4[2][256];
     uint8_t a3[2][256], b3[2][256], e3[2][256];
+    uint8_t code[2][512];
 };
 __constant__ Bc1Tables kTab;
+
+// Per-workgroup LDS: -2 x the prefix sums of the ordered texels, row 3 s + c
+// holding channel c of the sum over the first s texels, one column per lane;
+// and the nearest-code table with its expanded values.
+struct Bc1Lds {
+    int m2P[17 * 3][kBlock];
+    uint8_t code[2][512];
+    uint8_t val[2][512];
+};
 
 __host__ __device__ inline int e5(int c) { return (c << 3) | (c >> 2); }
 __host__ __device__ inline int e6(int c) { return (c << 2) | (c >> 4); }
@@ -38,31 +50,42 @@ __host__ __device__ inline int ew(int c, int wide) { return wide ? e6(c) : e5(c)
 
 __device__ inline int bitlen(int x) { return 32 - __clz(x); }
 
-// Least code c in [0, 2^w) minimising |E(c)*den - num|, den > 0 (lowest c on
-// ties).  E is increasing, so the minimiser is the last code with
-// E(c)*den <= num or the one after it; the float estimate lands within one
-// code of that one and two integer checks settle it.
-__device__ inline int quant_code(int num, int den, float inv, int wide)
+typedef short short2_t __attribute__((ext_vector_type(2)));
+
+// Nearest code to t = y / (2 det), det > 0 (least |E(c) det - y/2|, lowest c
+// on ties).  E is strictly increasing, so moving from c to c+1 helps exactly
+// when the midpoint (E(c) + E(c+1)) / 2 lies below t; the answer is the
+// number of such midpoints, a table lookup at h = ceil(y / det) clamped to
+// [0, 511] (every midpoint sum is an integer in [4, 506]).  The float
+// estimate of h is within one of the exact ceiling wherever |y / det| < 2^10
+// (reciprocal and product each within an ulp); two integer checks settle
+// it, and out-of-range values end clamped either way.
+__device__ __forceinline__ int quant_h(int y, int det, float inv)
 {
-    const int maxc = wide ? 63 : 31;
-    float f = (float)num * inv;                    // ~ num/den * maxc/255
-    int c = (int)floorf(f);
-    c = c < -1 ? -1 : (c > maxc ? maxc : c);
-    if (c >= 0 && __mul24(ew(c, wide), den) > num) c--;
-    if (c < maxc && __mul24(ew(c + 1, wide), den) <= num) c++;
-    if (c < 0) return 0;
-    if (c == maxc) return maxc;
-    int d0 = num - __mul24(ew(c, wide), den);
-    int d1 = __mul24(ew(c + 1, wide), den) - num;
-    return d0 <= d1 ? c : c + 1;
+    int h = (int)__builtin_ceilf((float)y * inv);
+    h = min(max(h, 0), 512);
+    const int hd = mul_i24(h, det);   // <= 512 * 20736
+    h += hd < y ? 1 : 0;
+    h -= hd - det >= y ? 1 : 0;
+    return min(max(h, 0), 511);
 }
 
 __device__ inline uint32_t pack565(int r, int g, int b) { return ((uint32_t)r << 11) | ((uint32_t)g << 5) | (uint32_t)b; }
 
+// Texels of the block for the index search: rg = R | G << 16, B, 64 |x|^2.
+struct Tex16 {
+    uint32_t rg[16];
+    int b[16], cx[16];
+};
+
 // Order the pair for the mode (4-colour: c0 > c1, 3-colour: c0 <= c1), then
-// give each texel its least-SSE palette entry (lowest index on ties).
-__device__ inline uint32_t canon_index(uint32_t &c0, uint32_t &c1, bool four, const int (&x)[16][3],
-                                       uint32_t &indices)
+// give each texel its least-SSE palette entry (lowest index on ties).  With
+// entry k held as (-128 pR, -128 pG), -128 pB and 64 |p|^2 + k, the key
+// 64 (|p|^2 - 2 x.p) + k is one 24-bit multiply-add and one 16-bit dot
+// product; 64 |x|^2 added to the least key is 64 SSE + k, and over 16 texels
+// the k terms stay below 64.  Indices enter a shift register from the top,
+// so texel 0 ends in bits 0-1.
+__device__ inline uint32_t canon_index(uint32_t &c0, uint32_t &c1, bool four, const Tex16 &T, uint32_t &indices)
 {
     if ((four && c0 < c1) || (!four && c0 > c1)) { uint32_t t = c0; c0 = c1; c1 = t; }
     int p[4][3];
@@ -82,33 +105,124 @@ __device__ inline uint32_t canon_index(uint32_t &c0, uint32_t &c1, bool four, co
             p[3][c] = 0;
         }
     }
-    uint32_t sse = 0, idx = 0;
+    uint32_t prg[4];
+    int pb[4], pk[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        prg[k] = ((uint32_t)(-128 * p[k][0]) & 0xFFFFu) | ((uint32_t)(-128 * p[k][1]) << 16);
+        pb[k] = -128 * p[k][2];
+        pk[k] = 64 * (mul_i24(p[k][0], p[k][0]) + mul_i24(p[k][1], p[k][1]) + mul_i24(p[k][2], p[k][2])) + k;
+    }
+    uint32_t acc = 0, idx = 0;
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-        uint32_t best = 0xFFFFFFFFu;
+        int kb = 0x7FFFFFFF;
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            int d0 = x[i][0] - p[k][0], d1 = x[i][1] - p[k][1], d2 = x[i][2] - p[k][2];
-            uint32_t d = (uint32_t)(d0 * d0 + d1 * d1 + d2 * d2);
-            uint32_t key = (d << 2) | (uint32_t)k;   // d < 2^18: exact order, index breaks ties
-            best = key < best ? key : best;
-        }
-        sse += best >> 2;
-        idx |= (best & 3u) << (2 * i);
+        for (int k = 0; k < 4; k++)
+            kb = min(kb, __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, T.rg[i]),
+                                                __builtin_bit_cast(short2_t, prg[k]), mul_i24(T.b[i], pb[k]) + pk[k],
+                                                false));
+        acc += (uint32_t)kb + (uint32_t)T.cx[i];
+        idx = __builtin_amdgcn_alignbit((uint32_t)kb, idx, 2);
     }
     indices = idx;
-    return sse;
+    return acc >> 6;
 }
 
-__device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, int *sP,
-                             uint32_t &w0, uint32_t &w1, uint32_t &sse_out)
+// Cluster fit over one split list in enumeration order (4-colour: s1 <= s2 <=
+// s3; 3-colour: s1 <= s2, s3 = 16).  The split bounds, weights and
+// determinant are wave-uniform; each lane forms its numerators from the
+// prefix sums, quantises, and scores the exact SSE of the split
+//   Q + sum_j p_j (n_j p_j - 2 X_j)
+// per channel.  With SA + SB = F tot, the numerators are
+//   2 num0 = -F (B + AB) (-2 SA) - 2 F AB F tot
+//   2 num1 =  F (A + AB) (-2 SA) + 2 F A F tot.
+// The best split (strictly less SSE, so the first on ties) is kept by its
+// packed bounds.
+template <bool FOUR>
+__device__ __forceinline__ void split_list(const Bc1Lds &L, int lane, const int (&tot)[3], const int (&m2tot)[3],
+                                           int Q, uint32_t &best, uint32_t &best_split)
 {
-    int x[16][3];
+    constexpr int F = FOUR ? 3 : 2;
+    for (int s1 = 0; s1 <= 16; s1++)
+        for (int s2 = s1; s2 <= 16; s2++)
+            for (int s3 = FOUR ? s2 : 16; s3 <= 16; s3++) {
+                const int n0 = s1, n1 = s2 - s1, n2 = s3 - s2, n3 = 16 - s3;
+                const int A = FOUR ? 9 * n0 + 4 * n1 + n2 : 4 * n0 + n1;
+                const int B = FOUR ? n1 + 4 * n2 + 9 * n3 : n1 + 4 * n2;
+                const int AB = FOUR ? 2 * (n1 + n2) : n1;
+                const int det = A * B - AB * AB;
+                if (det == 0) continue;
+                const float inv = __builtin_amdgcn_rcpf((float)det);
+                int sse = Q;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    const int wide = c == 1;
+                    const int a = L.m2P[s1 * 3 + c][lane], bq = L.m2P[s2 * 3 + c][lane];
+                    const int cq = FOUR ? L.m2P[s3 * 3 + c][lane] : m2tot[c];
+                    const int sam = FOUR ? a + bq + cq : a + bq;   // -2 SA
+                    const int y0 = mul_i24(sam, -F * (B + AB)) + mul_i24(tot[c], -2 * F * F * AB);
+                    const int y1 = mul_i24(sam, F * (A + AB)) + mul_i24(tot[c], 2 * F * F * A);
+                    const int e0 = L.val[wide][quant_h(y0, det, inv)];
+                    const int e1 = L.val[wide][quant_h(y1, det, inv)];
+                    if (FOUR) {
+                        // (2 e0 + e1 + 1) / 3 and (e0 + 2 e1 + 1) / 3 as (v * 43691) >> 17, exact for v < 2^17
+                        const int p1 = (int)((mul_u24((uint32_t)(2 * e0 + e1), 43691u) + 43691u) >> 17);
+                        const int p2 = (int)((mul_u24((uint32_t)(e0 + 2 * e1), 43691u) + 43691u) >> 17);
+                        sse += mul_i24(e0, mul_i24(n0, e0) + a);
+                        sse += mul_i24(p1, mul_i24(n1, p1) + (bq - a));
+                        sse += mul_i24(p2, mul_i24(n2, p2) + (cq - bq));
+                        sse += mul_i24(e1, mul_i24(n3, e1) + (m2tot[c] - cq));
+                    } else {
+                        const int p1 = (e0 + e1 + 1) >> 1;
+                        sse += mul_i24(e0, mul_i24(n0, e0) + a);
+                        sse += mul_i24(p1, mul_i24(n1, p1) + (bq - a));
+                        sse += mul_i24(e1, mul_i24(n2, e1) + (m2tot[c] - bq));
+                    }
+                }
+                if ((uint32_t)sse < best) {
+                    best = (uint32_t)sse;
+                    best_split = (uint32_t)s1 | ((uint32_t)s2 << 5) | ((uint32_t)s3 << 10) | (FOUR ? 1u << 15 : 0u);
+                }
+            }
+}
+
+// Endpoint codes of one split (the same arithmetic as split_list).
+__device__ void split_codes(const Bc1Lds &L, int lane, const int (&tot)[3], const int (&m2tot)[3], uint32_t split,
+                            int (&q0)[3], int (&q1)[3])
+{
+    const bool four = (split >> 15) & 1;
+    const int s1 = split & 31, s2 = (split >> 5) & 31, s3 = (split >> 10) & 31;
+    const int F = four ? 3 : 2;
+    const int n0 = s1, n1 = s2 - s1, n2 = s3 - s2, n3 = 16 - s3;
+    const int A = four ? 9 * n0 + 4 * n1 + n2 : 4 * n0 + n1;
+    const int B = four ? n1 + 4 * n2 + 9 * n3 : n1 + 4 * n2;
+    const int AB = four ? 2 * (n1 + n2) : n1;
+    const int det = A * B - AB * AB;
+    const float inv = __builtin_amdgcn_rcpf((float)det);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const int wide = c == 1;
+        const int a = L.m2P[s1 * 3 + c][lane], bq = L.m2P[s2 * 3 + c][lane];
+        const int cq = four ? L.m2P[s3 * 3 + c][lane] : m2tot[c];
+        const int sam = four ? a + bq + cq : a + bq;
+        const int y0 = sam * (-F * (B + AB)) + tot[c] * (-2 * F * F * AB);
+        const int y1 = sam * (F * (A + AB)) + tot[c] * (2 * F * F * A);
+        q0[c] = L.code[wide][quant_h(y0, det, inv)];
+        q1[c] = L.code[wide][quant_h(y1, det, inv)];
+    }
+}
+
+__device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, Bc1Lds &L, int lane, uint32_t &w0,
+                             uint32_t &w1, uint32_t &sse_out)
+{
+    Tex16 T;
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-        x[i][0] = t[i] & 255;
-        x[i][1] = (t[i] >> 8) & 255;
-        x[i][2] = (t[i] >> 16) & 255;
+        const uint32_t r = t[i] & 255u, g = (t[i] >> 8) & 255u, bb = (t[i] >> 16) & 255u;
+        T.rg[i] = r | (g << 16);
+        T.b[i] = (int)bb;
+        T.cx[i] = (int)(64u * (r * r + g * g + bb * bb));
     }
     bool constant = true;
 #pragma unroll
@@ -119,7 +233,7 @@ __device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, int
         int a4[3], b4[3], a3[3], b3[3], err4 = 0, err3 = 0;
 #pragma unroll
         for (int c = 0; c < 3; c++) {
-            int wide = c == 1, v = x[0][c];
+            int wide = c == 1, v = (int)((t[0] >> (8 * c)) & 255u);
             a4[c] = kTab.a4[wide][v]; b4[c] = kTab.b4[wide][v];
             a3[c] = kTab.a3[wide][v]; b3[c] = kTab.b3[wide][v];
             int e4 = kTab.e4[wide][v], e3 = kTab.e3[wide][v];
@@ -129,7 +243,7 @@ __device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, int
         bool four = err4 <= err3;
         c0 = four ? pack565(a4[0], a4[1], a4[2]) : pack565(a3[0], a3[1], a3[2]);
         c1 = four ? pack565(b4[0], b4[1], b4[2]) : pack565(b3[0], b3[1], b3[2]);
-        sse = canon_index(c0, c1, four, x, idx);
+        sse = canon_index(c0, c1, four, T, idx);
         w0 = c0 | (c1 << 16);
         w1 = idx;
         sse_out = sse;
@@ -138,25 +252,26 @@ __device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, int
 
     // ---- principal axis (integer power iteration, int32 exact)
     int S[3] = {0, 0, 0}, XX[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-    int Q = 0;
 #pragma unroll
-    for (int i = 0; i < 16; i++)
+    for (int i = 0; i < 16; i++) {
+        const int x[3] = {(int)(t[i] & 255u), (int)((t[i] >> 8) & 255u), (int)((t[i] >> 16) & 255u)};
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            S[a] += x[i][a];
+            S[a] += x[a];
 #pragma unroll
-            for (int b = a; b < 3; b++) XX[a][b] += x[i][a] * x[i][b];
-            Q += x[i][a] * x[i][a];
+            for (int b = a; b < 3; b++) XX[a][b] += x[a] * x[b];
         }
+    }
+    const int Q = XX[0][0] + XX[1][1] + XX[2][2];
     int C[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++)
 #pragma unroll
-        for (int b = a; b < 3; b++) { C[a][b] = 16 * XX[a][b] - S[a] * S[b]; C[b][a] = C[a][b]; }
+        for (int b = a; b < 3; b++) { C[a][b] = 16 * XX[a][b] - __mul24(S[a], S[b]); C[b][a] = C[a][b]; }
     // row of the largest diagonal entry (lowest index on ties), by selects
     const int j = (C[1][1] > C[0][0]) ? ((C[2][2] > C[1][1]) ? 2 : 1) : ((C[2][2] > C[0][0]) ? 2 : 0);
     const int dmax = j == 0 ? C[0][0] : (j == 1 ? C[1][1] : C[2][2]);
-    int tsh = max(0, bitlen(dmax) - 14);
+    const int tsh = max(0, bitlen(dmax) - 14);
     int Cs[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++)
@@ -165,11 +280,20 @@ __device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, int
     int v[3];
 #pragma unroll
     for (int b = 0; b < 3; b++) v[b] = j == 0 ? Cs[0][b] : (j == 1 ? Cs[1][b] : Cs[2][b]);
+    // |Cs| <= 2^14 and |v| <= 2^15: 16-bit dot products, exact 32-bit sums
+    short2_t c01[3], c2[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        c01[a] = short2_t{(short)Cs[a][0], (short)Cs[a][1]};
+        c2[a] = short2_t{(short)Cs[a][2], (short)0};
+    }
 #pragma unroll
     for (int it = 0; it < 8; it++) {
+        const short2_t v01 = {(short)v[0], (short)v[1]}, v2 = {(short)v[2], (short)0};
         int u[3];
 #pragma unroll
-        for (int a = 0; a < 3; a++) u[a] = Cs[a][0] * v[0] + Cs[a][1] * v[1] + Cs[a][2] * v[2];
+        for (int a = 0; a < 3; a++)
+            u[a] = __builtin_amdgcn_sdot2(c01[a], v01, __builtin_amdgcn_sdot2(c2[a], v2, 0, false), false);
         int m = max(abs(u[0]), max(abs(u[1]), abs(u[2])));
         int s = max(0, bitlen(m) - 15);
 #pragma unroll
@@ -177,94 +301,44 @@ __device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, int
     }
     if (v[0] == 0 && v[1] == 0 && v[2] == 0) v[0] = v[1] = v[2] = 1;
 
-    // ---- order texels by (projection, index); prefix sums into LDS
+    // ---- order texels by (projection, index): rank, scatter, prefix sums
+    const short2_t v01 = {(short)v[0], (short)v[1]};
     int proj[16];
 #pragma unroll
-    for (int i = 0; i < 16; i++) proj[i] = v[0] * x[i][0] + v[1] * x[i][1] + v[2] * x[i][2];
-    int rank[16];
+    for (int i = 0; i < 16; i++)
+        proj[i] = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, T.rg[i]), v01, __mul24(T.b[i], v[2]), false);
 #pragma unroll
     for (int i = 0; i < 16; i++) {
         int r = 0;
 #pragma unroll
-        for (int k = 0; k < 16; k++) r += (proj[k] < proj[i]) || (proj[k] == proj[i] && k < i);
-        rank[i] = r;
+        for (int k = 0; k < 16; k++)
+            if (k != i) r += (k < i ? proj[k] <= proj[i] : proj[k] < proj[i]) ? 1 : 0;
+        L.m2P[3 * r][lane] = (int)(t[i] & 0xFFFFFFu);   // texel of rank r, parked in row 3 r
     }
-    // xs[k] = x of the texel with rank k; P[s] = sum of xs[0..s)
+    // row 3 k still holds the texel of rank k when the prefix rows of k are written
     int run[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k <= 16; k++) {
+        const uint32_t x = k < 16 ? (uint32_t)L.m2P[3 * k][lane] : 0u;
 #pragma unroll
-        for (int c = 0; c < 3; c++) sP[(k * 3 + c) * kBlock] = run[c];
-        if (k < 16) {
-#pragma unroll
-            for (int i = 0; i < 16; i++)
-                if (rank[i] == k) { run[0] += x[i][0]; run[1] += x[i][1]; run[2] += x[i][2]; }
-        }
+        for (int c = 0; c < 3; c++) L.m2P[3 * k + c][lane] = -2 * run[c];
+        run[0] += (int)(x & 255u);
+        run[1] += (int)((x >> 8) & 255u);
+        run[2] += (int)((x >> 16) & 255u);
     }
     const int tot[3] = {run[0], run[1], run[2]};
+    const int m2tot[3] = {-2 * run[0], -2 * run[1], -2 * run[2]};
 
     // ---- cluster fit over every split (4-colour list, then 3-colour list)
-    uint32_t best = 0xFFFFFFFFu;
-    int bq[6] = {0, 0, 0, 0, 0, 0};
-    bool bfour = true;
-    for (int list = 0; list < 2; list++) {
-        const bool four = list == 0;
-        const int F = four ? 3 : 2;
-        for (int s1 = 0; s1 <= 16; s1++) {
-            for (int s2 = s1; s2 <= 16; s2++) {
-                const int s3lo = four ? s2 : 16;
-                for (int s3 = s3lo; s3 <= 16; s3++) {
-                    int n0 = s1, n1 = s2 - s1, n2 = s3 - s2, n3 = 16 - s3;
-                    int A, B, AB;
-                    if (four) { A = 9 * n0 + 4 * n1 + n2; B = n1 + 4 * n2 + 9 * n3; AB = 2 * (n1 + n2); }
-                    else { A = 4 * n0 + n1; B = n1 + 4 * n2; AB = n1; }
-                    int det = A * B - AB * AB;
-                    if (det == 0) continue;
-                    float inv5 = 31.0f / (255.0f * (float)det), inv6 = 63.0f / (255.0f * (float)det);
-                    int q0[3], q1[3];
-                    int sse = Q;
-#pragma unroll
-                    for (int c = 0; c < 3; c++) {
-                        int P1 = sP[(s1 * 3 + c) * kBlock], P2 = sP[(s2 * 3 + c) * kBlock];
-                        int P3 = sP[(s3 * 3 + c) * kBlock];
-                        int X0 = P1, X1 = P2 - P1, X2 = P3 - P2, X3 = tot[c] - P3;
-                        int SA, SB;
-                        if (four) { SA = 3 * X0 + 2 * X1 + X2; SB = X1 + 2 * X2 + 3 * X3; }
-                        else { SA = 2 * X0 + X1; SB = X1 + 2 * X2; }
-                        int num0 = F * (__mul24(B, SA) - __mul24(AB, SB));
-                        int num1 = F * (__mul24(A, SB) - __mul24(AB, SA));
-                        const int wide = c == 1;
-                        const float inv = wide ? inv6 : inv5;
-                        q0[c] = quant_code(num0, det, inv, wide);
-                        q1[c] = quant_code(num1, det, inv, wide);
-                        int e0 = ew(q0[c], wide), e1 = ew(q1[c], wide);
-                        if (four) {
-                            int p1 = (uint32_t)(2 * e0 + e1 + 1) / 3u, p2 = (uint32_t)(e0 + 2 * e1 + 1) / 3u;
-                            sse += __mul24(n0, e0 * e0) - 2 * __mul24(e0, X0);
-                            sse += __mul24(n1, p1 * p1) - 2 * __mul24(p1, X1);
-                            sse += __mul24(n2, p2 * p2) - 2 * __mul24(p2, X2);
-                            sse += __mul24(n3, e1 * e1) - 2 * __mul24(e1, X3);
-                        } else {
-                            int p1 = (e0 + e1 + 1) >> 1;
-                            sse += __mul24(n0, e0 * e0) - 2 * __mul24(e0, X0);
-                            sse += __mul24(n1, p1 * p1) - 2 * __mul24(p1, X1);
-                            sse += __mul24(n2, e1 * e1) - 2 * __mul24(e1, X2);
-                        }
-                    }
-                    if ((uint32_t)sse < best) {
-                        best = (uint32_t)sse;
-                        bq[0] = q0[0]; bq[1] = q0[1]; bq[2] = q0[2];
-                        bq[3] = q1[0]; bq[4] = q1[1]; bq[5] = q1[2];
-                        bfour = four;
-                    }
-                }
-            }
-        }
-    }
+    uint32_t best = 0xFFFFFFFFu, best_split = 1u << 15;
+    split_list<true>(L, lane, tot, m2tot, Q, best, best_split);
+    split_list<false>(L, lane, tot, m2tot, Q, best, best_split);
+    int bq0[3], bq1[3];
+    split_codes(L, lane, tot, m2tot, best_split, bq0, bq1);
 
-    c0 = pack565(bq[0], bq[1], bq[2]);
-    c1 = pack565(bq[3], bq[4], bq[5]);
-    sse = canon_index(c0, c1, bfour, x, idx);
+    c0 = pack565(bq0[0], bq0[1], bq0[2]);
+    c1 = pack565(bq1[0], bq1[1], bq1[2]);
+    sse = canon_index(c0, c1, (best_split >> 15) & 1, T, idx);
 
     // ---- refinement: best of the 12 one-step moves, taken if strictly better
     for (uint32_t step = 0; step < refine_steps; step++) {
@@ -280,7 +354,7 @@ __device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, int
             int nv = cand[ch] + dlt;
             cand[ch] = nv < 0 ? 0 : (nv > maxc ? maxc : nv);
             uint32_t a = pack565(cand[0], cand[1], cand[2]), b = pack565(cand[3], cand[4], cand[5]), ii;
-            uint32_t s = canon_index(a, b, four, x, ii);
+            uint32_t s = canon_index(a, b, four, T, ii);
             if (s < nb_sse) { nb_sse = s; nb0 = a; nb1 = b; nbi = ii; }
         }
         if (nb_sse < sse) { sse = nb_sse; c0 = nb0; c1 = nb1; idx = nbi; }
@@ -293,7 +367,13 @@ __device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, int
 
 __global__ __launch_bounds__(kBlock) void k_bc1_encode(EncodeArgs a)
 {
-    __shared__ int sP[17 * 3 * kBlock];
+    __shared__ Bc1Lds L;
+    for (int e = threadIdx.x; e < 2 * 512; e += kBlock) {
+        const int wide = e >> 9, c = kTab.code[wide][e & 511];
+        L.code[wide][e & 511] = (uint8_t)c;
+        L.val[wide][e & 511] = (uint8_t)ew(c, wide);
+    }
+    __syncthreads();
     const uint64_t g0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
     const uint64_t total = (uint64_t)a.nbands * a.nblk;
     const bool live = g0 < total;
@@ -308,7 +388,7 @@ __global__ __launch_bounds__(kBlock) void k_bc1_encode(EncodeArgs a)
         t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
     }
     uint32_t w0, w1, sse;
-    encode_block(t, a.refine_steps, sP + threadIdx.x, w0, w1, sse);
+    encode_block(t, a.refine_steps, L, threadIdx.x, w0, w1, sse);
     if (live) {
         uint2 *dst = reinterpret_cast<uint2 *>(a.out + a.out_offset[band] + b * 8);
         *dst = make_uint2(w0, w1);
@@ -349,6 +429,11 @@ void build_tables(Bc1Tables &T)
                 B[v] = (uint8_t)(best % nc);
                 E[v] = (uint8_t)be;
             }
+        }
+        for (int h = 0; h < 512; h++) {
+            int n = 0;
+            for (int c = 0; c + 1 < nc; c++) n += ew(c, wide) + ew(c + 1, wide) < h;
+            T.code[wide][h] = (uint8_t)n;
         }
     }
 }

@@ -13,6 +13,15 @@ namespace gsbc {
 void trace_begin(const char *kernel, hipStream_t st);
 void trace_end(hipStream_t st);
 
+// 24-bit multiplies (v_mul_i32_i24 / v_mul_u32_u24, full rate) whatever
+// operand ranges the compiler can prove; the result is the low 32 bits of
+// the product of the sign- (zero-) extended low 24 bits, so it is exact for
+// operands in [-2^23, 2^23) (resp. [0, 2^24)) whose product fits 32 bits.
+extern "C" __device__ int gsbc_llvm_mul_i24(int, int) __asm("llvm.amdgcn.mul.i24");
+extern "C" __device__ unsigned gsbc_llvm_mul_u24(unsigned, unsigned) __asm("llvm.amdgcn.mul.u24");
+__device__ __forceinline__ int mul_i24(int a, int b) { return gsbc_llvm_mul_i24(a, b); }
+__device__ __forceinline__ uint32_t mul_u24(uint32_t a, uint32_t b) { return gsbc_llvm_mul_u24(a, b); }
+
 // Add v (one value per lane; lanes with live == false add nothing) into
 // sums[band].  Lanes of a wave usually share a band (consecutive blocks):
 // then the wave sums in registers and one lane issues the atomic; otherwise
