@@ -20,6 +20,7 @@ step time, in Mblocks/s.  Also reported:
   cpu_baseline        the CPU oracle on a bounded sample of the same step.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -49,6 +50,21 @@ ALGO_OPS = {
     "bc7_search_1subset": (3_072 + 1_024 + 2_048) * OPS_PER_EVAL,  # modes 4, 5, 6
 }
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def traffic_bytes(name):
+    """HBM bytes per launch of kernel `name` from the committed rocprofv3
+    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or
+    None when there is none or the kernel's source changed since."""
+    if not os.path.exists(TRAFFIC):
+        return None
+    ent = json.load(open(TRAFFIC)).get(name)
+    if not ent:
+        return None
+    src = os.path.join(ROOT, ent["source"])
+    if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != ent["source_sha1"]:
+        return None
+    return ent["bytes"]
 
 
 def parse():
@@ -148,9 +164,7 @@ def main():
         dom_s = per_step[dom] / launches * 1e-3                     # average launch, s
         units = 16 * nblk                                           # blocks per launch
         work = ALGO_OPS.get(dom)
-        traffic = None
-        if os.path.exists(TRAFFIC):
-            traffic = json.load(open(TRAFFIC)).get(dom)
+        traffic = traffic_bytes(dom)
         roof = {"kernel": dom, "bound": "alu", "achieved": work * units / dom_s / 1e12 if work else None,
                 "peak": VALU_PEAK / 1e12, "unit": "Tops/s",
                 "frac": work * units / dom_s / VALU_PEAK if work else None, "traffic": traffic,
@@ -202,9 +216,7 @@ def main():
                 tf.append(e0.elapsed_time(e1) * 1e-3)
             fill_gbps = out3.numel() * 4 / float(np.mean(tf)) / 1e9
             de_bytes = c3["dirs"] * c3["n"] * 12 + dd2.payload_bytes + c3["dirs"] * 12
-            tr_de = None
-            if os.path.exists(TRAFFIC):
-                tr_de = json.load(open(TRAFFIC)).get("k_decode_eval")
+            tr_de = traffic_bytes("k_decode_eval")
             roof_de = {"kernel": "k_decode_eval", "bound": "hbm", "achieved": de_bytes / de_s / 1e9,
                        "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": de_bytes / de_s / HBM_PEAK,
                        "traffic": tr_de, "launch_ms": de_s * 1e3,
