@@ -21,7 +21,8 @@
  *     by the caller.  Every size is an element count unless it says bytes.
  *   - Calls enqueue work on the context's stream.  gsbc_reorder and
  *     gsbc_encode also copy a few header values back and wait for the stream
- *     before they return; the other calls return without waiting.  Device
+ *     before they return; the other calls return without waiting (except
+ *     gsbc_encode_batch when asked for band SSEs).  Device
  *     faults surface as GSBC_E_DEVICE from the next call or from gsbc_sync.
  *   - Every call returns a gsbc_status; on error the context keeps a message
  *     (gsbc_last_error).  Argument errors are detected before any work is
@@ -54,7 +55,7 @@ enum {
     GSBC_E_BUFFER = -6       /* a caller buffer is too small (see gsbc_query_sizes) */
 };
 
-enum { GSBC_FMT_AUTO = 0, GSBC_FMT_BC1 = 1, GSBC_FMT_BC7 = 7 };
+enum { GSBC_FMT_AUTO = 0, GSBC_FMT_BC1 = 1, GSBC_FMT_BANDS = 2, GSBC_FMT_BC7 = 7 };
 
 typedef struct gsbc_ctx gsbc_ctx;
 
@@ -127,7 +128,10 @@ GSBC_API gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *
 /* Encode every band (Sec. III-A BTC; Sec. IV-B per-bitstream formats).
  *   textures device, layout of gsbc_reorder; desc host, in: n_prims, n_pad,
  *            blocks_per_band, vmin, vmax; out: format, offset, payload_bytes
- *   format   GSBC_FMT_BC1 or GSBC_FMT_BC7 for all bands, or GSBC_FMT_AUTO:
+ *   format   GSBC_FMT_BC1 or GSBC_FMT_BC7 for all bands; GSBC_FMT_BANDS for
+ *            the per-band formats the caller put in desc->format[k] (each
+ *            BC1 or BC7, e.g. band 0 BC7 and the rest BC1 as in Sec. V); or
+ *            GSBC_FMT_AUTO:
  *            every band is coded in both formats, then band 0 is BC7 and of
  *            bands 1..15 the k = 4*rate - 17 with the largest
  *            (SSE_BC1 - SSE_BC7) * delta_k^2 are BC7 (lower band first on
@@ -145,6 +149,59 @@ GSBC_API gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *
 GSBC_API gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc *desc,
                         int format, double rate, const gsbc_params *params, uint8_t *blocks,
                         uint64_t blocks_capacity, int64_t *band_sse);
+
+/* Work distribution of gsbc_encode_batch.  Every setting gives the same
+ * bits: each block is coded on its own and every decision is a fixed
+ * integer computation (results do not depend on launch shapes).
+ *   item_rounds  256-block rounds per work item, 1..64
+ *   wgs_per_cu   0: one workgroup per item (a plain grid); 1..16: that many
+ *                persistent workgroups per compute unit pop items from a
+ *                device counter until none are left
+ *   bc1_lanes    BC1 workgroup size: 64, 128 or 256
+ *   bc7_split    BC7 candidate groups per search kernel: 0 = three kernels
+ *                (2-subset, 3-subset, 1-subset modes), 1 = two (the 3- and
+ *                1-subset modes together), 2 = one kernel
+ *   concurrent   1: the BC1 blocks run on a second stream beside the BC7
+ *                blocks; 0: after them on the context's stream */
+typedef struct {
+    uint32_t item_rounds;
+    uint32_t wgs_per_cu;
+    uint32_t bc1_lanes;
+    uint32_t bc7_split;
+    uint32_t concurrent;
+} gsbc_batch_tuning;
+
+/* Defaults: item_rounds 1, wgs_per_cu 0, bc1_lanes 128, bc7_split 0,
+ * concurrent 0 (the launch shapes of gsbc_encode). */
+GSBC_API void gsbc_default_batch_tuning(gsbc_batch_tuning *t);
+
+/* Encode many scenes in one launch sequence.  Blocks are independent and
+ * fixed-size (Sec. I; Sec. III-A), so the blocks of every band of every
+ * scene in one format form a single index space that one kernel per step
+ * covers, however uneven the scenes.  Scene i is coded exactly as
+ * gsbc_encode(ctx, textures[i], &descs[i], GSBC_FMT_BANDS, ...) would code
+ * it, bit for bit.  The launch sequence is captured once into a HIP graph
+ * (on the context's stream, which must not be the legacy null stream) and
+ * replayed while later calls pass the same scene count, pointers, block
+ * counts, formats, params and tuning; otherwise the plan is rebuilt, which
+ * allocates device memory the context holds until the next rebuild or
+ * gsbc_destroy.
+ *   n_scenes         1..4096
+ *   textures         host array of n_scenes device pointers (gsbc_reorder layout)
+ *   descs            host array of n_scenes; in: n_prims, n_pad,
+ *                    blocks_per_band, vmin, vmax and format[16] (each BC1
+ *                    or BC7); out: offset, payload_bytes
+ *   blocks           host array of n_scenes device pointers, 16-byte aligned
+ *   blocks_capacity  host uint64[n_scenes]: bytes behind each blocks[i]
+ *                    (GSBC_E_BUFFER if below the scene's payload)
+ *   params, tuning   host, or NULL for the defaults
+ *   band_sse         host int64[n_scenes][16] or NULL, out: each band's SSE
+ *                    in its format; when given the call waits for the
+ *                    stream, otherwise it returns once the graph is queued */
+GSBC_API gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *const *textures,
+                                       gsbc_stream_desc *descs, uint8_t *const *blocks,
+                                       const uint64_t *blocks_capacity, const gsbc_params *params,
+                                       const gsbc_batch_tuning *tuning, int64_t *band_sse);
 
 /* Decode every band back to textures (layout of gsbc_reorder) -- BC1 and BC7
  * decoders of the format definitions; BC1 interpolants rounded to nearest.

@@ -26,6 +26,15 @@ struct gsbc_ctx {
     void *small = nullptr;          // fixed device block: range, selection, SSE sums, offsets
     void *pinned = nullptr;         // host staging for read-backs
     char err[512] = {0};
+    // gsbc_encode_batch: the last plan (device tables + captured graph)
+    hipStream_t side = nullptr;      // second stream for BC1 beside BC7
+    hipEvent_t fork = nullptr, join = nullptr;
+    std::vector<uint64_t> plan_sig;
+    void *plan_mem = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    unsigned long long *plan_sse = nullptr;
+    bool capturing = false;
     // kernel timing (gsbc_profile_enable)
     bool profiling = false;
     struct Rec { const char *name; size_t ev; };
@@ -176,6 +185,48 @@ BandArgs band_args(const gsbc_stream_desc *d)
 
 char *small_ptr(gsbc_ctx *ctx, size_t off) { return static_cast<char *>(ctx->small) + off; }
 
+// Block runs of one format, laid out in one global index space.
+struct Runs {
+    std::vector<BlockRun> v;
+    uint64_t total = 0;
+    void add(const uint8_t *src, uint8_t *dst, unsigned long long *sse, uint64_t nblk)
+    {
+        v.push_back({src, dst, sse, total, nblk});
+        total += run_span(nblk);
+    }
+};
+
+// Stream layout of the band formats: band k at offset[k], 16-byte aligned.
+uint64_t layout(const uint32_t fmt[16], uint64_t nblk, uint64_t off[16])
+{
+    uint64_t pos = 0;
+    for (int k = 0; k < 16; k++) {
+        off[k] = pos;
+        pos = align16(pos + nblk * (fmt[k] == GSBC_FMT_BC1 ? 8 : 16));
+    }
+    return pos;
+}
+
+// Default work split of the single-scene calls: one workgroup per 256-block
+// round, BC1 on 128-lane workgroups, three BC7 search kernels.
+constexpr WorkSplit kPlainSplit = {1, 0, nullptr};
+constexpr uint32_t kPlainBc1Lanes = 128;
+constexpr uint32_t kPlainBc7Split = 0;
+constexpr size_t kRunTableBytes = 16 * sizeof(BlockRun);   // one scene, one format
+constexpr size_t kRunStageOff = 2048;                        // in ctx->pinned
+
+void drop_plan(gsbc_ctx *ctx)
+{
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+    if (ctx->plan_mem) (void)hipFree(ctx->plan_mem);
+    ctx->graph_exec = nullptr;
+    ctx->graph = nullptr;
+    ctx->plan_mem = nullptr;
+    ctx->plan_sse = nullptr;
+    ctx->plan_sig.clear();
+}
+
 }  // namespace
 
 namespace gsbc {
@@ -183,7 +234,7 @@ namespace gsbc {
 void trace_begin(const char *kernel, hipStream_t st)
 {
     gsbc_ctx *c = t_active;
-    if (!c || !c->profiling) return;
+    if (!c || !c->profiling || c->capturing) return;
     size_t k = c->recs.size();
     while (c->events.size() < 2 * (k + 1)) {
         hipEvent_t e;
@@ -197,7 +248,7 @@ void trace_begin(const char *kernel, hipStream_t st)
 void trace_end(hipStream_t st)
 {
     gsbc_ctx *c = t_active;
-    if (!c || !c->profiling || c->recs.empty()) return;
+    if (!c || !c->profiling || c->capturing || c->recs.empty()) return;
     (void)hipEventRecord(c->events[c->recs.back().ev + 1], st);
 }
 
@@ -253,6 +304,11 @@ gsbc_status gsbc_destroy(gsbc_ctx *ctx)
     if (hipSetDevice(ctx->device) != hipSuccess) s = GSBC_E_DEVICE;
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) s = GSBC_E_DEVICE;
     for (hipEvent_t e : ctx->events) (void)hipEventDestroy(e);
+    drop_plan(ctx);
+    if (ctx->side) (void)hipStreamSynchronize(ctx->side);
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->join) (void)hipEventDestroy(ctx->join);
+    if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->arena) (void)hipFree(ctx->arena);
     if (ctx->small) (void)hipFree(ctx->small);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
@@ -320,100 +376,292 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
     if ((reinterpret_cast<uintptr_t>(textures) & 15) || (reinterpret_cast<uintptr_t>(blocks) & 15))
         return fail(ctx, GSBC_E_ARG, "textures and blocks must be 16-byte aligned");
     if ((s = check_desc(ctx, desc))) return s;
-    if (format != GSBC_FMT_AUTO && format != GSBC_FMT_BC1 && format != GSBC_FMT_BC7)
-        return fail(ctx, GSBC_E_ARG, "format %d is not AUTO(0), BC1(1) or BC7(7)", format);
+    if (format != GSBC_FMT_AUTO && format != GSBC_FMT_BC1 && format != GSBC_FMT_BC7 && format != GSBC_FMT_BANDS)
+        return fail(ctx, GSBC_E_ARG, "format %d is not AUTO(0), BC1(1), BANDS(2) or BC7(7)", format);
+    if (format == GSBC_FMT_BANDS)
+        for (int k = 0; k < 16; k++)
+            if (desc->format[k] != GSBC_FMT_BC1 && desc->format[k] != GSBC_FMT_BC7)
+                return fail(ctx, GSBC_E_ARG, "desc.format[%d] = %u is not BC1 or BC7", k, desc->format[k]);
     gsbc_params p = resolve(params);
     if ((s = check_params(ctx, p))) return s;
     const uint64_t nblk = desc->blocks_per_band;
     unsigned long long *sse1 = reinterpret_cast<unsigned long long *>(small_ptr(ctx, kSse1Off));
     unsigned long long *sse7 = reinterpret_cast<unsigned long long *>(small_ptr(ctx, kSse7Off));
-
-    EncodeArgs a;
-    memset(&a, 0, sizeof a);
-    a.textures = textures;
-    a.nblk = nblk;
-    a.refine_steps = p.refine_steps;
-    a.mode_mask = p.bc7_mode_mask;
+    const uint64_t tex_band = nblk * 64;
 
     uint64_t host_off[16];
     uint32_t host_fmt[16];
     uint64_t payload = 0;
+    uint32_t k_auto = 0;
+    bool have1 = false, have7 = false;
+    Runs r1, r7;
+    uint8_t *buf1 = nullptr, *buf7 = nullptr;
+    uint64_t off1[16], off7[16];
+    size_t front = 0;
     if (format != GSBC_FMT_AUTO) {
-        for (int k = 0; k < 16; k++) {
-            host_off[k] = payload;
-            host_fmt[k] = (uint32_t)format;
-            payload = align16(payload + nblk * (format == GSBC_FMT_BC1 ? 8 : 16));
-        }
+        for (int k = 0; k < 16; k++) host_fmt[k] = format == GSBC_FMT_BANDS ? desc->format[k] : (uint32_t)format;
+        payload = layout(host_fmt, nblk, host_off);
         if (blocks_capacity < payload)
             return fail(ctx, GSBC_E_BUFFER, "blocks_capacity %llu < payload %llu bytes", (unsigned long long)blocks_capacity,
                         (unsigned long long)payload);
-        if ((s = ensure_arena(ctx, bc7_scratch_bytes(16 * nblk)))) return s;
-        a.keys = static_cast<uint32_t *>(ctx->arena);
-        HIP_TRY(ctx, launch_fill_u64(sse1, 32, 0, ctx->stream), "clear");
-        a.band0 = 0;
-        a.nbands = 16;
-        a.out = blocks;
-        memcpy(a.out_offset, host_off, sizeof host_off);
-        a.band_sse = format == GSBC_FMT_BC1 ? sse1 : sse7;
-        HIP_TRY(ctx, format == GSBC_FMT_BC1 ? launch_bc1_encode(a, ctx->stream) : launch_bc7_encode(a, ctx->stream), "encode launch");
+        for (int k = 0; k < 16; k++) {
+            if (host_fmt[k] == GSBC_FMT_BC7) r7.add(textures + k * tex_band, blocks + host_off[k], sse7 + k, nblk);
+            else r1.add(textures + k * tex_band, blocks + host_off[k], sse1 + k, nblk);
+        }
     } else {
         double kd = 4.0 * rate - 17.0;
         if (!(kd >= 0.0 && kd <= 15.0) || kd != floor(kd))
             return fail(ctx, GSBC_E_INFEASIBLE, "rate %.17g bits/texel needs 4*rate-17 BC7 bands, not an integer in 0..15", rate);
-        const uint32_t k = (uint32_t)kd;
-        payload = (uint64_t)(k + 1) * 16 * nblk + (uint64_t)(15 - k) * align16(8 * nblk);
+        k_auto = (uint32_t)kd;
+        payload = (uint64_t)(k_auto + 1) * 16 * nblk + (uint64_t)(15 - k_auto) * align16(8 * nblk);
         if (blocks_capacity < payload)
             return fail(ctx, GSBC_E_BUFFER, "blocks_capacity %llu < payload %llu bytes", (unsigned long long)blocks_capacity,
                         (unsigned long long)payload);
-        const uint64_t s1 = align16(8 * nblk), s7 = 16 * nblk;
-        if ((s = ensure_arena(ctx, 16 * s1 + 16 * s7 + bc7_scratch_bytes(16 * nblk)))) return s;
-        uint8_t *buf1 = static_cast<uint8_t *>(ctx->arena), *buf7 = buf1 + 16 * s1;
-        a.keys = reinterpret_cast<uint32_t *>(buf7 + 16 * s7);
-        uint64_t off1[16], off7[16];
-        for (int q = 0; q < 16; q++) { off1[q] = q * s1; off7[q] = q * s7; }
+        front = 16 * align16(8 * nblk) + 16 * 16 * nblk;   // both candidate payloads
+    }
+    // arena: [candidate payloads (AUTO)] [BC7 runs] [BC1 runs] [BC7 key scratch]
+    const uint64_t total7 = format == GSBC_FMT_AUTO ? 16 * run_span(nblk) : r7.total;
+    if ((s = ensure_arena(ctx, front + 2 * kRunTableBytes + bc7_scratch_bytes(total7)))) return s;
+    uint8_t *arena = static_cast<uint8_t *>(ctx->arena);
+    if (format == GSBC_FMT_AUTO) {
+        buf1 = arena;
+        buf7 = buf1 + 16 * align16(8 * nblk);
+        for (int q = 0; q < 16; q++) {
+            off1[q] = q * align16(8 * nblk);
+            off7[q] = q * 16 * nblk;
+            r7.add(textures + q * tex_band, buf7 + off7[q], sse7 + q, nblk);
+            r1.add(textures + q * tex_band, buf1 + off1[q], sse1 + q, nblk);   // band 0 too: its BC1 SSE is reported
+        }
+    }
+    BlockRun *druns7 = reinterpret_cast<BlockRun *>(arena + front);
+    BlockRun *druns1 = druns7 + 16;
+    have1 = !r1.v.empty();
+    have7 = !r7.v.empty();
+    char *stage = static_cast<char *>(ctx->pinned) + kRunStageOff;
+    memcpy(stage, r7.v.data(), r7.v.size() * sizeof(BlockRun));
+    memcpy(stage + kRunTableBytes, r1.v.data(), r1.v.size() * sizeof(BlockRun));
+    HIP_TRY(ctx, hipMemcpyAsync(druns7, stage, 2 * kRunTableBytes, hipMemcpyHostToDevice, ctx->stream), "run tables");
+    HIP_TRY(ctx, launch_fill_u64(sse1, 32, 0, ctx->stream), "clear");
+    EncodeArgs a;
+    memset(&a, 0, sizeof a);
+    a.refine_steps = p.refine_steps;
+    a.mode_mask = p.bc7_mode_mask;
+    a.keys = reinterpret_cast<uint32_t *>(arena + front + 2 * kRunTableBytes);
+    const WorkSplit w3[3] = {kPlainSplit, kPlainSplit, kPlainSplit};
+    if (have7) {
+        a.run = druns7;
+        a.nrun = (uint32_t)r7.v.size();
+        a.total = r7.total;
+        HIP_TRY(ctx, launch_bc7_encode(a, w3, kPlainBc7Split, ctx->stream), "bc7 launch");
+    }
+    if (have1) {
+        a.run = druns1;
+        a.nrun = (uint32_t)r1.v.size();
+        a.total = r1.total;
+        HIP_TRY(ctx, launch_bc1_encode(a, kPlainSplit, kPlainBc1Lanes, ctx->stream), "bc1 launch");
+    }
+    if (format == GSBC_FMT_AUTO) {
         uint64_t *doff1 = reinterpret_cast<uint64_t *>(small_ptr(ctx, kOff1Off));
         uint64_t *doff7 = reinterpret_cast<uint64_t *>(small_ptr(ctx, kOff7Off));
-        uint64_t *stage = static_cast<uint64_t *>(ctx->pinned);
-        memcpy(stage, off1, sizeof off1);
-        memcpy(stage + 16, off7, sizeof off7);
-        HIP_TRY(ctx, hipMemcpyAsync(doff1, stage, 2 * sizeof off1, hipMemcpyHostToDevice, ctx->stream), "offsets");
-        HIP_TRY(ctx, launch_fill_u64(sse1, 32, 0, ctx->stream), "clear");
-        a.out = buf7;
-        memcpy(a.out_offset, off7, sizeof off7);
-        a.band0 = 0;
-        a.nbands = 16;
-        a.band_sse = sse7;
-        HIP_TRY(ctx, launch_bc7_encode(a, ctx->stream), "bc7 launch");
-        a.out = buf1;
-        memcpy(a.out_offset, off1, sizeof off1);
-        a.band0 = 0;            // band 0 is always BC7; its BC1 SSE is reported too
-        a.nbands = 16;
-        a.band_sse = sse1;
-        HIP_TRY(ctx, launch_bc1_encode(a, ctx->stream), "bc1 launch");
+        uint64_t *ostage = reinterpret_cast<uint64_t *>(static_cast<char *>(ctx->pinned) + kRunStageOff + 2 * kRunTableBytes);
+        memcpy(ostage, off1, sizeof off1);
+        memcpy(ostage + 16, off7, sizeof off7);
+        HIP_TRY(ctx, hipMemcpyAsync(doff1, ostage, 2 * sizeof off1, hipMemcpyHostToDevice, ctx->stream), "offsets");
         RateSel *sel = reinterpret_cast<RateSel *>(small_ptr(ctx, kSelOff));
-        HIP_TRY(ctx, launch_rate_select(sse1, sse7, band_args(desc), k, nblk, sel, ctx->stream), "rate select");
+        HIP_TRY(ctx, launch_rate_select(sse1, sse7, band_args(desc), k_auto, nblk, sel, ctx->stream), "rate select");
         HIP_TRY(ctx, launch_copy_streams(buf1, doff1, buf7, doff7, sel, nblk, blocks, ctx->stream), "stream copy");
-        // stage[0..] is reused for the read-back below, after the H2D copy has run
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "encode");
         HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, sel, sizeof(RateSel), hipMemcpyDeviceToHost, ctx->stream), "selection read-back");
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "encode");
+    }
+    char *sstage = static_cast<char *>(ctx->pinned) + 1024;
+    HIP_TRY(ctx, hipMemcpyAsync(sstage, sse1, 32 * sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream), "sse read-back");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "encode");
+    if (format == GSBC_FMT_AUTO) {
         const RateSel *r = static_cast<const RateSel *>(ctx->pinned);
         for (int q = 0; q < 16; q++) { host_fmt[q] = r->format[q]; host_off[q] = r->offset[q]; }
         if (r->payload_bytes != payload) return fail(ctx, GSBC_E_DEVICE, "selected payload size disagrees with the budget");
     }
-    char *stage = static_cast<char *>(ctx->pinned) + 1024;
-    HIP_TRY(ctx, hipMemcpyAsync(stage, sse1, 32 * sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream), "sse read-back");
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "encode");
     if (band_sse) {
-        const uint64_t *h = reinterpret_cast<const uint64_t *>(stage);
-        bool have1 = format != GSBC_FMT_BC7, have7 = format != GSBC_FMT_BC1;
+        const uint64_t *h = reinterpret_cast<const uint64_t *>(sstage);
         for (int q = 0; q < 16; q++) {
-            band_sse[q] = have1 ? (int64_t)h[q] : -1;
-            band_sse[16 + q] = have7 ? (int64_t)h[16 + q] : -1;
+            const bool c1 = format == GSBC_FMT_AUTO || (have1 && host_fmt[q] == GSBC_FMT_BC1);
+            const bool c7 = format == GSBC_FMT_AUTO || (have7 && host_fmt[q] == GSBC_FMT_BC7);
+            band_sse[q] = c1 ? (int64_t)h[q] : -1;
+            band_sse[16 + q] = c7 ? (int64_t)h[16 + q] : -1;
         }
     }
     for (int q = 0; q < 16; q++) { desc->format[q] = (uint8_t)host_fmt[q]; desc->offset[q] = host_off[q]; }
     desc->payload_bytes = payload;
+    return GSBC_OK;
+}
+
+void gsbc_default_batch_tuning(gsbc_batch_tuning *t)
+{
+    if (!t) return;
+    t->item_rounds = 1;
+    t->wgs_per_cu = 0;
+    t->bc1_lanes = kPlainBc1Lanes;
+    t->bc7_split = kPlainBc7Split;
+    t->concurrent = 0;
+}
+
+gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *const *textures,
+                              gsbc_stream_desc *descs, uint8_t *const *blocks, const uint64_t *blocks_capacity,
+                              const gsbc_params *params, const gsbc_batch_tuning *tuning, int64_t *band_sse)
+{
+    gsbc_status s = begin(ctx);
+    if (s) return s;
+    ActiveGuard guard(ctx);
+    if (!textures || !descs || !blocks || !blocks_capacity) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
+    if (n_scenes == 0 || n_scenes > 4096) return fail(ctx, GSBC_E_ARG, "n_scenes %u not in 1..4096", n_scenes);
+    gsbc_params p = resolve(params);
+    if ((s = check_params(ctx, p))) return s;
+    gsbc_batch_tuning t;
+    gsbc_default_batch_tuning(&t);
+    if (tuning) t = *tuning;
+    if (t.item_rounds < 1 || t.item_rounds > 64) return fail(ctx, GSBC_E_ARG, "tuning.item_rounds %u not in 1..64", t.item_rounds);
+    if (t.wgs_per_cu > 16) return fail(ctx, GSBC_E_ARG, "tuning.wgs_per_cu %u > 16", t.wgs_per_cu);
+    if (t.bc1_lanes != 64 && t.bc1_lanes != 128 && t.bc1_lanes != 256)
+        return fail(ctx, GSBC_E_ARG, "tuning.bc1_lanes %u is not 64, 128 or 256", t.bc1_lanes);
+    if (t.bc7_split > 2) return fail(ctx, GSBC_E_ARG, "tuning.bc7_split %u > 2", t.bc7_split);
+    if (t.concurrent > 1) return fail(ctx, GSBC_E_ARG, "tuning.concurrent %u > 1", t.concurrent);
+    // validate every scene and lay out its streams (host only, nothing enqueued yet)
+    std::vector<uint64_t> offs(16 * (size_t)n_scenes), pay(n_scenes);
+    std::vector<uint32_t> fmts(16 * (size_t)n_scenes);
+    for (uint32_t i = 0; i < n_scenes; i++) {
+        if (!textures[i] || !blocks[i]) return fail(ctx, GSBC_E_ARG, "scene %u: NULL pointer", i);
+        if ((reinterpret_cast<uintptr_t>(textures[i]) & 15) || (reinterpret_cast<uintptr_t>(blocks[i]) & 15))
+            return fail(ctx, GSBC_E_ARG, "scene %u: textures and blocks must be 16-byte aligned", i);
+        if ((s = check_desc(ctx, &descs[i]))) return s;
+        for (int k = 0; k < 16; k++) {
+            fmts[16 * i + k] = descs[i].format[k];
+            if (fmts[16 * i + k] != GSBC_FMT_BC1 && fmts[16 * i + k] != GSBC_FMT_BC7)
+                return fail(ctx, GSBC_E_ARG, "scene %u: desc.format[%d] = %u is not BC1 or BC7", i, k, descs[i].format[k]);
+        }
+        pay[i] = layout(&fmts[16 * i], descs[i].blocks_per_band, &offs[16 * i]);
+        if (blocks_capacity[i] < pay[i])
+            return fail(ctx, GSBC_E_BUFFER, "scene %u: blocks_capacity %llu < payload %llu bytes", i,
+                        (unsigned long long)blocks_capacity[i], (unsigned long long)pay[i]);
+    }
+    // the plan signature: everything the captured launches depend on
+    std::vector<uint64_t> sig;
+    sig.reserve(8 + 20 * (size_t)n_scenes);
+    sig.push_back(n_scenes);
+    sig.push_back(p.refine_steps);
+    sig.push_back(p.bc7_mode_mask);
+    sig.push_back(((uint64_t)t.item_rounds << 32) | t.wgs_per_cu);
+    sig.push_back(((uint64_t)t.bc1_lanes << 32) | (t.bc7_split << 1) | t.concurrent);
+    for (uint32_t i = 0; i < n_scenes; i++) {
+        sig.push_back(reinterpret_cast<uintptr_t>(textures[i]));
+        sig.push_back(reinterpret_cast<uintptr_t>(blocks[i]));
+        sig.push_back(descs[i].blocks_per_band);
+        uint64_t f = 0;
+        for (int k = 0; k < 16; k++) f |= (uint64_t)(fmts[16 * i + k] == GSBC_FMT_BC7) << k;
+        sig.push_back(f);
+    }
+    if (sig != ctx->plan_sig) {
+        drop_plan(ctx);
+        Runs r1, r7;
+        for (uint32_t i = 0; i < n_scenes; i++) {
+            const uint64_t nblk = descs[i].blocks_per_band;
+            for (int k = 0; k < 16; k++) {
+                const uint8_t *src = textures[i] + (uint64_t)k * nblk * 64;
+                uint8_t *dst = blocks[i] + offs[16 * i + k];
+                if (fmts[16 * i + k] == GSBC_FMT_BC7) r7.add(src, dst, nullptr, nblk);
+                else r1.add(src, dst, nullptr, nblk);
+            }
+        }
+        // plan memory: [runs7][runs1][sse n_scenes x 16][queues 4 x u64][BC7 keys]
+        const size_t b7 = align16(r7.v.size() * sizeof(BlockRun)), b1 = align16(r1.v.size() * sizeof(BlockRun));
+        const size_t bs = 16 * (size_t)n_scenes * 8, bq = 64;
+        const size_t bytes = b7 + b1 + bs + bq + bc7_scratch_bytes(r7.total);
+        if (injected_alloc_failure()) return fail(ctx, GSBC_E_NOMEM, "plan allocation of %zu bytes failed (injected)", bytes);
+        hipError_t e = hipMalloc(&ctx->plan_mem, bytes);
+        if (e != hipSuccess) {
+            ctx->plan_mem = nullptr;
+            (void)hipGetLastError();
+            return fail(ctx, GSBC_E_NOMEM, "plan allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+        }
+        uint8_t *pm = static_cast<uint8_t *>(ctx->plan_mem);
+        BlockRun *d7 = reinterpret_cast<BlockRun *>(pm), *d1 = reinterpret_cast<BlockRun *>(pm + b7);
+        ctx->plan_sse = reinterpret_cast<unsigned long long *>(pm + b7 + b1);
+        uint32_t *queues = reinterpret_cast<uint32_t *>(pm + b7 + b1 + bs);
+        uint32_t *keys = reinterpret_cast<uint32_t *>(pm + b7 + b1 + bs + bq);
+        {   // each run adds into its (scene, band) SSE slot
+            size_t q7 = 0, q1 = 0;
+            for (uint32_t i = 0; i < n_scenes; i++)
+                for (int k = 0; k < 16; k++) {
+                    BlockRun &r = fmts[16 * i + k] == GSBC_FMT_BC7 ? r7.v[q7++] : r1.v[q1++];
+                    r.sse = ctx->plan_sse + 16 * (size_t)i + k;
+                }
+        }
+        if (!r7.v.empty()) HIP_TRY(ctx, hipMemcpy(d7, r7.v.data(), r7.v.size() * sizeof(BlockRun), hipMemcpyHostToDevice), "run table");
+        if (!r1.v.empty()) HIP_TRY(ctx, hipMemcpy(d1, r1.v.data(), r1.v.size() * sizeof(BlockRun), hipMemcpyHostToDevice), "run table");
+        int cus = 0;
+        HIP_TRY(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device), "device attribute");
+        if (t.concurrent && !ctx->side) {
+            HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "side stream");
+            HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming), "event");
+            HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming), "event");
+        }
+        EncodeArgs a;
+        memset(&a, 0, sizeof a);
+        a.refine_steps = p.refine_steps;
+        a.mode_mask = p.bc7_mode_mask;
+        a.keys = keys;
+        WorkSplit w3[3], w1;
+        for (int q = 0; q < 3; q++)
+            w3[q] = {t.item_rounds, (uint32_t)cus * t.wgs_per_cu, t.wgs_per_cu ? queues + 2 * q : nullptr};
+        w1 = {t.item_rounds, (uint32_t)cus * t.wgs_per_cu, t.wgs_per_cu ? queues + 6 : nullptr};
+        // capture the whole sequence once
+        ctx->capturing = true;
+        e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) { ctx->capturing = false; drop_plan(ctx); return hip_fail(ctx, e, "graph capture"); }
+        hipError_t le = launch_fill_u64(ctx->plan_sse, 16 * (uint64_t)n_scenes, 0, ctx->stream);
+        hipStream_t s1 = ctx->stream;
+        if (le == hipSuccess && t.concurrent && !r1.v.empty() && !r7.v.empty()) {
+            le = hipEventRecord(ctx->fork, ctx->stream);
+            if (le == hipSuccess) le = hipStreamWaitEvent(ctx->side, ctx->fork, 0);
+            s1 = ctx->side;
+        }
+        if (le == hipSuccess && !r7.v.empty()) {
+            a.run = d7;
+            a.nrun = (uint32_t)r7.v.size();
+            a.total = r7.total;
+            le = launch_bc7_encode(a, w3, t.bc7_split, ctx->stream);
+        }
+        if (le == hipSuccess && !r1.v.empty()) {
+            a.run = d1;
+            a.nrun = (uint32_t)r1.v.size();
+            a.total = r1.total;
+            le = launch_bc1_encode(a, w1, t.bc1_lanes, s1);
+        }
+        if (le == hipSuccess && s1 != ctx->stream) {
+            le = hipEventRecord(ctx->join, s1);
+            if (le == hipSuccess) le = hipStreamWaitEvent(ctx->stream, ctx->join, 0);
+        }
+        e = hipStreamEndCapture(ctx->stream, &ctx->graph);
+        ctx->capturing = false;
+        if (le != hipSuccess || e != hipSuccess) {
+            drop_plan(ctx);
+            return hip_fail(ctx, le != hipSuccess ? le : e, "batch capture");
+        }
+        e = hipGraphInstantiate(&ctx->graph_exec, ctx->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) { drop_plan(ctx); return hip_fail(ctx, e, "graph instantiate"); }
+        ctx->plan_sig = sig;
+    }
+    trace_begin("encode_batch_graph", ctx->stream);
+    HIP_TRY(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream), "graph launch");
+    trace_end(ctx->stream);
+    for (uint32_t i = 0; i < n_scenes; i++) {
+        for (int k = 0; k < 16; k++) descs[i].offset[k] = offs[16 * i + k];
+        descs[i].payload_bytes = pay[i];
+    }
+    if (band_sse) {
+        std::vector<uint64_t> h(16 * (size_t)n_scenes);
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "encode_batch");
+        HIP_TRY(ctx, hipMemcpy(h.data(), ctx->plan_sse, h.size() * 8, hipMemcpyDeviceToHost), "sse read-back");
+        for (size_t q = 0; q < h.size(); q++) band_sse[q] = (int64_t)h[q];
+    }
     return GSBC_OK;
 }
 

@@ -23,7 +23,6 @@
 namespace gsbc {
 namespace {
 
-constexpr int kBlock = 128;   // lanes per workgroup
 
 // Constant-colour endpoint tables per channel width (0: 5 bits, 1: 6 bits),
 // and the nearest-code table of the cluster fit: code[w][h] is the number of
@@ -38,8 +37,9 @@ __constant__ Bc1Tables kTab;
 // Per-workgroup LDS: -2 x the prefix sums of the ordered texels, row 3 s + c
 // holding channel c of the sum over the first s texels, one column per lane;
 // and the nearest-code table with its expanded values.
+template <int LANES>
 struct Bc1Lds {
-    int m2P[17 * 3][kBlock];
+    int m2P[17 * 3][LANES];
     uint8_t code[2][512];
     uint8_t val[2][512];
 };
@@ -139,8 +139,8 @@ __device__ inline uint32_t canon_index(uint32_t &c0, uint32_t &c1, bool four, co
 //   2 num1 =  F (A + AB) (-2 SA) + 2 F A F tot.
 // The best split (strictly less SSE, so the first on ties) is kept by its
 // packed bounds.
-template <bool FOUR>
-__device__ __forceinline__ void split_list(const Bc1Lds &L, int lane, const int (&tot)[3], const int (&m2tot)[3],
+template <bool FOUR, class Lds>
+__device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&tot)[3], const int (&m2tot)[3],
                                            int Q, uint32_t &best, uint32_t &best_split)
 {
     constexpr int F = FOUR ? 3 : 2;
@@ -188,7 +188,8 @@ __device__ __forceinline__ void split_list(const Bc1Lds &L, int lane, const int 
 }
 
 // Endpoint codes of one split (the same arithmetic as split_list).
-__device__ void split_codes(const Bc1Lds &L, int lane, const int (&tot)[3], const int (&m2tot)[3], uint32_t split,
+template <class Lds>
+__device__ __forceinline__ void split_codes(const Lds &L, int lane, const int (&tot)[3], const int (&m2tot)[3], uint32_t split,
                             int (&q0)[3], int (&q1)[3])
 {
     const bool four = (split >> 15) & 1;
@@ -213,7 +214,8 @@ __device__ void split_codes(const Bc1Lds &L, int lane, const int (&tot)[3], cons
     }
 }
 
-__device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, Bc1Lds &L, int lane, uint32_t &w0,
+template <class Lds>
+__device__ __forceinline__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, Lds &L, int lane, uint32_t &w0,
                              uint32_t &w1, uint32_t &sse_out)
 {
     Tex16 T;
@@ -365,36 +367,57 @@ __device__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, Bc1
     sse_out = sse;
 }
 
-__global__ __launch_bounds__(kBlock) void k_bc1_encode(EncodeArgs a)
+// One lane per block over the run map; rounds of LANES blocks (a run never
+// straddles a round since runs start at multiples of 256).
+template <int LANES>
+__global__ __launch_bounds__(LANES) __attribute__((amdgpu_waves_per_eu(3))) void k_bc1_encode(EncodeArgs a, WorkSplit w)
 {
-    __shared__ Bc1Lds L;
-    for (int e = threadIdx.x; e < 2 * 512; e += kBlock) {
+    __shared__ Bc1Lds<LANES> L;
+    __shared__ uint32_t s_item;
+    for (int e = threadIdx.x; e < 2 * 512; e += LANES) {
         const int wide = e >> 9, c = kTab.code[wide][e & 511];
         L.code[wide][e & 511] = (uint8_t)c;
         L.val[wide][e & 511] = (uint8_t)ew(c, wide);
     }
     __syncthreads();
-    const uint64_t g0 = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
-    const uint64_t total = (uint64_t)a.nbands * a.nblk;
-    const bool live = g0 < total;
-    const uint64_t g = live ? g0 : total - 1;   // past-the-end lanes redo the last block, write nothing
-    const uint32_t band = a.band0 + (uint32_t)(g / a.nblk);
-    const uint64_t b = g % a.nblk;
-    const uint4 *src = reinterpret_cast<const uint4 *>(a.textures + ((uint64_t)band * a.nblk + b) * 64);
-    uint32_t t[16];
+    const uint64_t n_items = (a.total + (uint64_t)w.item_rounds * LANES - 1) / ((uint64_t)w.item_rounds * LANES);
+    uint32_t item = blockIdx.x;
+    if (w.queue) {
+        if (threadIdx.x == 0) s_item = atomicAdd(w.queue, 1u);
+        __syncthreads();
+        item = s_item;
+    }
+    while (item < n_items) {
+        for (uint32_t r = 0; r < w.item_rounds; r++) {
+            const uint64_t g0 = ((uint64_t)item * w.item_rounds + r) * LANES;
+            if (g0 >= a.total) break;
+            const BlockRun run = a.run[find_run(a.run, a.nrun, g0)];
+            const uint64_t b = g0 - run.gbase + threadIdx.x;
+            const bool live = b < run.nblk;
+            if (__ballot(live) == 0) continue;   // padding (per wave; no barriers below)
+            const uint64_t bl = live ? b : run.nblk - 1;   // dead lanes redo the last block, write nothing
+            const uint4 *src = reinterpret_cast<const uint4 *>(run.src + bl * 64);
+            uint32_t t[16];
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        uint4 v = src[q];
-        t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
+            for (int q = 0; q < 4; q++) {
+                uint4 v = src[q];
+                t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
+            }
+            uint32_t w0, w1, sse;
+            encode_block(t, a.refine_steps, L, threadIdx.x, w0, w1, sse);
+            if (live) {
+                uint2 *dst = reinterpret_cast<uint2 *>(run.dst + b * 8);
+                *dst = make_uint2(w0, w1);
+                if (b == run.nblk - 1 && (run.nblk & 1)) dst[1] = make_uint2(0, 0);   // 16-byte stream alignment
+            }
+            if (run.sse) band_add(run.sse, 0, sse, live);
+        }
+        if (!w.queue) break;
+        __syncthreads();   // every thread has read s_item
+        if (threadIdx.x == 0) s_item = atomicAdd(w.queue, 1u);
+        __syncthreads();
+        item = s_item;
     }
-    uint32_t w0, w1, sse;
-    encode_block(t, a.refine_steps, L, threadIdx.x, w0, w1, sse);
-    if (live) {
-        uint2 *dst = reinterpret_cast<uint2 *>(a.out + a.out_offset[band] + b * 8);
-        *dst = make_uint2(w0, w1);
-        if (b == a.nblk - 1 && (a.nblk & 1)) dst[1] = make_uint2(0, 0);   // 16-byte stream alignment
-    }
-    if (a.band_sse) band_add(a.band_sse, band, sse, live);
 }
 
 // Host-side construction of the constant-colour tables: for each channel
@@ -448,11 +471,19 @@ hipError_t upload_bc1_tables(hipStream_t st)
     return hipMemcpyToSymbolAsync(HIP_SYMBOL(kTab), &host, sizeof(host), 0, hipMemcpyHostToDevice, st);
 }
 
-hipError_t launch_bc1_encode(const EncodeArgs &a, hipStream_t st)
+hipError_t launch_bc1_encode(const EncodeArgs &a, const WorkSplit &w, uint32_t lanes, hipStream_t st)
 {
-    uint64_t total = (uint64_t)a.nbands * a.nblk;
-    if (total == 0) return hipSuccess;
-    GSBC_LAUNCH("bc1_encode", k_bc1_encode, dim3((uint32_t)((total + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, a);
+    if (a.total == 0) return hipSuccess;
+    if (lanes != 64 && lanes != 128 && lanes != 256) return hipErrorInvalidValue;
+    if (w.queue) {
+        hipError_t f = launch_fill_u64(reinterpret_cast<unsigned long long *>(w.queue), 1, 0, st);
+        if (f != hipSuccess) return f;
+    }
+    const uint64_t rounds = a.total / lanes;
+    const dim3 grid(w.queue ? w.grid : (uint32_t)((rounds + w.item_rounds - 1) / w.item_rounds));
+    if (lanes == 64) GSBC_LAUNCH("bc1_encode", k_bc1_encode<64>, grid, dim3(64), 0, st, a, w);
+    else if (lanes == 128) GSBC_LAUNCH("bc1_encode", k_bc1_encode<128>, grid, dim3(128), 0, st, a, w);
+    else GSBC_LAUNCH("bc1_encode", k_bc1_encode<256>, grid, dim3(256), 0, st, a, w);
     return hipGetLastError();
 }
 

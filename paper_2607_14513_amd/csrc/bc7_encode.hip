@@ -535,7 +535,7 @@ __device__ __forceinline__ void consider(uint32_t sse, int ci, uint32_t &best)
 }
 
 template <int GROUP>
-__device__ uint32_t search_group(const TexLds &S, uint32_t mode_mask, const uint32_t *sv)
+__device__ __forceinline__ uint32_t search_group(const TexLds &S, uint32_t mode_mask, const uint32_t *sv)
 {
     uint32_t best = 0xFFFFFFFFu;
     if (GROUP == 0) {
@@ -716,31 +716,27 @@ __device__ __forceinline__ void emit(const TexLds &S, int ci, const uint32_t *sv
 struct Bc7Launch {
     EncodeArgs a;
     Tables T;
+    WorkSplit w;
 };
 
-// Stage this workgroup's blocks in LDS (4x-scaled packed texels, one column
-// per lane) with the endpoint-quantisation table; returns false for lanes
-// past the last block (they still take part in the barrier).
-__device__ __forceinline__ bool stage_block(TexLds &S, const Bc7Launch &L, uint32_t &band, uint64_t &b)
+__device__ __forceinline__ void stage_table(TexLds &S, const Tables &T)
 {
-    const EncodeArgs &a = L.a;
     for (int q = threadIdx.x; q < kQEntries / 2; q += kWG)
-        reinterpret_cast<uint32_t *>(S.q)[q] = reinterpret_cast<const uint32_t *>(L.T.nearest)[q];
-    const uint64_t g = (uint64_t)blockIdx.x * kWG + threadIdx.x;
-    const uint64_t total = (uint64_t)a.nbands * a.nblk;
+        reinterpret_cast<uint32_t *>(S.q)[q] = reinterpret_cast<const uint32_t *>(T.nearest)[q];
+}
+
+// This lane's block (zeros when not live) as 4x-scaled packed texels in its
+// LDS column.  The caller brackets it with barriers.
+__device__ __forceinline__ void stage_texels(TexLds &S, const uint8_t *src, bool live)
+{
     uint32_t t[16];
 #pragma unroll
     for (int i = 0; i < 16; i++) t[i] = 0;
-    band = 0;
-    b = 0;
-    const bool live = g < total;
     if (live) {
-        band = a.band0 + (uint32_t)(g / a.nblk);
-        b = g % a.nblk;
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.textures + ((uint64_t)band * a.nblk + b) * 64);
+        const uint4 *p = reinterpret_cast<const uint4 *>(src);
 #pragma unroll
         for (int q = 0; q < 4; q++) {
-            uint4 v = src[q];
+            uint4 v = p[q];
             t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
         }
     }
@@ -750,33 +746,80 @@ __device__ __forceinline__ bool stage_block(TexLds &S, const Bc7Launch &L, uint3
         S.rg[i][threadIdx.x] = (r << 4) | (g << 20);
         S.bx[i][threadIdx.x] = bb | (256u * (r * r + g * g + bb * bb));
     }
-    __syncthreads();
-    return live;
 }
 
-// Pass 1: the best key of every block over one candidate group, min-combined
-// into the block's key word (group 0 writes it first).
-template <int GROUP>
+// Items of the work split handled by this workgroup: one (its own index)
+// without a queue, else popped from the queue until exhausted.  Every
+// workgroup leaves the loop once the counter passes the last item.
+struct ItemLoop {
+    uint32_t item, n_items;
+    __device__ __forceinline__ ItemLoop(const WorkSplit &w, uint64_t total, uint32_t round, uint32_t *s_item)
+    {
+        n_items = (uint32_t)((total + (uint64_t)w.item_rounds * round - 1) / ((uint64_t)w.item_rounds * round));
+        item = blockIdx.x;
+        if (w.queue) {
+            if (threadIdx.x == 0) *s_item = atomicAdd(w.queue, 1u);
+            __syncthreads();
+            item = *s_item;
+        }
+    }
+    __device__ __forceinline__ bool next(const WorkSplit &w, uint32_t *s_item)
+    {
+        if (!w.queue) return false;
+        __syncthreads();   // every thread has read *s_item
+        if (threadIdx.x == 0) *s_item = atomicAdd(w.queue, 1u);
+        __syncthreads();
+        item = *s_item;
+        return item < n_items;
+    }
+};
+
+// Pass 1: the best key of every block over the candidate groups in GMASK
+// (bit 0: 2-subset modes, bit 1: 3-subset modes, bit 2: 1-subset modes),
+// min-combined into the block's key word.  The kernel holding group 0 runs
+// first and writes the word (all-ones for padding indices); the one holding
+// group 2 runs last and adds the final SSE (key >> 9) into the run's sum.
+template <int GMASK>
 __global__ __launch_bounds__(kWG) void k_bc7_search(Bc7Launch L)
 {
     __shared__ TexLds S;
-    uint32_t band;
-    uint64_t b;
-    const bool live = stage_block(S, L, band, b);
-    if (__ballot(live) == 0) return;
-    uint32_t key = live ? search_group<GROUP>(S, L.a.mode_mask, L.T.sv) : 0u;
-    uint32_t *slot = L.a.keys + (uint64_t)blockIdx.x * kWG + threadIdx.x;   // block g's key
-    if (live) {
-        if (GROUP > 0) key = min(key, *slot);
-        *slot = key;
-    }
-    // the last group holds each block's final key: its SSE is key >> 9
-    if (GROUP == 2 && L.a.band_sse) band_add(L.a.band_sse, band, key >> 9, live);
+    __shared__ uint32_t s_item;
+    const EncodeArgs &a = L.a;
+    stage_table(S, L.T);
+    ItemLoop it(L.w, a.total, kWG, &s_item);
+    if (it.item >= it.n_items) return;
+    do {
+        for (uint32_t r = 0; r < L.w.item_rounds; r++) {
+            const uint64_t g0 = ((uint64_t)it.item * L.w.item_rounds + r) * kWG;
+            if (g0 >= a.total) break;
+            const BlockRun run = a.run[find_run(a.run, a.nrun, g0)];
+            const uint64_t b = g0 - run.gbase + threadIdx.x;
+            const bool live = b < run.nblk;
+            __syncthreads();   // the previous round's LDS reads are done
+            stage_texels(S, run.src + b * 64, live);
+            __syncthreads();
+            uint32_t *slot = a.keys + g0 + threadIdx.x;
+            if (__ballot(live) == 0) {
+                if (GMASK & 1) *slot = ~0u;
+                continue;
+            }
+            uint32_t key = ~0u;
+            if (live) {
+                if (GMASK & 1) key = min(key, search_group<0>(S, a.mode_mask, L.T.sv));
+                if (GMASK & 2) key = min(key, search_group<1>(S, a.mode_mask, L.T.sv));
+                if (GMASK & 4) key = min(key, search_group<2>(S, a.mode_mask, L.T.sv));
+                if (!(GMASK & 1)) key = min(key, *slot);
+            }
+            if ((GMASK & 1) || live) *slot = live ? key : ~0u;
+            if ((GMASK & 4) && run.sse) band_add(run.sse, 0, key >> 9, live);
+        }
+    } while (it.next(L.w, &s_item));
 }
 
 // Between the passes: bucket the blocks by the mode of their winner, so that
 // the emit kernel of each mode runs full waves of that mode.  Order inside a
-// bucket does not matter: every block is emitted independently.
+// bucket does not matter: every block is emitted independently.  Padding
+// indices (key all-ones) join no bucket.
 __device__ __forceinline__ int mode_of_candidate(int ci)
 {
     return ci < 16 ? 0 : ci < 80 ? 1 : ci < 144 ? 2 : ci < 208 ? 3 : ci < 216 ? 4 : ci < 220 ? 5 : ci < 221 ? 6 : 7;
@@ -789,7 +832,8 @@ __global__ __launch_bounds__(kWG) void k_bc7_bucket_count(const uint32_t *keys, 
     if (threadIdx.x < 8) c[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t g = (uint64_t)blockIdx.x * kWG + threadIdx.x;
-    if (g < total) atomicAdd(&c[mode_of_candidate((int)(keys[g] & 511u))], 1u);
+    const uint32_t key = g < total ? keys[g] : ~0u;
+    if (key != ~0u) atomicAdd(&c[mode_of_candidate((int)(key & 511u))], 1u);
     __syncthreads();
     if (threadIdx.x < 8) wgcount[(uint64_t)blockIdx.x * 8 + threadIdx.x] = c[threadIdx.x];
 }
@@ -847,7 +891,7 @@ __global__ __launch_bounds__(kWG) void k_bc7_bucket_fill(const uint32_t *keys, u
     if (threadIdx.x < 8) c[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t g = (uint64_t)blockIdx.x * kWG + threadIdx.x;
-    if (g >= total) return;
+    if (g >= total || keys[g] == ~0u) return;
     const int m = mode_of_candidate((int)(keys[g] & 511u));
     const uint32_t rank = atomicAdd(&c[m], 1u);
     list[count[8 + m] + wgoff[(uint64_t)blockIdx.x * 8 + m] + rank] = (uint32_t)g;
@@ -860,41 +904,22 @@ __global__ __launch_bounds__(kWG) void k_bc7_emit(Bc7Launch L)
 {
     __shared__ TexLds S;
     const EncodeArgs &a = L.a;
-    const uint64_t total = (uint64_t)a.nbands * a.nblk;
-    const uint32_t *list = a.keys + total, *count = a.keys + 2 * total;
+    const uint32_t *list = a.keys + a.total, *count = a.keys + 2 * a.total;
     const uint32_t n = count[M], off = count[8 + M];
     const uint64_t e = (uint64_t)blockIdx.x * kWG + threadIdx.x;
     if ((uint64_t)blockIdx.x * kWG >= n) return;   // whole workgroup past the bucket
     const bool live = e < n;
-    const uint64_t g = live ? list[off + e] : 0;
-    // stage the block in LDS (lanes past the bucket stage zeros)
-    for (int q = threadIdx.x; q < kQEntries / 2; q += kWG)
-        reinterpret_cast<uint32_t *>(S.q)[q] = reinterpret_cast<const uint32_t *>(L.T.nearest)[q];
-    uint32_t t[16];
-#pragma unroll
-    for (int i = 0; i < 16; i++) t[i] = 0;
-    const uint32_t band = a.band0 + (uint32_t)(g / a.nblk);
-    const uint64_t b = g % a.nblk;
-    if (live) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.textures + ((uint64_t)band * a.nblk + b) * 64);
-#pragma unroll
-        for (int q = 0; q < 4; q++) {
-            uint4 v = src[q];
-            t[4 * q] = v.x; t[4 * q + 1] = v.y; t[4 * q + 2] = v.z; t[4 * q + 3] = v.w;
-        }
-    }
-#pragma unroll
-    for (int i = 0; i < 16; i++) {
-        const uint32_t r = t[i] & 255u, g = (t[i] >> 8) & 255u, bb = (t[i] >> 16) & 255u;
-        S.rg[i][threadIdx.x] = (r << 4) | (g << 20);
-        S.bx[i][threadIdx.x] = bb | (256u * (r * r + g * g + bb * bb));
-    }
+    const uint64_t g = live ? list[off + e] : a.run[0].gbase;
+    const BlockRun run = a.run[find_run(a.run, a.nrun, g)];
+    const uint64_t b = g - run.gbase;
+    stage_table(S, L.T);
+    stage_texels(S, run.src + b * 64, live);   // lanes past the bucket stage zeros
     __syncthreads();
     if (!live) return;
     const uint32_t key = a.keys[g];
     uint64_t lo, hi;
     emit<M>(S, (int)(key & 511u), L.T.sv, lo, hi);
-    *reinterpret_cast<ulonglong2 *>(a.out + a.out_offset[band] + b * 16) = make_ulonglong2(lo, hi);
+    *reinterpret_cast<ulonglong2 *>(run.dst + b * 16) = make_ulonglong2(lo, hi);
 }
 
 // ---- host-side table construction
@@ -1004,29 +1029,47 @@ hipError_t upload_bc7_tables(int device, hipStream_t st)
     return hipSuccess;
 }
 
-hipError_t launch_bc7_encode(const EncodeArgs &a, hipStream_t st)
+hipError_t launch_bc7_encode(const EncodeArgs &a, const WorkSplit *w3, uint32_t split, hipStream_t st)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return e;
     if (!g_tab[dev]) return hipErrorNotInitialized;
-    uint64_t total = (uint64_t)a.nbands * a.nblk;
-    if (total == 0) return hipSuccess;
+    if (a.total == 0) return hipSuccess;
+    if (split > 2) return hipErrorInvalidValue;
     Bc7Launch L;
     L.a = a;
     L.T.nearest = static_cast<const uint16_t *>(g_tab[dev]);
     L.T.sv = reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(g_tab[dev]) + 10 * 2 * 256 * 2);
-    const dim3 sgrid((uint32_t)((total + kWG - 1) / kWG));
-    GSBC_LAUNCH("bc7_search_2subset", k_bc7_search<0>, sgrid, dim3(kWG), 0, st, L);
-    GSBC_LAUNCH("bc7_search_3subset", k_bc7_search<1>, sgrid, dim3(kWG), 0, st, L);
-    GSBC_LAUNCH("bc7_search_1subset", k_bc7_search<2>, sgrid, dim3(kWG), 0, st, L);
+    const uint32_t nwg = (uint32_t)(a.total / kWG);
+    const dim3 sgrid(nwg);
+    auto launch = [&](int q, auto kernel, const char *name) -> hipError_t {
+        L.w = w3[q];
+        dim3 grid(L.w.queue ? L.w.grid : (uint32_t)((nwg + L.w.item_rounds - 1) / L.w.item_rounds));
+        if (L.w.queue) {
+            hipError_t f = launch_fill_u64(reinterpret_cast<unsigned long long *>(L.w.queue), 1, 0, st);
+            if (f != hipSuccess) return f;
+        }
+        GSBC_LAUNCH(name, kernel, grid, dim3(kWG), 0, st, L);
+        return hipGetLastError();
+    };
+    if (split == 0) {
+        if ((e = launch(0, k_bc7_search<1>, "bc7_search_2subset")) != hipSuccess) return e;
+        if ((e = launch(1, k_bc7_search<2>, "bc7_search_3subset")) != hipSuccess) return e;
+        if ((e = launch(2, k_bc7_search<4>, "bc7_search_1subset")) != hipSuccess) return e;
+    } else if (split == 1) {
+        if ((e = launch(0, k_bc7_search<1>, "bc7_search_2subset")) != hipSuccess) return e;
+        if ((e = launch(1, k_bc7_search<6>, "bc7_search_3subset_1subset")) != hipSuccess) return e;
+    } else {
+        if ((e = launch(0, k_bc7_search<7>, "bc7_search_all")) != hipSuccess) return e;
+    }
     // key scratch: keys[total] | list[total] | count[8] start[8] | wgcount[nwg][8]
-    uint32_t *count = a.keys + 2 * total, *wgcount = count + 16;
-    const uint32_t nwg = sgrid.x;
-    GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_count, sgrid, dim3(kWG), 0, st, a.keys, total, wgcount);
+    uint32_t *count = a.keys + 2 * a.total, *wgcount = count + 16;
+    GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_count, sgrid, dim3(kWG), 0, st, a.keys, a.total, wgcount);
     GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_scan, dim3(1), dim3(256), 0, st, wgcount, nwg, count);
-    GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_fill, sgrid, dim3(kWG), 0, st, a.keys, total, wgcount, count,
-                a.keys + total);
+    GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_fill, sgrid, dim3(kWG), 0, st, a.keys, a.total, wgcount, count,
+                a.keys + a.total);
+    L.w = w3[0];
     if (a.mode_mask & 0x01) GSBC_LAUNCH("bc7_emit_m0", k_bc7_emit<0>, sgrid, dim3(kWG), 0, st, L);
     if (a.mode_mask & 0x02) GSBC_LAUNCH("bc7_emit_m1", k_bc7_emit<1>, sgrid, dim3(kWG), 0, st, L);
     if (a.mode_mask & 0x04) GSBC_LAUNCH("bc7_emit_m2", k_bc7_emit<2>, sgrid, dim3(kWG), 0, st, L);

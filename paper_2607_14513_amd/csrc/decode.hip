@@ -90,7 +90,6 @@ __global__ void k_sh_basis(const float *dirs, uint32_t n, float *basis)
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kSlots = 256;                 // slots per workgroup
 constexpr int kCols = 3 * kSlots;           // output floats per direction
-constexpr int kColTiles = kCols / 16;       // 48, 12 per wave
 constexpr int kDirChunk = 256;              // directions per workgroup (grid.y)
 
 __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *blocks, BandArgs b,

@@ -73,25 +73,61 @@ hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_
                           hipStream_t st);
 
 // ---- encoders (bc1_encode.hip, bc7_encode.hip)
-// Encode bands [band0, band0 + nbands) of textures[16][nblk][16][4]; band b's
-// blocks go to out + out_offset[b], block sse added into band_sse[b] (int64
-// atomics, order independent).
-struct EncodeArgs {
-    const uint8_t *textures;
+// The encoders work on runs: a run is the consecutive blocks of one band of
+// one scene, read from `src` (64-byte RGBA blocks) and written to `dst`
+// (8- or 16-byte coded blocks), with their SSE added into *sse (int64
+// atomics, order independent).  Runs sit in one global block index space at
+// multiples of kRunAlign, so a 256-lane round never straddles two runs;
+// indices past a run's end up to the next run are padding and code nothing.
+constexpr uint32_t kRunAlign = 256;
+struct BlockRun {
+    const uint8_t *src;
+    uint8_t *dst;
+    unsigned long long *sse;        // may be null
+    uint64_t gbase;                 // global index of the run's first block
     uint64_t nblk;
-    uint32_t band0, nbands;
-    uint8_t *out;
-    uint64_t out_offset[16];
-    unsigned long long *band_sse;   // [16], may be null
+};
+inline uint64_t run_span(uint64_t nblk) { return (nblk + kRunAlign - 1) / kRunAlign * kRunAlign; }
+
+// Index of the run holding global block g (runs sorted by gbase, g >= run[0].gbase).
+__device__ __forceinline__ uint32_t find_run(const BlockRun *run, uint32_t nrun, uint64_t g)
+{
+    uint32_t lo = 0, hi = nrun;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (run[mid].gbase <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Work distribution of the encoder kernels: the global index space is cut
+// into items of `item_rounds` x 256 blocks.  With queue == null each
+// workgroup codes one item (grid = items); otherwise `grid` persistent
+// workgroups pop items from *queue (zeroed beforehand) until none are left.
+struct WorkSplit {
+    uint32_t item_rounds;           // >= 1
+    uint32_t grid;                  // persistent workgroups (queue != null)
+    uint32_t *queue;                // one counter per kernel launch, or null
+};
+
+struct EncodeArgs {
+    const BlockRun *run;            // device array
+    uint32_t nrun;
+    uint64_t total;                 // end of the global index space (multiple of 256)
     uint32_t refine_steps;
     uint32_t mode_mask;
-    uint32_t *keys;                 // BC7 only: scratch of bc7_scratch_bytes(nbands * nblk)
+    uint32_t *keys;                 // BC7 only: scratch of bc7_scratch_bytes(total)
 };
-// Scratch bytes the BC7 encoder needs for `blocks` blocks: a key and a
-// bucket-list word per block, plus per-mode counters.
+// Scratch bytes the BC7 encoder needs for `blocks` global indices: a key and
+// a bucket-list word per index, plus per-mode counters.
 inline size_t bc7_scratch_bytes(uint64_t blocks) { return (size_t)blocks * 8 + 64 + ((blocks + 255) / 256) * 32; }
-hipError_t launch_bc1_encode(const EncodeArgs &a, hipStream_t st);
-hipError_t launch_bc7_encode(const EncodeArgs &a, hipStream_t st);
+// How the BC7 candidate search is split over kernels: 0 -> three kernels
+// (2-subset, 3-subset, 1-subset modes), 1 -> two (the 1-subset modes folded
+// into the 3-subset kernel), 2 -> one kernel for all modes.  Every split
+// gives the same bits (the winner is a minimum over a total order).
+hipError_t launch_bc1_encode(const EncodeArgs &a, const WorkSplit &w, uint32_t lanes, hipStream_t st);
+hipError_t launch_bc7_encode(const EncodeArgs &a, const WorkSplit *w3, uint32_t split, hipStream_t st);
 hipError_t upload_bc1_tables(hipStream_t st);
 hipError_t upload_bc7_tables(int device, hipStream_t st);
 

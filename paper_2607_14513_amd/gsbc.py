@@ -15,11 +15,12 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsbc.so")
 
 OK, E_ARG, E_UNSUPPORTED, E_NOMEM, E_INFEASIBLE, E_DEVICE, E_BUFFER = 0, -1, -2, -3, -4, -5, -6
-FMT_AUTO, FMT_BC1, FMT_BC7 = 0, 1, 7
+FMT_AUTO, FMT_BC1, FMT_BANDS, FMT_BC7 = 0, 1, 2, 7
 
 EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_default_params",
-            "gsbc_query_sizes", "gsbc_reorder", "gsbc_encode", "gsbc_decode", "gsbc_decode_eval",
-            "gsbc_profile_enable", "gsbc_profile_read")
+            "gsbc_query_sizes", "gsbc_reorder", "gsbc_encode", "gsbc_default_batch_tuning",
+            "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_profile_enable",
+            "gsbc_profile_read")
 
 
 class GsbcError(RuntimeError):
@@ -31,6 +32,15 @@ class GsbcError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("grid_bits", ctypes.c_uint32), ("refine_steps", ctypes.c_uint32),
                 ("bc7_mode_mask", ctypes.c_uint32)]
+
+
+class BatchTuning(ctypes.Structure):
+    _fields_ = [("item_rounds", ctypes.c_uint32), ("wgs_per_cu", ctypes.c_uint32),
+                ("bc1_lanes", ctypes.c_uint32), ("bc7_split", ctypes.c_uint32),
+                ("concurrent", ctypes.c_uint32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class StreamDesc(ctypes.Structure):
@@ -76,12 +86,16 @@ def load():
         lib.gsbc_reorder.argtypes = [P, P, P, u64, ctypes.POINTER(Params), P, P, ctypes.POINTER(StreamDesc)]
         lib.gsbc_encode.argtypes = [P, P, ctypes.POINTER(StreamDesc), ctypes.c_int, ctypes.c_double,
                                     ctypes.POINTER(Params), P, u64, P]
+        lib.gsbc_default_batch_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
+        lib.gsbc_default_batch_tuning.restype = None
+        lib.gsbc_encode_batch.argtypes = [P, u32, P, P, P, P, ctypes.POINTER(Params),
+                                          ctypes.POINTER(BatchTuning), P]
         lib.gsbc_decode.argtypes = [P, P, ctypes.POINTER(StreamDesc), P]
         lib.gsbc_decode_eval.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, u32, P, u64, P]
         lib.gsbc_profile_enable.argtypes = [P, ctypes.c_int]
         lib.gsbc_profile_read.argtypes = [P, u32, P, P, P, ctypes.POINTER(u32)]
         for name in EXPORTED:
-            if name not in ("gsbc_default_params", "gsbc_last_error"):
+            if name not in ("gsbc_default_params", "gsbc_last_error", "gsbc_default_batch_tuning"):
                 getattr(lib, name).restype = i32
         _lib = lib
     return _lib
@@ -93,6 +107,14 @@ def default_params(**kw):
     for k, v in kw.items():
         setattr(p, k, int(v))
     return p
+
+
+def default_batch_tuning(**kw):
+    t = BatchTuning()
+    load().gsbc_default_batch_tuning(ctypes.byref(t))
+    for k, v in kw.items():
+        setattr(t, k, int(v))
+    return t
 
 
 def query_sizes(n, n_dirs=0):
@@ -194,7 +216,8 @@ class Context:
         return perm, tex, desc
 
     def encode(self, textures, desc, fmt=FMT_AUTO, rate=6.0, params=None, blocks=None, want_sse=False):
-        """Encode all bands -> (blocks uint8 device tensor, desc, band_sse int64[2][16] or None)."""
+        """Encode all bands -> (blocks uint8 device tensor, desc, band_sse int64[2][16] or None).
+        fmt FMT_BANDS codes band k in desc.format[k] (set by the caller)."""
         _dev_tensor(textures, torch.uint8, "textures")
         desc = desc.copy()
         if blocks is None:
@@ -206,6 +229,31 @@ class Context:
                                        ctypes.byref(p), _ptr(blocks), blocks.numel(),
                                        ctypes.c_void_p(sse.ctypes.data) if sse is not None else None))
         return blocks, desc, (sse.reshape(2, 16) if sse is not None else None)
+
+    def encode_batch(self, textures, descs, blocks, params=None, tuning=None, want_sse=False):
+        """textures: list of device uint8 tensors (reorder layout); descs: list
+        of StreamDesc with format[16] set (each BC1 or BC7); blocks: list of
+        device uint8 tensors.  Returns (descs filled, band_sse int64[n][16] or
+        None).  Without want_sse the call returns once the graph is queued."""
+        n = len(textures)
+        if not (n == len(descs) == len(blocks)):
+            raise ValueError("textures, descs and blocks differ in length")
+        for i, t in enumerate(textures):
+            _dev_tensor(t, torch.uint8, f"textures[{i}]")
+            _dev_tensor(blocks[i], torch.uint8, f"blocks[{i}]")
+        tp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in textures])
+        bp = (ctypes.c_void_p * n)(*[b.data_ptr() for b in blocks])
+        cap = (ctypes.c_uint64 * n)(*[b.numel() for b in blocks])
+        darr = (StreamDesc * n)()
+        for i, d in enumerate(descs):
+            ctypes.memmove(ctypes.byref(darr[i]), ctypes.byref(d), ctypes.sizeof(StreamDesc))
+        sse = np.zeros(16 * n, np.int64) if want_sse else None
+        p = params if params is not None else default_params()
+        t = tuning if tuning is not None else default_batch_tuning()
+        self._check(load().gsbc_encode_batch(self._h, n, tp, darr, bp, cap, ctypes.byref(p), ctypes.byref(t),
+                                             ctypes.c_void_p(sse.ctypes.data) if sse is not None else None))
+        out = [darr[i].copy() for i in range(n)]
+        return out, (sse.reshape(n, 16) if sse is not None else None)
 
     def decode(self, blocks, desc, out=None):
         if out is None:
