@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (for counter scaling)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batched-encode leg")
+    ap.add_argument("--batch-scenes", type=int, default=64)
     return ap.parse_args()
 
 
@@ -224,6 +226,7 @@ def main():
                        "plain_fill_gbps": round(fill_gbps, 1)}
             del out3, b3
             torch.cuda.empty_cache()
+        batch = None if args.no_batch else batch_leg(ctx, stream, dev, args.batch_scenes, max(3, args.steps))
         ctx.close()
 
     cpu = None if args.no_cpu else cpu_baseline(pos, sh, dirs, rate)
@@ -244,9 +247,76 @@ def main():
         "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "roofline": roof,
         "roofline_decode_eval": roof_de,
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
+
+
+def batch_leg(ctx, stream, dev, n_scenes, reps):
+    """64 scenes of log-uniform size in [5e4, 2e6] primitives (seed 4; scene i
+    drawn with seed 1000 + i on the device), band 0 BC7 and bands 1..15 BC1:
+    one autotuned, graph-captured batched call against 64 single-scene calls.
+    Both must give identical bitstreams."""
+    import torch
+    from paper_2607_14513_amd import autotune, gsbc, synth
+    sizes = synth.batch_sizes(n_scenes, seed=4)
+    texs, descs = [], []
+    for i, n in enumerate(sizes):
+        pos_i, sh_i = synth.make_scene_device(n, seed=1000 + i, device=dev)
+        _, tex_i, d_i = ctx.reorder(pos_i, sh_i)
+        for k in range(16):
+            d_i.format[k] = gsbc.FMT_BC7 if k == 0 else gsbc.FMT_BC1
+        texs.append(tex_i)
+        descs.append(d_i)
+        del pos_i, sh_i
+    torch.cuda.synchronize()
+    nblocks = sum(16 * d.blocks_per_band for d in descs)
+    pay = [d.blocks_per_band * (16 + 15 * 8) + 16 * 16 for d in descs]
+    plain_out = [torch.empty(p, dtype=torch.uint8, device=dev) for p in pay]
+    batch_out = [torch.empty(p, dtype=torch.uint8, device=dev) for p in pay]
+
+    def plain_pass():
+        outs = []
+        for i in range(n_scenes):
+            _, di, _ = ctx.encode(texs[i], descs[i], fmt=gsbc.FMT_BANDS, blocks=plain_out[i])
+            outs.append(di)
+        return outs
+
+    plain_pass()
+    torch.cuda.synchronize()
+    t_plain = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        pd = plain_pass()
+        torch.cuda.synchronize()
+        t_plain.append(time.perf_counter() - t0)
+    tuning, tinfo = autotune.tune(ctx, texs, descs, batch_out, repeats=2,
+                                  log=lambda m: print(m, file=sys.stderr, flush=True))
+    bd, _ = ctx.encode_batch(texs, descs, batch_out, tuning=tuning)    # capture (or replay)
+    torch.cuda.synchronize()
+    t_batch, t_dev = [], []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        bd, _ = ctx.encode_batch(texs, descs, batch_out, tuning=tuning)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t_batch.append(time.perf_counter() - t0)
+        t_dev.append(e0.elapsed_time(e1) * 1e-3)
+    same = all(pd[i].payload_bytes == bd[i].payload_bytes and
+               torch.equal(plain_out[i][:pd[i].payload_bytes], batch_out[i][:bd[i].payload_bytes])
+               for i in range(n_scenes))
+    tp, tb = float(np.median(t_plain)), float(np.median(t_batch))
+    return {"workload": f"{n_scenes} scenes, {sum(sizes)} primitives (log-uniform 5e4..2e6, seed 4), "
+                        "band 0 BC7 + bands 1..15 BC1",
+            "blocks": int(nblocks), "plain_ms": round(tp * 1e3, 3), "batched_ms": round(tb * 1e3, 3),
+            "batched_device_ms": round(float(np.median(t_dev)) * 1e3, 3),
+            "plain_mblocks_s": round(nblocks / tp / 1e6, 3), "batched_mblocks_s": round(nblocks / tb / 1e6, 3),
+            "speedup": round(tp / tb, 3), "identical_bitstreams": bool(same),
+            "tuning": tuning.as_dict(), "autotune": {k: tinfo[k] for k in ("ms", "default_ms", "configs_timed",
+                                                                          "search_s", "cached") if k in tinfo}}
 
 
 def cpu_baseline(pos, sh, dirs, rate):

@@ -43,6 +43,31 @@ def make_scene(n, clusters=32, comps=64, seed=1):
     return pos.astype(np.float32), sh.astype(np.float32)
 
 
+def make_scene_device(n, clusters=32, comps=64, seed=1, device="cuda"):
+    """The same recipe drawn with torch's generator on the device, for
+    workloads too large to draw on the host (the batched and served
+    benchmarks).  A different random stream from make_scene: use make_scene
+    wherever the oracle sees the same inputs.  Returns device tensors
+    (pos float32[n][3], sh float32[n][16][3])."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f = dict(device=device, generator=g)
+    centres = torch.rand((clusters, 3), dtype=torch.float64, **f)
+    which = torch.randint(0, clusters, (n,), **f)
+    pos = centres[which] + (torch.rand((n, 3), dtype=torch.float64, **f) - 0.5) * 0.1
+    means = torch.rand((comps, 3), dtype=torch.float64, **f)
+    comp = torch.randint(0, comps, (n,), **f)
+    sh = torch.empty((n, 16, 3), dtype=torch.float32, device=device)
+    dc = means[comp] + torch.randn((n, 3), dtype=torch.float64, **f) * 0.05
+    sh[:, 0, :] = dc.clamp_(0.0, 1.0).float()
+    for k in range(1, 16):
+        scale = 0.2 / (band_degree(k) + 1) ** 2
+        u = torch.rand((n, 3), dtype=torch.float64, **f) - 0.5   # Laplace by inverse CDF
+        sh[:, k, :] = (-scale * torch.sign(u) * torch.log1p(-2.0 * u.abs())).float()
+    return pos.float().contiguous(), sh
+
+
 def make_dirs(v, seed=1):
     """float32[v][3] unit view directions."""
     rng = _rng(seed + 7919)
