@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (for counter scaling)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batched-encode leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--batch-scenes", type=int, default=64)
     return ap.parse_args()
 
@@ -228,6 +230,7 @@ def main():
             torch.cuda.empty_cache()
         batch = None if args.no_batch else batch_leg(ctx, stream, dev, args.batch_scenes, max(3, args.steps))
         ctx.close()
+    served = None if args.no_serve else serve_leg(dev, args.serve_requests)
 
     cpu = None if args.no_cpu else cpu_baseline(pos, sh, dirs, rate)
     line = {
@@ -248,6 +251,7 @@ def main():
         "roofline": roof,
         "roofline_decode_eval": roof_de,
         "batch": batch,
+        "serving": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))
@@ -317,6 +321,55 @@ def batch_leg(ctx, stream, dev, n_scenes, reps):
             "speedup": round(tp / tb, 3), "identical_bitstreams": bool(same),
             "tuning": tuning.as_dict(), "autotune": {k: tinfo[k] for k in ("ms", "default_ms", "configs_timed",
                                                                           "search_s", "cached") if k in tinfo}}
+
+
+def serve_leg(dev, count):
+    """Poisson arrivals of encode (70%) and decode_eval (30%) requests; N
+    log-uniform in [1e4, 4e6] primitives (slices of a 4M-primitive scene drawn
+    on the device, seed 5), V log-uniform in [1, 1024]; encodes at 6 bits per
+    texel stay resident; 4 slots, 200 GB HBM budget.  The arrival rate is 70%
+    of the plain path's capacity, measured first by serving a calibration set
+    one request at a time.  A sample of requests is re-run alone afterwards
+    and must give identical results."""
+    import torch
+    from paper_2607_14513_amd import serve, synth
+    pool_n = 4_000_000
+    pos, sh = synth.make_scene_device(pool_n, seed=5, device=dev)
+    torch.cuda.synchronize()
+    # plain capacity: one slot, requests back to back
+    cal = serve.make_requests(60, 1e9, seed=55, pool_n=pool_n)
+    s1 = serve.Server(pos, sh, slots=1, hbm_budget=200e9, fingerprint_ids=set())
+    try:
+        s1.run(cal[:6])                       # warm-up (contexts, allocator)
+        t0 = time.perf_counter()
+        s1.run(cal[6:])
+        service = (time.perf_counter() - t0) / len(cal[6:])
+    finally:
+        s1.close()
+    del s1
+    torch.cuda.empty_cache()
+    capacity = 1.0 / service
+    lam = 0.7 * capacity
+    reqs = serve.make_requests(count, lam, seed=5, pool_n=pool_n)
+    sample = set(range(0, count, max(1, count // 24)))
+    srv = serve.Server(pos, sh, slots=4, hbm_budget=200e9, fingerprint_ids=sample)
+    try:
+        done = srv.run(reqs)
+        summ = serve.summarize(done, srv.t_elapsed, srv.t0)
+        same = 0
+        checked = 0
+        for r in sorted(done, key=lambda r: r.rid):
+            if r.rid in sample and r.error is None:
+                checked += 1
+                same += int(srv.run_alone(r) == r.fingerprint)
+        summ.update({"workload": f"{count} requests, Poisson arrivals at {lam:.2f}/s (70% of the measured "
+                                 f"one-at-a-time capacity {capacity:.2f}/s), 70% encode at 6 bits/texel / 30% "
+                                 "decode_eval, N log-uniform 1e4..4e6, V log-uniform 1..1024, 4 slots, 200 GB budget",
+                     "arrival_rate_hz": round(lam, 3), "plain_capacity_hz": round(capacity, 3),
+                     "identity_checked": checked, "identity_same": same, "evicted_scenes": srv.evicted})
+    finally:
+        srv.close()
+    return summ
 
 
 def cpu_baseline(pos, sh, dirs, rate):

@@ -1,0 +1,89 @@
+"""GPU: the serving loop.  Requests of mixed kinds and sizes overlap on the
+device through several slots; each result must be the same as the request
+run alone afterwards (bit-identical blocks and colours), the HBM budget must
+hold requests back or reject them without crashing, and the deadline
+watchdog must drop requests that wait too long."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2607_14513_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+POOL = 200_000
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pool():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    pos, sh = synth.make_scene_device(POOL, seed=5, device="cuda")
+    torch.cuda.synchronize()
+    return pos, sh
+
+
+def _reqs(serve, count, rate, seed, n_hi=60_000, v_hi=96):
+    return serve.make_requests(count, rate, seed=seed, n_lo=1_000, n_hi=n_hi, v_lo=1, v_hi=v_hi, pool_n=POOL)
+
+
+def test_mix_equals_alone(pool):
+    from paper_2607_14513_amd import serve
+    reqs = _reqs(serve, 40, 3000.0, seed=21)
+    srv = serve.Server(*pool, slots=3, hbm_budget=4e9)
+    try:
+        say("serve mix", len(reqs))
+        done = srv.run(reqs)
+        assert len(done) == len(reqs)
+        assert all(r.error is None for r in done), [r.error for r in done if r.error]
+        assert srv.inflight == 0
+        kinds = {r.kind for r in done}
+        assert kinds == {serve.ENCODE, serve.DECODE}
+        overlapped = sum(1 for a in done for b in done
+                         if a.rid < b.rid and a.started < b.done and b.started < a.done)
+        say("overlapping pairs", overlapped)
+        for r in sorted(done, key=lambda r: r.rid):
+            alone = srv.run_alone(r)
+            assert alone == r.fingerprint, (r.rid, r.kind, r.n, r.v)
+    finally:
+        srv.close()
+
+
+def test_budget_admission_and_eviction(pool):
+    from paper_2607_14513_amd import serve
+    reqs = _reqs(serve, 24, 5000.0, seed=22, n_hi=40_000, v_hi=16)
+    # one oversized decode (needs more than the whole budget) among them
+    reqs.append(serve.Request(len(reqs), serve.DECODE, reqs[-1].arrival + 1e-3, v=4000))
+    budget = 8e6        # an encode needs up to ~6 MB: resident scenes must be evicted
+    srv = serve.Server(*pool, slots=2, hbm_budget=budget)
+    try:
+        done = srv.run(reqs)
+        assert len(done) == len(reqs)
+        errs = [r for r in done if r.error]
+        assert any("budget" in r.error for r in errs)
+        assert all(r.error is None for r in done if r.kind == serve.ENCODE)
+        assert srv.inflight == 0
+        assert srv.resident_bytes() <= budget
+        assert srv.evicted > 0
+    finally:
+        srv.close()
+
+
+def test_deadline_watchdog(pool):
+    from paper_2607_14513_amd import serve
+    reqs = _reqs(serve, 12, 1e6, seed=23, n_hi=40_000)
+    srv = serve.Server(*pool, slots=1, hbm_budget=4e9)
+    try:
+        done = srv.run(reqs, deadline_s=0.002)
+        assert len(done) == len(reqs)
+        dropped = [r for r in done if r.error and "deadline" in r.error]
+        assert dropped
+        assert any(r.error is None for r in done)
+        assert srv.inflight == 0
+    finally:
+        srv.close()
