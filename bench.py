@@ -188,6 +188,21 @@ def main():
                 ts.append(e0.elapsed_time(e1) * 1e-3)
             rates[name] = 16 * nblk / float(np.mean(ts)) / 1e6
 
+        # ---- per-band PSNR of the decoded coefficient texels (sorted order and
+        # the input order), 10 log10(255^2 / MSE) over all RGB texels
+        def band_psnr(texd, fmt):
+            b, dd, _ = ctx.encode(texd, d7, fmt=fmt, blocks=blocks)
+            dec = ctx.decode(b, dd)
+            diff = dec[..., :3].to(torch.int32) - texd[..., :3].to(torch.int32)
+            mse = (diff * diff).sum(dim=(1, 2, 3)).double().cpu().numpy() / (dd.n_pad * 3)
+            return [round(float(10 * np.log10(255.0 ** 2 / m)), 2) if m > 0 else None for m in mse]
+
+        _, tex_id, d_id = ctx.reorder(pos_d, sh_d, params=gsbc.default_params(order=1))
+        psnr = {"bc1_sorted": band_psnr(tex, gsbc.FMT_BC1), "bc7_sorted": band_psnr(tex, gsbc.FMT_BC7),
+                "bc1_input_order": band_psnr(tex_id, gsbc.FMT_BC1),
+                "bc7_input_order": band_psnr(tex_id, gsbc.FMT_BC7)}
+        del tex_id
+
         # ---- decode_eval on the 3,145,728-primitive scene at 1,024 directions
         roof_de = None
         if not args.no_large:
@@ -247,6 +262,7 @@ def main():
                       "decode_eval": round(float(stage[:, 2].mean()), 3)},
         "bc7_encode_mblocks_s": round(rates["bc7"], 3),
         "bc1_encode_mblocks_s": round(rates["bc1"], 3),
+        "psnr_db_per_band": psnr,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "roofline": roof,
         "roofline_decode_eval": roof_de,

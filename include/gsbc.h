@@ -52,7 +52,8 @@ enum {
     GSBC_E_NOMEM = -3,       /* scratch allocation failed */
     GSBC_E_INFEASIBLE = -4,  /* the rate target cannot be met exactly */
     GSBC_E_DEVICE = -5,      /* a HIP call or kernel failed */
-    GSBC_E_BUFFER = -6       /* a caller buffer is too small (see gsbc_query_sizes) */
+    GSBC_E_BUFFER = -6,      /* a caller buffer is too small (see gsbc_query_sizes) */
+    GSBC_E_IO = -7           /* a container file cannot be read or written, or is malformed */
 };
 
 enum { GSBC_FMT_AUTO = 0, GSBC_FMT_BC1 = 1, GSBC_FMT_BANDS = 2, GSBC_FMT_BC7 = 7 };
@@ -63,6 +64,9 @@ typedef struct {
     uint32_t grid_bits;      /* spatial chunk grid: 2^g cells per axis, 0..10 (default 3) */
     uint32_t refine_steps;   /* BC1 endpoint refinement steps, 0..8 (default 2) */
     uint32_t bc7_mode_mask;  /* BC7 modes searched, bit m = mode m, nonzero (default 0xFF) */
+    uint32_t order;          /* gsbc_reorder: 0 = sort by (spatial cell, colour) (default);
+                                1 = keep the input order (perm[s] = s), the unsorted
+                                baseline the paper compares sorting against (Sec. III-C) */
 } gsbc_params;
 
 /* Header of a coded scene: one bitstream per SH band (Sec. IV-A: typed
@@ -95,7 +99,7 @@ GSBC_API const char *gsbc_last_error(const gsbc_ctx *ctx);
 /* Wait for all work enqueued by this context. */
 GSBC_API gsbc_status gsbc_sync(gsbc_ctx *ctx);
 
-/* Fill `p` (host) with the defaults: grid_bits 3, refine_steps 2, mode mask 0xFF. */
+/* Fill `p` (host) with the defaults: grid_bits 3, refine_steps 2, mode mask 0xFF, order 0. */
 GSBC_API void gsbc_default_params(gsbc_params *p);
 
 /* Sizes in bytes for N primitives and V directions (any output may be NULL):
@@ -222,6 +226,29 @@ GSBC_API gsbc_status gsbc_decode(gsbc_ctx *ctx, const uint8_t *blocks, const gsb
 GSBC_API gsbc_status gsbc_decode_eval(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_desc *desc,
                              const float *dirs, uint32_t n_dirs, const uint32_t *prim_idx,
                              uint64_t m, float *out);
+
+/* ---------------------------------------------------------------- container */
+
+/* The durable form of a coded scene: fixed-size blocks in one bitstream per
+ * band, found by index times block size (Sec. I; Sec. IV-A typed streams).
+ * Little-endian file layout:
+ *   bytes 0..63     header: "GSBC" magic, u32 version (1), u64 n_prims,
+ *                   u64 n_pad, u64 blocks_per_band, u64 payload_bytes,
+ *                   u32 record bytes (24), zero padding to 64
+ *   16 x 24 bytes   band records: u32 format, u32 0, u64 offset, f32 vmin,
+ *                   f32 vmax
+ *   payload         payload_bytes bytes, band k at offset[k]
+ * gsbc_save copies the payload from the device (waits for the stream) and
+ * writes the file.  gsbc_load reads and checks it (GSBC_E_IO if the magic,
+ * version, record size, sizes or stream layout are wrong, or the file is
+ * short), fills *desc, and when `blocks` (device) is non-NULL copies the
+ * payload there (GSBC_E_BUFFER if blocks_capacity < payload_bytes; waits
+ * for the stream).  With blocks == NULL, ctx may be NULL: only the header
+ * is read. */
+GSBC_API gsbc_status gsbc_save(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_desc *desc,
+                               const char *path);
+GSBC_API gsbc_status gsbc_load(gsbc_ctx *ctx, const char *path, gsbc_stream_desc *desc, uint8_t *blocks,
+                               uint64_t blocks_capacity);
 
 /* ---------------------------------------------------------------- tracing */
 

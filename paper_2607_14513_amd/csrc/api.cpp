@@ -143,6 +143,7 @@ gsbc_status check_params(gsbc_ctx *ctx, const gsbc_params &p)
     if (p.grid_bits > 10) return fail(ctx, GSBC_E_ARG, "grid_bits %u > 10", p.grid_bits);
     if (p.refine_steps > 8) return fail(ctx, GSBC_E_ARG, "refine_steps %u > 8", p.refine_steps);
     if (p.bc7_mode_mask == 0 || p.bc7_mode_mask > 0xFF) return fail(ctx, GSBC_E_ARG, "bc7_mode_mask 0x%x not in 1..0xFF", p.bc7_mode_mask);
+    if (p.order > 1) return fail(ctx, GSBC_E_ARG, "order %u is not 0 (sorted) or 1 (identity)", p.order);
     return GSBC_OK;
 }
 
@@ -262,6 +263,7 @@ void gsbc_default_params(gsbc_params *p)
     p->grid_bits = 3;
     p->refine_steps = 2;
     p->bc7_mode_mask = 0xFF;
+    p->order = 0;
 }
 
 gsbc_status gsbc_create(gsbc_ctx **out, int device, void *hip_stream)
@@ -354,7 +356,8 @@ gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, uint6
     if ((s = check_params(ctx, p))) return s;
     if ((s = ensure_arena(ctx, reorder_scratch_bytes(n, p.grid_bits)))) return s;
     RangeRec *range = reinterpret_cast<RangeRec *>(small_ptr(ctx, kRangeOff));
-    HIP_TRY(ctx, launch_reorder(pos, sh, n, p.grid_bits, perm, textures, ctx->arena, range, ctx->stream), "reorder launch");
+    HIP_TRY(ctx, launch_reorder(pos, sh, n, p.grid_bits, p.order == 1, perm, textures, ctx->arena, range, ctx->stream),
+            "reorder launch");
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, range, sizeof(RangeRec), hipMemcpyDeviceToHost, ctx->stream), "range read-back");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "reorder");
     const RangeRec *r = static_cast<const RangeRec *>(ctx->pinned);
@@ -662,6 +665,108 @@ gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *c
         HIP_TRY(ctx, hipMemcpy(h.data(), ctx->plan_sse, h.size() * 8, hipMemcpyDeviceToHost), "sse read-back");
         for (size_t q = 0; q < h.size(); q++) band_sse[q] = (int64_t)h[q];
     }
+    return GSBC_OK;
+}
+
+// ---- container files
+namespace {
+constexpr uint32_t kContainerVersion = 1;
+constexpr uint32_t kRecordBytes = 24;
+
+struct FileCloser {
+    FILE *f;
+    ~FileCloser() { if (f) fclose(f); }
+};
+
+void put32(uint8_t *p, uint32_t v) { memcpy(p, &v, 4); }
+void put64(uint8_t *p, uint64_t v) { memcpy(p, &v, 8); }
+uint32_t get32(const uint8_t *p) { uint32_t v; memcpy(&v, p, 4); return v; }
+uint64_t get64(const uint8_t *p) { uint64_t v; memcpy(&v, p, 8); return v; }
+}  // namespace
+
+gsbc_status gsbc_save(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_desc *desc, const char *path)
+{
+    gsbc_status s = begin(ctx);
+    if (s) return s;
+    ActiveGuard guard(ctx);
+    if (!blocks || !desc || !path) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
+    if ((s = check_stream(ctx, desc))) return s;
+    std::vector<uint8_t> buf(64 + 16 * kRecordBytes + desc->payload_bytes, 0);
+    memcpy(buf.data(), "GSBC", 4);
+    put32(&buf[4], kContainerVersion);
+    put64(&buf[8], desc->n_prims);
+    put64(&buf[16], desc->n_pad);
+    put64(&buf[24], desc->blocks_per_band);
+    put64(&buf[32], desc->payload_bytes);
+    put32(&buf[40], kRecordBytes);
+    for (int k = 0; k < 16; k++) {
+        uint8_t *r = &buf[64 + k * kRecordBytes];
+        put32(r, desc->format[k]);
+        put64(r + 8, desc->offset[k]);
+        memcpy(r + 16, &desc->vmin[k], 4);
+        memcpy(r + 20, &desc->vmax[k], 4);
+    }
+    HIP_TRY(ctx, hipMemcpyAsync(&buf[64 + 16 * kRecordBytes], blocks, desc->payload_bytes, hipMemcpyDeviceToHost,
+                                ctx->stream), "payload read-back");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "save");
+    FileCloser fc{fopen(path, "wb")};
+    if (!fc.f) return fail(ctx, GSBC_E_IO, "cannot open %s for writing", path);
+    if (fwrite(buf.data(), 1, buf.size(), fc.f) != buf.size() || fflush(fc.f) != 0)
+        return fail(ctx, GSBC_E_IO, "short write to %s", path);
+    return GSBC_OK;
+}
+
+gsbc_status gsbc_load(gsbc_ctx *ctx, const char *path, gsbc_stream_desc *desc, uint8_t *blocks, uint64_t blocks_capacity)
+{
+    if (blocks) {
+        gsbc_status s = begin(ctx);
+        if (s) return s;
+    } else if (ctx) {
+        ctx->err[0] = 0;
+    }
+    if (!path || !desc) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
+    FileCloser fc{fopen(path, "rb")};
+    if (!fc.f) return fail(ctx, GSBC_E_IO, "cannot open %s", path);
+    uint8_t head[64 + 16 * kRecordBytes];
+    if (fread(head, 1, sizeof head, fc.f) != sizeof head) return fail(ctx, GSBC_E_IO, "%s: short header", path);
+    if (memcmp(head, "GSBC", 4) != 0) return fail(ctx, GSBC_E_IO, "%s: not a container (bad magic)", path);
+    if (get32(&head[4]) != kContainerVersion) return fail(ctx, GSBC_E_IO, "%s: version %u not supported", path, get32(&head[4]));
+    if (get32(&head[40]) != kRecordBytes) return fail(ctx, GSBC_E_IO, "%s: record size %u", path, get32(&head[40]));
+    gsbc_stream_desc d;
+    memset(&d, 0, sizeof d);
+    d.n_prims = get64(&head[8]);
+    d.n_pad = get64(&head[16]);
+    d.blocks_per_band = get64(&head[24]);
+    d.payload_bytes = get64(&head[32]);
+    for (int k = 0; k < 16; k++) {
+        const uint8_t *r = &head[64 + k * kRecordBytes];
+        const uint32_t f = get32(r);
+        d.format[k] = (uint8_t)(f <= 255 ? f : 0);
+        d.offset[k] = get64(r + 8);
+        memcpy(&d.vmin[k], r + 16, 4);
+        memcpy(&d.vmax[k], r + 20, 4);
+    }
+    gsbc_ctx scratch_ctx;
+    if (check_stream(ctx ? ctx : &scratch_ctx, &d) != GSBC_OK)
+        return fail(ctx, GSBC_E_IO, "%s: inconsistent header (%s)", path, ctx ? ctx->err : scratch_ctx.err);
+    // the file holds exactly the header, the records and the payload
+    if (fseek(fc.f, 0, SEEK_END) != 0) return fail(ctx, GSBC_E_IO, "%s: cannot seek", path);
+    const long size = ftell(fc.f);
+    if (size < 0 || (uint64_t)size != sizeof head + d.payload_bytes)
+        return fail(ctx, GSBC_E_IO, "%s: %ld bytes, expected %llu", path, size,
+                    (unsigned long long)(sizeof head + d.payload_bytes));
+    if (fseek(fc.f, (long)sizeof head, SEEK_SET) != 0) return fail(ctx, GSBC_E_IO, "%s: cannot seek", path);
+    if (blocks) {
+        if (blocks_capacity < d.payload_bytes)
+            return fail(ctx, GSBC_E_BUFFER, "blocks_capacity %llu < payload %llu bytes", (unsigned long long)blocks_capacity,
+                        (unsigned long long)d.payload_bytes);
+        std::vector<uint8_t> buf(d.payload_bytes);
+        if (fread(buf.data(), 1, buf.size(), fc.f) != buf.size()) return fail(ctx, GSBC_E_IO, "%s: short payload", path);
+        ActiveGuard guard(ctx);
+        HIP_TRY(ctx, hipMemcpyAsync(blocks, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream), "payload upload");
+        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "load");
+    }
+    *desc = d;
     return GSBC_OK;
 }
 

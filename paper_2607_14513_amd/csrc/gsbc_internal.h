@@ -68,7 +68,8 @@ struct RangeRec {
 
 // ---- reorder (reorder.hip)
 size_t reorder_scratch_bytes(uint64_t n, uint32_t grid_bits);
-hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_t grid_bits,
+// identity: keep the input order (perm[s] = s) instead of sorting.
+hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_t grid_bits, bool identity,
                           uint32_t *perm, uint8_t *textures, void *scratch, RangeRec *range_dev,
                           hipStream_t st);
 

@@ -305,7 +305,14 @@ Layout layout(uint64_t n)
 
 size_t reorder_scratch_bytes(uint64_t n, uint32_t) { return layout(n).bytes; }
 
-hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_t grid_bits,
+// perm[s] = s (the unsorted order).
+__global__ void k_iota(uint32_t *perm, uint64_t n)
+{
+    const uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (s < n) perm[s] = (uint32_t)s;
+}
+
+hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_t grid_bits, bool identity,
                           uint32_t *perm, uint8_t *textures, void *scratch, RangeRec *range_dev,
                           hipStream_t st)
 {
@@ -322,6 +329,13 @@ hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_
     GSBC_LAUNCH("range_partial", k_range_partial, dim3(nb), dim3(kRangeBlock), 0, st,
                        reinterpret_cast<const float4 *>(sh), pos, n, acc);
     GSBC_LAUNCH("range_final", k_range_final, dim3(1), dim3(64), 0, st, acc, grid_bits, range_dev);
+    if (identity) {
+        GSBC_LAUNCH("iota", k_iota, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, perm, n);
+        const uint64_t nblk = (n + 15) / 16;
+        GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((nblk * 16 + 255) / 256)), dim3(256), 0, st,
+                    sh, perm, n, nblk, range_dev, reinterpret_cast<uint32_t *>(textures));
+        return hipGetLastError();
+    }
     GSBC_LAUNCH("keys", k_keys, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, pos, sh, n,
                        grid_bits, range_dev, ka, va);
 

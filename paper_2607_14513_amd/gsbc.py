@@ -14,13 +14,13 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsbc.so")
 
-OK, E_ARG, E_UNSUPPORTED, E_NOMEM, E_INFEASIBLE, E_DEVICE, E_BUFFER = 0, -1, -2, -3, -4, -5, -6
+OK, E_ARG, E_UNSUPPORTED, E_NOMEM, E_INFEASIBLE, E_DEVICE, E_BUFFER, E_IO = 0, -1, -2, -3, -4, -5, -6, -7
 FMT_AUTO, FMT_BC1, FMT_BANDS, FMT_BC7 = 0, 1, 2, 7
 
 EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_default_params",
             "gsbc_query_sizes", "gsbc_reorder", "gsbc_encode", "gsbc_default_batch_tuning",
-            "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_profile_enable",
-            "gsbc_profile_read")
+            "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_save", "gsbc_load",
+            "gsbc_profile_enable", "gsbc_profile_read")
 
 
 class GsbcError(RuntimeError):
@@ -31,7 +31,7 @@ class GsbcError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("grid_bits", ctypes.c_uint32), ("refine_steps", ctypes.c_uint32),
-                ("bc7_mode_mask", ctypes.c_uint32)]
+                ("bc7_mode_mask", ctypes.c_uint32), ("order", ctypes.c_uint32)]
 
 
 class BatchTuning(ctypes.Structure):
@@ -92,6 +92,8 @@ def load():
                                           ctypes.POINTER(BatchTuning), P]
         lib.gsbc_decode.argtypes = [P, P, ctypes.POINTER(StreamDesc), P]
         lib.gsbc_decode_eval.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, u32, P, u64, P]
+        lib.gsbc_save.argtypes = [P, P, ctypes.POINTER(StreamDesc), ctypes.c_char_p]
+        lib.gsbc_load.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(StreamDesc), P, u64]
         lib.gsbc_profile_enable.argtypes = [P, ctypes.c_int]
         lib.gsbc_profile_read.argtypes = [P, u32, P, P, P, ctypes.POINTER(u32)]
         for name in EXPORTED:
@@ -123,6 +125,15 @@ def query_sizes(n, n_dirs=0):
     if st != OK:
         raise GsbcError(st, "query_sizes")
     return t.value, b.value, o.value
+
+
+def load_header(path):
+    """StreamDesc of a container file (host only, no device needed)."""
+    d = StreamDesc()
+    st = load().gsbc_load(None, os.fsencode(path), ctypes.byref(d), None, 0)
+    if st != OK:
+        raise GsbcError(st, f"cannot read container {path}")
+    return d
 
 
 def _ptr(t):
@@ -254,6 +265,18 @@ class Context:
                                              ctypes.c_void_p(sse.ctypes.data) if sse is not None else None))
         out = [darr[i].copy() for i in range(n)]
         return out, (sse.reshape(n, 16) if sse is not None else None)
+
+    def save(self, path, blocks, desc):
+        """Write the coded scene (device blocks + desc) as a container file."""
+        _dev_tensor(blocks, torch.uint8, "blocks")
+        self._check(load().gsbc_save(self._h, _ptr(blocks), ctypes.byref(desc), os.fsencode(path)))
+
+    def load(self, path):
+        """Read a container file -> (device blocks tensor, desc)."""
+        d = load_header(path)
+        blocks = torch.empty(d.payload_bytes, dtype=torch.uint8, device=self.device)
+        self._check(load().gsbc_load(self._h, os.fsencode(path), ctypes.byref(d), _ptr(blocks), blocks.numel()))
+        return blocks, d
 
     def decode(self, blocks, desc, out=None):
         if out is None:

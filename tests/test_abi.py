@@ -54,3 +54,48 @@ def test_create_without_a_device_fails_cleanly():
     assert not h.value
     with pytest.raises(RuntimeError):
         gsbc.Context(0)
+
+
+def _container(path, n=37, fmts=None, magic=b"GSBC", version=1, truncate=0, offset_bump=0):
+    """A container file written from the layout the header documents."""
+    import struct
+    nblk = (n + 15) // 16
+    fmts = fmts or [7] + [1] * 15
+    offs, pos = [], 0
+    for f in fmts:
+        offs.append(pos)
+        pos = (pos + nblk * (16 if f == 7 else 8) + 15) // 16 * 16
+    head = magic + struct.pack("<IQQQQI", version, n, nblk * 16, nblk, pos, 24)
+    head += b"\0" * (64 - len(head))
+    recs = b"".join(struct.pack("<IIQff", f, 0, o + (offset_bump if k == 5 else 0), -0.5 - k, 0.25 * k)
+                    for k, (f, o) in enumerate(zip(fmts, offs)))
+    payload = bytes(range(256)) * (pos // 256 + 1)
+    data = (head + recs + payload[:pos])
+    with open(path, "wb") as f:
+        f.write(data[:len(data) - truncate] if truncate else data)
+    return nblk, offs, pos
+
+
+def test_container_header_host_only(tmp_path):
+    from paper_2607_14513_amd import gsbc
+    p = str(tmp_path / "scene.gsbc")
+    nblk, offs, pos = _container(p)
+    d = gsbc.load_header(p)
+    assert (d.n_prims, d.n_pad, d.blocks_per_band, d.payload_bytes) == (37, nblk * 16, nblk, pos)
+    assert list(d.formats()) == [7] + [1] * 15
+    assert list(d.offsets()) == offs
+    vmin, vmax = d.ranges()
+    assert vmin[3] == -3.5 and vmax[3] == 0.75
+
+
+@pytest.mark.parametrize("bad", ["magic", "version", "layout", "truncated", "missing"])
+def test_container_rejects_malformed(tmp_path, bad):
+    from paper_2607_14513_amd import gsbc
+    p = str(tmp_path / "bad.gsbc")
+    kw = {"magic": dict(magic=b"GSBX"), "version": dict(version=2), "layout": dict(offset_bump=16),
+          "truncated": dict(truncate=500), "missing": None}[bad]
+    if kw is not None:
+        _container(p, **kw)
+    with pytest.raises(gsbc.GsbcError) as e:
+        gsbc.load_header(p)
+    assert e.value.status == gsbc.E_IO

@@ -117,6 +117,23 @@ def test_reorder_degenerate_inputs(G):
     assert np.array_equal(d.ranges()[0].view(np.uint32), rvmin.view(np.uint32))
 
 
+@pytest.mark.parametrize("n,seed", [(1, 8), (17, 9), (4101, 10)])
+def test_reorder_identity_order(G, n, seed):
+    """order = 1: no sort, perm[s] = s; textures are the quantised input in
+    its own order."""
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(n, seed=seed)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh), params=gsbc.default_params(order=1))
+    vmin, vmax = O.band_range(sh)
+    ident = np.arange(n, dtype=np.uint32)
+    assert np.array_equal(host(perm).view(np.uint32), ident)
+    assert np.array_equal(host(tex), O.pack(O.quantise(sh, vmin, vmax), ident))
+    assert np.array_equal(d.ranges()[0], vmin) and np.array_equal(d.ranges()[1], vmax)
+    with pytest.raises(gsbc.GsbcError) as e:
+        ctx.reorder(dev(pos), dev(sh), params=gsbc.default_params(order=2))
+    assert e.value.status == gsbc.E_ARG
+
+
 def test_reorder_full_size(G):
     """1,048,576 primitives: permutation, ranges and textures bit-exact."""
     gsbc, ctx = G
@@ -264,6 +281,24 @@ def test_rate_auto_bit_exact(G, rate):
     nblk = rtex.shape[1]
     block_bits = sum(nblk * (64 if f == 1 else 128) for f in fmt)
     assert block_bits == rate * 16 * (nblk * 16)
+
+
+def test_container_round_trip(G, tmp_path):
+    """save -> load gives the same payload and header, and decodes the same."""
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(5000 + 3, seed=33)
+    _, tex, d = ctx.reorder(dev(pos), dev(sh))
+    blocks, d2, _ = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=6.0)
+    path = str(tmp_path / "scene.gsbc")
+    ctx.save(path, blocks, d2)
+    b2, d3 = ctx.load(path)
+    assert bytes(d3) == bytes(d2)
+    assert np.array_equal(host(b2), host(blocks)[:d2.payload_bytes])
+    assert np.array_equal(host(ctx.decode(b2, d3)), host(ctx.decode(blocks, d2)))
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    st = gsbc.load().gsbc_load(ctx._h, path.encode(), gsbc.ctypes.byref(gsbc.StreamDesc()),
+                               gsbc.ctypes.c_void_p(small.data_ptr()), small.numel())
+    assert st == gsbc.E_BUFFER
 
 
 def test_rate_infeasible_and_errors(G):
