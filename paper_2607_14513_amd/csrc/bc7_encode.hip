@@ -138,42 +138,76 @@ __device__ __forceinline__ void unpack(uint32_t rg, int b, int (&x)[3])
 struct Prep {
     bool same;
     int lo[3], hi[3];
+    int Sx[3];   // member sums per channel (for the least-squares refit)
 };
 
-__device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int rot)
+// Member sums of a subset: count, per-channel sums and the six distinct
+// products (RR, RG, RB, GG, GB, BB).  Integer, so the sums of disjoint
+// subsets add up exactly: the last subset of a partition is the block total
+// minus the others.
+struct Sums {
+    int n;
+    int Sx[3];
+    int XX[6];
+};
+
+__device__ __forceinline__ Sums subset_sums(const TexLds &S, uint32_t mask, int rot)
 {
-    Prep P;
-    const int first = __ffs(mask) - 1;
-    uint32_t rg0;
-    int b0;
-    texel(S, first, rot, rg0, b0);
-    bool same = true;
-    int Sx[3] = {0, 0, 0}, XX[6] = {0, 0, 0, 0, 0, 0};
-    for (uint32_t m = mask; m; m &= m - 1) {
+    Sums m;
+    m.n = __popc(mask);
+    m.Sx[0] = m.Sx[1] = m.Sx[2] = 0;
+#pragma unroll
+    for (int q = 0; q < 6; q++) m.XX[q] = 0;
+    for (uint32_t mm = mask; mm; mm &= mm - 1) {
         uint32_t rg;
         int b;
-        texel(S, __ffs(m) - 1, rot, rg, b);
-        same &= (rg == rg0) && (b == b0);
+        texel(S, __ffs(mm) - 1, rot, rg, b);
         int x[3];
         unpack(rg, b, x);
-        Sx[0] += x[0]; Sx[1] += x[1]; Sx[2] += x[2];
-        XX[0] += x[0] * x[0]; XX[1] += x[0] * x[1]; XX[2] += x[0] * x[2];
-        XX[3] += x[1] * x[1]; XX[4] += x[1] * x[2]; XX[5] += x[2] * x[2];
+        m.Sx[0] += x[0]; m.Sx[1] += x[1]; m.Sx[2] += x[2];
+        m.XX[0] += x[0] * x[0]; m.XX[1] += x[0] * x[1]; m.XX[2] += x[0] * x[2];
+        m.XX[3] += x[1] * x[1]; m.XX[4] += x[1] * x[2]; m.XX[5] += x[2] * x[2];
     }
-    P.same = same;
-    unpack(rg0, b0, P.lo);
-    P.hi[0] = P.lo[0]; P.hi[1] = P.lo[1]; P.hi[2] = P.lo[2];
-    if (same) return P;
-    // principal axis: integer power iteration on the exact covariance
+    return m;
+}
+
+__device__ __forceinline__ Sums sums_minus(const Sums &t, const Sums &a)
+{
+    Sums m;
+    m.n = t.n - a.n;
+#pragma unroll
+    for (int c = 0; c < 3; c++) m.Sx[c] = t.Sx[c] - a.Sx[c];
+#pragma unroll
+    for (int q = 0; q < 6; q++) m.XX[q] = t.XX[q] - a.XX[q];
+    return m;
+}
+
+// Principal axis and endpoint texels of a subset from its sums.  The exact
+// covariance C = n XX - Sx Sx^T is zero exactly when every member has the
+// same colour.
+__device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int rot, const Sums &m)
+{
+    Prep P;
     // n <= 16, XX < 2^21 and Sx < 2^12: 24-bit multiplies with exact products
-    const int n = __popc(mask);
+    const int n = m.n;
     int C[3][3];
-    C[0][0] = __mul24(n, XX[0]) - __mul24(Sx[0], Sx[0]);
-    C[0][1] = C[1][0] = __mul24(n, XX[1]) - __mul24(Sx[0], Sx[1]);
-    C[0][2] = C[2][0] = __mul24(n, XX[2]) - __mul24(Sx[0], Sx[2]);
-    C[1][1] = __mul24(n, XX[3]) - __mul24(Sx[1], Sx[1]);
-    C[1][2] = C[2][1] = __mul24(n, XX[4]) - __mul24(Sx[1], Sx[2]);
-    C[2][2] = __mul24(n, XX[5]) - __mul24(Sx[2], Sx[2]);
+    C[0][0] = __mul24(n, m.XX[0]) - __mul24(m.Sx[0], m.Sx[0]);
+    C[0][1] = C[1][0] = __mul24(n, m.XX[1]) - __mul24(m.Sx[0], m.Sx[1]);
+    C[0][2] = C[2][0] = __mul24(n, m.XX[2]) - __mul24(m.Sx[0], m.Sx[2]);
+    C[1][1] = __mul24(n, m.XX[3]) - __mul24(m.Sx[1], m.Sx[1]);
+    C[1][2] = C[2][1] = __mul24(n, m.XX[4]) - __mul24(m.Sx[1], m.Sx[2]);
+    C[2][2] = __mul24(n, m.XX[5]) - __mul24(m.Sx[2], m.Sx[2]);
+    P.same = (C[0][0] | C[1][1] | C[2][2]) == 0;
+    P.Sx[0] = m.Sx[0]; P.Sx[1] = m.Sx[1]; P.Sx[2] = m.Sx[2];
+    if (P.same) {
+        uint32_t rg;
+        int b;
+        texel(S, __ffs(mask) - 1, rot, rg, b);
+        unpack(rg, b, P.lo);
+        P.hi[0] = P.lo[0]; P.hi[1] = P.lo[1]; P.hi[2] = P.lo[2];
+        return P;
+    }
+    // principal axis: integer power iteration on the exact covariance
     // row of the largest diagonal entry (lowest index on ties), by selects
     const int j = (C[1][1] > C[0][0]) ? ((C[2][2] > C[1][1]) ? 2 : 1) : ((C[2][2] > C[0][0]) ? 2 : 0);
     const int tsh = max(0, bitlen(j == 0 ? C[0][0] : (j == 1 ? C[1][1] : C[2][2])) - 14);
@@ -207,20 +241,33 @@ __device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int 
         for (int a = 0; a < 3; a++) v[a] = u[a] >> sh;
     }
     if (v[0] == 0 && v[1] == 0 && v[2] == 0) v[0] = v[1] = v[2] = 1;
-    int plo = 0, phi = 0;
-    bool any = false;
-    for (uint32_t m = mask; m; m &= m - 1) {
+    // members of least and greatest projection, the first of each on ties:
+    // keys 16 p + i and 16 p + 15 - i (|16 p| < 2^29), from the 16x-scaled
+    // packed texels in two operations
+    const short2_t v01 = {(short)v[0], (short)v[1]};
+    const int v2x16 = 16 * v[2];
+    int klo = 0x7FFFFFFF, khi = (int)0x80000000;
+    for (uint32_t mm = mask; mm; mm &= mm - 1) {
+        const int i = __ffs(mm) - 1;
         uint32_t rg;
         int b;
-        texel(S, __ffs(m) - 1, rot, rg, b);
-        int x[3];
-        unpack(rg, b, x);
-        int p = v[0] * x[0] + v[1] * x[1] + v[2] * x[2];
-        if (!any || p < plo) { plo = p; P.lo[0] = x[0]; P.lo[1] = x[1]; P.lo[2] = x[2]; }
-        if (!any || p > phi) { phi = p; P.hi[0] = x[0]; P.hi[1] = x[1]; P.hi[2] = x[2]; }
-        any = true;
+        texel(S, i, rot, rg, b);
+        const int p16 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg), v01, __mul24(b, v2x16), false);
+        klo = min(klo, p16 + i);
+        khi = max(khi, p16 + (15 - i));
     }
+    uint32_t rg;
+    int b;
+    texel(S, klo & 15, rot, rg, b);
+    unpack(rg, b, P.lo);
+    texel(S, 15 - (khi & 15), rot, rg, b);
+    unpack(rg, b, P.hi);
     return P;
+}
+
+__device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int rot)
+{
+    return prep_subset(S, mask, rot, subset_sums(S, mask, rot));
 }
 
 // Result of fitting one endpoint pair to a subset.  eval_pair leaves idx in
@@ -329,12 +376,34 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
     return best;
 }
 
-// (d) least-squares endpoints for the chosen indices; false if singular.
-template <int NB>
-__device__ __forceinline__ bool ls_endpoints(const TexLds &S, uint32_t mask, int rot, uint64_t idx, int (&lo)[3],
-                                             int (&hi)[3])
+// Index weight of NB-bit index k from the weight table packed in bytes
+// (v_perm_b32 picks byte k; selector 0x0C gives zero bytes).
+__host__ __device__ constexpr uint32_t pack_weights(int nb, int first)
 {
-    int A = 0, B = 0, AB = 0, SA[3] = {0, 0, 0}, SB[3] = {0, 0, 0};
+    return (uint32_t)bc7_weight(nb, first) | ((uint32_t)bc7_weight(nb, first + 1) << 8) |
+           ((uint32_t)bc7_weight(nb, first + 2) << 16) | ((uint32_t)bc7_weight(nb, first + 3) << 24);
+}
+static_assert(pack_weights(2, 0) == 0x402B1500u && pack_weights(3, 0) == 0x1B120900u &&
+              pack_weights(3, 4) == 0x40372E25u, "BC7 weight tables");
+
+template <int NB>
+__device__ __forceinline__ int weight_of(int k)
+{
+    if (NB == 2) return (int)__builtin_amdgcn_perm(0u, pack_weights(2, 0), (uint32_t)k | 0x0C0C0C00u);
+    if (NB == 3) return (int)__builtin_amdgcn_perm(pack_weights(3, 4), pack_weights(3, 0), (uint32_t)k | 0x0C0C0C00u);
+    return bc7_weight(NB, k);
+}
+
+// (d) least-squares endpoints for the chosen indices; false if singular.
+// With weights (64 - w, w) the normal-equation sums follow from the member
+// count n, sum(w), sum(w^2), the channel sums Sx and sum(w x):
+//   A = 4096 n - 128 sum(w) + sum(w^2), B = sum(w^2), AB = 64 sum(w) - sum(w^2),
+//   SA = 64 Sx - SB.
+template <int NB>
+__device__ __forceinline__ bool ls_endpoints(const TexLds &S, uint32_t mask, int rot, uint64_t idx, const int (&Sx)[3],
+                                             int (&lo)[3], int (&hi)[3])
+{
+    int W1 = 0, W2 = 0, SB[3] = {0, 0, 0};
     for (uint32_t m = mask; m; m &= m - 1) {
         const int i = __ffs(m) - 1;
         uint32_t rg;
@@ -342,13 +411,18 @@ __device__ __forceinline__ bool ls_endpoints(const TexLds &S, uint32_t mask, int
         texel(S, i, rot, rg, b);
         int x[3];
         unpack(rg, b, x);
-        const int k = (int)(idx & 15);   // member order
+        const int w = weight_of<NB>((int)(idx & 15));   // member order
         idx >>= 4;
-        const int w = bc7_weight(NB, k), a = 64 - w;
-        A += a * a; B += w * w; AB += a * w;
+        W1 += w;
+        W2 += w * w;
 #pragma unroll
-        for (int c = 0; c < 3; c++) { SA[c] += a * x[c]; SB[c] += w * x[c]; }
+        for (int c = 0; c < 3; c++) SB[c] += w * x[c];
     }
+    const int n = __popc(mask);
+    const int A = 4096 * n - 128 * W1 + W2, B = W2, AB = 64 * W1 - W2;
+    int SA[3];
+#pragma unroll
+    for (int c = 0; c < 3; c++) SA[c] = 64 * Sx[c] - SB[c];
     const double det = (double)A * (double)B - (double)AB * (double)AB;
     if (det == 0.0) return false;
 #pragma unroll
@@ -412,7 +486,7 @@ __device__ __forceinline__ PairFit fit_colour(const TexLds &S, uint32_t mask, in
     // (d) one least-squares refit kept only if strictly better
     PairFit f = eval_pair<CB, PB, NB>(S, mask, rot, P.lo, P.hi);
     int rlo[3], rhi[3];
-    if (ls_endpoints<NB>(S, mask, rot, f.idx, rlo, rhi)) {
+    if (ls_endpoints<NB>(S, mask, rot, f.idx, P.Sx, rlo, rhi)) {
         PairFit g = eval_pair<CB, PB, NB>(S, mask, rot, rlo, rhi);
         if (g.sse < f.sse) f = g;
     }
@@ -538,12 +612,14 @@ template <int GROUP>
 __device__ __forceinline__ uint32_t search_group(const TexLds &S, uint32_t mode_mask, const uint32_t *sv)
 {
     uint32_t best = 0xFFFFFFFFu;
+    const Sums tot = GROUP < 2 ? subset_sums(S, 0xFFFFu, 0) : Sums{};
     if (GROUP == 0) {
         // 2-subset partitions: modes 1, 3, 7
         if (mode_mask & 0x8A)
             for (int p = 0; p < 64; p++) {
                 const uint32_t m0 = mask2(p, 0), m1 = mask2(p, 1);
-                const Prep P0 = prep_subset(S, m0, 0), P1 = prep_subset(S, m1, 0);
+                const Sums s0 = subset_sums(S, m0, 0);
+                const Prep P0 = prep_subset(S, m0, 0, s0), P1 = prep_subset(S, m1, 0, sums_minus(tot, s0));
                 if (mode_mask & 0x02)
                     consider(fit_colour<6, 1, 3>(S, m0, 0, P0, sv).sse + fit_colour<6, 1, 3>(S, m1, 0, P1, sv).sse,
                              16 + p, best);
@@ -559,7 +635,9 @@ __device__ __forceinline__ uint32_t search_group(const TexLds &S, uint32_t mode_
         if (mode_mask & 0x05)
             for (int p = 0; p < ((mode_mask & 0x04) ? 64 : 16); p++) {
                 const uint32_t m0 = mask3(p, 0), m1 = mask3(p, 1), m2 = mask3(p, 2);
-                const Prep P0 = prep_subset(S, m0, 0), P1 = prep_subset(S, m1, 0), P2 = prep_subset(S, m2, 0);
+                const Sums s0 = subset_sums(S, m0, 0), s1 = subset_sums(S, m1, 0);
+                const Prep P0 = prep_subset(S, m0, 0, s0), P1 = prep_subset(S, m1, 0, s1);
+                const Prep P2 = prep_subset(S, m2, 0, sums_minus(sums_minus(tot, s0), s1));
                 if ((mode_mask & 0x01) && p < 16)
                     consider(fit_colour<4, 2, 3>(S, m0, 0, P0, sv).sse + fit_colour<4, 2, 3>(S, m1, 0, P1, sv).sse +
                                  fit_colour<4, 2, 3>(S, m2, 0, P2, sv).sse, p, best);
@@ -780,7 +858,7 @@ struct ItemLoop {
 // first and writes the word (all-ones for padding indices); the one holding
 // group 2 runs last and adds the final SSE (key >> 9) into the run's sum.
 template <int GMASK>
-__global__ __launch_bounds__(kWG) void k_bc7_search(Bc7Launch L)
+__global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_bc7_search(Bc7Launch L)
 {
     __shared__ TexLds S;
     __shared__ uint32_t s_item;
