@@ -56,17 +56,22 @@ typedef short short2_t __attribute__((ext_vector_type(2)));
 // on ties).  E is strictly increasing, so moving from c to c+1 helps exactly
 // when the midpoint (E(c) + E(c+1)) / 2 lies below t; the answer is the
 // number of such midpoints, a table lookup at h = ceil(y / det) clamped to
-// [0, 511] (every midpoint sum is an integer in [4, 506]).  The float
-// estimate of h is within one of the exact ceiling wherever |y / det| < 2^10
-// (reciprocal and product each within an ulp); two integer checks settle
-// it, and out-of-range values end clamped either way.
-__device__ __forceinline__ int quant_h(int y, int det, float inv)
+// [0, 511] (every midpoint sum is an integer in [4, 506]).
+// ceil(y / det) is taken as ceil(y * inv - 2^-24) in FP64: y / det is a
+// multiple of 1/det >= 1/5184 (determinants of the split lists lie in
+// [60, 5184]), so any value within 2^-24 below it has the same ceiling, and
+// with inv within 2^-44 of 1/det and |y| < 2^25 the FP64 error is below
+// 2^-28.
+__device__ __forceinline__ double recip(int det)
 {
-    int h = (int)__builtin_ceilf((float)y * inv);
-    h = min(max(h, 0), 512);
-    const int hd = mul_i24(h, det);   // <= 512 * 20736
-    h += hd < y ? 1 : 0;
-    h -= hd - det >= y ? 1 : 0;
+    const double d = (double)det;
+    const double x = (double)__builtin_amdgcn_rcpf((float)det);   // within 2^-22
+    return fma(fma(-d, x, 1.0), x, x);                           // one Newton step
+}
+
+__device__ __forceinline__ int quant_h(int y, double inv)
+{
+    const int h = (int)ceil(fma((double)y, inv, -0x1p-24));
     return min(max(h, 0), 511);
 }
 
@@ -153,7 +158,7 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
                 const int AB = FOUR ? 2 * (n1 + n2) : n1;
                 const int det = A * B - AB * AB;
                 if (det == 0) continue;
-                const float inv = __builtin_amdgcn_rcpf((float)det);
+                const double inv = recip(det);
                 int sse = Q;
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
@@ -163,8 +168,8 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
                     const int sam = FOUR ? a + bq + cq : a + bq;   // -2 SA
                     const int y0 = mul_i24(sam, -F * (B + AB)) + mul_i24(tot[c], -2 * F * F * AB);
                     const int y1 = mul_i24(sam, F * (A + AB)) + mul_i24(tot[c], 2 * F * F * A);
-                    const int e0 = L.val[wide][quant_h(y0, det, inv)];
-                    const int e1 = L.val[wide][quant_h(y1, det, inv)];
+                    const int e0 = L.val[wide][quant_h(y0, inv)];
+                    const int e1 = L.val[wide][quant_h(y1, inv)];
                     if (FOUR) {
                         // (2 e0 + e1 + 1) / 3 and (e0 + 2 e1 + 1) / 3 as (v * 43691) >> 17, exact for v < 2^17
                         const int p1 = (int)((mul_u24((uint32_t)(2 * e0 + e1), 43691u) + 43691u) >> 17);
@@ -200,7 +205,7 @@ __device__ __forceinline__ void split_codes(const Lds &L, int lane, const int (&
     const int B = four ? n1 + 4 * n2 + 9 * n3 : n1 + 4 * n2;
     const int AB = four ? 2 * (n1 + n2) : n1;
     const int det = A * B - AB * AB;
-    const float inv = __builtin_amdgcn_rcpf((float)det);
+    const double inv = recip(det);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         const int wide = c == 1;
@@ -209,8 +214,8 @@ __device__ __forceinline__ void split_codes(const Lds &L, int lane, const int (&
         const int sam = four ? a + bq + cq : a + bq;
         const int y0 = sam * (-F * (B + AB)) + tot[c] * (-2 * F * F * AB);
         const int y1 = sam * (F * (A + AB)) + tot[c] * (2 * F * F * A);
-        q0[c] = L.code[wide][quant_h(y0, det, inv)];
-        q1[c] = L.code[wide][quant_h(y1, det, inv)];
+        q0[c] = L.code[wide][quant_h(y0, inv)];
+        q1[c] = L.code[wide][quant_h(y1, inv)];
     }
 }
 
