@@ -349,9 +349,12 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
                 int kb = 0x7FFFFFFF;
 #pragma unroll
                 for (int k = 0; k < NE; k++) {
+                    // with a p-bit per endpoint, entry 0 depends only on p0 and
+                    // entry NE-1 only on p1: combinations share those keys
+                    const int js = (PB == 2 && CPV == 4) ? (k == 0 ? (j & 1) : k == NE - 1 ? (j & 2) : j) : j;
                     const int key = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg),
-                                                           __builtin_bit_cast(short2_t, prg[j][k]),
-                                                           __mul24(b, pb[j][k]) + pk[j][k], false);
+                                                           __builtin_bit_cast(short2_t, prg[js][k]),
+                                                           __mul24(b, pb[js][k]) + pk[js][k], false);
                     kb = min(kb, key);
                 }
                 acc[j] += (uint32_t)kb + (uint32_t)cx;   // 256 SSE + k of this member
@@ -425,18 +428,22 @@ __device__ __forceinline__ bool ls_endpoints(const TexLds &S, uint32_t mask, int
     for (int c = 0; c < 3; c++) SA[c] = 64 * Sx[c] - SB[c];
     const double det = (double)A * (double)B - (double)AB * (double)AB;
     if (det == 0.0) return false;
+    // 1/det in FP64 from the FP32 reciprocal and two Newton steps (within 2^-50)
+    double inv = (double)__builtin_amdgcn_rcpf((float)det);
+    inv = fma(fma(-det, inv, 1.0), inv, inv);
+    inv = fma(fma(-det, inv, 1.0), inv, inv);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        // Exact numerators (< 2^42).  The quotient is correctly rounded, so
-        // floor(q + 1/2) takes the same decision as floor(n/det + 1/2) on the
-        // exact rational whenever the result is in range (|n/det| <= 256):
-        // a half-integer quotient is exact, and any other one is at least
-        // 1/(2 det) > 1e-10 away from a half-integer.
-        double n0 = 64.0 * ((double)B * (double)SA[c] - (double)AB * (double)SB[c]);
-        double n1 = 64.0 * ((double)A * (double)SB[c] - (double)AB * (double)SA[c]);
-        double q0 = floor(n0 / det + 0.5), q1 = floor(n1 / det + 0.5);
-        lo[c] = q0 < 0.0 ? 0 : (q0 > 255.0 ? 255 : (int)q0);
-        hi[c] = q1 < 0.0 ? 0 : (q1 > 255.0 ? 255 : (int)q1);
+        // Exact numerators (< 2^42).  floor(n/det + 1/2) is taken as
+        // floor(n * inv + 1/2 + 2^-37): (2 n + det) / (2 det) is a multiple of
+        // 1/(2 det) >= 2^-33, and for |n/det| <= 512 the FP64 error is below
+        // 2^-40, so the margin never moves the floor; larger quotients clamp
+        // to 0 or 255 either way.
+        const double n0 = 64.0 * ((double)B * (double)SA[c] - (double)AB * (double)SB[c]);
+        const double n1 = 64.0 * ((double)A * (double)SB[c] - (double)AB * (double)SA[c]);
+        const double q0 = floor(fma(n0, inv, 0.5 + 0x1p-37)), q1 = floor(fma(n1, inv, 0.5 + 0x1p-37));
+        lo[c] = (int)fmin(fmax(q0, 0.0), 255.0);
+        hi[c] = (int)fmin(fmax(q1, 0.0), 255.0);
     }
     return true;
 }
