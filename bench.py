@@ -49,6 +49,8 @@ ALGO_OPS = {
     "bc7_search_3subset": (16_384 + 8_192) * OPS_PER_EVAL,     # modes 0, 2
     "bc7_search_1subset": (3_072 + 1_024 + 2_048) * OPS_PER_EVAL,  # modes 4, 5, 6
 }
+# one launch over every group (work items per group, or all groups per block)
+ALGO_OPS["bc7_search_items"] = ALGO_OPS["bc7_search_all"] = sum(ALGO_OPS.values())
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 

@@ -164,7 +164,9 @@ GSBC_API gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_st
  *   bc1_lanes    BC1 workgroup size: 64, 128 or 256
  *   bc7_split    BC7 candidate groups per search kernel: 0 = three kernels
  *                (2-subset, 3-subset, 1-subset modes), 1 = two (the 3- and
- *                1-subset modes together), 2 = one kernel
+ *                1-subset modes together), 2 = one kernel running all
+ *                groups per block, 3 = one kernel whose work items are
+ *                (group, rounds) pairs, heavy groups first
  *   concurrent   1: the BC1 blocks run on a second stream beside the BC7
  *                blocks; 0: after them on the context's stream */
 typedef struct {
@@ -175,7 +177,7 @@ typedef struct {
     uint32_t concurrent;
 } gsbc_batch_tuning;
 
-/* Defaults: item_rounds 1, wgs_per_cu 0, bc1_lanes 128, bc7_split 0,
+/* Defaults: item_rounds 1, wgs_per_cu 0, bc1_lanes 128, bc7_split 3,
  * concurrent 0 (the launch shapes of gsbc_encode). */
 GSBC_API void gsbc_default_batch_tuning(gsbc_batch_tuning *t);
 

@@ -26,7 +26,7 @@ SPACE = {
     "item_rounds": [1, 2, 4, 8],
     "wgs_per_cu": [0, 2, 4, 8, 12],
     "bc1_lanes": [64, 128, 256],
-    "bc7_split": [0, 1, 2],
+    "bc7_split": [0, 1, 2, 3],
     "concurrent": [0, 1],
 }
 

@@ -209,10 +209,11 @@ uint64_t layout(const uint32_t fmt[16], uint64_t nblk, uint64_t off[16])
 }
 
 // Default work split of the single-scene calls: one workgroup per 256-block
-// round, BC1 on 128-lane workgroups, three BC7 search kernels.
+// round, BC1 on 128-lane workgroups, one BC7 search launch whose work items
+// are (candidate group, round) pairs.
 constexpr WorkSplit kPlainSplit = {1, 0, nullptr};
 constexpr uint32_t kPlainBc1Lanes = 128;
-constexpr uint32_t kPlainBc7Split = 0;
+constexpr uint32_t kPlainBc7Split = 3;
 constexpr size_t kRunTableBytes = 16 * sizeof(BlockRun);   // one scene, one format
 constexpr size_t kRunStageOff = 2048;                        // in ctx->pinned
 
@@ -525,7 +526,7 @@ gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *c
     if (t.wgs_per_cu > 16) return fail(ctx, GSBC_E_ARG, "tuning.wgs_per_cu %u > 16", t.wgs_per_cu);
     if (t.bc1_lanes != 64 && t.bc1_lanes != 128 && t.bc1_lanes != 256)
         return fail(ctx, GSBC_E_ARG, "tuning.bc1_lanes %u is not 64, 128 or 256", t.bc1_lanes);
-    if (t.bc7_split > 2) return fail(ctx, GSBC_E_ARG, "tuning.bc7_split %u > 2", t.bc7_split);
+    if (t.bc7_split > 3) return fail(ctx, GSBC_E_ARG, "tuning.bc7_split %u > 3", t.bc7_split);
     if (t.concurrent > 1) return fail(ctx, GSBC_E_ARG, "tuning.concurrent %u > 1", t.concurrent);
     // validate every scene and lay out its streams (host only, nothing enqueued yet)
     std::vector<uint64_t> offs(16 * (size_t)n_scenes), pay(n_scenes);

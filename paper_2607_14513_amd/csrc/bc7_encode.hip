@@ -861,21 +861,27 @@ struct ItemLoop {
 
 // Pass 1: the best key of every block over the candidate groups in GMASK
 // (bit 0: 2-subset modes, bit 1: 3-subset modes, bit 2: 1-subset modes),
-// min-combined into the block's key word.  The kernel holding group 0 runs
-// first and writes the word (all-ones for padding indices); the one holding
-// group 2 runs last and adds the final SSE (key >> 9) into the run's sum.
+// min-combined into the block's key word (set to all-ones beforehand) with
+// an atomic minimum, so kernels and work items may run in any order.
+// GMASK == 8 makes each (group, rounds) pair a work item of its own, heavy
+// groups first, so one launch covers all groups and ends on light items.
 template <int GMASK>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_bc7_search(Bc7Launch L)
 {
     __shared__ TexLds S;
     __shared__ uint32_t s_item;
+    constexpr bool kItems = GMASK == 8;
     const EncodeArgs &a = L.a;
+    const uint64_t rounds = a.total / kWG;
+    const uint64_t per_group = (rounds + L.w.item_rounds - 1) / L.w.item_rounds;   // items per group
     stage_table(S, L.T);
-    ItemLoop it(L.w, a.total, kWG, &s_item);
+    ItemLoop it(L.w, kItems ? 3 * per_group * L.w.item_rounds * kWG : a.total, kWG, &s_item);
     if (it.item >= it.n_items) return;
     do {
+        const uint32_t group = kItems ? (uint32_t)(it.item / per_group) : 0u;
+        const uint64_t first = kItems ? (it.item % per_group) * L.w.item_rounds : (uint64_t)it.item * L.w.item_rounds;
         for (uint32_t r = 0; r < L.w.item_rounds; r++) {
-            const uint64_t g0 = ((uint64_t)it.item * L.w.item_rounds + r) * kWG;
+            const uint64_t g0 = (first + r) * kWG;
             if (g0 >= a.total) break;
             const BlockRun run = a.run[find_run(a.run, a.nrun, g0)];
             const uint64_t b = g0 - run.gbase + threadIdx.x;
@@ -883,20 +889,20 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
             __syncthreads();   // the previous round's LDS reads are done
             stage_texels(S, run.src + b * 64, live);
             __syncthreads();
-            uint32_t *slot = a.keys + g0 + threadIdx.x;
-            if (__ballot(live) == 0) {
-                if (GMASK & 1) *slot = ~0u;
-                continue;
-            }
-            uint32_t key = ~0u;
+            if (__ballot(live) == 0) continue;
             if (live) {
-                if (GMASK & 1) key = min(key, search_group<0>(S, a.mode_mask, L.T.sv));
-                if (GMASK & 2) key = min(key, search_group<1>(S, a.mode_mask, L.T.sv));
-                if (GMASK & 4) key = min(key, search_group<2>(S, a.mode_mask, L.T.sv));
-                if (!(GMASK & 1)) key = min(key, *slot);
+                uint32_t key = ~0u;
+                if (kItems) {
+                    key = group == 0 ? search_group<0>(S, a.mode_mask, L.T.sv)
+                                     : group == 1 ? search_group<1>(S, a.mode_mask, L.T.sv)
+                                                  : search_group<2>(S, a.mode_mask, L.T.sv);
+                } else {
+                    if (GMASK & 1) key = min(key, search_group<0>(S, a.mode_mask, L.T.sv));
+                    if (GMASK & 2) key = min(key, search_group<1>(S, a.mode_mask, L.T.sv));
+                    if (GMASK & 4) key = min(key, search_group<2>(S, a.mode_mask, L.T.sv));
+                }
+                atomicMin(a.keys + g0 + threadIdx.x, key);
             }
-            if ((GMASK & 1) || live) *slot = live ? key : ~0u;
-            if ((GMASK & 4) && run.sse) band_add(run.sse, 0, key >> 9, live);
         }
     } while (it.next(L.w, &s_item));
 }
@@ -910,15 +916,19 @@ __device__ __forceinline__ int mode_of_candidate(int ci)
     return ci < 16 ? 0 : ci < 80 ? 1 : ci < 144 ? 2 : ci < 208 ? 3 : ci < 216 ? 4 : ci < 220 ? 5 : ci < 221 ? 6 : 7;
 }
 
-// Per-workgroup mode counts (LDS atomics), written to wgcount[wg][8].
-__global__ __launch_bounds__(kWG) void k_bc7_bucket_count(const uint32_t *keys, uint64_t total, uint32_t *wgcount)
+// Per-workgroup mode counts (LDS atomics), written to wgcount[wg][8]; each
+// block's final SSE (key >> 9) is added into its run's sum here.
+__global__ __launch_bounds__(kWG) void k_bc7_bucket_count(EncodeArgs a, uint32_t *wgcount)
 {
     __shared__ uint32_t c[8];
     if (threadIdx.x < 8) c[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t g = (uint64_t)blockIdx.x * kWG + threadIdx.x;
-    const uint32_t key = g < total ? keys[g] : ~0u;
-    if (key != ~0u) atomicAdd(&c[mode_of_candidate((int)(key & 511u))], 1u);
+    const uint64_t g0 = (uint64_t)blockIdx.x * kWG, g = g0 + threadIdx.x;
+    const uint32_t key = g < a.total ? a.keys[g] : ~0u;
+    const bool live = key != ~0u;
+    if (live) atomicAdd(&c[mode_of_candidate((int)(key & 511u))], 1u);
+    const BlockRun run = a.run[find_run(a.run, a.nrun, g0)];
+    if (run.sse) band_add(run.sse, 0, key >> 9, live);
     __syncthreads();
     if (threadIdx.x < 8) wgcount[(uint64_t)blockIdx.x * 8 + threadIdx.x] = c[threadIdx.x];
 }
@@ -1121,16 +1131,20 @@ hipError_t launch_bc7_encode(const EncodeArgs &a, const WorkSplit *w3, uint32_t 
     if (e != hipSuccess) return e;
     if (!g_tab[dev]) return hipErrorNotInitialized;
     if (a.total == 0) return hipSuccess;
-    if (split > 2) return hipErrorInvalidValue;
+    if (split > 3) return hipErrorInvalidValue;
     Bc7Launch L;
     L.a = a;
     L.T.nearest = static_cast<const uint16_t *>(g_tab[dev]);
     L.T.sv = reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(g_tab[dev]) + 10 * 2 * 256 * 2);
     const uint32_t nwg = (uint32_t)(a.total / kWG);
     const dim3 sgrid(nwg);
+    // every key word starts all-ones (padding indices keep it)
+    if ((e = launch_fill_u64(reinterpret_cast<unsigned long long *>(a.keys), a.total / 2, ~0ull, st)) != hipSuccess)
+        return e;
     auto launch = [&](int q, auto kernel, const char *name) -> hipError_t {
         L.w = w3[q];
-        dim3 grid(L.w.queue ? L.w.grid : (uint32_t)((nwg + L.w.item_rounds - 1) / L.w.item_rounds));
+        const uint32_t per = (uint32_t)((nwg + L.w.item_rounds - 1) / L.w.item_rounds);
+        dim3 grid(L.w.queue ? L.w.grid : (split == 3 ? 3 * per : per));
         if (L.w.queue) {
             hipError_t f = launch_fill_u64(reinterpret_cast<unsigned long long *>(L.w.queue), 1, 0, st);
             if (f != hipSuccess) return f;
@@ -1145,12 +1159,14 @@ hipError_t launch_bc7_encode(const EncodeArgs &a, const WorkSplit *w3, uint32_t 
     } else if (split == 1) {
         if ((e = launch(0, k_bc7_search<1>, "bc7_search_2subset")) != hipSuccess) return e;
         if ((e = launch(1, k_bc7_search<6>, "bc7_search_3subset_1subset")) != hipSuccess) return e;
-    } else {
+    } else if (split == 2) {
         if ((e = launch(0, k_bc7_search<7>, "bc7_search_all")) != hipSuccess) return e;
+    } else {
+        if ((e = launch(0, k_bc7_search<8>, "bc7_search_items")) != hipSuccess) return e;
     }
     // key scratch: keys[total] | list[total] | count[8] start[8] | wgcount[nwg][8]
     uint32_t *count = a.keys + 2 * a.total, *wgcount = count + 16;
-    GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_count, sgrid, dim3(kWG), 0, st, a.keys, a.total, wgcount);
+    GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_count, sgrid, dim3(kWG), 0, st, a, wgcount);
     GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_scan, dim3(1), dim3(256), 0, st, wgcount, nwg, count);
     GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_fill, sgrid, dim3(kWG), 0, st, a.keys, a.total, wgcount, count,
                 a.keys + a.total);

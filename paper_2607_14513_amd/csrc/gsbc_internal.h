@@ -125,8 +125,9 @@ struct EncodeArgs {
 inline size_t bc7_scratch_bytes(uint64_t blocks) { return (size_t)blocks * 8 + 64 + ((blocks + 255) / 256) * 32; }
 // How the BC7 candidate search is split over kernels: 0 -> three kernels
 // (2-subset, 3-subset, 1-subset modes), 1 -> two (the 1-subset modes folded
-// into the 3-subset kernel), 2 -> one kernel for all modes.  Every split
-// gives the same bits (the winner is a minimum over a total order).
+// into the 3-subset kernel), 2 -> one kernel for all modes, 3 -> one kernel
+// with (group, rounds) work items.  Every split gives the same bits (the
+// winner is a minimum over a total order, combined with atomic minima).
 hipError_t launch_bc1_encode(const EncodeArgs &a, const WorkSplit &w, uint32_t lanes, hipStream_t st);
 hipError_t launch_bc7_encode(const EncodeArgs &a, const WorkSplit *w3, uint32_t split, hipStream_t st);
 hipError_t upload_bc1_tables(hipStream_t st);

@@ -93,6 +93,8 @@ TUNINGS = [
     {"item_rounds": 3, "wgs_per_cu": 2, "bc1_lanes": 64, "bc7_split": 1, "concurrent": 1},
     {"item_rounds": 1, "wgs_per_cu": 1, "bc1_lanes": 256, "bc7_split": 2, "concurrent": 0},
     {"item_rounds": 8, "wgs_per_cu": 4, "bc1_lanes": 128, "bc7_split": 0, "concurrent": 1},
+    {"item_rounds": 2, "wgs_per_cu": 0, "bc1_lanes": 128, "bc7_split": 3, "concurrent": 1},
+    {"item_rounds": 1, "wgs_per_cu": 3, "bc1_lanes": 64, "bc7_split": 3, "concurrent": 0},
 ]
 
 
