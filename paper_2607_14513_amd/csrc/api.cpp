@@ -217,6 +217,16 @@ constexpr uint32_t kPlainBc7Split = 3;
 constexpr size_t kRunTableBytes = 16 * sizeof(BlockRun);   // one scene, one format
 constexpr size_t kRunStageOff = 2048;                        // in ctx->pinned
 
+// The second stream (default priority) and its fork/join events.
+gsbc_status ensure_side(gsbc_ctx *ctx)
+{
+    if (ctx->side) return GSBC_OK;
+    HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "side stream");
+    HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming), "event");
+    HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming), "event");
+    return GSBC_OK;
+}
+
 void drop_plan(gsbc_ctx *ctx)
 {
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -452,17 +462,25 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
     a.mode_mask = p.bc7_mode_mask;
     a.keys = reinterpret_cast<uint32_t *>(arena + front + 2 * kRunTableBytes);
     const WorkSplit w3[3] = {kPlainSplit, kPlainSplit, kPlainSplit};
+    // both formats on the context's stream, one after the other, so each
+    // kernel's device time is its own (gsbc_encode_batch can overlap them)
+    hipStream_t s1 = ctx->stream;
+    if (have1) {
+        EncodeArgs a1 = a;
+        a1.run = druns1;
+        a1.nrun = (uint32_t)r1.v.size();
+        a1.total = r1.total;
+        HIP_TRY(ctx, launch_bc1_encode(a1, kPlainSplit, kPlainBc1Lanes, s1), "bc1 launch");
+    }
     if (have7) {
         a.run = druns7;
         a.nrun = (uint32_t)r7.v.size();
         a.total = r7.total;
         HIP_TRY(ctx, launch_bc7_encode(a, w3, kPlainBc7Split, ctx->stream), "bc7 launch");
     }
-    if (have1) {
-        a.run = druns1;
-        a.nrun = (uint32_t)r1.v.size();
-        a.total = r1.total;
-        HIP_TRY(ctx, launch_bc1_encode(a, kPlainSplit, kPlainBc1Lanes, ctx->stream), "bc1 launch");
+    if (s1 != ctx->stream) {
+        HIP_TRY(ctx, hipEventRecord(ctx->join, s1), "join");
+        HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ctx->join, 0), "join");
     }
     if (format == GSBC_FMT_AUTO) {
         uint64_t *doff1 = reinterpret_cast<uint64_t *>(small_ptr(ctx, kOff1Off));
@@ -602,11 +620,7 @@ gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *c
         if (!r1.v.empty()) HIP_TRY(ctx, hipMemcpy(d1, r1.v.data(), r1.v.size() * sizeof(BlockRun), hipMemcpyHostToDevice), "run table");
         int cus = 0;
         HIP_TRY(ctx, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device), "device attribute");
-        if (t.concurrent && !ctx->side) {
-            HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking), "side stream");
-            HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->fork, hipEventDisableTiming), "event");
-            HIP_TRY(ctx, hipEventCreateWithFlags(&ctx->join, hipEventDisableTiming), "event");
-        }
+        if (t.concurrent && (s = ensure_side(ctx))) return s;
         EncodeArgs a;
         memset(&a, 0, sizeof a);
         a.refine_steps = p.refine_steps;

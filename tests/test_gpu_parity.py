@@ -420,3 +420,33 @@ def test_decode_eval_large_sampled(G):
     gain = (sse[0] - sse[1]).astype(np.float64) * delta * delta
     order = sorted(range(1, 16), key=lambda k: (-gain[k], k))
     assert set(np.nonzero(f6[1:] == 7)[0] + 1) == set(order[:7])
+
+
+def test_injected_scratch_allocation_failure():
+    """GSBC_FAULT=alloc:1 fails the first scratch allocation of the process:
+    the call reports GSBC_E_NOMEM and the context stays usable.  Run in a
+    fresh process (the allocation counter is per process)."""
+    import os
+    import subprocess
+    code = (
+        "import numpy as np, torch\n"
+        "from paper_2607_14513_amd import gsbc, synth\n"
+        "ctx = gsbc.Context(0)\n"
+        "pos, sh = synth.make_scene(1000, seed=3)\n"
+        "p, s = torch.from_numpy(pos).cuda(), torch.from_numpy(sh).cuda()\n"
+        "try:\n"
+        "    ctx.reorder(p, s)\n"
+        "    print('NO-ERROR')\n"
+        "except gsbc.GsbcError as e:\n"
+        "    print('STATUS', e.status)\n"
+        "perm, tex, d = ctx.reorder(p, s)\n"
+        "torch.cuda.synchronize()\n"
+        "print('RECOVERED', d.n_prims)\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, GSBC_FAULT="alloc:1", PYTHONPATH=root)
+    r = subprocess.run([sys.executable, "-c", code], env=env, cwd=root, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0, r.stderr[-2000:]
+    from paper_2607_14513_amd import gsbc
+    assert f"STATUS {gsbc.E_NOMEM}" in r.stdout, r.stdout
+    assert "RECOVERED 1000" in r.stdout, r.stdout
