@@ -60,6 +60,7 @@ def _load():
             "ref_rate_select": (i32, [P, P, P, P, ctypes.c_double, P]),
             "ref_sh_basis": (None, [ctypes.c_double] * 3 + [P]),
             "ref_decode_eval": (None, [P, P, P, P, P, P, u32, P, u64, P, P]),
+            "ref_decode_eval_view": (None, [P, P, P, P, P, P, P, P, P, u64, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -286,4 +287,21 @@ def decode_eval(payload, off, fmt, vmin, vmax, dirs, slots, with_scale=True):
     _load().ref_decode_eval(_p(payload), _p(_c(fmt, np.uint8)), _p(_c(off, np.uint64)),
                             _p(_c(vmin, np.float32)), _p(_c(vmax, np.float32)), _p(dirs), V,
                             _p(slots), M, _p(out), _p(scale) if scale is not None else None)
+    return (out, scale) if with_scale else out
+
+
+def decode_eval_view(payload, off, fmt, vmin, vmax, pos, perm, view, slots, with_scale=True):
+    """FP64 colour of each slot seen from view position `view` (direction
+    (view - p)/|view - p| per primitive).  Returns out[M][3] (and scale)."""
+    payload = _c(payload, np.uint8)
+    pos = _c(pos, np.float32).reshape(-1, 3)
+    perm = _c(perm, np.uint32)
+    slots = _c(slots, np.uint32)
+    view = _c(np.asarray(view, np.float32).reshape(3), np.float32)
+    M = slots.shape[0]
+    out = np.empty((M, 3), np.float64)
+    scale = np.empty((M, 3), np.float64) if with_scale else None
+    _load().ref_decode_eval_view(_p(payload), _p(_c(fmt, np.uint8)), _p(_c(off, np.uint64)),
+                                 _p(_c(vmin, np.float32)), _p(_c(vmax, np.float32)), _p(pos), _p(perm),
+                                 _p(view), _p(slots), M, _p(out), _p(scale) if scale is not None else None)
     return (out, scale) if with_scale else out

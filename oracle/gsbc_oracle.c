@@ -1212,6 +1212,50 @@ EXPORT void ref_decode_eval(const uint8_t *blocks, const uint8_t *fmt, const uin
     }
 }
 
+/* View-dependent colour of each listed slot from one view position f
+ * (Sec. II colour equation c(f) = H w(f - p)): the SH basis is evaluated at
+ * the unit vector d = (f - p) / |f - p| from the primitive towards the view
+ * position (d = 0 when f = p), all in FP64 from the FP32 inputs.  pos is in
+ * input order; perm maps a slot to its primitive. */
+EXPORT void ref_decode_eval_view(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset,
+                                 const float *vmin, const float *vmax, const float *pos, const uint32_t *perm,
+                                 const float *view, const uint32_t *slots, uint64_t m, double *out, double *scale)
+{
+    #pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < (int64_t)m; j++) {
+        uint32_t s = slots[j];
+        const float *p = pos + 3 * (uint64_t)perm[s];
+        double d[3], r2 = 0.0;
+        for (int c = 0; c < 3; c++) {
+            d[c] = (double)view[c] - (double)p[c];
+            r2 += d[c] * d[c];
+        }
+        double r = sqrt(r2);
+        for (int c = 0; c < 3; c++) d[c] = r > 0.0 ? d[c] / r : 0.0;
+        double Y[16];
+        ref_sh_basis(d[0], d[1], d[2], Y);
+        uint64_t b = s / 16;
+        int texel = (int)ref_zigzag_texel(s % 16);
+        double H[16][3];
+        for (int k = 0; k < 16; k++) {
+            uint8_t px[64];
+            if (fmt[k] == 1) ref_bc1_decode_block(blocks + offset[k] + b * 8, px);
+            else ref_bc7_decode_block(blocks + offset[k] + b * 16, px);
+            double delta = ((double)vmax[k] - (double)vmin[k]) / 255.0;
+            for (int c = 0; c < 3; c++) H[k][c] = (double)vmin[k] + (double)px[texel * 4 + c] * delta;
+        }
+        for (int c = 0; c < 3; c++) {
+            double acc = 0.0, mag = 0.0;
+            for (int k = 0; k < 16; k++) {
+                acc += H[k][c] * Y[k];
+                mag += fabs(H[k][c] * Y[k]);
+            }
+            out[(uint64_t)j * 3 + c] = acc;
+            if (scale) scale[(uint64_t)j * 3 + c] = mag;
+        }
+    }
+}
+
 /* ======================================================================
  * Brute-force searchers used only to pin the encoders on tiny inputs.
  * ====================================================================== */

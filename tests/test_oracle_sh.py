@@ -79,3 +79,67 @@ def test_decode_eval_is_dequantised_texels_times_basis():
             Y = O.sh_basis(dirs[v].astype(np.float64))
             assert np.allclose(out[v, j], Y @ H, rtol=0, atol=1e-13)
             assert np.allclose(scale[v, j], np.abs(Y[:, None] * H).sum(0), rtol=0, atol=1e-13)
+
+
+def _decoded_H(payload, off, fmt, vmin, vmax, nblk, s):
+    dec = O.decode_stream(payload, off, fmt, nblk)
+    z = [[0, 1, 4, 5], [2, 3, 6, 7], [8, 9, 12, 13], [10, 11, 14, 15]]
+    where = {z[y][x]: 4 * y + x for y in range(4) for x in range(4)}
+    q = dec[:, s // 16, where[s % 16], :3].astype(np.float64)
+    delta = (vmax.astype(np.float64) - vmin.astype(np.float64)) / 255.0
+    return vmin.astype(np.float64)[:, None] + q * delta[:, None]
+
+
+def test_view_colour_closed_forms():
+    """decode_eval_view (Sec. II, c(f) = H w(f - p)): a view position straight
+    above a primitive sees it along +z, where only Y_0, Y_2, Y_6 and Y_12 are
+    non-zero: 1/(2 sqrt pi), sqrt(3/4pi), (1/2) sqrt(5/pi), (1/2) sqrt(7/pi);
+    a view position at the primitive itself (d = 0) leaves the DC term."""
+    pos, sh = synth.make_scene(700, seed=8)
+    perm, tex, vmin, vmax = O.reorder(pos, sh)
+    nblk = tex.shape[1]
+    fmt = np.array([7, 1, 7, 1] + [1] * 12, np.uint8)
+    payload, off, _ = O.encode(tex, fmt)
+    up = np.zeros(16)
+    up[0] = 0.5 / np.sqrt(np.pi)
+    up[2] = np.sqrt(3 / (4 * np.pi))
+    up[6] = 0.5 * np.sqrt(5 / np.pi)
+    up[12] = 0.5 * np.sqrt(7 / np.pi)
+    for s in (0, 5, 16, 333, 699):
+        p = pos[perm[s]]
+        H = _decoded_H(payload, off, fmt, vmin, vmax, nblk, s)
+        above = np.array([p[0], p[1], p[2] + np.float32(3.0)], np.float32)
+        assert above[2] > p[2]
+        out = O.decode_eval_view(payload, off, fmt, vmin, vmax, pos, perm, above, np.array([s], np.uint32),
+                                 with_scale=False)
+        assert np.allclose(out[0], up @ H, rtol=0, atol=1e-13)
+        at = O.decode_eval_view(payload, off, fmt, vmin, vmax, pos, perm, p, np.array([s], np.uint32),
+                                with_scale=False)
+        assert np.allclose(at[0], H[0] * 0.5 / np.sqrt(np.pi), rtol=0, atol=1e-15)
+
+
+def test_view_colour_direction_is_towards_the_view_position():
+    """Moving the view position along the ray from a primitive does not
+    change its colour (only the direction counts), and mirroring it through
+    the primitive flips the odd-degree terms: c(p + u) - c(p - u) =
+    2 sum_{l odd} H_lm Y_lm(u)."""
+    pos, sh = synth.make_scene(300, seed=9)
+    perm, tex, vmin, vmax = O.reorder(pos, sh)
+    nblk = tex.shape[1]
+    fmt = np.array([7] + [1] * 15, np.uint8)
+    payload, off, _ = O.encode(tex, fmt)
+    rng = np.random.default_rng(3)
+    odd = np.array([0, 1, 1, 1, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1], np.float64)
+    for s in (3, 77, 299):
+        p = pos[perm[s]].astype(np.float64)
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        H = _decoded_H(payload, off, fmt, vmin, vmax, nblk, s)
+        sl = np.array([s], np.uint32)
+        cols = []
+        for lam in (0.5, 4.0, -0.5):
+            f = (p + lam * u).astype(np.float32)
+            cols.append(O.decode_eval_view(payload, off, fmt, vmin, vmax, pos, perm, f, sl, with_scale=False)[0])
+        assert np.allclose(cols[0], cols[1], rtol=0, atol=1e-6)     # float32 view positions
+        Yu = O.sh_basis(u)
+        assert np.allclose(cols[0] - cols[2], 2 * (odd * Yu) @ H, rtol=0, atol=1e-5)
