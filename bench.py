@@ -215,7 +215,7 @@ def main():
             dirs3 = torch.from_numpy(synth.make_dirs(c3["dirs"], seed=c3["seed"])).to(dev)
             p3, t3, dd = ctx.reorder(torch.from_numpy(pos3).to(dev), torch.from_numpy(sh3).to(dev))
             b3, dd2, _ = ctx.encode(t3, dd, fmt=gsbc.FMT_AUTO, rate=c3["rate"])
-            del t3, p3
+            del t3
             out3 = torch.empty((c3["dirs"], c3["n"], 3), dtype=torch.float32, device=dev)
             ctx.decode_eval(b3, dd2, dirs3, out=out3)
             torch.cuda.synchronize()
@@ -226,6 +226,22 @@ def main():
             kd = ctx.profile_read()
             ctx.profile(False)
             de_s = kd["decode_eval"][1] / kd["decode_eval"][0] * 1e-3
+            # every primitive's colour from one view position (its own direction)
+            pos3d = torch.from_numpy(pos3).to(dev)
+            view = (0.5, 0.5, 2.5)
+            ctx.decode_eval_view(b3, dd2, pos3d, p3, view)
+            ctx.profile(True)
+            ctx.profile_read()
+            for i in range(3):
+                ov = ctx.decode_eval_view(b3, dd2, pos3d, p3, view)
+            kv = ctx.profile_read()
+            ctx.profile(False)
+            view_s = kv["decode_eval_view"][1] / kv["decode_eval_view"][0] * 1e-3
+            view_leg = {"workload": "3,145,728 primitives, one view position, each primitive at its own direction",
+                        "ms": round(view_s * 1e3, 4), "gslots_s": round(c3["n"] / view_s / 1e9, 3),
+                        "bytes": int(dd2.payload_bytes + c3["n"] * (12 + 4 + 12))}
+            view_leg["gb_s"] = round(view_leg["bytes"] / view_s / 1e9, 1)
+            del ov, pos3d, p3
             # context: a plain device fill of the same output (write ceiling)
             tf = []
             for i in range(3):
@@ -242,7 +258,7 @@ def main():
                        "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": de_bytes / de_s / HBM_PEAK,
                        "traffic": tr_de, "launch_ms": de_s * 1e3,
                        "workload": "3,145,728 primitives x 1,024 directions, 6 bits/texel",
-                       "plain_fill_gbps": round(fill_gbps, 1)}
+                       "plain_fill_gbps": round(fill_gbps, 1), "view": view_leg}
             del out3, b3
             torch.cuda.empty_cache()
         batch = None if args.no_batch else batch_leg(ctx, stream, dev, args.batch_scenes, max(3, args.steps))

@@ -229,6 +229,22 @@ GSBC_API gsbc_status gsbc_decode_eval(gsbc_ctx *ctx, const uint8_t *blocks, cons
                              const float *dirs, uint32_t n_dirs, const uint32_t *prim_idx,
                              uint64_t m, float *out);
 
+/* Colour of each listed slot seen from one view position f: the colour
+ * equation c(f) = H w(f - p) of Sec. II evaluated per primitive at the unit
+ * direction d = (f - p)/|f - p| towards the view position (d = 0 when f = p),
+ * the per-primitive colour a rasteriser's blending stage consumes (Sec. II,
+ * eq. preblend).  FP32: d from the FP32 inputs, then as gsbc_decode_eval.
+ *   blocks, desc   as gsbc_decode_eval
+ *   pos       device float[n_prims][3], primitive positions in input order
+ *   perm      device uint32[n_prims] from gsbc_reorder (slot -> primitive)
+ *   view      host float[3], the view position f
+ *   prim_idx  device uint32[m] sorted-slot ids, or NULL for all slots (then
+ *             m must equal n_prims); ids >= n_prims give NaN colours
+ *   out       device float[m][3] */
+GSBC_API gsbc_status gsbc_decode_eval_view(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_desc *desc,
+                                           const float *pos, const uint32_t *perm, const float *view,
+                                           const uint32_t *prim_idx, uint64_t m, float *out);
+
 /* ---------------------------------------------------------------- container */
 
 /* The durable form of a coded scene: fixed-size blocks in one bitstream per

@@ -820,6 +820,29 @@ gsbc_status gsbc_decode_eval(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_st
     return GSBC_OK;
 }
 
+gsbc_status gsbc_decode_eval_view(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_desc *desc, const float *pos,
+                                  const uint32_t *perm, const float *view, const uint32_t *prim_idx, uint64_t m,
+                                  float *out)
+{
+    gsbc_status s = begin(ctx);
+    if (s) return s;
+    ActiveGuard guard(ctx);
+    if (!blocks || !pos || !perm || !view || !out) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
+    if (reinterpret_cast<uintptr_t>(blocks) & 15) return fail(ctx, GSBC_E_ARG, "blocks must be 16-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(pos) & 3) || (reinterpret_cast<uintptr_t>(perm) & 3) ||
+        (reinterpret_cast<uintptr_t>(out) & 3) || (reinterpret_cast<uintptr_t>(prim_idx) & 3))
+        return fail(ctx, GSBC_E_ARG, "pos, perm, prim_idx and out must be 4-byte aligned");
+    if ((s = check_stream(ctx, desc))) return s;
+    if (m == 0) return fail(ctx, GSBC_E_ARG, "m must be >= 1");
+    if (!prim_idx && m != desc->n_prims) return fail(ctx, GSBC_E_ARG, "prim_idx NULL requires m == n_prims");
+    if (m > 0xFFFFFFFFull * 256) return fail(ctx, GSBC_E_ARG, "m too large");
+    const float f[3] = {view[0], view[1], view[2]};
+    if (!(isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2]))) return fail(ctx, GSBC_E_ARG, "view position not finite");
+    HIP_TRY(ctx, launch_decode_eval_view(blocks, band_args(desc), desc->n_prims, pos, perm, f, prim_idx, m, out,
+                                         ctx->stream), "decode_eval_view launch");
+    return GSBC_OK;
+}
+
 gsbc_status gsbc_profile_enable(gsbc_ctx *ctx, int on)
 {
     gsbc_status s = begin(ctx);

@@ -181,7 +181,77 @@ __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *block
     }
 }
 
+// Colour of each listed slot seen from one view position f (Sec. II,
+// c(f) = H w(f - p)): one lane per slot gathers its primitive's position
+// through perm, takes d = (f - p)/|f - p| (zero when f = p), evaluates the 16
+// basis functions and dots them with the decoded, dequantised texels (FP32,
+// k order).  Out-of-range slot ids give NaN.
+__global__ __launch_bounds__(256) void k_decode_eval_view(const uint8_t *blocks, BandArgs b, const uint32_t *prim_idx,
+                                                          uint64_t m, uint64_t n_prims, const float *pos,
+                                                          const uint32_t *perm, float fx, float fy, float fz,
+                                                          float *out)
+{
+    const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= m) return;
+    const uint32_t s = prim_idx ? prim_idx[j] : (uint32_t)j;
+    float c[3] = {__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
+    if (s < n_prims) {
+        const uint64_t pi = perm[s];
+        float x = fx - pos[3 * pi], y = fy - pos[3 * pi + 1], z = fz - pos[3 * pi + 2];
+        const float r = sqrtf(x * x + y * y + z * z);
+        const float inv = r > 0.0f ? 1.0f / r : 0.0f;
+        x *= inv;
+        y *= inv;
+        z *= inv;
+        const float c0 = 0.28209479177387814f, c1 = 0.4886025119029199f;
+        const float c2a = 1.0925484305920792f, c2b = 0.31539156525252005f, c2c = 0.5462742152960396f;
+        const float c3a = 0.5900435899266435f, c3b = 2.890611442640554f, c3c = 0.4570457994644658f;
+        const float c3d = 0.3731763325901154f, c3e = 1.445305721320277f;
+        const float xx = x * x, yy = y * y, zz = z * z;
+        float Y[16];
+        Y[0] = c0;
+        Y[1] = -c1 * y;
+        Y[2] = c1 * z;
+        Y[3] = -c1 * x;
+        Y[4] = c2a * x * y;
+        Y[5] = -c2a * y * z;
+        Y[6] = c2b * (2.0f * zz - xx - yy);
+        Y[7] = -c2a * x * z;
+        Y[8] = c2c * (xx - yy);
+        Y[9] = -c3a * y * (3.0f * xx - yy);
+        Y[10] = c3b * x * y * z;
+        Y[11] = -c3c * y * (4.0f * zz - xx - yy);
+        Y[12] = c3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+        Y[13] = -c3c * x * (4.0f * zz - xx - yy);
+        Y[14] = c3e * z * (xx - yy);
+        Y[15] = -c3a * x * (xx - 3.0f * yy);
+        const uint64_t blk = s >> 4;
+        const int texel = (int)zigzag_texel(s & 15u);
+        c[0] = c[1] = c[2] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 16; k++) {
+            const uint32_t px = band_texel(blocks, b, k, blk, texel);
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++)
+                c[ch] = fmaf(fmaf((float)((px >> (8 * ch)) & 255), b.delta[k], b.vmin[k]), Y[k], c[ch]);
+        }
+    }
+    out[3 * j] = c[0];
+    out[3 * j + 1] = c[1];
+    out[3 * j + 2] = c[2];
+}
+
 }  // namespace
+
+hipError_t launch_decode_eval_view(const uint8_t *blocks, const BandArgs &b, uint64_t n_prims, const float *pos,
+                                   const uint32_t *perm, const float view[3], const uint32_t *prim_idx, uint64_t m,
+                                   float *out, hipStream_t st)
+{
+    if (m == 0) return hipSuccess;
+    GSBC_LAUNCH("decode_eval_view", k_decode_eval_view, dim3((uint32_t)((m + 255) / 256)), dim3(256), 0, st, blocks, b,
+                prim_idx, m, n_prims, pos, perm, view[0], view[1], view[2], out);
+    return hipGetLastError();
+}
 
 hipError_t launch_decode(const uint8_t *blocks, const BandArgs &b, uint64_t nblk, uint8_t *textures,
                          hipStream_t st)

@@ -159,4 +159,10 @@ hipError_t launch_decode_eval(const uint8_t *blocks, const BandArgs &b, uint64_t
                               const float *dirs, uint32_t n_dirs, const uint32_t *prim_idx,
                               uint64_t m, float *out, float *basis_scratch, hipStream_t st);
 
+// One view position: out[j] = colour of slot prim_idx[j] (or j) at the
+// direction from its primitive (pos[perm[slot]]) towards `view`.
+hipError_t launch_decode_eval_view(const uint8_t *blocks, const BandArgs &b, uint64_t n_prims, const float *pos,
+                                   const uint32_t *perm, const float view[3], const uint32_t *prim_idx, uint64_t m,
+                                   float *out, hipStream_t st);
+
 }  // namespace gsbc

@@ -19,7 +19,7 @@ FMT_AUTO, FMT_BC1, FMT_BANDS, FMT_BC7 = 0, 1, 2, 7
 
 EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_default_params",
             "gsbc_query_sizes", "gsbc_reorder", "gsbc_encode", "gsbc_default_batch_tuning",
-            "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_save", "gsbc_load",
+            "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_decode_eval_view", "gsbc_save", "gsbc_load",
             "gsbc_profile_enable", "gsbc_profile_read")
 
 
@@ -92,6 +92,7 @@ def load():
                                           ctypes.POINTER(BatchTuning), P]
         lib.gsbc_decode.argtypes = [P, P, ctypes.POINTER(StreamDesc), P]
         lib.gsbc_decode_eval.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, u32, P, u64, P]
+        lib.gsbc_decode_eval_view.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, P, P, P, u64, P]
         lib.gsbc_save.argtypes = [P, P, ctypes.POINTER(StreamDesc), ctypes.c_char_p]
         lib.gsbc_load.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(StreamDesc), P, u64]
         lib.gsbc_profile_enable.argtypes = [P, ctypes.c_int]
@@ -265,6 +266,21 @@ class Context:
                                              ctypes.c_void_p(sse.ctypes.data) if sse is not None else None))
         out = [darr[i].copy() for i in range(n)]
         return out, (sse.reshape(n, 16) if sse is not None else None)
+
+    def decode_eval_view(self, blocks, desc, pos, perm, view, prim_idx=None, out=None):
+        """pos float32[n][3] (input order) and perm int32[n] on the device, view
+        3 floats (host) -> out float32[m][3]: each slot's colour seen from view."""
+        _dev_tensor(pos, torch.float32, "pos")
+        _dev_tensor(perm, torch.int32, "perm")
+        m = desc.n_prims if prim_idx is None else prim_idx.numel()
+        if prim_idx is not None:
+            _dev_tensor(prim_idx, torch.int32, "prim_idx")
+        if out is None:
+            out = torch.empty((m, 3), dtype=torch.float32, device=self.device)
+        f = (ctypes.c_float * 3)(*[float(x) for x in view])
+        self._check(load().gsbc_decode_eval_view(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(pos), _ptr(perm), f,
+                                                 _ptr(prim_idx), m, _ptr(out)))
+        return out
 
     def save(self, path, blocks, desc):
         """Write the coded scene (device blocks + desc) as a container file."""

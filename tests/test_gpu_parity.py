@@ -382,6 +382,36 @@ def test_decode_eval_prim_subset_and_bounds(G):
     assert np.array_equal(full[:, idx[good], :], out[:, good, :])
 
 
+@pytest.mark.parametrize("n,seed", [(4101, 21), (65_536, 22)])
+def test_decode_eval_view(G, n, seed):
+    """Per-primitive view directions from one view position (outside the
+    scene, inside it, and exactly at a primitive) against the FP64 oracle;
+    a slot subset with out-of-range ids gives NaN there."""
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(n, seed=seed)
+    rperm, rtex, vmin, vmax = O.reorder(pos, sh)
+    fmt = np.array([7, 7, 1, 1] + [7, 1] * 6, np.uint8)
+    payload, off, _ = O.encode(rtex, fmt)
+    d = _desc_for(gsbc, n, fmt)
+    for k in range(16):
+        d.vmin[k], d.vmax[k] = float(vmin[k]), float(vmax[k])
+    assert d.payload_bytes == payload.size
+    blocks, posd, permd = dev(payload), dev(pos), dev(rperm.view(np.int32))
+    views = [np.array([3.0, -2.0, 0.5], np.float32), np.array([0.5, 0.5, 0.5], np.float32), pos[rperm[7]]]
+    slots = np.arange(n, dtype=np.uint32)
+    for f in views:
+        say("view", n, f)
+        out = host(ctx.decode_eval_view(blocks, d, posd, permd, f))
+        ref, scale = O.decode_eval_view(payload, off, fmt, vmin, vmax, pos, rperm, f, slots)
+        _check_colours(out, ref, scale)
+    sub = np.array([n - 1, 0, 7, n, 5, 2 ** 31], np.uint32)
+    out = host(ctx.decode_eval_view(blocks, d, posd, permd, views[0], prim_idx=dev(sub.view(np.int32))))
+    ok = sub < n
+    ref, scale = O.decode_eval_view(payload, off, fmt, vmin, vmax, pos, rperm, views[0], sub[ok])
+    _check_colours(out[ok], ref, scale)
+    assert np.all(np.isnan(out[~ok]))
+
+
 def test_decode_eval_large_sampled(G):
     """3,145,728 primitives, 256 clusters, 1,024 view directions in one launch
     (38.7 GB of output).  Band 0 BC7, bands 1..15 BC1 (rate 4.25, where the
