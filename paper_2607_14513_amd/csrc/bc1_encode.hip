@@ -34,12 +34,13 @@ struct Bc1Tables {
 };
 __constant__ Bc1Tables kTab;
 
-// Per-workgroup LDS: -2 x the prefix sums of the ordered texels, row 3 s + c
-// holding channel c of the sum over the first s texels, one column per lane;
-// and the nearest-code table with its expanded values.
+// Per-workgroup LDS: -2 x the prefix sums of the ordered texels (16-bit:
+// |-2 P| <= 8160), row 3 s + c holding channel c of the sum over the first s
+// texels, one column per lane; and the nearest-code table with its expanded
+// values.
 template <int LANES>
 struct Bc1Lds {
-    int m2P[17 * 3][LANES];
+    short m2P[17 * 3][LANES];
     uint8_t code[2][512];
     uint8_t val[2][512];
 };
@@ -320,15 +321,17 @@ __device__ __forceinline__ void encode_block(const uint32_t (&t)[16], uint32_t r
 #pragma unroll
         for (int k = 0; k < 16; k++)
             if (k != i) r += (k < i ? proj[k] <= proj[i] : proj[k] < proj[i]) ? 1 : 0;
-        L.m2P[3 * r][lane] = (int)(t[i] & 0xFFFFFFu);   // texel of rank r, parked in row 3 r
+        // texel of rank r parked in rows 3 r (R, G) and 3 r + 1 (B)
+        L.m2P[3 * r][lane] = (short)(t[i] & 0xFFFFu);
+        L.m2P[3 * r + 1][lane] = (short)((t[i] >> 16) & 255u);
     }
-    // row 3 k still holds the texel of rank k when the prefix rows of k are written
+    // rows 3 k and 3 k + 1 still hold the texel of rank k when the prefix rows of k are written
     int run[3] = {0, 0, 0};
 #pragma unroll
     for (int k = 0; k <= 16; k++) {
-        const uint32_t x = k < 16 ? (uint32_t)L.m2P[3 * k][lane] : 0u;
+        const uint32_t x = k < 16 ? ((uint32_t)(uint16_t)L.m2P[3 * k][lane] | ((uint32_t)L.m2P[3 * k + 1][lane] << 16)) : 0u;
 #pragma unroll
-        for (int c = 0; c < 3; c++) L.m2P[3 * k + c][lane] = -2 * run[c];
+        for (int c = 0; c < 3; c++) L.m2P[3 * k + c][lane] = (short)(-2 * run[c]);
         run[0] += (int)(x & 255u);
         run[1] += (int)((x >> 8) & 255u);
         run[2] += (int)((x >> 16) & 255u);
