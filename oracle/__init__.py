@@ -41,6 +41,8 @@ def _load():
             "ref_band_range": (None, [P, u64, P, P]),
             "ref_pos_aabb": (None, [P, u64, P, P]),
             "ref_quantise": (None, [P, u64, P, P, P]),
+            "ref_premultiply": (None, [P, P, u64, P]),
+            "ref_band_range_coverage": (None, [P, u64, u32, u32, P, P]),
             "ref_morton_rgb": (u32, [u32, u32, u32]),
             "ref_morton3": (u32, [u32, u32, u32, u32]),
             "ref_keys": (None, [P, P, u64, u32, P, P, P]),
@@ -95,6 +97,23 @@ def band_range(sh):
     return vmin, vmax
 
 
+def premultiply(sh, opacity):
+    """H~ = mu H per primitive, FP32."""
+    sh = _c(sh, np.float32)
+    out = np.empty_like(sh)
+    _load().ref_premultiply(_p(sh), _p(_c(opacity, np.float32)), sh.shape[0], _p(out))
+    return out
+
+
+def band_range_coverage(sh, num=995, den=1000):
+    """Symmetric per-band range [-t, t] holding num/den of the coefficients."""
+    sh = _c(sh, np.float32)
+    vmin = np.empty(16, np.float32)
+    vmax = np.empty(16, np.float32)
+    _load().ref_band_range_coverage(_p(sh), sh.shape[0], int(num), int(den), _p(vmin), _p(vmax))
+    return vmin, vmax
+
+
 def pos_aabb(pos):
     pos = _c(pos, np.float32)
     lo = np.empty(3, np.float32)
@@ -144,9 +163,13 @@ def pack(q, perm):
     return tex
 
 
-def reorder(pos, sh, grid_bits=3):
-    """Q + K + S + B.  Returns (perm, textures[16][nblk][16][4], vmin, vmax)."""
-    vmin, vmax = band_range(sh)
+def reorder(pos, sh, grid_bits=3, opacity=None, quantiser=0):
+    """Q + K + S + B.  Returns (perm, textures[16][nblk][16][4], vmin, vmax).
+    opacity: premultiply the coefficients first; quantiser 1: the symmetric
+    99.5 % coverage range instead of min/max."""
+    if opacity is not None:
+        sh = premultiply(sh, opacity)
+    vmin, vmax = band_range_coverage(sh) if quantiser == 1 else band_range(sh)
     lo, hi = pos_aabb(pos)
     q = quantise(sh, vmin, vmax)
     k = keys(pos, q, grid_bits, lo, hi)

@@ -70,6 +70,44 @@ EXPORT void ref_pos_aabb(const float *pos, uint64_t n, float *lo, float *hi)
     }
 }
 
+/* Opacity premultiplication before coding (Sec. II: the coded coefficients
+ * are H~ = mu H, eq. premult; Sec. V-A): out = mu_i * x in FP32. */
+EXPORT void ref_premultiply(const float *sh, const float *opacity, uint64_t n, float *out)
+{
+    for (uint64_t i = 0; i < n; i++)
+        for (int e = 0; e < 48; e++) out[i * 48 + e] = opacity[i] * sh[i * 48 + e];
+}
+
+static int cmp_float(const void *a, const void *b)
+{
+    float x = *(const float *)a, y = *(const float *)b;
+    return (x > y) - (x < y);
+}
+
+/* The paper's range (Sec. V-A): per band a scale such that after
+ * normalisation the given share (num/den, 995/1000 there) of the band's
+ * coefficients lies in [-0.5, 0.5].  Read as the symmetric interval
+ * [-t, t] with t the r-th smallest |x| over the band's 3n coefficients,
+ * r = ceil(3n num / den): the least t with at least that share inside.
+ * Quantisation is then the same rint((x - vmin) 255/(vmax - vmin)), clamped,
+ * with vmin = -t, vmax = t. */
+EXPORT void ref_band_range_coverage(const float *sh, uint64_t n, uint32_t num, uint32_t den, float *vmin,
+                                    float *vmax)
+{
+    const uint64_t M = 3 * n;
+    const uint64_t r = (M * num + den - 1) / den;   /* 1-based rank */
+    float *a = (float *)malloc(M * sizeof(float));
+    for (int k = 0; k < 16; k++) {
+        for (uint64_t i = 0; i < n; i++)
+            for (int c = 0; c < 3; c++) a[i * 3 + c] = fabsf(sh[(i * 16 + k) * 3 + c]);
+        qsort(a, M, sizeof(float), cmp_float);
+        float t = a[r - 1];
+        vmin[k] = t == 0.0f ? 0.0f : -t;
+        vmax[k] = t;
+    }
+    free(a);
+}
+
 EXPORT void ref_quantise(const float *sh, uint64_t n, const float *vmin,
                          const float *vmax, uint8_t *q)
 {

@@ -108,3 +108,58 @@ def test_reorder_groups_by_chunk_then_colour():
     lo, hi = O.pos_aabb(pos)
     k = O.keys(pos, q, 3, lo, hi)
     assert (np.diff(k[perm].astype(np.int64)) >= 0).all()
+
+
+def test_coverage_range_order_statistic():
+    """The paper's range (Sec. V-A): the least symmetric [-t, t] holding 99.5 %
+    of a band's coefficients.  Built bands with known order statistics: |x|
+    a permutation of 1..M with random signs, so t is the rank ceil(0.995 M)."""
+    rng = np.random.default_rng(4)
+    for n in (1000, 1001, 7):                              # 0.995*3n integer or not
+        M = 3 * n
+        sh = np.empty((n, 16, 3), np.float32)
+        for k in range(16):
+            v = rng.permutation(M).astype(np.float32) + 1
+            v *= rng.choice([-1.0, 1.0], M).astype(np.float32)
+            sh[:, k, :] = (v * (0.25 * (k + 1))).reshape(n, 3)
+        vmin, vmax = O.band_range_coverage(sh)
+        r = -(-M * 995 // 1000)
+        for k in range(16):
+            t = np.float32(r * 0.25 * (k + 1))
+            assert vmax[k] == t and vmin[k] == -t
+            inside = (np.abs(sh[:, k, :]) <= t).mean()
+            assert inside >= 0.995 and (np.abs(sh[:, k, :]) < t).mean() < 0.995
+
+
+def test_coverage_range_zero_band_and_quantisation():
+    pos, sh = synth.make_scene(2000, seed=12)
+    sh[:, 4, :] = 0.0
+    vmin, vmax = O.band_range_coverage(sh)
+    assert vmin[4] == 0.0 and vmax[4] == 0.0 and not np.signbit(vmin[4])
+    q = O.quantise(sh, vmin, vmax)
+    assert not q[:, 4, :].any()
+    for k in (0, 1, 9):
+        band = sh[:, k, :]
+        inside = np.abs(band) <= vmax[k]
+        assert inside.mean() >= 0.995
+        # values outside the interval clamp to the ends; 0 maps to the middle code
+        hi, lo = band >= vmax[k], band <= vmin[k]
+        assert hi.any() and q[:, k, :][hi].min() == 255
+        assert not lo.any() or q[:, k, :][lo].max() == 0
+        assert int(O.quantise(np.zeros((1, 16, 3), np.float32), vmin, vmax)[0, k, 0]) in (127, 128)
+
+
+def test_premultiply_is_the_fp32_product():
+    pos, sh = synth.make_scene(500, seed=13)
+    rng = np.random.default_rng(5)
+    mu = rng.uniform(0, 1, 500).astype(np.float32)
+    mu[:3] = (0.0, 1.0, 0.5)
+    h = O.premultiply(sh, mu)
+    assert np.array_equal(h, (mu[:, None, None] * sh).astype(np.float32))
+    assert not h[0].any() and np.array_equal(h[1], sh[1]) and np.array_equal(h[2], sh[2] * np.float32(0.5))
+    # mu = 1 everywhere: reorder unchanged; a power-of-two opacity scales the coverage range exactly
+    a = O.reorder(pos, sh, quantiser=1)
+    b = O.reorder(pos, sh, quantiser=1, opacity=np.ones(500, np.float32))
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    c = O.reorder(pos, sh, quantiser=1, opacity=np.full(500, 0.25, np.float32))
+    assert np.array_equal(c[3], a[3] * np.float32(0.25))
