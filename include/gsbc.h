@@ -67,6 +67,11 @@ typedef struct {
     uint32_t order;          /* gsbc_reorder: 0 = sort by (spatial cell, colour) (default);
                                 1 = keep the input order (perm[s] = s), the unsorted
                                 baseline the paper compares sorting against (Sec. III-C) */
+    uint32_t quantiser;      /* gsbc_reorder: per-band range of the 8-bit quantiser (Sec. V-A):
+                                0 = [min, max] of the band's coefficients (default);
+                                1 = [-t, t] with t the ceil(0.995 * 3n)-th smallest |x| of
+                                    the band, so that 99.5 % of its coefficients lie inside
+                                    and the rest clamp (vmin = +0 when t = 0) */
 } gsbc_params;
 
 /* Header of a coded scene: one bitstream per SH band (Sec. IV-A: typed
@@ -99,7 +104,8 @@ GSBC_API const char *gsbc_last_error(const gsbc_ctx *ctx);
 /* Wait for all work enqueued by this context. */
 GSBC_API gsbc_status gsbc_sync(gsbc_ctx *ctx);
 
-/* Fill `p` (host) with the defaults: grid_bits 3, refine_steps 2, mode mask 0xFF, order 0. */
+/* Fill `p` (host) with the defaults: grid_bits 3, refine_steps 2, mode mask 0xFF, order 0,
+ * quantiser 0. */
 GSBC_API void gsbc_default_params(gsbc_params *p);
 
 /* Sizes in bytes for N primitives and V directions (any output may be NULL):
@@ -110,12 +116,16 @@ GSBC_API gsbc_status gsbc_query_sizes(uint64_t n, uint32_t n_dirs, uint64_t *tex
 
 /* ---------------------------------------------------------------- calls */
 
-/* Reorder and pack (Sec. III-C and Sec. IV-B, Fig. SetupD; quantiser of
- * Sec. V-A with a per-band min/max range).
+/* Reorder and pack (Sec. III-C and Sec. IV-B, Fig. SetupD; preprocessing
+ * and 8-bit quantiser of Sec. V-A).
  *   pos     device float[n][3]      primitive centres
  *   sh      device float[n][16][3]  SH colour coefficients (band-major per primitive)
- *   n       1 .. 2^31-1 primitives
- *   params  host, NULL for defaults (grid_bits is used)
+ *   opacity device float[n] or NULL: when given, every coefficient of
+ *           primitive i is first multiplied by opacity[i] in FP32 (the
+ *           opacity-premultiplied colours of Sec. V-A); the range, keys and
+ *           textures all use the products
+ *   n       1 .. 2^31-1 primitives (quantiser 1: 3n < 2^32)
+ *   params  host, NULL for defaults (grid_bits, order, quantiser are used)
  *   perm    device uint32[n]        out: perm[s] = original index at slot s
  *   textures device uint8[16][n_pad/16][16][4] out: band k, block b, texel
  *           4y+x holds the 8-bit RGB (alpha 255) of slot 16b+j, j placed at
@@ -125,8 +135,8 @@ GSBC_API gsbc_status gsbc_query_sizes(uint64_t n, uint32_t n_dirs, uint64_t *tex
  * Keys: (Morton cell of the position on a 2^g grid over the bounding box) << 24
  * | interleaved bits of the band-0 quantised R,G,B (R highest in each triple);
  * stable ascending sort.  Inputs must be finite. */
-GSBC_API gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, uint64_t n,
-                         const gsbc_params *params, uint32_t *perm, uint8_t *textures,
+GSBC_API gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, const float *opacity,
+                         uint64_t n, const gsbc_params *params, uint32_t *perm, uint8_t *textures,
                          gsbc_stream_desc *desc);
 
 /* Encode every band (Sec. III-A BTC; Sec. IV-B per-bitstream formats).

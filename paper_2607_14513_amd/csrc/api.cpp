@@ -144,6 +144,7 @@ gsbc_status check_params(gsbc_ctx *ctx, const gsbc_params &p)
     if (p.refine_steps > 8) return fail(ctx, GSBC_E_ARG, "refine_steps %u > 8", p.refine_steps);
     if (p.bc7_mode_mask == 0 || p.bc7_mode_mask > 0xFF) return fail(ctx, GSBC_E_ARG, "bc7_mode_mask 0x%x not in 1..0xFF", p.bc7_mode_mask);
     if (p.order > 1) return fail(ctx, GSBC_E_ARG, "order %u is not 0 (sorted) or 1 (identity)", p.order);
+    if (p.quantiser > 1) return fail(ctx, GSBC_E_ARG, "quantiser %u is not 0 (min/max) or 1 (99.5%% coverage)", p.quantiser);
     return GSBC_OK;
 }
 
@@ -275,6 +276,7 @@ void gsbc_default_params(gsbc_params *p)
     p->refine_steps = 2;
     p->bc7_mode_mask = 0xFF;
     p->order = 0;
+    p->quantiser = 0;
 }
 
 gsbc_status gsbc_create(gsbc_ctx **out, int device, void *hip_stream)
@@ -352,8 +354,8 @@ gsbc_status gsbc_query_sizes(uint64_t n, uint32_t n_dirs, uint64_t *textures_byt
     return GSBC_OK;
 }
 
-gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, uint64_t n, const gsbc_params *params,
-                         uint32_t *perm, uint8_t *textures, gsbc_stream_desc *desc)
+gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, const float *opacity, uint64_t n,
+                         const gsbc_params *params, uint32_t *perm, uint8_t *textures, gsbc_stream_desc *desc)
 {
     gsbc_status s = begin(ctx);
     if (s) return s;
@@ -361,13 +363,18 @@ gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, uint6
     if (!pos || !sh || !perm || !textures || !desc) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
     if (n == 0 || n > 0x7FFFFFFFull) return fail(ctx, GSBC_E_ARG, "n = %llu not in 1..2^31-1", (unsigned long long)n);
     if ((reinterpret_cast<uintptr_t>(sh) & 15) || (reinterpret_cast<uintptr_t>(textures) & 15) ||
-        (reinterpret_cast<uintptr_t>(pos) & 3) || (reinterpret_cast<uintptr_t>(perm) & 3))
-        return fail(ctx, GSBC_E_ARG, "sh and textures must be 16-byte aligned, pos and perm 4-byte aligned");
+        (reinterpret_cast<uintptr_t>(pos) & 3) || (reinterpret_cast<uintptr_t>(perm) & 3) ||
+        (reinterpret_cast<uintptr_t>(opacity) & 3))
+        return fail(ctx, GSBC_E_ARG, "sh and textures must be 16-byte aligned, pos, opacity and perm 4-byte aligned");
     gsbc_params p = resolve(params);
     if ((s = check_params(ctx, p))) return s;
+    if (p.quantiser == 1 && 3 * n > 0xFFFFFFFFull)
+        return fail(ctx, GSBC_E_ARG, "quantiser 1 counts 3n coefficients per band in 32 bits: n = %llu too large",
+                    (unsigned long long)n);
     if ((s = ensure_arena(ctx, reorder_scratch_bytes(n, p.grid_bits)))) return s;
     RangeRec *range = reinterpret_cast<RangeRec *>(small_ptr(ctx, kRangeOff));
-    HIP_TRY(ctx, launch_reorder(pos, sh, n, p.grid_bits, p.order == 1, perm, textures, ctx->arena, range, ctx->stream),
+    HIP_TRY(ctx, launch_reorder(pos, sh, opacity, n, p.grid_bits, p.quantiser, p.order == 1, perm, textures, ctx->arena,
+                                 range, ctx->stream),
             "reorder launch");
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, range, sizeof(RangeRec), hipMemcpyDeviceToHost, ctx->stream), "range read-back");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "reorder");

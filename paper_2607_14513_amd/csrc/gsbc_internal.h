@@ -69,9 +69,11 @@ struct RangeRec {
 // ---- reorder (reorder.hip)
 size_t reorder_scratch_bytes(uint64_t n, uint32_t grid_bits);
 // identity: keep the input order (perm[s] = s) instead of sorting.
-hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_t grid_bits, bool identity,
-                          uint32_t *perm, uint8_t *textures, void *scratch, RangeRec *range_dev,
-                          hipStream_t st);
+// opacity: null, or per-primitive weights multiplied into every coefficient
+// first; quantiser: 0 = per-band min/max range, 1 = symmetric 99.5 % range.
+hipError_t launch_reorder(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
+                          uint32_t quantiser, bool identity, uint32_t *perm, uint8_t *textures, void *scratch,
+                          RangeRec *range_dev, hipStream_t st);
 
 // ---- encoders (bc1_encode.hip, bc7_encode.hip)
 // The encoders work on runs: a run is the consecutive blocks of one band of

@@ -64,8 +64,8 @@ __global__ void k_range_init(uint32_t *acc)
     if (t < 38) acc[t] = (t < 16 || (t >= 32 && t < 35)) ? 0xFFFFFFFFu : 0u;
 }
 
-__global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4, const float *pos,
-                                                               uint64_t n, uint32_t *acc)
+__global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4, const float *opacity,
+                                                               const float *pos, uint64_t n, uint32_t *acc)
 {
     __shared__ uint32_t s_acc[38];
     if (threadIdx.x < 38) s_acc[threadIdx.x] = (threadIdx.x < 16 || (threadIdx.x >= 32 && threadIdx.x < 35)) ? 0xFFFFFFFFu : 0u;
@@ -80,6 +80,11 @@ __global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4
     for (uint64_t q = t; q < nq; q += T) {
         float4 v = sh4[q];
         float f[4] = {v.x, v.y, v.z, v.w};
+        if (opacity) {   // H~ = mu H (FP32 products)
+            const float mu = opacity[q / 12];
+#pragma unroll
+            for (int c = 0; c < 4; c++) f[c] = mu * f[c];
+        }
 #pragma unroll
         for (int c = 0; c < 4; c++) {
             if ((4 * j + c) / 3 == bandA) { minA = fminf(minA, f[c]); maxA = fmaxf(maxA, f[c]); }
@@ -112,11 +117,18 @@ __global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4
 // Signed zero: the range endpoints are values, stored as +0 when zero.
 __device__ __forceinline__ float canon_zero(float x) { return x == 0.0f ? 0.0f : x; }
 
-__global__ void k_range_final(const uint32_t *acc, uint32_t grid_bits, RangeRec *r)
+// cov: null for the min/max range, else the coverage state (prefix[16] =
+// bit pattern of t per band after the last selection pass) for [-t, t].
+__global__ void k_range_final(const uint32_t *acc, const uint32_t *cov, uint32_t grid_bits, RangeRec *r)
 {
     int k = threadIdx.x;
     if (k < 16) {
         float lo = canon_zero(float_of(acc[k])), hi = canon_zero(float_of(acc[16 + k]));
+        if (cov) {
+            const float t = __uint_as_float(cov[k]);
+            lo = canon_zero(-t);
+            hi = t;
+        }
         r->vmin[k] = lo;
         r->vmax[k] = hi;
         float range = hi - lo;
@@ -131,7 +143,7 @@ __global__ void k_range_final(const uint32_t *acc, uint32_t grid_bits, RangeRec 
     }
 }
 
-__global__ __launch_bounds__(256) void k_keys(const float *pos, const float *sh, uint64_t n,
+__global__ __launch_bounds__(256) void k_keys(const float *pos, const float *sh, const float *opacity, uint64_t n,
                                               uint32_t grid_bits, const RangeRec *r,
                                               uint64_t *keys, uint32_t *vals)
 {
@@ -147,9 +159,12 @@ __global__ __launch_bounds__(256) void k_keys(const float *pos, const float *sh,
         cell[a] = v < cmax ? v : cmax;
     }
     const float *dc = sh + i * 48;
-    uint32_t q0 = quant8(dc[0], r->vmin[0], r->scale[0]);
-    uint32_t q1 = quant8(dc[1], r->vmin[0], r->scale[0]);
-    uint32_t q2 = quant8(dc[2], r->vmin[0], r->scale[0]);
+    const float mu = opacity ? opacity[i] : 1.0f;
+    float d0 = dc[0], d1 = dc[1], d2 = dc[2];
+    if (opacity) { d0 = mu * d0; d1 = mu * d1; d2 = mu * d2; }
+    uint32_t q0 = quant8(d0, r->vmin[0], r->scale[0]);
+    uint32_t q1 = quant8(d1, r->vmin[0], r->scale[0]);
+    uint32_t q2 = quant8(d2, r->vmin[0], r->scale[0]);
     uint64_t chunk = spread3(cell[0]) | (spread3(cell[1]) << 1) | (spread3(cell[2]) << 2);
     uint32_t colour = (spread3(q0) << 2) | (spread3(q1) << 1) | spread3(q2);
     keys[i] = (chunk << 24) | colour;
@@ -254,8 +269,8 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *keys_in, 
 }
 
 // Slot s -> block s/16, texel zigzag(s%16); 16 band texels per slot.
-__global__ __launch_bounds__(256) void k_gather_pack(const float *sh, const uint32_t *perm, uint64_t n,
-                                                     uint64_t nblk, const RangeRec *r, uint32_t *tex)
+__global__ __launch_bounds__(256) void k_gather_pack(const float *sh, const float *opacity, const uint32_t *perm,
+                                                     uint64_t n, uint64_t nblk, const RangeRec *r, uint32_t *tex)
 {
     uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nblk * 16) return;
@@ -271,6 +286,11 @@ __global__ __launch_bounds__(256) void k_gather_pack(const float *sh, const uint
         float4 v = p[c];
         f[4 * c] = v.x; f[4 * c + 1] = v.y; f[4 * c + 2] = v.z; f[4 * c + 3] = v.w;
     }
+    if (opacity) {
+        const float mu = opacity[src];
+#pragma unroll
+        for (int e = 0; e < 48; e++) f[e] = mu * f[e];
+    }
 #pragma unroll
     for (int k = 0; k < 16; k++) {
         float vm = r->vmin[k], sc = r->scale[k];
@@ -280,8 +300,80 @@ __global__ __launch_bounds__(256) void k_gather_pack(const float *sh, const uint
     }
 }
 
+// ---- the coverage range: per band the r-th smallest |x| over its 3n
+// coefficients, by radix selection on the bit patterns of |x| (non-negative
+// floats order like their bits): four passes over bits 30..23, 22..15,
+// 14..7 and 6..0, each a histogram of the next digit among the values that
+// match the prefix chosen so far, then a scan that picks the digit holding
+// the remaining rank.
+constexpr int kCovWG = 256;
+constexpr uint64_t kCoverNum = 995, kCoverDen = 1000;   // 99.5 % of each band inside [-t, t]                    // workgroups of the histogram pass
+constexpr int kCovShift[4] = {23, 15, 7, 0};
+constexpr int kCovWidth[4] = {8, 8, 8, 7};
+
+// part[wg][band][256]: this workgroup's digit counts; state[band] = prefix,
+// state[16 + band] = remaining rank.
+__global__ __launch_bounds__(kRangeBlock) void k_cov_hist(const float4 *sh4, const float *opacity, uint64_t n,
+                                                          int pass, const uint32_t *state, uint32_t *part)
+{
+    __shared__ uint32_t h[16][256];
+    for (int e = threadIdx.x; e < 16 * 256; e += kRangeBlock) h[e >> 8][e & 255] = 0;
+    __syncthreads();
+    const int shift = kCovShift[pass], width = kCovWidth[pass];
+    const uint64_t T = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = (int)(t % 12);
+    const uint64_t nq = n * 12;
+    for (uint64_t q = t; q < nq; q += T) {
+        float4 v = sh4[q];
+        float f[4] = {v.x, v.y, v.z, v.w};
+        const float mu = opacity ? opacity[q / 12] : 1.0f;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const int band = (4 * j + c) / 3;
+            const uint32_t u = __float_as_uint(opacity ? mu * f[c] : f[c]) & 0x7FFFFFFFu;
+            if (pass > 0 && (u >> (shift + width)) != state[band]) continue;
+            atomicAdd(&h[band][(u >> shift) & ((1u << width) - 1u)], 1u);
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * 256; e += kRangeBlock)
+        part[(uint64_t)blockIdx.x * 4096 + e] = h[e >> 8][e & 255];
+}
+
+// One workgroup per band, one thread per digit: total the partial counts,
+// scan, and keep the digit whose cumulative count reaches the rank.
+__global__ __launch_bounds__(256) void k_cov_select(const uint32_t *part, uint32_t nwg, int pass, uint32_t *state)
+{
+    __shared__ uint32_t scan[256];
+    const int band = blockIdx.x, d = threadIdx.x;
+    uint32_t c = 0;
+    for (uint32_t w = 0; w < nwg; w++) c += part[(uint64_t)w * 4096 + band * 256 + d];
+    scan[d] = c;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {   // inclusive scan
+        const uint32_t x = d >= off ? scan[d - off] : 0u;
+        __syncthreads();
+        scan[d] += x;
+        __syncthreads();
+    }
+    const uint32_t rank = state[16 + band], incl = scan[d], excl = incl - c;
+    if (c > 0 && excl < rank && rank <= incl) {
+        state[band] = (state[band] << kCovWidth[pass]) | (uint32_t)d;
+        state[16 + band] = rank - excl;
+    }
+}
+
+__global__ void k_cov_init(uint32_t *state, uint32_t rank)
+{
+    if (threadIdx.x < 16) {
+        state[threadIdx.x] = 0;
+        state[16 + threadIdx.x] = rank;
+    }
+}
+
 struct Layout {
-    size_t acc, keys_a, keys_b, vals_a, vals_b, hist, total, bytes;
+    size_t acc, keys_a, keys_b, vals_a, vals_b, hist, total, cov_state, cov_part, bytes;
 };
 
 Layout layout(uint64_t n)
@@ -297,6 +389,8 @@ Layout layout(uint64_t n)
     L.vals_b = o; o += al(n * 4);
     L.hist = o; o += al(ntiles * kDigits * 4);
     L.total = o; o += al(kDigits * 4);
+    L.cov_state = o; o += al(32 * 4);
+    L.cov_part = o; o += al((size_t)kCovWG * 4096 * 4);
     L.bytes = o;
     return L;
 }
@@ -312,9 +406,9 @@ __global__ void k_iota(uint32_t *perm, uint64_t n)
     if (s < n) perm[s] = (uint32_t)s;
 }
 
-hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_t grid_bits, bool identity,
-                          uint32_t *perm, uint8_t *textures, void *scratch, RangeRec *range_dev,
-                          hipStream_t st)
+hipError_t launch_reorder(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
+                          uint32_t quantiser, bool identity, uint32_t *perm, uint8_t *textures, void *scratch,
+                          RangeRec *range_dev, hipStream_t st)
 {
     Layout L = layout(n);
     char *s = static_cast<char *>(scratch);
@@ -327,16 +421,30 @@ hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_
     uint64_t want = (n * 12 + kRangeBlock - 1) / kRangeBlock;
     uint32_t nb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 2048);
     GSBC_LAUNCH("range_partial", k_range_partial, dim3(nb), dim3(kRangeBlock), 0, st,
-                       reinterpret_cast<const float4 *>(sh), pos, n, acc);
-    GSBC_LAUNCH("range_final", k_range_final, dim3(1), dim3(64), 0, st, acc, grid_bits, range_dev);
+                       reinterpret_cast<const float4 *>(sh), opacity, pos, n, acc);
+    uint32_t *cov = nullptr;
+    if (quantiser == 1) {
+        cov = reinterpret_cast<uint32_t *>(s + L.cov_state);
+        uint32_t *part = reinterpret_cast<uint32_t *>(s + L.cov_part);
+        // 1-based rank of the covering magnitude among the 3n per band
+        const uint32_t rank = (uint32_t)((3 * n * kCoverNum + kCoverDen - 1) / kCoverDen);
+        GSBC_LAUNCH("cov_init", k_cov_init, dim3(1), dim3(64), 0, st, cov, rank);
+        const uint32_t ncw = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), kCovWG);
+        for (int pass = 0; pass < 4; pass++) {
+            GSBC_LAUNCH("cov_hist", k_cov_hist, dim3(ncw), dim3(kRangeBlock), 0, st,
+                        reinterpret_cast<const float4 *>(sh), opacity, n, pass, cov, part);
+            GSBC_LAUNCH("cov_select", k_cov_select, dim3(16), dim3(256), 0, st, part, ncw, pass, cov);
+        }
+    }
+    GSBC_LAUNCH("range_final", k_range_final, dim3(1), dim3(64), 0, st, acc, cov, grid_bits, range_dev);
     if (identity) {
         GSBC_LAUNCH("iota", k_iota, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, perm, n);
         const uint64_t nblk = (n + 15) / 16;
         GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((nblk * 16 + 255) / 256)), dim3(256), 0, st,
-                    sh, perm, n, nblk, range_dev, reinterpret_cast<uint32_t *>(textures));
+                    sh, opacity, perm, n, nblk, range_dev, reinterpret_cast<uint32_t *>(textures));
         return hipGetLastError();
     }
-    GSBC_LAUNCH("keys", k_keys, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, pos, sh, n,
+    GSBC_LAUNCH("keys", k_keys, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, pos, sh, opacity, n,
                        grid_bits, range_dev, ka, va);
 
     const int key_bits = 24 + 3 * (int)grid_bits;
@@ -359,7 +467,7 @@ hipError_t launch_reorder(const float *pos, const float *sh, uint64_t n, uint32_
     }
     uint64_t nblk = (n + 15) / 16;
     GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((nblk * 16 + 255) / 256)), dim3(256), 0, st,
-                       sh, perm, n, nblk, range_dev, reinterpret_cast<uint32_t *>(textures));
+                       sh, opacity, perm, n, nblk, range_dev, reinterpret_cast<uint32_t *>(textures));
     return hipGetLastError();
 }
 

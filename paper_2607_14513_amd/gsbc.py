@@ -31,7 +31,8 @@ class GsbcError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("grid_bits", ctypes.c_uint32), ("refine_steps", ctypes.c_uint32),
-                ("bc7_mode_mask", ctypes.c_uint32), ("order", ctypes.c_uint32)]
+                ("bc7_mode_mask", ctypes.c_uint32), ("order", ctypes.c_uint32),
+                ("quantiser", ctypes.c_uint32)]
 
 
 class BatchTuning(ctypes.Structure):
@@ -83,7 +84,7 @@ def load():
         lib.gsbc_default_params.argtypes = [ctypes.POINTER(Params)]
         lib.gsbc_default_params.restype = None
         lib.gsbc_query_sizes.argtypes = [u64, u32, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)]
-        lib.gsbc_reorder.argtypes = [P, P, P, u64, ctypes.POINTER(Params), P, P, ctypes.POINTER(StreamDesc)]
+        lib.gsbc_reorder.argtypes = [P, P, P, P, u64, ctypes.POINTER(Params), P, P, ctypes.POINTER(StreamDesc)]
         lib.gsbc_encode.argtypes = [P, P, ctypes.POINTER(StreamDesc), ctypes.c_int, ctypes.c_double,
                                     ctypes.POINTER(Params), P, u64, P]
         lib.gsbc_default_batch_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
@@ -108,6 +109,8 @@ def default_params(**kw):
     p = Params()
     load().gsbc_default_params(ctypes.byref(p))
     for k, v in kw.items():
+        if k not in dict(Params._fields_):
+            raise TypeError(f"unknown parameter {k!r}")
         setattr(p, k, int(v))
     return p
 
@@ -209,12 +212,16 @@ class Context:
         return out
 
     # ------------------------------------------------------------- calls
-    def reorder(self, pos, sh, params=None, out=None):
-        """pos float32[n][3], sh float32[n][16][3] on the device ->
-        (perm uint32-as-int32[n], textures uint8[16][nblk][16][4], desc)."""
+    def reorder(self, pos, sh, params=None, out=None, opacity=None):
+        """pos float32[n][3], sh float32[n][16][3], opacity float32[n] or None
+        on the device -> (perm uint32-as-int32[n], textures uint8[16][nblk][16][4], desc)."""
         _dev_tensor(pos, torch.float32, "pos")
         _dev_tensor(sh, torch.float32, "sh")
         n = pos.shape[0]
+        if opacity is not None:
+            _dev_tensor(opacity, torch.float32, "opacity")
+            if opacity.numel() != n:
+                raise ValueError("opacity must hold one weight per primitive")
         nblk = (n + 15) // 16
         if out is None:
             perm = torch.empty(n, dtype=torch.int32, device=self.device)
@@ -223,7 +230,8 @@ class Context:
             perm, tex = out
         desc = StreamDesc()
         p = params if params is not None else default_params()
-        self._check(load().gsbc_reorder(self._h, _ptr(pos), _ptr(sh), n, ctypes.byref(p), _ptr(perm),
+        self._check(load().gsbc_reorder(self._h, _ptr(pos), _ptr(sh),
+                                        _ptr(opacity) if opacity is not None else None, n, ctypes.byref(p), _ptr(perm),
                                         _ptr(tex), ctypes.byref(desc)))
         return perm, tex, desc
 

@@ -68,6 +68,16 @@ def make_scene_device(n, clusters=32, comps=64, seed=1, device="cuda"):
     return pos.float().contiguous(), sh
 
 
+def make_opacity(n, seed=1):
+    """float32[n] opacities in (0, 1]: a mix of nearly opaque primitives,
+    faint ones and a uniform middle, the spread a trained scene shows."""
+    rng = _rng(seed + 104729)
+    kind = rng.random(n)
+    a = np.where(kind < 0.45, 1.0 - 0.1 * rng.random(n),
+                 np.where(kind < 0.7, 0.05 * rng.random(n) + 1e-3, rng.random(n) * 0.999 + 1e-3))
+    return a.astype(np.float32)
+
+
 def make_dirs(v, seed=1):
     """float32[v][3] unit view directions."""
     rng = _rng(seed + 7919)

@@ -134,14 +134,82 @@ def test_reorder_identity_order(G, n, seed):
     assert e.value.status == gsbc.E_ARG
 
 
-def test_reorder_full_size(G):
-    """1,048,576 primitives: permutation, ranges and textures bit-exact."""
+@pytest.mark.parametrize("n,seed,opaque,quant", [(1, 31, True, 1), (17, 32, True, 0), (333, 33, False, 1),
+                                                  (4101, 34, True, 1), (65_536, 35, True, 1)])
+def test_reorder_preprocessing(G, n, seed, opaque, quant):
+    """Sec. V-A preprocessing: opacity-premultiplied coefficients and the
+    symmetric 99.5 % coverage range; perm, ranges and textures bit-exact."""
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(n, seed=seed)
+    mu = synth.make_opacity(n, seed=seed) if opaque else None
+    say("reorder preprocessing", n, opaque, quant)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh), opacity=dev(mu) if opaque else None,
+                               params=gsbc.default_params(quantiser=quant))
+    rperm, rtex, rvmin, rvmax = O.reorder(pos, sh, opacity=mu, quantiser=quant)
+    vmin, vmax = d.ranges()
+    assert np.array_equal(vmin.view(np.uint32), rvmin.view(np.uint32))
+    assert np.array_equal(vmax.view(np.uint32), rvmax.view(np.uint32))
+    assert np.array_equal(host(perm).view(np.uint32), rperm)
+    assert np.array_equal(host(tex), rtex)
+
+
+def test_reorder_coverage_ties_and_zero_bands(G):
+    """Coverage range with heavy ties, a band that is all zero (t = 0, signed
+    zeros), a band with one large outlier, and identity order."""
+    gsbc, ctx = G
+    n = 2000
+    pos, sh = synth.make_scene(n, seed=36)
+    sh[:, 2, :] = np.float32(0.0)
+    sh[::2, 2, 1] = np.float32(-0.0)
+    sh[:, 5, :] = np.float32(0.25)
+    sh[::3, 5, :] = np.float32(-0.25)
+    sh[:, 7, :] = np.float32(1e-3)
+    sh[0, 7, 0] = np.float32(50.0)
+    mu = synth.make_opacity(n, seed=36)
+    mu[::5] = np.float32(0.0)
+    for order in (0, 1):
+        perm, tex, d = ctx.reorder(dev(pos), dev(sh), opacity=dev(mu),
+                                   params=gsbc.default_params(quantiser=1, order=order))
+        if order == 0:
+            rperm, rtex, rvmin, rvmax = O.reorder(pos, sh, opacity=mu, quantiser=1)
+        else:
+            p = O.premultiply(sh, mu)
+            rvmin, rvmax = O.band_range_coverage(p)
+            rperm = np.arange(n, dtype=np.uint32)
+            rtex = O.pack(O.quantise(p, rvmin, rvmax), rperm)
+        vmin, vmax = d.ranges()
+        assert np.array_equal(vmin.view(np.uint32), rvmin.view(np.uint32)), order
+        assert np.array_equal(vmax.view(np.uint32), rvmax.view(np.uint32)), order
+        assert np.array_equal(host(perm).view(np.uint32), rperm), order
+        assert np.array_equal(host(tex), rtex), order
+
+
+def test_reorder_preprocessing_errors(G):
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(100, seed=37)
+    with pytest.raises(gsbc.GsbcError) as e:
+        ctx.reorder(dev(pos), dev(sh), params=gsbc.default_params(quantiser=2))
+    assert e.value.status == gsbc.E_ARG
+    with pytest.raises(ValueError):
+        ctx.reorder(dev(pos), dev(sh), opacity=dev(np.ones(99, np.float32)))
+    with pytest.raises(TypeError):
+        gsbc.default_params(quantizer=1)
+
+
+@pytest.mark.parametrize("pre", [False, True])
+def test_reorder_full_size(G, pre):
+    """1,048,576 primitives: permutation, ranges and textures bit-exact, with
+    and without the Sec. V-A preprocessing."""
     gsbc, ctx = G
     c = synth.CONFIGS["mid"]
     pos, sh = synth.make_scene(c["n"], c["clusters"], c["comps"], c["seed"])
-    say("reorder full", c["n"])
-    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
-    rperm, rtex, rvmin, rvmax = O.reorder(pos, sh)
+    mu = synth.make_opacity(c["n"], seed=c["seed"]) if pre else None
+    say("reorder full", c["n"], pre)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh), opacity=dev(mu) if pre else None,
+                               params=gsbc.default_params(quantiser=int(pre)))
+    rperm, rtex, rvmin, rvmax = O.reorder(pos, sh, opacity=mu, quantiser=int(pre))
+    assert np.array_equal(d.ranges()[0].view(np.uint32), rvmin.view(np.uint32))
+    assert np.array_equal(d.ranges()[1].view(np.uint32), rvmax.view(np.uint32))
     assert np.array_equal(host(perm).view(np.uint32), rperm)
     assert np.array_equal(host(tex), rtex)
 
