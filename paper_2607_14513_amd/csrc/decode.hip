@@ -90,14 +90,19 @@ __global__ void k_sh_basis(const float *dirs, uint32_t n, float *basis)
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 constexpr int kSlots = 256;                 // slots per workgroup
 constexpr int kCols = 3 * kSlots;           // output floats per direction
-constexpr int kDirChunk = 256;              // directions per workgroup (grid.y)
+constexpr int kDirChunk = 256;              // directions per workgroup (grid.y); their basis rows sit in LDS
+constexpr int kBasStride = 17;              // padded basis row in LDS
+constexpr int kStageStride = 196;           // padded staging row (192 columns per wave)
+constexpr int kPhase2Floats = kDirChunk * kBasStride + 4 * 16 * kStageStride;
+constexpr int kLdsFloats = kPhase2Floats > 16 * kCols ? kPhase2Floats : 16 * kCols;
 
 __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *blocks, BandArgs b,
                                                             const uint32_t *prim_idx, uint64_t m,
                                                             uint64_t n_prims, const float *basis,
                                                             uint32_t n_dirs, float *out)
 {
-    __shared__ float Hm[16][kCols];
+    __shared__ float lds[kLdsFloats];
+    float(*Hm)[kCols] = reinterpret_cast<float(*)[kCols]>(lds);
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const uint64_t j0 = (uint64_t)blockIdx.x * kSlots;
     // ---- decode: lane t -> slot j0 + t
@@ -145,18 +150,28 @@ __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *block
     const uint64_t row_stride = 3 * m;
     const uint32_t wcol0 = 16 * 12 * wave;                  // this wave's first column
     float *obase = out + 3 * j0 + wcol0;
-    // Hm is dead once every wave holds its B operands: its rows become each
-    // wave's staging area (16 rows x 192 columns), so results leave as whole
-    // row segments (each store instruction writes 256 contiguous bytes).
+    // Hm is dead once every wave holds its B operands.  It then holds this
+    // workgroup's basis rows (the A operands) and each wave's staging tile,
+    // so the direction loop issues no vector-memory loads: on this ISA one
+    // counter tracks loads and stores together, and waiting for a load would
+    // also wait for every store issued before it.
+    float *bas = lds;                                                  // [kDirChunk][kBasStride]
+    float(*stage)[kStageStride] = reinterpret_cast<float(*)[kStageStride]>(lds + kDirChunk * kBasStride) + 16 * wave;
+    const uint32_t vc0 = blockIdx.y * kDirChunk;
+    const uint32_t v_end = min(n_dirs, vc0 + kDirChunk);
+    __syncthreads();           // every wave holds its B operands
+    for (uint32_t e = t; e < kDirChunk * 16; e += kEvalBlock) {
+        const uint32_t v = vc0 + e / 16;
+        bas[(e / 16) * kBasStride + e % 16] = v < v_end ? basis[16 * (uint64_t)v + e % 16] : 0.0f;
+    }
     __syncthreads();
-    float(*stage)[192] = reinterpret_cast<float(*)[192]>(&Hm[0][0]) + 16 * wave;
-    const uint32_t v_end = min(n_dirs, (blockIdx.y + 1) * kDirChunk);
-    for (uint32_t v0 = blockIdx.y * kDirChunk; v0 < v_end; v0 += 16) {
+    for (uint32_t v0 = vc0; v0 < v_end; v0 += 16) {
         // A operand: Y[v0 + col][4s + row]
         float aop[4];
-        const uint32_t va = v0 + col;
 #pragma unroll
-        for (int s = 0; s < 4; s++) aop[s] = va < n_dirs ? basis[16 * (uint64_t)va + 4 * s + row] : 0.0f;
+        for (int s = 0; s < 4; s++) aop[s] = bas[(v0 - vc0 + col) * kBasStride + 4 * s + row];
+        // all 12 tiles staged (16 rows x 192 columns), then each row leaves as
+        // three back-to-back stores of 64 floats: 768 contiguous bytes
 #pragma unroll
         for (int q = 0; q < 12; q++) {
             floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
@@ -165,18 +180,29 @@ __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *block
 #pragma unroll
             for (int r = 0; r < 4; r++) stage[4 * row + r][16 * q + col] = acc[r];
         }
-        // rows v0..v0+15, 192 floats each = 3 x 64 lanes
-#pragma unroll 4
-        for (int rr = 0; rr < 16; rr++) {
-            const uint32_t v = v0 + rr;
-            if (v >= v_end) break;
-            float *orow = obase + v * row_stride;
+        bool cok[3];
 #pragma unroll
-            for (int h = 0; h < 3; h++) {
-                const uint32_t c = 64 * h + lane;
-                const float x = stage[rr][c];
-                if (wcol0 + c < cols_valid) __builtin_nontemporal_store(x, orow + c);
+        for (int h = 0; h < 3; h++) cok[h] = wcol0 + 64 * h + lane < cols_valid;
+        float *o = obase + v0 * row_stride + lane;
+        if (v0 + 16 <= v_end) {
+#pragma unroll
+            for (int half = 0; half < 2; half++) {
+                float x[8][3];
+#pragma unroll
+                for (int rr = 0; rr < 8; rr++)
+#pragma unroll
+                    for (int h = 0; h < 3; h++) x[rr][h] = stage[8 * half + rr][64 * h + lane];
+#pragma unroll
+                for (int rr = 0; rr < 8; rr++)
+#pragma unroll
+                    for (int h = 0; h < 3; h++)
+                        if (cok[h]) __builtin_nontemporal_store(x[rr][h], o + (8 * half + rr) * row_stride + 64 * h);
             }
+        } else {
+            for (uint32_t rr = 0; v0 + rr < v_end; rr++)
+#pragma unroll
+                for (int h = 0; h < 3; h++)
+                    if (cok[h]) __builtin_nontemporal_store(stage[rr][64 * h + lane], o + rr * row_stride + 64 * h);
         }
     }
 }

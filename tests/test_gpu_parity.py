@@ -411,7 +411,7 @@ def _oracle_payload_for_slots(rtex, fmt, slots):
     return payload, off, renum
 
 
-@pytest.mark.parametrize("n,V", [(65_536, 64), (1000 + 3, 1), (16, 7), (17, 200)])
+@pytest.mark.parametrize("n,V", [(65_536, 64), (1000 + 3, 1), (16, 7), (17, 200), (2000 + 5, 529)])
 def test_decode_eval_all_slots(G, n, V):
     gsbc, ctx = G
     pos, sh = synth.make_scene(n, seed=41)
