@@ -9,7 +9,8 @@ Steps (see the C file for the definitions and paper sections):
   band_range / pos_aabb / quantise   -- Q (Sec. V-A)
   keys                               -- K (Sec. III-C, Fig. Bit4Scan)
   sort                               -- S (Sec. III-C)
-  pack                               -- B (Fig. SetupD, Fig. ZigZagScan)
+  pack                               -- B (Fig. SetupD, Fig. ZigZagScan;
+                                        Figs. SetupA and SetupB)
   bc1_decode / bc7_decode            -- D1 / D2 (BC formats, Sec. III-B)
   bc1_encode / bc7_encode            -- E1 / E2 (BTC, Sec. III-A)
   rate_select / encode_auto          -- R (Sec. IV-B)
@@ -26,6 +27,12 @@ _lib = None
 
 FMT_BC1 = 1
 FMT_BC7 = 7
+
+# Arrangements of the band coefficients into blocks (Sec. IV-B)
+ARR_BANDS = 0   # Fig. SetupD: 16 primitives per block, one stream per band
+ARR_PRIM = 1    # Fig. SetupA: one primitive per block, one stream
+ARR_QUAD = 2    # Fig. SetupB: four primitives per four blocks, four streams
+N_STREAMS = {ARR_BANDS: 16, ARR_PRIM: 1, ARR_QUAD: 4}
 
 
 def _load():
@@ -49,6 +56,8 @@ def _load():
             "ref_sort": (None, [P, u64, P]),
             "ref_zigzag_texel": (u32, [u32]),
             "ref_pack": (None, [P, P, u64, P]),
+            "ref_pack_prim": (None, [P, P, u64, P]),
+            "ref_pack_quad": (None, [P, P, u64, P]),
             "ref_bc1_decode_block": (None, [P, P]),
             "ref_bc7_decode_block": (None, [P, P]),
             "ref_bc1_encode_block": (u32, [P, u32, P]),
@@ -61,8 +70,8 @@ def _load():
             "ref_bc7_decode": (None, [P, u64, P]),
             "ref_rate_select": (i32, [P, P, P, P, ctypes.c_double, P]),
             "ref_sh_basis": (None, [ctypes.c_double] * 3 + [P]),
-            "ref_decode_eval": (None, [P, P, P, P, P, P, u32, P, u64, P, P]),
-            "ref_decode_eval_view": (None, [P, P, P, P, P, P, P, P, P, u64, P, P]),
+            "ref_decode_eval": (None, [P, P, P, u32, P, P, P, u32, P, u64, P, P]),
+            "ref_decode_eval_view": (None, [P, P, P, u32, P, P, P, P, P, P, u64, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -153,20 +162,23 @@ def sort(k):
     return perm
 
 
-def pack(q, perm):
+def pack(q, perm, arrangement=ARR_BANDS):
+    """textures uint8[S][npad/S][16][4] of the arrangement (S streams)."""
     q = _c(q, np.uint8)
     perm = _c(perm, np.uint32)
     n = perm.shape[0]
-    nblk = (n + 15) // 16
-    tex = np.empty((16, nblk, 16, 4), np.uint8)
-    _load().ref_pack(_p(q), _p(perm), n, _p(tex))
+    npad = (n + 15) // 16 * 16
+    S = N_STREAMS[arrangement]
+    tex = np.empty((S, npad // S, 16, 4), np.uint8)
+    fn = {ARR_BANDS: "ref_pack", ARR_PRIM: "ref_pack_prim", ARR_QUAD: "ref_pack_quad"}[arrangement]
+    getattr(_load(), fn)(_p(q), _p(perm), n, _p(tex))
     return tex
 
 
-def reorder(pos, sh, grid_bits=3, opacity=None, quantiser=0):
-    """Q + K + S + B.  Returns (perm, textures[16][nblk][16][4], vmin, vmax).
+def reorder(pos, sh, grid_bits=3, opacity=None, quantiser=0, arrangement=ARR_BANDS):
+    """Q + K + S + B.  Returns (perm, textures[S][nblk][16][4], vmin, vmax).
     opacity: premultiply the coefficients first; quantiser 1: the symmetric
-    99.5 % coverage range instead of min/max."""
+    99.5 % coverage range instead of min/max; arrangement: the block packing."""
     if opacity is not None:
         sh = premultiply(sh, opacity)
     vmin, vmax = band_range_coverage(sh) if quantiser == 1 else band_range(sh)
@@ -174,7 +186,7 @@ def reorder(pos, sh, grid_bits=3, opacity=None, quantiser=0):
     q = quantise(sh, vmin, vmax)
     k = keys(pos, q, grid_bits, lo, hi)
     perm = sort(k)
-    return perm, pack(q, perm), vmin, vmax
+    return perm, pack(q, perm, arrangement), vmin, vmax
 
 
 # ---------------------------------------------------------------- D, E
@@ -231,11 +243,11 @@ def rate_select(sse1, sse7, vmin, vmax, rate):
 
 
 def stream_layout(fmt, nblk):
-    """Byte offset of each band stream in the concatenated payload (bands in order,
-    each stream 16-byte aligned) and the total payload size."""
-    off = np.zeros(16, np.uint64)
+    """Byte offset of each stream in the concatenated payload (streams in order,
+    each 16-byte aligned; one per entry of fmt) and the total payload size."""
+    off = np.zeros(len(fmt), np.uint64)
     pos = 0
-    for b in range(16):
+    for b in range(len(fmt)):
         off[b] = pos
         pos += nblk * (8 if int(fmt[b]) == FMT_BC1 else 16)
         pos = (pos + 15) // 16 * 16
@@ -243,14 +255,16 @@ def stream_layout(fmt, nblk):
 
 
 def encode(tex, fmt, refine_steps=2, mode_mask=0xFF):
-    """Encode every band of tex[16][nblk][16][4] in the given per-band formats;
-    returns (payload uint8[], offsets uint64[16], sse int64[16])."""
+    """Encode every stream of tex[S][nblk][16][4] in the given per-stream formats
+    (the first S entries of fmt); returns (payload uint8[], offsets uint64[S],
+    sse int64[S])."""
     tex = _c(tex, np.uint8)
-    nblk = tex.shape[1]
+    S, nblk = tex.shape[0], tex.shape[1]
+    fmt = np.asarray(fmt)[:S]
     off, total = stream_layout(fmt, nblk)
     payload = np.zeros(total, np.uint8)
-    sse = np.zeros(16, np.int64)
-    for b in range(16):
+    sse = np.zeros(S, np.int64)
+    for b in range(S):
         if int(fmt[b]) == FMT_BC1:
             blk, s = bc1_encode(tex[b], refine_steps)
         else:
@@ -280,9 +294,9 @@ def encode_auto(tex, vmin, vmax, rate, refine_steps=2, mode_mask=0xFF):
 
 
 def decode_stream(payload, off, fmt, nblk):
-    """Decode every band stream back to textures uint8[16][nblk][16][4]."""
-    out = np.empty((16, nblk, 16, 4), np.uint8)
-    for b in range(16):
+    """Decode every stream (one per entry of fmt) back to textures uint8[S][nblk][16][4]."""
+    out = np.empty((len(fmt), nblk, 16, 4), np.uint8)
+    for b in range(len(fmt)):
         o = int(off[b])
         if int(fmt[b]) == FMT_BC1:
             out[b] = bc1_decode(payload[o:o + nblk * 8])
@@ -299,23 +313,34 @@ def sh_basis(d):
     return Y
 
 
-def decode_eval(payload, off, fmt, vmin, vmax, dirs, slots, with_scale=True):
+def _streams16(fmt, off):
+    f = np.zeros(16, np.uint8)
+    o = np.zeros(16, np.uint64)
+    f[:len(fmt)] = fmt
+    o[:len(off)] = off
+    return f, o
+
+
+def decode_eval(payload, off, fmt, vmin, vmax, dirs, slots, with_scale=True, arrangement=ARR_BANDS):
     """FP64 decode_eval.  Returns out[V][M][3] (and scale[V][M][3])."""
+    fmt, off = _streams16(fmt, off)
     payload = _c(payload, np.uint8)
     dirs = _c(dirs, np.float32).reshape(-1, 3)
     slots = _c(slots, np.uint32)
     V, M = dirs.shape[0], slots.shape[0]
     out = np.empty((V, M, 3), np.float64)
     scale = np.empty((V, M, 3), np.float64) if with_scale else None
-    _load().ref_decode_eval(_p(payload), _p(_c(fmt, np.uint8)), _p(_c(off, np.uint64)),
+    _load().ref_decode_eval(_p(payload), _p(_c(fmt, np.uint8)), _p(_c(off, np.uint64)), int(arrangement),
                             _p(_c(vmin, np.float32)), _p(_c(vmax, np.float32)), _p(dirs), V,
                             _p(slots), M, _p(out), _p(scale) if scale is not None else None)
     return (out, scale) if with_scale else out
 
 
-def decode_eval_view(payload, off, fmt, vmin, vmax, pos, perm, view, slots, with_scale=True):
+def decode_eval_view(payload, off, fmt, vmin, vmax, pos, perm, view, slots, with_scale=True,
+                     arrangement=ARR_BANDS):
     """FP64 colour of each slot seen from view position `view` (direction
     (view - p)/|view - p| per primitive).  Returns out[M][3] (and scale)."""
+    fmt, off = _streams16(fmt, off)
     payload = _c(payload, np.uint8)
     pos = _c(pos, np.float32).reshape(-1, 3)
     perm = _c(perm, np.uint32)
@@ -324,7 +349,7 @@ def decode_eval_view(payload, off, fmt, vmin, vmax, pos, perm, view, slots, with
     M = slots.shape[0]
     out = np.empty((M, 3), np.float64)
     scale = np.empty((M, 3), np.float64) if with_scale else None
-    _load().ref_decode_eval_view(_p(payload), _p(_c(fmt, np.uint8)), _p(_c(off, np.uint64)),
+    _load().ref_decode_eval_view(_p(payload), _p(_c(fmt, np.uint8)), _p(_c(off, np.uint64)), int(arrangement),
                                  _p(_c(vmin, np.float32)), _p(_c(vmax, np.float32)), _p(pos), _p(perm),
                                  _p(view), _p(slots), M, _p(out), _p(scale) if scale is not None else None)
     return (out, scale) if with_scale else out

@@ -20,7 +20,9 @@
  *      and spatial chunk                         (Sec. III-C, last paragraph)
  *   S  stable ascending sort                     (Sec. III-C, step 2)
  *   B  16 primitives of one band -> 4x4 block    (Sec. IV-B, Fig. SetupD),
- *      zigzag texel order                        (Sec. III-C, Fig. ZigZagScan)
+ *      zigzag texel order                        (Sec. III-C, Fig. ZigZagScan);
+ *      one primitive -> one block                (Fig. SetupA);
+ *      four primitives -> four blocks            (Fig. SetupB)
  *   D1 BC1 decode, D2 BC7 decode                 (Sec. III-B, BC formats)
  *   E1 BC1 encode, E2 BC7 encode                 (Sec. III-A BTC palette and
  *      index rule; endpoint search is this project's deterministic definition)
@@ -229,6 +231,54 @@ EXPORT void ref_pack(const uint8_t *q, const uint32_t *perm, uint64_t n, uint8_t
             t[2] = q[((uint64_t)src * 16 + k) * 3 + 2];
             t[3] = 255;
         }
+    }
+}
+
+/* The other two arrangements of Sec. IV-B.  Slots past n repeat perm[n-1]
+ * as above; slots are padded to a multiple of 16 in every arrangement.
+ *   Fig. SetupA (one primitive -> one block): a single stream of npad
+ *   blocks; block s holds slot s, band k at texel k (raster order).
+ *   Fig. SetupB (four primitives -> four blocks): four streams of npad/4
+ *   blocks; stream g holds bands 4g..4g+3, block s/4 holds slots 4(s/4)..+3,
+ *   slot s%4 on row y and band k%4 in column x: texel 4 (s%4) + k%4. */
+EXPORT void ref_pack_prim(const uint8_t *q, const uint32_t *perm, uint64_t n, uint8_t *tex)
+{
+    uint64_t npad = (n + 15) / 16 * 16;
+    for (uint64_t s = 0; s < npad; s++) {
+        uint32_t src = perm[s < n ? s : n - 1];
+        for (int k = 0; k < 16; k++) {
+            uint8_t *t = tex + (s * 16 + (uint64_t)k) * 4;
+            for (int c = 0; c < 3; c++) t[c] = q[((uint64_t)src * 16 + k) * 3 + c];
+            t[3] = 255;
+        }
+    }
+}
+
+EXPORT void ref_pack_quad(const uint8_t *q, const uint32_t *perm, uint64_t n, uint8_t *tex)
+{
+    uint64_t npad = (n + 15) / 16 * 16;
+    uint64_t nblk = npad / 4;
+    for (uint64_t s = 0; s < npad; s++) {
+        uint32_t src = perm[s < n ? s : n - 1];
+        for (int k = 0; k < 16; k++) {
+            uint64_t g = (uint64_t)k / 4, b = s / 4;
+            uint32_t i = 4 * (uint32_t)(s % 4) + (uint32_t)(k % 4);
+            uint8_t *t = tex + ((g * nblk + b) * 16 + i) * 4;
+            for (int c = 0; c < 3; c++) t[c] = q[((uint64_t)src * 16 + k) * 3 + c];
+            t[3] = 255;
+        }
+    }
+}
+
+/* Where band k of slot s lives: stream, block within the stream, texel. */
+static void locate(uint32_t arr, uint32_t s, int k, int *stream, uint64_t *block, int *texel)
+{
+    if (arr == 1) {
+        *stream = 0; *block = s; *texel = k;
+    } else if (arr == 2) {
+        *stream = k / 4; *block = s / 4; *texel = 4 * (int)(s % 4) + k % 4;
+    } else {
+        *stream = k; *block = s / 16; *texel = (int)ref_zigzag_texel(s % 16);
     }
 }
 
@@ -1217,23 +1267,30 @@ EXPORT void ref_sh_basis(double x, double y, double z, double *Y)
  * out[v][j][c] = sum_k Hhat[slot][k][c] * Y_k(dir_v) with
  * Hhat = vmin_k + q * delta_k, delta_k = (vmax_k - vmin_k)/255, in FP64;
  * scale[v][j][c] = sum_k |Hhat * Y_k| (the size of the terms). */
-EXPORT void ref_decode_eval(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset,
+/* Dequantised decoded band vectors of slot s; fmt and offset are per stream. */
+static void slot_coefficients(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset, uint32_t arr,
+                              const float *vmin, const float *vmax, uint32_t s, double H[16][3])
+{
+    for (int k = 0; k < 16; k++) {
+        int st, texel;
+        uint64_t b;
+        locate(arr, s, k, &st, &b, &texel);
+        uint8_t px[64];
+        if (fmt[st] == 1) ref_bc1_decode_block(blocks + offset[st] + b * 8, px);
+        else ref_bc7_decode_block(blocks + offset[st] + b * 16, px);
+        double delta = ((double)vmax[k] - (double)vmin[k]) / 255.0;
+        for (int c = 0; c < 3; c++) H[k][c] = (double)vmin[k] + (double)px[texel * 4 + c] * delta;
+    }
+}
+
+EXPORT void ref_decode_eval(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset, uint32_t arr,
                             const float *vmin, const float *vmax, const float *dirs, uint32_t V,
                             const uint32_t *slots, uint64_t m, double *out, double *scale)
 {
     #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < (int64_t)m; j++) {
-        uint32_t s = slots[j];
-        uint64_t b = s / 16;
-        int texel = (int)ref_zigzag_texel(s % 16);
         double H[16][3];
-        for (int k = 0; k < 16; k++) {
-            uint8_t px[64];
-            if (fmt[k] == 1) ref_bc1_decode_block(blocks + offset[k] + b * 8, px);
-            else ref_bc7_decode_block(blocks + offset[k] + b * 16, px);
-            double delta = ((double)vmax[k] - (double)vmin[k]) / 255.0;
-            for (int c = 0; c < 3; c++) H[k][c] = (double)vmin[k] + (double)px[texel * 4 + c] * delta;
-        }
+        slot_coefficients(blocks, fmt, offset, arr, vmin, vmax, slots[j], H);
         for (uint32_t v = 0; v < V; v++) {
             double Y[16];
             ref_sh_basis((double)dirs[v * 3 + 0], (double)dirs[v * 3 + 1], (double)dirs[v * 3 + 2], Y);
@@ -1255,7 +1312,7 @@ EXPORT void ref_decode_eval(const uint8_t *blocks, const uint8_t *fmt, const uin
  * the unit vector d = (f - p) / |f - p| from the primitive towards the view
  * position (d = 0 when f = p), all in FP64 from the FP32 inputs.  pos is in
  * input order; perm maps a slot to its primitive. */
-EXPORT void ref_decode_eval_view(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset,
+EXPORT void ref_decode_eval_view(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset, uint32_t arr,
                                  const float *vmin, const float *vmax, const float *pos, const uint32_t *perm,
                                  const float *view, const uint32_t *slots, uint64_t m, double *out, double *scale)
 {
@@ -1272,16 +1329,8 @@ EXPORT void ref_decode_eval_view(const uint8_t *blocks, const uint8_t *fmt, cons
         for (int c = 0; c < 3; c++) d[c] = r > 0.0 ? d[c] / r : 0.0;
         double Y[16];
         ref_sh_basis(d[0], d[1], d[2], Y);
-        uint64_t b = s / 16;
-        int texel = (int)ref_zigzag_texel(s % 16);
         double H[16][3];
-        for (int k = 0; k < 16; k++) {
-            uint8_t px[64];
-            if (fmt[k] == 1) ref_bc1_decode_block(blocks + offset[k] + b * 8, px);
-            else ref_bc7_decode_block(blocks + offset[k] + b * 16, px);
-            double delta = ((double)vmax[k] - (double)vmin[k]) / 255.0;
-            for (int c = 0; c < 3; c++) H[k][c] = (double)vmin[k] + (double)px[texel * 4 + c] * delta;
-        }
+        slot_coefficients(blocks, fmt, offset, arr, vmin, vmax, s, H);
         for (int c = 0; c < 3; c++) {
             double acc = 0.0, mag = 0.0;
             for (int k = 0; k < 16; k++) {
