@@ -309,8 +309,8 @@ def batch_leg(ctx, stream, dev, n_scenes, reps):
         descs.append(d_i)
         del pos_i, sh_i
     torch.cuda.synchronize()
-    nblocks = sum(16 * d.blocks_per_band for d in descs)
-    pay = [d.blocks_per_band * (16 + 15 * 8) + 16 * 16 for d in descs]
+    nblocks = sum(16 * d.blocks_per_stream for d in descs)
+    pay = [d.blocks_per_stream * (16 + 15 * 8) + 16 * 16 for d in descs]
     plain_out = [torch.empty(p, dtype=torch.uint8, device=dev) for p in pay]
     batch_out = [torch.empty(p, dtype=torch.uint8, device=dev) for p in pay]
 

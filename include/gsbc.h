@@ -58,6 +58,19 @@ enum {
 
 enum { GSBC_FMT_AUTO = 0, GSBC_FMT_BC1 = 1, GSBC_FMT_BANDS = 2, GSBC_FMT_BC7 = 7 };
 
+/* Arrangements of the 16 band vectors of the primitives into 4x4 blocks
+ * (Sec. IV-B).  Slots are padded to n_pad (a multiple of 16) by repeating
+ * slot n-1; an arrangement with S streams has n_pad/S blocks per stream.
+ *   GSBC_ARR_BANDS (Fig. SetupD, default): S = 16; stream k holds band k,
+ *       block s/16, slot s%16 at the zigzag texel 4y+x, x = j0|j2<<1,
+ *       y = j1|j3<<1 (j = s%16).
+ *   GSBC_ARR_PRIM (Fig. SetupA): S = 1; block s holds slot s, band k at
+ *       texel k.
+ *   GSBC_ARR_QUAD (Fig. SetupB): S = 4; stream g holds bands 4g..4g+3,
+ *       block s/4, texel 4*(s%4) + k%4 (slot on the row, band on the
+ *       column). */
+enum { GSBC_ARR_BANDS = 0, GSBC_ARR_PRIM = 1, GSBC_ARR_QUAD = 2 };
+
 typedef struct gsbc_ctx gsbc_ctx;
 
 typedef struct {
@@ -67,6 +80,7 @@ typedef struct {
     uint32_t order;          /* gsbc_reorder: 0 = sort by (spatial cell, colour) (default);
                                 1 = keep the input order (perm[s] = s), the unsorted
                                 baseline the paper compares sorting against (Sec. III-C) */
+    uint32_t arrangement;    /* gsbc_reorder: GSBC_ARR_BANDS (default), GSBC_ARR_PRIM or GSBC_ARR_QUAD */
     uint32_t quantiser;      /* gsbc_reorder: per-band range of the 8-bit quantiser (Sec. V-A):
                                 0 = [min, max] of the band's coefficients (default);
                                 1 = [-t, t] with t the ceil(0.995 * 3n)-th smallest |x| of
@@ -74,16 +88,18 @@ typedef struct {
                                     and the rest clamp (vmin = +0 when t = 0) */
 } gsbc_params;
 
-/* Header of a coded scene: one bitstream per SH band (Sec. IV-A: typed
- * bitstreams; the stream index selects the decoder). */
+/* Header of a coded scene: one bitstream per stream of the arrangement
+ * (Sec. IV-A: typed bitstreams; the stream index selects the decoder). */
 typedef struct {
-    uint8_t format[16];          /* per band: GSBC_FMT_BC1 or GSBC_FMT_BC7 */
-    uint64_t offset[16];         /* byte offset of band k's stream in the payload (16-byte aligned) */
+    uint8_t format[16];          /* per stream: GSBC_FMT_BC1 or GSBC_FMT_BC7 (entries past n_streams unused) */
+    uint64_t offset[16];         /* byte offset of stream s in the payload (16-byte aligned) */
     float vmin[16], vmax[16];    /* per-band quantiser range: q = rint((x - vmin) * 255/(vmax - vmin)) */
     uint64_t n_prims;            /* N */
     uint64_t n_pad;              /* N rounded up to a multiple of 16 */
-    uint64_t blocks_per_band;    /* n_pad / 16 */
-    uint64_t payload_bytes;      /* bytes of the concatenated band streams */
+    uint64_t blocks_per_stream;  /* n_pad / n_streams */
+    uint64_t payload_bytes;      /* bytes of the concatenated streams */
+    uint32_t arrangement;        /* GSBC_ARR_* of the textures */
+    uint32_t n_streams;          /* 16, 1 or 4 (BANDS, PRIM, QUAD) */
 } gsbc_stream_desc;
 
 /* ---------------------------------------------------------------- context */
@@ -105,12 +121,13 @@ GSBC_API const char *gsbc_last_error(const gsbc_ctx *ctx);
 GSBC_API gsbc_status gsbc_sync(gsbc_ctx *ctx);
 
 /* Fill `p` (host) with the defaults: grid_bits 3, refine_steps 2, mode mask 0xFF, order 0,
- * quantiser 0. */
+ * arrangement GSBC_ARR_BANDS, quantiser 0. */
 GSBC_API void gsbc_default_params(gsbc_params *p);
 
 /* Sizes in bytes for N primitives and V directions (any output may be NULL):
- * textures: uint8[16][n_pad/16][16][4];  max_blocks: the payload when every
- * band is BC7 (an upper bound for any format choice);  out: float[V][N][3]. */
+ * textures: n_pad * 64 bytes (uint8[S][n_pad/S][16][4] in every arrangement);
+ * max_blocks: the payload when every stream is BC7 (an upper bound for any
+ * format choice and arrangement);  out: float[V][N][3]. */
 GSBC_API gsbc_status gsbc_query_sizes(uint64_t n, uint32_t n_dirs, uint64_t *textures_bytes,
                              uint64_t *max_blocks_bytes, uint64_t *out_bytes);
 
@@ -125,13 +142,15 @@ GSBC_API gsbc_status gsbc_query_sizes(uint64_t n, uint32_t n_dirs, uint64_t *tex
  *           opacity-premultiplied colours of Sec. V-A); the range, keys and
  *           textures all use the products
  *   n       1 .. 2^31-1 primitives (quantiser 1: 3n < 2^32)
- *   params  host, NULL for defaults (grid_bits, order, quantiser are used)
+ *   params  host, NULL for defaults (grid_bits, order, arrangement and
+ *           quantiser are used)
  *   perm    device uint32[n]        out: perm[s] = original index at slot s
- *   textures device uint8[16][n_pad/16][16][4] out: band k, block b, texel
- *           4y+x holds the 8-bit RGB (alpha 255) of slot 16b+j, j placed at
- *           the 2-D zigzag position x = j0|j2<<1, y = j1|j3<<1; slots past n
- *           repeat slot n-1
- *   desc    host, out: vmin, vmax, n_prims, n_pad, blocks_per_band filled
+ *   textures device uint8[S][n_pad/S][16][4] out: the 8-bit RGB (alpha 255)
+ *           of every (slot, band) at the stream, block and texel the
+ *           arrangement assigns (GSBC_ARR_*; n_pad * 64 bytes in every
+ *           arrangement); slots past n repeat slot n-1
+ *   desc    host, out: vmin, vmax, n_prims, n_pad, blocks_per_stream,
+ *           arrangement, n_streams filled
  * Keys: (Morton cell of the position on a 2^g grid over the bounding box) << 24
  * | interleaved bits of the band-0 quantised R,G,B (R highest in each triple);
  * stable ascending sort.  Inputs must be finite. */
@@ -139,13 +158,16 @@ GSBC_API gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *
                          uint64_t n, const gsbc_params *params, uint32_t *perm, uint8_t *textures,
                          gsbc_stream_desc *desc);
 
-/* Encode every band (Sec. III-A BTC; Sec. IV-B per-bitstream formats).
+/* Encode every stream (Sec. III-A BTC; Sec. IV-B per-bitstream formats).
  *   textures device, layout of gsbc_reorder; desc host, in: n_prims, n_pad,
- *            blocks_per_band, vmin, vmax; out: format, offset, payload_bytes
- *   format   GSBC_FMT_BC1 or GSBC_FMT_BC7 for all bands; GSBC_FMT_BANDS for
- *            the per-band formats the caller put in desc->format[k] (each
- *            BC1 or BC7, e.g. band 0 BC7 and the rest BC1 as in Sec. V); or
- *            GSBC_FMT_AUTO:
+ *            blocks_per_stream, arrangement, n_streams, vmin, vmax; out:
+ *            format, offset, payload_bytes
+ *   format   GSBC_FMT_BC1 or GSBC_FMT_BC7 for all streams; GSBC_FMT_BANDS
+ *            for the per-stream formats the caller put in desc->format[s]
+ *            (each BC1 or BC7, e.g. band 0 BC7 and the rest BC1 as in
+ *            Sec. V, or the first SetupB stream BC7 and the other three BC1
+ *            as in Table I); or GSBC_FMT_AUTO (GSBC_ARR_BANDS only, else
+ *            GSBC_E_UNSUPPORTED):
  *            every band is coded in both formats, then band 0 is BC7 and of
  *            bands 1..15 the k = 4*rate - 17 with the largest
  *            (SSE_BC1 - SSE_BC7) * delta_k^2 are BC7 (lower band first on
@@ -154,12 +176,12 @@ GSBC_API gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *
  *            delta_k = (vmax_k - vmin_k)/255 in FP32; `rate` is ignored
  *            otherwise
  *   params   host, NULL for defaults (refine_steps, bc7_mode_mask are used)
- *   blocks   device uint8[blocks_capacity] out: band k's blocks at offset[k],
- *            8 bytes (BC1) or 16 bytes (BC7) each; GSBC_E_BUFFER if
- *            blocks_capacity < payload size
- *   band_sse host int64[2][16] or NULL, out: total RGB SSE of each band coded
- *            in BC1 (row 0) and BC7 (row 1) over all n_pad slots, -1 where that
- *            format was not coded */
+ *   blocks   device uint8[blocks_capacity] out: stream s's blocks at
+ *            offset[s], 8 bytes (BC1) or 16 bytes (BC7) each; GSBC_E_BUFFER
+ *            if blocks_capacity < payload size
+ *   band_sse host int64[2][16] or NULL, out: total RGB SSE of each stream
+ *            coded in BC1 (row 0) and BC7 (row 1) over all its blocks, -1
+ *            where that format was not coded or the stream does not exist */
 GSBC_API gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc *desc,
                         int format, double rate, const gsbc_params *params, uint8_t *blocks,
                         uint64_t blocks_capacity, int64_t *band_sse);
@@ -205,21 +227,22 @@ GSBC_API void gsbc_default_batch_tuning(gsbc_batch_tuning *t);
  *   n_scenes         1..4096
  *   textures         host array of n_scenes device pointers (gsbc_reorder layout)
  *   descs            host array of n_scenes; in: n_prims, n_pad,
- *                    blocks_per_band, vmin, vmax and format[16] (each BC1
- *                    or BC7); out: offset, payload_bytes
+ *                    blocks_per_stream, arrangement, n_streams, vmin, vmax
+ *                    and format[s] (each BC1 or BC7) of every stream; out:
+ *                    offset, payload_bytes
  *   blocks           host array of n_scenes device pointers, 16-byte aligned
  *   blocks_capacity  host uint64[n_scenes]: bytes behind each blocks[i]
  *                    (GSBC_E_BUFFER if below the scene's payload)
  *   params, tuning   host, or NULL for the defaults
- *   band_sse         host int64[n_scenes][16] or NULL, out: each band's SSE
- *                    in its format; when given the call waits for the
+ *   band_sse         host int64[n_scenes][16] or NULL, out: each stream's
+ *                    SSE in its format (0 past n_streams); when given the call waits for the
  *                    stream, otherwise it returns once the graph is queued */
 GSBC_API gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *const *textures,
                                        gsbc_stream_desc *descs, uint8_t *const *blocks,
                                        const uint64_t *blocks_capacity, const gsbc_params *params,
                                        const gsbc_batch_tuning *tuning, int64_t *band_sse);
 
-/* Decode every band back to textures (layout of gsbc_reorder) -- BC1 and BC7
+/* Decode every stream back to textures (layout of gsbc_reorder) -- BC1 and BC7
  * decoders of the format definitions; BC1 interpolants rounded to nearest.
  *   blocks device, desc host (filled by gsbc_encode), textures_out device. */
 GSBC_API gsbc_status gsbc_decode(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_desc *desc,
@@ -228,7 +251,8 @@ GSBC_API gsbc_status gsbc_decode(gsbc_ctx *ctx, const uint8_t *blocks, const gsb
 /* Random-access decode + SH evaluation (Sec. II colour equation; Sec. I
  * random access).  For every direction v and listed slot j:
  *   out[v][j][c] = sum_k Hhat_k[c] * Y_k(dir_v),
- *   Hhat_k = vmin_k + qhat * (vmax_k - vmin_k)/255 with qhat the decoded texel,
+ *   Hhat_k = vmin_k + qhat * (vmax_k - vmin_k)/255 with qhat the decoded
+ *   texel of (slot, band k), found through the arrangement,
  *   Y_k the real SH basis of degree <= 3 (k = l^2 + l + m, 3DGS signs), FP32.
  *   blocks   device payload; desc host (filled by gsbc_encode)
  *   dirs     device float[n_dirs][3], used as given (no normalisation)
@@ -258,14 +282,17 @@ GSBC_API gsbc_status gsbc_decode_eval_view(gsbc_ctx *ctx, const uint8_t *blocks,
 /* ---------------------------------------------------------------- container */
 
 /* The durable form of a coded scene: fixed-size blocks in one bitstream per
- * band, found by index times block size (Sec. I; Sec. IV-A typed streams).
+ * stream, found by index times block size (Sec. I; Sec. IV-A typed streams).
  * Little-endian file layout:
- *   bytes 0..63     header: "GSBC" magic, u32 version (1), u64 n_prims,
- *                   u64 n_pad, u64 blocks_per_band, u64 payload_bytes,
- *                   u32 record bytes (24), zero padding to 64
- *   16 x 24 bytes   band records: u32 format, u32 0, u64 offset, f32 vmin,
- *                   f32 vmax
- *   payload         payload_bytes bytes, band k at offset[k]
+ *   bytes 0..63     header: "GSBC" magic, u32 version (2), u64 n_prims,
+ *                   u64 n_pad, u64 blocks_per_stream, u64 payload_bytes,
+ *                   u32 record bytes (24), u32 arrangement, u32 n_streams,
+ *                   zero padding to 64 (version 1 files, written before
+ *                   arrangements existed, hold GSBC_ARR_BANDS)
+ *   16 x 24 bytes   records k = 0..15: u32 format of stream k (0 past
+ *                   n_streams), u32 0, u64 offset of stream k, f32 vmin of
+ *                   band k, f32 vmax of band k
+ *   payload         payload_bytes bytes, stream s at offset[s]
  * gsbc_save copies the payload from the device (waits for the stream) and
  * writes the file.  gsbc_load reads and checks it (GSBC_E_IO if the magic,
  * version, record size, sizes or stream layout are wrong, or the file is

@@ -40,7 +40,7 @@ def workload_key(descs, params=None):
     h = hashlib.sha1()
     h.update(f"{p.refine_steps},{p.bc7_mode_mask}".encode())
     for d in descs:
-        h.update(f"{d.blocks_per_band}:{''.join(str(int(f)) for f in d.formats())};".encode())
+        h.update(f"{d.blocks_per_stream}:{''.join(str(int(f)) for f in d.formats())};".encode())
     props = torch.cuda.get_device_properties(torch.cuda.current_device())
     return f"{props.name}|{props.multi_processor_count}|{h.hexdigest()[:16]}"
 

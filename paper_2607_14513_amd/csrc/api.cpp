@@ -129,6 +129,8 @@ gsbc_status ensure_arena(gsbc_ctx *ctx, size_t bytes)
 }
 
 uint64_t pad16(uint64_t n) { return (n + 15) / 16 * 16; }
+// Streams of an arrangement: one per band, one, or one per band group.
+uint32_t streams_of(uint32_t arr) { return arr == GSBC_ARR_PRIM ? 1u : arr == GSBC_ARR_QUAD ? 4u : 16u; }
 uint64_t align16(uint64_t x) { return (x + 15) & ~(uint64_t)15; }
 
 gsbc_params resolve(const gsbc_params *p)
@@ -145,6 +147,8 @@ gsbc_status check_params(gsbc_ctx *ctx, const gsbc_params &p)
     if (p.bc7_mode_mask == 0 || p.bc7_mode_mask > 0xFF) return fail(ctx, GSBC_E_ARG, "bc7_mode_mask 0x%x not in 1..0xFF", p.bc7_mode_mask);
     if (p.order > 1) return fail(ctx, GSBC_E_ARG, "order %u is not 0 (sorted) or 1 (identity)", p.order);
     if (p.quantiser > 1) return fail(ctx, GSBC_E_ARG, "quantiser %u is not 0 (min/max) or 1 (99.5%% coverage)", p.quantiser);
+    if (p.arrangement > GSBC_ARR_QUAD)
+        return fail(ctx, GSBC_E_ARG, "arrangement %u is not BANDS(0), PRIM(1) or QUAD(2)", p.arrangement);
     return GSBC_OK;
 }
 
@@ -152,9 +156,12 @@ gsbc_status check_desc(gsbc_ctx *ctx, const gsbc_stream_desc *d)
 {
     if (!d) return fail(ctx, GSBC_E_ARG, "desc is NULL");
     if (d->n_prims == 0 || d->n_prims > 0x7FFFFFFFull) return fail(ctx, GSBC_E_ARG, "desc.n_prims %llu out of range", (unsigned long long)d->n_prims);
-    if (d->n_pad != pad16(d->n_prims) || d->blocks_per_band * 16 != d->n_pad)
-        return fail(ctx, GSBC_E_ARG, "desc sizes inconsistent (n_prims %llu, n_pad %llu, blocks %llu)",
-                    (unsigned long long)d->n_prims, (unsigned long long)d->n_pad, (unsigned long long)d->blocks_per_band);
+    if (d->arrangement > GSBC_ARR_QUAD || d->n_streams != streams_of(d->arrangement))
+        return fail(ctx, GSBC_E_ARG, "desc.arrangement %u with %u streams is not a known arrangement", d->arrangement,
+                    d->n_streams);
+    if (d->n_pad != pad16(d->n_prims) || d->blocks_per_stream * d->n_streams != d->n_pad)
+        return fail(ctx, GSBC_E_ARG, "desc sizes inconsistent (n_prims %llu, n_pad %llu, blocks per stream %llu)",
+                    (unsigned long long)d->n_prims, (unsigned long long)d->n_pad, (unsigned long long)d->blocks_per_stream);
     return GSBC_OK;
 }
 
@@ -163,11 +170,11 @@ gsbc_status check_stream(gsbc_ctx *ctx, const gsbc_stream_desc *d)
     gsbc_status s = check_desc(ctx, d);
     if (s) return s;
     uint64_t pos = 0;
-    for (int k = 0; k < 16; k++) {
+    for (uint32_t k = 0; k < d->n_streams; k++) {
         if (d->format[k] != GSBC_FMT_BC1 && d->format[k] != GSBC_FMT_BC7)
-            return fail(ctx, GSBC_E_ARG, "desc.format[%d] = %u is not BC1 or BC7", k, d->format[k]);
-        if (d->offset[k] != pos) return fail(ctx, GSBC_E_ARG, "desc.offset[%d] does not follow the stream layout", k);
-        pos = align16(pos + d->blocks_per_band * (d->format[k] == GSBC_FMT_BC1 ? 8 : 16));
+            return fail(ctx, GSBC_E_ARG, "desc.format[%u] = %u is not BC1 or BC7", k, d->format[k]);
+        if (d->offset[k] != pos) return fail(ctx, GSBC_E_ARG, "desc.offset[%u] does not follow the stream layout", k);
+        pos = align16(pos + d->blocks_per_stream * (d->format[k] == GSBC_FMT_BC1 ? 8 : 16));
     }
     if (d->payload_bytes != pos) return fail(ctx, GSBC_E_ARG, "desc.payload_bytes inconsistent");
     return GSBC_OK;
@@ -176,9 +183,12 @@ gsbc_status check_stream(gsbc_ctx *ctx, const gsbc_stream_desc *d)
 BandArgs band_args(const gsbc_stream_desc *d)
 {
     BandArgs b;
+    b.arrangement = d->arrangement;
+    b.n_streams = d->n_streams;
     for (int k = 0; k < 16; k++) {
-        b.offset[k] = d->offset[k];
-        b.format[k] = d->format[k];
+        const bool live = (uint32_t)k < d->n_streams;
+        b.offset[k] = live ? d->offset[k] : 0;
+        b.format[k] = live ? d->format[k] : 0;
         b.vmin[k] = d->vmin[k];
         b.delta[k] = (d->vmax[k] - d->vmin[k]) / 255.0f;
     }
@@ -198,11 +208,13 @@ struct Runs {
     }
 };
 
-// Stream layout of the band formats: band k at offset[k], 16-byte aligned.
-uint64_t layout(const uint32_t fmt[16], uint64_t nblk, uint64_t off[16])
+// Stream layout of the formats: stream k at offset[k], 16-byte aligned;
+// entries past n_streams are zero.
+uint64_t layout(const uint32_t fmt[16], uint32_t n_streams, uint64_t nblk, uint64_t off[16])
 {
     uint64_t pos = 0;
-    for (int k = 0; k < 16; k++) {
+    for (uint32_t k = n_streams; k < 16; k++) off[k] = 0;
+    for (uint32_t k = 0; k < n_streams; k++) {
         off[k] = pos;
         pos = align16(pos + nblk * (fmt[k] == GSBC_FMT_BC1 ? 8 : 16));
     }
@@ -276,6 +288,7 @@ void gsbc_default_params(gsbc_params *p)
     p->refine_steps = 2;
     p->bc7_mode_mask = 0xFF;
     p->order = 0;
+    p->arrangement = GSBC_ARR_BANDS;
     p->quantiser = 0;
 }
 
@@ -373,8 +386,8 @@ gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, const
                     (unsigned long long)n);
     if ((s = ensure_arena(ctx, reorder_scratch_bytes(n, p.grid_bits)))) return s;
     RangeRec *range = reinterpret_cast<RangeRec *>(small_ptr(ctx, kRangeOff));
-    HIP_TRY(ctx, launch_reorder(pos, sh, opacity, n, p.grid_bits, p.quantiser, p.order == 1, perm, textures, ctx->arena,
-                                 range, ctx->stream),
+    HIP_TRY(ctx, launch_reorder(pos, sh, opacity, n, p.grid_bits, p.quantiser, p.order == 1, p.arrangement, perm,
+                                 textures, ctx->arena, range, ctx->stream),
             "reorder launch");
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, range, sizeof(RangeRec), hipMemcpyDeviceToHost, ctx->stream), "range read-back");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "reorder");
@@ -383,7 +396,9 @@ gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, const
     for (int k = 0; k < 16; k++) { desc->vmin[k] = r->vmin[k]; desc->vmax[k] = r->vmax[k]; }
     desc->n_prims = n;
     desc->n_pad = pad16(n);
-    desc->blocks_per_band = desc->n_pad / 16;
+    desc->arrangement = p.arrangement;
+    desc->n_streams = streams_of(p.arrangement);
+    desc->blocks_per_stream = desc->n_pad / desc->n_streams;
     return GSBC_OK;
 }
 
@@ -399,13 +414,16 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
     if ((s = check_desc(ctx, desc))) return s;
     if (format != GSBC_FMT_AUTO && format != GSBC_FMT_BC1 && format != GSBC_FMT_BC7 && format != GSBC_FMT_BANDS)
         return fail(ctx, GSBC_E_ARG, "format %d is not AUTO(0), BC1(1), BANDS(2) or BC7(7)", format);
+    const uint32_t S = desc->n_streams;
     if (format == GSBC_FMT_BANDS)
-        for (int k = 0; k < 16; k++)
+        for (uint32_t k = 0; k < S; k++)
             if (desc->format[k] != GSBC_FMT_BC1 && desc->format[k] != GSBC_FMT_BC7)
-                return fail(ctx, GSBC_E_ARG, "desc.format[%d] = %u is not BC1 or BC7", k, desc->format[k]);
+                return fail(ctx, GSBC_E_ARG, "desc.format[%u] = %u is not BC1 or BC7", k, desc->format[k]);
+    if (format == GSBC_FMT_AUTO && desc->arrangement != GSBC_ARR_BANDS)
+        return fail(ctx, GSBC_E_UNSUPPORTED, "the rate controller chooses formats per band: GSBC_ARR_BANDS only");
     gsbc_params p = resolve(params);
     if ((s = check_params(ctx, p))) return s;
-    const uint64_t nblk = desc->blocks_per_band;
+    const uint64_t nblk = desc->blocks_per_stream;
     unsigned long long *sse1 = reinterpret_cast<unsigned long long *>(small_ptr(ctx, kSse1Off));
     unsigned long long *sse7 = reinterpret_cast<unsigned long long *>(small_ptr(ctx, kSse7Off));
     const uint64_t tex_band = nblk * 64;
@@ -420,12 +438,13 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
     uint64_t off1[16], off7[16];
     size_t front = 0;
     if (format != GSBC_FMT_AUTO) {
-        for (int k = 0; k < 16; k++) host_fmt[k] = format == GSBC_FMT_BANDS ? desc->format[k] : (uint32_t)format;
-        payload = layout(host_fmt, nblk, host_off);
+        for (uint32_t k = 0; k < 16; k++)
+            host_fmt[k] = k >= S ? 0u : format == GSBC_FMT_BANDS ? desc->format[k] : (uint32_t)format;
+        payload = layout(host_fmt, S, nblk, host_off);
         if (blocks_capacity < payload)
             return fail(ctx, GSBC_E_BUFFER, "blocks_capacity %llu < payload %llu bytes", (unsigned long long)blocks_capacity,
                         (unsigned long long)payload);
-        for (int k = 0; k < 16; k++) {
+        for (uint32_t k = 0; k < S; k++) {
             if (host_fmt[k] == GSBC_FMT_BC7) r7.add(textures + k * tex_band, blocks + host_off[k], sse7 + k, nblk);
             else r1.add(textures + k * tex_band, blocks + host_off[k], sse1 + k, nblk);
         }
@@ -511,9 +530,9 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
     }
     if (band_sse) {
         const uint64_t *h = reinterpret_cast<const uint64_t *>(sstage);
-        for (int q = 0; q < 16; q++) {
-            const bool c1 = format == GSBC_FMT_AUTO || (have1 && host_fmt[q] == GSBC_FMT_BC1);
-            const bool c7 = format == GSBC_FMT_AUTO || (have7 && host_fmt[q] == GSBC_FMT_BC7);
+        for (uint32_t q = 0; q < 16; q++) {
+            const bool c1 = q < S && (format == GSBC_FMT_AUTO || (have1 && host_fmt[q] == GSBC_FMT_BC1));
+            const bool c7 = q < S && (format == GSBC_FMT_AUTO || (have7 && host_fmt[q] == GSBC_FMT_BC7));
             band_sse[q] = c1 ? (int64_t)h[q] : -1;
             band_sse[16 + q] = c7 ? (int64_t)h[16 + q] : -1;
         }
@@ -561,12 +580,12 @@ gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *c
         if ((reinterpret_cast<uintptr_t>(textures[i]) & 15) || (reinterpret_cast<uintptr_t>(blocks[i]) & 15))
             return fail(ctx, GSBC_E_ARG, "scene %u: textures and blocks must be 16-byte aligned", i);
         if ((s = check_desc(ctx, &descs[i]))) return s;
-        for (int k = 0; k < 16; k++) {
-            fmts[16 * i + k] = descs[i].format[k];
-            if (fmts[16 * i + k] != GSBC_FMT_BC1 && fmts[16 * i + k] != GSBC_FMT_BC7)
-                return fail(ctx, GSBC_E_ARG, "scene %u: desc.format[%d] = %u is not BC1 or BC7", i, k, descs[i].format[k]);
+        for (uint32_t k = 0; k < 16; k++) {
+            fmts[16 * i + k] = k < descs[i].n_streams ? descs[i].format[k] : 0u;
+            if (k < descs[i].n_streams && fmts[16 * i + k] != GSBC_FMT_BC1 && fmts[16 * i + k] != GSBC_FMT_BC7)
+                return fail(ctx, GSBC_E_ARG, "scene %u: desc.format[%u] = %u is not BC1 or BC7", i, k, descs[i].format[k]);
         }
-        pay[i] = layout(&fmts[16 * i], descs[i].blocks_per_band, &offs[16 * i]);
+        pay[i] = layout(&fmts[16 * i], descs[i].n_streams, descs[i].blocks_per_stream, &offs[16 * i]);
         if (blocks_capacity[i] < pay[i])
             return fail(ctx, GSBC_E_BUFFER, "scene %u: blocks_capacity %llu < payload %llu bytes", i,
                         (unsigned long long)blocks_capacity[i], (unsigned long long)pay[i]);
@@ -582,8 +601,8 @@ gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *c
     for (uint32_t i = 0; i < n_scenes; i++) {
         sig.push_back(reinterpret_cast<uintptr_t>(textures[i]));
         sig.push_back(reinterpret_cast<uintptr_t>(blocks[i]));
-        sig.push_back(descs[i].blocks_per_band);
-        uint64_t f = 0;
+        sig.push_back(descs[i].blocks_per_stream);
+        uint64_t f = (uint64_t)descs[i].n_streams << 32;
         for (int k = 0; k < 16; k++) f |= (uint64_t)(fmts[16 * i + k] == GSBC_FMT_BC7) << k;
         sig.push_back(f);
     }
@@ -591,8 +610,8 @@ gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *c
         drop_plan(ctx);
         Runs r1, r7;
         for (uint32_t i = 0; i < n_scenes; i++) {
-            const uint64_t nblk = descs[i].blocks_per_band;
-            for (int k = 0; k < 16; k++) {
+            const uint64_t nblk = descs[i].blocks_per_stream;
+            for (uint32_t k = 0; k < descs[i].n_streams; k++) {
                 const uint8_t *src = textures[i] + (uint64_t)k * nblk * 64;
                 uint8_t *dst = blocks[i] + offs[16 * i + k];
                 if (fmts[16 * i + k] == GSBC_FMT_BC7) r7.add(src, dst, nullptr, nblk);
@@ -618,7 +637,7 @@ gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *c
         {   // each run adds into its (scene, band) SSE slot
             size_t q7 = 0, q1 = 0;
             for (uint32_t i = 0; i < n_scenes; i++)
-                for (int k = 0; k < 16; k++) {
+                for (uint32_t k = 0; k < descs[i].n_streams; k++) {
                     BlockRun &r = fmts[16 * i + k] == GSBC_FMT_BC7 ? r7.v[q7++] : r1.v[q1++];
                     r.sse = ctx->plan_sse + 16 * (size_t)i + k;
                 }
@@ -692,7 +711,7 @@ gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *c
 
 // ---- container files
 namespace {
-constexpr uint32_t kContainerVersion = 1;
+constexpr uint32_t kContainerVersion = 2;   // 1: before arrangements (always GSBC_ARR_BANDS)
 constexpr uint32_t kRecordBytes = 24;
 
 struct FileCloser {
@@ -718,13 +737,15 @@ gsbc_status gsbc_save(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_de
     put32(&buf[4], kContainerVersion);
     put64(&buf[8], desc->n_prims);
     put64(&buf[16], desc->n_pad);
-    put64(&buf[24], desc->blocks_per_band);
+    put64(&buf[24], desc->blocks_per_stream);
     put64(&buf[32], desc->payload_bytes);
     put32(&buf[40], kRecordBytes);
-    for (int k = 0; k < 16; k++) {
+    put32(&buf[44], desc->arrangement);
+    put32(&buf[48], desc->n_streams);
+    for (uint32_t k = 0; k < 16; k++) {
         uint8_t *r = &buf[64 + k * kRecordBytes];
-        put32(r, desc->format[k]);
-        put64(r + 8, desc->offset[k]);
+        put32(r, k < desc->n_streams ? desc->format[k] : 0u);
+        put64(r + 8, k < desc->n_streams ? desc->offset[k] : 0u);
         memcpy(r + 16, &desc->vmin[k], 4);
         memcpy(r + 20, &desc->vmax[k], 4);
     }
@@ -752,14 +773,17 @@ gsbc_status gsbc_load(gsbc_ctx *ctx, const char *path, gsbc_stream_desc *desc, u
     uint8_t head[64 + 16 * kRecordBytes];
     if (fread(head, 1, sizeof head, fc.f) != sizeof head) return fail(ctx, GSBC_E_IO, "%s: short header", path);
     if (memcmp(head, "GSBC", 4) != 0) return fail(ctx, GSBC_E_IO, "%s: not a container (bad magic)", path);
-    if (get32(&head[4]) != kContainerVersion) return fail(ctx, GSBC_E_IO, "%s: version %u not supported", path, get32(&head[4]));
+    const uint32_t version = get32(&head[4]);
+    if (version != 1 && version != kContainerVersion) return fail(ctx, GSBC_E_IO, "%s: version %u not supported", path, version);
     if (get32(&head[40]) != kRecordBytes) return fail(ctx, GSBC_E_IO, "%s: record size %u", path, get32(&head[40]));
     gsbc_stream_desc d;
     memset(&d, 0, sizeof d);
     d.n_prims = get64(&head[8]);
     d.n_pad = get64(&head[16]);
-    d.blocks_per_band = get64(&head[24]);
+    d.blocks_per_stream = get64(&head[24]);
     d.payload_bytes = get64(&head[32]);
+    d.arrangement = version == 1 ? (uint32_t)GSBC_ARR_BANDS : get32(&head[44]);
+    d.n_streams = version == 1 ? 16u : get32(&head[48]);
     for (int k = 0; k < 16; k++) {
         const uint8_t *r = &head[64 + k * kRecordBytes];
         const uint32_t f = get32(r);
@@ -801,7 +825,8 @@ gsbc_status gsbc_decode(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_
     if ((reinterpret_cast<uintptr_t>(blocks) & 15) || (reinterpret_cast<uintptr_t>(textures_out) & 15))
         return fail(ctx, GSBC_E_ARG, "blocks and textures_out must be 16-byte aligned");
     if ((s = check_stream(ctx, desc))) return s;
-    HIP_TRY(ctx, launch_decode(blocks, band_args(desc), desc->blocks_per_band, textures_out, ctx->stream), "decode launch");
+    HIP_TRY(ctx, launch_decode(blocks, band_args(desc), desc->blocks_per_stream, textures_out, ctx->stream),
+            "decode launch");
     return GSBC_OK;
 }
 

@@ -35,11 +35,32 @@ __device__ __forceinline__ uint32_t band_texel(const uint8_t *blocks, const Band
     return bc7_texel(q, texel);
 }
 
+// The 16 band texels of slot s, each found through the arrangement:
+// 0: stream k, block s/16, zigzag texel of s%16; 1: stream 0, block s,
+// texel k; 2: stream k/4, block s/4, texel 4 (s%4) + k%4.
+template <int ARR>
+__device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16])
+{
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        if (ARR == 1) px[k] = band_texel(blocks, b, 0, s, k);
+        else if (ARR == 2) px[k] = band_texel(blocks, b, k >> 2, s >> 2, 4 * (int)(s & 3u) + (k & 3));
+        else px[k] = band_texel(blocks, b, k, s >> 4, (int)zigzag_texel(s & 15u));
+    }
+}
+
+__device__ __forceinline__ void slot_texels(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16])
+{
+    if (b.arrangement == 1) slot_texels_arr<1>(blocks, b, s, px);
+    else if (b.arrangement == 2) slot_texels_arr<2>(blocks, b, s, px);
+    else slot_texels_arr<0>(blocks, b, s, px);
+}
+
 __global__ __launch_bounds__(256) void k_decode(const uint8_t *blocks, BandArgs b, uint64_t nblk,
                                                 uint32_t *tex)
 {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= 16 * nblk) return;
+    if (g >= (uint64_t)b.n_streams * nblk) return;
     const int k = (int)(g / nblk);
     const uint64_t blk = g % nblk;
     uint32_t out[16];
@@ -112,14 +133,13 @@ __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *block
         if (j < m) {
             const uint32_t s = prim_idx ? prim_idx[j] : (uint32_t)j;
             if (s < n_prims) {
-                const uint64_t blk = s >> 4;
-                const int texel = (int)zigzag_texel(s & 15u);
+                uint32_t px[16];
+                slot_texels(blocks, b, s, px);
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
-                    uint32_t px = band_texel(blocks, b, k, blk, texel);
-                    h[k][0] = fmaf((float)(px & 255), b.delta[k], b.vmin[k]);
-                    h[k][1] = fmaf((float)((px >> 8) & 255), b.delta[k], b.vmin[k]);
-                    h[k][2] = fmaf((float)((px >> 16) & 255), b.delta[k], b.vmin[k]);
+                    h[k][0] = fmaf((float)(px[k] & 255), b.delta[k], b.vmin[k]);
+                    h[k][1] = fmaf((float)((px[k] >> 8) & 255), b.delta[k], b.vmin[k]);
+                    h[k][2] = fmaf((float)((px[k] >> 16) & 255), b.delta[k], b.vmin[k]);
                 }
             } else {   // not a slot of this scene: NaN colours, no block access
 #pragma unroll
@@ -251,15 +271,14 @@ __global__ __launch_bounds__(256) void k_decode_eval_view(const uint8_t *blocks,
         Y[13] = -c3c * x * (4.0f * zz - xx - yy);
         Y[14] = c3e * z * (xx - yy);
         Y[15] = -c3a * x * (xx - 3.0f * yy);
-        const uint64_t blk = s >> 4;
-        const int texel = (int)zigzag_texel(s & 15u);
+        uint32_t px[16];
+        slot_texels(blocks, b, s, px);
         c[0] = c[1] = c[2] = 0.0f;
 #pragma unroll
         for (int k = 0; k < 16; k++) {
-            const uint32_t px = band_texel(blocks, b, k, blk, texel);
 #pragma unroll
             for (int ch = 0; ch < 3; ch++)
-                c[ch] = fmaf(fmaf((float)((px >> (8 * ch)) & 255), b.delta[k], b.vmin[k]), Y[k], c[ch]);
+                c[ch] = fmaf(fmaf((float)((px[k] >> (8 * ch)) & 255), b.delta[k], b.vmin[k]), Y[k], c[ch]);
         }
     }
     out[3 * j] = c[0];
@@ -282,7 +301,7 @@ hipError_t launch_decode_eval_view(const uint8_t *blocks, const BandArgs &b, uin
 hipError_t launch_decode(const uint8_t *blocks, const BandArgs &b, uint64_t nblk, uint8_t *textures,
                          hipStream_t st)
 {
-    uint64_t total = 16 * nblk;
+    uint64_t total = (uint64_t)b.n_streams * nblk;
     GSBC_LAUNCH("decode", k_decode, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, blocks, b, nblk,
                        reinterpret_cast<uint32_t *>(textures));
     return hipGetLastError();

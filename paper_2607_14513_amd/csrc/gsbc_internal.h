@@ -51,10 +51,12 @@ __device__ __forceinline__ void band_add(unsigned long long *sums, uint32_t band
 
 // Per-band stream description passed to kernels by value.
 struct BandArgs {
-    uint64_t offset[16];   // byte offset of each band stream in the payload
-    uint32_t format[16];   // 1 (BC1) or 7 (BC7)
-    float vmin[16];        // dequantisation: vmin + q * delta
+    uint64_t offset[16];   // byte offset of each stream in the payload
+    uint32_t format[16];   // per stream: 1 (BC1) or 7 (BC7)
+    float vmin[16];        // per band, dequantisation: vmin + q * delta
     float delta[16];
+    uint32_t arrangement;  // 0 one stream per band, 1 one primitive per block, 2 four per four blocks
+    uint32_t n_streams;    // 16, 1 or 4
 };
 
 // Range / scale record produced on the device by the reorder prologue.
@@ -71,9 +73,11 @@ size_t reorder_scratch_bytes(uint64_t n, uint32_t grid_bits);
 // identity: keep the input order (perm[s] = s) instead of sorting.
 // opacity: null, or per-primitive weights multiplied into every coefficient
 // first; quantiser: 0 = per-band min/max range, 1 = symmetric 99.5 % range.
+// arrangement: the block packing of the textures (0 bands, 1 one primitive
+// per block, 2 four primitives per four blocks).
 hipError_t launch_reorder(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
-                          uint32_t quantiser, bool identity, uint32_t *perm, uint8_t *textures, void *scratch,
-                          RangeRec *range_dev, hipStream_t st);
+                          uint32_t quantiser, bool identity, uint32_t arrangement, uint32_t *perm, uint8_t *textures,
+                          void *scratch, RangeRec *range_dev, hipStream_t st);
 
 // ---- encoders (bc1_encode.hip, bc7_encode.hip)
 // The encoders work on runs: a run is the consecutive blocks of one band of

@@ -268,17 +268,16 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *keys_in, 
     }
 }
 
-// Slot s -> block s/16, texel zigzag(s%16); 16 band texels per slot.
+// One thread per slot s < npad: quantise its 16 band vectors and place them
+// by the arrangement (0: stream k, block s/16, texel zigzag(s%16); 1: block
+// s, texel k; 2: stream k/4, block s/4, texel 4 (s%4) + k%4).
 __global__ __launch_bounds__(256) void k_gather_pack(const float *sh, const float *opacity, const uint32_t *perm,
-                                                     uint64_t n, uint64_t nblk, const RangeRec *r, uint32_t *tex)
+                                                     uint64_t n, uint64_t npad, uint32_t arrangement,
+                                                     const RangeRec *r, uint32_t *tex)
 {
     uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nblk * 16) return;
+    if (s >= npad) return;
     uint32_t src = perm[s < n ? s : n - 1];
-    uint32_t j = (uint32_t)(s & 15);
-    uint32_t x = (j & 1u) | (((j >> 2) & 1u) << 1);
-    uint32_t y = ((j >> 1) & 1u) | (((j >> 3) & 1u) << 1);
-    uint64_t texel = (s >> 4) * 16 + 4 * y + x;
     const float4 *p = reinterpret_cast<const float4 *>(sh + (uint64_t)src * 48);
     float f[48];
 #pragma unroll
@@ -291,12 +290,31 @@ __global__ __launch_bounds__(256) void k_gather_pack(const float *sh, const floa
 #pragma unroll
         for (int e = 0; e < 48; e++) f[e] = mu * f[e];
     }
+    uint32_t w[16];
 #pragma unroll
     for (int k = 0; k < 16; k++) {
         float vm = r->vmin[k], sc = r->scale[k];
-        uint32_t w = quant8(f[3 * k], vm, sc) | (quant8(f[3 * k + 1], vm, sc) << 8) |
-                     (quant8(f[3 * k + 2], vm, sc) << 16) | 0xFF000000u;
-        tex[(uint64_t)k * nblk * 16 + texel] = w;
+        w[k] = quant8(f[3 * k], vm, sc) | (quant8(f[3 * k + 1], vm, sc) << 8) |
+               (quant8(f[3 * k + 2], vm, sc) << 16) | 0xFF000000u;
+    }
+    if (arrangement == 1) {            // one primitive per block: 64 contiguous bytes
+        uint4 *d = reinterpret_cast<uint4 *>(tex + s * 16);
+#pragma unroll
+        for (int q = 0; q < 4; q++) d[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+    } else if (arrangement == 2) {     // four primitives per four blocks: one 16-byte row per stream
+        const uint64_t bps = npad / 4;
+#pragma unroll
+        for (int g = 0; g < 4; g++)
+            *reinterpret_cast<uint4 *>(tex + ((uint64_t)g * bps + (s >> 2)) * 16 + 4 * (s & 3)) =
+                make_uint4(w[4 * g], w[4 * g + 1], w[4 * g + 2], w[4 * g + 3]);
+    } else {
+        const uint64_t nblk = npad / 16;
+        const uint32_t j = (uint32_t)(s & 15);
+        const uint32_t x = (j & 1u) | (((j >> 2) & 1u) << 1);
+        const uint32_t y = ((j >> 1) & 1u) | (((j >> 3) & 1u) << 1);
+        const uint64_t texel = (s >> 4) * 16 + 4 * y + x;
+#pragma unroll
+        for (int k = 0; k < 16; k++) tex[(uint64_t)k * nblk * 16 + texel] = w[k];
     }
 }
 
@@ -407,8 +425,8 @@ __global__ void k_iota(uint32_t *perm, uint64_t n)
 }
 
 hipError_t launch_reorder(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
-                          uint32_t quantiser, bool identity, uint32_t *perm, uint8_t *textures, void *scratch,
-                          RangeRec *range_dev, hipStream_t st)
+                          uint32_t quantiser, bool identity, uint32_t arrangement, uint32_t *perm, uint8_t *textures,
+                          void *scratch, RangeRec *range_dev, hipStream_t st)
 {
     Layout L = layout(n);
     char *s = static_cast<char *>(scratch);
@@ -439,9 +457,9 @@ hipError_t launch_reorder(const float *pos, const float *sh, const float *opacit
     GSBC_LAUNCH("range_final", k_range_final, dim3(1), dim3(64), 0, st, acc, cov, grid_bits, range_dev);
     if (identity) {
         GSBC_LAUNCH("iota", k_iota, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, perm, n);
-        const uint64_t nblk = (n + 15) / 16;
-        GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((nblk * 16 + 255) / 256)), dim3(256), 0, st,
-                    sh, opacity, perm, n, nblk, range_dev, reinterpret_cast<uint32_t *>(textures));
+        const uint64_t npad = (n + 15) / 16 * 16;
+        GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0, st,
+                    sh, opacity, perm, n, npad, arrangement, range_dev, reinterpret_cast<uint32_t *>(textures));
         return hipGetLastError();
     }
     GSBC_LAUNCH("keys", k_keys, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, pos, sh, opacity, n,
@@ -465,9 +483,9 @@ hipError_t launch_reorder(const float *pos, const float *sh, const float *opacit
         vin = vdst;
         vout = (vdst == va) ? vb : va;
     }
-    uint64_t nblk = (n + 15) / 16;
-    GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((nblk * 16 + 255) / 256)), dim3(256), 0, st,
-                       sh, opacity, perm, n, nblk, range_dev, reinterpret_cast<uint32_t *>(textures));
+    const uint64_t npad = (n + 15) / 16 * 16;
+    GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0, st,
+                       sh, opacity, perm, n, npad, arrangement, range_dev, reinterpret_cast<uint32_t *>(textures));
     return hipGetLastError();
 }
 

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libgsbc.so")
 
 OK, E_ARG, E_UNSUPPORTED, E_NOMEM, E_INFEASIBLE, E_DEVICE, E_BUFFER, E_IO = 0, -1, -2, -3, -4, -5, -6, -7
 FMT_AUTO, FMT_BC1, FMT_BANDS, FMT_BC7 = 0, 1, 2, 7
+ARR_BANDS, ARR_PRIM, ARR_QUAD = 0, 1, 2
+N_STREAMS = {ARR_BANDS: 16, ARR_PRIM: 1, ARR_QUAD: 4}
 
 EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_default_params",
             "gsbc_query_sizes", "gsbc_reorder", "gsbc_encode", "gsbc_default_batch_tuning",
@@ -32,7 +34,7 @@ class GsbcError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("grid_bits", ctypes.c_uint32), ("refine_steps", ctypes.c_uint32),
                 ("bc7_mode_mask", ctypes.c_uint32), ("order", ctypes.c_uint32),
-                ("quantiser", ctypes.c_uint32)]
+                ("arrangement", ctypes.c_uint32), ("quantiser", ctypes.c_uint32)]
 
 
 class BatchTuning(ctypes.Structure):
@@ -48,13 +50,16 @@ class StreamDesc(ctypes.Structure):
     _fields_ = [("format", ctypes.c_uint8 * 16), ("offset", ctypes.c_uint64 * 16),
                 ("vmin", ctypes.c_float * 16), ("vmax", ctypes.c_float * 16),
                 ("n_prims", ctypes.c_uint64), ("n_pad", ctypes.c_uint64),
-                ("blocks_per_band", ctypes.c_uint64), ("payload_bytes", ctypes.c_uint64)]
+                ("blocks_per_stream", ctypes.c_uint64), ("payload_bytes", ctypes.c_uint64),
+                ("arrangement", ctypes.c_uint32), ("n_streams", ctypes.c_uint32)]
 
     def formats(self):
-        return np.array(list(self.format), np.uint8)
+        """Per-stream formats (n_streams entries)."""
+        return np.array(list(self.format)[:self.n_streams], np.uint8)
 
     def offsets(self):
-        return np.array(list(self.offset), np.uint64)
+        """Per-stream payload offsets (n_streams entries)."""
+        return np.array(list(self.offset)[:self.n_streams], np.uint64)
 
     def ranges(self):
         return np.array(list(self.vmin), np.float32), np.array(list(self.vmax), np.float32)
@@ -222,22 +227,23 @@ class Context:
             _dev_tensor(opacity, torch.float32, "opacity")
             if opacity.numel() != n:
                 raise ValueError("opacity must hold one weight per primitive")
-        nblk = (n + 15) // 16
+        p = params if params is not None else default_params()
+        S = N_STREAMS.get(int(p.arrangement), 16)
+        npad = (n + 15) // 16 * 16
         if out is None:
             perm = torch.empty(n, dtype=torch.int32, device=self.device)
-            tex = torch.empty((16, nblk, 16, 4), dtype=torch.uint8, device=self.device)
+            tex = torch.empty((S, npad // S, 16, 4), dtype=torch.uint8, device=self.device)
         else:
             perm, tex = out
         desc = StreamDesc()
-        p = params if params is not None else default_params()
         self._check(load().gsbc_reorder(self._h, _ptr(pos), _ptr(sh),
                                         _ptr(opacity) if opacity is not None else None, n, ctypes.byref(p), _ptr(perm),
                                         _ptr(tex), ctypes.byref(desc)))
         return perm, tex, desc
 
     def encode(self, textures, desc, fmt=FMT_AUTO, rate=6.0, params=None, blocks=None, want_sse=False):
-        """Encode all bands -> (blocks uint8 device tensor, desc, band_sse int64[2][16] or None).
-        fmt FMT_BANDS codes band k in desc.format[k] (set by the caller)."""
+        """Encode all streams -> (blocks uint8 device tensor, desc, band_sse int64[2][16] or None).
+        fmt FMT_BANDS codes stream k in desc.format[k] (set by the caller)."""
         _dev_tensor(textures, torch.uint8, "textures")
         desc = desc.copy()
         if blocks is None:
@@ -304,7 +310,7 @@ class Context:
 
     def decode(self, blocks, desc, out=None):
         if out is None:
-            out = torch.empty((16, desc.blocks_per_band, 16, 4), dtype=torch.uint8, device=self.device)
+            out = torch.empty((desc.n_streams, desc.blocks_per_stream, 16, 4), dtype=torch.uint8, device=self.device)
         self._check(load().gsbc_decode(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(out)))
         return out
 

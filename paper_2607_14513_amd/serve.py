@@ -188,7 +188,7 @@ class Server:
         _, tex, d = ctx.reorder(pos, sh)
         blocks, d2, _ = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=self.rate_bits)
         blocks = blocks[:d2.payload_bytes].clone()   # keep only the payload resident
-        req.blocks_coded = 16 * d2.blocks_per_band
+        req.blocks_coded = 16 * d2.blocks_per_stream
         return blocks, d2
 
     def _run_decode(self, ctx, req, scene):

@@ -81,7 +81,8 @@ def test_container_header_host_only(tmp_path):
     p = str(tmp_path / "scene.gsbc")
     nblk, offs, pos = _container(p)
     d = gsbc.load_header(p)
-    assert (d.n_prims, d.n_pad, d.blocks_per_band, d.payload_bytes) == (37, nblk * 16, nblk, pos)
+    assert (d.n_prims, d.n_pad, d.blocks_per_stream, d.payload_bytes) == (37, nblk * 16, nblk, pos)
+    assert (d.arrangement, d.n_streams) == (gsbc.ARR_BANDS, 16)          # a version-1 file
     assert list(d.formats()) == [7] + [1] * 15
     assert list(d.offsets()) == offs
     vmin, vmax = d.ranges()
@@ -99,3 +100,32 @@ def test_container_rejects_malformed(tmp_path, bad):
     with pytest.raises(gsbc.GsbcError) as e:
         gsbc.load_header(p)
     assert e.value.status == gsbc.E_IO
+
+
+def test_ctypes_structs_match_the_header(tmp_path):
+    """The binding's structures have the C layout of include/gsbc.h (sizes
+    and every field offset, measured by a C program built against it)."""
+    import ctypes
+    import subprocess
+    from paper_2607_14513_amd import gsbc
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"gsbc_params": gsbc.Params, "gsbc_stream_desc": gsbc.StreamDesc,
+               "gsbc_batch_tuning": gsbc.BatchTuning}
+    lines = []
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gsbc.h"\nint main(void) {\n'
+                   + "\n".join(lines) + "\nreturn 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines():
+        c, f, v = line.split()
+        got[(c, f)] = int(v)
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)

@@ -45,7 +45,8 @@ def host(t):
 def _desc_for(gsbc, n, fmt):
     d = gsbc.StreamDesc()
     nblk = (n + 15) // 16
-    d.n_prims, d.n_pad, d.blocks_per_band = n, nblk * 16, nblk
+    d.n_prims, d.n_pad, d.blocks_per_stream = n, nblk * 16, nblk
+    d.arrangement, d.n_streams = gsbc.ARR_BANDS, 16
     pos = 0
     for k in range(16):
         d.format[k] = fmt[k]
@@ -70,7 +71,7 @@ def test_decode_random_blocks(G, fmt):
         payload[::16][:50] = 0              # some reserved-mode blocks
     say("decode random", fmt)
     out = host(ctx.decode(dev(payload), d))
-    nblk = d.blocks_per_band
+    nblk = d.blocks_per_stream
     ref = O.decode_stream(payload, d.offsets(), d.formats(), nblk)
     assert np.array_equal(out, ref)
 
@@ -512,7 +513,7 @@ def test_decode_eval_large_sampled(G):
     blocks6, d6, sse = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=c["rate"], want_sse=True)
     f6 = d6.formats()
     assert f6[0] == 7 and (f6 == 7).sum() == 8
-    nblk = d6.blocks_per_band
+    nblk = d6.blocks_per_stream
     assert sum(nblk * (64 if f == 1 else 128) for f in f6) == 6 * 16 * 16 * nblk
     delta = np.array([np.float32((d6.vmax[k] - d6.vmin[k]) / np.float32(255.0)) for k in range(16)], np.float64)
     gain = (sse[0] - sse[1]).astype(np.float64) * delta * delta
