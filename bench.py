@@ -205,6 +205,32 @@ def main():
                 "bc7_input_order": band_psnr(tex_id, gsbc.FMT_BC7)}
         del tex_id
 
+        # ---- the arrangements of Table I (Figs. SetupA, SetupB, SetupD) on this
+        # scene: PSNR of the decoded texels over all bands and slots, and the
+        # coded bytes per primitive
+        def arrangement_row(label, arr, order, fmts):
+            _, tx, dd = ctx.reorder(pos_d, sh_d, params=gsbc.default_params(arrangement=arr, order=order))
+            for k, f in enumerate(fmts):
+                dd.format[k] = f
+            b, d3, _ = ctx.encode(tx, dd, fmt=gsbc.FMT_BANDS, blocks=blocks)
+            dec = ctx.decode(b, d3)
+            diff = dec[..., :3].to(torch.int32) - tx[..., :3].to(torch.int32)
+            mse = float((diff * diff).sum(dtype=torch.float64).item()) / (d3.n_pad * 48)
+            return {"arrangement": label, "psnr_db": round(float(10 * np.log10(255.0 ** 2 / mse)), 2),
+                    "bytes_per_primitive": round(d3.payload_bytes / n, 3)}
+
+        arrangements = []
+        for label, arr, order, fmts in (
+                ("SetupA: BC1", 1, 1, [1]), ("SetupA: BC7", 1, 1, [7]),
+                ("SetupB: BC7 + 3 BC1, input order", 2, 1, [7, 1, 1, 1]),
+                ("SetupB: BC7 + 3 BC1, sorted", 2, 0, [7, 1, 1, 1]),
+                ("SetupD: 16 BC1, input order", 0, 1, [1] * 16), ("SetupD: 16 BC1, sorted", 0, 0, [1] * 16),
+                ("SetupD: BC7 + 15 BC1, input order", 0, 1, [7] + [1] * 15),
+                ("SetupD: BC7 + 15 BC1, sorted", 0, 0, [7] + [1] * 15),
+                ("SetupD: 16 BC7, input order", 0, 1, [7] * 16), ("SetupD: 16 BC7, sorted", 0, 0, [7] * 16)):
+            arrangements.append(arrangement_row(label, arr, order, fmts))
+        torch.cuda.empty_cache()
+
         # ---- decode_eval on the 3,145,728-primitive scene at 1,024 directions
         roof_de = None
         if not args.no_large:
@@ -281,6 +307,7 @@ def main():
         "bc7_encode_mblocks_s": round(rates["bc7"], 3),
         "bc1_encode_mblocks_s": round(rates["bc1"], 3),
         "psnr_db_per_band": psnr,
+        "arrangements": arrangements,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "roofline": roof,
         "roofline_decode_eval": roof_de,
