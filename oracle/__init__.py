@@ -70,8 +70,9 @@ def _load():
             "ref_bc7_decode": (None, [P, u64, P]),
             "ref_rate_select": (i32, [P, P, P, P, ctypes.c_double, P]),
             "ref_sh_basis": (None, [ctypes.c_double] * 3 + [P]),
-            "ref_decode_eval": (None, [P, P, P, u32, P, P, P, u32, P, u64, P, P]),
-            "ref_decode_eval_view": (None, [P, P, P, u32, P, P, P, P, P, P, u64, P, P]),
+            "ref_decode_eval": (None, [P, P, P, u32, u32, P, P, P, u32, P, u64, P, P]),
+            "ref_decode_eval_view": (None, [P, P, P, u32, u32, P, P, P, P, P, P, u64, P, P]),
+            "ref_degrees": (None, [P, u64, ctypes.c_float, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -187,6 +188,43 @@ def reorder(pos, sh, grid_bits=3, opacity=None, quantiser=0, arrangement=ARR_BAN
     k = keys(pos, q, grid_bits, lo, hi)
     perm = sort(k)
     return perm, pack(q, perm, arrangement), vmin, vmax
+
+
+def degrees(sh, tau=0.0):
+    """uint8[n] degree class of every primitive (coefficients above tau)."""
+    sh = _c(sh, np.float32)
+    out = np.empty(sh.shape[0], np.uint8)
+    _load().ref_degrees(_p(sh), sh.shape[0], float(tau), _p(out))
+    return out
+
+
+def reorder_degrees(pos, sh, tau=0.0, grid_bits=3, opacity=None, quantiser=0):
+    """Variable number of bands (Sec. IV-B): every primitive goes to the
+    bitstreams of its degree class, with (L+1)^2 bands.  Key = degree above
+    the spatial cell and colour fields, so the sort groups the classes (in
+    increasing degree) and orders each by cell and colour.  The quantiser
+    range is taken over all coefficients, dropped ones included.  Returns
+    (perm, counts[4], textures: list of 4 (uint8[(L+1)^2][nblk_L][16][4], or
+    None for an empty class), vmin, vmax); class L owns slots
+    sum(counts[:L]) .. sum(counts[:L+1]) - 1 of perm."""
+    if opacity is not None:
+        sh = premultiply(sh, opacity)
+    vmin, vmax = band_range_coverage(sh) if quantiser == 1 else band_range(sh)
+    lo, hi = pos_aabb(pos)
+    q = quantise(sh, vmin, vmax)
+    deg = degrees(sh, tau)
+    k = keys(pos, q, grid_bits, lo, hi) | (deg.astype(np.uint64) << np.uint64(24 + 3 * grid_bits))
+    perm = sort(k)
+    counts = np.bincount(deg, minlength=4).astype(np.int64)
+    start = np.concatenate([[0], np.cumsum(counts)])
+    tex = []
+    for L in range(4):
+        if counts[L] == 0:
+            tex.append(None)
+            continue
+        part = perm[start[L]:start[L + 1]]
+        tex.append(pack(q, part)[:(L + 1) ** 2])
+    return perm, counts, tex, vmin, vmax
 
 
 # ---------------------------------------------------------------- D, E
@@ -314,6 +352,7 @@ def sh_basis(d):
 
 
 def _streams16(fmt, off):
+    """Pad per-stream formats and offsets to the 16 entries the C side reads."""
     f = np.zeros(16, np.uint8)
     o = np.zeros(16, np.uint64)
     f[:len(fmt)] = fmt
@@ -322,7 +361,10 @@ def _streams16(fmt, off):
 
 
 def decode_eval(payload, off, fmt, vmin, vmax, dirs, slots, with_scale=True, arrangement=ARR_BANDS):
-    """FP64 decode_eval.  Returns out[V][M][3] (and scale[V][M][3])."""
+    """FP64 decode_eval.  Returns out[V][M][3] (and scale[V][M][3]).  With the
+    band arrangement, fewer than 16 formats mean a scene of lower-degree
+    primitives: the missing bands are zero."""
+    ns = len(fmt)
     fmt, off = _streams16(fmt, off)
     payload = _c(payload, np.uint8)
     dirs = _c(dirs, np.float32).reshape(-1, 3)
@@ -330,7 +372,7 @@ def decode_eval(payload, off, fmt, vmin, vmax, dirs, slots, with_scale=True, arr
     V, M = dirs.shape[0], slots.shape[0]
     out = np.empty((V, M, 3), np.float64)
     scale = np.empty((V, M, 3), np.float64) if with_scale else None
-    _load().ref_decode_eval(_p(payload), _p(_c(fmt, np.uint8)), _p(_c(off, np.uint64)), int(arrangement),
+    _load().ref_decode_eval(_p(payload), _p(_c(fmt, np.uint8)), _p(_c(off, np.uint64)), int(arrangement), ns,
                             _p(_c(vmin, np.float32)), _p(_c(vmax, np.float32)), _p(dirs), V,
                             _p(slots), M, _p(out), _p(scale) if scale is not None else None)
     return (out, scale) if with_scale else out
@@ -340,6 +382,7 @@ def decode_eval_view(payload, off, fmt, vmin, vmax, pos, perm, view, slots, with
                      arrangement=ARR_BANDS):
     """FP64 colour of each slot seen from view position `view` (direction
     (view - p)/|view - p| per primitive).  Returns out[M][3] (and scale)."""
+    ns = len(fmt)
     fmt, off = _streams16(fmt, off)
     payload = _c(payload, np.uint8)
     pos = _c(pos, np.float32).reshape(-1, 3)
@@ -349,7 +392,7 @@ def decode_eval_view(payload, off, fmt, vmin, vmax, pos, perm, view, slots, with
     M = slots.shape[0]
     out = np.empty((M, 3), np.float64)
     scale = np.empty((M, 3), np.float64) if with_scale else None
-    _load().ref_decode_eval_view(_p(payload), _p(_c(fmt, np.uint8)), _p(_c(off, np.uint64)), int(arrangement),
+    _load().ref_decode_eval_view(_p(payload), _p(_c(fmt, np.uint8)), _p(_c(off, np.uint64)), int(arrangement), ns,
                                  _p(_c(vmin, np.float32)), _p(_c(vmax, np.float32)), _p(pos), _p(perm),
                                  _p(view), _p(slots), M, _p(out), _p(scale) if scale is not None else None)
     return (out, scale) if with_scale else out

@@ -180,6 +180,24 @@ EXPORT void ref_keys(const float *pos, const uint8_t *q, uint64_t n, uint32_t g,
     }
 }
 
+/* Degree class of each primitive for the variable number of bands (Sec.
+ * IV-B: primitives whose higher-order SH are zero, or small enough to be
+ * treated as zero, go to bitstreams with fewer bands): the largest SH degree
+ * l in 1..3 with some coefficient of a degree-l band (bands l^2..l^2+2l)
+ * above tau in magnitude, else 0.  The primitive keeps its (l+1)^2 lowest
+ * bands; the higher ones are dropped and decode as zero. */
+EXPORT void ref_degrees(const float *sh, uint64_t n, float tau, uint8_t *deg)
+{
+    for (uint64_t i = 0; i < n; i++) {
+        int L = 0;
+        for (int l = 1; l <= 3; l++)
+            for (int k = l * l; k <= l * l + 2 * l; k++)
+                for (int c = 0; c < 3; c++)
+                    if (fabsf(sh[(i * 16 + (uint64_t)k) * 3 + c]) > tau) L = l;
+        deg[i] = (uint8_t)L;
+    }
+}
+
 /* ======================================================================
  * S -- stable ascending sort of the keys (Sec. III-C, step 2, increasing
  * order).  perm[s] = original index at sorted slot s.  Comparing (key, index)
@@ -1267,11 +1285,17 @@ EXPORT void ref_sh_basis(double x, double y, double z, double *Y)
  * out[v][j][c] = sum_k Hhat[slot][k][c] * Y_k(dir_v) with
  * Hhat = vmin_k + q * delta_k, delta_k = (vmax_k - vmin_k)/255, in FP64;
  * scale[v][j][c] = sum_k |Hhat * Y_k| (the size of the terms). */
-/* Dequantised decoded band vectors of slot s; fmt and offset are per stream. */
+/* Dequantised decoded band vectors of slot s; fmt and offset are per stream.
+ * With the band arrangement, bands at or past n_streams are dropped bands
+ * (a scene of lower-degree primitives) and are exactly zero. */
 static void slot_coefficients(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset, uint32_t arr,
-                              const float *vmin, const float *vmax, uint32_t s, double H[16][3])
+                              uint32_t n_streams, const float *vmin, const float *vmax, uint32_t s, double H[16][3])
 {
     for (int k = 0; k < 16; k++) {
+        if (arr == 0 && (uint32_t)k >= n_streams) {
+            H[k][0] = H[k][1] = H[k][2] = 0.0;
+            continue;
+        }
         int st, texel;
         uint64_t b;
         locate(arr, s, k, &st, &b, &texel);
@@ -1284,13 +1308,13 @@ static void slot_coefficients(const uint8_t *blocks, const uint8_t *fmt, const u
 }
 
 EXPORT void ref_decode_eval(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset, uint32_t arr,
-                            const float *vmin, const float *vmax, const float *dirs, uint32_t V,
+                            uint32_t n_streams, const float *vmin, const float *vmax, const float *dirs, uint32_t V,
                             const uint32_t *slots, uint64_t m, double *out, double *scale)
 {
     #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < (int64_t)m; j++) {
         double H[16][3];
-        slot_coefficients(blocks, fmt, offset, arr, vmin, vmax, slots[j], H);
+        slot_coefficients(blocks, fmt, offset, arr, n_streams, vmin, vmax, slots[j], H);
         for (uint32_t v = 0; v < V; v++) {
             double Y[16];
             ref_sh_basis((double)dirs[v * 3 + 0], (double)dirs[v * 3 + 1], (double)dirs[v * 3 + 2], Y);
@@ -1313,7 +1337,7 @@ EXPORT void ref_decode_eval(const uint8_t *blocks, const uint8_t *fmt, const uin
  * position (d = 0 when f = p), all in FP64 from the FP32 inputs.  pos is in
  * input order; perm maps a slot to its primitive. */
 EXPORT void ref_decode_eval_view(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset, uint32_t arr,
-                                 const float *vmin, const float *vmax, const float *pos, const uint32_t *perm,
+                                 uint32_t n_streams, const float *vmin, const float *vmax, const float *pos, const uint32_t *perm,
                                  const float *view, const uint32_t *slots, uint64_t m, double *out, double *scale)
 {
     #pragma omp parallel for schedule(static)
@@ -1330,7 +1354,7 @@ EXPORT void ref_decode_eval_view(const uint8_t *blocks, const uint8_t *fmt, cons
         double Y[16];
         ref_sh_basis(d[0], d[1], d[2], Y);
         double H[16][3];
-        slot_coefficients(blocks, fmt, offset, arr, vmin, vmax, s, H);
+        slot_coefficients(blocks, fmt, offset, arr, n_streams, vmin, vmax, s, H);
         for (int c = 0; c < 3; c++) {
             double acc = 0.0, mag = 0.0;
             for (int k = 0; k < 16; k++) {

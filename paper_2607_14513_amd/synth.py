@@ -27,8 +27,12 @@ def band_degree(k):
     return int(math.isqrt(k))
 
 
-def make_scene(n, clusters=32, comps=64, seed=1):
-    """Returns (pos float32[n][3], sh float32[n][16][3])."""
+def make_scene(n, clusters=32, comps=64, seed=1, degree_mix=None, small=0.0):
+    """Returns (pos float32[n][3], sh float32[n][16][3]).  With degree_mix
+    (probabilities of SH degree 0..3), each primitive draws its degree L and
+    its bands of higher degree are replaced by U[-small, small] values
+    (exact zeros for small = 0): the view-dependent colour many primitives
+    barely use."""
     rng = _rng(seed)
     centres = rng.uniform(0.0, 1.0, (clusters, 3))
     which = rng.integers(0, clusters, n)
@@ -40,6 +44,12 @@ def make_scene(n, clusters=32, comps=64, seed=1):
     for k in range(1, 16):
         scale = 0.2 / (band_degree(k) + 1) ** 2
         sh[:, k, :] = rng.laplace(0.0, scale, (n, 3))
+    if degree_mix is not None:
+        L = rng.choice(4, size=n, p=np.asarray(degree_mix, np.float64))
+        tiny = rng.uniform(-small, small, (n, 16, 3))
+        for k in range(1, 16):
+            drop = band_degree(k) > L
+            sh[drop, k, :] = tiny[drop, k, :]
     return pos.astype(np.float32), sh.astype(np.float32)
 
 
