@@ -96,10 +96,11 @@ typedef struct {
     float vmin[16], vmax[16];    /* per-band quantiser range: q = rint((x - vmin) * 255/(vmax - vmin)) */
     uint64_t n_prims;            /* N */
     uint64_t n_pad;              /* N rounded up to a multiple of 16 */
-    uint64_t blocks_per_stream;  /* n_pad / n_streams */
+    uint64_t blocks_per_stream;  /* n_pad / 16 (BANDS), n_pad (PRIM), n_pad / 4 (QUAD) */
     uint64_t payload_bytes;      /* bytes of the concatenated streams */
     uint32_t arrangement;        /* GSBC_ARR_* of the textures */
-    uint32_t n_streams;          /* 16, 1 or 4 (BANDS, PRIM, QUAD) */
+    uint32_t n_streams;          /* 16, 1 or 4 (BANDS, PRIM, QUAD); 1, 4 or 9 for a degree class
+                                    of gsbc_reorder_degrees (bands past n_streams are zero) */
 } gsbc_stream_desc;
 
 /* ---------------------------------------------------------------- context */
@@ -157,6 +158,40 @@ GSBC_API gsbc_status gsbc_query_sizes(uint64_t n, uint32_t n_dirs, uint64_t *tex
 GSBC_API gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, const float *opacity,
                          uint64_t n, const gsbc_params *params, uint32_t *perm, uint8_t *textures,
                          gsbc_stream_desc *desc);
+
+/* Variable number of bands (Sec. IV-B: primitives whose higher-order SH are
+ * zero, or small enough to count as zero, go to bitstreams with fewer
+ * bands; Fig. SetupD in its variable form).  Each primitive's degree class
+ * L is the largest SH degree l in 1..3 with a coefficient of a degree-l band
+ * (bands l^2..l^2+2l) above tau in magnitude, else 0; the primitive keeps
+ * its (L+1)^2 lowest bands and the others decode as exactly zero.  The sort
+ * key is (L, Morton cell, colour), so class L is a contiguous range of perm
+ * in increasing L, each ordered as gsbc_reorder orders a scene.  Every
+ * class is an independent scene in the band arrangement with (L+1)^2
+ * streams, to be coded with gsbc_encode or gsbc_encode_batch (per-band or
+ * whole formats; the rate controller needs all 16 bands) and decoded with
+ * class-local slot ids.  The quantiser range covers all coefficients,
+ * dropped ones included.
+ *   pos, sh, opacity, n   as gsbc_reorder
+ *   tau        >= 0, FP32 magnitudes at or below it count as zero (after
+ *              opacity premultiplication)
+ *   params     host, NULL for defaults (grid_bits and quantiser are used;
+ *              order must be 0 and arrangement GSBC_ARR_BANDS)
+ *   perm       device uint32[n] out: slot -> primitive; class L owns slots
+ *              counts[0] + .. + counts[L-1] .. + counts[L] - 1
+ *   textures   device, textures_capacity bytes, at least n_pad*64 + 1800
+ *              (GSBC_E_BUFFER otherwise); out: class L's textures
+ *              uint8[(L+1)^2][pad16(counts[L])/16][16][4] (the layout of
+ *              gsbc_reorder) at byte offset tex_offset[L]
+ *   counts     host uint64[4] out: primitives per class
+ *   tex_offset host uint64[4] out
+ *   descs      host gsbc_stream_desc[4] out: class L's scene (n_prims =
+ *              counts[L], n_streams = (L+1)^2, ranges); an empty class has
+ *              n_prims 0 and is not a scene to code */
+GSBC_API gsbc_status gsbc_reorder_degrees(gsbc_ctx *ctx, const float *pos, const float *sh, const float *opacity,
+                                          uint64_t n, float tau, const gsbc_params *params, uint32_t *perm,
+                                          uint8_t *textures, uint64_t textures_capacity, uint64_t counts[4],
+                                          uint64_t tex_offset[4], gsbc_stream_desc descs[4]);
 
 /* Encode every stream (Sec. III-A BTC; Sec. IV-B per-bitstream formats).
  *   textures device, layout of gsbc_reorder; desc host, in: n_prims, n_pad,

@@ -59,6 +59,7 @@ constexpr size_t kSse1Off = 1024;                // 16 x u64
 constexpr size_t kSse7Off = 1152;                // 16 x u64
 constexpr size_t kOff1Off = 1280;                // 16 x u64
 constexpr size_t kOff7Off = 1408;                // 16 x u64
+constexpr size_t kClassOff = 1536;               // 4 x u32 degree-class counts
 constexpr size_t kSmallBytes = 2048;
 
 std::atomic<long> g_alloc_count{0};
@@ -129,6 +130,10 @@ gsbc_status ensure_arena(gsbc_ctx *ctx, size_t bytes)
 }
 
 uint64_t pad16(uint64_t n) { return (n + 15) / 16 * 16; }
+// Textures of the four degree classes: sum over L of (L+1)^2 streams of
+// pad16(n_L) texels of 4 bytes, at most 4 (16 n + 15 (1 + 4 + 9 + 16))
+// <= n_pad*64 + 1800 bytes.
+uint64_t degree_textures_bytes(uint64_t n) { return pad16(n) * 64 + 1800; }
 // Streams of an arrangement: one per band, one, or one per band group.
 uint32_t streams_of(uint32_t arr) { return arr == GSBC_ARR_PRIM ? 1u : arr == GSBC_ARR_QUAD ? 4u : 16u; }
 uint64_t align16(uint64_t x) { return (x + 15) & ~(uint64_t)15; }
@@ -156,10 +161,13 @@ gsbc_status check_desc(gsbc_ctx *ctx, const gsbc_stream_desc *d)
 {
     if (!d) return fail(ctx, GSBC_E_ARG, "desc is NULL");
     if (d->n_prims == 0 || d->n_prims > 0x7FFFFFFFull) return fail(ctx, GSBC_E_ARG, "desc.n_prims %llu out of range", (unsigned long long)d->n_prims);
-    if (d->arrangement > GSBC_ARR_QUAD || d->n_streams != streams_of(d->arrangement))
+    // the band arrangement may keep only the (L+1)^2 lowest bands (a degree class)
+    const bool bands_ok = d->arrangement == GSBC_ARR_BANDS &&
+                          (d->n_streams == 1 || d->n_streams == 4 || d->n_streams == 9 || d->n_streams == 16);
+    if (d->arrangement > GSBC_ARR_QUAD || (!bands_ok && d->n_streams != streams_of(d->arrangement)))
         return fail(ctx, GSBC_E_ARG, "desc.arrangement %u with %u streams is not a known arrangement", d->arrangement,
                     d->n_streams);
-    if (d->n_pad != pad16(d->n_prims) || d->blocks_per_stream * d->n_streams != d->n_pad)
+    if (d->n_pad != pad16(d->n_prims) || d->blocks_per_stream * streams_of(d->arrangement) != d->n_pad)
         return fail(ctx, GSBC_E_ARG, "desc sizes inconsistent (n_prims %llu, n_pad %llu, blocks per stream %llu)",
                     (unsigned long long)d->n_prims, (unsigned long long)d->n_pad, (unsigned long long)d->blocks_per_stream);
     return GSBC_OK;
@@ -402,6 +410,74 @@ gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, const
     return GSBC_OK;
 }
 
+gsbc_status gsbc_reorder_degrees(gsbc_ctx *ctx, const float *pos, const float *sh, const float *opacity, uint64_t n,
+                                 float tau, const gsbc_params *params, uint32_t *perm, uint8_t *textures,
+                                 uint64_t textures_capacity, uint64_t counts[4], uint64_t tex_offset[4],
+                                 gsbc_stream_desc descs[4])
+{
+    gsbc_status s = begin(ctx);
+    if (s) return s;
+    ActiveGuard guard(ctx);
+    if (!pos || !sh || !perm || !textures || !counts || !tex_offset || !descs)
+        return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
+    if (n == 0 || n > 0x7FFFFFFFull) return fail(ctx, GSBC_E_ARG, "n = %llu not in 1..2^31-1", (unsigned long long)n);
+    if ((reinterpret_cast<uintptr_t>(sh) & 15) || (reinterpret_cast<uintptr_t>(textures) & 15) ||
+        (reinterpret_cast<uintptr_t>(pos) & 3) || (reinterpret_cast<uintptr_t>(perm) & 3) ||
+        (reinterpret_cast<uintptr_t>(opacity) & 3))
+        return fail(ctx, GSBC_E_ARG, "sh and textures must be 16-byte aligned, pos, opacity and perm 4-byte aligned");
+    if (!(tau >= 0.0f) || !isfinite(tau)) return fail(ctx, GSBC_E_ARG, "tau must be finite and >= 0");
+    gsbc_params p = resolve(params);
+    if ((s = check_params(ctx, p))) return s;
+    if (p.order != 0 || p.arrangement != GSBC_ARR_BANDS)
+        return fail(ctx, GSBC_E_ARG, "degree classes use the sorted band arrangement (order 0, GSBC_ARR_BANDS)");
+    if (p.quantiser == 1 && 3 * n > 0xFFFFFFFFull)
+        return fail(ctx, GSBC_E_ARG, "quantiser 1 counts 3n coefficients per band in 32 bits: n = %llu too large",
+                    (unsigned long long)n);
+    const uint64_t need = degree_textures_bytes(n);
+    if (textures_capacity < need)
+        return fail(ctx, GSBC_E_BUFFER, "textures_capacity %llu < %llu bytes", (unsigned long long)textures_capacity,
+                    (unsigned long long)need);
+    if ((s = ensure_arena(ctx, reorder_scratch_bytes(n, p.grid_bits)))) return s;
+    RangeRec *range = reinterpret_cast<RangeRec *>(small_ptr(ctx, kRangeOff));
+    uint32_t *cls = reinterpret_cast<uint32_t *>(small_ptr(ctx, kClassOff));
+    HIP_TRY(ctx, launch_degree_sort(pos, sh, opacity, n, p.grid_bits, p.quantiser, tau, perm, ctx->arena, range, cls,
+                                    ctx->stream), "degree sort launch");
+    char *stage = static_cast<char *>(ctx->pinned);
+    HIP_TRY(ctx, hipMemcpyAsync(stage, range, sizeof(RangeRec), hipMemcpyDeviceToHost, ctx->stream), "range read-back");
+    HIP_TRY(ctx, hipMemcpyAsync(stage + 512, cls, 4 * sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream),
+            "class counts");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "degree sort");
+    RangeRec r;
+    memcpy(&r, stage, sizeof r);
+    uint32_t c32[4];
+    memcpy(c32, stage + 512, sizeof c32);
+    DegreeLayout lay;
+    lay.slot_start[0] = lay.pad_start[0] = 0;
+    uint64_t word = 0;
+    for (int L = 0; L < 4; L++) {
+        counts[L] = c32[L];
+        lay.slot_start[L + 1] = lay.slot_start[L] + c32[L];
+        lay.pad_start[L + 1] = lay.pad_start[L] + pad16(c32[L]);
+        lay.tex_word[L] = word;
+        tex_offset[L] = word * 4;
+        word += (uint64_t)(L + 1) * (L + 1) * pad16(c32[L]);    // (L+1)^2 streams of pad16/16 blocks x 16 words
+    }
+    if (lay.slot_start[4] != n) return fail(ctx, GSBC_E_DEVICE, "class counts do not add up to n");
+    HIP_TRY(ctx, launch_pack_degrees(sh, opacity, perm, lay, range, textures, ctx->stream), "degree pack launch");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "degree pack");
+    for (int L = 0; L < 4; L++) {
+        gsbc_stream_desc &d = descs[L];
+        memset(&d, 0, sizeof d);
+        for (int k = 0; k < 16; k++) { d.vmin[k] = r.vmin[k]; d.vmax[k] = r.vmax[k]; }
+        d.n_prims = counts[L];
+        d.n_pad = pad16(counts[L]);
+        d.arrangement = GSBC_ARR_BANDS;
+        d.n_streams = (uint32_t)((L + 1) * (L + 1));
+        d.blocks_per_stream = d.n_pad / 16;
+    }
+    return GSBC_OK;
+}
+
 gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc *desc, int format, double rate,
                         const gsbc_params *params, uint8_t *blocks, uint64_t blocks_capacity, int64_t *band_sse)
 {
@@ -419,8 +495,8 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
         for (uint32_t k = 0; k < S; k++)
             if (desc->format[k] != GSBC_FMT_BC1 && desc->format[k] != GSBC_FMT_BC7)
                 return fail(ctx, GSBC_E_ARG, "desc.format[%u] = %u is not BC1 or BC7", k, desc->format[k]);
-    if (format == GSBC_FMT_AUTO && desc->arrangement != GSBC_ARR_BANDS)
-        return fail(ctx, GSBC_E_UNSUPPORTED, "the rate controller chooses formats per band: GSBC_ARR_BANDS only");
+    if (format == GSBC_FMT_AUTO && (desc->arrangement != GSBC_ARR_BANDS || S != 16))
+        return fail(ctx, GSBC_E_UNSUPPORTED, "the rate controller chooses among 16 bands: GSBC_ARR_BANDS with all bands only");
     gsbc_params p = resolve(params);
     if ((s = check_params(ctx, p))) return s;
     const uint64_t nblk = desc->blocks_per_stream;

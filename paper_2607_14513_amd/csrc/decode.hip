@@ -35,8 +35,9 @@ __device__ __forceinline__ uint32_t band_texel(const uint8_t *blocks, const Band
     return bc7_texel(q, texel);
 }
 
-// The 16 band texels of slot s, each found through the arrangement:
-// 0: stream k, block s/16, zigzag texel of s%16; 1: stream 0, block s,
+// The band texels of slot s, each found through the arrangement:
+// 0: stream k, block s/16, zigzag texel of s%16 (only the n_streams kept
+// bands of a lower-degree scene; px[k] = 0 past them); 1: stream 0, block s,
 // texel k; 2: stream k/4, block s/4, texel 4 (s%4) + k%4.
 template <int ARR>
 __device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16])
@@ -45,9 +46,13 @@ __device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const Ban
     for (int k = 0; k < 16; k++) {
         if (ARR == 1) px[k] = band_texel(blocks, b, 0, s, k);
         else if (ARR == 2) px[k] = band_texel(blocks, b, k >> 2, s >> 2, 4 * (int)(s & 3u) + (k & 3));
-        else px[k] = band_texel(blocks, b, k, s >> 4, (int)zigzag_texel(s & 15u));
+        else px[k] = (uint32_t)k < b.n_streams ? band_texel(blocks, b, k, s >> 4, (int)zigzag_texel(s & 15u)) : 0u;
     }
 }
+
+// Bands present in the scene: all 16, or the n_streams lowest of a
+// lower-degree scene in the band arrangement (the rest are exactly zero).
+__device__ __forceinline__ uint32_t kept_bands(const BandArgs &b) { return b.arrangement == 0 ? b.n_streams : 16u; }
 
 __device__ __forceinline__ void slot_texels(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16])
 {
@@ -135,11 +140,13 @@ __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *block
             if (s < n_prims) {
                 uint32_t px[16];
                 slot_texels(blocks, b, s, px);
+                const uint32_t nb = kept_bands(b);
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
-                    h[k][0] = fmaf((float)(px[k] & 255), b.delta[k], b.vmin[k]);
-                    h[k][1] = fmaf((float)((px[k] >> 8) & 255), b.delta[k], b.vmin[k]);
-                    h[k][2] = fmaf((float)((px[k] >> 16) & 255), b.delta[k], b.vmin[k]);
+                    const bool kept = (uint32_t)k < nb;
+                    h[k][0] = kept ? fmaf((float)(px[k] & 255), b.delta[k], b.vmin[k]) : 0.0f;
+                    h[k][1] = kept ? fmaf((float)((px[k] >> 8) & 255), b.delta[k], b.vmin[k]) : 0.0f;
+                    h[k][2] = kept ? fmaf((float)((px[k] >> 16) & 255), b.delta[k], b.vmin[k]) : 0.0f;
                 }
             } else {   // not a slot of this scene: NaN colours, no block access
 #pragma unroll
@@ -273,12 +280,15 @@ __global__ __launch_bounds__(256) void k_decode_eval_view(const uint8_t *blocks,
         Y[15] = -c3a * x * (xx - 3.0f * yy);
         uint32_t px[16];
         slot_texels(blocks, b, s, px);
+        const uint32_t nb = kept_bands(b);
         c[0] = c[1] = c[2] = 0.0f;
 #pragma unroll
         for (int k = 0; k < 16; k++) {
+            if ((uint32_t)k < nb) {
 #pragma unroll
-            for (int ch = 0; ch < 3; ch++)
-                c[ch] = fmaf(fmaf((float)((px[k] >> (8 * ch)) & 255), b.delta[k], b.vmin[k]), Y[k], c[ch]);
+                for (int ch = 0; ch < 3; ch++)
+                    c[ch] = fmaf(fmaf((float)((px[k] >> (8 * ch)) & 255), b.delta[k], b.vmin[k]), Y[k], c[ch]);
+            }
         }
     }
     out[3 * j] = c[0];

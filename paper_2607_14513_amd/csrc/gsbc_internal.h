@@ -79,6 +79,23 @@ hipError_t launch_reorder(const float *pos, const float *sh, const float *opacit
                           uint32_t quantiser, bool identity, uint32_t arrangement, uint32_t *perm, uint8_t *textures,
                           void *scratch, RangeRec *range_dev, hipStream_t st);
 
+// Variable number of bands: class L (SH degree L, (L+1)^2 bands) owns dense
+// slots [slot_start[L], slot_start[L+1]) of perm and padded slots
+// [pad_start[L], pad_start[L+1]) (each class padded to a multiple of 16);
+// its textures start at word tex_word[L] of the textures buffer.
+struct DegreeLayout {
+    uint64_t slot_start[5];
+    uint64_t pad_start[5];
+    uint64_t tex_word[4];
+};
+// Range, keys with the degree class above the cell and colour fields, class
+// counts (device uint32[4]) and the sort into perm.
+hipError_t launch_degree_sort(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
+                              uint32_t quantiser, float tau, uint32_t *perm, void *scratch, RangeRec *range_dev,
+                              uint32_t *class_count, hipStream_t st);
+hipError_t launch_pack_degrees(const float *sh, const float *opacity, const uint32_t *perm, const DegreeLayout &lay,
+                               const RangeRec *range_dev, uint8_t *textures, hipStream_t st);
+
 // ---- encoders (bc1_encode.hip, bc7_encode.hip)
 // The encoders work on runs: a run is the consecutive blocks of one band of
 // one scene, read from `src` (64-byte RGBA blocks) and written to `dst`

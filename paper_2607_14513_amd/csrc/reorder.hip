@@ -143,12 +143,22 @@ __global__ void k_range_final(const uint32_t *acc, const uint32_t *cov, uint32_t
     }
 }
 
+// DEG: also the degree class (the largest SH degree with a coefficient above
+// tau in magnitude, 0 if none) above the cell and colour fields, and the
+// class counts.
+template <bool DEG>
 __global__ __launch_bounds__(256) void k_keys(const float *pos, const float *sh, const float *opacity, uint64_t n,
                                               uint32_t grid_bits, const RangeRec *r,
-                                              uint64_t *keys, uint32_t *vals)
+                                              uint64_t *keys, uint32_t *vals, float tau, uint32_t *class_count)
 {
+    __shared__ uint32_t cls[4];
+    if (DEG) {
+        if (threadIdx.x < 4) cls[threadIdx.x] = 0;
+        __syncthreads();
+    }
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (!DEG && i >= n) return;
+    if (i < n) {
     const uint32_t cmax = (1u << grid_bits) - 1u;
     uint32_t cell[3];
 #pragma unroll
@@ -167,8 +177,32 @@ __global__ __launch_bounds__(256) void k_keys(const float *pos, const float *sh,
     uint32_t q2 = quant8(d2, r->vmin[0], r->scale[0]);
     uint64_t chunk = spread3(cell[0]) | (spread3(cell[1]) << 1) | (spread3(cell[2]) << 2);
     uint32_t colour = (spread3(q0) << 2) | (spread3(q1) << 1) | spread3(q2);
-    keys[i] = (chunk << 24) | colour;
+    uint64_t key = (chunk << 24) | colour;
+    if (DEG) {
+        const float4 *p4 = reinterpret_cast<const float4 *>(dc);
+        float f[48];
+#pragma unroll
+        for (int c = 0; c < 12; c++) {
+            const float4 v = p4[c];
+            f[4 * c] = v.x; f[4 * c + 1] = v.y; f[4 * c + 2] = v.z; f[4 * c + 3] = v.w;
+        }
+        uint32_t L = 0;
+#pragma unroll
+        for (int e = 3; e < 48; e++) {       // bands 1..15; band k has degree floor(sqrt(k))
+            const int k = e / 3, l = k >= 9 ? 3 : k >= 4 ? 2 : 1;
+            const float x = opacity ? mu * f[e] : f[e];
+            if (fabsf(x) > tau) L = L > (uint32_t)l ? L : (uint32_t)l;
+        }
+        key |= (uint64_t)L << (24 + 3 * grid_bits);
+        atomicAdd(&cls[L], 1u);
+    }
+    keys[i] = key;
     vals[i] = (uint32_t)i;
+    }
+    if (DEG) {
+        __syncthreads();
+        if (threadIdx.x < 4 && cls[threadIdx.x]) atomicAdd(&class_count[threadIdx.x], cls[threadIdx.x]);
+    }
 }
 
 // Digit counts of each wave tile; hist is tile-major: hist[tile][digit].
@@ -390,6 +424,53 @@ __global__ void k_cov_init(uint32_t *state, uint32_t rank)
     }
 }
 
+__global__ void k_zero4(uint32_t *c)
+{
+    if (threadIdx.x < 4) c[threadIdx.x] = 0;
+}
+
+// One thread per padded slot of every class: thread t of class L (t in
+// [pad_start[L], pad_start[L+1])) is class slot j = t - pad_start[L], the
+// dense slot slot_start[L] + min(j, count[L] - 1); its (L+1)^2 kept bands go
+// to stream k of the class, block j/16, zigzag texel of j%16.
+__global__ __launch_bounds__(256) void k_pack_degrees(const float *sh, const float *opacity, const uint32_t *perm,
+                                                      DegreeLayout lay, const RangeRec *r, uint32_t *tex)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= lay.pad_start[4]) return;
+    int L = 0;
+    while (L < 3 && t >= lay.pad_start[L + 1]) L++;
+    const uint64_t j = t - lay.pad_start[L];
+    const uint64_t cnt = lay.slot_start[L + 1] - lay.slot_start[L];
+    const uint32_t src = perm[lay.slot_start[L] + (j < cnt ? j : cnt - 1)];
+    const float4 *p = reinterpret_cast<const float4 *>(sh + (uint64_t)src * 48);
+    float f[48];
+#pragma unroll
+    for (int c = 0; c < 12; c++) {
+        const float4 v = p[c];
+        f[4 * c] = v.x; f[4 * c + 1] = v.y; f[4 * c + 2] = v.z; f[4 * c + 3] = v.w;
+    }
+    if (opacity) {
+        const float mu = opacity[src];
+#pragma unroll
+        for (int e = 0; e < 48; e++) f[e] = mu * f[e];
+    }
+    const int nb = (L + 1) * (L + 1);
+    const uint64_t nblk = (lay.pad_start[L + 1] - lay.pad_start[L]) / 16;
+    const uint32_t jj = (uint32_t)(j & 15);
+    const uint32_t x = (jj & 1u) | (((jj >> 2) & 1u) << 1);
+    const uint32_t y = ((jj >> 1) & 1u) | (((jj >> 3) & 1u) << 1);
+    uint32_t *base = tex + lay.tex_word[L] + (j >> 4) * 16 + 4 * y + x;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        if (k < nb) {
+            const float vm = r->vmin[k], sc = r->scale[k];
+            base[(uint64_t)k * nblk * 16] = quant8(f[3 * k], vm, sc) | (quant8(f[3 * k + 1], vm, sc) << 8) |
+                                            (quant8(f[3 * k + 2], vm, sc) << 16) | 0xFF000000u;
+        }
+    }
+}
+
 struct Layout {
     size_t acc, keys_a, keys_b, vals_a, vals_b, hist, total, cov_state, cov_part, bytes;
 };
@@ -424,17 +505,13 @@ __global__ void k_iota(uint32_t *perm, uint64_t n)
     if (s < n) perm[s] = (uint32_t)s;
 }
 
-hipError_t launch_reorder(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
-                          uint32_t quantiser, bool identity, uint32_t arrangement, uint32_t *perm, uint8_t *textures,
-                          void *scratch, RangeRec *range_dev, hipStream_t st)
-{
-    Layout L = layout(n);
-    char *s = static_cast<char *>(scratch);
-    uint32_t *acc = reinterpret_cast<uint32_t *>(s + L.acc);
-    uint64_t *ka = reinterpret_cast<uint64_t *>(s + L.keys_a), *kb = reinterpret_cast<uint64_t *>(s + L.keys_b);
-    uint32_t *va = reinterpret_cast<uint32_t *>(s + L.vals_a), *vb = reinterpret_cast<uint32_t *>(s + L.vals_b);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(s + L.hist), *total = reinterpret_cast<uint32_t *>(s + L.total);
+namespace {
 
+// Range prologue: min/max (and the coverage range when asked) into range_dev.
+void enqueue_range(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
+                   uint32_t quantiser, const Layout &L, char *s, RangeRec *range_dev, hipStream_t st)
+{
+    uint32_t *acc = reinterpret_cast<uint32_t *>(s + L.acc);
     GSBC_LAUNCH("range_init", k_range_init, dim3(1), dim3(64), 0, st, acc);
     uint64_t want = (n * 12 + kRangeBlock - 1) / kRangeBlock;
     uint32_t nb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 2048);
@@ -455,17 +532,15 @@ hipError_t launch_reorder(const float *pos, const float *sh, const float *opacit
         }
     }
     GSBC_LAUNCH("range_final", k_range_final, dim3(1), dim3(64), 0, st, acc, cov, grid_bits, range_dev);
-    if (identity) {
-        GSBC_LAUNCH("iota", k_iota, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, perm, n);
-        const uint64_t npad = (n + 15) / 16 * 16;
-        GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0, st,
-                    sh, opacity, perm, n, npad, arrangement, range_dev, reinterpret_cast<uint32_t *>(textures));
-        return hipGetLastError();
-    }
-    GSBC_LAUNCH("keys", k_keys, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, pos, sh, opacity, n,
-                       grid_bits, range_dev, ka, va);
+}
 
-    const int key_bits = 24 + 3 * (int)grid_bits;
+// LSD radix sort of the keys in keys_a (values vals_a) over key_bits bits;
+// the last pass writes the values to perm.
+void enqueue_sort(uint64_t n, int key_bits, const Layout &L, char *s, uint32_t *perm, hipStream_t st)
+{
+    uint64_t *ka = reinterpret_cast<uint64_t *>(s + L.keys_a), *kb = reinterpret_cast<uint64_t *>(s + L.keys_b);
+    uint32_t *va = reinterpret_cast<uint32_t *>(s + L.vals_a), *vb = reinterpret_cast<uint32_t *>(s + L.vals_b);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(s + L.hist), *total = reinterpret_cast<uint32_t *>(s + L.total);
     const int passes = (key_bits + kDigitBits - 1) / kDigitBits;
     const uint32_t ntiles = (uint32_t)((n + kTile - 1) / kTile);
     const uint32_t nblocks = (ntiles + 3) / 4;
@@ -483,9 +558,55 @@ hipError_t launch_reorder(const float *pos, const float *sh, const float *opacit
         vin = vdst;
         vout = (vdst == va) ? vb : va;
     }
+}
+
+}  // namespace
+
+hipError_t launch_reorder(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
+                          uint32_t quantiser, bool identity, uint32_t arrangement, uint32_t *perm, uint8_t *textures,
+                          void *scratch, RangeRec *range_dev, hipStream_t st)
+{
+    Layout L = layout(n);
+    char *s = static_cast<char *>(scratch);
+    enqueue_range(pos, sh, opacity, n, grid_bits, quantiser, L, s, range_dev, st);
+    if (identity) {
+        GSBC_LAUNCH("iota", k_iota, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, perm, n);
+    } else {
+        uint64_t *ka = reinterpret_cast<uint64_t *>(s + L.keys_a);
+        uint32_t *va = reinterpret_cast<uint32_t *>(s + L.vals_a);
+        GSBC_LAUNCH("keys", k_keys<false>, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, pos, sh, opacity, n,
+                           grid_bits, range_dev, ka, va, 0.0f, (uint32_t *)nullptr);
+        enqueue_sort(n, 24 + 3 * (int)grid_bits, L, s, perm, st);
+    }
     const uint64_t npad = (n + 15) / 16 * 16;
     GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0, st,
                        sh, opacity, perm, n, npad, arrangement, range_dev, reinterpret_cast<uint32_t *>(textures));
+    return hipGetLastError();
+}
+
+hipError_t launch_degree_sort(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
+                              uint32_t quantiser, float tau, uint32_t *perm, void *scratch, RangeRec *range_dev,
+                              uint32_t *class_count, hipStream_t st)
+{
+    Layout L = layout(n);
+    char *s = static_cast<char *>(scratch);
+    enqueue_range(pos, sh, opacity, n, grid_bits, quantiser, L, s, range_dev, st);
+    GSBC_LAUNCH("fill_count", k_zero4, dim3(1), dim3(64), 0, st, class_count);
+    uint64_t *ka = reinterpret_cast<uint64_t *>(s + L.keys_a);
+    uint32_t *va = reinterpret_cast<uint32_t *>(s + L.vals_a);
+    GSBC_LAUNCH("keys_degree", k_keys<true>, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, pos, sh, opacity,
+                       n, grid_bits, range_dev, ka, va, tau, class_count);
+    enqueue_sort(n, 26 + 3 * (int)grid_bits, L, s, perm, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_degrees(const float *sh, const float *opacity, const uint32_t *perm, const DegreeLayout &lay,
+                               const RangeRec *range_dev, uint8_t *textures, hipStream_t st)
+{
+    const uint64_t threads = lay.pad_start[4];
+    if (threads == 0) return hipSuccess;
+    GSBC_LAUNCH("pack_degrees", k_pack_degrees, dim3((uint32_t)((threads + 255) / 256)), dim3(256), 0, st,
+                       sh, opacity, perm, lay, range_dev, reinterpret_cast<uint32_t *>(textures));
     return hipGetLastError();
 }
 

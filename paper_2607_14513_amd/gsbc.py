@@ -20,7 +20,7 @@ ARR_BANDS, ARR_PRIM, ARR_QUAD = 0, 1, 2
 N_STREAMS = {ARR_BANDS: 16, ARR_PRIM: 1, ARR_QUAD: 4}
 
 EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_default_params",
-            "gsbc_query_sizes", "gsbc_reorder", "gsbc_encode", "gsbc_default_batch_tuning",
+            "gsbc_query_sizes", "gsbc_reorder", "gsbc_reorder_degrees", "gsbc_encode", "gsbc_default_batch_tuning",
             "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_decode_eval_view", "gsbc_save", "gsbc_load",
             "gsbc_profile_enable", "gsbc_profile_read")
 
@@ -90,6 +90,8 @@ def load():
         lib.gsbc_default_params.restype = None
         lib.gsbc_query_sizes.argtypes = [u64, u32, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)]
         lib.gsbc_reorder.argtypes = [P, P, P, P, u64, ctypes.POINTER(Params), P, P, ctypes.POINTER(StreamDesc)]
+        lib.gsbc_reorder_degrees.argtypes = [P, P, P, P, u64, ctypes.c_float, ctypes.POINTER(Params), P, P, u64,
+                                             ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(StreamDesc)]
         lib.gsbc_encode.argtypes = [P, P, ctypes.POINTER(StreamDesc), ctypes.c_int, ctypes.c_double,
                                     ctypes.POINTER(Params), P, u64, P]
         lib.gsbc_default_batch_tuning.argtypes = [ctypes.POINTER(BatchTuning)]
@@ -240,6 +242,38 @@ class Context:
                                         _ptr(opacity) if opacity is not None else None, n, ctypes.byref(p), _ptr(perm),
                                         _ptr(tex), ctypes.byref(desc)))
         return perm, tex, desc
+
+    def reorder_degrees(self, pos, sh, tau=0.0, params=None, opacity=None):
+        """Degree classes (variable number of bands).  Returns (perm int32[n],
+        counts[4], textures: list of 4 device uint8 views [(L+1)^2][nblk][16][4]
+        or None for an empty class, descs: list of 4 StreamDesc)."""
+        _dev_tensor(pos, torch.float32, "pos")
+        _dev_tensor(sh, torch.float32, "sh")
+        n = pos.shape[0]
+        if opacity is not None:
+            _dev_tensor(opacity, torch.float32, "opacity")
+            if opacity.numel() != n:
+                raise ValueError("opacity must hold one weight per primitive")
+        p = params if params is not None else default_params()
+        cap = (n + 15) // 16 * 16 * 64 + 1800
+        buf = torch.empty(cap, dtype=torch.uint8, device=self.device)
+        perm = torch.empty(n, dtype=torch.int32, device=self.device)
+        counts = (ctypes.c_uint64 * 4)()
+        offs = (ctypes.c_uint64 * 4)()
+        descs = (StreamDesc * 4)()
+        self._check(load().gsbc_reorder_degrees(self._h, _ptr(pos), _ptr(sh),
+                                                _ptr(opacity) if opacity is not None else None, n, float(tau),
+                                                ctypes.byref(p), _ptr(perm), _ptr(buf), cap, counts, offs, descs))
+        tex = []
+        for L in range(4):
+            c = int(counts[L])
+            if c == 0:
+                tex.append(None)
+                continue
+            nb, nblk = (L + 1) ** 2, (c + 15) // 16
+            o = int(offs[L])
+            tex.append(buf[o:o + nb * nblk * 64].view(nb, nblk, 16, 4))
+        return perm, [int(c) for c in counts], tex, [descs[L] for L in range(4)]
 
     def encode(self, textures, desc, fmt=FMT_AUTO, rate=6.0, params=None, blocks=None, want_sse=False):
         """Encode all streams -> (blocks uint8 device tensor, desc, band_sse int64[2][16] or None).
