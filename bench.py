@@ -82,6 +82,7 @@ def parse():
                     help="run a plain 1 GiB device copy first (for counter scaling)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-scene batched-encode leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-degrees", action="store_true", help="skip the degree-class (variable bands) leg")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--batch-scenes", type=int, default=64)
     return ap.parse_args()
@@ -231,6 +232,62 @@ def main():
             arrangements.append(arrangement_row(label, arr, order, fmts))
         torch.cuda.empty_cache()
 
+        # ---- variable number of bands (degree classes) on a scene of the same
+        # size whose primitives use SH degree 0..3 in proportions MIX: classes
+        # coded band 0 BC7 + the rest BC1 in one batch, against all 16 bands
+        degrees = None
+        if not args.no_degrees:
+            mix = (0.35, 0.2, 0.15, 0.3)
+            posg, shg = synth.make_scene(n, cfg["clusters"], cfg["comps"], cfg["seed"] + 100, degree_mix=mix)
+            posg_d, shg_d = torch.from_numpy(posg).to(dev), torch.from_numpy(shg).to(dev)
+            del posg, shg
+            ctx.reorder_degrees(posg_d, shg_d)                    # warm-up
+            t_re = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                permg, counts, texg, descg = ctx.reorder_degrees(posg_d, shg_d)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t_re.append(e0.elapsed_time(e1))
+            live = [L for L in range(4) if counts[L]]
+            for L in live:
+                for k in range(descg[L].n_streams):
+                    descg[L].format[k] = 7 if k == 0 else 1
+            bufs = [torch.empty(descg[L].n_pad * 16, dtype=torch.uint8, device=dev) for L in live]
+            tx = [texg[L] for L in live]
+            dsc = [descg[L] for L in live]
+            ctx.encode_batch(tx, dsc, bufs)
+            t_cls = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                outd, _ = ctx.encode_batch(tx, dsc, bufs)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t_cls.append(e0.elapsed_time(e1))
+            bytes_cls = sum(d.payload_bytes for d in outd)
+            _, tfull, dfull = ctx.reorder(posg_d, shg_d)
+            for k in range(16):
+                dfull.format[k] = 7 if k == 0 else 1
+            t_full = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                _, df2, _ = ctx.encode(tfull, dfull, fmt=gsbc.FMT_BANDS, blocks=blocks)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t_full.append(e0.elapsed_time(e1))
+            degrees = {"workload": f"{n:,} primitives, SH degree 0..3 drawn with probabilities {list(mix)}, "
+                                   "band 0 BC7 + the other kept bands BC1, classes in one batch",
+                       "class_counts": counts, "reorder_ms": round(float(np.median(t_re)), 3),
+                       "encode_classes_ms": round(float(np.median(t_cls)), 3),
+                       "encode_all_bands_ms": round(float(np.median(t_full)), 3),
+                       "bytes_per_primitive_classes": round(bytes_cls / n, 3),
+                       "bytes_per_primitive_all_bands": round(df2.payload_bytes / n, 3)}
+            del posg_d, shg_d, permg, texg, tx, bufs, tfull
+            torch.cuda.empty_cache()
+
         # ---- decode_eval on the 3,145,728-primitive scene at 1,024 directions
         roof_de = None
         if not args.no_large:
@@ -308,6 +365,7 @@ def main():
         "bc1_encode_mblocks_s": round(rates["bc1"], 3),
         "psnr_db_per_band": psnr,
         "arrangements": arrangements,
+        "degree_classes": degrees,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "roofline": roof,
         "roofline_decode_eval": roof_de,
