@@ -77,17 +77,17 @@ __device__ __forceinline__ void candidate(int ci, int &m, int &p, int &r, int &s
 // ---- texels in LDS
 //
 // Texels sit in LDS, one column per lane: rg = 16 R | 16 G << 16 and
-// bx = B | 256 (R^2 + G^2 + B^2) (the low byte of the second term is zero).
-// Because |x|^2 is the same for every palette entry, the least-SSE entry is
-// the least 256 (|p|^2 - 2 x.p) + k, so with each entry held as
+// bx = B.  Because |x|^2 is the same for every palette entry, the least-SSE
+// entry is the least 256 (|p|^2 - 2 x.p) + k, so with each entry held as
 // (-32 pR, -32 pG), -512 pB and 256 |p|^2 + k one texel x entry evaluation is
 // three VALU ops:
 //   t = B * (-512 pB) + (256 |p|^2 + k)            (v_mad_i32_i24)
 //   t = 16 R * (-32 pR) + 16 G * (-32 pG) + t      (v_dot2c_i32_i16)
 //   best = min(best, t)                            (v_min_i32)
-// and 256 |x|^2 added to the minimum gives 256 SSE + k exactly (all terms
-// stay within int32: |t| < 2^26).  Summed over at most 16 members the k
-// terms stay below 256, so the subset SSE is the sum shifted right by 8.
+// and the members' minima plus 256 sum |x|^2 (taken once per subset from
+// its sums) give 256 SSE + sum k exactly (all terms stay within int32:
+// |t| < 2^26).  Summed over at most 16 members the k terms stay below 256,
+// so the subset SSE is the sum shifted right by 8.
 // In the search the subset masks are wave-uniform, so texel loops walk the
 // set bits of a mask with scalar control.
 constexpr int kWG = 256;
@@ -101,28 +101,19 @@ struct TexLds {
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
-// Texel i of this lane: packed 16 R | 16 G << 16, B, and 256 |x|^2;
-// rotation r puts 255 in channel r-1.
-__device__ __forceinline__ void texel(const TexLds &S, int i, int rot, uint32_t &rg, int &b, int &cx)
+// Texel i of this lane: packed 16 R | 16 G << 16 and B; rotation r puts
+// 255 in channel r-1.
+__device__ __forceinline__ void texel(const TexLds &S, int i, int rot, uint32_t &rg, int &b)
 {
     rg = S.rg[i][threadIdx.x];
-    const uint32_t bx = S.bx[i][threadIdx.x];
-    b = (int)(bx & 255u);
-    cx = (int)(bx & ~255u);
+    b = (int)S.bx[i][threadIdx.x];
     if (rot) {
         int r = (int)__builtin_amdgcn_ubfe(rg, 4, 8), g = (int)(rg >> 20);
         if (rot == 1) r = 255;
         else if (rot == 2) g = 255;
         else b = 255;
         rg = (uint32_t)(16 * r) | ((uint32_t)(16 * g) << 16);
-        cx = 256 * (r * r + g * g + b * b);
     }
-}
-
-__device__ __forceinline__ void texel(const TexLds &S, int i, int rot, uint32_t &rg, int &b)
-{
-    int cx;
-    texel(S, i, rot, rg, b, cx);
 }
 
 __device__ __forceinline__ void unpack(uint32_t rg, int b, int (&x)[3])
@@ -139,6 +130,7 @@ struct Prep {
     bool same;
     int lo[3], hi[3];
     int Sx[3];   // member sums per channel (for the least-squares refit)
+    int xx;      // sum of |x|^2 over the members
 };
 
 // Member sums of a subset: count, per-channel sums and the six distinct
@@ -199,6 +191,7 @@ __device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int 
     C[2][2] = __mul24(n, m.XX[5]) - __mul24(m.Sx[2], m.Sx[2]);
     P.same = (C[0][0] | C[1][1] | C[2][2]) == 0;
     P.Sx[0] = m.Sx[0]; P.Sx[1] = m.Sx[1]; P.Sx[2] = m.Sx[2];
+    P.xx = m.XX[0] + m.XX[3] + m.XX[5];
     if (P.same) {
         uint32_t rg;
         int b;
@@ -235,7 +228,8 @@ __device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int 
 #pragma unroll
         for (int a = 0; a < 3; a++)
             u[a] = __builtin_amdgcn_sdot2(c01[a], v01, __builtin_amdgcn_sdot2(c2[a], v2, 0, false), false);
-        int mx = max(abs(u[0]), max(abs(u[1]), abs(u[2])));
+        // max |u_a| as max(max u, -min u): two three-way operations
+        const int mx = max(max(u[0], max(u[1], u[2])), -min(u[0], min(u[1], u[2])));
         int sh = max(0, bitlen(mx) - 15);
 #pragma unroll
         for (int a = 0; a < 3; a++) v[a] = u[a] >> sh;
@@ -286,10 +280,10 @@ struct PairFit {
 // for all combinations (once per combination for 16-entry palettes).  Per member and combination the running sum
 // takes 256 SSE + k in one add and the index enters a 64-bit shift register
 // (newest member at the top; the register holds the n indices in its top
-// 4 n bits).
-template <int CB, int PB, int NB>
+// 4 n bits).  IDX = false: the SSE only (the indices are not kept).
+template <int CB, int PB, int NB, bool IDX = true>
 __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int rot, const int (&lo)[3],
-                                             const int (&hi)[3])
+                                             const int (&hi)[3], int xx)
 {
     constexpr int NPC = PB == 2 ? 4 : PB == 1 ? 2 : 1;
     constexpr int NE = 1 << NB;
@@ -329,21 +323,29 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
             const int a_b = 64 * d0[2] + 32, s_b = d1[2] - d0[2];
 #pragma unroll
             for (int k = 0; k < NE; k++) {
+                // entries 0 and NE-1 are the endpoints themselves (weights 0 and 64)
                 const short w = (short)bc7_weight(NB, k);
-                const short2_t v = (a_rg + s_rg * w) >> (short)6;
-                const int bb = (int)__builtin_amdgcn_ubfe((uint32_t)(a_b + s_b * w), 6, 8);
+                const short2_t v = k == 0 ? short2_t{(short)d0[0], (short)d0[1]}
+                                 : k == NE - 1 ? short2_t{(short)d1[0], (short)d1[1]}
+                                               : (a_rg + s_rg * w) >> (short)6;
+                const int bb = k == 0 ? d0[2] : k == NE - 1 ? d1[2]
+                                      : (int)__builtin_amdgcn_ubfe((uint32_t)(a_b + s_b * w), 6, 8);
                 prg[j][k] = __builtin_bit_cast(uint32_t, v * (short)-32);
                 pb[j][k] = -512 * bb;
                 pk[j][k] = 256 * __builtin_amdgcn_sdot2(v, v, __mul24(bb, bb), false) + k;
             }
         }
+        // 256 SSE + k summed over members: 256 |x|^2 added once per subset
         uint32_t acc[CPV], rlo[CPV], rhi[CPV];
 #pragma unroll
-        for (int j = 0; j < CPV; j++) acc[j] = rlo[j] = rhi[j] = 0;
+        for (int j = 0; j < CPV; j++) {
+            acc[j] = 256u * (uint32_t)xx;
+            rlo[j] = rhi[j] = 0;
+        }
         for (uint32_t m = mask; m; m &= m - 1) {
             uint32_t rg;
-            int b, cx;
-            texel(S, __ffs(m) - 1, rot, rg, b, cx);
+            int b;
+            texel(S, __ffs(m) - 1, rot, rg, b);
 #pragma unroll
             for (int j = 0; j < CPV; j++) {
                 int kb = 0x7FFFFFFF;
@@ -357,9 +359,11 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
                                                            __mul24(b, pb[js][k]) + pk[js][k], false);
                     kb = min(kb, key);
                 }
-                acc[j] += (uint32_t)kb + (uint32_t)cx;   // 256 SSE + k of this member
-                rlo[j] = __builtin_amdgcn_alignbit(rhi[j], rlo[j], 4);
-                rhi[j] = __builtin_amdgcn_alignbit((uint32_t)kb, rhi[j], 4);
+                acc[j] += (uint32_t)kb;   // 256 (SSE - |x|^2) + k of this member
+                if (IDX) {
+                    rlo[j] = __builtin_amdgcn_alignbit(rhi[j], rlo[j], 4);
+                    rhi[j] = __builtin_amdgcn_alignbit((uint32_t)kb, rhi[j], 4);
+                }
             }
         }
 #pragma unroll
@@ -368,7 +372,7 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
             if (sse < best.sse) {
                 const int pc = pc0 + j;
                 best.sse = sse;
-                best.idx = (((uint64_t)rhi[j] << 32) | rlo[j]) >> (64 - 4 * n);
+                best.idx = IDX ? (((uint64_t)rhi[j] << 32) | rlo[j]) >> (64 - 4 * n) : 0;
                 best.c0 = c0[j];
                 best.c1 = c1[j];
                 best.p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
@@ -449,7 +453,9 @@ __device__ __forceinline__ bool ls_endpoints(const TexLds &S, uint32_t mask, int
 }
 
 // Fit one colour subset with endpoint precision (CB, PB) and NB-bit indices.
-template <int CB, int PB, int NB>
+// SEARCH: only the SSE is wanted (the search pass); the refit's indices and
+// the positional index layout are skipped.
+template <int CB, int PB, int NB, bool SEARCH = false>
 __device__ __forceinline__ PairFit fit_colour(const TexLds &S, uint32_t mask, int rot, const Prep &P,
                                               const uint32_t *sv)
 {
@@ -491,12 +497,13 @@ __device__ __forceinline__ PairFit fit_colour(const TexLds &S, uint32_t mask, in
     }
     // (b) endpoints from the principal axis, (c) quantise and index,
     // (d) one least-squares refit kept only if strictly better
-    PairFit f = eval_pair<CB, PB, NB>(S, mask, rot, P.lo, P.hi);
+    PairFit f = eval_pair<CB, PB, NB>(S, mask, rot, P.lo, P.hi, P.xx);
     int rlo[3], rhi[3];
     if (ls_endpoints<NB>(S, mask, rot, f.idx, P.Sx, rlo, rhi)) {
-        PairFit g = eval_pair<CB, PB, NB>(S, mask, rot, rlo, rhi);
+        PairFit g = eval_pair<CB, PB, NB, !SEARCH>(S, mask, rot, rlo, rhi, P.xx);
         if (g.sse < f.sse) f = g;
     }
+    if (SEARCH) return f;
     // member order -> texel positions
     uint64_t pos = 0, c = f.idx;
     for (uint32_t m = mask; m; m &= m - 1) {
@@ -628,13 +635,13 @@ __device__ __forceinline__ uint32_t search_group(const TexLds &S, uint32_t mode_
                 const Sums s0 = subset_sums(S, m0, 0);
                 const Prep P0 = prep_subset(S, m0, 0, s0), P1 = prep_subset(S, m1, 0, sums_minus(tot, s0));
                 if (mode_mask & 0x02)
-                    consider(fit_colour<6, 1, 3>(S, m0, 0, P0, sv).sse + fit_colour<6, 1, 3>(S, m1, 0, P1, sv).sse,
+                    consider(fit_colour<6, 1, 3, true>(S, m0, 0, P0, sv).sse + fit_colour<6, 1, 3, true>(S, m1, 0, P1, sv).sse,
                              16 + p, best);
                 if (mode_mask & 0x08)
-                    consider(fit_colour<7, 2, 2>(S, m0, 0, P0, sv).sse + fit_colour<7, 2, 2>(S, m1, 0, P1, sv).sse,
+                    consider(fit_colour<7, 2, 2, true>(S, m0, 0, P0, sv).sse + fit_colour<7, 2, 2, true>(S, m1, 0, P1, sv).sse,
                              144 + p, best);
                 if (mode_mask & 0x80)
-                    consider(fit_colour<5, 2, 2>(S, m0, 0, P0, sv).sse + fit_colour<5, 2, 2>(S, m1, 0, P1, sv).sse,
+                    consider(fit_colour<5, 2, 2, true>(S, m0, 0, P0, sv).sse + fit_colour<5, 2, 2, true>(S, m1, 0, P1, sv).sse,
                              221 + p, best);
             }
     } else if (GROUP == 1) {
@@ -646,11 +653,11 @@ __device__ __forceinline__ uint32_t search_group(const TexLds &S, uint32_t mode_
                 const Prep P0 = prep_subset(S, m0, 0, s0), P1 = prep_subset(S, m1, 0, s1);
                 const Prep P2 = prep_subset(S, m2, 0, sums_minus(sums_minus(tot, s0), s1));
                 if ((mode_mask & 0x01) && p < 16)
-                    consider(fit_colour<4, 2, 3>(S, m0, 0, P0, sv).sse + fit_colour<4, 2, 3>(S, m1, 0, P1, sv).sse +
-                                 fit_colour<4, 2, 3>(S, m2, 0, P2, sv).sse, p, best);
+                    consider(fit_colour<4, 2, 3, true>(S, m0, 0, P0, sv).sse + fit_colour<4, 2, 3, true>(S, m1, 0, P1, sv).sse +
+                                 fit_colour<4, 2, 3, true>(S, m2, 0, P2, sv).sse, p, best);
                 if (mode_mask & 0x04)
-                    consider(fit_colour<5, 0, 2>(S, m0, 0, P0, sv).sse + fit_colour<5, 0, 2>(S, m1, 0, P1, sv).sse +
-                                 fit_colour<5, 0, 2>(S, m2, 0, P2, sv).sse, 80 + p, best);
+                    consider(fit_colour<5, 0, 2, true>(S, m0, 0, P0, sv).sse + fit_colour<5, 0, 2, true>(S, m1, 0, P1, sv).sse +
+                                 fit_colour<5, 0, 2, true>(S, m2, 0, P2, sv).sse, 80 + p, best);
             }
     } else {
         // one subset: mode 6, and modes 4 / 5 for every rotation
@@ -658,16 +665,16 @@ __device__ __forceinline__ uint32_t search_group(const TexLds &S, uint32_t mode_
             for (int r = 0; r < 4; r++) {
                 if (r > 0 && !(mode_mask & 0x30)) break;
                 const Prep P = prep_subset(S, 0xFFFFu, r);
-                if (r == 0 && (mode_mask & 0x40)) consider(fit_colour<7, 2, 4>(S, 0xFFFFu, 0, P, sv).sse, 220, best);
+                if (r == 0 && (mode_mask & 0x40)) consider(fit_colour<7, 2, 4, true>(S, 0xFFFFu, 0, P, sv).sse, 220, best);
                 if (mode_mask & 0x10) {
-                    uint32_t s0 = fit_colour<5, 0, 2>(S, 0xFFFFu, r, P, sv).sse;
-                    uint32_t s1 = fit_colour<5, 0, 3>(S, 0xFFFFu, r, P, sv).sse;
+                    uint32_t s0 = fit_colour<5, 0, 2, true>(S, 0xFFFFu, r, P, sv).sse;
+                    uint32_t s1 = fit_colour<5, 0, 3, true>(S, 0xFFFFu, r, P, sv).sse;
                     if (r) { s0 += fit_scalar<6, 3>(S, r, sv).sse; s1 += fit_scalar<6, 2>(S, r, sv).sse; }
                     consider(s0, 208 + 2 * r, best);
                     consider(s1, 209 + 2 * r, best);
                 }
                 if (mode_mask & 0x20) {
-                    uint32_t s5 = fit_colour<7, 0, 2>(S, 0xFFFFu, r, P, sv).sse;
+                    uint32_t s5 = fit_colour<7, 0, 2, true>(S, 0xFFFFu, r, P, sv).sse;
                     if (r) s5 += fit_scalar<8, 2>(S, r, sv).sse;
                     consider(s5, 216 + r, best);
                 }
@@ -829,7 +836,7 @@ __device__ __forceinline__ void stage_texels(TexLds &S, const uint8_t *src, bool
     for (int i = 0; i < 16; i++) {
         const uint32_t r = t[i] & 255u, g = (t[i] >> 8) & 255u, bb = (t[i] >> 16) & 255u;
         S.rg[i][threadIdx.x] = (r << 4) | (g << 20);
-        S.bx[i][threadIdx.x] = bb | (256u * (r * r + g * g + bb * bb));
+        S.bx[i][threadIdx.x] = bb;
     }
 }
 
