@@ -432,20 +432,21 @@ __device__ __forceinline__ bool ls_endpoints(const TexLds &S, uint32_t mask, int
     for (int c = 0; c < 3; c++) SA[c] = 64 * Sx[c] - SB[c];
     const double det = (double)A * (double)B - (double)AB * (double)AB;
     if (det == 0.0) return false;
-    // 1/det in FP64 from the FP32 reciprocal and two Newton steps (within 2^-50)
+    // 1/det in FP64 from the FP32 reciprocal and two Newton steps (within
+    // 2^-50), times 64 (exact) for the numerators' common factor
     double inv = (double)__builtin_amdgcn_rcpf((float)det);
     inv = fma(fma(-det, inv, 1.0), inv, inv);
-    inv = fma(fma(-det, inv, 1.0), inv, inv);
+    inv = 64.0 * fma(fma(-det, inv, 1.0), inv, inv);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        // Exact numerators (< 2^42).  floor(n/det + 1/2) is taken as
-        // floor(n * inv + 1/2 + 2^-37): (2 n + det) / (2 det) is a multiple of
-        // 1/(2 det) >= 2^-33, and for |n/det| <= 512 the FP64 error is below
-        // 2^-40, so the margin never moves the floor; larger quotients clamp
-        // to 0 or 255 either way.
-        const double n0 = 64.0 * ((double)B * (double)SA[c] - (double)AB * (double)SB[c]);
-        const double n1 = 64.0 * ((double)A * (double)SB[c] - (double)AB * (double)SA[c]);
-        const double q0 = floor(fma(n0, inv, 0.5 + 0x1p-37)), q1 = floor(fma(n1, inv, 0.5 + 0x1p-37));
+        // Exact numerators n = 64 m (m < 2^36).  floor(n/det + 1/2) is taken
+        // as floor(m * 64 inv + 1/2 + 2^-37): (2 n + det) / (2 det) is a
+        // multiple of 1/(2 det) >= 2^-33, and for |n/det| <= 512 the FP64
+        // error is below 2^-40, so the margin never moves the floor; larger
+        // quotients clamp to 0 or 255 either way.
+        const double m0 = (double)B * (double)SA[c] - (double)AB * (double)SB[c];
+        const double m1 = (double)A * (double)SB[c] - (double)AB * (double)SA[c];
+        const double q0 = floor(fma(m0, inv, 0.5 + 0x1p-37)), q1 = floor(fma(m1, inv, 0.5 + 0x1p-37));
         lo[c] = (int)fmin(fmax(q0, 0.0), 255.0);
         hi[c] = (int)fmin(fmax(q1, 0.0), 255.0);
     }
