@@ -24,6 +24,12 @@
 #include <vector>
 
 namespace gsbc {
+
+// (-32, -32) as packed 16-bit lanes, read from memory (external linkage, so
+// it is not folded) so that the palette scaling is one packed multiply by a
+// scalar register; a literal -32 becomes a shift and a negation.
+__constant__ uint32_t g_bc7_neg32_pair = 0xFFE0FFE0u;
+
 namespace {
 
 // ---- tables (device global memory, built on the host at first use)
@@ -290,6 +296,7 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
     constexpr int CPV = NPC * NE <= 32 ? NPC : 1;   // combinations per member visit
     constexpr int cls = cls_of(CB, PB);
     const int n = __popc(mask);
+    const short2_t m32 = __builtin_bit_cast(short2_t, g_bc7_neg32_pair);
     PairFit best;
     best.sse = 0xFFFFFFFFu;
     best.idx = 0;
@@ -330,7 +337,7 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
                                                : (a_rg + s_rg * w) >> (short)6;
                 const int bb = k == 0 ? d0[2] : k == NE - 1 ? d1[2]
                                       : (int)__builtin_amdgcn_ubfe((uint32_t)(a_b + s_b * w), 6, 8);
-                prg[j][k] = __builtin_bit_cast(uint32_t, v * (short)-32);
+                prg[j][k] = __builtin_bit_cast(uint32_t, v * m32);
                 pb[j][k] = -512 * bb;
                 pk[j][k] = 256 * __builtin_amdgcn_sdot2(v, v, __mul24(bb, bb), false) + k;
             }
@@ -446,7 +453,8 @@ __device__ __forceinline__ bool ls_endpoints(const TexLds &S, uint32_t mask, int
         // quotients clamp to 0 or 255 either way.
         const double m0 = (double)B * (double)SA[c] - (double)AB * (double)SB[c];
         const double m1 = (double)A * (double)SB[c] - (double)AB * (double)SA[c];
-        const double q0 = floor(fma(m0, inv, 0.5 + 0x1p-37)), q1 = floor(fma(m1, inv, 0.5 + 0x1p-37));
+        // floor then clamp to [0, 255] equals clamp then truncate
+        const double q0 = fma(m0, inv, 0.5 + 0x1p-37), q1 = fma(m1, inv, 0.5 + 0x1p-37);
         lo[c] = (int)fmin(fmax(q0, 0.0), 255.0);
         hi[c] = (int)fmin(fmax(q1, 0.0), 255.0);
     }
