@@ -18,6 +18,7 @@
 #include "gsbc_internal.h"
 #include "bc_format.h"
 
+#include <cstdlib>
 #include <vector>
 
 namespace gsbc {
@@ -25,12 +26,16 @@ namespace {
 
 
 // Constant-colour endpoint tables per channel width (0: 5 bits, 1: 6 bits),
-// and the nearest-code table of the cluster fit: code[w][h] is the number of
-// codes c < max with E(c) + E(c+1) < h.
+// the nearest-code table of the cluster fit (code[w][h] is the number of
+// codes c < max with E(c) + E(c+1) < h), and for every split of the 4- and
+// 3-cluster lists, in enumeration order, the division multiplier
+// ceil(2^36 / det) of its determinant (0 where det = 0).
+constexpr int kSplits4 = 969, kSplits3 = 153;
 struct Bc1Tables {
     uint8_t a4[2][256], b4[2][256], e4[2][256];
     uint8_t a3[2][256], b3[2][256], e3[2][256];
     uint8_t code[2][512];
+    uint32_t magic4[kSplits4], magic3[kSplits3];
 };
 __constant__ Bc1Tables kTab;
 
@@ -74,6 +79,19 @@ __device__ __forceinline__ int quant_h(int y, double inv)
 {
     const int h = (int)ceil(fma((double)y, inv, -0x1p-24));
     return min(max(h, 0), 511);
+}
+
+// The same h in integer arithmetic for a wave-uniform det with M =
+// ceil(2^36 / det): y is clamped to [1 - det, 511 det] (which leaves the
+// clamped ceiling unchanged), then ceil(y / det) = floor(n / det) with
+// n = y + det - 1 in [0, 2^22), and floor(n / det) = floor(n M / 2^36) for
+// every n < 2^23 because det <= 2^13 (the multiplier's error n e / 2^36,
+// e < 1, stays below 2^-13 <= 1/det, the least distance of n/det below the
+// next integer).
+__device__ __forceinline__ int quant_h_int(int y, int det, uint32_t M)
+{
+    const int yc = min(max(y, 1 - det), 511 * det);
+    return (int)(__umulhi((uint32_t)(yc + det - 1), M) >> 4);
 }
 
 __device__ inline uint32_t pack565(int r, int g, int b) { return ((uint32_t)r << 11) | ((uint32_t)g << 5) | (uint32_t)b; }
@@ -150,16 +168,18 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
                                            int Q, uint32_t &best, uint32_t &best_split)
 {
     constexpr int F = FOUR ? 3 : 2;
+    const uint32_t *magic = FOUR ? kTab.magic4 : kTab.magic3;
+    int si = 0;   // split number in enumeration order
     for (int s1 = 0; s1 <= 16; s1++)
         for (int s2 = s1; s2 <= 16; s2++)
             for (int s3 = FOUR ? s2 : 16; s3 <= 16; s3++) {
+                const uint32_t M = magic[si++];
                 const int n0 = s1, n1 = s2 - s1, n2 = s3 - s2, n3 = 16 - s3;
                 const int A = FOUR ? 9 * n0 + 4 * n1 + n2 : 4 * n0 + n1;
                 const int B = FOUR ? n1 + 4 * n2 + 9 * n3 : n1 + 4 * n2;
                 const int AB = FOUR ? 2 * (n1 + n2) : n1;
                 const int det = A * B - AB * AB;
                 if (det == 0) continue;
-                const double inv = recip(det);
                 int sse = Q;
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
@@ -169,8 +189,8 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
                     const int sam = FOUR ? a + bq + cq : a + bq;   // -2 SA
                     const int y0 = mul_i24(sam, -F * (B + AB)) + mul_i24(tot[c], -2 * F * F * AB);
                     const int y1 = mul_i24(sam, F * (A + AB)) + mul_i24(tot[c], 2 * F * F * A);
-                    const int e0 = L.val[wide][quant_h(y0, inv)];
-                    const int e1 = L.val[wide][quant_h(y1, inv)];
+                    const int e0 = L.val[wide][quant_h_int(y0, det, M)];
+                    const int e1 = L.val[wide][quant_h_int(y1, det, M)];
                     if (FOUR) {
                         // (2 e0 + e1 + 1) / 3 and (e0 + 2 e1 + 1) / 3 as (v * 43691) >> 17, exact for v < 2^17
                         const int p1 = (int)((mul_u24((uint32_t)(2 * e0 + e1), 43691u) + 43691u) >> 17);
@@ -466,6 +486,23 @@ void build_tables(Bc1Tables &T)
             for (int c = 0; c + 1 < nc; c++) n += ew(c, wide) + ew(c + 1, wide) < h;
             T.code[wide][h] = (uint8_t)n;
         }
+    }
+    // split multipliers, enumerated as the device's split lists are
+    for (int four = 0; four < 2; four++) {
+        uint32_t *M = four ? T.magic4 : T.magic3;
+        int si = 0;
+        for (int s1 = 0; s1 <= 16; s1++)
+            for (int s2 = s1; s2 <= 16; s2++)
+                for (int s3 = four ? s2 : 16; s3 <= 16; s3++) {
+                    const int n0 = s1, n1 = s2 - s1, n2 = s3 - s2, n3 = 16 - s3;
+                    const int A = four ? 9 * n0 + 4 * n1 + n2 : 4 * n0 + n1;
+                    const int B = four ? n1 + 4 * n2 + 9 * n3 : n1 + 4 * n2;
+                    const int AB = four ? 2 * (n1 + n2) : n1;
+                    const long long det = (long long)A * B - (long long)AB * AB;
+                    M[si++] = det > 0 ? (uint32_t)(((1ull << 36) + (unsigned long long)det - 1) / (unsigned long long)det)
+                                      : 0u;
+                }
+        if (si != (four ? kSplits4 : kSplits3)) abort();
     }
 }
 
