@@ -296,9 +296,42 @@ def main():
             c3 = synth.CONFIGS["large"]
             pos3, sh3 = synth.make_scene(c3["n"], c3["clusters"], c3["comps"], c3["seed"])
             dirs3 = torch.from_numpy(synth.make_dirs(c3["dirs"], seed=c3["seed"])).to(dev)
-            p3, t3, dd = ctx.reorder(torch.from_numpy(pos3).to(dev), torch.from_numpy(sh3).to(dev))
+            pos3_d, sh3_d = torch.from_numpy(pos3).to(dev), torch.from_numpy(sh3).to(dev)
+            p3, t3, dd = ctx.reorder(pos3_d, sh3_d)
             b3, dd2, _ = ctx.encode(t3, dd, fmt=gsbc.FMT_AUTO, rate=c3["rate"])
-            del t3
+            # timed reorder and rate-controlled encode of this scene (both
+            # formats on every band, then the exact 6 bits/texel choice)
+            t_re, t_en = [], []
+            for i in range(3):
+                e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+                e0.record(stream)
+                p3, t3, dd = ctx.reorder(pos3_d, sh3_d, out=(p3, t3))
+                e1.record(stream)
+                b3, dd2, _ = ctx.encode(t3, dd, fmt=gsbc.FMT_AUTO, rate=c3["rate"], blocks=b3)
+                e2.record(stream)
+                torch.cuda.synchronize()
+                t_re.append(e0.elapsed_time(e1) * 1e-3)
+                t_en.append(e1.elapsed_time(e2) * 1e-3)
+            nblk3 = dd.blocks_per_stream
+            budget = int(c3["rate"] * 16 * 16 * nblk3 // 8)       # bits per texel x texels, in bytes
+            # reorder bytes per primitive: range pass (SH 192 + position 12),
+            # key pass (position 12 + DC 12 read, key 8 + index 4 written),
+            # three sort passes (key 8 read for the histogram, key and index
+            # 12 read and 12 written by the scatter), gather (perm 4 + SH 192
+            # read, texels 64 written)
+            re_bytes_per_prim = 204 + 36 + 3 * 32 + 260
+            re_s = float(np.median(t_re))
+            large_enc = {"workload": "3,145,728 primitives (256 clusters, 256-component DC mixture, seed 3), "
+                                     "6 bits/texel: band 0 BC7, 7 of bands 1..15 BC7, the rest BC1",
+                         "reorder_ms": round(re_s * 1e3, 3),
+                         "reorder_gb_s": round(re_bytes_per_prim * c3["n"] / re_s / 1e9, 1),
+                         "encode_ms": round(float(np.median(t_en)) * 1e3, 3),
+                         "blocks_coded": 2 * 16 * nblk3,
+                         "encode_mblocks_s": round(2 * 16 * nblk3 / float(np.median(t_en)) / 1e6, 2),
+                         "payload_bytes": int(dd2.payload_bytes), "budget_bytes": budget,
+                         "rate_exact": int(dd2.payload_bytes) == budget,
+                         "bc7_bands": int((dd2.formats() == gsbc.FMT_BC7).sum())}
+            del t3, sh3_d
             out3 = torch.empty((c3["dirs"], c3["n"], 3), dtype=torch.float32, device=dev)
             ctx.decode_eval(b3, dd2, dirs3, out=out3)
             torch.cuda.synchronize()
@@ -341,8 +374,8 @@ def main():
                        "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": de_bytes / de_s / HBM_PEAK,
                        "traffic": tr_de, "launch_ms": de_s * 1e3,
                        "workload": "3,145,728 primitives x 1,024 directions, 6 bits/texel",
-                       "plain_fill_gbps": round(fill_gbps, 1), "view": view_leg}
-            del out3, b3
+                       "plain_fill_gbps": round(fill_gbps, 1), "view": view_leg, "encode": large_enc}
+            del out3, b3, pos3_d
             torch.cuda.empty_cache()
         batch = None if args.no_batch else batch_leg(ctx, stream, dev, args.batch_scenes, max(3, args.steps))
         ctx.close()
