@@ -227,38 +227,47 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t *keys, uint64
 }
 
 // Exclusive prefix of each digit's column over the tiles; digit totals.
+// Sixteen tiles' counts are loaded before any is rewritten, so a thread keeps
+// sixteen loads in flight instead of one.
+constexpr int kScanBatch = 16;
 __global__ __launch_bounds__(256) void k_radix_colscan(uint32_t *hist, uint32_t ntiles, uint32_t *total)
 {
     const int d = blockIdx.x * blockDim.x + threadIdx.x;
     if (d >= kDigits) return;
     uint32_t run = 0;
-    for (uint32_t t = 0; t < ntiles; t++) {
-        uint32_t c = hist[(uint64_t)t * kDigits + d];
-        hist[(uint64_t)t * kDigits + d] = run;
-        run += c;
+    for (uint32_t t0 = 0; t0 < ntiles; t0 += kScanBatch) {
+        uint32_t c[kScanBatch];
+#pragma unroll
+        for (int j = 0; j < kScanBatch; j++)
+            c[j] = t0 + j < ntiles ? hist[(uint64_t)(t0 + j) * kDigits + d] : 0u;
+#pragma unroll
+        for (int j = 0; j < kScanBatch; j++) {
+            if (t0 + j < ntiles) hist[(uint64_t)(t0 + j) * kDigits + d] = run;
+            run += c[j];
+        }
     }
     total[d] = run;
 }
 
-// Exclusive scan of the digit totals (one workgroup of 1024 threads).
+// Exclusive scan of the digit totals (one workgroup of 1024 threads, two
+// digits each): pair sums, an inclusive scan over the 1024 pairs in LDS
+// (ten doubling steps), then each pair's exclusive offsets.
 __global__ __launch_bounds__(1024) void k_radix_digitscan(uint32_t *total)
 {
-    __shared__ uint32_t s[kDigits];
+    __shared__ uint32_t s[1024];
     const int t = threadIdx.x;
-    s[2 * t] = total[2 * t];
-    s[2 * t + 1] = total[2 * t + 1];
+    const uint32_t a = total[2 * t], b = total[2 * t + 1];
+    s[t] = a + b;
     __syncthreads();
-    if (t == 0) {
-        uint32_t run = 0;
-        for (int d = 0; d < kDigits; d++) {
-            uint32_t c = s[d];
-            s[d] = run;
-            run += c;
-        }
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t x = t >= off ? s[t - off] : 0u;
+        __syncthreads();
+        s[t] += x;
+        __syncthreads();
     }
-    __syncthreads();
-    total[2 * t] = s[2 * t];
-    total[2 * t + 1] = s[2 * t + 1];
+    const uint32_t before = s[t] - (a + b);
+    total[2 * t] = before;
+    total[2 * t + 1] = before + a;
 }
 
 // Stable scatter: each wave walks its tile in order; lanes with equal digits
