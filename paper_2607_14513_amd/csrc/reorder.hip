@@ -21,8 +21,9 @@ namespace {
 
 constexpr int kDigitBits = 11;
 constexpr int kDigits = 1 << kDigitBits;
-constexpr int kWaveItems = 64;                 // keys per lane per tile
+constexpr int kWaveItems = 16;                 // keys per lane per tile
 constexpr int kTile = 64 * kWaveItems;         // keys per wave tile
+constexpr int kChunkTiles = 16;                // tiles per chunk of the column scan
 constexpr int kRangeBlock = 384;               // multiple of 12 and 3
 
 __device__ __forceinline__ uint32_t ord_of(float f)
@@ -226,23 +227,39 @@ __global__ __launch_bounds__(256) void k_radix_hist(const uint64_t *keys, uint64
         for (int d = lane; d < kDigits; d += 64) hist[(uint64_t)tile * kDigits + d] = cnt[w][d];
 }
 
-// Exclusive prefix of each digit's column over the tiles; digit totals.
-// Sixteen tiles' counts are loaded before any is rewritten, so a thread keeps
-// sixteen loads in flight instead of one.
-constexpr int kScanBatch = 16;
-__global__ __launch_bounds__(256) void k_radix_colscan(uint32_t *hist, uint32_t ntiles, uint32_t *total)
+// Column scan in two levels (grid: chunks x digit blocks).  Chunk level:
+// thread (digit d, chunk c) turns its kChunkTiles counts into exclusive
+// prefixes within the chunk (all loads issued before any store) and leaves
+// the chunk total in ctot[c][d].
+__global__ __launch_bounds__(256) void k_radix_chunkscan(uint32_t *hist, uint32_t ntiles, uint32_t *ctot)
+{
+    const int d = blockIdx.y * blockDim.x + threadIdx.x;
+    const uint32_t t0 = blockIdx.x * kChunkTiles;
+    uint32_t c[kChunkTiles];
+#pragma unroll
+    for (int j = 0; j < kChunkTiles; j++) c[j] = t0 + j < ntiles ? hist[(uint64_t)(t0 + j) * kDigits + d] : 0u;
+    uint32_t run = 0;
+#pragma unroll
+    for (int j = 0; j < kChunkTiles; j++) {
+        if (t0 + j < ntiles) hist[(uint64_t)(t0 + j) * kDigits + d] = run;
+        run += c[j];
+    }
+    ctot[(uint64_t)blockIdx.x * kDigits + d] = run;
+}
+
+// Chunk totals level: per digit, exclusive prefixes over the chunks (in
+// place, sixteen loads in flight) and the digit total.
+__global__ __launch_bounds__(256) void k_radix_chunkprefix(uint32_t *ctot, uint32_t nchunks, uint32_t *total)
 {
     const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= kDigits) return;
     uint32_t run = 0;
-    for (uint32_t t0 = 0; t0 < ntiles; t0 += kScanBatch) {
-        uint32_t c[kScanBatch];
+    for (uint32_t c0 = 0; c0 < nchunks; c0 += 16) {
+        uint32_t c[16];
 #pragma unroll
-        for (int j = 0; j < kScanBatch; j++)
-            c[j] = t0 + j < ntiles ? hist[(uint64_t)(t0 + j) * kDigits + d] : 0u;
+        for (int j = 0; j < 16; j++) c[j] = c0 + j < nchunks ? ctot[(uint64_t)(c0 + j) * kDigits + d] : 0u;
 #pragma unroll
-        for (int j = 0; j < kScanBatch; j++) {
-            if (t0 + j < ntiles) hist[(uint64_t)(t0 + j) * kDigits + d] = run;
+        for (int j = 0; j < 16; j++) {
+            if (c0 + j < nchunks) ctot[(uint64_t)(c0 + j) * kDigits + d] = run;
             run += c[j];
         }
     }
@@ -274,15 +291,17 @@ __global__ __launch_bounds__(1024) void k_radix_digitscan(uint32_t *total)
 // are ranked by lane id through ballots over the digit bits.
 __global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *keys_in, const uint32_t *vals_in,
                                                        uint64_t n, int shift, uint32_t ntiles,
-                                                       const uint32_t *hist, const uint32_t *digit_base,
+                                                       const uint32_t *hist, const uint32_t *chunk_base,
+                                                       const uint32_t *digit_base,
                                                        uint64_t *keys_out, uint32_t *vals_out)
 {
     __shared__ uint32_t ctr[4][kDigits];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t tile = blockIdx.x * 4 + w;
     if (tile >= ntiles) return;   // whole wave leaves; no block barrier below
+    const uint32_t *cb = chunk_base + (uint64_t)(tile / kChunkTiles) * kDigits;
     for (int d = lane; d < kDigits; d += 64)
-        ctr[w][d] = hist[(uint64_t)tile * kDigits + d] + digit_base[d];
+        ctr[w][d] = hist[(uint64_t)tile * kDigits + d] + cb[d] + digit_base[d];
     __builtin_amdgcn_wave_barrier();
     const uint64_t base = (uint64_t)tile * kTile;
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -481,7 +500,7 @@ __global__ __launch_bounds__(256) void k_pack_degrees(const float *sh, const flo
 }
 
 struct Layout {
-    size_t acc, keys_a, keys_b, vals_a, vals_b, hist, total, cov_state, cov_part, bytes;
+    size_t acc, keys_a, keys_b, vals_a, vals_b, hist, ctot, total, cov_state, cov_part, bytes;
 };
 
 Layout layout(uint64_t n)
@@ -496,6 +515,7 @@ Layout layout(uint64_t n)
     L.vals_a = o; o += al(n * 4);
     L.vals_b = o; o += al(n * 4);
     L.hist = o; o += al(ntiles * kDigits * 4);
+    L.ctot = o; o += al((ntiles + kChunkTiles - 1) / kChunkTiles * kDigits * 4);
     L.total = o; o += al(kDigits * 4);
     L.cov_state = o; o += al(32 * 4);
     L.cov_part = o; o += al((size_t)kCovWG * 4096 * 4);
@@ -550,8 +570,10 @@ void enqueue_sort(uint64_t n, int key_bits, const Layout &L, char *s, uint32_t *
     uint64_t *ka = reinterpret_cast<uint64_t *>(s + L.keys_a), *kb = reinterpret_cast<uint64_t *>(s + L.keys_b);
     uint32_t *va = reinterpret_cast<uint32_t *>(s + L.vals_a), *vb = reinterpret_cast<uint32_t *>(s + L.vals_b);
     uint32_t *hist = reinterpret_cast<uint32_t *>(s + L.hist), *total = reinterpret_cast<uint32_t *>(s + L.total);
+    uint32_t *ctot = reinterpret_cast<uint32_t *>(s + L.ctot);
     const int passes = (key_bits + kDigitBits - 1) / kDigitBits;
     const uint32_t ntiles = (uint32_t)((n + kTile - 1) / kTile);
+    const uint32_t nchunks = (ntiles + kChunkTiles - 1) / kChunkTiles;
     const uint32_t nblocks = (ntiles + 3) / 4;
     uint64_t *kin = ka, *kout = kb;
     uint32_t *vin = va, *vout = vb;
@@ -559,10 +581,12 @@ void enqueue_sort(uint64_t n, int key_bits, const Layout &L, char *s, uint32_t *
         int shift = p * kDigitBits;
         uint32_t *vdst = (p == passes - 1) ? perm : vout;
         GSBC_LAUNCH("radix_hist", k_radix_hist, dim3(nblocks), dim3(256), 0, st, kin, n, shift, ntiles, hist);
-        GSBC_LAUNCH("radix_colscan", k_radix_colscan, dim3(kDigits / 256), dim3(256), 0, st, hist, ntiles, total);
+        GSBC_LAUNCH("radix_colscan", k_radix_chunkscan, dim3(nchunks, kDigits / 256), dim3(256), 0, st, hist,
+                           ntiles, ctot);
+        GSBC_LAUNCH("radix_colscan", k_radix_chunkprefix, dim3(kDigits / 256), dim3(256), 0, st, ctot, nchunks, total);
         GSBC_LAUNCH("radix_digitscan", k_radix_digitscan, dim3(1), dim3(1024), 0, st, total);
         GSBC_LAUNCH("radix_scatter", k_radix_scatter, dim3(nblocks), dim3(256), 0, st, kin, vin, n, shift,
-                           ntiles, hist, total, kout, vdst);
+                           ntiles, hist, ctot, total, kout, vdst);
         std::swap(kin, kout);
         vin = vdst;
         vout = (vdst == va) ? vb : va;
