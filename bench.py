@@ -14,6 +14,12 @@ step time, in Mblocks/s.  Also reported:
                       algorithmic integer ops per launch / its average launch
                       time (HIP events the library records on its stream),
                       against the VALU peak;
+  valu_issue          the BC7 search and BC1 encoders' VALU instructions per
+                      launch (SQ_INSTS_VALU of the committed rocprofv3 pass)
+                      over the live launch time, against one wave64
+                      instruction per SIMD every 4 cycles at 2.4 GHz (1.0 =
+                      every issue slot used; the 4-cycle model is not exact
+                      for every instruction, so it can read slightly above 1);
   roofline_decode_eval  decode + SH evaluation of 3,145,728 primitives at
                       1,024 directions: bytes written+read per launch / time,
                       against 8 TB/s;
@@ -32,6 +38,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 VALU_PEAK = 256 * 4 * 16 * 2.4e9        # integer lane-ops/s: 256 CUs x 4 SIMD16 x 2.4 GHz
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4    # wave64 VALU instructions/s (4 cycles each per SIMD)
 HBM_PEAK = 8.0e12                        # bytes/s
 # VALU issue slots (lane-instructions) that one exact texel x palette-entry
 # distance comparison needs at the least on gfx950: one v_dot2 for two
@@ -54,19 +61,24 @@ ALGO_OPS["bc7_search_items"] = ALGO_OPS["bc7_search_all"] = sum(ALGO_OPS.values(
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def traffic_bytes(name):
-    """HBM bytes per launch of kernel `name` from the committed rocprofv3
-    counter summary (FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy), or
-    None when there is none or the kernel's source changed since."""
+def profiled(name, field="bytes"):
+    """A per-launch figure of kernel `name` from the committed rocprofv3
+    counter summary: "bytes" = HBM bytes (FETCH_SIZE and WRITE_SIZE scaled by
+    a 1 GiB copy), "valu_insts" = SQ_INSTS_VALU.  None when there is none or
+    the kernel's source changed since."""
     if not os.path.exists(TRAFFIC):
         return None
     ent = json.load(open(TRAFFIC)).get(name)
-    if not ent:
+    if not ent or field not in ent:
         return None
     src = os.path.join(ROOT, ent["source"])
     if not os.path.exists(src) or hashlib.sha1(open(src, "rb").read()).hexdigest() != ent["source_sha1"]:
         return None
-    return ent["bytes"]
+    return ent[field]
+
+
+def traffic_bytes(name):
+    return profiled(name, "bytes")
 
 
 def parse():
@@ -176,6 +188,16 @@ def main():
                 "peak": VALU_PEAK / 1e12, "unit": "Tops/s",
                 "frac": work * units / dom_s / VALU_PEAK if work else None, "traffic": traffic,
                 "launch_ms": round(dom_s * 1e3, 4), "algorithmic_ops_per_block": work, "blocks_per_launch": units}
+
+        # ---- counter-measured VALU issue utilisation of the encoders: the
+        # committed SQ_INSTS_VALU count of a launch over the live launch time
+        valu = {}
+        for name in ("bc7_search_items", "bc1_encode"):
+            insts = profiled(name, "valu_insts")
+            if name in kern and insts:
+                t = per_step[name] / (kern[name][0] / nprof) * 1e-3
+                valu[name] = {"valu_insts_per_launch": insts, "launch_ms": round(t * 1e3, 4),
+                              "issue_busy": round(insts / t / VALU_ISSUE_PEAK, 4)}
 
         # ---- whole-format encode rates (every band in one format)
         d7 = d2.copy()
@@ -401,6 +423,7 @@ def main():
         "degree_classes": degrees,
         "kernels_ms_per_step": {k: round(v, 4) for k, v in sorted(per_step.items(), key=lambda kv: -kv[1])},
         "roofline": roof,
+        "valu_issue": valu or None,
         "roofline_decode_eval": roof_de,
         "batch": batch,
         "serving": served,
