@@ -120,21 +120,56 @@ static __constant__ uint8_t kAnchor3c[64] = {
     15, 3, 15, 15, 15, 15, 15, 15, 15, 15, 15, 15, 3, 15, 15, 8,
 };
 
-// Subset of texel i in partition p of an ns-subset mode.
-__device__ inline int bc7_subset(int ns, int p, int i)
+// Partition-map and anchor access for the texel decoder.  The default reads
+// the constant-memory tables above; a kernel can hand it a copy of them in
+// LDS (Bc7PackedLut) so that its per-lane lookups wait on LDS instead of on
+// the vector-memory counter its loads and stores share.
+struct Bc7ConstLut {
+    __device__ uint32_t part2(int p) const { return kPart2[p]; }
+    __device__ uint32_t part3(int p) const { return kPart3[p]; }
+    __device__ int anchor2(int p) const { return kAnchor2[p]; }
+    __device__ int anchor3b(int p) const { return kAnchor3b[p]; }
+    __device__ int anchor3c(int p) const { return kAnchor3c[p]; }
+};
+
+// The same tables as 128 words: word p (p < 64) = 2-subset mask | 2-subset
+// anchor << 16 | 3-subset anchors << 20 and << 24; word 64 + p = 3-subset map.
+constexpr int kBc7LutWords = 128;
+__device__ inline uint32_t bc7_lut_word(int e)
 {
-    if (ns == 1) return 0;
-    if (ns == 2) return (kPart2[p] >> i) & 1;
-    return (kPart3[p] >> (2 * i)) & 3;
+    if (e >= 64) return kPart3[e - 64];
+    return (uint32_t)kPart2[e] | (uint32_t)kAnchor2[e] << 16 | (uint32_t)kAnchor3b[e] << 20 |
+           (uint32_t)kAnchor3c[e] << 24;
 }
 
+struct Bc7PackedLut {
+    const uint32_t *w;   // kBc7LutWords words of bc7_lut_word
+    __device__ uint32_t part2(int p) const { return w[p] & 0xFFFFu; }
+    __device__ uint32_t part3(int p) const { return w[64 + p]; }
+    __device__ int anchor2(int p) const { return (int)(w[p] >> 16) & 15; }
+    __device__ int anchor3b(int p) const { return (int)(w[p] >> 20) & 15; }
+    __device__ int anchor3c(int p) const { return (int)(w[p] >> 24) & 15; }
+};
+
+// Subset of texel i in partition p of an ns-subset mode.
+template <class Lut>
+__device__ inline int bc7_subset(int ns, int p, int i, const Lut &lut)
+{
+    if (ns == 1) return 0;
+    if (ns == 2) return (lut.part2(p) >> i) & 1;
+    return (lut.part3(p) >> (2 * i)) & 3;
+}
+__device__ inline int bc7_subset(int ns, int p, int i) { return bc7_subset(ns, p, i, Bc7ConstLut{}); }
+
 // Anchor texel of subset s.
-__device__ inline int bc7_anchor(int ns, int p, int s)
+template <class Lut>
+__device__ inline int bc7_anchor(int ns, int p, int s, const Lut &lut)
 {
     if (s == 0) return 0;
-    if (ns == 2) return kAnchor2[p];
-    return s == 1 ? kAnchor3b[p] : kAnchor3c[p];
+    if (ns == 2) return lut.anchor2(p);
+    return s == 1 ? lut.anchor3b(p) : lut.anchor3c(p);
 }
+__device__ inline int bc7_anchor(int ns, int p, int s) { return bc7_anchor(ns, p, s, Bc7ConstLut{}); }
 
 // ------------------------------------------------------------- bit access
 // A 128-bit block held as two little-endian 64-bit halves.
@@ -187,7 +222,8 @@ __device__ inline uint32_t bc1_texel(uint32_t w0, uint32_t w1, int i)
 
 // ------------------------------------------------------------- BC7 decode
 // Texel i of a BC7 block, RGBA packed in a uint32 (R in the low byte).
-__device__ inline uint32_t bc7_texel(const Blk128 &b, int i)
+template <class Lut>
+__device__ inline uint32_t bc7_texel(const Blk128 &b, int i, const Lut &lut)
 {
     uint32_t b0 = (uint32_t)b.lo & 0xFF;
     if (b0 == 0) return 0;  // reserved mode: all zero
@@ -201,7 +237,7 @@ __device__ inline uint32_t bc7_texel(const Blk128 &b, int i)
     int sel = md.selbits ? (int)get_field(b, pos, 1) : 0;
     pos += md.selbits;
     int ns = md.ns, ne = 2 * ns;
-    int s = bc7_subset(ns, part, i);
+    int s = bc7_subset(ns, part, i, lut);
     int e0[4], e1[4];
     int cpos = pos;
     pos += 3 * ne * md.cb;
@@ -229,8 +265,8 @@ __device__ inline uint32_t bc7_texel(const Blk128 &b, int i)
         e0[3] = e1[3] = 255;
     }
     // primary index: one bit less for each anchor texel before i and for i itself
-    int a1 = ns >= 2 ? bc7_anchor(ns, part, 1) : 99;
-    int a2 = ns == 3 ? bc7_anchor(ns, part, 2) : 99;
+    int a1 = ns >= 2 ? bc7_anchor(ns, part, 1, lut) : 99;
+    int a2 = ns == 3 ? bc7_anchor(ns, part, 2, lut) : 99;
     int before = (i > 0) + (a1 < i) + (a2 < i);
     int anchored = (i == 0) || (i == a1) || (i == a2);
     int i1 = (int)get_field(b, pos + i * md.ib - before, md.ib - anchored);
@@ -249,5 +285,6 @@ __device__ inline uint32_t bc7_texel(const Blk128 &b, int i)
     if (rot) { int t = px[3]; px[3] = px[rot - 1]; px[rot - 1] = t; }
     return (uint32_t)px[0] | ((uint32_t)px[1] << 8) | ((uint32_t)px[2] << 16) | ((uint32_t)px[3] << 24);
 }
+__device__ inline uint32_t bc7_texel(const Blk128 &b, int i) { return bc7_texel(b, i, Bc7ConstLut{}); }
 
 }  // namespace gsbc

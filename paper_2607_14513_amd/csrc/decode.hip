@@ -39,6 +39,8 @@ __device__ __forceinline__ uint32_t band_texel(const uint8_t *blocks, const Band
 // 0: stream k, block s/16, zigzag texel of s%16 (only the n_streams kept
 // bands of a lower-degree scene; px[k] = 0 past them); 1: stream 0, block s,
 // texel k; 2: stream k/4, block s/4, texel 4 (s%4) + k%4.
+// One load per block, each decoded as it arrives (the fewest memory
+// instructions, for gathers that issue little else):
 template <int ARR>
 __device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16])
 {
@@ -47,6 +49,34 @@ __device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const Ban
         if (ARR == 1) px[k] = band_texel(blocks, b, 0, s, k);
         else if (ARR == 2) px[k] = band_texel(blocks, b, k >> 2, s >> 2, 4 * (int)(s & 3u) + (k & 3));
         else px[k] = (uint32_t)k < b.n_streams ? band_texel(blocks, b, k, s >> 4, (int)zigzag_texel(s & 15u)) : 0u;
+    }
+}
+
+// or every block loaded before any is decoded, as two 8-byte halves (an
+// 8-byte BC1 block loads its one half twice), so that the loads share one
+// wait, and the BC7 tables read through `lut`:
+template <int ARR, class Lut>
+__device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16],
+                                                const Lut &lut)
+{
+    uint2 lo[16], hi[16];
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        // stream of band k (a dropped band reads stream 0's block and ignores it)
+        const int sk = ARR == 1 ? 0 : ARR == 2 ? (k >> 2) : ((uint32_t)k < b.n_streams ? k : 0);
+        const uint64_t blk = ARR == 1 ? s : ARR == 2 ? (s >> 2) : (s >> 4);
+        const bool wide = b.format[sk] != 1;
+        const uint8_t *q = blocks + b.offset[sk] + blk * (wide ? 16 : 8);
+        lo[k] = *reinterpret_cast<const uint2 *>(q);
+        hi[k] = *reinterpret_cast<const uint2 *>(q + (wide ? 8 : 0));
+    }
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        const int sk = ARR == 1 ? 0 : ARR == 2 ? (k >> 2) : k;
+        const int texel = ARR == 1 ? k : ARR == 2 ? 4 * (int)(s & 3u) + (k & 3) : (int)zigzag_texel(s & 15u);
+        if (ARR == 0 && (uint32_t)k >= b.n_streams) px[k] = 0u;
+        else if (b.format[sk] == 1) px[k] = bc1_texel(lo[k].x, lo[k].y, texel);
+        else px[k] = bc7_texel(Blk128{lo[k].x | (uint64_t)lo[k].y << 32, hi[k].x | (uint64_t)hi[k].y << 32}, texel, lut);
     }
 }
 
@@ -59,6 +89,15 @@ __device__ __forceinline__ void slot_texels(const uint8_t *blocks, const BandArg
     if (b.arrangement == 1) slot_texels_arr<1>(blocks, b, s, px);
     else if (b.arrangement == 2) slot_texels_arr<2>(blocks, b, s, px);
     else slot_texels_arr<0>(blocks, b, s, px);
+}
+
+template <class Lut>
+__device__ __forceinline__ void slot_texels(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16],
+                                            const Lut &lut)
+{
+    if (b.arrangement == 1) slot_texels_arr<1>(blocks, b, s, px, lut);
+    else if (b.arrangement == 2) slot_texels_arr<2>(blocks, b, s, px, lut);
+    else slot_texels_arr<0>(blocks, b, s, px, lut);
 }
 
 __global__ __launch_bounds__(256) void k_decode(const uint8_t *blocks, BandArgs b, uint64_t nblk,
@@ -120,26 +159,31 @@ constexpr int kDirChunk = 256;              // directions per workgroup (grid.y)
 constexpr int kBasStride = 17;              // padded basis row in LDS
 constexpr int kStageStride = 196;           // padded staging row (192 columns per wave)
 constexpr int kPhase2Floats = kDirChunk * kBasStride + 4 * 16 * kStageStride;
-constexpr int kLdsFloats = kPhase2Floats > 16 * kCols ? kPhase2Floats : 16 * kCols;
+constexpr int kLdsFloats = kPhase2Floats > 16 * kCols + kBc7LutWords ? kPhase2Floats : 16 * kCols + kBc7LutWords;
 
 __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *blocks, BandArgs b,
                                                             const uint32_t *prim_idx, uint64_t m,
                                                             uint64_t n_prims, const float *basis,
                                                             uint32_t n_dirs, float *out)
 {
-    __shared__ float lds[kLdsFloats];
+    __shared__ __align__(16) float lds[kLdsFloats];
     float(*Hm)[kCols] = reinterpret_cast<float(*)[kCols]>(lds);
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const uint64_t j0 = (uint64_t)blockIdx.x * kSlots;
     // ---- decode: lane t -> slot j0 + t
     {
         const uint64_t j = j0 + t;
+        const uint32_t s = j < m ? (prim_idx ? prim_idx[j] : (uint32_t)j) : 0u;
+        // BC7 partition tables for the decode, in the LDS past Hm (their
+        // loads issued with the slot's index load)
+        uint32_t *lutw = reinterpret_cast<uint32_t *>(lds + 16 * kCols);
+        if (t < kBc7LutWords) lutw[t] = bc7_lut_word(t);
+        __syncthreads();
         float h[16][3];
         if (j < m) {
-            const uint32_t s = prim_idx ? prim_idx[j] : (uint32_t)j;
             if (s < n_prims) {
                 uint32_t px[16];
-                slot_texels(blocks, b, s, px);
+                slot_texels(blocks, b, s, px, Bc7PackedLut{lutw});
                 const uint32_t nb = kept_bands(b);
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
@@ -175,6 +219,8 @@ __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *block
     }
     const uint64_t cols_valid = (m - j0 < (uint64_t)kSlots ? m - j0 : (uint64_t)kSlots) * 3;
     const uint64_t row_stride = 3 * m;
+    // rows start 16-byte aligned (output base aligned, row length a multiple of 4 floats)
+    const bool rows16 = (row_stride & 3) == 0 && (reinterpret_cast<uintptr_t>(out) & 15) == 0;
     const uint32_t wcol0 = 16 * 12 * wave;                  // this wave's first column
     float *obase = out + 3 * j0 + wcol0;
     // Hm is dead once every wave holds its B operands.  It then holds this
@@ -211,7 +257,23 @@ __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *block
 #pragma unroll
         for (int h = 0; h < 3; h++) cok[h] = wcol0 + 64 * h + lane < cols_valid;
         float *o = obase + v0 * row_stride + lane;
-        if (v0 + 16 <= v_end) {
+        if (v0 + 16 <= v_end && wcol0 + 192 <= cols_valid && rows16) {
+            // whole rows, every column valid, 16-byte aligned: lanes 0..47
+            // store 4 consecutive columns each, one instruction per row
+            if (lane < 48) {
+                floatx4 *o4 = reinterpret_cast<floatx4 *>(obase + v0 * row_stride) + lane;
+#pragma unroll
+                for (int half = 0; half < 2; half++) {
+                    floatx4 x[8];
+#pragma unroll
+                    for (int rr = 0; rr < 8; rr++)
+                        x[rr] = *reinterpret_cast<const floatx4 *>(&stage[8 * half + rr][4 * lane]);
+#pragma unroll
+                    for (int rr = 0; rr < 8; rr++)
+                        __builtin_nontemporal_store(x[rr], o4 + (8 * half + rr) * (row_stride / 4));
+                }
+            }
+        } else if (v0 + 16 <= v_end) {
 #pragma unroll
             for (int half = 0; half < 2; half++) {
                 float x[8][3];

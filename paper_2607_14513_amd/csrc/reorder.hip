@@ -78,8 +78,7 @@ __global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4
     const int bandA = (4 * j) / 3, bandB = (4 * j + 3) / 3;
     float minA = INFINITY, maxA = -INFINITY, minB = INFINITY, maxB = -INFINITY;
     const uint64_t nq = n * 12;
-    for (uint64_t q = t; q < nq; q += T) {
-        float4 v = sh4[q];
+    auto take = [&](float4 v, uint64_t q) {
         float f[4] = {v.x, v.y, v.z, v.w};
         if (opacity) {   // H~ = mu H (FP32 products)
             const float mu = opacity[q / 12];
@@ -91,7 +90,17 @@ __global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4
             if ((4 * j + c) / 3 == bandA) { minA = fminf(minA, f[c]); maxA = fmaxf(maxA, f[c]); }
             else { minB = fminf(minB, f[c]); maxB = fmaxf(maxB, f[c]); }
         }
+    };
+    // four loads in flight per lane, then the remainder one at a time
+    uint64_t q = t;
+    for (; q + 3 * T < nq; q += 4 * T) {
+        const float4 v0 = sh4[q], v1 = sh4[q + T], v2 = sh4[q + 2 * T], v3 = sh4[q + 3 * T];
+        take(v0, q);
+        take(v1, q + T);
+        take(v2, q + 2 * T);
+        take(v3, q + 3 * T);
     }
+    for (; q < nq; q += T) take(sh4[q], q);
     const int axis = (int)(t % 3);
     float pmin = INFINITY, pmax = -INFINITY;
     for (uint64_t f = t; f < n * 3; f += T) {

@@ -431,6 +431,49 @@ def test_decode_eval_all_slots(G, n, V):
     _check_colours(out, ref, scale)
 
 
+@pytest.mark.parametrize("fmt", [[7] * 16, [7, 1] * 8])
+def test_decode_eval_random_blocks(G, fmt):
+    """decode_eval and the view decode over random block bits: every BC7
+    mode and partition (and reserved-mode blocks) passes through the texel
+    decode that feeds the SH sum, against the FP64 oracle on the same bits."""
+    gsbc, ctx = G
+    n = 16 * 1001 - 5
+    fmt = np.array(fmt, np.uint8)
+    d = _desc_for(gsbc, n, fmt)
+    rng = np.random.default_rng(70 + int(fmt[1]))
+    payload = rng.integers(0, 256, d.payload_bytes, dtype=np.uint8)
+    payload[0:16 * 50:16] = 0                       # band 0 (BC7): reserved-mode blocks
+    off = d.offsets()
+    vmin, vmax = np.full(16, -1.0, np.float32), np.full(16, 1.0, np.float32)
+    dirs = synth.make_dirs(7, seed=70)
+    slots = np.arange(n, dtype=np.uint32)
+    say("decode_eval random blocks", fmt.tolist())
+    out = host(ctx.decode_eval(dev(payload), d, dev(dirs)))
+    ref, scale = O.decode_eval(payload, off, fmt, vmin, vmax, dirs, slots)
+    _check_colours(out, ref, scale)
+    pos = rng.uniform(-1.0, 1.0, (n, 3)).astype(np.float32)
+    perm = rng.permutation(n).astype(np.uint32)
+    f = np.array([2.0, -1.5, 0.25], np.float32)
+    out = host(ctx.decode_eval_view(dev(payload), d, dev(pos), dev(perm.view(np.int32)), f))
+    ref, scale = O.decode_eval_view(payload, off, fmt, vmin, vmax, pos, perm, f, slots)
+    _check_colours(out, ref, scale)
+
+
+def test_decode_eval_unaligned_output(G):
+    """An output buffer that is not 16-byte aligned is written column by
+    column instead of 16 bytes per lane: the same values as an aligned one."""
+    gsbc, ctx = G
+    n, V = 4096, 20
+    d = _desc_for(gsbc, n, np.array([7, 1] * 8, np.uint8))
+    rng = np.random.default_rng(71)
+    payload = dev(rng.integers(0, 256, d.payload_bytes, dtype=np.uint8))
+    dirs = dev(synth.make_dirs(V, seed=71))
+    a = host(ctx.decode_eval(payload, d, dirs))
+    buf = torch.empty(V * n * 3 + 1, dtype=torch.float32, device="cuda")
+    b = host(ctx.decode_eval(payload, d, dirs, out=buf[1:].view(V, n, 3)))
+    assert np.array_equal(a, b)
+
+
 def test_decode_eval_prim_subset_and_bounds(G):
     gsbc, ctx = G
     n = 5000
