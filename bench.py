@@ -300,8 +300,33 @@ def main():
                 e1.record(stream)
                 torch.cuda.synchronize()
                 t_full.append(e0.elapsed_time(e1))
+            # the degree-1 class in per-band streams (Fig. SetupD) and in Fig.
+            # SetupC (four primitives' bands 0..3 per block): PSNR of its
+            # decoded texels and its bytes per primitive
+            def class1_row(label, tex_c, d_c, fmts):
+                d_c = d_c.copy()
+                for k, f in enumerate(fmts):
+                    d_c.format[k] = f
+                b, d3, _ = ctx.encode(tex_c, d_c, fmt=gsbc.FMT_BANDS, blocks=blocks)
+                dec = ctx.decode(b, d3)
+                diff = dec[..., :3].to(torch.int32) - tex_c[..., :3].to(torch.int32)
+                mse = float((diff * diff).sum(dtype=torch.float64).item()) / (d3.n_pad * 12)
+                return {"layout": label, "psnr_db": round(float(10 * np.log10(255.0 ** 2 / mse)), 2),
+                        "bytes_per_primitive": round(d3.payload_bytes / counts[1], 3)}
+
+            deg1 = None
+            if counts[1]:
+                _, _, texq, descq = ctx.reorder_degrees(posg_d, shg_d,
+                                                        params=gsbc.default_params(arrangement=gsbc.ARR_QUAD))
+                deg1 = [class1_row("SetupD: 4 BC1", texg[1], descg[1], [1] * 4),
+                        class1_row("SetupC: BC1", texq[1], descq[1], [1]),
+                        class1_row("SetupD: BC7 + 3 BC1", texg[1], descg[1], [7, 1, 1, 1]),
+                        class1_row("SetupD: 4 BC7", texg[1], descg[1], [7] * 4),
+                        class1_row("SetupC: BC7", texq[1], descq[1], [7])]
+                del texq
             degrees = {"workload": f"{n:,} primitives, SH degree 0..3 drawn with probabilities {list(mix)}, "
                                    "band 0 BC7 + the other kept bands BC1, classes in one batch",
+                       "degree1_layouts": deg1,
                        "class_counts": counts, "reorder_ms": round(float(np.median(t_re)), 3),
                        "encode_classes_ms": round(float(np.median(t_cls)), 3),
                        "encode_all_bands_ms": round(float(np.median(t_full)), 3),

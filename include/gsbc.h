@@ -68,7 +68,9 @@ enum { GSBC_FMT_AUTO = 0, GSBC_FMT_BC1 = 1, GSBC_FMT_BANDS = 2, GSBC_FMT_BC7 = 7
  *       texel k.
  *   GSBC_ARR_QUAD (Fig. SetupB): S = 4; stream g holds bands 4g..4g+3,
  *       block s/4, texel 4*(s%4) + k%4 (slot on the row, band on the
- *       column). */
+ *       column).  With S = 1 it is Fig. SetupC: bands 0..3 of four
+ *       primitives in one block (the degree-1 class of
+ *       gsbc_reorder_degrees), bands 4..15 dropped. */
 enum { GSBC_ARR_BANDS = 0, GSBC_ARR_PRIM = 1, GSBC_ARR_QUAD = 2 };
 
 typedef struct gsbc_ctx gsbc_ctx;
@@ -96,11 +98,12 @@ typedef struct {
     float vmin[16], vmax[16];    /* per-band quantiser range: q = rint((x - vmin) * 255/(vmax - vmin)) */
     uint64_t n_prims;            /* N */
     uint64_t n_pad;              /* N rounded up to a multiple of 16 */
-    uint64_t blocks_per_stream;  /* n_pad / 16 (BANDS), n_pad (PRIM), n_pad / 4 (QUAD) */
+    uint64_t blocks_per_stream;  /* n_pad / 16 (BANDS), n_pad (PRIM), n_pad / 4 (QUAD, either S) */
     uint64_t payload_bytes;      /* bytes of the concatenated streams */
     uint32_t arrangement;        /* GSBC_ARR_* of the textures */
-    uint32_t n_streams;          /* 16, 1 or 4 (BANDS, PRIM, QUAD); 1, 4 or 9 for a degree class
-                                    of gsbc_reorder_degrees (bands past n_streams are zero) */
+    uint32_t n_streams;          /* 16, 1 or 4 (BANDS, PRIM, QUAD); 1, 4 or 9 (BANDS) or 1
+                                    (QUAD) for a degree class of gsbc_reorder_degrees: the bands
+                                    past the streams' (n_streams, or 4 n_streams) are zero */
 } gsbc_stream_desc;
 
 /* ---------------------------------------------------------------- context */
@@ -161,14 +164,15 @@ GSBC_API gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *
 
 /* Variable number of bands (Sec. IV-B: primitives whose higher-order SH are
  * zero, or small enough to count as zero, go to bitstreams with fewer
- * bands; Fig. SetupD in its variable form).  Each primitive's degree class
+ * bands; Fig. SetupD in its variable form, and Fig. SetupC for degree 1).
+ * Each primitive's degree class
  * L is the largest SH degree l in 1..3 with a coefficient of a degree-l band
  * (bands l^2..l^2+2l) above tau in magnitude, else 0; the primitive keeps
  * its (L+1)^2 lowest bands and the others decode as exactly zero.  The sort
  * key is (L, Morton cell, colour), so class L is a contiguous range of perm
  * in increasing L, each ordered as gsbc_reorder orders a scene.  Every
- * class is an independent scene in the band arrangement with (L+1)^2
- * streams, to be coded with gsbc_encode or gsbc_encode_batch (per-band or
+ * class is an independent scene with its (L+1)^2 bands in (L+1)^2 band
+ * streams (or, for degree 1, the one stream of Fig. SetupC), to be coded with gsbc_encode or gsbc_encode_batch (per-band or
  * whole formats; the rate controller needs all 16 bands) and decoded with
  * class-local slot ids.  The quantiser range covers all coefficients,
  * dropped ones included.
@@ -176,18 +180,25 @@ GSBC_API gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *
  *   tau        >= 0, FP32 magnitudes at or below it count as zero (after
  *              opacity premultiplication)
  *   params     host, NULL for defaults (grid_bits and quantiser are used;
- *              order must be 0 and arrangement GSBC_ARR_BANDS)
+ *              order must be 0); arrangement GSBC_ARR_BANDS puts every
+ *              class in per-band streams (Fig. SetupD), GSBC_ARR_QUAD the
+ *              degree-1 class in one stream of blocks holding bands 0..3 of
+ *              four primitives each (Fig. SetupC: texel 4 (j%4) + k of
+ *              block j/4 for class slot j) and the others per band
  *   perm       device uint32[n] out: slot -> primitive; class L owns slots
  *              counts[0] + .. + counts[L-1] .. + counts[L] - 1
  *   textures   device, textures_capacity bytes, at least n_pad*64 + 1800
  *              (GSBC_E_BUFFER otherwise); out: class L's textures
  *              uint8[(L+1)^2][pad16(counts[L])/16][16][4] (the layout of
- *              gsbc_reorder) at byte offset tex_offset[L]
+ *              gsbc_reorder), or for Fig. SetupC
+ *              uint8[1][pad16(counts[1])/4][16][4], at byte offset
+ *              tex_offset[L]
  *   counts     host uint64[4] out: primitives per class
  *   tex_offset host uint64[4] out
  *   descs      host gsbc_stream_desc[4] out: class L's scene (n_prims =
- *              counts[L], n_streams = (L+1)^2, ranges); an empty class has
- *              n_prims 0 and is not a scene to code */
+ *              counts[L], arrangement and n_streams: GSBC_ARR_BANDS with
+ *              (L+1)^2, or GSBC_ARR_QUAD with 1 for Fig. SetupC; ranges);
+ *              an empty class has n_prims 0 and is not a scene to code */
 GSBC_API gsbc_status gsbc_reorder_degrees(gsbc_ctx *ctx, const float *pos, const float *sh, const float *opacity,
                                           uint64_t n, float tau, const gsbc_params *params, uint32_t *perm,
                                           uint8_t *textures, uint64_t textures_capacity, uint64_t counts[4],

@@ -198,7 +198,7 @@ def degrees(sh, tau=0.0):
     return out
 
 
-def reorder_degrees(pos, sh, tau=0.0, grid_bits=3, opacity=None, quantiser=0):
+def reorder_degrees(pos, sh, tau=0.0, grid_bits=3, opacity=None, quantiser=0, arrangement=ARR_BANDS):
     """Variable number of bands (Sec. IV-B): every primitive goes to the
     bitstreams of its degree class, with (L+1)^2 bands.  Key = degree above
     the spatial cell and colour fields, so the sort groups the classes (in
@@ -206,7 +206,10 @@ def reorder_degrees(pos, sh, tau=0.0, grid_bits=3, opacity=None, quantiser=0):
     range is taken over all coefficients, dropped ones included.  Returns
     (perm, counts[4], textures: list of 4 (uint8[(L+1)^2][nblk_L][16][4], or
     None for an empty class), vmin, vmax); class L owns slots
-    sum(counts[:L]) .. sum(counts[:L+1]) - 1 of perm."""
+    sum(counts[:L]) .. sum(counts[:L+1]) - 1 of perm.  arrangement ARR_QUAD
+    packs the degree-1 class as Fig. SetupC: its four bands of four
+    primitives per block, which is the first stream of Fig. SetupB's
+    packing (uint8[1][pad16(counts[1])/4][16][4])."""
     if opacity is not None:
         sh = premultiply(sh, opacity)
     vmin, vmax = band_range_coverage(sh) if quantiser == 1 else band_range(sh)
@@ -223,7 +226,10 @@ def reorder_degrees(pos, sh, tau=0.0, grid_bits=3, opacity=None, quantiser=0):
             tex.append(None)
             continue
         part = perm[start[L]:start[L + 1]]
-        tex.append(pack(q, part)[:(L + 1) ** 2])
+        if L == 1 and arrangement == ARR_QUAD:
+            tex.append(pack(q, part, ARR_QUAD)[:1])
+        else:
+            tex.append(pack(q, part)[:(L + 1) ** 2])
     return perm, counts, tex, vmin, vmax
 
 
@@ -361,9 +367,10 @@ def _streams16(fmt, off):
 
 
 def decode_eval(payload, off, fmt, vmin, vmax, dirs, slots, with_scale=True, arrangement=ARR_BANDS):
-    """FP64 decode_eval.  Returns out[V][M][3] (and scale[V][M][3]).  With the
-    band arrangement, fewer than 16 formats mean a scene of lower-degree
-    primitives: the missing bands are zero."""
+    """FP64 decode_eval.  Returns out[V][M][3] (and scale[V][M][3]).  Fewer
+    formats than the arrangement's streams mean a scene of lower-degree
+    primitives (band arrangement: bands past the streams; quad arrangement
+    with one stream: Fig. SetupC, bands 4..15): the missing bands are zero."""
     ns = len(fmt)
     fmt, off = _streams16(fmt, off)
     payload = _c(payload, np.uint8)

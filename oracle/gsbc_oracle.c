@@ -1287,12 +1287,15 @@ EXPORT void ref_sh_basis(double x, double y, double z, double *Y)
  * scale[v][j][c] = sum_k |Hhat * Y_k| (the size of the terms). */
 /* Dequantised decoded band vectors of slot s; fmt and offset are per stream.
  * With the band arrangement, bands at or past n_streams are dropped bands
- * (a scene of lower-degree primitives) and are exactly zero. */
+ * (a scene of lower-degree primitives) and are exactly zero; so are the
+ * bands of the quad arrangement past its streams (one stream holds bands
+ * 0..3 of four primitives per block: Fig. SetupC). */
 static void slot_coefficients(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset, uint32_t arr,
                               uint32_t n_streams, const float *vmin, const float *vmax, uint32_t s, double H[16][3])
 {
+    const uint32_t kept = arr == 0 ? n_streams : arr == 2 ? 4 * n_streams : 16;
     for (int k = 0; k < 16; k++) {
-        if (arr == 0 && (uint32_t)k >= n_streams) {
+        if ((uint32_t)k >= kept) {
             H[k][0] = H[k][1] = H[k][2] = 0.0;
             continue;
         }

@@ -161,10 +161,12 @@ gsbc_status check_desc(gsbc_ctx *ctx, const gsbc_stream_desc *d)
 {
     if (!d) return fail(ctx, GSBC_E_ARG, "desc is NULL");
     if (d->n_prims == 0 || d->n_prims > 0x7FFFFFFFull) return fail(ctx, GSBC_E_ARG, "desc.n_prims %llu out of range", (unsigned long long)d->n_prims);
-    // the band arrangement may keep only the (L+1)^2 lowest bands (a degree class)
+    // the band arrangement may keep only the (L+1)^2 lowest bands (a degree
+    // class), and the quad arrangement only its first stream (Fig. SetupC)
     const bool bands_ok = d->arrangement == GSBC_ARR_BANDS &&
                           (d->n_streams == 1 || d->n_streams == 4 || d->n_streams == 9 || d->n_streams == 16);
-    if (d->arrangement > GSBC_ARR_QUAD || (!bands_ok && d->n_streams != streams_of(d->arrangement)))
+    const bool quad1_ok = d->arrangement == GSBC_ARR_QUAD && d->n_streams == 1;
+    if (d->arrangement > GSBC_ARR_QUAD || (!bands_ok && !quad1_ok && d->n_streams != streams_of(d->arrangement)))
         return fail(ctx, GSBC_E_ARG, "desc.arrangement %u with %u streams is not a known arrangement", d->arrangement,
                     d->n_streams);
     if (d->n_pad != pad16(d->n_prims) || d->blocks_per_stream * streams_of(d->arrangement) != d->n_pad)
@@ -199,6 +201,7 @@ BandArgs band_args(const gsbc_stream_desc *d)
         b.format[k] = live ? d->format[k] : 0;
         b.vmin[k] = d->vmin[k];
         b.delta[k] = (d->vmax[k] - d->vmin[k]) / 255.0f;
+        b.delta64[k] = ((double)d->vmax[k] - (double)d->vmin[k]) / 255.0;
     }
     return b;
 }
@@ -428,8 +431,11 @@ gsbc_status gsbc_reorder_degrees(gsbc_ctx *ctx, const float *pos, const float *s
     if (!(tau >= 0.0f) || !isfinite(tau)) return fail(ctx, GSBC_E_ARG, "tau must be finite and >= 0");
     gsbc_params p = resolve(params);
     if ((s = check_params(ctx, p))) return s;
-    if (p.order != 0 || p.arrangement != GSBC_ARR_BANDS)
-        return fail(ctx, GSBC_E_ARG, "degree classes use the sorted band arrangement (order 0, GSBC_ARR_BANDS)");
+    if (p.order != 0 || (p.arrangement != GSBC_ARR_BANDS && p.arrangement != GSBC_ARR_QUAD))
+        return fail(ctx, GSBC_E_ARG,
+                    "degree classes are sorted (order 0) in band streams (GSBC_ARR_BANDS) or with the degree-1 "
+                    "class in Fig. SetupC (GSBC_ARR_QUAD)");
+    const bool setup_c = p.arrangement == GSBC_ARR_QUAD;
     if (p.quantiser == 1 && 3 * n > 0xFFFFFFFFull)
         return fail(ctx, GSBC_E_ARG, "quantiser 1 counts 3n coefficients per band in 32 bits: n = %llu too large",
                     (unsigned long long)n);
@@ -463,6 +469,7 @@ gsbc_status gsbc_reorder_degrees(gsbc_ctx *ctx, const float *pos, const float *s
         word += (uint64_t)(L + 1) * (L + 1) * pad16(c32[L]);    // (L+1)^2 streams of pad16/16 blocks x 16 words
     }
     if (lay.slot_start[4] != n) return fail(ctx, GSBC_E_DEVICE, "class counts do not add up to n");
+    lay.quad1 = setup_c ? 1u : 0u;
     HIP_TRY(ctx, launch_pack_degrees(sh, opacity, perm, lay, range, textures, ctx->stream), "degree pack launch");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "degree pack");
     for (int L = 0; L < 4; L++) {
@@ -471,9 +478,15 @@ gsbc_status gsbc_reorder_degrees(gsbc_ctx *ctx, const float *pos, const float *s
         for (int k = 0; k < 16; k++) { d.vmin[k] = r.vmin[k]; d.vmax[k] = r.vmax[k]; }
         d.n_prims = counts[L];
         d.n_pad = pad16(counts[L]);
-        d.arrangement = GSBC_ARR_BANDS;
-        d.n_streams = (uint32_t)((L + 1) * (L + 1));
-        d.blocks_per_stream = d.n_pad / 16;
+        if (setup_c && L == 1) {   // one stream of n_pad/4 blocks, four primitives each
+            d.arrangement = GSBC_ARR_QUAD;
+            d.n_streams = 1;
+            d.blocks_per_stream = d.n_pad / 4;
+        } else {
+            d.arrangement = GSBC_ARR_BANDS;
+            d.n_streams = (uint32_t)((L + 1) * (L + 1));
+            d.blocks_per_stream = d.n_pad / 16;
+        }
     }
     return GSBC_OK;
 }

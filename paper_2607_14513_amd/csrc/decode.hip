@@ -38,7 +38,8 @@ __device__ __forceinline__ uint32_t band_texel(const uint8_t *blocks, const Band
 // The band texels of slot s, each found through the arrangement:
 // 0: stream k, block s/16, zigzag texel of s%16 (only the n_streams kept
 // bands of a lower-degree scene; px[k] = 0 past them); 1: stream 0, block s,
-// texel k; 2: stream k/4, block s/4, texel 4 (s%4) + k%4.
+// texel k; 2: stream k/4, block s/4, texel 4 (s%4) + k%4 (only the bands of
+// the n_streams streams: one stream is Fig. SetupC, bands 0..3).
 // One load per block, each decoded as it arrives (the fewest memory
 // instructions, for gathers that issue little else):
 template <int ARR>
@@ -47,7 +48,8 @@ __device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const Ban
 #pragma unroll
     for (int k = 0; k < 16; k++) {
         if (ARR == 1) px[k] = band_texel(blocks, b, 0, s, k);
-        else if (ARR == 2) px[k] = band_texel(blocks, b, k >> 2, s >> 2, 4 * (int)(s & 3u) + (k & 3));
+        else if (ARR == 2) px[k] = (uint32_t)(k >> 2) < b.n_streams
+                                       ? band_texel(blocks, b, k >> 2, s >> 2, 4 * (int)(s & 3u) + (k & 3)) : 0u;
         else px[k] = (uint32_t)k < b.n_streams ? band_texel(blocks, b, k, s >> 4, (int)zigzag_texel(s & 15u)) : 0u;
     }
 }
@@ -63,7 +65,9 @@ __device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const Ban
 #pragma unroll
     for (int k = 0; k < 16; k++) {
         // stream of band k (a dropped band reads stream 0's block and ignores it)
-        const int sk = ARR == 1 ? 0 : ARR == 2 ? (k >> 2) : ((uint32_t)k < b.n_streams ? k : 0);
+        const int sk = ARR == 1 ? 0
+                     : ARR == 2 ? ((uint32_t)(k >> 2) < b.n_streams ? (k >> 2) : 0)
+                                : ((uint32_t)k < b.n_streams ? k : 0);
         const uint64_t blk = ARR == 1 ? s : ARR == 2 ? (s >> 2) : (s >> 4);
         const bool wide = b.format[sk] != 1;
         const uint8_t *q = blocks + b.offset[sk] + blk * (wide ? 16 : 8);
@@ -74,15 +78,28 @@ __device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const Ban
     for (int k = 0; k < 16; k++) {
         const int sk = ARR == 1 ? 0 : ARR == 2 ? (k >> 2) : k;
         const int texel = ARR == 1 ? k : ARR == 2 ? 4 * (int)(s & 3u) + (k & 3) : (int)zigzag_texel(s & 15u);
-        if (ARR == 0 && (uint32_t)k >= b.n_streams) px[k] = 0u;
+        if ((ARR == 0 && (uint32_t)k >= b.n_streams) || (ARR == 2 && (uint32_t)(k >> 2) >= b.n_streams)) px[k] = 0u;
         else if (b.format[sk] == 1) px[k] = bc1_texel(lo[k].x, lo[k].y, texel);
         else px[k] = bc7_texel(Blk128{lo[k].x | (uint64_t)lo[k].y << 32, hi[k].x | (uint64_t)hi[k].y << 32}, texel, lut);
     }
 }
 
-// Bands present in the scene: all 16, or the n_streams lowest of a
-// lower-degree scene in the band arrangement (the rest are exactly zero).
-__device__ __forceinline__ uint32_t kept_bands(const BandArgs &b) { return b.arrangement == 0 ? b.n_streams : 16u; }
+// Dequantised coefficient of code q (low byte) in band k: vmin + q delta in
+// FP64, rounded once to FP32.  With an FP32 step the rounding of delta
+// (relative 2^-24 of the whole band range) would dominate whenever vmin and
+// q delta nearly cancel; this way the value carries only its own rounding.
+__device__ __forceinline__ float dequant(uint32_t q, const BandArgs &b, int k)
+{
+    return (float)fma((double)(q & 255u), b.delta64[k], (double)b.vmin[k]);
+}
+
+// Bands present in the scene: all 16, or the lowest n_streams (band
+// arrangement) or 4 n_streams (quad arrangement, Fig. SetupC with one
+// stream) of a lower-degree scene; the rest are exactly zero.
+__device__ __forceinline__ uint32_t kept_bands(const BandArgs &b)
+{
+    return b.arrangement == 0 ? b.n_streams : b.arrangement == 2 ? 4u * b.n_streams : 16u;
+}
 
 __device__ __forceinline__ void slot_texels(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16])
 {
@@ -188,9 +205,8 @@ __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *block
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
                     const bool kept = (uint32_t)k < nb;
-                    h[k][0] = kept ? fmaf((float)(px[k] & 255), b.delta[k], b.vmin[k]) : 0.0f;
-                    h[k][1] = kept ? fmaf((float)((px[k] >> 8) & 255), b.delta[k], b.vmin[k]) : 0.0f;
-                    h[k][2] = kept ? fmaf((float)((px[k] >> 16) & 255), b.delta[k], b.vmin[k]) : 0.0f;
+#pragma unroll
+                    for (int c = 0; c < 3; c++) h[k][c] = kept ? dequant(px[k] >> (8 * c), b, k) : 0.0f;
                 }
             } else {   // not a slot of this scene: NaN colours, no block access
 #pragma unroll
@@ -349,7 +365,7 @@ __global__ __launch_bounds__(256) void k_decode_eval_view(const uint8_t *blocks,
             if ((uint32_t)k < nb) {
 #pragma unroll
                 for (int ch = 0; ch < 3; ch++)
-                    c[ch] = fmaf(fmaf((float)((px[k] >> (8 * ch)) & 255), b.delta[k], b.vmin[k]), Y[k], c[ch]);
+                    c[ch] = fmaf(dequant(px[k] >> (8 * ch), b, k), Y[k], c[ch]);
             }
         }
     }

@@ -54,7 +54,8 @@ struct BandArgs {
     uint64_t offset[16];   // byte offset of each stream in the payload
     uint32_t format[16];   // per stream: 1 (BC1) or 7 (BC7)
     float vmin[16];        // per band, dequantisation: vmin + q * delta
-    float delta[16];
+    float delta[16];       // (vmax - vmin) / 255 in FP32 (the rate controller's gain weight)
+    double delta64[16];    // the same step in FP64, for dequantising decoded codes
     uint32_t arrangement;  // 0 one stream per band, 1 one primitive per block, 2 four per four blocks
     uint32_t n_streams;    // 16, 1 or 4
 };
@@ -87,6 +88,7 @@ struct DegreeLayout {
     uint64_t slot_start[5];
     uint64_t pad_start[5];
     uint64_t tex_word[4];
+    uint32_t quad1;   // 1: the degree-1 class in Fig. SetupC (one stream, four primitives per block)
 };
 // Range, keys with the degree class above the cell and colour fields, class
 // counts (device uint32[4]) and the sort into perm.

@@ -469,7 +469,9 @@ __global__ void k_zero4(uint32_t *c)
 // One thread per padded slot of every class: thread t of class L (t in
 // [pad_start[L], pad_start[L+1])) is class slot j = t - pad_start[L], the
 // dense slot slot_start[L] + min(j, count[L] - 1); its (L+1)^2 kept bands go
-// to stream k of the class, block j/16, zigzag texel of j%16.
+// to stream k of the class, block j/16, zigzag texel of j%16 -- or, for the
+// degree-1 class in Fig. SetupC, bands 0..3 to texels 4 (j%4) + k of block
+// j/4 of the class's one stream.
 __global__ __launch_bounds__(256) void k_pack_degrees(const float *sh, const float *opacity, const uint32_t *perm,
                                                       DegreeLayout lay, const RangeRec *r, uint32_t *tex)
 {
@@ -493,6 +495,16 @@ __global__ __launch_bounds__(256) void k_pack_degrees(const float *sh, const flo
         for (int e = 0; e < 48; e++) f[e] = mu * f[e];
     }
     const int nb = (L + 1) * (L + 1);
+    if (L == 1 && lay.quad1) {
+        uint32_t *blk = tex + lay.tex_word[1] + (j >> 2) * 16 + 4 * (j & 3);
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const float vm = r->vmin[k], sc = r->scale[k];
+            blk[k] = quant8(f[3 * k], vm, sc) | (quant8(f[3 * k + 1], vm, sc) << 8) |
+                     (quant8(f[3 * k + 2], vm, sc) << 16) | 0xFF000000u;
+        }
+        return;
+    }
     const uint64_t nblk = (lay.pad_start[L + 1] - lay.pad_start[L]) / 16;
     const uint32_t jj = (uint32_t)(j & 15);
     const uint32_t x = (jj & 1u) | (((jj >> 2) & 1u) << 1);

@@ -245,8 +245,10 @@ class Context:
 
     def reorder_degrees(self, pos, sh, tau=0.0, params=None, opacity=None):
         """Degree classes (variable number of bands).  Returns (perm int32[n],
-        counts[4], textures: list of 4 device uint8 views [(L+1)^2][nblk][16][4]
-        or None for an empty class, descs: list of 4 StreamDesc)."""
+        counts[4], textures: list of 4 device uint8 views [S][blocks][16][4]
+        ([(L+1)^2][pad16/16] per band, or [1][pad16/4] for the degree-1 class
+        in Fig. SetupC when params.arrangement is ARR_QUAD) or None for an
+        empty class, descs: list of 4 StreamDesc)."""
         _dev_tensor(pos, torch.float32, "pos")
         _dev_tensor(sh, torch.float32, "sh")
         n = pos.shape[0]
@@ -270,7 +272,8 @@ class Context:
             if c == 0:
                 tex.append(None)
                 continue
-            nb, nblk = (L + 1) ** 2, (c + 15) // 16
+            d = descs[L]
+            nb, nblk = int(d.n_streams), int(d.blocks_per_stream)
             o = int(offs[L])
             tex.append(buf[o:o + nb * nblk * 64].view(nb, nblk, 16, 4))
         return perm, [int(c) for c in counts], tex, [descs[L] for L in range(4)]

@@ -127,3 +127,87 @@ def test_degree_errors(G):
         with pytest.raises(gsbc.GsbcError) as e:
             ctx.reorder_degrees(dev(pos), dev(sh), **kw)
         assert e.value.status == gsbc.E_ARG, kw
+
+
+@pytest.mark.parametrize("n,seed,mix,tau", [(1, 11, (0.0, 1.0, 0.0, 0.0), 0.0), (19, 12, MIX, 0.0),
+                                            (4101, 13, MIX, 1e-4), (65_536, 14, MIX, 0.0)])
+def test_setup_c_class_bit_exact(G, n, seed, mix, tau):
+    """Fig. SetupC for the degree-1 class: permutation, counts and every
+    class texture bit-exact against the oracle; the class is one stream of
+    pad16/4 blocks, the other classes unchanged."""
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(n, seed=seed, degree_mix=mix, small=1e-4 if tau else 0.0)
+    say("reorder degrees SetupC", n, mix, tau)
+    perm, counts, tex, descs = ctx.reorder_degrees(dev(pos), dev(sh), tau=tau,
+                                                   params=gsbc.default_params(arrangement=gsbc.ARR_QUAD))
+    rperm, rcounts, rtex, _, _ = O.reorder_degrees(pos, sh, tau, arrangement=O.ARR_QUAD)
+    assert counts == rcounts.tolist()
+    assert np.array_equal(host(perm).view(np.uint32), rperm)
+    for L in range(4):
+        d = descs[L]
+        if L == 1:
+            assert d.arrangement == gsbc.ARR_QUAD and d.n_streams == 1 and d.blocks_per_stream == d.n_pad // 4
+        else:
+            assert d.arrangement == gsbc.ARR_BANDS and d.n_streams == (L + 1) ** 2
+        if counts[L] == 0:
+            assert tex[L] is None and rtex[L] is None
+        else:
+            assert np.array_equal(host(tex[L]), rtex[L]), L
+
+
+def test_setup_c_encode_decode_and_container(G, tmp_path):
+    """The Fig. SetupC class coded in BC1 and in BC7, alone and in a batch,
+    decoded whole, by direction and by view position, and through a
+    container file: bitstreams and texels bit-exact, colours within 1e-5 of
+    the FP64 oracle."""
+    gsbc, ctx = G
+    n = 20_011
+    pos, sh = synth.make_scene(n, seed=15, degree_mix=MIX)
+    perm, counts, tex, descs = ctx.reorder_degrees(dev(pos), dev(sh),
+                                                   params=gsbc.default_params(arrangement=gsbc.ARR_QUAD))
+    rperm, rcounts, rtex, vmin, vmax = O.reorder_degrees(pos, sh, 0.0, arrangement=O.ARR_QUAD)
+    c1 = counts[1]
+    s1 = counts[0]
+    slots = np.arange(c1, dtype=np.uint32)
+    dirs = synth.make_dirs(9, seed=15)
+    view = np.array([-0.3, 1.1, 0.6], np.float32)
+    for f in (1, 7):
+        d = descs[1]
+        d.format[0] = f
+        fmt = np.array([f], np.uint8)
+        say("SetupC class", c1, "format", f)
+        blocks, d2, _ = ctx.encode(tex[1], d, fmt=gsbc.FMT_BANDS)
+        rpay, roff, _ = O.encode(rtex[1], fmt)
+        assert np.array_equal(host(blocks)[:rpay.size], rpay) and d2.payload_bytes == rpay.size
+        assert np.array_equal(host(ctx.decode(blocks, d2)), O.decode_stream(rpay, roff, fmt, rtex[1].shape[1]))
+        out = host(ctx.decode_eval(blocks, d2, dev(dirs)))
+        r, sc = O.decode_eval(rpay, roff, fmt, vmin, vmax, dirs, slots, arrangement=O.ARR_QUAD)
+        bad = np.argwhere(np.abs(out.astype(np.float64) - r) > REL_TOL * sc)
+        assert bad.size == 0, (f, len(bad), bad[:8].tolist(), [(float(out[tuple(i)]), float(r[tuple(i)]))
+                                                                 for i in bad[:4]])
+        part = perm[s1:s1 + c1].contiguous()
+        ov = host(ctx.decode_eval_view(blocks, d2, dev(pos), part, view))
+        rv, sv = O.decode_eval_view(rpay, roff, fmt, vmin, vmax, pos, rperm[s1:s1 + c1], view, slots,
+                                    arrangement=O.ARR_QUAD)
+        assert np.all(np.abs(ov.astype(np.float64) - rv) <= REL_TOL * sv), f
+        path = str(tmp_path / f"setup_c_{f}.gsbc")
+        ctx.save(path, blocks, d2)
+        b3, d3 = ctx.load(path)
+        assert d3.arrangement == gsbc.ARR_QUAD and d3.n_streams == 1
+        assert np.array_equal(host(b3)[:rpay.size], rpay)
+        assert np.array_equal(host(ctx.decode_eval(b3, d3, dev(dirs))), out)
+        with pytest.raises(gsbc.GsbcError) as e:
+            ctx.encode(tex[1], d, fmt=gsbc.FMT_AUTO, rate=6.0)
+        assert e.value.status == gsbc.E_UNSUPPORTED
+    # the class in a batch beside a per-band class
+    d1 = descs[1]
+    d1.format[0] = 7
+    d3 = descs[3]
+    for k in range(16):
+        d3.format[k] = 7 if k == 0 else 1
+    ref = [O.encode(rtex[1], np.array([7], np.uint8))[0],
+           O.encode(rtex[3], np.array([7] + [1] * 15, np.uint8))[0]]
+    outb = [torch.zeros(r.size + 64, dtype=torch.uint8, device="cuda") for r in ref]
+    ctx.encode_batch([tex[1], tex[3]], [d1, d3], outb)
+    for i, r in enumerate(ref):
+        assert np.array_equal(host(outb[i])[:r.size], r), i

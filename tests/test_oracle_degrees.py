@@ -97,3 +97,56 @@ def test_decode_eval_of_dropped_bands_is_zero():
         H[j, :4] = vmin[:4, None] + codes * delta[:4, None]
     Y = np.stack([O.sh_basis(d) for d in dirs])
     assert np.allclose(out, np.einsum("vk,jkc->vjc", Y, H), rtol=0, atol=1e-12)
+
+
+def test_setup_c_block_layout():
+    """Fig. SetupC: block b of the degree-1 class holds class slots 4b..4b+3,
+    slot i of the block on row i and band k (0..3) in column k -- its four
+    texels are that primitive's four kept codes; the other classes keep the
+    per-band streams.  Padded slots repeat the class's last primitive."""
+    n = 1003
+    pos, sh = synth.make_scene(n, seed=20, degree_mix=(0.25, 0.35, 0.15, 0.25))
+    perm, counts, tex, vmin, vmax = O.reorder_degrees(pos, sh, 0.0, arrangement=O.ARR_QUAD)
+    p2, c2, t2, _, _ = O.reorder_degrees(pos, sh, 0.0)
+    assert np.array_equal(perm, p2) and np.array_equal(counts, c2)
+    for L in (0, 2, 3):
+        assert np.array_equal(tex[L], t2[L])
+    q = O.quantise(sh, vmin, vmax)
+    c1 = int(counts[1])
+    part = perm[counts[0]:counts[0] + c1]
+    t = tex[1]
+    npad = (c1 + 15) // 16 * 16
+    assert t.shape == (1, npad // 4, 16, 4)
+    for j in range(npad):
+        src = part[min(j, c1 - 1)]
+        block = t[0, j // 4]
+        assert np.array_equal(block[4 * (j % 4):4 * (j % 4) + 4, :3], q[src, :4]), j
+        assert np.all(block[:, 3] == 255)
+    # the same codes as the per-band class textures, moved
+    for j in range(c1):
+        for k in range(4):
+            assert np.array_equal(t[0, j // 4, 4 * (j % 4) + k, :3], t2[1][k, j // 16, O.zigzag_texel(j % 16), :3])
+
+
+def test_setup_c_decode_eval():
+    """decode_eval of a Fig. SetupC scene: each slot's four texels of its
+    block, dequantised, dotted with the first four basis functions; bands
+    4..15 contribute nothing."""
+    n = 500
+    pos, sh = synth.make_scene(n, seed=21, degree_mix=(0.0, 1.0, 0.0, 0.0))
+    perm, counts, tex, vmin, vmax = O.reorder_degrees(pos, sh, 0.0, arrangement=O.ARR_QUAD)
+    assert counts.tolist() == [0, n, 0, 0] and tex[1].shape[0] == 1
+    for f in (1, 7):
+        fmt = np.array([f], np.uint8)
+        payload, off, _ = O.encode(tex[1], fmt)
+        dirs = synth.make_dirs(5, seed=21)
+        slots = np.arange(n, dtype=np.uint32)
+        out = O.decode_eval(payload, off, fmt, vmin, vmax, dirs, slots, with_scale=False, arrangement=O.ARR_QUAD)
+        dec = O.decode_stream(payload, off, fmt, tex[1].shape[1])
+        delta = (vmax.astype(np.float64) - vmin.astype(np.float64)) / 255.0
+        H = np.zeros((n, 16, 3))
+        for j in range(n):
+            codes = dec[0, j // 4, 4 * (j % 4):4 * (j % 4) + 4, :3].astype(np.float64)
+            H[j, :4] = vmin[:4, None] + codes * delta[:4, None]
+        Y = np.stack([O.sh_basis(d) for d in dirs])
+        assert np.allclose(out, np.einsum("vk,jkc->vjc", Y, H), rtol=0, atol=1e-12)
