@@ -221,22 +221,21 @@ __device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int 
     // |Cs| <= 2^14 (the largest diagonal is below 2^14 and bounds every entry
     // of the positive semi-definite C) and |v| <= 2^15, so the products are
     // 16-bit dot products with exact 32-bit sums (|u| < 3 * 2^29).
-    short2_t c01[3], c2[3];
+    short2_t c01[3];
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        c01[a] = short2_t{(short)Cs[a][0], (short)Cs[a][1]};
-        c2[a] = short2_t{(short)Cs[a][2], (short)0};
-    }
+    for (int a = 0; a < 3; a++) c01[a] = short2_t{(short)Cs[a][0], (short)Cs[a][1]};
 #pragma unroll
     for (int it = 0; it < 8; it++) {
-        const short2_t v01 = {(short)v[0], (short)v[1]}, v2 = {(short)v[2], (short)0};
+        const short2_t v01 = {(short)v[0], (short)v[1]};
         int u[3];
+        // the third term as a 24-bit product (|Cs| <= 2^14, |v| <= 2^15)
+        // accumulated into by the dot product of the first two
 #pragma unroll
-        for (int a = 0; a < 3; a++)
-            u[a] = __builtin_amdgcn_sdot2(c01[a], v01, __builtin_amdgcn_sdot2(c2[a], v2, 0, false), false);
+        for (int a = 0; a < 3; a++) u[a] = __builtin_amdgcn_sdot2(c01[a], v01, __mul24(Cs[a][2], v[2]), false);
         // max |u_a| as max(max u, -min u): two three-way operations
         const int mx = max(max(u[0], max(u[1], u[2])), -min(u[0], min(u[1], u[2])));
-        int sh = max(0, bitlen(mx) - 15);
+        // bitlen(mx) - 15, with mx | 1 so that the count is defined at 0
+        int sh = max(0, 17 - __builtin_clz((uint32_t)mx | 1u));
 #pragma unroll
         for (int a = 0; a < 3; a++) v[a] = u[a] >> sh;
     }
