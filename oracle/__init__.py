@@ -58,6 +58,7 @@ def _load():
             "ref_pack": (None, [P, P, u64, P]),
             "ref_pack_prim": (None, [P, P, u64, P]),
             "ref_pack_quad": (None, [P, P, u64, P]),
+            "ref_principal_axis": (None, [i32, P, P]),
             "ref_bc1_decode_block": (None, [P, P]),
             "ref_bc7_decode_block": (None, [P, P]),
             "ref_bc1_encode_block": (u32, [P, u32, P]),
@@ -234,6 +235,14 @@ def reorder_degrees(pos, sh, tau=0.0, grid_bits=3, opacity=None, quantiser=0, ar
 
 
 # ---------------------------------------------------------------- D, E
+def principal_axis(x):
+    """Integer power-iteration axis (E1 step 2) of the triples x[n][3]."""
+    x = _c(np.asarray(x), np.int32).reshape(-1, 3)
+    v = np.zeros(3, np.int64)
+    _load().ref_principal_axis(x.shape[0], _p(x), _p(v))
+    return v
+
+
 def bc1_decode(blocks):
     blocks = _c(blocks, np.uint8).reshape(-1, 8)
     out = np.empty((blocks.shape[0], 16, 4), np.uint8)

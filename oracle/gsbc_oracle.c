@@ -575,6 +575,12 @@ static void principal_axis(int n, const int (*x)[3], int64_t v[3])
     if (v[0] == 0 && v[1] == 0 && v[2] == 0) v[0] = v[1] = v[2] = 1;
 }
 
+/* The axis of n triples x[n][3] (for the pins of the step above). */
+EXPORT void ref_principal_axis(int n, const int *x, int64_t *v)
+{
+    principal_axis(n, (const int (*)[3])x, v);
+}
+
 /* floor(num/den) for den > 0 */
 static int64_t floor_div(int64_t num, int64_t den)
 {
