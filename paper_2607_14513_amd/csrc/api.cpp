@@ -201,7 +201,9 @@ BandArgs band_args(const gsbc_stream_desc *d)
         b.format[k] = live ? d->format[k] : 0;
         b.vmin[k] = d->vmin[k];
         b.delta[k] = (d->vmax[k] - d->vmin[k]) / 255.0f;
-        b.delta64[k] = ((double)d->vmax[k] - (double)d->vmin[k]) / 255.0;
+        const double d64 = ((double)d->vmax[k] - (double)d->vmin[k]) / 255.0;
+        b.dhi[k] = (float)d64;
+        b.dlo[k] = (float)(d64 - (double)b.dhi[k]);
     }
     return b;
 }

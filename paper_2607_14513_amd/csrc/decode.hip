@@ -84,13 +84,16 @@ __device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const Ban
     }
 }
 
-// Dequantised coefficient of code q (low byte) in band k: vmin + q delta in
-// FP64, rounded once to FP32.  With an FP32 step the rounding of delta
-// (relative 2^-24 of the whole band range) would dominate whenever vmin and
-// q delta nearly cancel; this way the value carries only its own rounding.
+// Dequantised coefficient of code q (low byte) in band k: vmin + q delta with
+// the FP64 step delta = dhi + dlo (to 2^-48).  Each fused step rounds once,
+// relative to its own result: vmin + q dhi, then + q dlo, so the value
+// carries about one FP32 rounding of itself.  With delta rounded to FP32
+// the step's error (2^-24 of the whole band range) would dominate whenever
+// vmin and q delta nearly cancel.
 __device__ __forceinline__ float dequant(uint32_t q, const BandArgs &b, int k)
 {
-    return (float)fma((double)(q & 255u), b.delta64[k], (double)b.vmin[k]);
+    const float qf = (float)(q & 255u);
+    return fmaf(qf, b.dlo[k], fmaf(qf, b.dhi[k], b.vmin[k]));
 }
 
 // Bands present in the scene: all 16, or the lowest n_streams (band

@@ -55,7 +55,7 @@ struct BandArgs {
     uint32_t format[16];   // per stream: 1 (BC1) or 7 (BC7)
     float vmin[16];        // per band, dequantisation: vmin + q * delta
     float delta[16];       // (vmax - vmin) / 255 in FP32 (the rate controller's gain weight)
-    double delta64[16];    // the same step in FP64, for dequantising decoded codes
+    float dhi[16], dlo[16];  // the FP64 step split as dhi + dlo (FP32 each), for dequantising decoded codes
     uint32_t arrangement;  // 0 one stream per band, 1 one primitive per block, 2 four per four blocks
     uint32_t n_streams;    // 16, 1 or 4
 };
