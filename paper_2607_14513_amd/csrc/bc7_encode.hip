@@ -932,20 +932,31 @@ __device__ __forceinline__ int mode_of_candidate(int ci)
 }
 
 // Per-workgroup mode counts (LDS atomics), written to wgcount[wg][8]; each
-// block's final SSE (key >> 9) is added into its run's sum here.
+// block's final SSE (key >> 9) is added into its run's sum here.  Runs
+// start at multiples of 256 blocks, so a workgroup lies in one run: its
+// SSEs are summed in LDS first and reach the run's sum as one atomic (per
+// wave, a thousand waves of one band would queue on the same address).
 __global__ __launch_bounds__(kWG) void k_bc7_bucket_count(EncodeArgs a, uint32_t *wgcount)
 {
     __shared__ uint32_t c[8];
+    __shared__ unsigned long long s_sse;
     if (threadIdx.x < 8) c[threadIdx.x] = 0;
+    if (threadIdx.x == 0) s_sse = 0;
     __syncthreads();
     const uint64_t g0 = (uint64_t)blockIdx.x * kWG, g = g0 + threadIdx.x;
     const uint32_t key = g < a.total ? a.keys[g] : ~0u;
     const bool live = key != ~0u;
     if (live) atomicAdd(&c[mode_of_candidate((int)(key & 511u))], 1u);
     const BlockRun run = a.run[find_run(a.run, a.nrun, g0)];
-    if (run.sse) band_add(run.sse, 0, key >> 9, live);
+    if (run.sse) {
+        unsigned long long x = live ? (unsigned long long)(key >> 9) : 0ull;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        if ((threadIdx.x & 63) == 0) atomicAdd(&s_sse, x);
+    }
     __syncthreads();
     if (threadIdx.x < 8) wgcount[(uint64_t)blockIdx.x * 8 + threadIdx.x] = c[threadIdx.x];
+    if (threadIdx.x == 0 && run.sse && s_sse) atomicAdd(&run.sse[0], s_sse);
 }
 
 // Exclusive scan of wgcount down each mode's column, then the buckets:
