@@ -579,21 +579,29 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
     a.mode_mask = p.bc7_mode_mask;
     a.keys = reinterpret_cast<uint32_t *>(arena + front + 2 * kRunTableBytes);
     const WorkSplit w3[3] = {kPlainSplit, kPlainSplit, kPlainSplit};
-    // both formats on the context's stream, one after the other, so each
-    // kernel's device time is its own (gsbc_encode_batch can overlap them)
+    // With both formats: the BC7 search runs alone on the context's stream
+    // (its device time is its own), then the BC1 encoder runs on a side
+    // stream beside the short, latency-bound BC7 bucketing and emit kernels,
+    // joined before anything reads either format's results.
     hipStream_t s1 = ctx->stream;
-    if (have1) {
-        EncodeArgs a1 = a;
-        a1.run = druns1;
-        a1.nrun = (uint32_t)r1.v.size();
-        a1.total = r1.total;
-        HIP_TRY(ctx, launch_bc1_encode(a1, kPlainSplit, kPlainBc1Lanes, s1), "bc1 launch");
+    const bool both = have1 && have7;
+    if (both) {
+        if ((s = ensure_side(ctx))) return s;
+        s1 = ctx->side;
     }
     if (have7) {
         a.run = druns7;
         a.nrun = (uint32_t)r7.v.size();
         a.total = r7.total;
-        HIP_TRY(ctx, launch_bc7_encode(a, w3, kPlainBc7Split, ctx->stream), "bc7 launch");
+        HIP_TRY(ctx, launch_bc7_encode(a, w3, kPlainBc7Split, ctx->stream, both ? ctx->fork : nullptr), "bc7 launch");
+    }
+    if (have1) {
+        EncodeArgs a1 = a;
+        a1.run = druns1;
+        a1.nrun = (uint32_t)r1.v.size();
+        a1.total = r1.total;
+        if (both) HIP_TRY(ctx, hipStreamWaitEvent(s1, ctx->fork, 0), "fork");
+        HIP_TRY(ctx, launch_bc1_encode(a1, kPlainSplit, kPlainBc1Lanes, s1), "bc1 launch");
     }
     if (s1 != ctx->stream) {
         HIP_TRY(ctx, hipEventRecord(ctx->join, s1), "join");

@@ -1150,7 +1150,8 @@ hipError_t upload_bc7_tables(int device, hipStream_t st)
     return hipSuccess;
 }
 
-hipError_t launch_bc7_encode(const EncodeArgs &a, const WorkSplit *w3, uint32_t split, hipStream_t st)
+hipError_t launch_bc7_encode(const EncodeArgs &a, const WorkSplit *w3, uint32_t split, hipStream_t st,
+                             hipEvent_t searched)
 {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -1190,6 +1191,7 @@ hipError_t launch_bc7_encode(const EncodeArgs &a, const WorkSplit *w3, uint32_t 
     } else {
         if ((e = launch(0, k_bc7_search<8>, "bc7_search_items")) != hipSuccess) return e;
     }
+    if (searched && (e = hipEventRecord(searched, st)) != hipSuccess) return e;
     // key scratch: keys[total] | list[total] | count[8] start[8] | wgcount[nwg][8]
     uint32_t *count = a.keys + 2 * a.total, *wgcount = count + 16;
     GSBC_LAUNCH("bc7_bucket", k_bc7_bucket_count, sgrid, dim3(kWG), 0, st, a, wgcount);

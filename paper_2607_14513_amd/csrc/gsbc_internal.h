@@ -154,7 +154,10 @@ inline size_t bc7_scratch_bytes(uint64_t blocks) { return (size_t)blocks * 8 + 6
 // with (group, rounds) work items.  Every split gives the same bits (the
 // winner is a minimum over a total order, combined with atomic minima).
 hipError_t launch_bc1_encode(const EncodeArgs &a, const WorkSplit &w, uint32_t lanes, hipStream_t st);
-hipError_t launch_bc7_encode(const EncodeArgs &a, const WorkSplit *w3, uint32_t split, hipStream_t st);
+// `searched`, when given, is recorded on st once the search kernels are
+// enqueued (before the bucketing and emit kernels).
+hipError_t launch_bc7_encode(const EncodeArgs &a, const WorkSplit *w3, uint32_t split, hipStream_t st,
+                             hipEvent_t searched = nullptr);
 hipError_t upload_bc1_tables(hipStream_t st);
 hipError_t upload_bc7_tables(int device, hipStream_t st);
 
