@@ -156,16 +156,22 @@ __device__ __forceinline__ Sums subset_sums(const TexLds &S, uint32_t mask, int 
     m.Sx[0] = m.Sx[1] = m.Sx[2] = 0;
 #pragma unroll
     for (int q = 0; q < 6; q++) m.XX[q] = 0;
+    // R and G summed in the halves of one word: 16 R and 16 G over at most
+    // 16 members stay below 2^16
+    uint32_t srg = 0;
     for (uint32_t mm = mask; mm; mm &= mm - 1) {
         uint32_t rg;
         int b;
         texel(S, __ffs(mm) - 1, rot, rg, b);
         int x[3];
         unpack(rg, b, x);
-        m.Sx[0] += x[0]; m.Sx[1] += x[1]; m.Sx[2] += x[2];
+        srg += rg;
+        m.Sx[2] += x[2];
         m.XX[0] += x[0] * x[0]; m.XX[1] += x[0] * x[1]; m.XX[2] += x[0] * x[2];
         m.XX[3] += x[1] * x[1]; m.XX[4] += x[1] * x[2]; m.XX[5] += x[2] * x[2];
     }
+    m.Sx[0] = (int)((srg & 0xFFFFu) >> 4);
+    m.Sx[1] = (int)(srg >> 20);
     return m;
 }
 
@@ -251,9 +257,10 @@ __device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int 
         uint32_t rg;
         int b;
         texel(S, i, rot, rg, b);
-        const int p16 = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg), v01, __mul24(b, v2x16), false);
-        klo = min(klo, p16 + i);
-        khi = max(khi, p16 + (15 - i));
+        // 16 p + i in one multiply-add and one dot product
+        const int pi = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg), v01, __mul24(b, v2x16) + i, false);
+        klo = min(klo, pi);
+        khi = max(khi, pi + (15 - 2 * i));
     }
     uint32_t rg;
     int b;
