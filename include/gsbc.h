@@ -355,7 +355,9 @@ GSBC_API gsbc_status gsbc_load(gsbc_ctx *ctx, const char *path, gsbc_stream_desc
 
 /* Kernel timing, a tracing aid.  While enabled, every kernel this context
  * launches is bracketed by HIP events on the context's stream (so the times
- * are device times of that stream).  gsbc_profile_read waits for the stream,
+ * are device times of that stream), and gsbc_encode runs its kernels one
+ * after another there (without timing, its BC1 kernel overlaps the BC7
+ * bucketing and emit kernels on a second stream).  gsbc_profile_read waits for the stream,
  * then returns per kernel name (at most max_entries of them, in first-launch
  * order) the number of launches and their total milliseconds since the
  * previous read, and forgets them.

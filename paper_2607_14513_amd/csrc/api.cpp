@@ -582,9 +582,11 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
     // With both formats: the BC7 search runs alone on the context's stream
     // (its device time is its own), then the BC1 encoder runs on a side
     // stream beside the short, latency-bound BC7 bucketing and emit kernels,
-    // joined before anything reads either format's results.
+    // joined before anything reads either format's results.  While kernel
+    // timing is on, everything stays on the context's stream, one kernel
+    // after another, so each timed kernel has the GPU to itself.
     hipStream_t s1 = ctx->stream;
-    const bool both = have1 && have7;
+    const bool both = have1 && have7 && !ctx->profiling;
     if (both) {
         if ((s = ensure_side(ctx))) return s;
         s1 = ctx->side;
