@@ -14,6 +14,10 @@ step time, in Mblocks/s.  Also reported:
                       algorithmic integer ops per launch / its average launch
                       time (HIP events the library records on its stream),
                       against the VALU peak;
+  kernels_ms_per_step per-kernel device times of the same step from extra
+                      passes with the library's kernel timing on, which runs
+                      the encoder's kernels one after another (the timed steps
+                      overlap BC1 with the BC7 bucketing and emit kernels);
   valu_issue          the BC7 search and BC1 encoders' VALU instructions per
                       launch (SQ_INSTS_VALU of the committed rocprofv3 pass)
                       over the live launch time, against one wave64
