@@ -352,6 +352,29 @@ def test_rate_auto_bit_exact(G, rate):
     assert block_bits == rate * 16 * (nblk * 16)
 
 
+def test_encode_same_with_kernel_timing(G):
+    """With kernel timing on the encoder runs its kernels one after another
+    on one stream instead of overlapping BC1 with the BC7 bucketing: the
+    payload, formats and band SSEs are the same, and every kernel of the
+    call is reported."""
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(70_001, seed=37)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    b0, d0, s0 = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=6.0, want_sse=True)
+    p0 = host(b0)[:d0.payload_bytes].copy()
+    ctx.profile(True)
+    ctx.profile_read()
+    try:
+        b1, d1, s1 = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=6.0, want_sse=True)
+        kern = ctx.profile_read()
+    finally:
+        ctx.profile(False)
+    assert np.array_equal(host(b1)[:d1.payload_bytes], p0)
+    assert np.array_equal(d1.formats(), d0.formats()) and np.array_equal(s1, s0)
+    assert "bc1_encode" in kern and "bc7_search_items" in kern and "bc7_bucket" in kern
+    assert all(v[1] > 0 for v in kern.values())
+
+
 def test_container_round_trip(G, tmp_path):
     """save -> load gives the same payload and header, and decodes the same."""
     gsbc, ctx = G
