@@ -178,17 +178,28 @@ constexpr int kCols = 3 * kSlots;           // output floats per direction
 constexpr int kDirChunk = 256;              // directions per workgroup (grid.y); their basis rows sit in LDS
 constexpr int kBasStride = 17;              // padded basis row in LDS
 constexpr int kStageStride = 196;           // padded staging row (192 columns per wave)
-constexpr int kPhase2Floats = kDirChunk * kBasStride + 4 * 16 * kStageStride;
-constexpr int kLdsFloats = kPhase2Floats > 16 * kCols + kBc7LutWords ? kPhase2Floats : 16 * kCols + kBc7LutWords;
-
-__global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *blocks, BandArgs b,
-                                                            const uint32_t *prim_idx, uint64_t m,
-                                                            uint64_t n_prims, const float *basis,
-                                                            uint32_t n_dirs, float *out)
+// SR staging rows per wave: 16 (all rows of a 16-direction tile at once;
+// two workgroups per CU) or 8 (the tile in two halves; 49.7 KB of LDS and at
+// most 168 VGPRs, so three workgroups per CU).  Three hide the decode
+// prologue better and win when a workgroup has few directions to write; at
+// hundreds of directions the two-workgroup form writes faster.
+template <int SR>
+constexpr int lds_floats()
 {
-    __shared__ __align__(16) float lds[kLdsFloats];
+    return kDirChunk * kBasStride + 4 * SR * kStageStride > 16 * kCols + kBc7LutWords
+               ? kDirChunk * kBasStride + 4 * SR * kStageStride
+               : 16 * kCols + kBc7LutWords;
+}
+
+template <int SR>
+__device__ __forceinline__ void decode_eval_body(const uint8_t *blocks, const BandArgs &b, const uint32_t *prim_idx,
+                                                 uint64_t m, uint64_t n_prims, const float *basis, uint32_t n_dirs,
+                                                 float *out)
+{
+    __shared__ __align__(16) float lds[lds_floats<SR>()];
     float(*Hm)[kCols] = reinterpret_cast<float(*)[kCols]>(lds);
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);   // wave-uniform: row addresses stay scalar
     const uint64_t j0 = (uint64_t)blockIdx.x * kSlots;
     // ---- decode: lane t -> slot j0 + t
     {
@@ -248,7 +259,7 @@ __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *block
     // counter tracks loads and stores together, and waiting for a load would
     // also wait for every store issued before it.
     float *bas = lds;                                                  // [kDirChunk][kBasStride]
-    float(*stage)[kStageStride] = reinterpret_cast<float(*)[kStageStride]>(lds + kDirChunk * kBasStride) + 16 * wave;
+    float(*stage)[kStageStride] = reinterpret_cast<float(*)[kStageStride]>(lds + kDirChunk * kBasStride) + SR * wave;
     const uint32_t vc0 = blockIdx.y * kDirChunk;
     const uint32_t v_end = min(n_dirs, vc0 + kDirChunk);
     __syncthreads();           // every wave holds its B operands
@@ -257,62 +268,127 @@ __global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *block
         bas[(e / 16) * kBasStride + e % 16] = v < v_end ? basis[16 * (uint64_t)v + e % 16] : 0.0f;
     }
     __syncthreads();
-    for (uint32_t v0 = vc0; v0 < v_end; v0 += 16) {
-        // A operand: Y[v0 + col][4s + row]
-        float aop[4];
-#pragma unroll
-        for (int s = 0; s < 4; s++) aop[s] = bas[(v0 - vc0 + col) * kBasStride + 4 * s + row];
-        // all 12 tiles staged (16 rows x 192 columns), then each row leaves as
-        // three back-to-back stores of 64 floats: 768 contiguous bytes
-#pragma unroll
-        for (int q = 0; q < 12; q++) {
-            floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
-#pragma unroll
-            for (int s = 0; s < 4; s++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[s], bop[q][s], acc, 0, 0, 0);
-#pragma unroll
-            for (int r = 0; r < 4; r++) stage[4 * row + r][16 * q + col] = acc[r];
-        }
-        bool cok[3];
-#pragma unroll
-        for (int h = 0; h < 3; h++) cok[h] = wcol0 + 64 * h + lane < cols_valid;
-        float *o = obase + v0 * row_stride + lane;
-        if (v0 + 16 <= v_end && wcol0 + 192 <= cols_valid && rows16) {
-            // whole rows, every column valid, 16-byte aligned: lanes 0..47
-            // store 4 consecutive columns each, one instruction per row
-            if (lane < 48) {
-                floatx4 *o4 = reinterpret_cast<floatx4 *>(obase + v0 * row_stride) + lane;
-#pragma unroll
+    if constexpr (SR == 16) {
+        for (uint32_t v0 = vc0; v0 < v_end; v0 += 16) {
+            // A operand: Y[v0 + col][4s + row]
+            float aop[4];
+    #pragma unroll
+            for (int s = 0; s < 4; s++) aop[s] = bas[(v0 - vc0 + col) * kBasStride + 4 * s + row];
+            // all 12 tiles staged (16 rows x 192 columns), then each row leaves as
+            // three back-to-back stores of 64 floats: 768 contiguous bytes
+    #pragma unroll
+            for (int q = 0; q < 12; q++) {
+                floatx4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+    #pragma unroll
+                for (int s = 0; s < 4; s++) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[s], bop[q][s], acc, 0, 0, 0);
+    #pragma unroll
+                for (int r = 0; r < 4; r++) stage[4 * row + r][16 * q + col] = acc[r];
+            }
+            bool cok[3];
+    #pragma unroll
+            for (int h = 0; h < 3; h++) cok[h] = wcol0 + 64 * h + lane < cols_valid;
+            float *o = obase + v0 * row_stride + lane;
+            if (v0 + 16 <= v_end && wcol0 + 192 <= cols_valid && rows16) {
+                // whole rows, every column valid, 16-byte aligned: lanes 0..47
+                // store 4 consecutive columns each, one instruction per row
+                if (lane < 48) {
+                    floatx4 *o4 = reinterpret_cast<floatx4 *>(obase + v0 * row_stride) + lane;
+    #pragma unroll
+                    for (int half = 0; half < 2; half++) {
+                        floatx4 x[8];
+    #pragma unroll
+                        for (int rr = 0; rr < 8; rr++)
+                            x[rr] = *reinterpret_cast<const floatx4 *>(&stage[8 * half + rr][4 * lane]);
+    #pragma unroll
+                        for (int rr = 0; rr < 8; rr++)
+                            __builtin_nontemporal_store(x[rr], o4 + (8 * half + rr) * (row_stride / 4));
+                    }
+                }
+            } else if (v0 + 16 <= v_end) {
+    #pragma unroll
                 for (int half = 0; half < 2; half++) {
-                    floatx4 x[8];
-#pragma unroll
+                    float x[8][3];
+    #pragma unroll
                     for (int rr = 0; rr < 8; rr++)
-                        x[rr] = *reinterpret_cast<const floatx4 *>(&stage[8 * half + rr][4 * lane]);
-#pragma unroll
+    #pragma unroll
+                        for (int h = 0; h < 3; h++) x[rr][h] = stage[8 * half + rr][64 * h + lane];
+    #pragma unroll
                     for (int rr = 0; rr < 8; rr++)
-                        __builtin_nontemporal_store(x[rr], o4 + (8 * half + rr) * (row_stride / 4));
+    #pragma unroll
+                        for (int h = 0; h < 3; h++)
+                            if (cok[h]) __builtin_nontemporal_store(x[rr][h], o + (8 * half + rr) * row_stride + 64 * h);
+                }
+            } else {
+                for (uint32_t rr = 0; v0 + rr < v_end; rr++)
+    #pragma unroll
+                    for (int h = 0; h < 3; h++)
+                        if (cok[h]) __builtin_nontemporal_store(stage[rr][64 * h + lane], o + rr * row_stride + 64 * h);
+            }
+        }
+    } else {
+        for (uint32_t v0 = vc0; v0 < v_end; v0 += 16) {
+            float aop[4];
+    #pragma unroll
+            for (int s = 0; s < 4; s++) aop[s] = bas[(v0 - vc0 + col) * kBasStride + 4 * s + row];
+            floatx4 acc[12];
+    #pragma unroll
+            for (int q = 0; q < 12; q++) {
+                acc[q] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    #pragma unroll
+                for (int s = 0; s < 4; s++) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(aop[s], bop[q][s], acc[q], 0, 0, 0);
+            }
+            bool cok[3];
+    #pragma unroll
+            for (int h = 0; h < 3; h++) cok[h] = wcol0 + 64 * h + lane < cols_valid;
+            const bool fast = v0 + 16 <= v_end && wcol0 + 192 <= cols_valid && rows16;
+            // half hr stages rows 4 i + 2 hr + e (i = 0..3, e = 0, 1) at staging row 2 i + e
+    #pragma unroll
+            for (int hr = 0; hr < 2; hr++) {
+    #pragma unroll
+                for (int q = 0; q < 12; q++)
+    #pragma unroll
+                    for (int e = 0; e < 2; e++) stage[2 * row + e][16 * q + col] = acc[q][2 * hr + e];
+                if (fast) {
+                    if (lane < 48) {
+                        floatx4 *o4 = reinterpret_cast<floatx4 *>(obase + (v0 + 2 * hr) * row_stride) + lane;
+    #pragma unroll
+                        for (int g = 0; g < 8; g += 4) {
+                            floatx4 x[4];
+    #pragma unroll
+                            for (int e = 0; e < 4; e++) x[e] = *reinterpret_cast<const floatx4 *>(&stage[g + e][4 * lane]);
+    #pragma unroll
+                            for (int e = 0; e < 4; e++)
+                                __builtin_nontemporal_store(x[e], o4 + (4 * ((g + e) >> 1) + ((g + e) & 1)) * (row_stride / 4));
+                        }
+                    }
+                } else {
+                    float *o = obase + v0 * row_stride + lane;
+                    for (int sr = 0; sr < 8; sr++) {
+                        const uint32_t dv = 4 * (sr >> 1) + 2 * hr + (sr & 1);
+                        if (v0 + dv < v_end)
+    #pragma unroll
+                            for (int h = 0; h < 3; h++)
+                                if (cok[h]) __builtin_nontemporal_store(stage[sr][64 * h + lane], o + dv * row_stride + 64 * h);
+                    }
                 }
             }
-        } else if (v0 + 16 <= v_end) {
-#pragma unroll
-            for (int half = 0; half < 2; half++) {
-                float x[8][3];
-#pragma unroll
-                for (int rr = 0; rr < 8; rr++)
-#pragma unroll
-                    for (int h = 0; h < 3; h++) x[rr][h] = stage[8 * half + rr][64 * h + lane];
-#pragma unroll
-                for (int rr = 0; rr < 8; rr++)
-#pragma unroll
-                    for (int h = 0; h < 3; h++)
-                        if (cok[h]) __builtin_nontemporal_store(x[rr][h], o + (8 * half + rr) * row_stride + 64 * h);
-            }
-        } else {
-            for (uint32_t rr = 0; v0 + rr < v_end; rr++)
-#pragma unroll
-                for (int h = 0; h < 3; h++)
-                    if (cok[h]) __builtin_nontemporal_store(stage[rr][64 * h + lane], o + rr * row_stride + 64 * h);
         }
     }
+}
+
+__global__ __launch_bounds__(kEvalBlock) void k_decode_eval(const uint8_t *blocks, BandArgs b,
+                                                            const uint32_t *prim_idx, uint64_t m,
+                                                            uint64_t n_prims, const float *basis,
+                                                            uint32_t n_dirs, float *out)
+{
+    decode_eval_body<16>(blocks, b, prim_idx, m, n_prims, basis, n_dirs, out);
+}
+
+__global__ __launch_bounds__(kEvalBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_decode_eval_small(
+    const uint8_t *blocks, BandArgs b, const uint32_t *prim_idx, uint64_t m, uint64_t n_prims, const float *basis,
+    uint32_t n_dirs, float *out)
+{
+    decode_eval_body<8>(blocks, b, prim_idx, m, n_prims, basis, n_dirs, out);
 }
 
 // Colour of each listed slot seen from one view position f (Sec. II,
@@ -405,8 +481,12 @@ hipError_t launch_decode_eval(const uint8_t *blocks, const BandArgs &b, uint64_t
     if (m == 0 || n_dirs == 0) return hipSuccess;
     GSBC_LAUNCH("sh_basis", k_sh_basis, dim3((n_dirs + 255) / 256), dim3(256), 0, st, dirs, n_dirs, basis);
     dim3 grid((uint32_t)((m + kSlots - 1) / kSlots), (n_dirs + kDirChunk - 1) / kDirChunk);
-    GSBC_LAUNCH("decode_eval", k_decode_eval, grid, dim3(kEvalBlock), 0, st, blocks, b, prim_idx, m, n_prims, basis,
-                       n_dirs, out);
+    if (n_dirs <= (uint32_t)kDirChunk)   // one direction chunk per workgroup: three workgroups per CU
+        GSBC_LAUNCH("decode_eval", k_decode_eval_small, grid, dim3(kEvalBlock), 0, st, blocks, b, prim_idx, m,
+                    n_prims, basis, n_dirs, out);
+    else
+        GSBC_LAUNCH("decode_eval", k_decode_eval, grid, dim3(kEvalBlock), 0, st, blocks, b, prim_idx, m, n_prims,
+                    basis, n_dirs, out);
     return hipGetLastError();
 }
 
