@@ -170,8 +170,20 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
     constexpr int F = FOUR ? 3 : 2;
     const uint32_t *magic = FOUR ? kTab.magic4 : kTab.magic3;
     int si = 0;   // split number in enumeration order
-    for (int s1 = 0; s1 <= 16; s1++)
-        for (int s2 = s1; s2 <= 16; s2++)
+    for (int s1 = 0; s1 <= 16; s1++) {
+        int a[3];
+#pragma unroll
+        for (int c = 0; c < 3; c++) a[c] = L.m2P[s1 * 3 + c][lane];
+        for (int s2 = s1; s2 <= 16; s2++) {
+            // prefix values of the outer bounds, and their sum and difference,
+            // once per (s1, s2) instead of once per split
+            int bq[3], ab[3], bma[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                bq[c] = L.m2P[s2 * 3 + c][lane];
+                ab[c] = a[c] + bq[c];
+                bma[c] = bq[c] - a[c];
+            }
             for (int s3 = FOUR ? s2 : 16; s3 <= 16; s3++) {
                 const uint32_t M = magic[si++];
                 const int n0 = s1, n1 = s2 - s1, n2 = s3 - s2, n3 = 16 - s3;
@@ -184,9 +196,8 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
                     const int wide = c == 1;
-                    const int a = L.m2P[s1 * 3 + c][lane], bq = L.m2P[s2 * 3 + c][lane];
                     const int cq = FOUR ? L.m2P[s3 * 3 + c][lane] : m2tot[c];
-                    const int sam = FOUR ? a + bq + cq : a + bq;   // -2 SA
+                    const int sam = FOUR ? ab[c] + cq : ab[c];   // -2 SA
                     const int y0 = mul_i24(sam, -F * (B + AB)) + mul_i24(tot[c], -2 * F * F * AB);
                     const int y1 = mul_i24(sam, F * (A + AB)) + mul_i24(tot[c], 2 * F * F * A);
                     const int e0 = L.val[wide][quant_h_int(y0, det, M)];
@@ -195,15 +206,15 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
                         // (2 e0 + e1 + 1) / 3 and (e0 + 2 e1 + 1) / 3 as (v * 43691) >> 17, exact for v < 2^17
                         const int p1 = (int)((mul_u24((uint32_t)(2 * e0 + e1), 43691u) + 43691u) >> 17);
                         const int p2 = (int)((mul_u24((uint32_t)(e0 + 2 * e1), 43691u) + 43691u) >> 17);
-                        sse += mul_i24(e0, mul_i24(n0, e0) + a);
-                        sse += mul_i24(p1, mul_i24(n1, p1) + (bq - a));
-                        sse += mul_i24(p2, mul_i24(n2, p2) + (cq - bq));
+                        sse += mul_i24(e0, mul_i24(n0, e0) + a[c]);
+                        sse += mul_i24(p1, mul_i24(n1, p1) + bma[c]);
+                        sse += mul_i24(p2, mul_i24(n2, p2) + (cq - bq[c]));
                         sse += mul_i24(e1, mul_i24(n3, e1) + (m2tot[c] - cq));
                     } else {
                         const int p1 = (e0 + e1 + 1) >> 1;
-                        sse += mul_i24(e0, mul_i24(n0, e0) + a);
-                        sse += mul_i24(p1, mul_i24(n1, p1) + (bq - a));
-                        sse += mul_i24(e1, mul_i24(n2, e1) + (m2tot[c] - bq));
+                        sse += mul_i24(e0, mul_i24(n0, e0) + a[c]);
+                        sse += mul_i24(p1, mul_i24(n1, p1) + bma[c]);
+                        sse += mul_i24(e1, mul_i24(n2, e1) + (m2tot[c] - bq[c]));
                     }
                 }
                 if ((uint32_t)sse < best) {
@@ -211,6 +222,8 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
                     best_split = (uint32_t)s1 | ((uint32_t)s2 << 5) | ((uint32_t)s3 << 10) | (FOUR ? 1u << 15 : 0u);
                 }
             }
+        }
+    }
 }
 
 // Endpoint codes of one split (the same arithmetic as split_list).
