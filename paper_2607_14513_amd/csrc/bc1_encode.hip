@@ -90,7 +90,9 @@ __device__ __forceinline__ int quant_h(int y, double inv)
 // next integer).
 __device__ __forceinline__ int quant_h_int(int y, int det, uint32_t M)
 {
-    const int yc = min(max(y, 1 - det), 511 * det);
+    // the clamp as a median of three (one v_med3_i32): 1 - det <= 0 < 511 det
+    const int lo = 1 - det, hi = 511 * det;
+    const int yc = max(min(y, lo), min(max(y, lo), hi));
     return (int)(__umulhi((uint32_t)(yc + det - 1), M) >> 4);
 }
 
