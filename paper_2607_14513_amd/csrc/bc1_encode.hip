@@ -179,12 +179,13 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
         for (int s2 = s1; s2 <= 16; s2++) {
             // prefix values of the outer bounds, and their sum and difference,
             // once per (s1, s2) instead of once per split
-            int bq[3], ab[3], bma[3];
+            int bq[3], ab[3];
+            short2_t abm[3];   // (a, bq - a) in 16-bit halves (|values| <= 2 * 16 * 255)
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 bq[c] = L.m2P[s2 * 3 + c][lane];
                 ab[c] = a[c] + bq[c];
-                bma[c] = bq[c] - a[c];
+                abm[c] = short2_t{(short)a[c], (short)(bq[c] - a[c])};
             }
             for (int s3 = FOUR ? s2 : 16; s3 <= 16; s3++) {
                 const uint32_t M = magic[si++];
@@ -194,6 +195,7 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
                 const int AB = FOUR ? 2 * (n1 + n2) : n1;
                 const int det = A * B - AB * AB;
                 if (det == 0) continue;
+                const short2_t n01 = {(short)n0, (short)n1}, n23 = {(short)n2, (short)n3};
                 int sse = Q;
 #pragma unroll
                 for (int c = 0; c < 3; c++) {
@@ -208,14 +210,18 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
                         // (2 e0 + e1 + 1) / 3 and (e0 + 2 e1 + 1) / 3 as (v * 43691) >> 17, exact for v < 2^17
                         const int p1 = (int)((mul_u24((uint32_t)(2 * e0 + e1), 43691u) + 43691u) >> 17);
                         const int p2 = (int)((mul_u24((uint32_t)(e0 + 2 * e1), 43691u) + 43691u) >> 17);
-                        sse += mul_i24(e0, mul_i24(n0, e0) + a[c]);
-                        sse += mul_i24(p1, mul_i24(n1, p1) + bma[c]);
-                        sse += mul_i24(p2, mul_i24(n2, p2) + (cq - bq[c]));
-                        sse += mul_i24(e1, mul_i24(n3, e1) + (m2tot[c] - cq));
+                        // p (n p + d) for the four clusters as two 16-bit
+                        // multiply-adds and two dot products (|n p + d| < 2^14)
+                        // codes and interpolants are 0..255: packed without masking
+                        const short2_t pe01 = __builtin_bit_cast(short2_t, (uint32_t)e0 | ((uint32_t)p1 << 16));
+                        const short2_t pe23 = __builtin_bit_cast(short2_t, (uint32_t)p2 | ((uint32_t)e1 << 16));
+                        const short2_t d23 = {(short)(cq - bq[c]), (short)(m2tot[c] - cq)};
+                        sse = __builtin_amdgcn_sdot2(pe01, n01 * pe01 + abm[c], sse, false);
+                        sse = __builtin_amdgcn_sdot2(pe23, n23 * pe23 + d23, sse, false);
                     } else {
                         const int p1 = (e0 + e1 + 1) >> 1;
-                        sse += mul_i24(e0, mul_i24(n0, e0) + a[c]);
-                        sse += mul_i24(p1, mul_i24(n1, p1) + bma[c]);
+                        const short2_t pe01 = __builtin_bit_cast(short2_t, (uint32_t)e0 | ((uint32_t)p1 << 16));
+                        sse = __builtin_amdgcn_sdot2(pe01, n01 * pe01 + abm[c], sse, false);
                         sse += mul_i24(e1, mul_i24(n2, e1) + (m2tot[c] - bq[c]));
                     }
                 }
