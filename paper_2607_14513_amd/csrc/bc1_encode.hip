@@ -419,7 +419,7 @@ __device__ __forceinline__ void encode_block(const uint32_t (&t)[16], uint32_t r
 // One lane per block over the run map; rounds of LANES blocks (a run never
 // straddles a round since runs start at multiples of 256).
 template <int LANES>
-__global__ __launch_bounds__(LANES) __attribute__((amdgpu_waves_per_eu(3))) void k_bc1_encode(EncodeArgs a, WorkSplit w)
+__global__ __launch_bounds__(LANES) __attribute__((amdgpu_waves_per_eu(4))) void k_bc1_encode(EncodeArgs a, WorkSplit w)
 {
     __shared__ Bc1Lds<LANES> L;
     __shared__ uint32_t s_item;
