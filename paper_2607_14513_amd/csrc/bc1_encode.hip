@@ -180,12 +180,14 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
             // prefix values of the outer bounds, and their sum and difference,
             // once per (s1, s2) instead of once per split
             int bq[3], ab[3];
-            short2_t abm[3];   // (a, bq - a) in 16-bit halves (|values| <= 2 * 16 * 255)
+            // (a, bq - a) and (-bq, m2tot) in 16-bit halves (|values| <= 2 * 16 * 255)
+            short2_t abm[3], bm[3];
 #pragma unroll
             for (int c = 0; c < 3; c++) {
                 bq[c] = L.m2P[s2 * 3 + c][lane];
                 ab[c] = a[c] + bq[c];
                 abm[c] = short2_t{(short)a[c], (short)(bq[c] - a[c])};
+                bm[c] = short2_t{(short)(-bq[c]), (short)m2tot[c]};
             }
             for (int s3 = FOUR ? s2 : 16; s3 <= 16; s3++) {
                 const uint32_t M = magic[si++];
@@ -215,7 +217,8 @@ __device__ __forceinline__ void split_list(const Lds &L, int lane, const int (&t
                         // codes and interpolants are 0..255: packed without masking
                         const short2_t pe01 = __builtin_bit_cast(short2_t, (uint32_t)e0 | ((uint32_t)p1 << 16));
                         const short2_t pe23 = __builtin_bit_cast(short2_t, (uint32_t)p2 | ((uint32_t)e1 << 16));
-                        const short2_t d23 = {(short)(cq - bq[c]), (short)(m2tot[c] - cq)};
+                        // (cq - bq, m2tot - cq) = (cq, cq) * (1, -1) + (-bq, m2tot)
+                        const short2_t d23 = short2_t{(short)cq, (short)cq} * short2_t{1, -1} + bm[c];
                         sse = __builtin_amdgcn_sdot2(pe01, n01 * pe01 + abm[c], sse, false);
                         sse = __builtin_amdgcn_sdot2(pe23, n23 * pe23 + d23, sse, false);
                     } else {
