@@ -482,6 +482,33 @@ def test_decode_eval_random_blocks(G, fmt):
     _check_colours(out, ref, scale)
 
 
+def test_decode_eval_cancelling_dequantisation(G):
+    """vmin = -1, vmax = 1.0079 and code 127 in every band and channel:
+    vmin + 127 delta = 1.2e-5, so vmin and q delta cancel to five digits.  A
+    step (vmax - vmin) / 255 rounded to FP32 would put errors of about
+    5e-3 of the colour there; the colours must still meet the 1e-5 bound.
+    BC7 codes constant blocks exactly."""
+    gsbc, ctx = G
+    n, V = 16 * 257 - 3, 11
+    nblk = (n + 15) // 16
+    tex = np.full((16, nblk, 16, 4), 127, np.uint8)
+    tex[..., 3] = 255
+    fmt = np.full(16, 7, np.uint8)
+    payload, off, _ = O.encode(tex, fmt)
+    d = _desc_for(gsbc, n, fmt)
+    vmax = np.float32(1.0079)
+    for k in range(16):
+        d.vmax[k] = float(vmax)
+    assert d.payload_bytes == payload.size and np.array_equal(d.offsets(), off)
+    dirs = synth.make_dirs(V, seed=73)
+    say("cancelling dequantisation")
+    out = host(ctx.decode_eval(dev(payload), d, dev(dirs)))
+    vmin, vmaxs = np.full(16, -1.0, np.float32), np.full(16, vmax, np.float32)
+    ref, scale = O.decode_eval(payload, off, fmt, vmin, vmaxs, dirs, np.arange(n, dtype=np.uint32))
+    assert 0 < np.abs(ref).max() < 1e-4                       # the colours really are tiny
+    _check_colours(out, ref, scale)
+
+
 def test_decode_eval_unaligned_output(G):
     """An output buffer that is not 16-byte aligned is written column by
     column instead of 16 bytes per lane: the same values as an aligned one."""
