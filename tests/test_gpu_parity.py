@@ -507,6 +507,13 @@ def test_decode_eval_cancelling_dequantisation(G):
     ref, scale = O.decode_eval(payload, off, fmt, vmin, vmaxs, dirs, np.arange(n, dtype=np.uint32))
     assert 0 < np.abs(ref).max() < 1e-4                       # the colours really are tiny
     _check_colours(out, ref, scale)
+    rng = np.random.default_rng(73)
+    pos = rng.uniform(-1.0, 1.0, (n, 3)).astype(np.float32)
+    perm = rng.permutation(n).astype(np.uint32)
+    f = np.array([0.3, 2.0, -0.7], np.float32)
+    out = host(ctx.decode_eval_view(dev(payload), d, dev(pos), dev(perm.view(np.int32)), f))
+    ref, scale = O.decode_eval_view(payload, off, fmt, vmin, vmaxs, pos, perm, f, np.arange(n, dtype=np.uint32))
+    _check_colours(out, ref, scale)
 
 
 def test_decode_eval_unaligned_output(G):
