@@ -62,7 +62,7 @@ ALGO_OPS = {
 }
 # one launch over every group (work items per group, or all groups per block)
 ALGO_OPS["bc7_search_items"] = ALGO_OPS["bc7_search_all"] = sum(ALGO_OPS.values())
-TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_encode_step_1M_and_decode_eval_3M.json")
 
 
 def profiled(name, field="bytes"):
