@@ -59,6 +59,7 @@ def _load():
             "ref_pack_prim": (None, [P, P, u64, P]),
             "ref_pack_quad": (None, [P, P, u64, P]),
             "ref_principal_axis": (None, [i32, P, P]),
+            "ref_bc7_ls_endpoints": (i32, [i32, P, P, i32, i32, P]),
             "ref_bc1_decode_block": (None, [P, P]),
             "ref_bc7_decode_block": (None, [P, P]),
             "ref_bc1_encode_block": (u32, [P, u32, P]),
@@ -241,6 +242,20 @@ def principal_axis(x):
     v = np.zeros(3, np.int64)
     _load().ref_principal_axis(x.shape[0], _p(x), _p(v))
     return v
+
+
+def bc7_ls_endpoints(x, idx, nb):
+    """E2 step (d): least-squares endpoints of the members x[n][nch] for
+    their nb-bit indices -> (lo[nch], hi[nch]) or None when singular."""
+    x = np.asarray(x)
+    nch = 1 if x.ndim == 1 else x.shape[1]
+    xx = np.zeros((len(x), 3), np.int32)
+    xx[:, :nch] = x.reshape(len(x), nch)
+    ii = _c(np.asarray(idx), np.int32)
+    out = np.zeros(6, np.int32)
+    if not _load().ref_bc7_ls_endpoints(len(x), _p(xx), _p(ii), int(nb), nch, _p(out)):
+        return None
+    return out[:nch].copy(), out[3:3 + nch].copy()
 
 
 def bc1_decode(blocks):

@@ -917,6 +917,40 @@ static void fit_eval(int nch, int n, const int (*x)[3], const int e_lo[3], const
 
 /* Fit one subset: n texels x[] with nch channels (3 for colour, 1 for the
  * scalar channel of modes 4/5). */
+/* E2 (d): least-squares endpoints of n members x[i][0..nch-1] for their
+ * indices idx[i] with weights w = W[idx] on (64 - w) e0 + w e1 = 64 x:
+ * with A = sum (64-w)^2, B = sum w^2, AB = sum (64-w) w, SA, SB the sums of
+ * (64-w) x and w x, e0 = 64 (B SA - AB SB) / det and e1 = 64 (A SB - AB SA)
+ * / det (det = A B - AB^2), each rounded half up and clamped to [0, 255].
+ * Returns 0 (endpoints untouched) when det = 0. */
+static int ls_endpoints(int n, const int (*x)[3], const int *idx, const int *W, int nch, int *r_lo, int *r_hi)
+{
+    int64_t A = 0, B = 0, AB = 0, SA[3] = {0, 0, 0}, SB[3] = {0, 0, 0};
+    for (int i = 0; i < n; i++) {
+        int b = W[idx[i]], a = 64 - b;
+        A += a * a; B += b * b; AB += a * b;
+        for (int c = 0; c < nch; c++) { SA[c] += a * x[i][c]; SB[c] += b * x[i][c]; }
+    }
+    int64_t det = A * B - AB * AB;
+    if (det == 0) return 0;
+    for (int c = 0; c < nch; c++) {
+        int64_t n0 = 64 * (B * SA[c] - AB * SB[c]);
+        int64_t n1 = 64 * (A * SB[c] - AB * SA[c]);
+        int64_t v0 = floor_div(2 * n0 + det, 2 * det);
+        int64_t v1 = floor_div(2 * n1 + det, 2 * det);
+        r_lo[c] = (int)(v0 < 0 ? 0 : v0 > 255 ? 255 : v0);
+        r_hi[c] = (int)(v1 < 0 ? 0 : v1 > 255 ? 255 : v1);
+    }
+    return 1;
+}
+
+/* The same for the pins: weights of nb-bit indices, nch channels;
+ * out[0..2] = low endpoint, out[3..5] = high endpoint. */
+EXPORT int ref_bc7_ls_endpoints(int n, const int *x, const int *idx, int nb, int nch, int *out)
+{
+    return ls_endpoints(n, (const int (*)[3])x, idx, weights(nb), nch, out, out + 3);
+}
+
 static void fit_subset(int nch, int n, const int (*x)[3], int cb, int pb, int nb, fit_t *out)
 {
     const int *W = weights(nb);
@@ -973,23 +1007,8 @@ static void fit_subset(int nch, int n, const int (*x)[3], int cb, int pb, int nb
     /* (c) */
     fit_eval(nch, n, x, e_lo, e_hi, cb, pb, nb, out);
     /* (d) one least-squares refinement with the chosen indices */
-    int64_t A = 0, B = 0, AB = 0, SA[3] = {0, 0, 0}, SB[3] = {0, 0, 0};
-    for (int i = 0; i < n; i++) {
-        int b = W[out->idx[i]], a = 64 - b;
-        A += a * a; B += b * b; AB += a * b;
-        for (int c = 0; c < nch; c++) { SA[c] += a * x[i][c]; SB[c] += b * x[i][c]; }
-    }
-    int64_t det = A * B - AB * AB;
-    if (det == 0) return;
     int r_lo[3] = {0, 0, 0}, r_hi[3] = {0, 0, 0};
-    for (int c = 0; c < nch; c++) {
-        int64_t n0 = 64 * (B * SA[c] - AB * SB[c]);
-        int64_t n1 = 64 * (A * SB[c] - AB * SA[c]);
-        int64_t v0 = floor_div(2 * n0 + det, 2 * det);
-        int64_t v1 = floor_div(2 * n1 + det, 2 * det);
-        r_lo[c] = (int)(v0 < 0 ? 0 : v0 > 255 ? 255 : v0);
-        r_hi[c] = (int)(v1 < 0 ? 0 : v1 > 255 ? 255 : v1);
-    }
+    if (!ls_endpoints(n, x, out->idx, W, nch, r_lo, r_hi)) return;
     fit_t g;
     fit_eval(nch, n, x, r_lo, r_hi, cb, pb, nb, &g);
     if (g.sse < out->sse) *out = g;

@@ -88,3 +88,54 @@ def test_bc7_beats_bc1_on_smooth_blocks():
     s1 = O.bc1_encode(tex)[1].astype(np.int64).sum()
     s7 = O.bc7_encode(tex)[1].astype(np.int64).sum()
     assert s7 < s1
+
+
+def _ls_reference(x, idx, nb):
+    """Endpoints by numpy's least squares on the stacked design matrix
+    (rows (64 - w, w), targets 64 x), rounded half up with exact fractions
+    deciding values within 1e-6 of a half, clamped to [0, 255]."""
+    from fractions import Fraction
+    m = (1 << nb) - 1
+    w = np.array([(128 * k + m) // (2 * m) for k in idx], np.int64)
+    D = np.stack([64 - w, w], 1).astype(np.float64)
+    if np.linalg.matrix_rank(D) < 2:
+        return None
+    sol, *_ = np.linalg.lstsq(D, 64.0 * x.astype(np.float64), rcond=None)   # [2][nch]
+    A, B, AB = int(((64 - w) ** 2).sum()), int((w * w).sum()), int(((64 - w) * w).sum())
+    det = A * B - AB * AB
+    out = np.empty_like(sol, dtype=np.int64)
+    for e in range(2):
+        for c in range(sol.shape[1]):
+            v = sol[e, c]
+            if abs(v - np.floor(v) - 0.5) < 1e-6:                 # a possible tie: decide exactly
+                SA, SB = int(((64 - w) * x[:, c]).sum()), int((w * x[:, c]).sum())
+                num = 64 * (B * SA - AB * SB) if e == 0 else 64 * (A * SB - AB * SA)
+                v = Fraction(num, det)
+                out[e, c] = int(np.floor(v + Fraction(1, 2)))
+            else:
+                out[e, c] = int(np.floor(v + 0.5))
+    return np.clip(out, 0, 255)
+
+
+@pytest.mark.parametrize("nb", [2, 3, 4])
+def test_least_squares_refit_matches_lstsq(nb):
+    """E2 step (d): the refit endpoints equal an independent least-squares
+    solve of (64 - w) e0 + w e1 = 64 x, rounded half up and clamped, on
+    random members (1 to 16, RGB and one channel), ties included; a single
+    used index (singular system) gives no refit."""
+    rng = np.random.default_rng(40 + nb)
+    for trial in range(400):
+        n = int(rng.integers(1, 17))
+        nch = 3 if trial % 4 else 1
+        x = rng.integers(0, 256, (n, nch))
+        if trial % 7 == 0:
+            x[:] = x[0]                                            # equal members: exact ties likely
+        idx = rng.integers(0, 1 << nb, n)
+        got = O.bc7_ls_endpoints(x, idx, nb)
+        ref = _ls_reference(x, idx, nb)
+        if ref is None:
+            assert got is None
+            continue
+        assert got is not None
+        assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (trial, x.tolist(), idx.tolist())
+    assert O.bc7_ls_endpoints(np.array([[5, 6, 7], [9, 9, 9]]), [1, 1], 2) is None
