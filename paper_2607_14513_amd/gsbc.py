@@ -151,12 +151,41 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _dev_tensor(t, dtype, name):
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
-        raise TypeError(f"{name} must be a device tensor")
+def _check(t, dtype, name, shape=None, min_numel=None):
+    """Type, layout and size of a tensor argument, checked on the host before
+    anything reaches the library: the C ABI takes bare pointers, so a tensor
+    too small for what the descriptor or the counts say would be read or
+    written past its end by the kernels."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
     if t.dtype != dtype or not t.is_contiguous():
         raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if shape is not None and tuple(t.shape) != tuple(int(x) for x in shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(int(x) for x in shape)}")
+    if min_numel is not None and t.numel() < int(min_numel):
+        raise ValueError(f"{name} holds {t.numel()} elements, needs at least {int(min_numel)}")
     return t
+
+
+def _on_device(*named):
+    for name, t in named:
+        if t is not None and not t.is_cuda:
+            raise TypeError(f"{name} must be a device tensor")
+
+
+def _dev_tensor(t, dtype, name, shape=None, min_numel=None):
+    _check(t, dtype, name, shape, min_numel)
+    _on_device((name, t))
+    return t
+
+
+def _desc_numbers(desc):
+    """(n_streams, blocks_per_stream, payload_bytes, n_prims) of a descriptor,
+    with the stream count bounded so that sizes derived from it are sane."""
+    S, nblk = int(desc.n_streams), int(desc.blocks_per_stream)
+    if not 1 <= S <= 16:
+        raise ValueError(f"desc.n_streams = {S} not in 1..16")
+    return S, nblk, int(desc.payload_bytes), int(desc.n_prims)
 
 
 class Context:
@@ -222,13 +251,12 @@ class Context:
     def reorder(self, pos, sh, params=None, out=None, opacity=None):
         """pos float32[n][3], sh float32[n][16][3], opacity float32[n] or None
         on the device -> (perm uint32-as-int32[n], textures uint8[16][nblk][16][4], desc)."""
-        _dev_tensor(pos, torch.float32, "pos")
-        _dev_tensor(sh, torch.float32, "sh")
-        n = pos.shape[0]
+        _check(pos, torch.float32, "pos")
+        n = pos.shape[0] if pos.dim() == 2 else -1
+        _check(pos, torch.float32, "pos", shape=(n, 3))
+        _check(sh, torch.float32, "sh", shape=(n, 16, 3))
         if opacity is not None:
-            _dev_tensor(opacity, torch.float32, "opacity")
-            if opacity.numel() != n:
-                raise ValueError("opacity must hold one weight per primitive")
+            _check(opacity, torch.float32, "opacity", shape=(n,))
         p = params if params is not None else default_params()
         S = N_STREAMS.get(int(p.arrangement), 16)
         npad = (n + 15) // 16 * 16
@@ -237,6 +265,9 @@ class Context:
             tex = torch.empty((S, npad // S, 16, 4), dtype=torch.uint8, device=self.device)
         else:
             perm, tex = out
+            _check(perm, torch.int32, "perm", shape=(n,))
+            _check(tex, torch.uint8, "textures", min_numel=npad * 64)
+        _on_device(("pos", pos), ("sh", sh), ("opacity", opacity), ("perm", perm), ("textures", tex))
         desc = StreamDesc()
         self._check(load().gsbc_reorder(self._h, _ptr(pos), _ptr(sh),
                                         _ptr(opacity) if opacity is not None else None, n, ctypes.byref(p), _ptr(perm),
@@ -249,13 +280,13 @@ class Context:
         ([(L+1)^2][pad16/16] per band, or [1][pad16/4] for the degree-1 class
         in Fig. SetupC when params.arrangement is ARR_QUAD) or None for an
         empty class, descs: list of 4 StreamDesc)."""
-        _dev_tensor(pos, torch.float32, "pos")
-        _dev_tensor(sh, torch.float32, "sh")
-        n = pos.shape[0]
+        _check(pos, torch.float32, "pos")
+        n = pos.shape[0] if pos.dim() == 2 else -1
+        _check(pos, torch.float32, "pos", shape=(n, 3))
+        _check(sh, torch.float32, "sh", shape=(n, 16, 3))
         if opacity is not None:
-            _dev_tensor(opacity, torch.float32, "opacity")
-            if opacity.numel() != n:
-                raise ValueError("opacity must hold one weight per primitive")
+            _check(opacity, torch.float32, "opacity", shape=(n,))
+        _on_device(("pos", pos), ("sh", sh), ("opacity", opacity))
         p = params if params is not None else default_params()
         cap = (n + 15) // 16 * 16 * 64 + 1800
         buf = torch.empty(cap, dtype=torch.uint8, device=self.device)
@@ -281,11 +312,14 @@ class Context:
     def encode(self, textures, desc, fmt=FMT_AUTO, rate=6.0, params=None, blocks=None, want_sse=False):
         """Encode all streams -> (blocks uint8 device tensor, desc, band_sse int64[2][16] or None).
         fmt FMT_BANDS codes stream k in desc.format[k] (set by the caller)."""
-        _dev_tensor(textures, torch.uint8, "textures")
+        S, nblk, _, _ = _desc_numbers(desc)
+        _check(textures, torch.uint8, "textures", min_numel=S * nblk * 64)
         desc = desc.copy()
         if blocks is None:
             _, cap, _ = query_sizes(desc.n_prims)
             blocks = torch.empty(cap, dtype=torch.uint8, device=self.device)
+        _check(blocks, torch.uint8, "blocks")
+        _on_device(("textures", textures), ("blocks", blocks))
         sse = np.zeros(32, np.int64) if want_sse else None
         p = params if params is not None else default_params()
         self._check(load().gsbc_encode(self._h, _ptr(textures), ctypes.byref(desc), int(fmt), float(rate),
@@ -302,7 +336,8 @@ class Context:
         if not (n == len(descs) == len(blocks)):
             raise ValueError("textures, descs and blocks differ in length")
         for i, t in enumerate(textures):
-            _dev_tensor(t, torch.uint8, f"textures[{i}]")
+            S, nblk, _, _ = _desc_numbers(descs[i])
+            _dev_tensor(t, torch.uint8, f"textures[{i}]", min_numel=S * nblk * 64)
             _dev_tensor(blocks[i], torch.uint8, f"blocks[{i}]")
         tp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in textures])
         bp = (ctypes.c_void_p * n)(*[b.data_ptr() for b in blocks])
@@ -321,13 +356,17 @@ class Context:
     def decode_eval_view(self, blocks, desc, pos, perm, view, prim_idx=None, out=None):
         """pos float32[n][3] (input order) and perm int32[n] on the device, view
         3 floats (host) -> out float32[m][3]: each slot's colour seen from view."""
-        _dev_tensor(pos, torch.float32, "pos")
-        _dev_tensor(perm, torch.int32, "perm")
-        m = desc.n_prims if prim_idx is None else prim_idx.numel()
+        _, _, payload, n = _desc_numbers(desc)
+        _check(blocks, torch.uint8, "blocks", min_numel=payload)
+        _check(pos, torch.float32, "pos", shape=(n, 3))
+        _check(perm, torch.int32, "perm", shape=(n,))
+        m = n if prim_idx is None else prim_idx.numel()
         if prim_idx is not None:
-            _dev_tensor(prim_idx, torch.int32, "prim_idx")
+            _check(prim_idx, torch.int32, "prim_idx", shape=(m,))
         if out is None:
             out = torch.empty((m, 3), dtype=torch.float32, device=self.device)
+        _check(out, torch.float32, "out", shape=(m, 3))
+        _on_device(("blocks", blocks), ("pos", pos), ("perm", perm), ("prim_idx", prim_idx), ("out", out))
         f = (ctypes.c_float * 3)(*[float(x) for x in view])
         self._check(load().gsbc_decode_eval_view(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(pos), _ptr(perm), f,
                                                  _ptr(prim_idx), m, _ptr(out)))
@@ -335,7 +374,7 @@ class Context:
 
     def save(self, path, blocks, desc):
         """Write the coded scene (device blocks + desc) as a container file."""
-        _dev_tensor(blocks, torch.uint8, "blocks")
+        _dev_tensor(blocks, torch.uint8, "blocks", min_numel=_desc_numbers(desc)[2])
         self._check(load().gsbc_save(self._h, _ptr(blocks), ctypes.byref(desc), os.fsencode(path)))
 
     def load(self, path):
@@ -346,21 +385,31 @@ class Context:
         return blocks, d
 
     def decode(self, blocks, desc, out=None):
+        """blocks (device payload) -> textures uint8[n_streams][blocks_per_stream][16][4]."""
+        S, nblk, payload, _ = _desc_numbers(desc)
+        _check(blocks, torch.uint8, "blocks", min_numel=payload)
         if out is None:
-            out = torch.empty((desc.n_streams, desc.blocks_per_stream, 16, 4), dtype=torch.uint8, device=self.device)
+            out = torch.empty((S, nblk, 16, 4), dtype=torch.uint8, device=self.device)
+        _check(out, torch.uint8, "out", shape=(S, nblk, 16, 4))
+        _on_device(("blocks", blocks), ("out", out))
         self._check(load().gsbc_decode(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(out)))
         return out
 
     def decode_eval(self, blocks, desc, dirs, prim_idx=None, out=None):
         """dirs float32[V][3] device; prim_idx int32[m] sorted-slot ids or None
         -> out float32[V][m][3]."""
-        _dev_tensor(dirs, torch.float32, "dirs")
-        V = dirs.shape[0]
-        m = desc.n_prims if prim_idx is None else prim_idx.numel()
+        _, _, payload, n = _desc_numbers(desc)
+        _check(blocks, torch.uint8, "blocks", min_numel=payload)
+        _check(dirs, torch.float32, "dirs")
+        V = dirs.shape[0] if dirs.dim() == 2 else -1
+        _check(dirs, torch.float32, "dirs", shape=(V, 3))
+        m = n if prim_idx is None else prim_idx.numel()
         if prim_idx is not None:
-            _dev_tensor(prim_idx, torch.int32, "prim_idx")
+            _check(prim_idx, torch.int32, "prim_idx", shape=(m,))
         if out is None:
             out = torch.empty((V, m, 3), dtype=torch.float32, device=self.device)
+        _check(out, torch.float32, "out", shape=(V, m, 3))
+        _on_device(("blocks", blocks), ("dirs", dirs), ("prim_idx", prim_idx), ("out", out))
         self._check(load().gsbc_decode_eval(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(dirs), V,
                                             _ptr(prim_idx), m, _ptr(out)))
         return out

@@ -302,18 +302,24 @@ def test_bc7_mode_masks(G, mask):
         assert np.array_equal(blocks[o:o + 8 * 16].reshape(8, 16), O.bc7_encode(tex[b], mask)[0])
 
 
+def _sample_blocks(nblk, count, seed):
+    """count distinct block indices of a stream, always holding its first and
+    last block (the ragged end of a launch's last workgroup)."""
+    rng = np.random.default_rng(seed)
+    inner = 1 + rng.choice(max(nblk - 2, 0), min(max(nblk - 2, 0), count - 2), replace=False)
+    return np.unique(np.concatenate([[0, nblk - 1], inner]))
+
+
 def test_encoders_full_size_sampled(G):
     """1,048,576 primitives, all 16 bands in BC1 and in BC7 (1,048,576 blocks
-    per format) in the launch the benchmark times; sampled blocks against the
+    per format) in the launch the benchmark times; 1,024 blocks of every band
+    of both formats (each band's first and last block included) against the
     oracle, and each band's reported SSE against the GPU's own decode."""
     gsbc, ctx = G
     c = synth.CONFIGS["mid"]
     pos, sh = synth.make_scene(c["n"], c["clusters"], c["comps"], c["seed"])
     _, rtex, _, _ = O.reorder(pos, sh)
     nblk = rtex.shape[1]
-    rng = np.random.default_rng(0)
-    pick = np.sort(rng.choice(nblk, 48, replace=False))
-    pick = np.concatenate([[0], pick, [nblk - 1]])
     texd = dev(rtex)
     for fmt in (1, 7):
         say("full-size encode", fmt)
@@ -321,11 +327,13 @@ def test_encoders_full_size_sampled(G):
         blocks, d, sse = ctx.encode(texd, d, fmt=fmt, want_sse=True)
         hb = host(blocks)
         bs = 8 if fmt == 1 else 16
-        for b in (0, 1, 5, 15):
+        for b in range(16):
+            pick = _sample_blocks(nblk, 1024, 100 * fmt + b)
+            assert pick.size == 1024
             o = int(d.offsets()[b])
             stream = hb[o:o + nblk * bs].reshape(nblk, bs)
             ref = O.bc1_encode(rtex[b][pick])[0] if fmt == 1 else O.bc7_encode(rtex[b][pick])[0]
-            assert np.array_equal(stream[pick], ref), f"band {b}"
+            assert np.array_equal(stream[pick], ref), f"format {fmt} band {b}"
         dec = ctx.decode(blocks, d)
         diff = dec[..., :3].to(torch.int64) - texd[..., :3].to(torch.int64)
         err = (diff * diff).sum(dim=(1, 2, 3)).cpu().numpy()
@@ -614,8 +622,11 @@ def test_decode_eval_large_sampled(G):
     """3,145,728 primitives, 256 clusters, 1,024 view directions in one launch
     (38.7 GB of output).  Band 0 BC7, bands 1..15 BC1 (rate 4.25, where the
     format choice is fixed); sampled outputs against the FP64 oracle on
-    oracle-encoded blocks.  Then the 6 bits/texel choice: exactly 8 BC7
-    bands, exact payload, and the k largest gains of the reported SSEs."""
+    oracle-encoded blocks.  Then the 6 bits/texel payload: the band SSE
+    totals of both formats equal the GPU's decode of whole payloads, the
+    format choice equals the oracle's rate selector on those totals, the
+    payload is exactly 6 bits/texel, and 256 blocks of every band match the
+    oracle's encoder in the chosen format."""
     gsbc, ctx = G
     c = synth.CONFIGS["large"]
     pos, sh = synth.make_scene(c["n"], c["clusters"], c["comps"], c["seed"])
@@ -639,15 +650,40 @@ def test_decode_eval_large_sampled(G):
     _check_colours(sub, ref, scale)
 
     say("large rate 6")
+    # the rate choice rests on the two formats' band SSE totals: each total
+    # equals the GPU's own decode of that format's whole payload, and the
+    # choice is the oracle's rate selector applied to those totals
     blocks6, d6, sse = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=c["rate"], want_sse=True)
     f6 = d6.formats()
+    for fi, fmt_all in enumerate((1, 7)):
+        dall = _desc_for(gsbc, c["n"], [fmt_all] * 16)
+        ball, dall, sall = ctx.encode(tex, dall, fmt=fmt_all, want_sse=True)
+        dec = ctx.decode(ball, dall)
+        del ball
+        diff = dec[..., :3].to(torch.int64) - tex[..., :3].to(torch.int64)
+        err = (diff * diff).sum(dim=(1, 2, 3)).cpu().numpy()
+        del dec, diff
+        k0 = 1 if fmt_all == 1 else 0        # AUTO never codes band 0 in BC1
+        assert np.array_equal(err[k0:], sall[fi][k0:]), fmt_all
+        assert np.array_equal(sse[fi][k0:], sall[fi][k0:]), fmt_all
+    torch.cuda.empty_cache()
+    assert np.array_equal(d6.ranges()[0].view(np.uint32), vmin.view(np.uint32))
+    assert np.array_equal(d6.ranges()[1].view(np.uint32), vmax.view(np.uint32))
+    want = O.rate_select(sse[0], sse[1], vmin, vmax, c["rate"])
+    assert want is not None and np.array_equal(f6, want)
     assert f6[0] == 7 and (f6 == 7).sum() == 8
     nblk = d6.blocks_per_stream
     assert sum(nblk * (64 if f == 1 else 128) for f in f6) == 6 * 16 * 16 * nblk
-    delta = np.array([np.float32((d6.vmax[k] - d6.vmin[k]) / np.float32(255.0)) for k in range(16)], np.float64)
-    gain = (sse[0] - sse[1]).astype(np.float64) * delta * delta
-    order = sorted(range(1, 16), key=lambda k: (-gain[k], k))
-    assert set(np.nonzero(f6[1:] == 7)[0] + 1) == set(order[:7])
+    assert np.array_equal(host(tex), rtex)
+    # every band of the payload in its chosen format, 256 blocks each (first
+    # and last included), against the oracle's encoder
+    hb = host(blocks6)
+    for k in range(16):
+        pick = _sample_blocks(nblk, 256, 300 + k)
+        bs = 8 if f6[k] == 1 else 16
+        stream = hb[int(d6.offsets()[k]):int(d6.offsets()[k]) + nblk * bs].reshape(nblk, bs)
+        ref = O.bc1_encode(rtex[k][pick])[0] if f6[k] == 1 else O.bc7_encode(rtex[k][pick])[0]
+        assert np.array_equal(stream[pick], ref), f"band {k} format {f6[k]}"
 
 
 def test_injected_scratch_allocation_failure():
