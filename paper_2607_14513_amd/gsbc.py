@@ -180,12 +180,25 @@ def _dev_tensor(t, dtype, name, shape=None, min_numel=None):
 
 
 def _desc_numbers(desc):
-    """(n_streams, blocks_per_stream, payload_bytes, n_prims) of a descriptor,
-    with the stream count bounded so that sizes derived from it are sane."""
-    S, nblk = int(desc.n_streams), int(desc.blocks_per_stream)
-    if not 1 <= S <= 16:
-        raise ValueError(f"desc.n_streams = {S} not in 1..16")
-    return S, nblk, int(desc.payload_bytes), int(desc.n_prims)
+    """(n_streams, blocks_per_stream, payload_bytes, n_prims) of a descriptor
+    whose sizes agree with each other, else None: the library rejects such a
+    descriptor itself (GSBC_E_ARG) before anything is enqueued, so sizes
+    derived from it are not checked here."""
+    if not isinstance(desc, StreamDesc):
+        raise TypeError("desc must be a StreamDesc")
+    S, nblk, n, npad = int(desc.n_streams), int(desc.blocks_per_stream), int(desc.n_prims), int(desc.n_pad)
+    arr = int(desc.arrangement)
+    allowed = {ARR_BANDS: (1, 4, 9, 16), ARR_PRIM: (1,), ARR_QUAD: (1, 4)}.get(arr, ())
+    per_block = {ARR_BANDS: 16, ARR_PRIM: 1, ARR_QUAD: 4}.get(arr, 0)
+    if S not in allowed or n < 1 or npad != (n + 15) // 16 * 16 or nblk * N_STREAMS[arr] != npad or per_block == 0:
+        return None
+    return S, nblk, int(desc.payload_bytes), n
+
+
+def _sizes(desc):
+    """Expected sizes of a consistent descriptor, or a tuple of None."""
+    r = _desc_numbers(desc)
+    return r if r is not None else (None, None, None, None)
 
 
 class Context:
@@ -312,8 +325,8 @@ class Context:
     def encode(self, textures, desc, fmt=FMT_AUTO, rate=6.0, params=None, blocks=None, want_sse=False):
         """Encode all streams -> (blocks uint8 device tensor, desc, band_sse int64[2][16] or None).
         fmt FMT_BANDS codes stream k in desc.format[k] (set by the caller)."""
-        S, nblk, _, _ = _desc_numbers(desc)
-        _check(textures, torch.uint8, "textures", min_numel=S * nblk * 64)
+        S, nblk, _, _ = _sizes(desc)
+        _check(textures, torch.uint8, "textures", min_numel=S * nblk * 64 if S else None)
         desc = desc.copy()
         if blocks is None:
             _, cap, _ = query_sizes(desc.n_prims)
@@ -336,8 +349,8 @@ class Context:
         if not (n == len(descs) == len(blocks)):
             raise ValueError("textures, descs and blocks differ in length")
         for i, t in enumerate(textures):
-            S, nblk, _, _ = _desc_numbers(descs[i])
-            _dev_tensor(t, torch.uint8, f"textures[{i}]", min_numel=S * nblk * 64)
+            S, nblk, _, _ = _sizes(descs[i])
+            _dev_tensor(t, torch.uint8, f"textures[{i}]", min_numel=S * nblk * 64 if S else None)
             _dev_tensor(blocks[i], torch.uint8, f"blocks[{i}]")
         tp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in textures])
         bp = (ctypes.c_void_p * n)(*[b.data_ptr() for b in blocks])
@@ -354,13 +367,18 @@ class Context:
         return out, (sse.reshape(n, 16) if sse is not None else None)
 
     def decode_eval_view(self, blocks, desc, pos, perm, view, prim_idx=None, out=None):
-        """pos float32[n][3] (input order) and perm int32[n] on the device, view
-        3 floats (host) -> out float32[m][3]: each slot's colour seen from view."""
-        _, _, payload, n = _desc_numbers(desc)
+        """pos float32[N][3] (the scene in input order) and perm int32[n_prims]
+        on the device (every perm value below N), view 3 floats (host) ->
+        out float32[m][3]: each slot's colour seen from view."""
+        _, _, payload, n = _sizes(desc)
         _check(blocks, torch.uint8, "blocks", min_numel=payload)
-        _check(pos, torch.float32, "pos", shape=(n, 3))
-        _check(perm, torch.int32, "perm", shape=(n,))
-        m = n if prim_idx is None else prim_idx.numel()
+        # pos holds the whole scene in input order (a degree class reads
+        # the rows its perm names), so it is at least as long as the slots
+        _check(pos, torch.float32, "pos")
+        if pos.dim() != 2 or pos.shape[1] != 3 or (n and pos.shape[0] < n):
+            raise ValueError(f"pos has shape {tuple(pos.shape)}, expected (N, 3) with N >= {n}")
+        _check(perm, torch.int32, "perm", shape=(n,) if n else None)
+        m = int(desc.n_prims) if prim_idx is None else prim_idx.numel()
         if prim_idx is not None:
             _check(prim_idx, torch.int32, "prim_idx", shape=(m,))
         if out is None:
@@ -374,7 +392,7 @@ class Context:
 
     def save(self, path, blocks, desc):
         """Write the coded scene (device blocks + desc) as a container file."""
-        _dev_tensor(blocks, torch.uint8, "blocks", min_numel=_desc_numbers(desc)[2])
+        _dev_tensor(blocks, torch.uint8, "blocks", min_numel=_sizes(desc)[2])
         self._check(load().gsbc_save(self._h, _ptr(blocks), ctypes.byref(desc), os.fsencode(path)))
 
     def load(self, path):
@@ -386,11 +404,12 @@ class Context:
 
     def decode(self, blocks, desc, out=None):
         """blocks (device payload) -> textures uint8[n_streams][blocks_per_stream][16][4]."""
-        S, nblk, payload, _ = _desc_numbers(desc)
+        S, nblk, payload, _ = _sizes(desc)
         _check(blocks, torch.uint8, "blocks", min_numel=payload)
         if out is None:
-            out = torch.empty((S, nblk, 16, 4), dtype=torch.uint8, device=self.device)
-        _check(out, torch.uint8, "out", shape=(S, nblk, 16, 4))
+            out = torch.empty((int(desc.n_streams), int(desc.blocks_per_stream), 16, 4), dtype=torch.uint8,
+                              device=self.device)
+        _check(out, torch.uint8, "out", shape=(S, nblk, 16, 4) if S else None)
         _on_device(("blocks", blocks), ("out", out))
         self._check(load().gsbc_decode(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(out)))
         return out
@@ -398,12 +417,12 @@ class Context:
     def decode_eval(self, blocks, desc, dirs, prim_idx=None, out=None):
         """dirs float32[V][3] device; prim_idx int32[m] sorted-slot ids or None
         -> out float32[V][m][3]."""
-        _, _, payload, n = _desc_numbers(desc)
+        _, _, payload, n = _sizes(desc)
         _check(blocks, torch.uint8, "blocks", min_numel=payload)
         _check(dirs, torch.float32, "dirs")
         V = dirs.shape[0] if dirs.dim() == 2 else -1
         _check(dirs, torch.float32, "dirs", shape=(V, 3))
-        m = n if prim_idx is None else prim_idx.numel()
+        m = int(desc.n_prims) if prim_idx is None else prim_idx.numel()
         if prim_idx is not None:
             _check(prim_idx, torch.int32, "prim_idx", shape=(m,))
         if out is None:

@@ -56,10 +56,19 @@ def test_mix_equals_alone(pool):
 
 def test_budget_admission_and_eviction(pool):
     from paper_2607_14513_amd import serve
-    reqs = _reqs(serve, 24, 5000.0, seed=22, n_hi=40_000, v_hi=16)
+    reqs = serve.make_requests(32, 5000.0, seed=22, n_lo=20_000, n_hi=40_000, v_lo=1, v_hi=16, pool_n=POOL)
     # one oversized decode (needs more than the whole budget) among them
     reqs.append(serve.Request(len(reqs), serve.DECODE, reqs[-1].arrival + 1e-3, v=4000))
-    budget = 8e6        # an encode needs up to ~6 MB: resident scenes must be evicted
+    budget = 6e6
+    enc = [r for r in reqs if r.kind == serve.ENCODE]
+    # every encode fits the budget alone, but their resident payloads
+    # together do not: since all encodes must succeed, idle scenes have to be
+    # evicted whatever the timing (payload at 6 bits/texel: 8 BC7 streams of
+    # 16 B and 8 BC1 streams of 8 B per block, each stream 16-byte aligned)
+    def payload(n):
+        nblk = (n + 15) // 16
+        return 8 * 16 * nblk + 8 * ((8 * nblk + 15) // 16 * 16)
+    assert max(serve.encode_bytes(r.n) for r in enc) <= budget < sum(payload(r.n) for r in enc)
     srv = serve.Server(*pool, slots=2, hbm_budget=budget)
     try:
         done = srv.run(reqs)
