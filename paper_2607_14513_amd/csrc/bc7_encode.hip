@@ -21,24 +21,27 @@
 #include "gsbc_internal.h"
 #include "bc_format.h"
 
+#include <mutex>
 #include <vector>
 
 namespace gsbc {
 
-// (-32, -32) as packed 16-bit lanes, read from memory (external linkage, so
-// it is not folded) so that the palette scaling is one packed multiply by a
-// scalar register; a literal -32 becomes a shift and a negation.
-__constant__ uint32_t g_bc7_neg32_pair = 0xFFE0FFE0u;
+// Zero, read from memory (external linkage, so it is not folded): see
+// entry_const.
+__constant__ uint32_t g_bc7_opaque_zero = 0u;
 
 namespace {
 
 // ---- tables (device global memory, built on the host at first use)
 // nearest[cls][p][t]: code c minimising |value(c, p) - t| (lowest on ties)
 // in the low byte, value(c, p) in the high byte; cls = (cb - 4) * 2 + has_pbit.
+// near64[cls][p][t]: 64 value(c, p) of the same code (the search reads only
+// values, in the scale its palette entries use).
 // sv[cls][p0 + 2 p1][slot][v]: single-value pair (c0 | c1 << 8 | err << 16)
 // whose interpolation at weight(nb, K) is nearest v; slot = nb offset + K.
 struct Tables {
     const uint16_t *nearest;
+    const uint16_t *near64;
     const uint32_t *sv;
 };
 constexpr int kSlots = 28;
@@ -82,51 +85,64 @@ __device__ __forceinline__ void candidate(int ci, int &m, int &p, int &r, int &s
 
 // ---- texels in LDS
 //
-// Texels sit in LDS, one column per lane: rg = 16 R | 16 G << 16 and
-// bx = B.  Because |x|^2 is the same for every palette entry, the least-SSE
-// entry is the least 256 (|p|^2 - 2 x.p) + k, so with each entry held as
-// (-32 pR, -32 pG), -512 pB and 256 |p|^2 + k one texel x entry evaluation is
-// three VALU ops:
-//   t = B * (-512 pB) + (256 |p|^2 + k)            (v_mad_i32_i24)
-//   t = 16 R * (-32 pR) + 16 G * (-32 pG) + t      (v_dot2c_i32_i16)
-//   best = min(best, t)                            (v_min_i32)
+// Texels sit in LDS, one column per lane, scaled by -8: rg holds -8 R and
+// -8 G as 16-bit halves, bx holds -8 B.  Because |x|^2 is the same for every
+// palette entry, the least-SSE entry is the least 256 (|p|^2 - 2 x.p) + k.
+// Each entry is held as E = (64 pR, 64 pG) in 16-bit halves, Eb = 64 pB and
+// C = 256 |p|^2 + k, so one texel x entry evaluation is
+//   t = (-8 B) * Eb + C                    (v_mad_i32_i24)
+//   t = (-8 R, -8 G) . E + t               (v_dot2c_i32_i16)
+//   best = min(best, t)                    (half a v_min3_i32)
 // and the members' minima plus 256 sum |x|^2 (taken once per subset from
 // its sums) give 256 SSE + sum k exactly (all terms stay within int32:
-// |t| < 2^26).  Summed over at most 16 members the k terms stay below 256,
-// so the subset SSE is the sum shifted right by 8.
+// |t| < 2^27).  Summed over at most 16 members the k terms stay below 256,
+// so the subset SSE is the sum shifted right by 8.  The 64-scaled entries
+// are what the interpolation (64 - w) e0 + w e1 + 32 yields once its low six
+// bits are masked off, which keeps palette construction short.
 // In the search the subset masks are wave-uniform, so texel loops walk the
 // set bits of a mask with scalar control.
 constexpr int kWG = 256;
 constexpr int kQEntries = 10 * 2 * 256;
+constexpr int kScaleNeg = -8;          // texel scale in LDS
 
 struct TexLds {
     uint32_t rg[16][kWG];
-    uint32_t bx[16][kWG];
-    uint16_t q[kQEntries];        // nearest-code table: code | value << 8
+    int32_t bx[16][kWG];
+    uint16_t q[kQEntries];        // search: near64; emit: nearest
 };
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 
-// Texel i of this lane: packed 16 R | 16 G << 16 and B; rotation r puts
-// 255 in channel r-1.
+// -8 times the value 255 (a rotated-out channel's replacement)
+constexpr int kNeg255 = kScaleNeg * 255;
+
+// Texel i of this lane in the LDS layout; rotation r puts 255 in channel r-1.
 __device__ __forceinline__ void texel(const TexLds &S, int i, int rot, uint32_t &rg, int &b)
 {
     rg = S.rg[i][threadIdx.x];
-    b = (int)S.bx[i][threadIdx.x];
+    b = S.bx[i][threadIdx.x];
     if (rot) {
-        int r = (int)__builtin_amdgcn_ubfe(rg, 4, 8), g = (int)(rg >> 20);
-        if (rot == 1) r = 255;
-        else if (rot == 2) g = 255;
-        else b = 255;
-        rg = (uint32_t)(16 * r) | ((uint32_t)(16 * g) << 16);
+        if (rot == 1) rg = (rg & 0xFFFF0000u) | ((uint32_t)kNeg255 & 0xFFFFu);
+        else if (rot == 2) rg = (rg & 0xFFFFu) | ((uint32_t)kNeg255 << 16);
+        else b = kNeg255;
     }
+}
+
+// The texel's channels, negated: (-R, -G, -B) (exact: the stored values are
+// multiples of 8).
+__device__ __forceinline__ void unpack_neg(uint32_t rg, int b, int (&x)[3])
+{
+    x[0] = __builtin_amdgcn_sbfe((int)rg, 3, 13);
+    x[1] = (int)rg >> 19;
+    x[2] = b >> 3;
 }
 
 __device__ __forceinline__ void unpack(uint32_t rg, int b, int (&x)[3])
 {
-    x[0] = (int)__builtin_amdgcn_ubfe(rg, 4, 8);
-    x[1] = (int)(rg >> 20);
-    x[2] = b;
+    unpack_neg(rg, b, x);
+    x[0] = -x[0];
+    x[1] = -x[1];
+    x[2] = -x[2];
 }
 
 // Per-subset data shared across modes: whether every member is the same
@@ -135,17 +151,17 @@ __device__ __forceinline__ void unpack(uint32_t rg, int b, int (&x)[3])
 struct Prep {
     bool same;
     int lo[3], hi[3];
-    int Sx[3];   // member sums per channel (for the least-squares refit)
+    int nSx[3];  // negated member sums per channel (for the least-squares refit)
     int xx;      // sum of |x|^2 over the members
 };
 
-// Member sums of a subset: count, per-channel sums and the six distinct
-// products (RR, RG, RB, GG, GB, BB).  Integer, so the sums of disjoint
-// subsets add up exactly: the last subset of a partition is the block total
-// minus the others.
+// Member sums of a subset: count, negated per-channel sums and the six
+// distinct products (RR, RG, RB, GG, GB, BB; the same for negated values).
+// Integer, so the sums of disjoint subsets add up exactly: the last subset
+// of a partition is the block total minus the others.
 struct Sums {
     int n;
-    int Sx[3];
+    int nSx[3];
     int XX[6];
 };
 
@@ -153,25 +169,25 @@ __device__ __forceinline__ Sums subset_sums(const TexLds &S, uint32_t mask, int 
 {
     Sums m;
     m.n = __popc(mask);
-    m.Sx[0] = m.Sx[1] = m.Sx[2] = 0;
+    m.nSx[0] = m.nSx[1] = m.nSx[2] = 0;
 #pragma unroll
     for (int q = 0; q < 6; q++) m.XX[q] = 0;
-    // R and G summed in the halves of one word: 16 R and 16 G over at most
-    // 16 members stay below 2^16
-    uint32_t srg = 0;
+    // -8 R and -8 G summed in the 16-bit halves of one word (at most 16
+    // members: |sum| <= 32640)
+    short2_t srg = {0, 0};
     for (uint32_t mm = mask; mm; mm &= mm - 1) {
         uint32_t rg;
         int b;
         texel(S, __ffs(mm) - 1, rot, rg, b);
         int x[3];
-        unpack(rg, b, x);
-        srg += rg;
-        m.Sx[2] += x[2];
-        m.XX[0] += x[0] * x[0]; m.XX[1] += x[0] * x[1]; m.XX[2] += x[0] * x[2];
-        m.XX[3] += x[1] * x[1]; m.XX[4] += x[1] * x[2]; m.XX[5] += x[2] * x[2];
+        unpack_neg(rg, b, x);
+        srg += __builtin_bit_cast(short2_t, rg);
+        m.nSx[2] += x[2];
+        m.XX[0] += mul_i24(x[0], x[0]); m.XX[1] += mul_i24(x[0], x[1]); m.XX[2] += mul_i24(x[0], x[2]);
+        m.XX[3] += mul_i24(x[1], x[1]); m.XX[4] += mul_i24(x[1], x[2]); m.XX[5] += mul_i24(x[2], x[2]);
     }
-    m.Sx[0] = (int)((srg & 0xFFFFu) >> 4);
-    m.Sx[1] = (int)(srg >> 20);
+    m.nSx[0] = (int)srg.x >> 3;
+    m.nSx[1] = (int)srg.y >> 3;
     return m;
 }
 
@@ -180,29 +196,29 @@ __device__ __forceinline__ Sums sums_minus(const Sums &t, const Sums &a)
     Sums m;
     m.n = t.n - a.n;
 #pragma unroll
-    for (int c = 0; c < 3; c++) m.Sx[c] = t.Sx[c] - a.Sx[c];
+    for (int c = 0; c < 3; c++) m.nSx[c] = t.nSx[c] - a.nSx[c];
 #pragma unroll
     for (int q = 0; q < 6; q++) m.XX[q] = t.XX[q] - a.XX[q];
     return m;
 }
 
 // Principal axis and endpoint texels of a subset from its sums.  The exact
-// covariance C = n XX - Sx Sx^T is zero exactly when every member has the
-// same colour.
+// covariance C = n XX - Sx Sx^T (the same from negated sums) is zero exactly
+// when every member has the same colour.
 __device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int rot, const Sums &m)
 {
     Prep P;
-    // n <= 16, XX < 2^21 and Sx < 2^12: 24-bit multiplies with exact products
+    // n <= 16, XX < 2^21 and |Sx| < 2^12: 24-bit multiplies with exact products
     const int n = m.n;
     int C[3][3];
-    C[0][0] = __mul24(n, m.XX[0]) - __mul24(m.Sx[0], m.Sx[0]);
-    C[0][1] = C[1][0] = __mul24(n, m.XX[1]) - __mul24(m.Sx[0], m.Sx[1]);
-    C[0][2] = C[2][0] = __mul24(n, m.XX[2]) - __mul24(m.Sx[0], m.Sx[2]);
-    C[1][1] = __mul24(n, m.XX[3]) - __mul24(m.Sx[1], m.Sx[1]);
-    C[1][2] = C[2][1] = __mul24(n, m.XX[4]) - __mul24(m.Sx[1], m.Sx[2]);
-    C[2][2] = __mul24(n, m.XX[5]) - __mul24(m.Sx[2], m.Sx[2]);
+    C[0][0] = __mul24(n, m.XX[0]) - __mul24(m.nSx[0], m.nSx[0]);
+    C[0][1] = C[1][0] = __mul24(n, m.XX[1]) - __mul24(m.nSx[0], m.nSx[1]);
+    C[0][2] = C[2][0] = __mul24(n, m.XX[2]) - __mul24(m.nSx[0], m.nSx[2]);
+    C[1][1] = __mul24(n, m.XX[3]) - __mul24(m.nSx[1], m.nSx[1]);
+    C[1][2] = C[2][1] = __mul24(n, m.XX[4]) - __mul24(m.nSx[1], m.nSx[2]);
+    C[2][2] = __mul24(n, m.XX[5]) - __mul24(m.nSx[2], m.nSx[2]);
     P.same = (C[0][0] | C[1][1] | C[2][2]) == 0;
-    P.Sx[0] = m.Sx[0]; P.Sx[1] = m.Sx[1]; P.Sx[2] = m.Sx[2];
+    P.nSx[0] = m.nSx[0]; P.nSx[1] = m.nSx[1]; P.nSx[2] = m.nSx[2];
     P.xx = m.XX[0] + m.XX[3] + m.XX[5];
     if (P.same) {
         uint32_t rg;
@@ -238,35 +254,35 @@ __device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int 
         // accumulated into by the dot product of the first two
 #pragma unroll
         for (int a = 0; a < 3; a++) u[a] = __builtin_amdgcn_sdot2(c01[a], v01, __mul24(Cs[a][2], v[2]), false);
-        // max |u_a| as max(max u, -min u): two three-way operations
-        const int mx = max(max(u[0], max(u[1], u[2])), -min(u[0], min(u[1], u[2])));
-        // bitlen(mx) - 15, with mx | 1 so that the count is defined at 0
-        int sh = max(0, 17 - __builtin_clz((uint32_t)mx | 1u));
+        // max(max |u_a|, 1) as max(max u, -min u, 1): its bit length minus 15,
+        // at least 0, is the shift that brings max |v| below 2^15
+        const int mx = max(max(u[0], max(u[1], u[2])), max(-min(u[0], min(u[1], u[2])), 1));
+        const uint32_t sh = __builtin_elementwise_sub_sat(17u, (uint32_t)__builtin_clz((uint32_t)mx));
 #pragma unroll
         for (int a = 0; a < 3; a++) v[a] = u[a] >> sh;
     }
     if (v[0] == 0 && v[1] == 0 && v[2] == 0) v[0] = v[1] = v[2] = 1;
-    // members of least and greatest projection, the first of each on ties:
-    // keys 16 p + i and 16 p + 15 - i (|16 p| < 2^29), from the 16x-scaled
-    // packed texels in two operations
+    // members of least and greatest projection p, the first of each on ties.
+    // The stored texels give q = -8 p in one dot product and one multiply-add
+    // (|q| < 2^28); 2 q = -16 p leaves four low bits for the member index:
+    // the largest 2q + 15 - i is the least p (first i), the least 2q + i is
+    // the greatest p (first i).
     const short2_t v01 = {(short)v[0], (short)v[1]};
-    const int v2x16 = 16 * v[2];
-    int klo = 0x7FFFFFFF, khi = (int)0x80000000;
+    int klo = (int)0x80000000, khi = 0x7FFFFFFF;
     for (uint32_t mm = mask; mm; mm &= mm - 1) {
         const int i = __ffs(mm) - 1;
         uint32_t rg;
         int b;
         texel(S, i, rot, rg, b);
-        // 16 p + i in one multiply-add and one dot product
-        const int pi = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg), v01, __mul24(b, v2x16) + i, false);
-        klo = min(klo, pi);
-        khi = max(khi, pi + (15 - 2 * i));
+        const int q = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg), v01, mul_i24(b, v[2]), false);
+        klo = max(klo, 2 * q + (15 - i));
+        khi = min(khi, 2 * q + i);
     }
     uint32_t rg;
     int b;
-    texel(S, klo & 15, rot, rg, b);
+    texel(S, 15 - (klo & 15), rot, rg, b);
     unpack(rg, b, P.lo);
-    texel(S, 15 - (khi & 15), rot, rg, b);
+    texel(S, khi & 15, rot, rg, b);
     unpack(rg, b, P.hi);
     return P;
 }
@@ -277,8 +293,9 @@ __device__ __forceinline__ Prep prep_subset(const TexLds &S, uint32_t mask, int 
 }
 
 // Result of fitting one endpoint pair to a subset.  eval_pair leaves idx in
-// member order (4 bits per member, first member lowest); fit_colour returns
-// it by texel position (4 bits at 4 i for member i).
+// member order (IW bits per member, first member lowest; IW = 2 for 2-bit
+// indices, else 4); fit_colour returns it by texel position (4 bits at 4 i
+// for member i).
 struct PairFit {
     uint32_t sse;
     uint64_t idx;
@@ -286,23 +303,68 @@ struct PairFit {
     int p0, p1;
 };
 
+template <int NB>
+constexpr int idx_width() { return NB == 2 ? 2 : 4; }
+
+// Zero, read from memory: added to a constant whose low bits the compiler
+// can prove clear of the product it joins, it keeps the sum an addition, so
+// product and sum fuse into one v_mad_u32_u24 instead of a multiply and an or.
+
+// Palette entry constant C = 256 |p|^2 + k from the 64-scaled entry:
+// (64 p) . (64 p) + 16 k = 16 C, exactly.  The opaque zero keeps 16 k an
+// addition (its bits are provably clear of the product's, which would turn
+// it into an or), so product and sum fuse into one v_mad_u32_u24.
+__device__ __forceinline__ int entry_const(uint32_t e, int eb, int k)
+{
+    const short2_t es = __builtin_bit_cast(short2_t, e);
+    const uint32_t b2k = mul_u24((uint32_t)eb, (uint32_t)eb) + (16u * (uint32_t)k + g_bc7_opaque_zero);
+    return __builtin_amdgcn_sdot2(es, es, (int)b2k, false) >> 4;
+}
+
 // (c) for one endpoint pair: quantise for every p-bit combination, index
 // every member by least SSE; keep the best combination (lowest on ties).
 // Up to 32 palette entries are held at once, so each member is read once
-// for all combinations (once per combination for 16-entry palettes).  Per member and combination the running sum
-// takes 256 SSE + k in one add and the index enters a 64-bit shift register
-// (newest member at the top; the register holds the n indices in its top
-// 4 n bits).  IDX = false: the SSE only (the indices are not kept).
-template <int CB, int PB, int NB, bool IDX = true>
+// for all combinations (once per combination for 16-entry palettes).  Per
+// member and combination the running sum takes 256 SSE + k in one add and
+// the index enters a shift register (newest member at the top; it holds the
+// n indices in its top IW n bits).  IDX = false: the SSE only.  CODES: the
+// LDS table holds code | value << 8 (the emit pass, which needs the codes);
+// otherwise it holds 64 value (the search).
+template <int CB, int PB, int NB, bool IDX, bool CODES>
 __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int rot, const int (&lo)[3],
                                              const int (&hi)[3], int xx)
 {
     constexpr int NPC = PB == 2 ? 4 : PB == 1 ? 2 : 1;
     constexpr int NE = 1 << NB;
     constexpr int CPV = NPC * NE <= 32 ? NPC : 1;   // combinations per member visit
+    constexpr int NP = PB ? 2 : 1;                  // p-bit values of an endpoint
+    constexpr int IW = idx_width<NB>();
+    constexpr bool WIDE = IW * 16 > 32;             // the indices need two words
     constexpr int cls = cls_of(CB, PB);
     const int n = __popc(mask);
-    const short2_t m32 = __builtin_bit_cast(short2_t, g_bc7_neg32_pair);
+    // each endpoint quantised for each p-bit value: E = (64 v_R, 64 v_G),
+    // Eb = 64 v_B, and the codes (emit)
+    uint32_t E[2][NP], code[2][NP];
+    int Eb[2][NP];
+#pragma unroll
+    for (int end = 0; end < 2; end++)
+#pragma unroll
+        for (int p = 0; p < NP; p++) {
+            const uint16_t *t = S.q + (cls * 2 + p) * 256;
+            const int *v = end ? hi : lo;
+            uint32_t e[3];
+#pragma unroll
+            for (int c = 0; c < 3; c++) e[c] = t[v[c]];
+            if (CODES) {
+                code[end][p] = (e[0] & 255u) | (e[1] & 255u) << 8 | (e[2] & 255u) << 16;
+#pragma unroll
+                for (int c = 0; c < 3; c++) e[c] = (e[c] >> 8) << 6;
+            } else {
+                code[end][p] = 0;
+            }
+            E[end][p] = e[0] | (e[1] << 16);
+            Eb[end][p] = (int)e[2];
+        }
     PairFit best;
     best.sse = 0xFFFFFFFFu;
     best.idx = 0;
@@ -310,42 +372,31 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
     best.p0 = best.p1 = 0;
 #pragma unroll
     for (int pc0 = 0; pc0 < NPC; pc0 += CPV) {
-        // palette entry k as (-32 pR, -32 pG) in 16-bit halves, -512 pB, 256 |p|^2 + k.
-        // Interpolation (64 - w) e0 + w e1 + 32 = (64 e0 + 32) + w (e1 - e0) stays
-        // within [32, 16352], so R and G are interpolated together in 16-bit lanes.
-        uint32_t prg[CPV][NE], c0[CPV], c1[CPV];
+        // Interpolation (64 - w) e0 + w e1 + 32 = (64 e0 + 32) + w (e1 - e0)
+        // stays within [32, 16352], so R and G are interpolated together in
+        // 16-bit lanes; masking its low six bits gives the 64-scaled entry.
+        uint32_t prg[CPV][NE];
         int pb[CPV][NE], pk[CPV][NE];
 #pragma unroll
         for (int j = 0; j < CPV; j++) {
             const int pc = pc0 + j;
             const int p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
             const int p1 = PB == 2 ? (pc >> 1) : PB == 1 ? pc : 0;
-            const uint16_t *q0 = S.q + (cls * 2 + p0) * 256, *q1 = S.q + (cls * 2 + p1) * 256;
-            int d0[3], d1[3];
-            c0[j] = c1[j] = 0;
-#pragma unroll
-            for (int c = 0; c < 3; c++) {
-                const uint32_t e0 = q0[lo[c]], e1 = q1[hi[c]];
-                d0[c] = (int)(e0 >> 8);
-                d1[c] = (int)(e1 >> 8);
-                c0[j] |= (e0 & 255u) << (8 * c);
-                c1[j] |= (e1 & 255u) << (8 * c);
-            }
-            const short2_t a_rg = {(short)(64 * d0[0] + 32), (short)(64 * d0[1] + 32)};
-            const short2_t s_rg = {(short)(d1[0] - d0[0]), (short)(d1[1] - d0[1])};
-            const int a_b = 64 * d0[2] + 32, s_b = d1[2] - d0[2];
+            const uint32_t E0 = E[0][p0], E1 = E[1][p1];
+            const int B0 = Eb[0][p0], B1 = Eb[1][p1];
+            const short2_t a_rg = __builtin_bit_cast(short2_t, E0 | 0x00200020u);
+            const short2_t s_rg = (__builtin_bit_cast(short2_t, E1) - __builtin_bit_cast(short2_t, E0)) >> (short)6;
+            const int a_b = B0 | 32, s_b = (B1 - B0) >> 6;
 #pragma unroll
             for (int k = 0; k < NE; k++) {
                 // entries 0 and NE-1 are the endpoints themselves (weights 0 and 64)
                 const short w = (short)bc7_weight(NB, k);
-                const short2_t v = k == 0 ? short2_t{(short)d0[0], (short)d0[1]}
-                                 : k == NE - 1 ? short2_t{(short)d1[0], (short)d1[1]}
-                                               : (a_rg + s_rg * w) >> (short)6;
-                const int bb = k == 0 ? d0[2] : k == NE - 1 ? d1[2]
-                                      : (int)__builtin_amdgcn_ubfe((uint32_t)(a_b + s_b * w), 6, 8);
-                prg[j][k] = __builtin_bit_cast(uint32_t, v * m32);
-                pb[j][k] = -512 * bb;
-                pk[j][k] = 256 * __builtin_amdgcn_sdot2(v, v, __mul24(bb, bb), false) + k;
+                const uint32_t e = k == 0 ? E0 : k == NE - 1 ? E1
+                                 : __builtin_bit_cast(uint32_t, a_rg + s_rg * w) & 0xFFC0FFC0u;
+                const int eb = k == 0 ? B0 : k == NE - 1 ? B1 : (a_b + mul_i24(s_b, w)) & ~63;
+                prg[j][k] = e;
+                pb[j][k] = eb;
+                pk[j][k] = entry_const(e, eb, k);
             }
         }
         // 256 SSE + k summed over members: 256 |x|^2 added once per subset
@@ -369,13 +420,17 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
                     const int js = (PB == 2 && CPV == 4) ? (k == 0 ? (j & 1) : k == NE - 1 ? (j & 2) : j) : j;
                     const int key = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg),
                                                            __builtin_bit_cast(short2_t, prg[js][k]),
-                                                           __mul24(b, pb[js][k]) + pk[js][k], false);
+                                                           mul_i24(b, pb[js][k]) + pk[js][k], false);
                     kb = min(kb, key);
                 }
                 acc[j] += (uint32_t)kb;   // 256 (SSE - |x|^2) + k of this member
                 if (IDX) {
-                    rlo[j] = __builtin_amdgcn_alignbit(rhi[j], rlo[j], 4);
-                    rhi[j] = __builtin_amdgcn_alignbit((uint32_t)kb, rhi[j], 4);
+                    if (WIDE) {
+                        rlo[j] = __builtin_amdgcn_alignbit(rhi[j], rlo[j], IW);
+                        rhi[j] = __builtin_amdgcn_alignbit((uint32_t)kb, rhi[j], IW);
+                    } else {
+                        rlo[j] = __builtin_amdgcn_alignbit((uint32_t)kb, rlo[j], IW);
+                    }
                 }
             }
         }
@@ -384,12 +439,16 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
             const uint32_t sse = acc[j] >> 8;
             if (sse < best.sse) {
                 const int pc = pc0 + j;
+                const int p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
+                const int p1 = PB == 2 ? (pc >> 1) : PB == 1 ? pc : 0;
                 best.sse = sse;
-                best.idx = IDX ? (((uint64_t)rhi[j] << 32) | rlo[j]) >> (64 - 4 * n) : 0;
-                best.c0 = c0[j];
-                best.c1 = c1[j];
-                best.p0 = PB == 2 ? (pc & 1) : PB == 1 ? pc : 0;
-                best.p1 = PB == 2 ? (pc >> 1) : PB == 1 ? pc : 0;
+                best.idx = !IDX ? 0
+                         : WIDE ? (((uint64_t)rhi[j] << 32) | rlo[j]) >> (64 - IW * n)
+                                : (uint64_t)(rlo[j] >> (32 - IW * n));
+                best.c0 = code[0][p0];
+                best.c1 = code[1][p1];
+                best.p0 = p0;
+                best.p1 = p1;
             }
         }
     }
@@ -406,12 +465,14 @@ __host__ __device__ constexpr uint32_t pack_weights(int nb, int first)
 static_assert(pack_weights(2, 0) == 0x402B1500u && pack_weights(3, 0) == 0x1B120900u &&
               pack_weights(3, 4) == 0x40372E25u, "BC7 weight tables");
 
+// Weight of the index in the low bits of f (the bits above are ignored).
 template <int NB>
-__device__ __forceinline__ int weight_of(int k)
+__device__ __forceinline__ int weight_of(uint32_t f)
 {
-    if (NB == 2) return (int)__builtin_amdgcn_perm(0u, pack_weights(2, 0), (uint32_t)k | 0x0C0C0C00u);
-    if (NB == 3) return (int)__builtin_amdgcn_perm(pack_weights(3, 4), pack_weights(3, 0), (uint32_t)k | 0x0C0C0C00u);
-    return bc7_weight(NB, k);
+    const uint32_t sel = (f & (NB == 2 ? 3u : 7u)) | 0x0C0C0C00u;
+    if (NB == 2) return (int)__builtin_amdgcn_perm(0u, pack_weights(2, 0), sel);
+    if (NB == 3) return (int)__builtin_amdgcn_perm(pack_weights(3, 4), pack_weights(3, 0), sel);
+    return bc7_weight(NB, (int)(f & 15u));
 }
 
 // (d) least-squares endpoints for the chosen indices; false if singular.
@@ -419,46 +480,54 @@ __device__ __forceinline__ int weight_of(int k)
 // count n, sum(w), sum(w^2), the channel sums Sx and sum(w x):
 //   A = 4096 n - 128 sum(w) + sum(w^2), B = sum(w^2), AB = 64 sum(w) - sum(w^2),
 //   SA = 64 Sx - SB.
+// The sums of w x are taken on the stored texels, -8 x, by 16-bit dot
+// products with (w, 0) and (0, w), so every channel sum carries the factor
+// -8; the right-hand sides are formed at that scale and the factor is taken
+// out exactly (a power of two) with the reciprocal.
 template <int NB>
-__device__ __forceinline__ bool ls_endpoints(const TexLds &S, uint32_t mask, int rot, uint64_t idx, const int (&Sx)[3],
+__device__ __forceinline__ bool ls_endpoints(const TexLds &S, uint32_t mask, int rot, uint64_t idx, const int (&nSx)[3],
                                              int (&lo)[3], int (&hi)[3])
 {
-    int W1 = 0, W2 = 0, SB[3] = {0, 0, 0};
-    for (uint32_t m = mask; m; m &= m - 1) {
-        const int i = __ffs(m) - 1;
+    constexpr int IW = idx_width<NB>();
+    int W1 = 0, W2 = 0, SB8[3] = {0, 0, 0};   // SB8 = -8 sum(w x)
+    uint32_t cur = (uint32_t)idx;
+    int j = 0;
+    for (uint32_t m = mask; m; m &= m - 1, j++) {
+        if (IW == 4 && j == 8) cur = (uint32_t)(idx >> 32);
         uint32_t rg;
         int b;
-        texel(S, i, rot, rg, b);
-        int x[3];
-        unpack(rg, b, x);
-        const int w = weight_of<NB>((int)(idx & 15));   // member order
-        idx >>= 4;
+        texel(S, __ffs(m) - 1, rot, rg, b);
+        const int w = weight_of<NB>(cur);   // member order
+        cur >>= IW;
         W1 += w;
-        W2 += w * w;
-#pragma unroll
-        for (int c = 0; c < 3; c++) SB[c] += w * x[c];
+        W2 += (int)mul_u24((uint32_t)w, (uint32_t)w);
+        SB8[0] = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg), __builtin_bit_cast(short2_t, (uint32_t)w),
+                                        SB8[0], false);
+        SB8[1] = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg),
+                                        __builtin_bit_cast(short2_t, (uint32_t)w << 16), SB8[1], false);
+        SB8[2] += mul_i24(b, w);
     }
     const int n = __popc(mask);
     const int A = 4096 * n - 128 * W1 + W2, B = W2, AB = 64 * W1 - W2;
-    int SA[3];
-#pragma unroll
-    for (int c = 0; c < 3; c++) SA[c] = 64 * Sx[c] - SB[c];
-    const double det = (double)A * (double)B - (double)AB * (double)AB;
+    const double det = fma((double)A, (double)B, -((double)AB * (double)AB));
     if (det == 0.0) return false;
     // 1/det in FP64 from the FP32 reciprocal and two Newton steps (within
-    // 2^-50), times 64 (exact) for the numerators' common factor
+    // 2^-50), times 64 (exact) for the numerators' common factor and -1/8
+    // (exact) for the texel scale
     double inv = (double)__builtin_amdgcn_rcpf((float)det);
     inv = fma(fma(-det, inv, 1.0), inv, inv);
-    inv = 64.0 * fma(fma(-det, inv, 1.0), inv, inv);
+    inv = -8.0 * fma(fma(-det, inv, 1.0), inv, inv);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-        // Exact numerators n = 64 m (m < 2^36).  floor(n/det + 1/2) is taken
-        // as floor(m * 64 inv + 1/2 + 2^-37): (2 n + det) / (2 det) is a
-        // multiple of 1/(2 det) >= 2^-33, and for |n/det| <= 512 the FP64
-        // error is below 2^-40, so the margin never moves the floor; larger
-        // quotients clamp to 0 or 255 either way.
-        const double m0 = (double)B * (double)SA[c] - (double)AB * (double)SB[c];
-        const double m1 = (double)A * (double)SB[c] - (double)AB * (double)SA[c];
+        // Exact numerators n = 64 m (|m| < 2^36), here formed as -8 m
+        // (|8 m| < 2^39, products and differences exact in FP64).
+        // floor(n/det + 1/2) is taken as floor(m * 64 inv + 1/2 + 2^-37):
+        // (2 n + det) / (2 det) is a multiple of 1/(2 det) >= 2^-33, and for
+        // |n/det| <= 512 the FP64 error is below 2^-40, so the margin never
+        // moves the floor; larger quotients clamp to 0 or 255 either way.
+        const double SA8 = (double)(512 * nSx[c] - SB8[c]);
+        const double m0 = fma((double)B, SA8, -((double)AB * (double)SB8[c]));
+        const double m1 = fma((double)A, (double)SB8[c], -((double)AB * SA8));
         // floor then clamp to [0, 255] equals clamp then truncate
         const double q0 = fma(m0, inv, 0.5 + 0x1p-37), q1 = fma(m1, inv, 0.5 + 0x1p-37);
         lo[c] = (int)fmin(fmax(q0, 0.0), 255.0);
@@ -468,14 +537,16 @@ __device__ __forceinline__ bool ls_endpoints(const TexLds &S, uint32_t mask, int
 }
 
 // Fit one colour subset with endpoint precision (CB, PB) and NB-bit indices.
-// SEARCH: only the SSE is wanted (the search pass); the refit's indices and
-// the positional index layout are skipped.
+// SEARCH: only the SSE is wanted (the search pass, whose LDS table holds 64-
+// scaled values); the refit's indices and the positional index layout are
+// skipped.
 template <int CB, int PB, int NB, bool SEARCH = false>
 __device__ __forceinline__ PairFit fit_colour(const TexLds &S, uint32_t mask, int rot, const Prep &P,
                                               const uint32_t *sv)
 {
     constexpr int NPC = PB == 2 ? 4 : PB == 1 ? 2 : 1;
     constexpr int cls = cls_of(CB, PB);
+    constexpr int IW = idx_width<NB>();
     if (P.same) {
         // (a) single value: best (p-bits, index) from the per-channel tables
         PairFit f;
@@ -512,18 +583,18 @@ __device__ __forceinline__ PairFit fit_colour(const TexLds &S, uint32_t mask, in
     }
     // (b) endpoints from the principal axis, (c) quantise and index,
     // (d) one least-squares refit kept only if strictly better
-    PairFit f = eval_pair<CB, PB, NB>(S, mask, rot, P.lo, P.hi, P.xx);
+    PairFit f = eval_pair<CB, PB, NB, true, !SEARCH>(S, mask, rot, P.lo, P.hi, P.xx);
     int rlo[3], rhi[3];
-    if (ls_endpoints<NB>(S, mask, rot, f.idx, P.Sx, rlo, rhi)) {
-        PairFit g = eval_pair<CB, PB, NB, !SEARCH>(S, mask, rot, rlo, rhi, P.xx);
+    if (ls_endpoints<NB>(S, mask, rot, f.idx, P.nSx, rlo, rhi)) {
+        PairFit g = eval_pair<CB, PB, NB, !SEARCH, !SEARCH>(S, mask, rot, rlo, rhi, P.xx);
         if (g.sse < f.sse) f = g;
     }
     if (SEARCH) return f;
     // member order -> texel positions
     uint64_t pos = 0, c = f.idx;
     for (uint32_t m = mask; m; m &= m - 1) {
-        pos |= (c & 15u) << (4 * (__ffs(m) - 1));
-        c >>= 4;
+        pos |= (c & ((1u << IW) - 1)) << (4 * (__ffs(m) - 1));
+        c >>= IW;
     }
     f.idx = pos;
     return f;
@@ -531,23 +602,25 @@ __device__ __forceinline__ PairFit fit_colour(const TexLds &S, uint32_t mask, in
 
 // Scalar channel of modes 4 and 5: the 16 values of channel r-1 (rotation
 // r > 0) or the constant 255 (r = 0); precision AB bits, NB-bit indices.
-template <int AB, int NB>
+// The values are taken negated from the stored texels; every sum below is
+// negated with them and the keys are unchanged.
+template <int AB, int NB, bool CODES>
 __device__ __forceinline__ PairFit fit_scalar(const TexLds &S, int rot, const uint32_t *sv)
 {
     constexpr int cls = cls_of(AB, 0);
-    auto value = [&](int i) {
+    auto nvalue = [&](int i) {
         const uint32_t rg = S.rg[i][threadIdx.x];
-        const int b = (int)(S.bx[i][threadIdx.x] & 255u);
-        return rot == 0 ? 255 : rot == 1 ? (int)__builtin_amdgcn_ubfe(rg, 4, 8) : rot == 2 ? (int)(rg >> 20) : b;
+        const int b = S.bx[i][threadIdx.x];
+        return rot == 0 ? -255 : rot == 1 ? __builtin_amdgcn_sbfe((int)rg, 3, 13) : rot == 2 ? (int)rg >> 19 : b >> 3;
     };
-    const int v0 = value(0);
-    int lo = v0, hi = v0;
+    const int v0 = nvalue(0);
+    int nlo = v0, nhi = v0;
     bool same = true;
     for (int i = 1; i < 16; i++) {
-        int v = value(i);
+        int v = nvalue(i);
         same &= v == v0;
-        lo = min(lo, v);
-        hi = max(hi, v);
+        nlo = min(nlo, v);
+        nhi = max(nhi, v);
     }
     PairFit best;
     best.sse = 0xFFFFFFFFu;
@@ -556,7 +629,7 @@ __device__ __forceinline__ PairFit fit_scalar(const TexLds &S, int rot, const ui
     best.p0 = best.p1 = 0;
     if (same) {
         for (int k = 0; k < (1 << NB); k++) {
-            const uint32_t ent = sv[((uint64_t)(cls * 4) * kSlots + slot_of(NB, k)) * 256 + v0];
+            const uint32_t ent = sv[((uint64_t)(cls * 4) * kSlots + slot_of(NB, k)) * 256 + (-v0)];
             const uint32_t er = ent >> 16;
             if (er * er < best.sse) {
                 best.sse = er * er;
@@ -568,43 +641,44 @@ __device__ __forceinline__ PairFit fit_scalar(const TexLds &S, int rot, const ui
         best.sse *= 16u;
         return best;
     }
-    int elo = lo, ehi = hi;
+    int elo = -nhi, ehi = -nlo;   // least and greatest value
     for (int pass = 0; pass < 2; pass++) {
         const uint32_t e0 = S.q[cls * 2 * 256 + elo], e1 = S.q[cls * 2 * 256 + ehi];
-        const int d0 = (int)(e0 >> 8), d1 = (int)(e1 >> 8);
-        // entry k as -32 p and 16 p^2 + k (see texel layout above)
+        const int d0 = CODES ? (int)(e0 >> 8) : (int)(e0 >> 6), d1 = CODES ? (int)(e1 >> 8) : (int)(e1 >> 6);
+        // entry k as 32 p (against the negated value) and 16 p^2 + k
         int pal[1 << NB], pk[1 << NB];
 #pragma unroll
         for (int k = 0; k < (1 << NB); k++) {
             const int pv = interp64(d0, d1, bc7_weight(NB, k));
-            pal[k] = -32 * pv;
+            pal[k] = 32 * pv;
             pk[k] = 16 * (int)__builtin_amdgcn_udot4((uint32_t)pv, (uint32_t)pv, 0u, false) + k;
         }
         uint32_t sse = 0;
         uint64_t idx = 0;
-        int A = 0, B = 0, AB2 = 0, SA = 0, SB = 0;
+        int A = 0, B = 0, AB2 = 0, nSA = 0, nSB = 0;
         for (int i = 0; i < 16; i++) {
-            const int x = value(i);
+            const int x = nvalue(i);
             int kmin = 0x7FFFFFFF;
 #pragma unroll
-            for (int k = 0; k < (1 << NB); k++) kmin = min(kmin, __mul24(x, pal[k]) + pk[k]);
+            for (int k = 0; k < (1 << NB); k++) kmin = min(kmin, mul_i24(x, pal[k]) + pk[k]);
             const uint32_t kb = (uint32_t)(kmin + 16 * x * x);   // 16 SSE + k
             sse += kb >> 4;
             idx |= (uint64_t)(kb & 15u) << (4 * i);
             const int w = bc7_weight(NB, (int)(kb & 15u)), a = 64 - w;
-            A += a * a; B += w * w; AB2 += a * w; SA += a * x; SB += w * x;
+            A += a * a; B += w * w; AB2 += a * w; nSA += a * x; nSB += w * x;
         }
         if (sse < best.sse) {
             best.sse = sse;
             best.idx = idx;
-            best.c0 = e0 & 255u;
-            best.c1 = e1 & 255u;
+            best.c0 = CODES ? e0 & 255u : 0u;
+            best.c1 = CODES ? e1 & 255u : 0u;
         }
         if (pass == 1) break;
         const double det = (double)A * (double)B - (double)AB2 * (double)AB2;
         if (det == 0.0) break;
-        double n0 = 64.0 * ((double)B * (double)SA - (double)AB2 * (double)SB);
-        double n1 = 64.0 * ((double)A * (double)SB - (double)AB2 * (double)SA);
+        // numerators of the positive values (the negated sums flip their sign)
+        double n0 = -64.0 * ((double)B * (double)nSA - (double)AB2 * (double)nSB);
+        double n1 = -64.0 * ((double)A * (double)nSB - (double)AB2 * (double)nSA);
         double q0 = floor(n0 / det + 0.5), q1 = floor(n1 / det + 0.5);
         elo = q0 < 0.0 ? 0 : (q0 > 255.0 ? 255 : (int)q0);
         ehi = q1 < 0.0 ? 0 : (q1 > 255.0 ? 255 : (int)q1);
@@ -684,13 +758,13 @@ __device__ __forceinline__ uint32_t search_group(const TexLds &S, uint32_t mode_
                 if (mode_mask & 0x10) {
                     uint32_t s0 = fit_colour<5, 0, 2, true>(S, 0xFFFFu, r, P, sv).sse;
                     uint32_t s1 = fit_colour<5, 0, 3, true>(S, 0xFFFFu, r, P, sv).sse;
-                    if (r) { s0 += fit_scalar<6, 3>(S, r, sv).sse; s1 += fit_scalar<6, 2>(S, r, sv).sse; }
+                    if (r) { s0 += fit_scalar<6, 3, false>(S, r, sv).sse; s1 += fit_scalar<6, 2, false>(S, r, sv).sse; }
                     consider(s0, 208 + 2 * r, best);
                     consider(s1, 209 + 2 * r, best);
                 }
                 if (mode_mask & 0x20) {
                     uint32_t s5 = fit_colour<7, 0, 2, true>(S, 0xFFFFu, r, P, sv).sse;
-                    if (r) s5 += fit_scalar<8, 2>(S, r, sv).sse;
+                    if (r) s5 += fit_scalar<8, 2, false>(S, r, sv).sse;
                     consider(s5, 216 + r, best);
                 }
             }
@@ -769,7 +843,7 @@ __device__ void emit_rotated(const TexLds &S, int r, int sel, const uint32_t *sv
     const Prep P = prep_subset(S, 0xFFFFu, r);
     PairFit fc = fit_colour<CB, 0, CNB>(S, 0xFFFFu, r, P, sv);
     anchor_fix<CNB>(fc, 0xFFFFu, 0);
-    PairFit fs = fit_scalar<AB, SNB>(S, r, sv);
+    PairFit fs = fit_scalar<AB, SNB, true>(S, r, sv);
     anchor_fix<SNB>(fs, 0xFFFFu, 0);
     w.put(1u << M, M + 1);
     w.put((uint32_t)r, 2);
@@ -826,14 +900,16 @@ struct Bc7Launch {
     WorkSplit w;
 };
 
-__device__ __forceinline__ void stage_table(TexLds &S, const Tables &T)
+// The nearest-code table into LDS: 64-scaled values for the search,
+// code | value << 8 for the emit pass.
+__device__ __forceinline__ void stage_table(TexLds &S, const uint16_t *table)
 {
     for (int q = threadIdx.x; q < kQEntries / 2; q += kWG)
-        reinterpret_cast<uint32_t *>(S.q)[q] = reinterpret_cast<const uint32_t *>(T.nearest)[q];
+        reinterpret_cast<uint32_t *>(S.q)[q] = reinterpret_cast<const uint32_t *>(table)[q];
 }
 
-// This lane's block (zeros when not live) as 4x-scaled packed texels in its
-// LDS column.  The caller brackets it with barriers.
+// This lane's block (zeros when not live) into its LDS column in the -8
+// scaled layout.  The caller brackets it with barriers.
 __device__ __forceinline__ void stage_texels(TexLds &S, const uint8_t *src, bool live)
 {
     uint32_t t[16];
@@ -849,9 +925,9 @@ __device__ __forceinline__ void stage_texels(TexLds &S, const uint8_t *src, bool
     }
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-        const uint32_t r = t[i] & 255u, g = (t[i] >> 8) & 255u, bb = (t[i] >> 16) & 255u;
-        S.rg[i][threadIdx.x] = (r << 4) | (g << 20);
-        S.bx[i][threadIdx.x] = bb;
+        const int r = (int)(t[i] & 255u), g = (int)((t[i] >> 8) & 255u), bb = (int)((t[i] >> 16) & 255u);
+        S.rg[i][threadIdx.x] = ((uint32_t)(kScaleNeg * r) & 0xFFFFu) | ((uint32_t)(kScaleNeg * g) << 16);
+        S.bx[i][threadIdx.x] = kScaleNeg * bb;
     }
 }
 
@@ -896,7 +972,7 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
     const EncodeArgs &a = L.a;
     const uint64_t rounds = a.total / kWG;
     const uint64_t per_group = (rounds + L.w.item_rounds - 1) / L.w.item_rounds;   // items per group
-    stage_table(S, L.T);
+    stage_table(S, L.T.near64);
     ItemLoop it(L.w, kItems ? 3 * per_group * L.w.item_rounds * kWG : a.total, kWG, &s_item);
     if (it.item >= it.n_items) return;
     do {
@@ -1040,7 +1116,7 @@ __global__ __launch_bounds__(kWG) void k_bc7_emit(Bc7Launch L)
     const uint64_t g = live ? list[off + e] : a.run[0].gbase;
     const BlockRun run = a.run[find_run(a.run, a.nrun, g)];
     const uint64_t b = g - run.gbase;
-    stage_table(S, L.T);
+    stage_table(S, L.T.nearest);
     stage_texels(S, run.src + b * 64, live);   // lanes past the bucket stage zeros
     __syncthreads();
     if (!live) return;
@@ -1053,6 +1129,7 @@ __global__ __launch_bounds__(kWG) void k_bc7_emit(Bc7Launch L)
 // ---- host-side table construction
 struct HostTables {
     std::vector<uint16_t> nearest;  // [10][2][256]
+    std::vector<uint16_t> near64;   // [10][2][256]
     std::vector<uint32_t> sv;       // [10][4][kSlots][256]
 };
 
@@ -1075,6 +1152,8 @@ void build_nearest(HostTables &H)
                     row[t] = (uint16_t)(bc | (ep_value(bc, p, cb, pb) << 8));
                 }
             }
+    H.near64.resize(H.nearest.size());
+    for (size_t q = 0; q < H.nearest.size(); q++) H.near64[q] = (uint16_t)((H.nearest[q] >> 8) << 6);
 }
 
 // Best pair per target value v for one (class, p-bits, weight): first the
@@ -1135,22 +1214,25 @@ void build_sv(HostTables &H)
 
 }  // namespace
 
-// Device copies of the tables, one set per device, made on first use.
+// Device copies of the tables, one set per device, made once per device
+// (under a lock: contexts may be created from several threads).
 static void *g_tab[64];
+static std::mutex g_tab_lock;
 
 hipError_t upload_bc7_tables(int device, hipStream_t st)
 {
     if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> guard(g_tab_lock);
     if (g_tab[device]) return hipSuccess;
     static HostTables H;
-    static bool built = false;
-    if (!built) { build_nearest(H); build_sv(H); built = true; }
+    if (H.nearest.empty()) { build_nearest(H); build_sv(H); }
     size_t nb = H.nearest.size() * 2, sb = H.sv.size() * 4;
     void *p = nullptr;
-    hipError_t e = hipMalloc(&p, nb + sb);
+    hipError_t e = hipMalloc(&p, 2 * nb + sb);
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(p, H.nearest.data(), nb, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync((char *)p + nb, H.sv.data(), sb, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync((char *)p + nb, H.near64.data(), nb, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync((char *)p + 2 * nb, H.sv.data(), sb, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) { (void)hipFree(p); return e; }
     g_tab[device] = p;
@@ -1169,7 +1251,8 @@ hipError_t launch_bc7_encode(const EncodeArgs &a, const WorkSplit *w3, uint32_t 
     Bc7Launch L;
     L.a = a;
     L.T.nearest = static_cast<const uint16_t *>(g_tab[dev]);
-    L.T.sv = reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(g_tab[dev]) + 10 * 2 * 256 * 2);
+    L.T.near64 = L.T.nearest + kQEntries;
+    L.T.sv = reinterpret_cast<const uint32_t *>(L.T.near64 + kQEntries);
     const uint32_t nwg = (uint32_t)(a.total / kWG);
     const dim3 sgrid(nwg);
     // every key word starts all-ones (padding indices keep it)
