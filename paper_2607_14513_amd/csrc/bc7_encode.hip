@@ -699,6 +699,79 @@ __device__ __forceinline__ void anchor_fix(PairFit &f, uint32_t mask, int anchor
     f.idx ^= spread;   // k -> (2^NB - 1) - k on the members
 }
 
+// ---- visiting order of the 3-subset partitions
+//
+// Of the 192 subset masks of the 64 three-subset partitions only 140 differ
+// (36 of the 48 of partitions 0..15, the ones mode 0 also uses).  The search
+// visits the partitions in the order below; a mask that recurs is fitted
+// once and its SSE kept in an LDS slot of its lane until its last use.  This
+// order (found offline by a local search) needs at most kSlots2 slots for
+// mode 2 and kSlots0 for mode 0; a static check below recomputes both.
+constexpr int kOrder3[64] = {62, 9,  2,  0,  60, 42, 61, 27, 38, 18, 46, 33, 51, 47, 55, 41,
+                             31, 17, 63, 15, 23, 10, 36, 22, 8,  56, 29, 4,  3,  24, 6,  32,
+                             25, 19, 14, 37, 34, 7,  26, 43, 52, 5,  54, 50, 20, 48, 1,  39,
+                             58, 13, 35, 57, 53, 30, 21, 59, 49, 40, 28, 45, 16, 11, 44, 12};
+constexpr int kSlots2 = 6, kSlots0 = 4;
+
+__host__ __device__ constexpr uint32_t mask3_of(int p, int s)
+{
+    uint32_t m = 0;
+    for (int i = 0; i < 16; i++) m |= (((kPart3[p] >> (2 * i)) & 3) == (uint32_t)s ? 1u : 0u) << i;
+    return m;
+}
+
+// What the search does at visit t (partition kOrder3[t]), subset s, per mode:
+//   kFit           fit the subset
+//   kKeep | slot   fit it and keep the SSE in the slot (the mask recurs)
+//   kTake | slot   take the SSE from the slot (fitted at an earlier visit)
+constexpr uint8_t kFit = 0, kKeep = 0x40, kTake = 0x80;
+struct Plan3 {
+    uint8_t act[2][64][3];   // [0]: mode 2 (all partitions), [1]: mode 0 (partitions 0..15)
+    int slots[2];            // slots each mode needs
+};
+
+constexpr Plan3 make_plan3()
+{
+    Plan3 P{};
+    for (int mode = 0; mode < 2; mode++) {
+        // each visit's mask, then its last visit
+        uint32_t mk[192] = {};
+        int pos[192] = {}, n = 0;
+        for (int t = 0; t < 64; t++)
+            for (int s = 0; s < 3; s++)
+                if (mode == 0 || kOrder3[t] < 16) { mk[n] = mask3_of(kOrder3[t], s); pos[n] = t * 3 + s; n++; }
+        bool used[8] = {};
+        uint32_t held[8] = {};
+        int most = 0;
+        for (int q = 0; q < n; q++) {
+            int later = -1, slot = -1;
+            for (int r = q + 1; r < n; r++)
+                if (mk[r] == mk[q]) { later = r; break; }
+            for (int z = 0; z < 8; z++)
+                if (used[z] && held[z] == mk[q]) slot = z;
+            uint8_t a = kFit;
+            if (slot >= 0) {
+                a = (uint8_t)(kTake | slot);
+                if (later < 0) used[slot] = false;   // last use
+            } else if (later >= 0) {
+                int z = 0;
+                while (used[z]) z++;
+                used[z] = true;
+                held[z] = mk[q];
+                a = (uint8_t)(kKeep | z);
+                int live = 0;
+                for (int y = 0; y < 8; y++) live += used[y] ? 1 : 0;
+                most = live > most ? live : most;
+            }
+            P.act[mode][pos[q] / 3][pos[q] % 3] = a;
+        }
+        P.slots[mode] = most;
+    }
+    return P;
+}
+constexpr Plan3 kPlan3 = make_plan3();
+static_assert(kPlan3.slots[0] <= kSlots2 && kPlan3.slots[1] <= kSlots0, "3-subset visiting order needs more slots");
+
 // ---- pass 1: best key over one candidate group
 //
 // The principal axis and the extreme texels of a subset depend only on the
@@ -711,11 +784,16 @@ __device__ __forceinline__ void consider(uint32_t sse, int ci, uint32_t &best)
     best = min(best, (sse << 9) | (uint32_t)ci);
 }
 
+// Per-lane SSE slots of the 3-subset search (kSlots2 for mode 2, then
+// kSlots0 for mode 0), one column per lane.
+typedef uint32_t Cache3[kSlots2 + kSlots0][kWG];
+
 template <int GROUP>
-__device__ __forceinline__ uint32_t search_group(const TexLds &S, uint32_t mode_mask, const uint32_t *sv)
+__device__ __forceinline__ uint32_t search_group(const TexLds &S, Cache3 &cache, uint32_t mode_mask,
+                                                 const uint32_t *sv)
 {
     uint32_t best = 0xFFFFFFFFu;
-    const Sums tot = GROUP < 2 ? subset_sums(S, 0xFFFFu, 0) : Sums{};
+    const Sums tot = GROUP == 0 ? subset_sums(S, 0xFFFFu, 0) : Sums{};
     if (GROUP == 0) {
         // 2-subset partitions: modes 1, 3, 7
         if (mode_mask & 0x8A)
@@ -734,19 +812,39 @@ __device__ __forceinline__ uint32_t search_group(const TexLds &S, uint32_t mode_
                              221 + p, best);
             }
     } else if (GROUP == 1) {
-        // 3-subset partitions: mode 0 (partitions 0..15), mode 2
-        if (mode_mask & 0x05)
-            for (int p = 0; p < ((mode_mask & 0x04) ? 64 : 16); p++) {
-                const uint32_t m0 = mask3(p, 0), m1 = mask3(p, 1), m2 = mask3(p, 2);
-                const Sums s0 = subset_sums(S, m0, 0), s1 = subset_sums(S, m1, 0);
-                const Prep P0 = prep_subset(S, m0, 0, s0), P1 = prep_subset(S, m1, 0, s1);
-                const Prep P2 = prep_subset(S, m2, 0, sums_minus(sums_minus(tot, s0), s1));
-                if ((mode_mask & 0x01) && p < 16)
-                    consider(fit_colour<4, 2, 3, true>(S, m0, 0, P0, sv).sse + fit_colour<4, 2, 3, true>(S, m1, 0, P1, sv).sse +
-                                 fit_colour<4, 2, 3, true>(S, m2, 0, P2, sv).sse, p, best);
-                if (mode_mask & 0x04)
-                    consider(fit_colour<5, 0, 2, true>(S, m0, 0, P0, sv).sse + fit_colour<5, 0, 2, true>(S, m1, 0, P1, sv).sse +
-                                 fit_colour<5, 0, 2, true>(S, m2, 0, P2, sv).sse, 80 + p, best);
+        // 3-subset partitions: mode 0 (partitions 0..15), mode 2; recurring
+        // subset masks are fitted once (see kPlan3)
+        const bool on2 = mode_mask & 0x04, on0 = mode_mask & 0x01;
+        if (on0 || on2)
+            for (int t = 0; t < 64; t++) {
+                const int p = kOrder3[t];
+                if (!on2 && p >= 16) continue;
+                const bool with0 = on0 && p < 16;
+                uint32_t e2 = 0, e0 = 0;
+#pragma unroll 1
+                for (int s = 0; s < 3; s++) {
+                    const uint32_t msk = mask3(p, s);
+                    const int a2 = kPlan3.act[0][t][s], a0 = kPlan3.act[1][t][s];
+                    const bool fit2 = on2 && !(a2 & kTake), fit0 = with0 && !(a0 & kTake);
+                    uint32_t v2 = 0, v0 = 0;
+                    if (on2 && (a2 & kTake)) v2 = cache[a2 & 15][threadIdx.x];
+                    if (with0 && (a0 & kTake)) v0 = cache[kSlots2 + (a0 & 15)][threadIdx.x];
+                    if (fit2 || fit0) {
+                        const Prep P = prep_subset(S, msk, 0);
+                        if (fit2) {
+                            v2 = fit_colour<5, 0, 2, true>(S, msk, 0, P, sv).sse;
+                            if (a2 & kKeep) cache[a2 & 15][threadIdx.x] = v2;
+                        }
+                        if (fit0) {
+                            v0 = fit_colour<4, 2, 3, true>(S, msk, 0, P, sv).sse;
+                            if (a0 & kKeep) cache[kSlots2 + (a0 & 15)][threadIdx.x] = v0;
+                        }
+                    }
+                    e2 += v2;
+                    e0 += v0;
+                }
+                if (on2) consider(e2, 80 + p, best);
+                if (with0) consider(e0, p, best);
             }
     } else {
         // one subset: mode 6, and modes 4 / 5 for every rotation
@@ -967,6 +1065,7 @@ template <int GMASK>
 __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k_bc7_search(Bc7Launch L)
 {
     __shared__ TexLds S;
+    __shared__ Cache3 cache;
     __shared__ uint32_t s_item;
     constexpr bool kItems = GMASK == 8;
     const EncodeArgs &a = L.a;
@@ -991,13 +1090,13 @@ __global__ __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(3))) void k
             if (live) {
                 uint32_t key = ~0u;
                 if (kItems) {
-                    key = group == 0 ? search_group<0>(S, a.mode_mask, L.T.sv)
-                                     : group == 1 ? search_group<1>(S, a.mode_mask, L.T.sv)
-                                                  : search_group<2>(S, a.mode_mask, L.T.sv);
+                    key = group == 0 ? search_group<0>(S, cache, a.mode_mask, L.T.sv)
+                                     : group == 1 ? search_group<1>(S, cache, a.mode_mask, L.T.sv)
+                                                  : search_group<2>(S, cache, a.mode_mask, L.T.sv);
                 } else {
-                    if (GMASK & 1) key = min(key, search_group<0>(S, a.mode_mask, L.T.sv));
-                    if (GMASK & 2) key = min(key, search_group<1>(S, a.mode_mask, L.T.sv));
-                    if (GMASK & 4) key = min(key, search_group<2>(S, a.mode_mask, L.T.sv));
+                    if (GMASK & 1) key = min(key, search_group<0>(S, cache, a.mode_mask, L.T.sv));
+                    if (GMASK & 2) key = min(key, search_group<1>(S, cache, a.mode_mask, L.T.sv));
+                    if (GMASK & 4) key = min(key, search_group<2>(S, cache, a.mode_mask, L.T.sv));
                 }
                 atomicMin(a.keys + g0 + threadIdx.x, key);
             }

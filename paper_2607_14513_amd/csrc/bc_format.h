@@ -74,7 +74,8 @@ __host__ __device__ constexpr uint32_t pack_row3(const char *r)
     return v;
 }
 
-static __constant__ uint32_t kPart3[64] = {
+// (constexpr: the encoder plans its visiting order from it at compile time)
+constexpr uint32_t kPart3[64] = {
     pack_row3("0011001102212222"), pack_row3("0001001122112221"), pack_row3("0000200122112211"),
     pack_row3("0222002200110111"), pack_row3("0000000011221122"), pack_row3("0011001100220022"),
     pack_row3("0022002211111111"), pack_row3("0011001122112211"), pack_row3("0000000011112222"),
