@@ -406,32 +406,56 @@ __device__ __forceinline__ PairFit eval_pair(const TexLds &S, uint32_t mask, int
             acc[j] = 256u * (uint32_t)xx;
             rlo[j] = rhi[j] = 0;
         }
-        for (uint32_t m = mask; m; m &= m - 1) {
+        // least key of one member against combination j's entries
+        auto least = [&](uint32_t rg, int b, int j) {
+            int kb = 0x7FFFFFFF;
+#pragma unroll
+            for (int k = 0; k < NE; k++) {
+                // with a p-bit per endpoint, entry 0 depends only on p0 and
+                // entry NE-1 only on p1: combinations share those keys
+                const int js = (PB == 2 && CPV == 4) ? (k == 0 ? (j & 1) : k == NE - 1 ? (j & 2) : j) : j;
+                const int key = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg),
+                                                       __builtin_bit_cast(short2_t, prg[js][k]),
+                                                       mul_i24(b, pb[js][k]) + pk[js][k], false);
+                kb = min(kb, key);
+            }
+            return (uint32_t)kb;   // 256 (SSE - |x|^2) + k of this member
+        };
+        auto push_index = [&](int j, uint32_t kb) {
+            if (IDX) {
+                if (WIDE) {
+                    rlo[j] = __builtin_amdgcn_alignbit(rhi[j], rlo[j], IW);
+                    rhi[j] = __builtin_amdgcn_alignbit(kb, rhi[j], IW);
+                } else {
+                    rlo[j] = __builtin_amdgcn_alignbit(kb, rlo[j], IW);
+                }
+            }
+        };
+        // members two at a time (their keys join the sums in one three-way
+        // add), then the odd one
+        uint32_t m = mask;
+        for (; m & (m - 1); m &= m - 1, m &= m - 1) {
+            uint32_t rg0, rg1;
+            int b0, b1;
+            texel(S, __ffs(m) - 1, rot, rg0, b0);
+            texel(S, __ffs(m & (m - 1)) - 1, rot, rg1, b1);
+#pragma unroll
+            for (int j = 0; j < CPV; j++) {
+                const uint32_t k0 = least(rg0, b0, j), k1 = least(rg1, b1, j);
+                acc[j] += k0 + k1;
+                push_index(j, k0);
+                push_index(j, k1);
+            }
+        }
+        if (m) {
             uint32_t rg;
             int b;
             texel(S, __ffs(m) - 1, rot, rg, b);
 #pragma unroll
             for (int j = 0; j < CPV; j++) {
-                int kb = 0x7FFFFFFF;
-#pragma unroll
-                for (int k = 0; k < NE; k++) {
-                    // with a p-bit per endpoint, entry 0 depends only on p0 and
-                    // entry NE-1 only on p1: combinations share those keys
-                    const int js = (PB == 2 && CPV == 4) ? (k == 0 ? (j & 1) : k == NE - 1 ? (j & 2) : j) : j;
-                    const int key = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg),
-                                                           __builtin_bit_cast(short2_t, prg[js][k]),
-                                                           mul_i24(b, pb[js][k]) + pk[js][k], false);
-                    kb = min(kb, key);
-                }
-                acc[j] += (uint32_t)kb;   // 256 (SSE - |x|^2) + k of this member
-                if (IDX) {
-                    if (WIDE) {
-                        rlo[j] = __builtin_amdgcn_alignbit(rhi[j], rlo[j], IW);
-                        rhi[j] = __builtin_amdgcn_alignbit((uint32_t)kb, rhi[j], IW);
-                    } else {
-                        rlo[j] = __builtin_amdgcn_alignbit((uint32_t)kb, rlo[j], IW);
-                    }
-                }
+                const uint32_t kb = least(rg, b, j);
+                acc[j] += kb;
+                push_index(j, kb);
             }
         }
 #pragma unroll
