@@ -98,22 +98,21 @@ __device__ __forceinline__ int quant_h_int(int y, int det, uint32_t M)
 
 __device__ inline uint32_t pack565(int r, int g, int b) { return ((uint32_t)r << 11) | ((uint32_t)g << 5) | (uint32_t)b; }
 
-// Texels of the block for the index search: rg = R | G << 16, B, 64 |x|^2.
-struct Tex16 {
-    uint32_t rg[16];
-    int b[16], cx[16];
-};
-
 // Order the pair for the mode (4-colour: c0 > c1, 3-colour: c0 <= c1), then
 // give each texel its least-SSE palette entry (lowest index on ties).  With
 // entry k held as (-128 pR, -128 pG), -128 pB and 64 |p|^2 + k, the key
 // 64 (|p|^2 - 2 x.p) + k is one 24-bit multiply-add and one 16-bit dot
-// product; 64 |x|^2 added to the least key is 64 SSE + k, and over 16 texels
-// the k terms stay below 64.  Indices enter a shift register from the top,
-// so texel 0 ends in bits 0-1.
-__device__ inline uint32_t canon_index(uint32_t &c0, uint32_t &c1, bool four, const Tex16 &T, uint32_t &indices)
+// product on the texel's (R, G) pair and B, both taken from its RGBA word
+// (one byte permute and one bit-field extract).  The least keys summed over
+// the 16 texels plus 64 sum |x|^2 (= 64 Q, the same for every palette) are
+// 64 SSE + sum k, and the k terms stay below 64.  Indices enter a shift
+// register from the top, so texel 0 ends in bits 0-1.  The texels stay as
+// their 16 RGBA words (not unpacked) so that they hold few registers across
+// the split search.
+__device__ inline uint32_t canon_index(uint32_t &c0, uint32_t &c1, bool four, const uint32_t (&t)[16], int Q,
+                                       uint32_t &indices)
 {
-    if ((four && c0 < c1) || (!four && c0 > c1)) { uint32_t t = c0; c0 = c1; c1 = t; }
+    if ((four && c0 < c1) || (!four && c0 > c1)) { uint32_t u = c0; c0 = c1; c1 = u; }
     int p[4][3];
     int e0[3], e1[3];
     bc1_expand(c0, e0);
@@ -139,16 +138,18 @@ __device__ inline uint32_t canon_index(uint32_t &c0, uint32_t &c1, bool four, co
         pb[k] = -128 * p[k][2];
         pk[k] = 64 * (mul_i24(p[k][0], p[k][0]) + mul_i24(p[k][1], p[k][1]) + mul_i24(p[k][2], p[k][2])) + k;
     }
-    uint32_t acc = 0, idx = 0;
+    uint32_t acc = 64u * (uint32_t)Q, idx = 0;
 #pragma unroll
     for (int i = 0; i < 16; i++) {
+        // R | G << 16 (bytes 0 and 1 of the RGBA word to bytes 0 and 2) and B
+        const uint32_t rg = __builtin_amdgcn_perm(0u, t[i], 0x0C010C00u);
+        const int b = (int)__builtin_amdgcn_ubfe(t[i], 16, 8);
         int kb = 0x7FFFFFFF;
 #pragma unroll
         for (int k = 0; k < 4; k++)
-            kb = min(kb, __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, T.rg[i]),
-                                                __builtin_bit_cast(short2_t, prg[k]), mul_i24(T.b[i], pb[k]) + pk[k],
-                                                false));
-        acc += (uint32_t)kb + (uint32_t)T.cx[i];
+            kb = min(kb, __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, rg), __builtin_bit_cast(short2_t, prg[k]),
+                                                mul_i24(b, pb[k]) + pk[k], false));
+        acc += (uint32_t)kb;
         idx = __builtin_amdgcn_alignbit((uint32_t)kb, idx, 2);
     }
     indices = idx;
@@ -268,13 +269,12 @@ template <class Lds>
 __device__ __forceinline__ void encode_block(const uint32_t (&t)[16], uint32_t refine_steps, Lds &L, int lane, uint32_t &w0,
                              uint32_t &w1, uint32_t &sse_out)
 {
-    Tex16 T;
+    // sum of |x|^2 over the texels (the palette-independent part of the SSE)
+    int Q = 0;
 #pragma unroll
     for (int i = 0; i < 16; i++) {
-        const uint32_t r = t[i] & 255u, g = (t[i] >> 8) & 255u, bb = (t[i] >> 16) & 255u;
-        T.rg[i] = r | (g << 16);
-        T.b[i] = (int)bb;
-        T.cx[i] = (int)(64u * (r * r + g * g + bb * bb));
+        const uint32_t rgb = t[i] & 0xFFFFFFu;
+        Q += (int)__builtin_amdgcn_udot4(rgb, rgb, 0u, false);
     }
     bool constant = true;
 #pragma unroll
@@ -295,7 +295,7 @@ __device__ __forceinline__ void encode_block(const uint32_t (&t)[16], uint32_t r
         bool four = err4 <= err3;
         c0 = four ? pack565(a4[0], a4[1], a4[2]) : pack565(a3[0], a3[1], a3[2]);
         c1 = four ? pack565(b4[0], b4[1], b4[2]) : pack565(b3[0], b3[1], b3[2]);
-        sse = canon_index(c0, c1, four, T, idx);
+        sse = canon_index(c0, c1, four, t, Q, idx);
         w0 = c0 | (c1 << 16);
         w1 = idx;
         sse_out = sse;
@@ -314,7 +314,6 @@ __device__ __forceinline__ void encode_block(const uint32_t (&t)[16], uint32_t r
             for (int b = a; b < 3; b++) XX[a][b] += x[a] * x[b];
         }
     }
-    const int Q = XX[0][0] + XX[1][1] + XX[2][2];
     int C[3][3];
 #pragma unroll
     for (int a = 0; a < 3; a++)
@@ -358,7 +357,8 @@ __device__ __forceinline__ void encode_block(const uint32_t (&t)[16], uint32_t r
     int proj[16];
 #pragma unroll
     for (int i = 0; i < 16; i++)
-        proj[i] = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, T.rg[i]), v01, __mul24(T.b[i], v[2]), false);
+        proj[i] = __builtin_amdgcn_sdot2(__builtin_bit_cast(short2_t, __builtin_amdgcn_perm(0u, t[i], 0x0C010C00u)), v01,
+                                         __mul24((int)__builtin_amdgcn_ubfe(t[i], 16, 8), v[2]), false);
 #pragma unroll
     for (int i = 0; i < 16; i++) {
         int r = 0;
@@ -392,23 +392,24 @@ __device__ __forceinline__ void encode_block(const uint32_t (&t)[16], uint32_t r
 
     c0 = pack565(bq0[0], bq0[1], bq0[2]);
     c1 = pack565(bq1[0], bq1[1], bq1[2]);
-    sse = canon_index(c0, c1, (best_split >> 15) & 1, T, idx);
+    sse = canon_index(c0, c1, (best_split >> 15) & 1, t, Q, idx);
 
     // ---- refinement: best of the 12 one-step moves, taken if strictly better
     for (uint32_t step = 0; step < refine_steps; step++) {
         const bool four = c0 > c1;
-        int cur[6] = {(int)(c0 >> 11) & 31, (int)(c0 >> 5) & 63, (int)c0 & 31,
-                      (int)(c1 >> 11) & 31, (int)(c1 >> 5) & 63, (int)c1 & 31};
         uint32_t nb_sse = 0xFFFFFFFFu, nb0 = 0, nb1 = 0, nbi = 0;
-#pragma unroll
+        // neighbour q moves channel q/2 (R0, G0, B0, R1, G1, B1) by -1 (q
+        // even) or +1, clamped; one neighbour at a time (a rolled loop, so
+        // that only one palette is live)
+#pragma unroll 1
         for (int q = 0; q < 12; q++) {
-            int ch = q >> 1, dlt = (q & 1) ? 1 : -1;
-            int maxc = (ch % 3 == 1) ? 63 : 31;
-            int cand[6] = {cur[0], cur[1], cur[2], cur[3], cur[4], cur[5]};
-            int nv = cand[ch] + dlt;
-            cand[ch] = nv < 0 ? 0 : (nv > maxc ? maxc : nv);
-            uint32_t a = pack565(cand[0], cand[1], cand[2]), b = pack565(cand[3], cand[4], cand[5]), ii;
-            uint32_t s = canon_index(a, b, four, T, ii);
+            const int ch = q >> 1, c = ch % 3;
+            const int shift = c == 0 ? 11 : c == 1 ? 5 : 0, maxc = c == 1 ? 63 : 31;
+            const uint32_t word = ch < 3 ? c0 : c1;
+            const int f = (int)((word >> shift) & (uint32_t)maxc) + ((q & 1) ? 1 : -1);
+            const uint32_t moved = (word & ~((uint32_t)maxc << shift)) | ((uint32_t)min(max(f, 0), maxc) << shift);
+            uint32_t a = ch < 3 ? moved : c0, b = ch < 3 ? c1 : moved, ii;
+            const uint32_t s = canon_index(a, b, four, t, Q, ii);
             if (s < nb_sse) { nb_sse = s; nb0 = a; nb1 = b; nbi = ii; }
         }
         if (nb_sse < sse) { sse = nb_sse; c0 = nb0; c1 = nb1; idx = nbi; }
