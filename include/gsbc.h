@@ -309,6 +309,22 @@ GSBC_API gsbc_status gsbc_decode_eval(gsbc_ctx *ctx, const uint8_t *blocks, cons
                              const float *dirs, uint32_t n_dirs, const uint32_t *prim_idx,
                              uint64_t m, float *out);
 
+/* gsbc_decode_eval for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * arguments, checks, kernels and results, but the per-call scratch (16 basis
+ * floats per direction) is a file-scope device array of the library instead
+ * of the context's arena, so the call allocates nothing (no device, host or
+ * event allocation; kernel timing is not recorded for it).
+ *   n_dirs   at most 1024 (GSBC_E_ARG above: the array's fixed size)
+ * Every call on one GPU shares that GPU's array (the library keeps it until
+ * the process ends; gsbc_create looks its address up): calls that overlap on
+ * one GPU, e.g. from two contexts on different streams, race on it and must
+ * be serialised by the caller.  Each call writes the rows it reads before
+ * reading them, so nothing needs clearing between calls. */
+GSBC_API gsbc_status gsbc_decode_eval_noalloc(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_desc *desc,
+                                     const float *dirs, uint32_t n_dirs, const uint32_t *prim_idx,
+                                     uint64_t m, float *out);
+
 /* Colour of each listed slot seen from one view position f: the colour
  * equation c(f) = H w(f - p) of Sec. II evaluated per primitive at the unit
  * direction d = (f - p)/|f - p| towards the view position (d = 0 when f = p),

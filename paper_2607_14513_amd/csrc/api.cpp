@@ -333,6 +333,7 @@ gsbc_status gsbc_create(gsbc_ctx **out, int device, void *hip_stream)
     if (hipHostMalloc(&ctx->pinned, 4096, hipHostMallocDefault) != hipSuccess) return bail(GSBC_E_NOMEM);
     if (upload_bc1_tables(ctx->stream) != hipSuccess) return bail(GSBC_E_DEVICE);
     if (upload_bc7_tables(device, ctx->stream) != hipSuccess) return bail(GSBC_E_DEVICE);
+    if (init_static_scratch(device) != hipSuccess) return bail(GSBC_E_DEVICE);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(GSBC_E_DEVICE);
     *out = ctx;
     return GSBC_OK;
@@ -950,6 +951,35 @@ gsbc_status gsbc_decode_eval(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_st
     if ((s = ensure_arena(ctx, (size_t)n_dirs * 16 * sizeof(float)))) return s;
     HIP_TRY(ctx, launch_decode_eval(blocks, band_args(desc), desc->n_prims, dirs, n_dirs, prim_idx, m, out,
                                     static_cast<float *>(ctx->arena), ctx->stream), "decode_eval launch");
+    return GSBC_OK;
+}
+
+gsbc_status gsbc_decode_eval_noalloc(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_desc *desc,
+                                     const float *dirs, uint32_t n_dirs, const uint32_t *prim_idx, uint64_t m,
+                                     float *out)
+{
+    // the same checks and kernels as gsbc_decode_eval, with the basis rows in
+    // the library's static device array instead of the context's arena: no
+    // allocation of any kind (and no kernel timing, whose events would be)
+    gsbc_status s = begin(ctx);
+    if (s) return s;
+    if (!blocks || !dirs || !out) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
+    if (reinterpret_cast<uintptr_t>(blocks) & 15) return fail(ctx, GSBC_E_ARG, "blocks must be 16-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(dirs) & 3) || (reinterpret_cast<uintptr_t>(out) & 3) ||
+        (reinterpret_cast<uintptr_t>(prim_idx) & 3))
+        return fail(ctx, GSBC_E_ARG, "dirs, prim_idx and out must be 4-byte aligned");
+    if ((s = check_stream(ctx, desc))) return s;
+    if (n_dirs == 0) return fail(ctx, GSBC_E_ARG, "n_dirs must be >= 1");
+    if (n_dirs > kStaticScratchDirs)
+        return fail(ctx, GSBC_E_ARG, "n_dirs %u exceeds the %u directions of the allocation-free scratch", n_dirs,
+                    kStaticScratchDirs);
+    if (m == 0) return fail(ctx, GSBC_E_ARG, "m must be >= 1");
+    if (!prim_idx && m != desc->n_prims) return fail(ctx, GSBC_E_ARG, "prim_idx NULL requires m == n_prims");
+    if (m > 0xFFFFFFFFull * 256) return fail(ctx, GSBC_E_ARG, "m too large");
+    float *basis = static_scratch(ctx->device);
+    if (!basis) return fail(ctx, GSBC_E_DEVICE, "static scratch of device %d not set up", ctx->device);
+    HIP_TRY(ctx, launch_decode_eval(blocks, band_args(desc), desc->n_prims, dirs, n_dirs, prim_idx, m, out, basis,
+                                    ctx->stream), "decode_eval launch");
     return GSBC_OK;
 }
 

@@ -10,6 +10,9 @@
 #include "gsbc_internal.h"
 #include "bc_format.h"
 
+#include <atomic>
+#include <mutex>
+
 namespace gsbc {
 namespace {
 
@@ -472,6 +475,33 @@ hipError_t launch_decode(const uint8_t *blocks, const BandArgs &b, uint64_t nblk
     GSBC_LAUNCH("decode", k_decode, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, blocks, b, nblk,
                        reinterpret_cast<uint32_t *>(textures));
     return hipGetLastError();
+}
+
+// ---- scratch of the allocation-free decode_eval
+// The basis rows (16 floats per direction) of gsbc_decode_eval_noalloc live
+// in this file-scope device array: the library holds one copy on each GPU it
+// runs on until the process ends.  Host code never uses the array's name as
+// an address (on the host it is only a stand-in for the symbol); each
+// device's address is looked up once, with that device current, and kept.
+static __device__ __align__(256) float scratch[kStaticScratchDirs * 16];
+static std::atomic<float *> g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_lock;
+
+hipError_t init_static_scratch(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> guard(g_scratch_lock);
+    if (g_scratch_ptr[device].load()) return hipSuccess;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device].store(static_cast<float *>(ptr));
+    return hipSuccess;
+}
+
+float *static_scratch(int device)
+{
+    return device >= 0 && device < kMaxDevices ? g_scratch_ptr[device].load() : nullptr;
 }
 
 hipError_t launch_decode_eval(const uint8_t *blocks, const BandArgs &b, uint64_t n_prims, const float *dirs,

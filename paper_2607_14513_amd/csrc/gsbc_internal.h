@@ -187,6 +187,15 @@ hipError_t launch_decode_eval(const uint8_t *blocks, const BandArgs &b, uint64_t
                               const float *dirs, uint32_t n_dirs, const uint32_t *prim_idx,
                               uint64_t m, float *out, float *basis_scratch, hipStream_t st);
 
+// The allocation-free decode_eval's basis scratch: a file-scope device
+// array of kStaticScratchDirs x 16 floats in decode.hip.  init_static_scratch
+// looks its address up on `device` (which must be current) once; after that
+// static_scratch returns it (null before).
+constexpr uint32_t kStaticScratchDirs = 1024;
+constexpr int kMaxDevices = 64;
+hipError_t init_static_scratch(int device);
+float *static_scratch(int device);
+
 // One view position: out[j] = colour of slot prim_idx[j] (or j) at the
 // direction from its primitive (pos[perm[slot]]) towards `view`.
 hipError_t launch_decode_eval_view(const uint8_t *blocks, const BandArgs &b, uint64_t n_prims, const float *pos,

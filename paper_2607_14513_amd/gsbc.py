@@ -21,7 +21,8 @@ N_STREAMS = {ARR_BANDS: 16, ARR_PRIM: 1, ARR_QUAD: 4}
 
 EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_default_params",
             "gsbc_query_sizes", "gsbc_reorder", "gsbc_reorder_degrees", "gsbc_encode", "gsbc_default_batch_tuning",
-            "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_decode_eval_view", "gsbc_save", "gsbc_load",
+            "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_decode_eval_noalloc", "gsbc_decode_eval_view",
+            "gsbc_save", "gsbc_load",
             "gsbc_profile_enable", "gsbc_profile_read")
 
 
@@ -100,6 +101,7 @@ def load():
                                           ctypes.POINTER(BatchTuning), P]
         lib.gsbc_decode.argtypes = [P, P, ctypes.POINTER(StreamDesc), P]
         lib.gsbc_decode_eval.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, u32, P, u64, P]
+        lib.gsbc_decode_eval_noalloc.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, u32, P, u64, P]
         lib.gsbc_decode_eval_view.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, P, P, P, u64, P]
         lib.gsbc_save.argtypes = [P, P, ctypes.POINTER(StreamDesc), ctypes.c_char_p]
         lib.gsbc_load.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(StreamDesc), P, u64]
@@ -414,9 +416,11 @@ class Context:
         self._check(load().gsbc_decode(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(out)))
         return out
 
-    def decode_eval(self, blocks, desc, dirs, prim_idx=None, out=None):
+    def decode_eval(self, blocks, desc, dirs, prim_idx=None, out=None, noalloc=False):
         """dirs float32[V][3] device; prim_idx int32[m] sorted-slot ids or None
-        -> out float32[V][m][3]."""
+        -> out float32[V][m][3].  noalloc: through gsbc_decode_eval_noalloc
+        (the library allocates nothing; V <= 1024; out must then be given by
+        a caller that cannot allocate, though one is made here if not)."""
         _, _, payload, n = _sizes(desc)
         _check(blocks, torch.uint8, "blocks", min_numel=payload)
         _check(dirs, torch.float32, "dirs")
@@ -429,6 +433,6 @@ class Context:
             out = torch.empty((V, m, 3), dtype=torch.float32, device=self.device)
         _check(out, torch.float32, "out", shape=(V, m, 3))
         _on_device(("blocks", blocks), ("dirs", dirs), ("prim_idx", prim_idx), ("out", out))
-        self._check(load().gsbc_decode_eval(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(dirs), V,
-                                            _ptr(prim_idx), m, _ptr(out)))
+        fn = load().gsbc_decode_eval_noalloc if noalloc else load().gsbc_decode_eval
+        self._check(fn(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(dirs), V, _ptr(prim_idx), m, _ptr(out)))
         return out
