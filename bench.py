@@ -527,14 +527,17 @@ def batch_leg(ctx, stream, dev, n_scenes, reps):
                                                                           "search_s", "cached") if k in tinfo}}
 
 
-def serve_leg(dev, count):
+def serve_leg(dev, count, slots=4):
     """Poisson arrivals of encode (70%) and decode_eval (30%) requests; N
     log-uniform in [1e4, 4e6] primitives (slices of a 4M-primitive scene drawn
-    on the device, seed 5), V log-uniform in [1, 1024]; encodes at 6 bits per
-    texel stay resident; 4 slots, 200 GB HBM budget.  The arrival rate is 70%
-    of the plain path's capacity, measured first by serving a calibration set
-    one request at a time.  A sample of requests is re-run alone afterwards
-    and must give identical results."""
+    on the device, seed 5), V log-uniform in [1, 1024], each decode reading
+    the scene of an earlier encode; encodes at 6 bits per texel stay
+    resident; 200 GB HBM budget.  The arrival rate is 70% of the plain path's
+    capacity, measured first by serving a calibration set one request at a
+    time.  The same arrivals are then served twice: by `slots` overlapping
+    slots (continuous batching) and by the plain path (one slot, first come
+    first served).  Sampled results are digested in both runs and re-run
+    alone; all three must agree."""
     import torch
     from paper_2607_14513_amd import serve, synth
     pool_n = 4_000_000
@@ -542,7 +545,7 @@ def serve_leg(dev, count):
     torch.cuda.synchronize()
     # plain capacity: one slot, requests back to back
     cal = serve.make_requests(60, 1e9, seed=55, pool_n=pool_n)
-    s1 = serve.Server(pos, sh, slots=1, hbm_budget=200e9, fingerprint_ids=set())
+    s1 = serve.Server(pos, sh, slots=1, hbm_budget=200e9, digest_ids=set())
     try:
         s1.run(cal[:6])                       # warm-up (contexts, allocator)
         t0 = time.perf_counter()
@@ -554,26 +557,36 @@ def serve_leg(dev, count):
     torch.cuda.empty_cache()
     capacity = 1.0 / service
     lam = 0.7 * capacity
-    reqs = serve.make_requests(count, lam, seed=5, pool_n=pool_n)
     sample = set(range(0, count, max(1, count // 24)))
-    srv = serve.Server(pos, sh, slots=4, hbm_budget=200e9, fingerprint_ids=sample)
-    try:
-        done = srv.run(reqs)
-        summ = serve.summarize(done, srv.t_elapsed, srv.t0)
-        same = 0
-        checked = 0
-        for r in sorted(done, key=lambda r: r.rid):
-            if r.rid in sample and r.error is None:
-                checked += 1
-                same += int(srv.run_alone(r) == r.fingerprint)
-        summ.update({"workload": f"{count} requests, Poisson arrivals at {lam:.2f}/s (70% of the measured "
-                                 f"one-at-a-time capacity {capacity:.2f}/s), 70% encode at 6 bits/texel / 30% "
-                                 "decode_eval, N log-uniform 1e4..4e6, V log-uniform 1..1024, 4 slots, 200 GB budget",
-                     "arrival_rate_hz": round(lam, 3), "plain_capacity_hz": round(capacity, 3),
-                     "identity_checked": checked, "identity_same": same, "evicted_scenes": srv.evicted})
-    finally:
-        srv.close()
-    return summ
+    out = {"workload": f"{count} requests, Poisson arrivals at {lam:.2f}/s (70% of the measured one-at-a-time "
+                       f"capacity {capacity:.2f}/s), 70% encode at 6 bits/texel / 30% decode_eval of an earlier "
+                       "request's scene, N log-uniform 1e4..4e6, V log-uniform 1..1024, 200 GB budget",
+           "arrival_rate_hz": round(lam, 3), "plain_capacity_hz": round(capacity, 3)}
+    digests = {}
+    for label, nslots in (("served", slots), ("plain", 1)):
+        reqs = serve.make_requests(count, lam, seed=5, pool_n=pool_n)
+        srv = serve.Server(pos, sh, slots=nslots, hbm_budget=200e9, digest_ids=sample)
+        try:
+            done = srv.run(reqs)
+            summ = serve.summarize(done, srv.t_elapsed, srv.t0)
+            summ.update({"slots": nslots, "evicted_scenes": srv.evicted, "arena_growths": srv.arena_growths()})
+            digests[label] = {r.rid: r.digest for r in done if r.rid in sample and r.error is None}
+            if label == "served":
+                same = checked = 0
+                for r in sorted(done, key=lambda r: r.rid):
+                    if r.rid in sample and r.error is None:
+                        checked += 1
+                        same += int(srv.run_alone(r)[0] == r.digest)
+                summ.update({"identity_checked": checked, "identity_same_alone": same})
+        finally:
+            srv.close()
+        del srv
+        torch.cuda.empty_cache()
+        out[label] = summ
+    common = set(digests["served"]) & set(digests["plain"])
+    out["identity_same_plain"] = sum(int(digests["served"][k] == digests["plain"][k]) for k in common)
+    out["identity_checked_plain"] = len(common)
+    return out
 
 
 def cpu_baseline(pos, sh, dirs, rate):

@@ -124,6 +124,19 @@ GSBC_API const char *gsbc_last_error(const gsbc_ctx *ctx);
 /* Wait for all work enqueued by this context. */
 GSBC_API gsbc_status gsbc_sync(gsbc_ctx *ctx);
 
+/* Size the context's scratch arena once for scenes of up to n_max primitives
+ * and decode_evals of up to n_dirs_max directions, so that calls within those
+ * sizes allocate nothing (a serving slot reserves its largest admissible
+ * request up front instead of growing mid-stream).  Outgrown arenas are kept
+ * until gsbc_destroy, since queued kernels may still read them and freeing
+ * device memory waits for the whole device.
+ * GSBC_E_ARG for n_max outside 1..2^31-1, GSBC_E_NOMEM if it cannot grow. */
+GSBC_API gsbc_status gsbc_reserve(gsbc_ctx *ctx, uint64_t n_max, uint32_t n_dirs_max);
+
+/* The arena's current size in bytes and how many times it has grown (either
+ * output may be NULL). */
+GSBC_API gsbc_status gsbc_arena_info(const gsbc_ctx *ctx, uint64_t *bytes, uint64_t *growths);
+
 /* Fill `p` (host) with the defaults: grid_bits 3, refine_steps 2, mode mask 0xFF, order 0,
  * arrangement GSBC_ARR_BANDS, quantiser 0. */
 GSBC_API void gsbc_default_params(gsbc_params *p);

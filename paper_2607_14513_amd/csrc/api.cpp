@@ -23,6 +23,8 @@ struct gsbc_ctx {
     bool own_stream = false;
     void *arena = nullptr;          // grows on demand; freed with the context
     size_t arena_bytes = 0;
+    std::vector<void *> retired;    // arenas outgrown while kernels could still read them
+    uint64_t arena_growths = 0;
     void *small = nullptr;          // fixed device block: range, selection, SSE sums, offsets
     void *pinned = nullptr;         // host staging for read-backs
     char err[512] = {0};
@@ -108,24 +110,28 @@ gsbc_status begin(gsbc_ctx *ctx)
     return GSBC_OK;
 }
 
+// Grow the context's scratch arena to at least `bytes`.  The old arena may
+// still be read by kernels queued on the stream, and freeing device memory
+// waits for the whole device (other contexts' streams included), so it is
+// retired, not freed: retired arenas are freed with the context.  Growth is
+// at least twofold, so retired memory stays below the live arena's size.
+// Calls within the sizes given to gsbc_reserve never grow it.
 gsbc_status ensure_arena(gsbc_ctx *ctx, size_t bytes)
 {
     if (bytes <= ctx->arena_bytes) return GSBC_OK;
-    if (ctx->arena) {
-        HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "hipStreamSynchronize");
-        HIP_TRY(ctx, hipFree(ctx->arena), "hipFree");
-        ctx->arena = nullptr;
-        ctx->arena_bytes = 0;
-    }
     if (injected_alloc_failure()) return fail(ctx, GSBC_E_NOMEM, "scratch allocation of %zu bytes failed (injected)", bytes);
-    size_t want = (bytes + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
-    hipError_t e = hipMalloc(&ctx->arena, want);
+    size_t want = std::max(bytes, 2 * ctx->arena_bytes);
+    want = (want + ((size_t)1 << 20) - 1) & ~(((size_t)1 << 20) - 1);
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
     if (e != hipSuccess) {
-        ctx->arena = nullptr;
         (void)hipGetLastError();
         return fail(ctx, GSBC_E_NOMEM, "scratch allocation of %zu bytes failed: %s", want, hipGetErrorString(e));
     }
+    if (ctx->arena) ctx->retired.push_back(ctx->arena);
+    ctx->arena = p;
     ctx->arena_bytes = want;
+    ctx->arena_growths++;
     return GSBC_OK;
 }
 
@@ -234,6 +240,11 @@ uint64_t layout(const uint32_t fmt[16], uint32_t n_streams, uint64_t nblk, uint6
     return pos;
 }
 
+// Arena bytes of one encode of nblk blocks per stream: [both candidate
+// payloads (AUTO)] [BC7 runs] [BC1 runs] [BC7 key scratch]; AUTO is the
+// largest (every band in both formats).
+size_t encode_front_bytes(uint64_t nblk) { return 16 * align16(8 * nblk) + 16 * 16 * nblk; }
+
 // Default work split of the single-scene calls: one workgroup per 256-block
 // round, BC1 on 128-lane workgroups, one BC7 search launch whose work items
 // are (candidate group, round) pairs.
@@ -255,6 +266,8 @@ gsbc_status ensure_side(gsbc_ctx *ctx)
 
 void drop_plan(gsbc_ctx *ctx)
 {
+    // a replay of the plan may still be running on the stream
+    if (ctx->graph_exec || ctx->plan_mem) (void)hipStreamSynchronize(ctx->stream);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
     if (ctx->plan_mem) (void)hipFree(ctx->plan_mem);
@@ -331,7 +344,7 @@ gsbc_status gsbc_create(gsbc_ctx **out, int device, void *hip_stream)
     }
     if (hipMalloc(&ctx->small, kSmallBytes) != hipSuccess) return bail(GSBC_E_NOMEM);
     if (hipHostMalloc(&ctx->pinned, 4096, hipHostMallocDefault) != hipSuccess) return bail(GSBC_E_NOMEM);
-    if (upload_bc1_tables(ctx->stream) != hipSuccess) return bail(GSBC_E_DEVICE);
+    if (upload_bc1_tables(device, ctx->stream) != hipSuccess) return bail(GSBC_E_DEVICE);
     if (upload_bc7_tables(device, ctx->stream) != hipSuccess) return bail(GSBC_E_DEVICE);
     if (init_static_scratch(device) != hipSuccess) return bail(GSBC_E_DEVICE);
     if (hipStreamSynchronize(ctx->stream) != hipSuccess) return bail(GSBC_E_DEVICE);
@@ -352,6 +365,7 @@ gsbc_status gsbc_destroy(gsbc_ctx *ctx)
     if (ctx->join) (void)hipEventDestroy(ctx->join);
     if (ctx->side) (void)hipStreamDestroy(ctx->side);
     if (ctx->arena) (void)hipFree(ctx->arena);
+    for (void *p : ctx->retired) (void)hipFree(p);
     if (ctx->small) (void)hipFree(ctx->small);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
@@ -378,6 +392,27 @@ gsbc_status gsbc_query_sizes(uint64_t n, uint32_t n_dirs, uint64_t *textures_byt
     if (textures_bytes) *textures_bytes = 16 * np * 4;
     if (max_blocks_bytes) *max_blocks_bytes = 16 * (np / 16) * 16;
     if (out_bytes) *out_bytes = (uint64_t)n_dirs * n * 12;
+    return GSBC_OK;
+}
+
+gsbc_status gsbc_reserve(gsbc_ctx *ctx, uint64_t n_max, uint32_t n_dirs_max)
+{
+    gsbc_status s = begin(ctx);
+    if (s) return s;
+    if (n_max == 0 || n_max > 0x7FFFFFFFull) return fail(ctx, GSBC_E_ARG, "n_max = %llu not in 1..2^31-1",
+                                                         (unsigned long long)n_max);
+    const uint64_t nblk = pad16(n_max) / 16;
+    size_t need = reorder_scratch_bytes(n_max, 3);
+    need = std::max(need, encode_front_bytes(nblk) + 2 * kRunTableBytes + bc7_scratch_bytes(16 * run_span(nblk)));
+    need = std::max(need, (size_t)n_dirs_max * 16 * sizeof(float));
+    return ensure_arena(ctx, need);
+}
+
+gsbc_status gsbc_arena_info(const gsbc_ctx *ctx, uint64_t *bytes, uint64_t *growths)
+{
+    if (!ctx) return GSBC_E_ARG;
+    if (bytes) *bytes = ctx->arena_bytes;
+    if (growths) *growths = ctx->arena_growths;
     return GSBC_OK;
 }
 
@@ -549,7 +584,7 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
         if (blocks_capacity < payload)
             return fail(ctx, GSBC_E_BUFFER, "blocks_capacity %llu < payload %llu bytes", (unsigned long long)blocks_capacity,
                         (unsigned long long)payload);
-        front = 16 * align16(8 * nblk) + 16 * 16 * nblk;   // both candidate payloads
+        front = encode_front_bytes(nblk);   // both candidate payloads
     }
     // arena: [candidate payloads (AUTO)] [BC7 runs] [BC1 runs] [BC7 key scratch]
     const uint64_t total7 = format == GSBC_FMT_AUTO ? 16 * run_span(nblk) : r7.total;

@@ -19,6 +19,7 @@
 #include "bc_format.h"
 
 #include <cstdlib>
+#include <mutex>
 #include <vector>
 
 namespace gsbc {
@@ -533,12 +534,23 @@ void build_tables(Bc1Tables &T)
 
 }  // namespace
 
-hipError_t upload_bc1_tables(hipStream_t st)
+// The tables are built once per process and copied once per device, under a
+// lock (contexts may be created from several threads; a context made later
+// must not rewrite the constant tables while kernels of another read them).
+hipError_t upload_bc1_tables(int device, hipStream_t st)
 {
+    static std::mutex lock;
     static Bc1Tables host;
     static bool built = false;
+    static bool uploaded[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> guard(lock);
     if (!built) { build_tables(host); built = true; }
-    return hipMemcpyToSymbolAsync(HIP_SYMBOL(kTab), &host, sizeof(host), 0, hipMemcpyHostToDevice, st);
+    if (uploaded[device]) return hipSuccess;
+    hipError_t e = hipMemcpyToSymbolAsync(HIP_SYMBOL(kTab), &host, sizeof(host), 0, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess) uploaded[device] = true;
+    return e;
 }
 
 hipError_t launch_bc1_encode(const EncodeArgs &a, const WorkSplit &w, uint32_t lanes, hipStream_t st)

@@ -1339,12 +1339,12 @@ void build_sv(HostTables &H)
 
 // Device copies of the tables, one set per device, made once per device
 // (under a lock: contexts may be created from several threads).
-static void *g_tab[64];
+static void *g_tab[kMaxDevices];
 static std::mutex g_tab_lock;
 
 hipError_t upload_bc7_tables(int device, hipStream_t st)
 {
-    if (device < 0 || device >= 64) return hipErrorInvalidDevice;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
     std::lock_guard<std::mutex> guard(g_tab_lock);
     if (g_tab[device]) return hipSuccess;
     static HostTables H;

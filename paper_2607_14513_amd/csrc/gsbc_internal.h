@@ -158,7 +158,7 @@ hipError_t launch_bc1_encode(const EncodeArgs &a, const WorkSplit &w, uint32_t l
 // enqueued (before the bucketing and emit kernels).
 hipError_t launch_bc7_encode(const EncodeArgs &a, const WorkSplit *w3, uint32_t split, hipStream_t st,
                              hipEvent_t searched = nullptr);
-hipError_t upload_bc1_tables(hipStream_t st);
+hipError_t upload_bc1_tables(int device, hipStream_t st);
 hipError_t upload_bc7_tables(int device, hipStream_t st);
 
 // ---- rate control (rate.hip)

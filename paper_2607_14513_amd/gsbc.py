@@ -19,7 +19,8 @@ FMT_AUTO, FMT_BC1, FMT_BANDS, FMT_BC7 = 0, 1, 2, 7
 ARR_BANDS, ARR_PRIM, ARR_QUAD = 0, 1, 2
 N_STREAMS = {ARR_BANDS: 16, ARR_PRIM: 1, ARR_QUAD: 4}
 
-EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_default_params",
+EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_reserve", "gsbc_arena_info",
+            "gsbc_default_params",
             "gsbc_query_sizes", "gsbc_reorder", "gsbc_reorder_degrees", "gsbc_encode", "gsbc_default_batch_tuning",
             "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_decode_eval_noalloc", "gsbc_decode_eval_view",
             "gsbc_save", "gsbc_load",
@@ -87,6 +88,8 @@ def load():
         lib.gsbc_last_error.argtypes = [P]
         lib.gsbc_last_error.restype = ctypes.c_char_p
         lib.gsbc_sync.argtypes = [P]
+        lib.gsbc_reserve.argtypes = [P, u64, u32]
+        lib.gsbc_arena_info.argtypes = [P, ctypes.POINTER(u64), ctypes.POINTER(u64)]
         lib.gsbc_default_params.argtypes = [ctypes.POINTER(Params)]
         lib.gsbc_default_params.restype = None
         lib.gsbc_query_sizes.argtypes = [u64, u32, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)]
@@ -244,6 +247,17 @@ class Context:
 
     def sync(self):
         self._check(load().gsbc_sync(self._h))
+
+    def reserve(self, n_max, n_dirs_max=0):
+        """Size the scratch arena once for scenes of up to n_max primitives and
+        decode_evals of up to n_dirs_max directions."""
+        self._check(load().gsbc_reserve(self._h, int(n_max), int(n_dirs_max)))
+
+    def arena_info(self):
+        """(arena bytes, times it has grown)."""
+        b, g = ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(load().gsbc_arena_info(self._h, ctypes.byref(b), ctypes.byref(g)))
+        return b.value, g.value
 
     def profile(self, on=True):
         """Bracket every kernel launch with HIP events on the context's stream."""

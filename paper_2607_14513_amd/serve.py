@@ -3,19 +3,27 @@
 Requests arrive as a Poisson process.  An encode request codes a scene of N
 primitives (reorder, then rate-controlled encode: band 0 BC7, the other
 bands chosen per band for an exact mean rate) and leaves its blocks resident
-on the device; a decode_eval request evaluates the SH colours of a resident
-scene at V view directions (random access into the fixed-size blocks,
-Sec. I of the paper; colour equation of Sec. II).
+on the device; a decode_eval request evaluates the SH colours of the scene
+one earlier encode request produced, at V view directions (random access
+into the fixed-size blocks, Sec. I of the paper; colour equation of Sec. II).
+A decode waits until its scene is resident.
 
 Continuous batching on one device: a dispatcher admits waiting requests in
 arrival order as soon as a slot is free and the request's peak device memory
 fits the HBM budget beside the resident scenes and the requests in flight
 (least-recently-used scenes that no request is using are evicted to make
 room).  Each slot is a worker thread with its own library context and HIP
-stream, so admitted requests overlap on the device.  Latency is measured
-from arrival to completion.  Every kernel decision is independent of what
-else runs, so a request's result is the same alone and in the mix; the
-fingerprints recorded per request let a caller check that.
+stream, its scratch arena sized once for the largest admissible request, so
+admitted requests overlap on the device and nothing is allocated by the
+library mid-stream.  With one slot the same loop is the plain path: one
+request at a time, first come first served.
+
+Per request the loop records arrival, admission, start and completion times
+and the device time between events on its slot's stream; latency runs from
+arrival to completion.  Every kernel decision is independent of what else
+runs, so a request's result is the same alone and in the mix; a 64-bit
+digest of each sampled result (and the result itself, when asked) lets a
+caller check that byte for byte.
 """
 import collections
 import math
@@ -32,15 +40,18 @@ ENCODE, DECODE = "encode", "decode_eval"
 
 
 class Request:
-    __slots__ = ("rid", "kind", "arrival", "n", "v", "offset", "scene", "admitted", "started", "done",
-                 "error", "fingerprint", "blocks_coded", "bytes_out", "mem")
+    __slots__ = ("rid", "kind", "arrival", "n", "v", "offset", "src", "scene", "admitted", "started", "done",
+                 "dev_ms", "error", "digest", "output", "blocks_coded", "bytes_out", "mem")
 
-    def __init__(self, rid, kind, arrival, n=0, v=0, offset=0):
+    def __init__(self, rid, kind, arrival, n=0, v=0, offset=0, src=-1):
         self.rid, self.kind, self.arrival, self.n, self.v, self.offset = rid, kind, arrival, n, v, offset
+        self.src = src            # decode: rid of the encode request whose scene it reads
         self.scene = None
         self.admitted = self.started = self.done = None
+        self.dev_ms = None
         self.error = None
-        self.fingerprint = None
+        self.digest = None
+        self.output = None
         self.blocks_coded = 0
         self.bytes_out = 0
         self.mem = 0
@@ -48,49 +59,76 @@ class Request:
 
 def make_requests(count, rate_hz, seed=5, n_lo=10_000, n_hi=4_000_000, v_lo=1, v_hi=1024,
                   encode_share=0.7, pool_n=4_000_000):
-    """Poisson arrivals at rate_hz; 70/30 encode/decode; N and V log-uniform."""
+    """Poisson arrivals at rate_hz; 70/30 encode/decode; N and V log-uniform;
+    each decode reads the scene of a uniformly chosen earlier encode."""
     rng = np.random.Generator(np.random.PCG64(seed))
     t = 0.0
-    out = []
+    out, encodes = [], []
     for i in range(count):
         t += rng.exponential(1.0 / rate_hz)
         if i == 0 or rng.random() < encode_share:
             n = int(round(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
             off = int(rng.integers(0, pool_n - n + 1))
             out.append(Request(i, ENCODE, t, n=n, offset=off))
+            encodes.append(i)
         else:
             v = int(round(math.exp(rng.uniform(math.log(v_lo), math.log(v_hi)))))
-            out.append(Request(i, DECODE, t, v=v))
+            src = encodes[int(rng.integers(0, len(encodes)))]
+            out.append(Request(i, DECODE, t, v=v, src=src))
     return out
 
 
+def payload_bytes(n, rate_bits=6.0):
+    """Coded bytes of an n-primitive scene at the rate (band streams 16-byte
+    aligned: k + 1 BC7 streams of 16 B per block, 15 - k BC1 of 8 B)."""
+    nblk = (n + 15) // 16
+    k = int(4 * rate_bits - 17)
+    return (k + 1) * 16 * nblk + (15 - k) * ((8 * nblk + 15) // 16 * 16)
+
+
 def encode_bytes(n):
-    """Peak device bytes of one encode request beyond its inputs: permutation,
-    textures, final blocks and the context's scratch (both candidate
-    payloads, run tables, BC7 keys)."""
+    """Peak device bytes of one encode request beyond its inputs and the
+    slot's reserved scratch: permutation, textures and the final blocks
+    (before and after trimming to the payload)."""
     npad = (n + 15) // 16 * 16
-    nblk = npad // 16
-    return 4 * n + 64 * npad + 16 * npad + (16 * (8 * nblk + 16) + 16 * 16 * nblk) + 8 * 16 * (nblk + 256) + (1 << 20)
+    return 4 * n + 64 * npad + 16 * npad + payload_bytes(n) + (1 << 20)
 
 
 def decode_bytes(n, v):
-    return 12 * n * v + 12 * v + 16 * 4 * v + (1 << 20)
+    return 12 * n * v + 12 * v + (1 << 20)
 
 
-def fingerprint(t):
-    """Order-sensitive 64-bit fingerprint of a device tensor's bytes (chunked)."""
+_M64 = (1 << 64) - 1
+
+
+def _s64(c):
+    return c - (1 << 64) if c >= 1 << 63 else c
+
+
+_K1, _K2, _K3 = _s64(0x9E3779B97F4A7C15), _s64(0xBF58476D1CE4E5B9), _s64(0x94D049BB133111EB)
+
+
+def digest(t):
+    """64-bit digest of a device tensor's bytes: every 8-byte word is mixed
+    with its position by the SplitMix64 finaliser (a bijective, non-linear
+    mix) and the mixed words are summed mod 2^64, so unlike a weighted sum no
+    pair of changes can cancel by construction.  Chunked to bound scratch."""
     flat = t.reshape(-1).view(torch.uint8)
     n = flat.numel()
-    n4 = n // 4 * 4
-    words = flat[:n4].view(torch.int32)
+    pad = (-n) % 8
+    if pad:
+        flat = torch.cat([flat, torch.zeros(pad, dtype=torch.uint8, device=flat.device)])
+    words = flat.view(torch.int64)
     h = 0
-    chunk = 1 << 26
+    chunk = 1 << 25
     for s in range(0, words.numel(), chunk):
-        w = words[s:s + chunk].to(torch.int64)
-        idx = torch.arange(s, s + w.numel(), device=w.device, dtype=torch.int64)
-        h = (h * 1_000_003 + int(((w + 0x9E3779B9) * (idx % 65_521 + 1)).sum().item())) & ((1 << 64) - 1)
-    tail = flat[n4:].to(torch.int64).sum().item() if n4 < n else 0
-    return (h ^ (tail * 0x100000001B3)) & ((1 << 64) - 1)
+        w = words[s:s + chunk]
+        z = torch.arange(s, s + w.numel(), device=w.device, dtype=torch.int64) * _K1 + w
+        z = (z ^ ((z >> 30) & ((1 << 34) - 1))) * _K2
+        z = (z ^ ((z >> 27) & ((1 << 37) - 1))) * _K3
+        z = z ^ ((z >> 31) & ((1 << 33) - 1))
+        h = (h + int(z.sum().item())) & _M64
+    return (h ^ n) & _M64
 
 
 class Scene:
@@ -105,32 +143,40 @@ class Scene:
 
 class Server:
     def __init__(self, pool_pos, pool_sh, slots=4, hbm_budget=200e9, rate_bits=6.0, device=0,
-                 fingerprint_ids=None, dirs_seed=11):
+                 digest_ids=None, keep_ids=(), dirs_seed=11, n_max=4_000_000, v_max=1024):
         self.pool_pos, self.pool_sh = pool_pos, pool_sh
         self.budget = float(hbm_budget)
         self.rate_bits = rate_bits
         self.device = torch.device("cuda", device)
-        self.fp_ids = fingerprint_ids      # request ids to fingerprint (None: all)
+        self.digest_ids = digest_ids       # request ids to digest (None: all)
+        self.keep_ids = set(keep_ids)      # request ids whose result is kept on the request
         self.dirs_seed = dirs_seed
-        self.scenes = collections.OrderedDict()   # sid -> Scene, LRU order
+        self.scenes = collections.OrderedDict()   # sid (= rid of its encode) -> Scene, LRU order
+        self.finished = {}                         # rid -> Request, for decodes' sources
         self.inflight = 0
         self.lock = threading.Lock()
         self.jobs = queue.Queue()
         self.results = queue.Queue()
         self.workers = []
         self.evicted = 0
-        self.sid_next = 0
-        self.rng = np.random.Generator(np.random.PCG64(1234))   # decode requests' scene choice
-        # contexts are created here (errors surface at once); each is then
-        # used by its own worker thread only
+        # contexts are created here (errors surface at once), each with its
+        # scratch sized for the largest admissible request; each is then used
+        # by its own worker thread only
         self.slots = []
         for k in range(slots):
             stream = torch.cuda.Stream(self.device)
-            self.slots.append((stream, gsbc.Context(self.device.index, stream=stream)))
+            ctx = gsbc.Context(self.device.index, stream=stream)
+            ctx.reserve(n_max, v_max)
+            self.slots.append((stream, ctx))
+        self.growths0 = sum(ctx.arena_info()[1] for _, ctx in self.slots)
         for k in range(slots):
             th = threading.Thread(target=self._worker, args=(k,), daemon=True)
             th.start()
             self.workers.append(th)
+
+    def arena_growths(self):
+        """Scratch growths of the slots' contexts since they were reserved."""
+        return sum(ctx.arena_info()[1] for _, ctx in self.slots) - self.growths0
 
     # ---------------------------------------------------------------- memory
     def resident_bytes(self):
@@ -156,6 +202,7 @@ class Server:
     def _worker(self, k):
         torch.cuda.set_device(self.device)
         stream, ctx = self.slots[k]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         while True:
             job = self.jobs.get()
             if job is None:
@@ -165,18 +212,24 @@ class Server:
             req.started = time.perf_counter()
             try:
                 with torch.cuda.stream(stream):
+                    e0.record(stream)
                     if req.kind == ENCODE:
                         out = self._run_encode(ctx, req)
                     else:
                         out = self._run_decode(ctx, req, scene)
+                    e1.record(stream)
                 stream.synchronize()
-                req.done = time.perf_counter()   # completion; fingerprinting is not part of it
-                if self.fp_ids is None or req.rid in self.fp_ids:
-                    req.fingerprint = fingerprint(out[0] if req.kind == ENCODE else out)
-                    stream.synchronize()
-                res = out if req.kind == ENCODE else None
-                out = None   # a decode output is released before its memory is
-                self.results.put((req, res))
+                req.done = time.perf_counter()   # completion; digests are not part of it
+                req.dev_ms = e0.elapsed_time(e1)
+                res = out[0] if req.kind == ENCODE else out
+                if self.digest_ids is None or req.rid in self.digest_ids:
+                    with torch.cuda.stream(stream):
+                        req.digest = digest(res)
+                if req.rid in self.keep_ids:
+                    req.output = res
+                out = out if req.kind == ENCODE else None
+                res = None   # a decode output is released before its memory is
+                self.results.put((req, out))
             except Exception as e:   # reported per request; the loop goes on
                 req.error = repr(e)
                 req.done = time.perf_counter()
@@ -198,6 +251,11 @@ class Server:
         return out
 
     # ---------------------------------------------------------------- dispatch
+    def _decode_source(self, req):
+        """The finished encode request a decode reads, or None while that
+        encode has not finished."""
+        return self.finished.get(req.src)
+
     def run(self, requests, time_scale=1.0, poll_s=2e-4, on_done=None, deadline_s=None):
         """Serve `requests` (arrival times in seconds from start).  A request
         still waiting for admission `deadline_s` after its arrival is dropped
@@ -206,9 +264,15 @@ class Server:
         waiting = []
         free_slots = len(self.workers)
         done = []
-        rng = self.rng
         t0 = time.perf_counter()
         total = len(requests)
+
+        def finish(req, err):
+            req.error = err
+            req.done = time.perf_counter()
+            self.finished[req.rid] = req
+            done.append(req)
+
         while len(done) < total:
             now = time.perf_counter() - t0
             while pending and pending[0].arrival * time_scale <= now:
@@ -216,34 +280,36 @@ class Server:
             if deadline_s is not None:
                 for req in [r for r in waiting if now - r.arrival * time_scale > deadline_s]:
                     waiting.remove(req)
-                    req.error = "deadline passed before admission"
-                    req.done = time.perf_counter()
-                    done.append(req)
+                    finish(req, "deadline passed before admission")
             # admit in arrival order while slots and memory allow
             i = 0
             while free_slots > 0 and i < len(waiting):
                 req = waiting[i]
                 with self.lock:
+                    sc = None
                     if req.kind == DECODE:
-                        if not self.scenes:
+                        src = self._decode_source(req)
+                        if src is None:        # its scene is still being coded
                             i += 1
                             continue
-                        keys = list(self.scenes)
-                        sc = self.scenes[keys[int(rng.integers(0, len(keys)))]]
-                        need = decode_bytes(sc.desc.n_prims, req.v)
-                    else:
-                        sc = None
-                        need = encode_bytes(req.n)
-                    if sc is not None:
+                        need = decode_bytes(src.n, req.v)
+                        sc = self.scenes.get(req.src)
+                        err = ("source scene unavailable" if src.error else
+                               "request exceeds the HBM budget" if need > self.budget else
+                               "source scene evicted" if sc is None else None)
+                        if err:
+                            waiting.pop(i)
+                            finish(req, err)
+                            continue
                         sc.users += 1          # the scene it reads is not evicted to make room
+                    else:
+                        need = encode_bytes(req.n)
                     if need > self.budget or not self._make_room(need):
                         if sc is not None:
                             sc.users -= 1
                         if need > self.budget:
-                            req.error = "request exceeds the HBM budget"
                             waiting.pop(i)
-                            req.done = time.perf_counter()
-                            done.append(req)
+                            finish(req, "request exceeds the HBM budget")
                             continue
                         i += 1
                         continue
@@ -271,10 +337,9 @@ class Server:
                     if req.kind == DECODE and req.scene in self.scenes:
                         self.scenes[req.scene].users -= 1
                     if req.kind == ENCODE and out is not None:
-                        sid = self.sid_next
-                        self.sid_next += 1
-                        self.scenes[sid] = Scene(sid, out[0], out[1])
-                        req.scene = sid
+                        self.scenes[req.rid] = Scene(req.rid, out[0], out[1])
+                        req.scene = req.rid
+                    self.finished[req.rid] = req
                 if on_done:
                     on_done(req)
                 done.append(req)
@@ -294,35 +359,55 @@ class Server:
 
     # ---------------------------------------------------------------- solo replay
     def run_alone(self, req):
-        """Run one finished request again with nothing else on the device and
-        return its fingerprint (decode requests reuse the scene they read)."""
-        r = Request(req.rid, req.kind, 0.0, n=req.n, v=req.v, offset=req.offset)
-        res = self.run([r]) if req.kind == ENCODE else None
-        if req.kind == DECODE:
-            sc = self.scenes[req.scene]
-            ctx = gsbc.Context(self.device.index)
-            out = self._run_decode(ctx, r, sc)
+        """Run one finished request again with nothing else on the device;
+        returns (digest, result).  A decode reads the same resident scene."""
+        torch.cuda.synchronize()
+        ctx = gsbc.Context(self.device.index)
+        try:
+            r = Request(req.rid, req.kind, 0.0, n=req.n, v=req.v, offset=req.offset, src=req.src)
+            if req.kind == ENCODE:
+                res = self._run_encode(ctx, r)[0]
+            else:
+                res = self._run_decode(ctx, r, self.scenes[req.scene])
             torch.cuda.synchronize()
-            fp = fingerprint(out)
+            return digest(res), res
+        finally:
             ctx.close()
-            return fp
-        return res[0].fingerprint
+
+
+def _pct(a, q):
+    return round(float(np.percentile(a, q)), 3) if len(a) else None
 
 
 def summarize(done, t_elapsed, t0):
-    lat = np.array([(r.done - (t0 + r.arrival)) * 1e3 for r in done if r.error is None])
-    enc = [r for r in done if r.kind == ENCODE and r.error is None]
-    dec = [r for r in done if r.kind == DECODE and r.error is None]
+    """Latency percentiles (arrival -> completion), their parts, throughput."""
+    ok = [r for r in done if r.error is None]
+
+    def lat(rs):
+        return np.array([(r.done - (t0 + r.arrival)) * 1e3 for r in rs])
+
+    enc = [r for r in ok if r.kind == ENCODE]
+    dec = [r for r in ok if r.kind == DECODE]
+    queue_ms = np.array([(r.admitted - (t0 + r.arrival)) * 1e3 for r in ok])
+    dispatch_ms = np.array([(r.started - r.admitted) * 1e3 for r in ok])
+    run_ms = np.array([(r.done - r.started) * 1e3 for r in ok])
+    dev_ms = np.array([r.dev_ms for r in ok])
     blocks = sum(r.blocks_coded for r in enc)
     by = sum(r.bytes_out for r in dec)
-
-    def pct(a, q):
-        return round(float(np.percentile(a, q)), 3) if len(a) else None
-    lat_e = np.array([(r.done - (t0 + r.arrival)) * 1e3 for r in enc])
-    lat_d = np.array([(r.done - (t0 + r.arrival)) * 1e3 for r in dec])
+    la = lat(ok)
     return {"requests": len(done), "errors": sum(r.error is not None for r in done),
-            "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
-            "encode_p50_ms": pct(lat_e, 50), "encode_p99_ms": pct(lat_e, 99),
-            "decode_p50_ms": pct(lat_d, 50), "decode_p99_ms": pct(lat_d, 99),
+            "p50_ms": _pct(la, 50), "p99_ms": _pct(la, 99), "mean_ms": round(float(la.mean()), 3) if len(la) else None,
+            "encode_p50_ms": _pct(lat(enc), 50), "encode_p99_ms": _pct(lat(enc), 99),
+            "decode_p50_ms": _pct(lat(dec), 50), "decode_p99_ms": _pct(lat(dec), 99),
+            # where the time goes: waiting for a slot or memory (arrival ->
+            # admission), hand-over to the slot's thread, and the slot's run
+            # (start -> completion: host work plus the device time below,
+            # which also counts time its kernels shared the GPU)
+            "breakdown_ms": {"queue_p50": _pct(queue_ms, 50), "queue_p99": _pct(queue_ms, 99),
+                             "queue_mean": round(float(queue_ms.mean()), 3) if len(ok) else None,
+                             "dispatch_p50": _pct(dispatch_ms, 50),
+                             "run_p50": _pct(run_ms, 50), "run_p99": _pct(run_ms, 99),
+                             "run_mean": round(float(run_ms.mean()), 3) if len(ok) else None,
+                             "device_p50": _pct(dev_ms, 50), "device_p99": _pct(dev_ms, 99)},
             "elapsed_s": round(t_elapsed, 3), "encode_mblocks_s": round(blocks / t_elapsed / 1e6, 3),
             "decode_gb_s": round(by / t_elapsed / 1e9, 3)}
