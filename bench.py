@@ -62,6 +62,12 @@ ALGO_OPS = {
 }
 # one launch over every group (work items per group, or all groups per block)
 ALGO_OPS["bc7_search_items"] = ALGO_OPS["bc7_search_all"] = sum(ALGO_OPS.values())
+# The evaluations the search actually executes: a 3-subset mask that recurs
+# across partitions is fitted once per mode and its SSE reused, so mode 2
+# fits 140 distinct masks of its 192 (5,984 of 8,192 evaluations) and mode 0
+# 36 of 48 (12,288 of 16,384).  The refit's evaluation is also skipped when
+# its normal equations are singular (data-dependent, not counted here).
+EXECUTED_EVALS = 3 * 32_768 + 12_288 + 5_984 + 3_072 + 1_024 + 2_048
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic_encode_step_1M_and_decode_eval_3M.json")
 
 
@@ -83,6 +89,25 @@ def profiled(name, field="bytes"):
 
 def traffic_bytes(name):
     return profiled(name, "bytes")
+
+
+def med_min(ts, scale=1.0, nd=4):
+    """Median and minimum of repeated timings (scaled, rounded)."""
+    return {"median": round(float(np.median(ts)) * scale, nd), "min": round(float(np.min(ts)) * scale, nd)}
+
+
+def kernel_ms(ctx, name, call, reps):
+    """Device time of kernel `name` in each of `reps` calls (the library's
+    HIP events on its stream), ms."""
+    ctx.profile(True)
+    ctx.profile_read()
+    ts = []
+    for _ in range(reps):
+        call()
+        k = ctx.profile_read()
+        ts.append(k[name][1] / k[name][0])
+    ctx.profile(False)
+    return ts
 
 
 def parse():
@@ -173,25 +198,38 @@ def main():
         value = blocks_per_step / (ms_step * 1e-3) / 1e6
 
         # ---- per-kernel device times of the same step (HIP events the library
-        # records on its stream around every launch)
+        # records on its stream around every launch), read back step by step
         ctx.profile(True)
         ctx.profile_read()
         nprof = max(3, args.steps)
+        per_run = []
         for _ in range(nprof):
             step()
-        kern = ctx.profile_read()
+            per_run.append(ctx.profile_read())
         ctx.profile(False)
+        kern = {}
+        for r in per_run:
+            for k, (cnt, ms) in r.items():
+                c0, m0 = kern.get(k, (0, 0.0))
+                kern[k] = (c0 + cnt, m0 + ms)
         per_step = {k: v[1] / nprof for k, v in kern.items()}
         dom = max(per_step, key=per_step.get)
         launches = kern[dom][0] / nprof
         dom_s = per_step[dom] / launches * 1e-3                     # average launch, s
+        dom_launch_ms = [r[dom][1] / r[dom][0] for r in per_run if dom in r]
         units = 16 * nblk                                           # blocks per launch
         work = ALGO_OPS.get(dom)
         traffic = traffic_bytes(dom)
         roof = {"kernel": dom, "bound": "alu", "achieved": work * units / dom_s / 1e12 if work else None,
                 "peak": VALU_PEAK / 1e12, "unit": "Tops/s",
                 "frac": work * units / dom_s / VALU_PEAK if work else None, "traffic": traffic,
-                "launch_ms": round(dom_s * 1e3, 4), "algorithmic_ops_per_block": work, "blocks_per_launch": units}
+                "launch_ms": round(dom_s * 1e3, 4), "launch_ms_median": round(float(np.median(dom_launch_ms)), 4),
+                "launch_ms_min": round(float(np.min(dom_launch_ms)), 4),
+                "algorithmic_ops_per_block": work, "blocks_per_launch": units}
+        if dom in ("bc7_search_items", "bc7_search_all"):
+            # the same floor over the evaluations the kernel executes
+            roof["executed_ops_per_block"] = EXECUTED_EVALS * OPS_PER_EVAL
+            roof["frac_executed"] = EXECUTED_EVALS * OPS_PER_EVAL * units / dom_s / VALU_PEAK
 
         # ---- counter-measured VALU issue utilisation of the encoders: the
         # committed SQ_INSTS_VALU count of a launch over the live launch time
@@ -215,7 +253,8 @@ def main():
                 e1.record(stream)
                 torch.cuda.synchronize()
                 ts.append(e0.elapsed_time(e1) * 1e-3)
-            rates[name] = 16 * nblk / float(np.mean(ts)) / 1e6
+            rates[name] = 16 * nblk / float(np.median(ts)) / 1e6
+            rates[name + "_ms"] = med_min(ts, 1e3)
 
         # ---- per-band PSNR of the decoded coefficient texels (sorted order and
         # the input order), 10 log10(255^2 / MSE) over all RGB texels
@@ -374,9 +413,11 @@ def main():
             re_s = float(np.median(t_re))
             large_enc = {"workload": "3,145,728 primitives (256 clusters, 256-component DC mixture, seed 3), "
                                      "6 bits/texel: band 0 BC7, 7 of bands 1..15 BC7, the rest BC1",
-                         "reorder_ms": round(re_s * 1e3, 3),
+                         "reorder_ms": round(re_s * 1e3, 3), "reorder_ms_min": round(float(np.min(t_re)) * 1e3, 3),
                          "reorder_gb_s": round(re_bytes_per_prim * c3["n"] / re_s / 1e9, 1),
+                         "reorder_hbm_frac": round(re_bytes_per_prim * c3["n"] / re_s / HBM_PEAK, 4),
                          "encode_ms": round(float(np.median(t_en)) * 1e3, 3),
+                         "encode_ms_min": round(float(np.min(t_en)) * 1e3, 3),
                          "blocks_coded": 2 * 16 * nblk3,
                          "encode_mblocks_s": round(2 * 16 * nblk3 / float(np.median(t_en)) / 1e6, 2),
                          "payload_bytes": int(dd2.payload_bytes), "budget_bytes": budget,
@@ -386,29 +427,28 @@ def main():
             out3 = torch.empty((c3["dirs"], c3["n"], 3), dtype=torch.float32, device=dev)
             ctx.decode_eval(b3, dd2, dirs3, out=out3)
             torch.cuda.synchronize()
-            ctx.profile(True)
-            ctx.profile_read()
-            for i in range(3):
-                ctx.decode_eval(b3, dd2, dirs3, out=out3)
-            kd = ctx.profile_read()
-            ctx.profile(False)
-            de_s = kd["decode_eval"][1] / kd["decode_eval"][0] * 1e-3
+            t_de = kernel_ms(ctx, "decode_eval", lambda: ctx.decode_eval(b3, dd2, dirs3, out=out3), 5)
+            de_s = float(np.mean(t_de)) * 1e-3
+            # the same kernel at half the directions: T(V) = P + V s splits a
+            # launch into the part that does not grow with the directions
+            # (each workgroup's decode prologue, launch and tail) and the
+            # per-direction evaluation and stores
+            half = c3["dirs"] // 2
+            t_half = kernel_ms(ctx, "decode_eval", lambda: ctx.decode_eval(b3, dd2, dirs3[:half], out=out3[:half]), 5)
+            th, tf_ = float(np.median(t_half)), float(np.median(t_de))
+            split = {"dirs": [half, c3["dirs"]], "ms": [round(th, 4), round(tf_, 4)],
+                     "fixed_ms": round(2 * th - tf_, 4), "per_direction_us": round((tf_ - th) / half * 1e3, 4)}
             # every primitive's colour from one view position (its own direction)
             pos3d = torch.from_numpy(pos3).to(dev)
             view = (0.5, 0.5, 2.5)
             ctx.decode_eval_view(b3, dd2, pos3d, p3, view)
-            ctx.profile(True)
-            ctx.profile_read()
-            for i in range(3):
-                ov = ctx.decode_eval_view(b3, dd2, pos3d, p3, view)
-            kv = ctx.profile_read()
-            ctx.profile(False)
-            view_s = kv["decode_eval_view"][1] / kv["decode_eval_view"][0] * 1e-3
+            t_view = kernel_ms(ctx, "decode_eval_view", lambda: ctx.decode_eval_view(b3, dd2, pos3d, p3, view), 3)
+            view_s = float(np.median(t_view)) * 1e-3
             view_leg = {"workload": "3,145,728 primitives, one view position, each primitive at its own direction",
-                        "ms": round(view_s * 1e3, 4), "gslots_s": round(c3["n"] / view_s / 1e9, 3),
+                        "ms": med_min(t_view), "gslots_s": round(c3["n"] / view_s / 1e9, 3),
                         "bytes": int(dd2.payload_bytes + c3["n"] * (12 + 4 + 12))}
             view_leg["gb_s"] = round(view_leg["bytes"] / view_s / 1e9, 1)
-            del ov, pos3d, p3
+            del pos3d, p3
             # context: a plain device fill of the same output (write ceiling)
             tf = []
             for i in range(3):
@@ -418,14 +458,15 @@ def main():
                 e1.record(stream)
                 torch.cuda.synchronize()
                 tf.append(e0.elapsed_time(e1) * 1e-3)
-            fill_gbps = out3.numel() * 4 / float(np.mean(tf)) / 1e9
+            fill_gbps = out3.numel() * 4 / float(np.median(tf)) / 1e9
             de_bytes = c3["dirs"] * c3["n"] * 12 + dd2.payload_bytes + c3["dirs"] * 12
             tr_de = traffic_bytes("k_decode_eval")
             roof_de = {"kernel": "k_decode_eval", "bound": "hbm", "achieved": de_bytes / de_s / 1e9,
                        "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": de_bytes / de_s / HBM_PEAK,
-                       "traffic": tr_de, "launch_ms": de_s * 1e3,
+                       "traffic": tr_de, "launch_ms": de_s * 1e3, "launch_ms_stats": med_min(t_de),
                        "workload": "3,145,728 primitives x 1,024 directions, 6 bits/texel",
-                       "plain_fill_gbps": round(fill_gbps, 1), "view": view_leg, "encode": large_enc}
+                       "split": split, "plain_fill_gbps": round(fill_gbps, 1),
+                       "fill_ms": med_min(tf, 1e3), "view": view_leg, "encode": large_enc}
             del out3, b3, pos3_d
             torch.cuda.empty_cache()
         batch = None if args.no_batch else batch_leg(ctx, stream, dev, args.batch_scenes, max(3, args.steps))
@@ -442,11 +483,13 @@ def main():
                                "reorder + BC1 and BC7 encode of all 16 bands + 6 bits/texel band choice "
                                "+ decode_eval at 64 directions",
                    "n_prims": n, "blocks_per_format": 16 * nblk, "rate_bits_per_texel": rate, "dirs": V},
-        "stages_ms": {"reorder": round(float(stage[:, 0].mean()), 3),
-                      "encode_auto": round(float(stage[:, 1].mean()), 3),
-                      "decode_eval": round(float(stage[:, 2].mean()), 3)},
+        "stages_ms": {"reorder": med_min(stage[:, 0], 1.0, 3),
+                      "encode_auto": med_min(stage[:, 1], 1.0, 3),
+                      "decode_eval": med_min(stage[:, 2], 1.0, 3),
+                      "step": med_min(stage.sum(axis=1), 1.0, 3)},
         "bc7_encode_mblocks_s": round(rates["bc7"], 3),
         "bc1_encode_mblocks_s": round(rates["bc1"], 3),
+        "format_encode_ms": {"bc7": rates["bc7_ms"], "bc1": rates["bc1_ms"]},
         "psnr_db_per_band": psnr,
         "arrangements": arrangements,
         "degree_classes": degrees,
@@ -624,12 +667,45 @@ def cpu_baseline(pos, sh, dirs, rate):
     O.decode_eval(payload, off, fmt, vmin, vmax, dirs, renum, with_scale=False)
     t_de = (time.perf_counter() - t) / len(slots)
     step = t_reorder + 16 * nblk * (t_bc1 + t_bc7) + n * t_de
+    # the same oracle on one thread, on a smaller sample (the reorder is
+    # single-threaded either way, so its full-scene time is reused)
+    O.set_threads(1)
+    S1 = 256
+    t = time.perf_counter()
+    O.bc1_encode(sample[:S1])
+    t1_bc1 = (time.perf_counter() - t) / S1
+    t = time.perf_counter()
+    O.bc7_encode(sample[:S1])
+    t1_bc7 = (time.perf_counter() - t) / S1
+    t = time.perf_counter()
+    O.decode_eval(payload, off, fmt, vmin, vmax, dirs, renum[:2048], with_scale=False)
+    t1_de = (time.perf_counter() - t) / 2048
+    O.set_threads(threads)
+    step1 = t_reorder + 16 * nblk * (t1_bc1 + t1_bc7) + n * t1_de
     return {"value": round(2 * 16 * nblk / step / 1e6, 6), "unit": "Mblocks/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"full reorder of {n} primitives ({t_reorder:.2f} s); BC1 and BC7 on {S} sampled "
                       f"blocks ({t_bc1 * 1e3:.3f} / {t_bc7 * 1e3:.3f} ms per block); decode_eval of "
                       f"{len(slots)} slots x {len(dirs)} directions; scaled to one step of "
-                      f"{2 * 16 * nblk} blocks ({step:.1f} s)"}
+                      f"{2 * 16 * nblk} blocks ({step:.1f} s)",
+            "single_thread": {
+                "value": round(2 * 16 * nblk / step1 / 1e6, 6), "unit": "Mblocks/s", "cores": 1,
+                "sample": f"BC1 and BC7 on {S1} of the sampled blocks ({t1_bc1 * 1e3:.3f} / {t1_bc7 * 1e3:.3f} "
+                          f"ms per block); decode_eval of 2048 slots x {len(dirs)} directions; the reorder "
+                          f"time above; scaled to one step ({step1:.1f} s)"}}
+
+
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), else the platform's."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
 
 
 if __name__ == "__main__":
