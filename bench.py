@@ -404,12 +404,13 @@ def main():
                 t_en.append(e1.elapsed_time(e2) * 1e-3)
             nblk3 = dd.blocks_per_stream
             budget = int(c3["rate"] * 16 * 16 * nblk3 // 8)       # bits per texel x texels, in bytes
-            # reorder bytes per primitive: range pass (SH 192 + position 12),
-            # key pass (position 12 + DC 12 read, key 8 + index 4 written),
-            # three sort passes (key 8 read for the histogram, key and index
-            # 12 read and 12 written by the scatter), gather (perm 4 + SH 192
-            # read, texels 64 written)
-            re_bytes_per_prim = 204 + 36 + 3 * 32 + 260
+            # reorder bytes per primitive: range pass (SH 192 + position 12
+            # read, band-0 colour 12 written), key pass (position 12 + colour
+            # 12 read, key 8 written), four sort passes of 8-9 bit digits
+            # (key 8 read, key 8 + index 4 written; then key and index 12 read
+            # and 12 written twice; then 12 read and the index 4 written),
+            # gather (perm 4 + SH 192 read, texels 64 written)
+            re_bytes_per_prim = 216 + 32 + (20 + 24 + 24 + 16) + 260
             re_s = float(np.median(t_re))
             large_enc = {"workload": "3,145,728 primitives (256 clusters, 256-component DC mixture, seed 3), "
                                      "6 bits/texel: band 0 BC7, 7 of bands 1..15 BC7, the rest BC1",

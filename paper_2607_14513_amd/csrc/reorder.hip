@@ -6,9 +6,13 @@
 //            integer atomics on an order-preserving encoding of the floats;
 //   keys     (Morton cell of the position) << 24 | RGB bit interleave of the
 //            quantised band-0 colour (Sec. III-C, Fig. Bit4Scan);
-//   sort     stable LSD radix sort, 11-bit digits, per-wave tiles with
-//            LDS-local counters and wave-ballot ranking (stable by
-//            construction: a wave walks its tile in order);
+//   sort     stable LSD radix sort, one launch per digit of 8 or 9 bits:
+//            each workgroup takes the next 4,096-key tile, ranks it stably
+//            (wave ballots, waves in order), finds the tile's place among
+//            all earlier tiles by decoupled look-back on per-tile digit
+//            counts, sorts the tile in LDS and writes each digit's keys as
+//            one contiguous run; the digit totals of every pass come from
+//            one histogram taken while the keys are made;
 //   pack     gather each slot's 48 coefficients, quantise, and write band k
 //            of slot s to texel zigzag(s % 16) of block s / 16 (Fig. SetupD,
 //            Fig. ZigZagScan).
@@ -19,12 +23,33 @@
 namespace gsbc {
 namespace {
 
-constexpr int kDigitBits = 11;
-constexpr int kDigits = 1 << kDigitBits;
-constexpr int kWaveItems = 16;                 // keys per lane per tile
-constexpr int kTile = 64 * kWaveItems;         // keys per wave tile
-constexpr int kChunkTiles = 16;                // tiles per chunk of the column scan
+constexpr int kSortKPT = 16;                   // keys per thread of a sort tile
+constexpr int kSortTile = 256 * kSortKPT;      // keys per tile (one workgroup)
+constexpr int kMaxDigitBits = 9;
+constexpr int kMaxBins = 1 << kMaxDigitBits;
+constexpr int kMaxPasses = 7;                  // 56-bit keys (grid 10 bits, degree class) in 9-bit digits
 constexpr int kRangeBlock = 384;               // multiple of 12 and 3
+constexpr uint32_t kSpinLimit = 1u << 22;      // look-back polls before a tile gives up (about 0.1 s)
+
+// Digits of each pass, low to high: ceil(bits / 9) passes of near-equal width.
+struct SortPlan {
+    int passes;
+    int shift[kMaxPasses], bits[kMaxPasses];
+};
+
+SortPlan plan_sort(int key_bits)
+{
+    SortPlan P{};
+    P.passes = (key_bits + kMaxDigitBits - 1) / kMaxDigitBits;
+    int at = 0;
+    for (int p = 0; p < P.passes; p++) {
+        const int w = (key_bits - at) / (P.passes - p);   // remaining bits spread over the remaining passes
+        P.shift[p] = at;
+        P.bits[p] = w + ((key_bits - at) % (P.passes - p) ? 1 : 0);
+        at += P.bits[p];
+    }
+    return P;
+}
 
 __device__ __forceinline__ uint32_t ord_of(float f)
 {
@@ -58,15 +83,20 @@ __device__ __forceinline__ uint32_t quant8(float x, float vmin, float s)
     return (uint32_t)v;
 }
 
-// acc layout: [0..15] band min, [16..31] band max, [32..34] pos min, [35..37] pos max
-__global__ void k_range_init(uint32_t *acc)
+// acc layout: [0..15] band min, [16..31] band max, [32..34] pos min, [35..37] pos max.
+// Also clears the sort's digit totals and tile counters (meta, meta_words).
+__global__ __launch_bounds__(256) void k_range_init(uint32_t *acc, uint32_t *meta, uint32_t meta_words)
 {
-    int t = threadIdx.x;
+    const int t = threadIdx.x;
     if (t < 38) acc[t] = (t < 16 || (t >= 32 && t < 35)) ? 0xFFFFFFFFu : 0u;
+    for (uint32_t e = t; e < meta_words; e += 256) meta[e] = 0u;
 }
 
+// dc (when not null): each primitive's band-0 colour (times its opacity),
+// three floats, for the key pass.
 __global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4, const float *opacity,
-                                                               const float *pos, uint64_t n, uint32_t *acc)
+                                                               const float *pos, uint64_t n, uint32_t *acc,
+                                                               float *dc)
 {
     __shared__ uint32_t s_acc[38];
     if (threadIdx.x < 38) s_acc[threadIdx.x] = (threadIdx.x < 16 || (threadIdx.x >= 32 && threadIdx.x < 35)) ? 0xFFFFFFFFu : 0u;
@@ -89,6 +119,12 @@ __global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4
         for (int c = 0; c < 4; c++) {
             if ((4 * j + c) / 3 == bandA) { minA = fminf(minA, f[c]); maxA = fmaxf(maxA, f[c]); }
             else { minB = fminf(minB, f[c]); maxB = fmaxf(maxB, f[c]); }
+        }
+        if (j == 0 && dc) {   // floats 0..2 of the primitive: its band-0 colour
+            float *o = dc + 3 * (q / 12);
+            o[0] = f[0];
+            o[1] = f[1];
+            o[2] = f[2];
         }
     };
     // four loads in flight per lane, then the remainder one at a time
@@ -144,6 +180,7 @@ __global__ void k_range_final(const uint32_t *acc, const uint32_t *cov, uint32_t
         float range = hi - lo;
         r->scale[k] = range > 0.0f ? 255.0f / range : 0.0f;
     }
+    if (k == 0) r->sort_fault = 0u;
     if (k < 3) {
         float lo = canon_zero(float_of(acc[32 + k])), hi = canon_zero(float_of(acc[35 + k]));
         r->lo[k] = lo;
@@ -153,189 +190,289 @@ __global__ void k_range_final(const uint32_t *acc, const uint32_t *cov, uint32_t
     }
 }
 
-// DEG: also the degree class (the largest SH degree with a coefficient above
-// tau in magnitude, 0 if none) above the cell and colour fields, and the
-// class counts.
+// Keys, 4,096 per workgroup: (Morton cell << 24) | colour interleave, and
+// the digit counts of every sort pass.  DEG: also the degree class (the
+// largest SH degree with a coefficient above tau in magnitude, 0 if none)
+// above the cell and colour fields, and the class counts.  The workgroups
+// also clear the sort's look-back words (status, status_words).
 template <bool DEG>
-__global__ __launch_bounds__(256) void k_keys(const float *pos, const float *sh, const float *opacity, uint64_t n,
-                                              uint32_t grid_bits, const RangeRec *r,
-                                              uint64_t *keys, uint32_t *vals, float tau, uint32_t *class_count)
+__global__ __launch_bounds__(256) void k_keys(const float *pos, const float *dc, const float *sh,
+                                              const float *opacity, uint64_t n, uint32_t grid_bits,
+                                              const RangeRec *r, SortPlan plan, uint64_t *keys, uint32_t *gcount,
+                                              uint64_t *status, uint64_t status_words, float tau,
+                                              uint32_t *class_count)
 {
+    __shared__ uint32_t hist[kMaxPasses][kMaxBins];
     __shared__ uint32_t cls[4];
-    if (DEG) {
-        if (threadIdx.x < 4) cls[threadIdx.x] = 0;
-        __syncthreads();
+    for (int e = threadIdx.x; e < kMaxPasses * kMaxBins; e += 256) (&hist[0][0])[e] = 0u;
+    if (DEG && threadIdx.x < 4) cls[threadIdx.x] = 0u;
+    {
+        const uint64_t per = (status_words + gridDim.x - 1) / gridDim.x;
+        const uint64_t z0 = (uint64_t)blockIdx.x * per, z1 = min(status_words, z0 + per);
+        for (uint64_t z = z0 + threadIdx.x; z < z1; z += 256) status[z] = 0ull;
     }
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (!DEG && i >= n) return;
-    if (i < n) {
+    __syncthreads();
     const uint32_t cmax = (1u << grid_bits) - 1u;
-    uint32_t cell[3];
+    for (int it = 0; it < kSortKPT; it++) {
+        const uint64_t i = (uint64_t)blockIdx.x * kSortTile + (uint64_t)it * 256 + threadIdx.x;
+        if (i >= n) break;
+        uint32_t cell[3];
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        float t = pos[i * 3 + a] - r->lo[a];
-        float u = t * r->cell_scale[a];
-        uint32_t v = (uint32_t)floorf(u);
-        cell[a] = v < cmax ? v : cmax;
-    }
-    const float *dc = sh + i * 48;
-    const float mu = opacity ? opacity[i] : 1.0f;
-    float d0 = dc[0], d1 = dc[1], d2 = dc[2];
-    if (opacity) { d0 = mu * d0; d1 = mu * d1; d2 = mu * d2; }
-    uint32_t q0 = quant8(d0, r->vmin[0], r->scale[0]);
-    uint32_t q1 = quant8(d1, r->vmin[0], r->scale[0]);
-    uint32_t q2 = quant8(d2, r->vmin[0], r->scale[0]);
-    uint64_t chunk = spread3(cell[0]) | (spread3(cell[1]) << 1) | (spread3(cell[2]) << 2);
-    uint32_t colour = (spread3(q0) << 2) | (spread3(q1) << 1) | spread3(q2);
-    uint64_t key = (chunk << 24) | colour;
-    if (DEG) {
-        const float4 *p4 = reinterpret_cast<const float4 *>(dc);
-        float f[48];
+        for (int a = 0; a < 3; a++) {
+            float t = pos[i * 3 + a] - r->lo[a];
+            float u = t * r->cell_scale[a];
+            uint32_t v = (uint32_t)floorf(u);
+            cell[a] = v < cmax ? v : cmax;
+        }
+        const float mu = opacity ? opacity[i] : 1.0f;
+        float d0, d1, d2;
+        if (DEG) {
+            d0 = sh[i * 48];
+            d1 = sh[i * 48 + 1];
+            d2 = sh[i * 48 + 2];
+            if (opacity) { d0 = mu * d0; d1 = mu * d1; d2 = mu * d2; }
+        } else {   // already times the opacity
+            d0 = dc[3 * i];
+            d1 = dc[3 * i + 1];
+            d2 = dc[3 * i + 2];
+        }
+        const uint32_t q0 = quant8(d0, r->vmin[0], r->scale[0]);
+        const uint32_t q1 = quant8(d1, r->vmin[0], r->scale[0]);
+        const uint32_t q2 = quant8(d2, r->vmin[0], r->scale[0]);
+        const uint64_t chunk = spread3(cell[0]) | (spread3(cell[1]) << 1) | (spread3(cell[2]) << 2);
+        const uint32_t colour = (spread3(q0) << 2) | (spread3(q1) << 1) | spread3(q2);
+        uint64_t key = (chunk << 24) | colour;
+        if (DEG) {
+            const float4 *p4 = reinterpret_cast<const float4 *>(sh + i * 48);
+            float f[48];
 #pragma unroll
-        for (int c = 0; c < 12; c++) {
-            const float4 v = p4[c];
-            f[4 * c] = v.x; f[4 * c + 1] = v.y; f[4 * c + 2] = v.z; f[4 * c + 3] = v.w;
-        }
-        uint32_t L = 0;
+            for (int c = 0; c < 12; c++) {
+                const float4 v = p4[c];
+                f[4 * c] = v.x; f[4 * c + 1] = v.y; f[4 * c + 2] = v.z; f[4 * c + 3] = v.w;
+            }
+            uint32_t L = 0;
 #pragma unroll
-        for (int e = 3; e < 48; e++) {       // bands 1..15; band k has degree floor(sqrt(k))
-            const int k = e / 3, l = k >= 9 ? 3 : k >= 4 ? 2 : 1;
-            const float x = opacity ? mu * f[e] : f[e];
-            if (fabsf(x) > tau) L = L > (uint32_t)l ? L : (uint32_t)l;
+            for (int e = 3; e < 48; e++) {       // bands 1..15; band k has degree floor(sqrt(k))
+                const int k = e / 3, l = k >= 9 ? 3 : k >= 4 ? 2 : 1;
+                const float x = opacity ? mu * f[e] : f[e];
+                if (fabsf(x) > tau) L = L > (uint32_t)l ? L : (uint32_t)l;
+            }
+            key |= (uint64_t)L << (24 + 3 * grid_bits);
+            atomicAdd(&cls[L], 1u);
         }
-        key |= (uint64_t)L << (24 + 3 * grid_bits);
-        atomicAdd(&cls[L], 1u);
-    }
-    keys[i] = key;
-    vals[i] = (uint32_t)i;
-    }
-    if (DEG) {
-        __syncthreads();
-        if (threadIdx.x < 4 && cls[threadIdx.x]) atomicAdd(&class_count[threadIdx.x], cls[threadIdx.x]);
-    }
-}
-
-// Digit counts of each wave tile; hist is tile-major: hist[tile][digit].
-__global__ __launch_bounds__(256) void k_radix_hist(const uint64_t *keys, uint64_t n, int shift,
-                                                    uint32_t ntiles, uint32_t *hist)
-{
-    __shared__ uint32_t cnt[4][kDigits];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int d = lane; d < kDigits; d += 64) cnt[w][d] = 0;
-    __syncthreads();
-    const uint32_t tile = blockIdx.x * 4 + w;
-    if (tile < ntiles) {
-        const uint64_t base = (uint64_t)tile * kTile;
-        for (int it = 0; it < kWaveItems; it++) {
-            uint64_t i = base + (uint64_t)it * 64 + lane;
-            if (i < n) atomicAdd(&cnt[w][(keys[i] >> shift) & (kDigits - 1)], 1u);
-        }
+        keys[i] = key;
+#pragma unroll
+        for (int p = 0; p < kMaxPasses; p++)
+            if (p < plan.passes) atomicAdd(&hist[p][(uint32_t)(key >> plan.shift[p]) & ((1u << plan.bits[p]) - 1u)], 1u);
     }
     __syncthreads();
-    if (tile < ntiles)
-        for (int d = lane; d < kDigits; d += 64) hist[(uint64_t)tile * kDigits + d] = cnt[w][d];
+#pragma unroll
+    for (int p = 0; p < kMaxPasses; p++)
+        if (p < plan.passes)
+            for (int d = threadIdx.x; d < (1 << plan.bits[p]); d += 256)
+                if (hist[p][d]) atomicAdd(&gcount[p * kMaxBins + d], hist[p][d]);
+    if (DEG && threadIdx.x < 4 && cls[threadIdx.x]) atomicAdd(&class_count[threadIdx.x], cls[threadIdx.x]);
 }
 
-// Column scan in two levels (grid: chunks x digit blocks).  Chunk level:
-// thread (digit d, chunk c) turns its kChunkTiles counts into exclusive
-// prefixes within the chunk (all loads issued before any store) and leaves
-// the chunk total in ctot[c][d].
-__global__ __launch_bounds__(256) void k_radix_chunkscan(uint32_t *hist, uint32_t ntiles, uint32_t *ctot)
+// Look-back words of (tile t, digit d): 0 = not yet written; else bits
+// 62..63 = 1 (partial: the count over tiles t - span .. t) or 2 (inclusive:
+// the count over tiles 0 .. t), bits 32..61 = span, low 32 bits = count.
+// A tile writes its own count first (span 0), then wider partial sums as
+// its look-back gathers them, then its inclusive count; a later tile that
+// reads a partial word jumps past the span, so the sums spread to later
+// tiles in a logarithmic number of steps even when every tile starts at
+// once.  Each word carries all it says, so its device-scope loads and stores
+// need no ordering (acquire loads would invalidate the cache on every poll).
+constexpr uint64_t kPartial = 1ull << 62, kInclusive = 2ull << 62;
+constexpr int kLookBack = 1;   // earlier tiles' words read per look-back step and digit (wider windows measured slower)
+
+__device__ __forceinline__ uint64_t lb_load(const uint64_t *p)
 {
-    const int d = blockIdx.y * blockDim.x + threadIdx.x;
-    const uint32_t t0 = blockIdx.x * kChunkTiles;
-    uint32_t c[kChunkTiles];
-#pragma unroll
-    for (int j = 0; j < kChunkTiles; j++) c[j] = t0 + j < ntiles ? hist[(uint64_t)(t0 + j) * kDigits + d] : 0u;
-    uint32_t run = 0;
-#pragma unroll
-    for (int j = 0; j < kChunkTiles; j++) {
-        if (t0 + j < ntiles) hist[(uint64_t)(t0 + j) * kDigits + d] = run;
-        run += c[j];
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One pass of the stable LSD sort over digit (shift, bits).  Tiles are
+// taken in order from tile_ctr, so every earlier tile belongs to a running
+// or finished workgroup, which writes its counts before it waits on anything.
+// vin null: the values are the element indices; kout null: only the values
+// are written (the last pass, into perm).  zero_status (null on the first
+// pass): the look-back words the next pass will use, cleared here.  A tile
+// whose look-back finds no count within kSpinLimit polls sets *fault and
+// goes on (wrong order, no hang); the host reports it.
+__global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
+                                                   uint32_t *vout, uint64_t n, int shift, int bits,
+                                                   const uint32_t *gcount, uint64_t *status, uint64_t *zero_status,
+                                                   uint64_t status_words, uint32_t *tile_ctr, uint32_t *fault)
+{
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sval[kSortTile];
+    __shared__ uint32_t ctr[4][kMaxBins];    // per wave: running digit counts, then the wave's offset in the tile
+    __shared__ uint32_t lstart[kMaxBins];    // first tile-local sorted position of each digit
+    __shared__ int32_t gadj[kMaxBins];       // output index of sorted position j of digit d: gadj[d] + j
+    __shared__ uint32_t wsum[4][2];
+    __shared__ uint32_t s_tile;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
+    for (int e = tid; e < 4 * kMaxBins; e += 256) (&ctr[0][0])[e] = 0u;
+    if (zero_status) {
+        const uint64_t per = (status_words + gridDim.x - 1) / gridDim.x;
+        const uint64_t z0 = (uint64_t)blockIdx.x * per, z1 = min(status_words, z0 + per);
+        for (uint64_t z = z0 + tid; z < z1; z += 256) zero_status[z] = 0ull;
     }
-    ctot[(uint64_t)blockIdx.x * kDigits + d] = run;
-}
-
-// Chunk totals level: per digit, exclusive prefixes over the chunks (in
-// place, sixteen loads in flight) and the digit total.
-__global__ __launch_bounds__(256) void k_radix_chunkprefix(uint32_t *ctot, uint32_t nchunks, uint32_t *total)
-{
-    const int d = blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t run = 0;
-    for (uint32_t c0 = 0; c0 < nchunks; c0 += 16) {
-        uint32_t c[16];
-#pragma unroll
-        for (int j = 0; j < 16; j++) c[j] = c0 + j < nchunks ? ctot[(uint64_t)(c0 + j) * kDigits + d] : 0u;
-#pragma unroll
-        for (int j = 0; j < 16; j++) {
-            if (c0 + j < nchunks) ctot[(uint64_t)(c0 + j) * kDigits + d] = run;
-            run += c[j];
-        }
-    }
-    total[d] = run;
-}
-
-// Exclusive scan of the digit totals (one workgroup of 1024 threads, two
-// digits each): pair sums, an inclusive scan over the 1024 pairs in LDS
-// (ten doubling steps), then each pair's exclusive offsets.
-__global__ __launch_bounds__(1024) void k_radix_digitscan(uint32_t *total)
-{
-    __shared__ uint32_t s[1024];
-    const int t = threadIdx.x;
-    const uint32_t a = total[2 * t], b = total[2 * t + 1];
-    s[t] = a + b;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t x = t >= off ? s[t - off] : 0u;
-        __syncthreads();
-        s[t] += x;
-        __syncthreads();
-    }
-    const uint32_t before = s[t] - (a + b);
-    total[2 * t] = before;
-    total[2 * t + 1] = before + a;
-}
-
-// Stable scatter: each wave walks its tile in order; lanes with equal digits
-// are ranked by lane id through ballots over the digit bits.
-__global__ __launch_bounds__(256) void k_radix_scatter(const uint64_t *keys_in, const uint32_t *vals_in,
-                                                       uint64_t n, int shift, uint32_t ntiles,
-                                                       const uint32_t *hist, const uint32_t *chunk_base,
-                                                       const uint32_t *digit_base,
-                                                       uint64_t *keys_out, uint32_t *vals_out)
-{
-    __shared__ uint32_t ctr[4][kDigits];
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const uint32_t tile = blockIdx.x * 4 + w;
-    if (tile >= ntiles) return;   // whole wave leaves; no block barrier below
-    const uint32_t *cb = chunk_base + (uint64_t)(tile / kChunkTiles) * kDigits;
-    for (int d = lane; d < kDigits; d += 64)
-        ctr[w][d] = hist[(uint64_t)tile * kDigits + d] + cb[d] + digit_base[d];
-    __builtin_amdgcn_wave_barrier();
-    const uint64_t base = (uint64_t)tile * kTile;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    for (int it = 0; it < kWaveItems; it++) {
-        uint64_t i = base + (uint64_t)it * 64 + lane;
-        bool valid = i < n;
-        uint64_t key = valid ? keys_in[i] : 0;
-        uint32_t val = valid ? vals_in[i] : 0;
-        uint32_t d = (uint32_t)(key >> shift) & (kDigits - 1);
-        uint64_t peers = __ballot(valid);
-        if (peers == 0) break;
+    const uint32_t tile = s_tile;
+    const uint32_t nbins = 1u << bits, mask = nbins - 1u;
+    const uint64_t t0 = (uint64_t)tile * kSortTile;
+    // wave w holds tile elements [w T/4, (w + 1) T/4), 64 consecutive per step
+    const uint64_t wbase = t0 + (uint64_t)w * (kSortTile / 4);
+    const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+    uint64_t key[kSortKPT];
+    uint32_t val[kSortKPT], rk[kSortKPT];
 #pragma unroll
-        for (int b = 0; b < kDigitBits; b++) {
-            uint64_t bal = __ballot((d >> b) & 1);
-            peers &= ((d >> b) & 1) ? bal : ~bal;
+    for (int it = 0; it < kSortKPT; it++) {
+        const uint64_t e = wbase + (uint64_t)it * 64 + lane;
+        const bool ok = e < n;
+        key[it] = ok ? kin[e] : 0ull;
+        val[it] = ok ? (vin ? vin[e] : (uint32_t)e) : 0u;
+    }
+    // rank of each key among the equal digits before it in its wave
+#pragma unroll
+    for (int it = 0; it < kSortKPT; it++) {
+        const bool ok = wbase + (uint64_t)it * 64 + lane < n;
+        const uint32_t d = (uint32_t)(key[it] >> shift) & mask;
+        uint64_t peers = __ballot(ok);
+        for (int b = 0; b < bits; b++) {
+            const uint64_t bal = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? bal : ~bal;
         }
-        if (valid) {
-            uint32_t rank = (uint32_t)__popcll(peers & below);
-            uint32_t off = ctr[w][d] + rank;
-            keys_out[off] = key;
-            vals_out[off] = val;
-        }
+        const uint32_t before = ok ? ctr[w][d] : 0u;
+        rk[it] = before + (uint32_t)__popcll(peers & below);
         __builtin_amdgcn_wave_barrier();
-        if (valid && (peers & below) == 0) ctr[w][d] += (uint32_t)__popcll(peers);
+        if (ok && (peers & below) == 0) ctr[w][d] = before + (uint32_t)__popcll(peers);
         __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+    // thread tid: digits 2 tid and 2 tid + 1.  Wave offsets within the tile,
+    // the tile's counts (published at once), tile-local and global prefixes.
+    uint32_t cnt[2], g[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const uint32_t d = 2 * tid + h;
+        uint32_t c = 0;
+        if (d < nbins) {
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const uint32_t x = ctr[q][d];
+                ctr[q][d] = c;
+                c += x;
+            }
+            if (tile > 0) lb_store(&status[(uint64_t)tile * kMaxBins + d], kPartial | c);
+        }
+        cnt[h] = c;
+        g[h] = d < nbins ? gcount[d] : 0u;
+    }
+    uint32_t lc = cnt[0] + cnt[1], gc = g[0] + g[1];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t a = __shfl_up(lc, o), b = __shfl_up(gc, o);
+        if (lane >= o) { lc += a; gc += b; }
+    }
+    if (lane == 63) { wsum[w][0] = lc; wsum[w][1] = gc; }
+    __syncthreads();
+    uint32_t lex = lc - (cnt[0] + cnt[1]), gex = gc - (g[0] + g[1]);
+    for (int q = 0; q < w; q++) { lex += wsum[q][0]; gex += wsum[q][1]; }
+    // Keys of digits 2 tid and 2 tid + 1 in all earlier tiles.  Per digit
+    // and step, the words of the next kLookBack earlier tiles are read at
+    // once and taken from the nearest back: a partial word adds its count and
+    // skips its span, an inclusive word ends the walk, an unwritten one is
+    // read again at the next step.  After each step the sum so far is
+    // published as this tile's partial word.
+    uint32_t before[2] = {0u, 0u};
+    int64_t q[2];
+    bool live[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        q[h] = (int64_t)tile - 1;
+        live[h] = 2 * tid + h < nbins && tile > 0;
+    }
+    uint32_t spins = 0;
+    while (live[0] || live[1]) {
+        uint64_t sw[2][kLookBack];
+#pragma unroll
+        for (int h = 0; h < 2; h++)
+#pragma unroll
+            for (int i = 0; i < kLookBack; i++)
+                sw[h][i] = live[h] && q[h] - i >= 0 ? lb_load(&status[(uint64_t)(q[h] - i) * kMaxBins + 2 * tid + h])
+                                                    : kInclusive;
+        bool stalled = false;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            if (!live[h]) continue;
+            int64_t nq = q[h];   // next tile whose word is needed
+            bool done = false, stop = false;
+#pragma unroll
+            for (int i = 0; i < kLookBack; i++) {
+                if (done || stop || q[h] - i != nq) continue;
+                const uint64_t x = sw[h][i];
+                if (x == 0) { stop = true; continue; }
+                before[h] += (uint32_t)x;
+                if (x & kInclusive) { done = true; continue; }
+                nq = q[h] - i - 1 - (int64_t)((x >> 32) & 0x3FFFFFFFu);
+            }
+            const uint32_t d = 2 * tid + h;
+            if (done) {
+                live[h] = false;
+            } else {
+                if (nq < q[h])
+                    lb_store(&status[(uint64_t)tile * kMaxBins + d],
+                             kPartial | (uint64_t)(tile - 1 - nq) << 32 | (before[h] + cnt[h]));
+                else
+                    stalled = true;
+                q[h] = nq;
+            }
+        }
+        if (stalled) {
+            if (++spins > kSpinLimit) {
+                atomicOr(fault, 1u);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const uint32_t d = 2 * tid + h;
+        if (d < nbins) {
+            lb_store(&status[(uint64_t)tile * kMaxBins + d], kInclusive | (before[h] + cnt[h]));
+            lstart[d] = lex;
+            gadj[d] = (int32_t)(gex + before[h]) - (int32_t)lex;
+        }
+        lex += cnt[h];
+        gex += g[h];
+    }
+    __syncthreads();
+    // the tile sorted by digit in LDS (stable: waves in order, then rank)
+#pragma unroll
+    for (int it = 0; it < kSortKPT; it++) {
+        if (wbase + (uint64_t)it * 64 + lane < n) {
+            const uint32_t d = (uint32_t)(key[it] >> shift) & mask;
+            const uint32_t lp = lstart[d] + ctr[w][d] + rk[it];
+            skey[lp] = key[it];
+            sval[lp] = val[it];
+        }
+    }
+    __syncthreads();
+    // each digit's keys leave as one contiguous run
+    const uint32_t tn = (uint32_t)(n - t0 < (uint64_t)kSortTile ? n - t0 : (uint64_t)kSortTile);
+    for (uint32_t j = tid; j < tn; j += 256) {
+        const uint64_t k = skey[j];
+        const uint32_t o = (uint32_t)(gadj[(uint32_t)(k >> shift) & mask] + (int32_t)j);
+        if (kout) kout[o] = k;
+        vout[o] = sval[j];
     }
 }
 
@@ -521,23 +658,27 @@ __global__ __launch_bounds__(256) void k_pack_degrees(const float *sh, const flo
 }
 
 struct Layout {
-    size_t acc, keys_a, keys_b, vals_a, vals_b, hist, ctot, total, cov_state, cov_part, bytes;
+    size_t acc, keys_a, keys_b, vals_a, vals_b, dc, status, meta, cov_state, cov_part, bytes;
+    uint64_t ntiles;
 };
+
+// meta: digit totals [kMaxPasses][kMaxBins], then one tile counter per pass
+constexpr uint32_t kMetaWords = kMaxPasses * kMaxBins + kMaxPasses;
 
 Layout layout(uint64_t n)
 {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    uint64_t ntiles = (n + kTile - 1) / kTile;
     Layout L;
+    L.ntiles = (n + kSortTile - 1) / kSortTile;
     size_t o = 0;
     L.acc = o; o += al(64 * 4);
     L.keys_a = o; o += al(n * 8);
     L.keys_b = o; o += al(n * 8);
     L.vals_a = o; o += al(n * 4);
     L.vals_b = o; o += al(n * 4);
-    L.hist = o; o += al(ntiles * kDigits * 4);
-    L.ctot = o; o += al((ntiles + kChunkTiles - 1) / kChunkTiles * kDigits * 4);
-    L.total = o; o += al(kDigits * 4);
+    L.dc = o; o += al(n * 12);
+    L.status = o; o += al(2 * L.ntiles * kMaxBins * 8);   // two look-back arrays, used by alternate passes
+    L.meta = o; o += al(kMetaWords * 4);
     L.cov_state = o; o += al(32 * 4);
     L.cov_part = o; o += al((size_t)kCovWG * 4096 * 4);
     L.bytes = o;
@@ -562,11 +703,12 @@ void enqueue_range(const float *pos, const float *sh, const float *opacity, uint
                    uint32_t quantiser, const Layout &L, char *s, RangeRec *range_dev, hipStream_t st)
 {
     uint32_t *acc = reinterpret_cast<uint32_t *>(s + L.acc);
-    GSBC_LAUNCH("range_init", k_range_init, dim3(1), dim3(64), 0, st, acc);
+    GSBC_LAUNCH("range_init", k_range_init, dim3(1), dim3(256), 0, st, acc, reinterpret_cast<uint32_t *>(s + L.meta),
+                kMetaWords);
     uint64_t want = (n * 12 + kRangeBlock - 1) / kRangeBlock;
     uint32_t nb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 2048);
     GSBC_LAUNCH("range_partial", k_range_partial, dim3(nb), dim3(kRangeBlock), 0, st,
-                       reinterpret_cast<const float4 *>(sh), opacity, pos, n, acc);
+                       reinterpret_cast<const float4 *>(sh), opacity, pos, n, acc, reinterpret_cast<float *>(s + L.dc));
     uint32_t *cov = nullptr;
     if (quantiser == 1) {
         cov = reinterpret_cast<uint32_t *>(s + L.cov_state);
@@ -584,33 +726,41 @@ void enqueue_range(const float *pos, const float *sh, const float *opacity, uint
     GSBC_LAUNCH("range_final", k_range_final, dim3(1), dim3(64), 0, st, acc, cov, grid_bits, range_dev);
 }
 
-// LSD radix sort of the keys in keys_a (values vals_a) over key_bits bits;
-// the last pass writes the values to perm.
-void enqueue_sort(uint64_t n, int key_bits, const Layout &L, char *s, uint32_t *perm, hipStream_t st)
+// The keys in keys_a: their digit totals and the cleared look-back words
+// (the key pass), then one stable pass per digit; the last pass writes the
+// values (the original indices) to perm.
+template <bool DEG>
+void enqueue_keys_and_sort(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
+                           float tau, const Layout &L, char *s, const RangeRec *range_dev, uint32_t *class_count,
+                           uint32_t *perm, hipStream_t st)
 {
+    const SortPlan P = plan_sort((DEG ? 26 : 24) + 3 * (int)grid_bits);
     uint64_t *ka = reinterpret_cast<uint64_t *>(s + L.keys_a), *kb = reinterpret_cast<uint64_t *>(s + L.keys_b);
     uint32_t *va = reinterpret_cast<uint32_t *>(s + L.vals_a), *vb = reinterpret_cast<uint32_t *>(s + L.vals_b);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(s + L.hist), *total = reinterpret_cast<uint32_t *>(s + L.total);
-    uint32_t *ctot = reinterpret_cast<uint32_t *>(s + L.ctot);
-    const int passes = (key_bits + kDigitBits - 1) / kDigitBits;
-    const uint32_t ntiles = (uint32_t)((n + kTile - 1) / kTile);
-    const uint32_t nchunks = (ntiles + kChunkTiles - 1) / kChunkTiles;
-    const uint32_t nblocks = (ntiles + 3) / 4;
-    uint64_t *kin = ka, *kout = kb;
-    uint32_t *vin = va, *vout = vb;
-    for (int p = 0; p < passes; p++) {
-        int shift = p * kDigitBits;
-        uint32_t *vdst = (p == passes - 1) ? perm : vout;
-        GSBC_LAUNCH("radix_hist", k_radix_hist, dim3(nblocks), dim3(256), 0, st, kin, n, shift, ntiles, hist);
-        GSBC_LAUNCH("radix_colscan", k_radix_chunkscan, dim3(nchunks, kDigits / 256), dim3(256), 0, st, hist,
-                           ntiles, ctot);
-        GSBC_LAUNCH("radix_colscan", k_radix_chunkprefix, dim3(kDigits / 256), dim3(256), 0, st, ctot, nchunks, total);
-        GSBC_LAUNCH("radix_digitscan", k_radix_digitscan, dim3(1), dim3(1024), 0, st, total);
-        GSBC_LAUNCH("radix_scatter", k_radix_scatter, dim3(nblocks), dim3(256), 0, st, kin, vin, n, shift,
-                           ntiles, hist, ctot, total, kout, vdst);
-        std::swap(kin, kout);
-        vin = vdst;
-        vout = (vdst == va) ? vb : va;
+    uint64_t *status[2] = {reinterpret_cast<uint64_t *>(s + L.status),
+                           reinterpret_cast<uint64_t *>(s + L.status) + L.ntiles * kMaxBins};
+    uint32_t *gcount = reinterpret_cast<uint32_t *>(s + L.meta);
+    uint32_t *tile_ctr = gcount + kMaxPasses * kMaxBins;
+    uint32_t *fault = const_cast<uint32_t *>(&range_dev->sort_fault);
+    const uint64_t words = L.ntiles * kMaxBins;
+    const dim3 grid((uint32_t)L.ntiles);
+    GSBC_LAUNCH(DEG ? "keys_degree" : "keys", k_keys<DEG>, grid, dim3(256), 0, st, pos,
+                reinterpret_cast<const float *>(s + L.dc), sh, opacity, n, grid_bits, range_dev, P, ka, gcount,
+                status[0], 2 * words, tau, class_count);
+    const uint64_t *kin = ka;
+    uint64_t *kout = kb;
+    const uint32_t *vin = nullptr;
+    uint32_t *vout = va;
+    for (int p = 0; p < P.passes; p++) {
+        const bool last = p == P.passes - 1;
+        GSBC_LAUNCH("sort_pass", k_sort_pass, grid, dim3(256), 0, st, kin, vin, last ? nullptr : kout,
+                    last ? perm : vout, n, P.shift[p], P.bits[p], gcount + p * kMaxBins, status[p & 1],
+                    p >= 1 ? status[(p + 1) & 1] : nullptr, words, tile_ctr + p, fault);
+        const uint64_t *kt = kin;
+        kin = kout;
+        kout = const_cast<uint64_t *>(kt);
+        vin = vout;
+        vout = vout == va ? vb : va;
     }
 }
 
@@ -626,11 +776,7 @@ hipError_t launch_reorder(const float *pos, const float *sh, const float *opacit
     if (identity) {
         GSBC_LAUNCH("iota", k_iota, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, perm, n);
     } else {
-        uint64_t *ka = reinterpret_cast<uint64_t *>(s + L.keys_a);
-        uint32_t *va = reinterpret_cast<uint32_t *>(s + L.vals_a);
-        GSBC_LAUNCH("keys", k_keys<false>, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, pos, sh, opacity, n,
-                           grid_bits, range_dev, ka, va, 0.0f, (uint32_t *)nullptr);
-        enqueue_sort(n, 24 + 3 * (int)grid_bits, L, s, perm, st);
+        enqueue_keys_and_sort<false>(pos, sh, opacity, n, grid_bits, 0.0f, L, s, range_dev, nullptr, perm, st);
     }
     const uint64_t npad = (n + 15) / 16 * 16;
     GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0, st,
@@ -646,11 +792,7 @@ hipError_t launch_degree_sort(const float *pos, const float *sh, const float *op
     char *s = static_cast<char *>(scratch);
     enqueue_range(pos, sh, opacity, n, grid_bits, quantiser, L, s, range_dev, st);
     GSBC_LAUNCH("fill_count", k_zero4, dim3(1), dim3(64), 0, st, class_count);
-    uint64_t *ka = reinterpret_cast<uint64_t *>(s + L.keys_a);
-    uint32_t *va = reinterpret_cast<uint32_t *>(s + L.vals_a);
-    GSBC_LAUNCH("keys_degree", k_keys<true>, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, pos, sh, opacity,
-                       n, grid_bits, range_dev, ka, va, tau, class_count);
-    enqueue_sort(n, 26 + 3 * (int)grid_bits, L, s, perm, st);
+    enqueue_keys_and_sort<true>(pos, sh, opacity, n, grid_bits, tau, L, s, range_dev, class_count, perm, st);
     return hipGetLastError();
 }
 
