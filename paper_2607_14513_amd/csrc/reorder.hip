@@ -8,7 +8,7 @@
 //            quantised band-0 colour (Sec. III-C, Fig. Bit4Scan);
 //   sort     stable LSD radix sort, one launch per digit of 8 or 9 bits:
 //            each workgroup takes the next 4,096-key tile, ranks it stably
-//            (wave ballots, waves in order), finds the tile's place among
+//            (per-wave LDS lane masks of equal digits, waves in order), finds the tile's place among
 //            all earlier tiles by decoupled look-back on per-tile digit
 //            counts, sorts the tile in LDS and writes each digit's keys as
 //            one contiguous run; the digit totals of every pass come from
@@ -311,13 +311,17 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
     __shared__ uint64_t skey[kSortTile];
     __shared__ uint32_t sval[kSortTile];
     __shared__ uint32_t ctr[4][kMaxBins];    // per wave: running digit counts, then the wave's offset in the tile
+    __shared__ uint64_t peer[4][kMaxBins];   // per wave: lanes of one step holding each digit (cleared after use)
     __shared__ uint32_t lstart[kMaxBins];    // first tile-local sorted position of each digit
     __shared__ int32_t gadj[kMaxBins];       // output index of sorted position j of digit d: gadj[d] + j
     __shared__ uint32_t wsum[4][2];
     __shared__ uint32_t s_tile;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
-    for (int e = tid; e < 4 * kMaxBins; e += 256) (&ctr[0][0])[e] = 0u;
+    for (int e = tid; e < 4 * kMaxBins; e += 256) {
+        (&ctr[0][0])[e] = 0u;
+        (&peer[0][0])[e] = 0ull;
+    }
     if (zero_status) {
         const uint64_t per = (status_words + gridDim.x - 1) / gridDim.x;
         const uint64_t z0 = (uint64_t)blockIdx.x * per, z1 = min(status_words, z0 + per);
@@ -339,20 +343,25 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
         key[it] = ok ? kin[e] : 0ull;
         val[it] = ok ? (vin ? vin[e] : (uint32_t)e) : 0u;
     }
-    // rank of each key among the equal digits before it in its wave
+    // rank of each key among the equal digits before it in its wave: per
+    // step, each lane ORs its bit into its digit's LDS mask, reads the mask
+    // back (the lanes of this step with the same digit) and the digit's
+    // running count; the lowest such lane advances the count and clears the
+    // mask (LDS operations of one wave complete in issue order)
 #pragma unroll
     for (int it = 0; it < kSortKPT; it++) {
         const bool ok = wbase + (uint64_t)it * 64 + lane < n;
         const uint32_t d = (uint32_t)(key[it] >> shift) & mask;
-        uint64_t peers = __ballot(ok);
-        for (int b = 0; b < bits; b++) {
-            const uint64_t bal = __ballot((d >> b) & 1u);
-            peers &= ((d >> b) & 1u) ? bal : ~bal;
-        }
+        if (ok) atomicOr(&peer[w][d], 1ull << lane);
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t peers = ok ? peer[w][d] : 0ull;
         const uint32_t before = ok ? ctr[w][d] : 0u;
         rk[it] = before + (uint32_t)__popcll(peers & below);
         __builtin_amdgcn_wave_barrier();
-        if (ok && (peers & below) == 0) ctr[w][d] = before + (uint32_t)__popcll(peers);
+        if (ok && (peers & below) == 0) {
+            ctr[w][d] = before + (uint32_t)__popcll(peers);
+            peer[w][d] = 0ull;
+        }
         __builtin_amdgcn_wave_barrier();
     }
     __syncthreads();
