@@ -13,7 +13,8 @@ Steps (see the C file for the definitions and paper sections):
                                         Figs. SetupA and SetupB)
   bc1_decode / bc7_decode            -- D1 / D2 (BC formats, Sec. III-B)
   bc1_encode / bc7_encode            -- E1 / E2 (BTC, Sec. III-A)
-  rate_select / encode_auto          -- R (Sec. IV-B)
+  rate_select / rate_select_zero /
+  band_hist / encode_auto            -- R (Sec. IV-B)
   sh_basis / decode_eval             -- H (Sec. II colour equation), FP64
 """
 import ctypes
@@ -27,6 +28,7 @@ _lib = None
 
 FMT_BC1 = 1
 FMT_BC7 = 7
+FMT_NONE = 3   # a stream given 0 bits: not stored, its bands decode to zero
 
 # Arrangements of the band coefficients into blocks (Sec. IV-B)
 ARR_BANDS = 0   # Fig. SetupD: 16 primitives per block, one stream per band
@@ -70,7 +72,8 @@ def _load():
             "ref_bc7_encode": (None, [P, u64, u32, P, P]),
             "ref_bc1_decode": (None, [P, u64, P]),
             "ref_bc7_decode": (None, [P, u64, P]),
-            "ref_rate_select": (i32, [P, P, P, P, ctypes.c_double, P]),
+            "ref_rate_select": (i32, [P, P, P, P, u32, ctypes.c_double, P]),
+            "ref_rate_select_zero": (i32, [P, P, P, P, P, u32, ctypes.c_double, P]),
             "ref_sh_basis": (None, [ctypes.c_double] * 3 + [P]),
             "ref_decode_eval": (None, [P, P, P, u32, u32, P, P, P, u32, P, u64, P, P]),
             "ref_decode_eval_view": (None, [P, P, P, u32, u32, P, P, P, P, P, P, u64, P, P]),
@@ -301,31 +304,58 @@ def bc7_candidate(ci):
 
 
 # ---------------------------------------------------------------- R
-def rate_select(sse1, sse7, vmin, vmax, rate):
-    """Per-band formats (uint8[16], 1 or 7) or None when the rate is infeasible."""
-    fmt = np.empty(16, np.uint8)
+def rate_select(sse1, sse7, vmin, vmax, rate, S=16):
+    """Per-band formats (uint8[S], 1 or 7) of an S-band scene, or None when
+    the rate is infeasible: band 0 BC7, the k = rate*S/4 - S - 1 largest-gain
+    bands of 1..S-1 BC7."""
+    fmt = np.zeros(16, np.uint8)
     rc = _load().ref_rate_select(_p(_c(sse1, np.int64)), _p(_c(sse7, np.int64)),
                                  _p(_c(vmin, np.float32)), _p(_c(vmax, np.float32)),
-                                 float(rate), _p(fmt))
-    return None if rc != 0 else fmt
+                                 int(S), float(rate), _p(fmt))
+    return None if rc != 0 else fmt[:S].copy()
+
+
+def band_hist(tex):
+    """Code histograms of each stream's R, G and B channels: uint64[S][256]
+    (the input of the 0-bit option's distortion)."""
+    tex = _c(tex, np.uint8)
+    S = tex.shape[0]
+    h = np.zeros((16, 256), np.uint64)
+    for b in range(S):
+        h[b] = np.bincount(tex[b][..., :3].reshape(-1), minlength=256).astype(np.uint64)
+    return h[:S]
+
+
+def rate_select_zero(sse1, sse7, hist, vmin, vmax, rate, S=16):
+    """Per-band formats (uint8[S]: 7, 1 or FMT_NONE) with the 0-bit option,
+    or None when infeasible (see ref_rate_select_zero)."""
+    h = np.zeros((16, 256), np.uint64)
+    h[:S] = np.asarray(hist, np.uint64)[:S]
+    fmt = np.zeros(16, np.uint8)
+    rc = _load().ref_rate_select_zero(_p(_c(sse1, np.int64)), _p(_c(sse7, np.int64)), _p(h),
+                                      _p(_c(vmin, np.float32)), _p(_c(vmax, np.float32)),
+                                      int(S), float(rate), _p(fmt))
+    return None if rc != 0 else fmt[:S].copy()
 
 
 def stream_layout(fmt, nblk):
     """Byte offset of each stream in the concatenated payload (streams in order,
-    each 16-byte aligned; one per entry of fmt) and the total payload size."""
+    each 16-byte aligned; one per entry of fmt; a 0-bit stream takes no bytes)
+    and the total payload size."""
     off = np.zeros(len(fmt), np.uint64)
     pos = 0
     for b in range(len(fmt)):
         off[b] = pos
-        pos += nblk * (8 if int(fmt[b]) == FMT_BC1 else 16)
+        f = int(fmt[b])
+        pos += 0 if f == FMT_NONE else nblk * (8 if f == FMT_BC1 else 16)
         pos = (pos + 15) // 16 * 16
     return off, pos
 
 
 def encode(tex, fmt, refine_steps=2, mode_mask=0xFF):
     """Encode every stream of tex[S][nblk][16][4] in the given per-stream formats
-    (the first S entries of fmt); returns (payload uint8[], offsets uint64[S],
-    sse int64[S])."""
+    (the first S entries of fmt; FMT_NONE streams are not stored); returns
+    (payload uint8[], offsets uint64[S], sse int64[S], 0 for FMT_NONE)."""
     tex = _c(tex, np.uint8)
     S, nblk = tex.shape[0], tex.shape[1]
     fmt = np.asarray(fmt)[:S]
@@ -333,6 +363,8 @@ def encode(tex, fmt, refine_steps=2, mode_mask=0xFF):
     payload = np.zeros(total, np.uint8)
     sse = np.zeros(S, np.int64)
     for b in range(S):
+        if int(fmt[b]) == FMT_NONE:
+            continue
         if int(fmt[b]) == FMT_BC1:
             blk, s = bc1_encode(tex[b], refine_steps)
         else:
@@ -343,18 +375,23 @@ def encode(tex, fmt, refine_steps=2, mode_mask=0xFF):
     return payload, off, sse
 
 
-def encode_auto(tex, vmin, vmax, rate, refine_steps=2, mode_mask=0xFF):
-    """Rate-controlled encode: band 0 BC7; bands 1..15 encoded in both formats,
-    the k = 4R - 17 largest-gain bands kept in BC7.  Returns
+def encode_auto(tex, vmin, vmax, rate, refine_steps=2, mode_mask=0xFF, zero=False):
+    """Rate-controlled encode of an S-band scene tex[S][nblk][16][4]: band 0
+    BC7; bands 1..S-1 encoded in both formats, then rate_select (or, with
+    zero, rate_select_zero over the band code histograms).  Returns
     (payload, offsets, formats) or None when infeasible."""
     tex = _c(tex, np.uint8)
+    S = tex.shape[0]
     sse1 = np.zeros(16, np.int64)
     sse7 = np.zeros(16, np.int64)
-    for b in range(1, 16):
+    for b in range(1, S):
         sse1[b] = int(bc1_encode(tex[b], refine_steps)[1].astype(np.int64).sum())
-    for b in range(16):
+    for b in range(S):
         sse7[b] = int(bc7_encode(tex[b], mode_mask)[1].astype(np.int64).sum())
-    fmt = rate_select(sse1, sse7, vmin, vmax, rate)
+    if zero:
+        fmt = rate_select_zero(sse1, sse7, band_hist(tex), vmin, vmax, rate, S)
+    else:
+        fmt = rate_select(sse1, sse7, vmin, vmax, rate, S)
     if fmt is None:
         return None
     payload, off, _ = encode(tex, fmt, refine_steps, mode_mask)
@@ -362,11 +399,14 @@ def encode_auto(tex, vmin, vmax, rate, refine_steps=2, mode_mask=0xFF):
 
 
 def decode_stream(payload, off, fmt, nblk):
-    """Decode every stream (one per entry of fmt) back to textures uint8[S][nblk][16][4]."""
+    """Decode every stream (one per entry of fmt) back to textures uint8[S][nblk][16][4]
+    (a FMT_NONE stream to zero texels; its coefficients are zero, not vmin)."""
     out = np.empty((len(fmt), nblk, 16, 4), np.uint8)
     for b in range(len(fmt)):
         o = int(off[b])
-        if int(fmt[b]) == FMT_BC1:
+        if int(fmt[b]) == FMT_NONE:   # no blocks: texels all zero
+            out[b] = 0
+        elif int(fmt[b]) == FMT_BC1:
             out[b] = bc1_decode(payload[o:o + nblk * 8])
         else:
             out[b] = bc7_decode(payload[o:o + nblk * 16])

@@ -26,7 +26,8 @@
  *   D1 BC1 decode, D2 BC7 decode                 (Sec. III-B, BC formats)
  *   E1 BC1 encode, E2 BC7 encode                 (Sec. III-A BTC palette and
  *      index rule; endpoint search is this project's deterministic definition)
- *   R  per-band format choice at a fixed rate    (Sec. IV-B)
+ *   R  per-band format choice at a fixed rate    (Sec. IV-B), with or
+ *      without a 0-bit option that drops a band
  *   H  SH colour c = H w(d)                      (Sec. II, colour equation)
  */
 #include <stdint.h>
@@ -1247,27 +1248,115 @@ EXPORT void ref_bc7_decode(const uint8_t *blocks, uint64_t nblk, uint8_t *tex)
  * upgraded; the lower band wins ties.
  * Returns 0, or -4 when k is not an integer in [0, 15].
  * ====================================================================== */
-EXPORT int ref_rate_select(const int64_t *sse1, const int64_t *sse7, const float *vmin,
-                           const float *vmax, double rate, uint8_t *fmt)
+/* Four-bit units of a rate target over S bands: rate * S / 4 bits per
+ * texel-position, accepted within 1e-9 of an integer (a class scene of 9
+ * bands has rates such as 44/9).  -1 when not an integer. */
+static long rate_units(double rate, uint32_t S)
 {
-    double kd = 4.0 * rate - 17.0;
-    if (!(kd >= 0.0 && kd <= 15.0) || kd != floor(kd)) return -4;
-    int k = (int)kd;
+    double u = rate * (double)S / 4.0;
+    double r = floor(u + 0.5);
+    if (!(fabs(u - r) <= 1e-9) || r < 0.0 || r > 1e6) return -1;
+    return (long)r;
+}
+
+/* Band 0 BC7; of bands 1..S-1 the k = rate*S/4 - S - 1 with the largest
+ * (SSE_BC1 - SSE_BC7) * delta^2 are BC7, the rest BC1 (lower band first on
+ * ties); S = 16 gives k = 4 rate - 17. */
+EXPORT int ref_rate_select(const int64_t *sse1, const int64_t *sse7, const float *vmin,
+                           const float *vmax, uint32_t S, double rate, uint8_t *fmt)
+{
+    if (S < 1 || S > 16) return -1;
+    long units = rate_units(rate, S);
+    long k = units - (long)S - 1;
+    if (units < 0 || k < 0 || k > (long)S - 1) return -4;
     double gain[16];
-    for (int b = 1; b < 16; b++) {
+    for (uint32_t b = 1; b < S; b++) {
         double delta = (double)((vmax[b] - vmin[b]) / 255.0f);
         gain[b] = (double)(sse1[b] - sse7[b]) * (delta * delta);
     }
     fmt[0] = 7;
-    for (int b = 1; b < 16; b++) fmt[b] = 1;
-    for (int pick = 0; pick < k; pick++) {
+    for (uint32_t b = 1; b < S; b++) fmt[b] = 1;
+    for (long pick = 0; pick < k; pick++) {
         int best = -1;
-        for (int b = 1; b < 16; b++) {
+        for (uint32_t b = 1; b < S; b++) {
             if (fmt[b] == 7) continue;
-            if (best < 0 || gain[b] > gain[best]) best = b;
+            if (best < 0 || gain[b] > gain[best]) best = (int)b;
         }
         fmt[best] = 7;
     }
+    return 0;
+}
+
+/* R0 -- the choice with a 0-bit option (Sec. IV-B: bitstreams for a varying
+ * number of nonzero SH vectors per primitive; a band given 0 bits is not
+ * stored and decodes to zero).  Band 0 is BC7; each band b = 1..S-1 is
+ * dropped (0 bits per texel), BC1 (4) or BC7 (8), with exactly rate bits per
+ * texel over the S bands: U = rate*S/4 - 2 four-bit units over bands 1..S-1,
+ * an integer in 0..2(S-1), else -4.
+ * Distortion of band b, in coefficient units with the rate controller's
+ * step delta_b = (double)((vmax_b - vmin_b)/255 in FP32):
+ *   BC1  SSE_BC1 delta_b^2,   BC7  SSE_BC7 delta_b^2,
+ *   dropped  the squared dequantised values of its texel channels,
+ *            sum over q = 0..255 (ascending) of hist_b[q] * v_q^2 with
+ *            v_q = vmin_b + q delta_b (hist_b: the band's code histogram
+ *            over the R, G and B channels of all its texels).
+ * Objective: the distortions summed from band S-1 down to band 1 (each
+ * added to the sum of the later bands).  Of the assignments with the least
+ * objective, the first in band order with BC7 before BC1 before dropped.
+ * Computed by dynamic programming over bands S-1..1 and units left; the
+ * least objective of bands b..S-1 with u units distributes over the choice
+ * at band b because rounded addition is monotone. */
+static double zero_distortion(const uint64_t *hist, float vmin, double delta)
+{
+    double z = 0.0;
+    for (int q = 0; q < 256; q++) {
+        double v = (double)vmin + (double)q * delta;
+        z += (double)hist[q] * (v * v);
+    }
+    return z;
+}
+
+EXPORT int ref_rate_select_zero(const int64_t *sse1, const int64_t *sse7, const uint64_t *hist,
+                                const float *vmin, const float *vmax, uint32_t S, double rate, uint8_t *fmt)
+{
+    if (S < 1 || S > 16) return -1;
+    long units = rate_units(rate, S);
+    long U = units - 2;
+    if (units < 0 || U < 0 || U > 2 * ((long)S - 1)) return -4;
+    static const int cost[3] = {2, 1, 0};          /* units of BC7, BC1, dropped */
+    static const uint8_t code[3] = {7, 1, 3};
+    double D[16][3];
+    for (uint32_t b = 1; b < S; b++) {
+        double delta = (double)((vmax[b] - vmin[b]) / 255.0f);
+        D[b][0] = (double)sse7[b] * (delta * delta);
+        D[b][1] = (double)sse1[b] * (delta * delta);
+        D[b][2] = zero_distortion(hist + 256 * (size_t)b, vmin[b], delta);
+    }
+    /* best[b][u]: least objective of bands b..S-1 using exactly u units */
+    double best[17][31];
+    int ok[17][31];
+    for (int u = 0; u <= 30; u++) ok[S][u] = (u == 0), best[S][u] = 0.0;
+    for (int b = (int)S - 1; b >= 1; b--)
+        for (int u = 0; u <= 30; u++) {
+            ok[b][u] = 0;
+            for (int o = 0; o < 3; o++) {
+                int r = u - cost[o];
+                if (r < 0 || !ok[b + 1][r]) continue;
+                double v = D[b][o] + best[b + 1][r];
+                if (!ok[b][u] || v < best[b][u]) best[b][u] = v, ok[b][u] = 1;
+            }
+        }
+    fmt[0] = 7;
+    int u = (int)U;
+    if (S > 1 && !ok[1][u]) return -4;
+    for (uint32_t b = 1; b < S; b++)
+        for (int o = 0; o < 3; o++) {
+            int r = u - cost[o];
+            if (r < 0 || !ok[b + 1][r] || D[b][o] + best[b + 1][r] != best[b][u]) continue;
+            fmt[b] = code[o];
+            u = r;
+            break;
+        }
     return 0;
 }
 
@@ -1305,7 +1394,7 @@ EXPORT void ref_sh_basis(double x, double y, double z, double *Y)
 }
 
 /* decode_eval oracle.  blocks: the concatenated band streams, band b at
- * offset[b] with format fmt[b] (1 or 7); nblk blocks per band.
+ * offset[b] with format fmt[b] (1 BC1, 7 BC7, 3 no bits: zero); nblk blocks per band.
  * dirs float[V][3]; slots uint32[m] (sorted-slot ids).
  * out[v][j][c] = sum_k Hhat[slot][k][c] * Y_k(dir_v) with
  * Hhat = vmin_k + q * delta_k, delta_k = (vmax_k - vmin_k)/255, in FP64;
@@ -1327,6 +1416,10 @@ static void slot_coefficients(const uint8_t *blocks, const uint8_t *fmt, const u
         int st, texel;
         uint64_t b;
         locate(arr, s, k, &st, &b, &texel);
+        if (fmt[st] == 3) {   /* a stream given 0 bits: its bands are zero */
+            H[k][0] = H[k][1] = H[k][2] = 0.0;
+            continue;
+        }
         uint8_t px[64];
         if (fmt[st] == 1) ref_bc1_decode_block(blocks + offset[st] + b * 8, px);
         else ref_bc7_decode_block(blocks + offset[st] + b * 16, px);

@@ -81,6 +81,42 @@ def test_decode_eval_is_dequantised_texels_times_basis():
             assert np.allclose(scale[v, j], np.abs(Y[:, None] * H).sum(0), rtol=0, atol=1e-13)
 
 
+def test_decode_eval_dropped_bands_are_zero():
+    """Streams given 0 bits (format 3) contribute nothing: with every band but
+    the DC dropped the colour is H_0 / (2 sqrt(pi)) in every direction, and
+    dropping bands changes the colour by exactly their terms."""
+    pos, sh = synth.make_scene(300, seed=6)
+    perm, tex, vmin, vmax = O.reorder(pos, sh)
+    nblk = tex.shape[1]
+    dirs = synth.make_dirs(7, seed=6)
+    slots = np.array([0, 5, 16, 150, 299], np.uint32)
+    only_dc = np.array([7] + [3] * 15, np.uint8)
+    payload, off, _ = O.encode(tex, only_dc)
+    assert payload.size == nblk * 16
+    out = O.decode_eval(payload, off, only_dc, vmin, vmax, dirs, slots, with_scale=False)
+    dec = O.decode_stream(payload, off, only_dc, nblk)
+    assert not dec[1:].any()
+    z = [[0, 1, 4, 5], [2, 3, 6, 7], [8, 9, 12, 13], [10, 11, 14, 15]]
+    where = {z[y][x]: 4 * y + x for y in range(4) for x in range(4)}
+    d0 = (np.float64(vmax[0]) - np.float64(vmin[0])) / 255.0
+    for j, s in enumerate(slots):
+        h0 = np.float64(vmin[0]) + dec[0, s // 16, where[s % 16], :3].astype(np.float64) * d0
+        assert np.abs(out[:, j] - h0 / (2 * np.sqrt(np.pi))).max() < 1e-14
+    full = np.array([7] + [1] * 15, np.uint8)
+    some = full.copy()
+    some[[3, 8, 15]] = 3
+    pf, of, _ = O.encode(tex, full)
+    ps, os_, _ = O.encode(tex, some)
+    a = O.decode_eval(pf, of, full, vmin, vmax, dirs, slots, with_scale=False)
+    b = O.decode_eval(ps, os_, some, vmin, vmax, dirs, slots, with_scale=False)
+    for j, s in enumerate(slots):
+        H = _decoded_H(pf, of, full, vmin, vmax, nblk, s)
+        for v in range(len(dirs)):
+            Y = O.sh_basis(dirs[v].astype(np.float64))
+            dropped = sum(H[k] * Y[k] for k in (3, 8, 15))
+            assert np.allclose(a[v, j] - b[v, j], dropped, rtol=0, atol=1e-13)
+
+
 def _decoded_H(payload, off, fmt, vmin, vmax, nblk, s):
     dec = O.decode_stream(payload, off, fmt, nblk)
     z = [[0, 1, 4, 5], [2, 3, 6, 7], [8, 9, 12, 13], [10, 11, 14, 15]]
