@@ -56,7 +56,19 @@ enum {
     GSBC_E_IO = -7           /* a container file cannot be read or written, or is malformed */
 };
 
-enum { GSBC_FMT_AUTO = 0, GSBC_FMT_BC1 = 1, GSBC_FMT_BANDS = 2, GSBC_FMT_BC7 = 7 };
+/* Stream formats: BC1 (8 bytes per block), BC7 (16), or NONE: a band
+ * stream given 0 bits (Sec. IV-B, bitstreams for a varying number of
+ * nonzero SH vectors), which stores no blocks and whose coefficients decode
+ * to exactly zero (band arrangement only).  AUTO and AUTO_ZERO ask
+ * gsbc_encode to choose per band at a rate; BANDS takes desc->format. */
+enum {
+    GSBC_FMT_AUTO = 0,
+    GSBC_FMT_BC1 = 1,
+    GSBC_FMT_BANDS = 2,
+    GSBC_FMT_NONE = 3,
+    GSBC_FMT_AUTO_ZERO = 4,
+    GSBC_FMT_BC7 = 7
+};
 
 /* Arrangements of the 16 band vectors of the primitives into 4x4 blocks
  * (Sec. IV-B).  Slots are padded to n_pad (a multiple of 16) by repeating
@@ -93,7 +105,8 @@ typedef struct {
 /* Header of a coded scene: one bitstream per stream of the arrangement
  * (Sec. IV-A: typed bitstreams; the stream index selects the decoder). */
 typedef struct {
-    uint8_t format[16];          /* per stream: GSBC_FMT_BC1 or GSBC_FMT_BC7 (entries past n_streams unused) */
+    uint8_t format[16];          /* per stream: GSBC_FMT_BC1, GSBC_FMT_BC7 or (band arrangement)
+                                    GSBC_FMT_NONE (entries past n_streams unused) */
     uint64_t offset[16];         /* byte offset of stream s in the payload (16-byte aligned) */
     float vmin[16], vmax[16];    /* per-band quantiser range: q = rint((x - vmin) * 255/(vmax - vmin)) */
     uint64_t n_prims;            /* N */
@@ -223,15 +236,28 @@ GSBC_API gsbc_status gsbc_reorder_degrees(gsbc_ctx *ctx, const float *pos, const
  *            format, offset, payload_bytes
  *   format   GSBC_FMT_BC1 or GSBC_FMT_BC7 for all streams; GSBC_FMT_BANDS
  *            for the per-stream formats the caller put in desc->format[s]
- *            (each BC1 or BC7, e.g. band 0 BC7 and the rest BC1 as in
- *            Sec. V, or the first SetupB stream BC7 and the other three BC1
- *            as in Table I); or GSBC_FMT_AUTO (GSBC_ARR_BANDS only, else
- *            GSBC_E_UNSUPPORTED):
- *            every band is coded in both formats, then band 0 is BC7 and of
- *            bands 1..15 the k = 4*rate - 17 with the largest
- *            (SSE_BC1 - SSE_BC7) * delta_k^2 are BC7 (lower band first on
- *            ties), the rest BC1, so the mean is exactly `rate` bits per texel
- *            (GSBC_E_INFEASIBLE if k is not an integer in 0..15), with
+ *            (each BC1, BC7 or, for band streams, NONE: e.g. band 0 BC7 and
+ *            the rest BC1 as in Sec. V, or the first SetupB stream BC7 and
+ *            the other three BC1 as in Table I); or a rate-controlled choice
+ *            over the S = n_streams bands of a GSBC_ARR_BANDS scene (16, or
+ *            (L+1)^2 for a degree class; other arrangements
+ *            GSBC_E_UNSUPPORTED), at exactly `rate` bits per texel over the
+ *            S bands: every band is coded in both formats, band 0 is BC7,
+ *            and with U = rate*S/4 four-bit units in all (an integer to
+ *            within 1e-9, else GSBC_E_INFEASIBLE):
+ *            GSBC_FMT_AUTO  of bands 1..S-1 the k = U - S - 1 (0..S-1) with
+ *                the largest (SSE_BC1 - SSE_BC7) * delta_k^2 are BC7 (lower
+ *                band first on ties), the rest BC1; S = 16 gives
+ *                k = 4*rate - 17;
+ *            GSBC_FMT_AUTO_ZERO  each band 1..S-1 is BC7, BC1 or NONE, with
+ *                U - 2 units (0..2(S-1)) over them (2, 1, 0 each), choosing
+ *                the least total distortion: SSE_BC7 delta_k^2,
+ *                SSE_BC1 delta_k^2, or for NONE the sum of the band's
+ *                squared dequantised texel values (vmin_k + q delta_k)^2
+ *                over its R, G, B codes q, summed in code order from a
+ *                histogram; the bands' distortions are added from band S-1
+ *                down to band 1; on ties the lower band takes BC7 before
+ *                BC1 before NONE;
  *            delta_k = (vmax_k - vmin_k)/255 in FP32; `rate` is ignored
  *            otherwise
  *   params   host, NULL for defaults (refine_steps, bc7_mode_mask are used)

@@ -163,6 +163,18 @@ gsbc_status check_params(gsbc_ctx *ctx, const gsbc_params &p)
     return GSBC_OK;
 }
 
+// Bytes of one stream: a 0-bit stream (GSBC_FMT_NONE) stores no blocks.
+uint64_t stream_bytes(uint32_t fmt, uint64_t nblk)
+{
+    return fmt == GSBC_FMT_NONE ? 0 : nblk * (fmt == GSBC_FMT_BC1 ? 8 : 16);
+}
+
+// A stream's format: BC1 or BC7; with the band arrangement also 0 bits.
+bool stream_format_ok(uint32_t fmt, uint32_t arrangement)
+{
+    return fmt == GSBC_FMT_BC1 || fmt == GSBC_FMT_BC7 || (fmt == GSBC_FMT_NONE && arrangement == GSBC_ARR_BANDS);
+}
+
 gsbc_status check_desc(gsbc_ctx *ctx, const gsbc_stream_desc *d)
 {
     if (!d) return fail(ctx, GSBC_E_ARG, "desc is NULL");
@@ -187,10 +199,10 @@ gsbc_status check_stream(gsbc_ctx *ctx, const gsbc_stream_desc *d)
     if (s) return s;
     uint64_t pos = 0;
     for (uint32_t k = 0; k < d->n_streams; k++) {
-        if (d->format[k] != GSBC_FMT_BC1 && d->format[k] != GSBC_FMT_BC7)
-            return fail(ctx, GSBC_E_ARG, "desc.format[%u] = %u is not BC1 or BC7", k, d->format[k]);
+        if (!stream_format_ok(d->format[k], d->arrangement))
+            return fail(ctx, GSBC_E_ARG, "desc.format[%u] = %u is not BC1, BC7 or (band streams) NONE", k, d->format[k]);
         if (d->offset[k] != pos) return fail(ctx, GSBC_E_ARG, "desc.offset[%u] does not follow the stream layout", k);
-        pos = align16(pos + d->blocks_per_stream * (d->format[k] == GSBC_FMT_BC1 ? 8 : 16));
+        pos = align16(pos + stream_bytes(d->format[k], d->blocks_per_stream));
     }
     if (d->payload_bytes != pos) return fail(ctx, GSBC_E_ARG, "desc.payload_bytes inconsistent");
     return GSBC_OK;
@@ -235,7 +247,7 @@ uint64_t layout(const uint32_t fmt[16], uint32_t n_streams, uint64_t nblk, uint6
     for (uint32_t k = n_streams; k < 16; k++) off[k] = 0;
     for (uint32_t k = 0; k < n_streams; k++) {
         off[k] = pos;
-        pos = align16(pos + nblk * (fmt[k] == GSBC_FMT_BC1 ? 8 : 16));
+        pos = align16(pos + stream_bytes(fmt[k], nblk));
     }
     return pos;
 }
@@ -244,6 +256,17 @@ uint64_t layout(const uint32_t fmt[16], uint32_t n_streams, uint64_t nblk, uint6
 // payloads (AUTO)] [BC7 runs] [BC1 runs] [BC7 key scratch]; AUTO is the
 // largest (every band in both formats).
 size_t encode_front_bytes(uint64_t nblk) { return 16 * align16(8 * nblk) + 16 * 16 * nblk; }
+constexpr size_t kHistBytes = 16 * 256 * sizeof(uint64_t);   // band code histograms (the 0-bit option)
+
+// Four-bit units of a rate target over S bands: rate*S/4, accepted within
+// 1e-9 of an integer (a 9-band class scene has rates such as 44/9); -1 if not.
+long rate_units(double rate, uint32_t S)
+{
+    const double u = rate * (double)S / 4.0;
+    const double r = floor(u + 0.5);
+    if (!(fabs(u - r) <= 1e-9) || r < 0.0 || r > 1e6) return -1;
+    return (long)r;
+}
 
 // Default work split of the single-scene calls: one workgroup per 256-block
 // round, BC1 on 128-lane workgroups, one BC7 search launch whose work items
@@ -403,7 +426,8 @@ gsbc_status gsbc_reserve(gsbc_ctx *ctx, uint64_t n_max, uint32_t n_dirs_max)
                                                          (unsigned long long)n_max);
     const uint64_t nblk = pad16(n_max) / 16;
     size_t need = reorder_scratch_bytes(n_max, 3);
-    need = std::max(need, encode_front_bytes(nblk) + 2 * kRunTableBytes + bc7_scratch_bytes(16 * run_span(nblk)));
+    need = std::max(need, encode_front_bytes(nblk) + 2 * kRunTableBytes + bc7_scratch_bytes(16 * run_span(nblk)) +
+                              kHistBytes);
     need = std::max(need, (size_t)n_dirs_max * 16 * sizeof(float));
     return ensure_arena(ctx, need);
 }
@@ -541,15 +565,18 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
     if ((reinterpret_cast<uintptr_t>(textures) & 15) || (reinterpret_cast<uintptr_t>(blocks) & 15))
         return fail(ctx, GSBC_E_ARG, "textures and blocks must be 16-byte aligned");
     if ((s = check_desc(ctx, desc))) return s;
-    if (format != GSBC_FMT_AUTO && format != GSBC_FMT_BC1 && format != GSBC_FMT_BC7 && format != GSBC_FMT_BANDS)
-        return fail(ctx, GSBC_E_ARG, "format %d is not AUTO(0), BC1(1), BANDS(2) or BC7(7)", format);
+    if (format != GSBC_FMT_AUTO && format != GSBC_FMT_AUTO_ZERO && format != GSBC_FMT_BC1 && format != GSBC_FMT_BC7 &&
+        format != GSBC_FMT_BANDS)
+        return fail(ctx, GSBC_E_ARG, "format %d is not AUTO(0), BC1(1), BANDS(2), AUTO_ZERO(4) or BC7(7)", format);
     const uint32_t S = desc->n_streams;
+    const bool autoc = format == GSBC_FMT_AUTO || format == GSBC_FMT_AUTO_ZERO;
     if (format == GSBC_FMT_BANDS)
         for (uint32_t k = 0; k < S; k++)
-            if (desc->format[k] != GSBC_FMT_BC1 && desc->format[k] != GSBC_FMT_BC7)
-                return fail(ctx, GSBC_E_ARG, "desc.format[%u] = %u is not BC1 or BC7", k, desc->format[k]);
-    if (format == GSBC_FMT_AUTO && (desc->arrangement != GSBC_ARR_BANDS || S != 16))
-        return fail(ctx, GSBC_E_UNSUPPORTED, "the rate controller chooses among 16 bands: GSBC_ARR_BANDS with all bands only");
+            if (!stream_format_ok(desc->format[k], desc->arrangement))
+                return fail(ctx, GSBC_E_ARG, "desc.format[%u] = %u is not BC1, BC7 or (band streams) NONE", k,
+                            desc->format[k]);
+    if (autoc && desc->arrangement != GSBC_ARR_BANDS)
+        return fail(ctx, GSBC_E_UNSUPPORTED, "the rate controller chooses per band: GSBC_ARR_BANDS scenes only");
     gsbc_params p = resolve(params);
     if ((s = check_params(ctx, p))) return s;
     const uint64_t nblk = desc->blocks_per_stream;
@@ -560,13 +587,13 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
     uint64_t host_off[16];
     uint32_t host_fmt[16];
     uint64_t payload = 0;
-    uint32_t k_auto = 0;
+    uint32_t k_auto = 0;   // AUTO: bands upgraded to BC7; AUTO_ZERO: units over bands 1..S-1
     bool have1 = false, have7 = false;
     Runs r1, r7;
     uint8_t *buf1 = nullptr, *buf7 = nullptr;
     uint64_t off1[16], off7[16];
     size_t front = 0;
-    if (format != GSBC_FMT_AUTO) {
+    if (!autoc) {
         for (uint32_t k = 0; k < 16; k++)
             host_fmt[k] = k >= S ? 0u : format == GSBC_FMT_BANDS ? desc->format[k] : (uint32_t)format;
         payload = layout(host_fmt, S, nblk, host_off);
@@ -575,29 +602,47 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
                         (unsigned long long)payload);
         for (uint32_t k = 0; k < S; k++) {
             if (host_fmt[k] == GSBC_FMT_BC7) r7.add(textures + k * tex_band, blocks + host_off[k], sse7 + k, nblk);
-            else r1.add(textures + k * tex_band, blocks + host_off[k], sse1 + k, nblk);
+            else if (host_fmt[k] == GSBC_FMT_BC1) r1.add(textures + k * tex_band, blocks + host_off[k], sse1 + k, nblk);
         }
     } else {
-        double kd = 4.0 * rate - 17.0;
-        if (!(kd >= 0.0 && kd <= 15.0) || kd != floor(kd))
-            return fail(ctx, GSBC_E_INFEASIBLE, "rate %.17g bits/texel needs 4*rate-17 BC7 bands, not an integer in 0..15", rate);
-        k_auto = (uint32_t)kd;
-        payload = (uint64_t)(k_auto + 1) * 16 * nblk + (uint64_t)(15 - k_auto) * align16(8 * nblk);
+        const long units = rate_units(rate, S);
+        if (format == GSBC_FMT_AUTO) {
+            const long k = units - (long)S - 1;
+            if (units < 0 || k < 0 || k > (long)S - 1)
+                return fail(ctx, GSBC_E_INFEASIBLE,
+                            "rate %.17g bits/texel over %u bands needs rate*S/4 - S - 1 BC7 bands, not an integer in 0..%u",
+                            rate, S, S - 1);
+            k_auto = (uint32_t)k;
+            payload = (uint64_t)(k_auto + 1) * 16 * nblk + (uint64_t)(S - 1 - k_auto) * align16(8 * nblk);
+        } else {
+            const long U = units - 2;
+            if (units < 0 || U < 0 || U > 2 * ((long)S - 1))
+                return fail(ctx, GSBC_E_INFEASIBLE,
+                            "rate %.17g bits/texel over %u bands needs rate*S/4 - 2 units, not an integer in 0..%u", rate, S,
+                            2 * (S - 1));
+            k_auto = (uint32_t)U;
+            // the largest payload of any choice with U units (BC1 streams pad to 16 bytes)
+            for (long n7 = U > (long)S - 1 ? U - ((long)S - 1) : 0; 2 * n7 <= U; n7++)
+                payload = std::max<uint64_t>(payload, (uint64_t)(1 + n7) * 16 * nblk + (uint64_t)(U - 2 * n7) * align16(8 * nblk));
+        }
         if (blocks_capacity < payload)
             return fail(ctx, GSBC_E_BUFFER, "blocks_capacity %llu < payload %llu bytes", (unsigned long long)blocks_capacity,
                         (unsigned long long)payload);
         front = encode_front_bytes(nblk);   // both candidate payloads
     }
-    // arena: [candidate payloads (AUTO)] [BC7 runs] [BC1 runs] [BC7 key scratch]
-    const uint64_t total7 = format == GSBC_FMT_AUTO ? 16 * run_span(nblk) : r7.total;
-    if ((s = ensure_arena(ctx, front + 2 * kRunTableBytes + bc7_scratch_bytes(total7)))) return s;
+    // arena: [candidate payloads (AUTO)] [BC7 runs] [BC1 runs] [BC7 key scratch] [band histograms (AUTO_ZERO)]
+    const uint64_t total7 = autoc ? (uint64_t)S * run_span(nblk) : r7.total;
+    const size_t hist_off = front + 2 * kRunTableBytes + bc7_scratch_bytes(total7);
+    if ((s = ensure_arena(ctx, hist_off + (format == GSBC_FMT_AUTO_ZERO ? kHistBytes : 0)))) return s;
     uint8_t *arena = static_cast<uint8_t *>(ctx->arena);
-    if (format == GSBC_FMT_AUTO) {
+    if (autoc) {
         buf1 = arena;
         buf7 = buf1 + 16 * align16(8 * nblk);
         for (int q = 0; q < 16; q++) {
             off1[q] = q * align16(8 * nblk);
             off7[q] = q * 16 * nblk;
+        }
+        for (uint32_t q = 0; q < S; q++) {
             r7.add(textures + q * tex_band, buf7 + off7[q], sse7 + q, nblk);
             r1.add(textures + q * tex_band, buf1 + off1[q], sse1 + q, nblk);   // band 0 too: its BC1 SSE is reported
         }
@@ -647,7 +692,7 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
         HIP_TRY(ctx, hipEventRecord(ctx->join, s1), "join");
         HIP_TRY(ctx, hipStreamWaitEvent(ctx->stream, ctx->join, 0), "join");
     }
-    if (format == GSBC_FMT_AUTO) {
+    if (autoc) {
         uint64_t *doff1 = reinterpret_cast<uint64_t *>(small_ptr(ctx, kOff1Off));
         uint64_t *doff7 = reinterpret_cast<uint64_t *>(small_ptr(ctx, kOff7Off));
         uint64_t *ostage = reinterpret_cast<uint64_t *>(static_cast<char *>(ctx->pinned) + kRunStageOff + 2 * kRunTableBytes);
@@ -655,23 +700,33 @@ gsbc_status gsbc_encode(gsbc_ctx *ctx, const uint8_t *textures, gsbc_stream_desc
         memcpy(ostage + 16, off7, sizeof off7);
         HIP_TRY(ctx, hipMemcpyAsync(doff1, ostage, 2 * sizeof off1, hipMemcpyHostToDevice, ctx->stream), "offsets");
         RateSel *sel = reinterpret_cast<RateSel *>(small_ptr(ctx, kSelOff));
-        HIP_TRY(ctx, launch_rate_select(sse1, sse7, band_args(desc), k_auto, nblk, sel, ctx->stream), "rate select");
-        HIP_TRY(ctx, launch_copy_streams(buf1, doff1, buf7, doff7, sel, nblk, blocks, ctx->stream), "stream copy");
+        if (format == GSBC_FMT_AUTO_ZERO) {
+            unsigned long long *hist = reinterpret_cast<unsigned long long *>(arena + hist_off);
+            HIP_TRY(ctx, launch_fill_u64(hist, 16 * 256, 0, ctx->stream), "clear");
+            HIP_TRY(ctx, launch_band_hist(textures, S, nblk, hist, ctx->stream), "band histograms");
+            HIP_TRY(ctx, launch_rate_select_zero(sse1, sse7, hist, band_args(desc), S, k_auto, nblk, sel, ctx->stream),
+                    "rate select");
+        } else {
+            HIP_TRY(ctx, launch_rate_select(sse1, sse7, band_args(desc), S, k_auto, nblk, sel, ctx->stream), "rate select");
+        }
+        HIP_TRY(ctx, launch_copy_streams(buf1, doff1, buf7, doff7, sel, S, nblk, blocks, ctx->stream), "stream copy");
         HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, sel, sizeof(RateSel), hipMemcpyDeviceToHost, ctx->stream), "selection read-back");
     }
     char *sstage = static_cast<char *>(ctx->pinned) + 1024;
     HIP_TRY(ctx, hipMemcpyAsync(sstage, sse1, 32 * sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream), "sse read-back");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "encode");
-    if (format == GSBC_FMT_AUTO) {
+    if (autoc) {
         const RateSel *r = static_cast<const RateSel *>(ctx->pinned);
         for (int q = 0; q < 16; q++) { host_fmt[q] = r->format[q]; host_off[q] = r->offset[q]; }
-        if (r->payload_bytes != payload) return fail(ctx, GSBC_E_DEVICE, "selected payload size disagrees with the budget");
+        if (format == GSBC_FMT_AUTO ? r->payload_bytes != payload : r->payload_bytes > payload)
+            return fail(ctx, GSBC_E_DEVICE, "selected payload size disagrees with the budget");
+        payload = r->payload_bytes;
     }
     if (band_sse) {
         const uint64_t *h = reinterpret_cast<const uint64_t *>(sstage);
         for (uint32_t q = 0; q < 16; q++) {
-            const bool c1 = q < S && (format == GSBC_FMT_AUTO || (have1 && host_fmt[q] == GSBC_FMT_BC1));
-            const bool c7 = q < S && (format == GSBC_FMT_AUTO || (have7 && host_fmt[q] == GSBC_FMT_BC7));
+            const bool c1 = q < S && (autoc || (have1 && host_fmt[q] == GSBC_FMT_BC1));
+            const bool c7 = q < S && (autoc || (have7 && host_fmt[q] == GSBC_FMT_BC7));
             band_sse[q] = c1 ? (int64_t)h[q] : -1;
             band_sse[16 + q] = c7 ? (int64_t)h[16 + q] : -1;
         }
@@ -721,8 +776,9 @@ gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *c
         if ((s = check_desc(ctx, &descs[i]))) return s;
         for (uint32_t k = 0; k < 16; k++) {
             fmts[16 * i + k] = k < descs[i].n_streams ? descs[i].format[k] : 0u;
-            if (k < descs[i].n_streams && fmts[16 * i + k] != GSBC_FMT_BC1 && fmts[16 * i + k] != GSBC_FMT_BC7)
-                return fail(ctx, GSBC_E_ARG, "scene %u: desc.format[%u] = %u is not BC1 or BC7", i, k, descs[i].format[k]);
+            if (k < descs[i].n_streams && !stream_format_ok(fmts[16 * i + k], descs[i].arrangement))
+                return fail(ctx, GSBC_E_ARG, "scene %u: desc.format[%u] = %u is not BC1, BC7 or (band streams) NONE", i, k,
+                            descs[i].format[k]);
         }
         pay[i] = layout(&fmts[16 * i], descs[i].n_streams, descs[i].blocks_per_stream, &offs[16 * i]);
         if (blocks_capacity[i] < pay[i])
@@ -742,7 +798,8 @@ gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *c
         sig.push_back(reinterpret_cast<uintptr_t>(blocks[i]));
         sig.push_back(descs[i].blocks_per_stream);
         uint64_t f = (uint64_t)descs[i].n_streams << 32;
-        for (int k = 0; k < 16; k++) f |= (uint64_t)(fmts[16 * i + k] == GSBC_FMT_BC7) << k;
+        for (int k = 0; k < 16; k++)
+            f |= (uint64_t)(fmts[16 * i + k] == GSBC_FMT_BC7 ? 2 : fmts[16 * i + k] == GSBC_FMT_NONE ? 3 : 1) << (2 * k);
         sig.push_back(f);
     }
     if (sig != ctx->plan_sig) {
@@ -754,7 +811,7 @@ gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *c
                 const uint8_t *src = textures[i] + (uint64_t)k * nblk * 64;
                 uint8_t *dst = blocks[i] + offs[16 * i + k];
                 if (fmts[16 * i + k] == GSBC_FMT_BC7) r7.add(src, dst, nullptr, nblk);
-                else r1.add(src, dst, nullptr, nblk);
+                else if (fmts[16 * i + k] == GSBC_FMT_BC1) r1.add(src, dst, nullptr, nblk);
             }
         }
         // plan memory: [runs7][runs1][sse n_scenes x 16][queues 4 x u64][BC7 keys]
@@ -777,6 +834,7 @@ gsbc_status gsbc_encode_batch(gsbc_ctx *ctx, uint32_t n_scenes, const uint8_t *c
             size_t q7 = 0, q1 = 0;
             for (uint32_t i = 0; i < n_scenes; i++)
                 for (uint32_t k = 0; k < descs[i].n_streams; k++) {
+                    if (fmts[16 * i + k] == GSBC_FMT_NONE) continue;
                     BlockRun &r = fmts[16 * i + k] == GSBC_FMT_BC7 ? r7.v[q7++] : r1.v[q1++];
                     r.sse = ctx->plan_sse + 16 * (size_t)i + k;
                 }

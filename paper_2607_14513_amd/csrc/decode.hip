@@ -28,6 +28,7 @@ __device__ __forceinline__ uint32_t zigzag_texel(uint32_t j)
 __device__ __forceinline__ uint32_t band_texel(const uint8_t *blocks, const BandArgs &b, int k,
                                                uint64_t blk, int texel)
 {
+    if (b.format[k] == GSBC_FMT_NONE) return 0u;   // a stream given 0 bits stores no blocks
     const uint8_t *base = blocks + b.offset[k];
     if (b.format[k] == 1) {
         uint2 w = *reinterpret_cast<const uint2 *>(base + blk * 8);
@@ -74,14 +75,18 @@ __device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const Ban
         const uint64_t blk = ARR == 1 ? s : ARR == 2 ? (s >> 2) : (s >> 4);
         const bool wide = b.format[sk] != 1;
         const uint8_t *q = blocks + b.offset[sk] + blk * (wide ? 16 : 8);
-        lo[k] = *reinterpret_cast<const uint2 *>(q);
-        hi[k] = *reinterpret_cast<const uint2 *>(q + (wide ? 8 : 0));
+        // a stream given 0 bits stores no blocks: nothing to load
+        const bool stored = b.format[sk] != GSBC_FMT_NONE;
+        lo[k] = stored ? *reinterpret_cast<const uint2 *>(q) : make_uint2(0u, 0u);
+        hi[k] = stored ? *reinterpret_cast<const uint2 *>(q + (wide ? 8 : 0)) : make_uint2(0u, 0u);
     }
 #pragma unroll
     for (int k = 0; k < 16; k++) {
         const int sk = ARR == 1 ? 0 : ARR == 2 ? (k >> 2) : k;
         const int texel = ARR == 1 ? k : ARR == 2 ? 4 * (int)(s & 3u) + (k & 3) : (int)zigzag_texel(s & 15u);
-        if ((ARR == 0 && (uint32_t)k >= b.n_streams) || (ARR == 2 && (uint32_t)(k >> 2) >= b.n_streams)) px[k] = 0u;
+        if ((ARR == 0 && (uint32_t)k >= b.n_streams) || (ARR == 2 && (uint32_t)(k >> 2) >= b.n_streams) ||
+            b.format[sk] == GSBC_FMT_NONE)
+            px[k] = 0u;
         else if (b.format[sk] == 1) px[k] = bc1_texel(lo[k].x, lo[k].y, texel);
         else px[k] = bc7_texel(Blk128{lo[k].x | (uint64_t)lo[k].y << 32, hi[k].x | (uint64_t)hi[k].y << 32}, texel, lut);
     }
@@ -105,6 +110,13 @@ __device__ __forceinline__ float dequant(uint32_t q, const BandArgs &b, int k)
 __device__ __forceinline__ uint32_t kept_bands(const BandArgs &b)
 {
     return b.arrangement == 0 ? b.n_streams : b.arrangement == 2 ? 4u * b.n_streams : 16u;
+}
+
+// Band k has coded values: it is one of the scene's bands and its stream
+// was not given 0 bits (band arrangement only); otherwise it is zero.
+__device__ __forceinline__ bool band_coded(const BandArgs &b, int k)
+{
+    return (uint32_t)k < kept_bands(b) && !(b.arrangement == 0 && b.format[k] == GSBC_FMT_NONE);
 }
 
 __device__ __forceinline__ void slot_texels(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16])
@@ -218,10 +230,9 @@ __device__ __forceinline__ void decode_eval_body(const uint8_t *blocks, const Ba
             if (s < n_prims) {
                 uint32_t px[16];
                 slot_texels(blocks, b, s, px, Bc7PackedLut{lutw});
-                const uint32_t nb = kept_bands(b);
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
-                    const bool kept = (uint32_t)k < nb;
+                    const bool kept = band_coded(b, k);
 #pragma unroll
                     for (int c = 0; c < 3; c++) h[k][c] = kept ? dequant(px[k] >> (8 * c), b, k) : 0.0f;
                 }
@@ -440,11 +451,10 @@ __global__ __launch_bounds__(256) void k_decode_eval_view(const uint8_t *blocks,
         Y[15] = -c3a * x * (xx - 3.0f * yy);
         uint32_t px[16];
         slot_texels(blocks, b, s, px);
-        const uint32_t nb = kept_bands(b);
         c[0] = c[1] = c[2] = 0.0f;
 #pragma unroll
         for (int k = 0; k < 16; k++) {
-            if ((uint32_t)k < nb) {
+            if (band_coded(b, k)) {
 #pragma unroll
                 for (int ch = 0; ch < 3; ch++)
                     c[ch] = fmaf(dequant(px[k] >> (8 * ch), b, k), Y[k], c[ch]);

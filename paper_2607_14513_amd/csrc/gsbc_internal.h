@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gsbc.h"
+
 namespace gsbc {
 
 // Kernel timing hooks around each launch; no-ops unless the calling context
@@ -171,12 +173,17 @@ struct RateSel {
     uint64_t payload_bytes;
 };
 hipError_t launch_rate_select(const unsigned long long *sse1, const unsigned long long *sse7,
-                              const BandArgs &b, uint32_t k, uint64_t nblk, RateSel *sel,
+                              const BandArgs &b, uint32_t S, uint32_t k, uint64_t nblk, RateSel *sel,
                               hipStream_t st);
-// Copies each chosen band stream and zero-fills its alignment padding.
+// Code histograms of the R, G, B channels of each of the S band streams
+// into hist[S][256] (which the caller clears).
+hipError_t launch_band_hist(const uint8_t *tex, uint32_t S, uint64_t nblk, unsigned long long *hist, hipStream_t st);
+hipError_t launch_rate_select_zero(const unsigned long long *sse1, const unsigned long long *sse7,
+                                   const unsigned long long *hist, const BandArgs &b, uint32_t S, uint32_t U,
+                                   uint64_t nblk, RateSel *sel, hipStream_t st);
 hipError_t launch_copy_streams(const uint8_t *src1, const uint64_t *off1, const uint8_t *src7,
-                               const uint64_t *off7, const RateSel *sel, uint64_t nblk,
-                               uint8_t *out, hipStream_t st);
+                               const uint64_t *off7, const RateSel *sel, uint32_t S, uint64_t nblk, uint8_t *out,
+                               hipStream_t st);
 hipError_t launch_fill_u64(unsigned long long *p, uint64_t n, unsigned long long v, hipStream_t st);
 
 // ---- decoders (decode.hip)

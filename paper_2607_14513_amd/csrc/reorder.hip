@@ -715,7 +715,9 @@ void enqueue_range(const float *pos, const float *sh, const float *opacity, uint
     GSBC_LAUNCH("range_init", k_range_init, dim3(1), dim3(256), 0, st, acc, reinterpret_cast<uint32_t *>(s + L.meta),
                 kMetaWords);
     uint64_t want = (n * 12 + kRangeBlock - 1) / kRangeBlock;
-    uint32_t nb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 2048);
+    // at most 1,024 workgroups: fewer block-level merges into the 38 global
+    // minima and maxima (measured faster at one million primitives, the same at three)
+    uint32_t nb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 1024);
     GSBC_LAUNCH("range_partial", k_range_partial, dim3(nb), dim3(kRangeBlock), 0, st,
                        reinterpret_cast<const float4 *>(sh), opacity, pos, n, acc, reinterpret_cast<float *>(s + L.dc));
     uint32_t *cov = nullptr;

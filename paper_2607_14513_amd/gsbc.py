@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsbc.so")
 
 OK, E_ARG, E_UNSUPPORTED, E_NOMEM, E_INFEASIBLE, E_DEVICE, E_BUFFER, E_IO = 0, -1, -2, -3, -4, -5, -6, -7
-FMT_AUTO, FMT_BC1, FMT_BANDS, FMT_BC7 = 0, 1, 2, 7
+FMT_AUTO, FMT_BC1, FMT_BANDS, FMT_NONE, FMT_AUTO_ZERO, FMT_BC7 = 0, 1, 2, 3, 4, 7
 ARR_BANDS, ARR_PRIM, ARR_QUAD = 0, 1, 2
 N_STREAMS = {ARR_BANDS: 16, ARR_PRIM: 1, ARR_QUAD: 4}
 
@@ -340,7 +340,9 @@ class Context:
 
     def encode(self, textures, desc, fmt=FMT_AUTO, rate=6.0, params=None, blocks=None, want_sse=False):
         """Encode all streams -> (blocks uint8 device tensor, desc, band_sse int64[2][16] or None).
-        fmt FMT_BANDS codes stream k in desc.format[k] (set by the caller)."""
+        fmt FMT_BANDS codes stream k in desc.format[k] (set by the caller:
+        FMT_BC1, FMT_BC7 or, for band streams, FMT_NONE); FMT_AUTO and
+        FMT_AUTO_ZERO choose per band at `rate` bits per texel."""
         S, nblk, _, _ = _sizes(desc)
         _check(textures, torch.uint8, "textures", min_numel=S * nblk * 64 if S else None)
         desc = desc.copy()
@@ -358,7 +360,7 @@ class Context:
 
     def encode_batch(self, textures, descs, blocks, params=None, tuning=None, want_sse=False):
         """textures: list of device uint8 tensors (reorder layout); descs: list
-        of StreamDesc with format[16] set (each BC1 or BC7); blocks: list of
+        of StreamDesc with format[16] set (each BC1, BC7 or NONE); blocks: list of
         device uint8 tensors.  Returns (descs filled, band_sse int64[n][16] or
         None).  Without want_sse the call returns once the graph is queued."""
         n = len(textures)

@@ -168,7 +168,7 @@ def test_batch_errors(G, scenes):
         ctx.encode_batch([tex], [d], [small])
     assert e.value.status == gsbc.E_BUFFER
     bad = d.copy()
-    bad.format[5] = 3
+    bad.format[5] = 5   # neither BC1, BC7 nor NONE
     big = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
     with pytest.raises(gsbc.GsbcError) as e:
         ctx.encode_batch([tex], [bad], [big])

@@ -106,10 +106,12 @@ def test_classes_encode_batch_and_decode(G):
         rv, sv = O.decode_eval_view(rpay, roff, fmt, vmin, vmax, pos, rperm[start[L]:start[L + 1]], view, slots)
         err = np.abs(ov.astype(np.float64) - rv)
         assert np.all(err <= REL_TOL * sv), L
-        if nb < 16:
-            with pytest.raises(gsbc.GsbcError) as e:
-                ctx.encode(tex[L], d, fmt=gsbc.FMT_AUTO, rate=6.0)
-            assert e.value.status == gsbc.E_UNSUPPORTED
+        # the rate controller over the class's bands (exact budget, as the oracle)
+        for mode, rate in ((gsbc.FMT_AUTO, (nb + 1 + nb // 2) * 4 / nb), (gsbc.FMT_AUTO_ZERO, (nb // 2 + 2) * 4 / nb)):
+            ab, ad, _ = ctx.encode(tex[L], d, fmt=mode, rate=rate)
+            apay, aoff, afmt = O.encode_auto(rtex[L], vmin, vmax, rate, zero=mode == gsbc.FMT_AUTO_ZERO)
+            assert np.array_equal(ad.formats(), afmt) and np.array_equal(ad.offsets(), aoff), (L, mode)
+            assert ad.payload_bytes == apay.size and np.array_equal(host(ab)[:apay.size], apay), (L, mode)
         texs.append(tex[L])
         dl.append(d)
         ref.append((rpay, d2))

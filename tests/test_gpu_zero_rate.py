@@ -1,0 +1,164 @@
+"""GPU: the 0-bit rate option (Sec. IV-B, bitstreams for a varying number of
+nonzero SH vectors) through the C ABI.  The rate-controlled choice over
+{no bits, BC1, BC7} per band, the payload and each band's SSE are bit-exact
+against the oracle; streams given 0 bits store nothing and decode to zero
+(texels, decode_eval and the view decode against the oracle's FP64 colour,
+the container and the batched encoder)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2607_14513_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-5
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def G():
+    from paper_2607_14513_amd import gsbc
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    ctx = gsbc.Context(0)
+    yield gsbc, ctx
+    ctx.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def scene():
+    """3,009 primitives; the oracle's textures, ranges and every band coded
+    in both formats (blocks and SSEs), computed once."""
+    pos, sh = synth.make_scene(3000 + 9, seed=31)
+    _, rtex, vmin, vmax = O.reorder(pos, sh)
+    enc = {}
+    for b in range(16):
+        b1, s1 = O.bc1_encode(rtex[b])
+        b7, s7 = O.bc7_encode(rtex[b])
+        enc[b] = (b1, int(s1.astype(np.int64).sum()), b7, int(s7.astype(np.int64).sum()))
+    return pos, sh, rtex, vmin, vmax, enc
+
+
+def _expected(rtex, enc, fmt):
+    """Payload of the oracle's per-band encodes laid out for formats fmt."""
+    off, total = O.stream_layout(fmt, rtex.shape[1])
+    pay = np.zeros(total, np.uint8)
+    for b, f in enumerate(fmt):
+        if f == O.FMT_NONE:
+            continue
+        blk = enc[b][0] if f == O.FMT_BC1 else enc[b][2]
+        pay[int(off[b]):int(off[b]) + blk.size] = blk.reshape(-1)
+    return pay, off
+
+
+@pytest.mark.parametrize("rate", [0.5, 2.0, 3.25, 5.5, 8.0])
+def test_auto_zero_bit_exact(G, scene, rate):
+    gsbc, ctx = G
+    pos, sh, rtex, vmin, vmax, enc = scene
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    say("auto zero rate", rate)
+    blocks, d2, sse = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO_ZERO, rate=rate, want_sse=True)
+    s1 = np.array([enc[b][1] for b in range(16)], np.int64)
+    s7 = np.array([enc[b][3] for b in range(16)], np.int64)
+    assert np.array_equal(sse[0], s1) and np.array_equal(sse[1], s7)
+    want = O.rate_select_zero(s1, s7, O.band_hist(rtex), vmin, vmax, rate, 16)
+    assert np.array_equal(d2.formats(), want), (d2.formats(), want)
+    pay, off = _expected(rtex, enc, want)
+    assert np.array_equal(d2.offsets(), off) and d2.payload_bytes == pay.size
+    assert np.array_equal(host(blocks)[:pay.size], pay)
+    nblk = rtex.shape[1]
+    bits = sum({7: 128, 1: 64, 3: 0}[int(f)] * nblk for f in want)
+    assert bits == rate * 16 * nblk * 16
+    if rate == 0.5:
+        assert list(want) == [7] + [3] * 15
+    if rate == 8.0:
+        assert list(want) == [7] * 16
+    if rate in (2.0, 3.25):
+        assert (want == 3).any() and (want != 3).sum() > 1
+
+
+def test_zero_streams_decode_to_zero(G, scene):
+    """Formats set by the caller with some bands given no bits: blocks,
+    texels, colours (all slots, 9 directions), the view colour, the
+    container and the batched encoder."""
+    gsbc, ctx = G
+    pos, sh, rtex, vmin, vmax, enc = scene
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    fmt = np.array([7, 1, 3, 7, 1, 3, 3, 1, 7, 3, 1, 1, 3, 7, 1, 3], np.uint8)
+    dd = d.copy()
+    for k in range(16):
+        dd.format[k] = int(fmt[k])
+    blocks, d2, sse = ctx.encode(tex, dd, fmt=gsbc.FMT_BANDS, want_sse=True)
+    pay, off = _expected(rtex, enc, fmt)
+    assert d2.payload_bytes == pay.size and np.array_equal(d2.offsets(), off)
+    assert np.array_equal(host(blocks)[:pay.size], pay)
+    for b in range(16):
+        assert sse[0][b] == (enc[b][1] if fmt[b] == 1 else -1) and sse[1][b] == (enc[b][3] if fmt[b] == 7 else -1)
+    nblk = rtex.shape[1]
+    dec = host(ctx.decode(blocks, d2))
+    assert np.array_equal(dec, O.decode_stream(pay, off, fmt, nblk))
+    assert not dec[fmt == 3].any()
+    n = pos.shape[0]
+    dirs = synth.make_dirs(9, seed=3)
+    out = host(ctx.decode_eval(blocks, d2, dev(dirs)))
+    slots = np.arange(n, dtype=np.uint32)
+    r, sc = O.decode_eval(pay, off, fmt, vmin, vmax, dirs, slots)
+    err = np.abs(out.astype(np.float64) - r)
+    assert np.all(err <= REL_TOL * sc), float((err / np.maximum(sc, 1e-30)).max())
+    # the noalloc variant reads the same streams
+    assert np.array_equal(host(ctx.decode_eval(blocks, d2, dev(dirs), noalloc=True)), out)
+    view = np.array([0.3, -1.1, 2.0], np.float32)
+    ov = host(ctx.decode_eval_view(blocks, d2, dev(pos), perm, view))
+    rv, sv = O.decode_eval_view(pay, off, fmt, vmin, vmax, pos, host(perm).view(np.uint32), view, slots)
+    assert np.all(np.abs(ov.astype(np.float64) - rv) <= REL_TOL * sv)
+    # batched: the same bits
+    bb = [torch.zeros(pay.size + 64, dtype=torch.uint8, device="cuda")]
+    ctx.encode_batch([tex], [dd], bb)
+    assert np.array_equal(host(bb[0])[:pay.size], pay)
+
+
+def test_zero_streams_container(G, scene, tmp_path):
+    gsbc, ctx = G
+    pos, sh, rtex, vmin, vmax, enc = scene
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    blocks, d2, _ = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO_ZERO, rate=2.0)
+    assert (d2.formats() == gsbc.FMT_NONE).any()
+    path = str(tmp_path / "zero.gsbc")
+    ctx.save(path, blocks, d2)
+    b3, d3 = ctx.load(path)
+    assert np.array_equal(d3.formats(), d2.formats()) and np.array_equal(d3.offsets(), d2.offsets())
+    assert np.array_equal(host(b3)[:d2.payload_bytes], host(blocks)[:d2.payload_bytes])
+
+
+def test_zero_option_errors(G, scene):
+    gsbc, ctx = G
+    pos, sh, rtex, vmin, vmax, enc = scene
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    for rate in (0.25, 0.3, 8.25, -1.0):
+        with pytest.raises(gsbc.GsbcError) as e:
+            ctx.encode(tex, d, fmt=gsbc.FMT_AUTO_ZERO, rate=rate)
+        assert e.value.status == gsbc.E_INFEASIBLE, rate
+    _, ptex, pd = ctx.reorder(dev(pos), dev(sh), params=gsbc.default_params(arrangement=gsbc.ARR_PRIM))
+    with pytest.raises(gsbc.GsbcError) as e:
+        ctx.encode(ptex, pd, fmt=gsbc.FMT_AUTO_ZERO, rate=4.0)
+    assert e.value.status == gsbc.E_UNSUPPORTED
+    bad = pd.copy()
+    bad.format[0] = gsbc.FMT_NONE
+    with pytest.raises(gsbc.GsbcError) as e:
+        ctx.encode(ptex, bad, fmt=gsbc.FMT_BANDS)
+    assert e.value.status == gsbc.E_ARG
