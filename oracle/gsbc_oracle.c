@@ -29,6 +29,8 @@
  *   R  per-band format choice at a fixed rate    (Sec. IV-B), with or
  *      without a 0-bit option that drops a band
  *   H  SH colour c = H w(d)                      (Sec. II, colour equation)
+ *   C  front-to-back blend of premultiplied      (Sec. II, eqs. blend,
+ *      colours over per-tile lists                preblend and premult)
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -1485,6 +1487,91 @@ EXPORT void ref_decode_eval_view(const uint8_t *blocks, const uint8_t *fmt, cons
             out[(uint64_t)j * 3 + c] = acc;
             if (scale) scale[(uint64_t)j * 3 + c] = mag;
         }
+    }
+}
+
+/* Colour stage of a tile rasteriser (Sec. II, eq. preblend with the
+ * premultiplied coefficients of eq. premult): for each pixel of a tile the
+ * primitives of the tile's list, front to back, add
+ *     g_i(x) * ctilde_i * T_i,   T_1 = 1,  T_{i+1} = T_i (1 - mu_i g_i(x)),
+ * where ctilde_i = Htilde_i w(f - p_i) is the primitive's decoded colour seen
+ * from the view position f (the stored coefficients are Htilde = mu H), mu_i
+ * its opacity and g_i(x) = exp(-q/2), q = a dx^2 + 2 b dx dy + c dy^2 its
+ * projected footprint at the pixel centre: (dx, dy) = (px + 1/2, py + 1/2)
+ * minus the footprint's mean.  Image of tiles_x by tiles_y tiles of 16 by 16
+ * pixels; list[tile_start[t] .. tile_start[t+1]) holds the slot ids of tile t
+ * (t = ty * tiles_x + tx) in depth order; pos, mu and foot (mean x, mean y,
+ * a, b, c) are per primitive in input order, perm maps a slot to its
+ * primitive.  All in FP64 from the FP32 inputs; out[y][x][3] the colour,
+ * trans[y][x] the final transmittance, bound[y][x][3] = sum_i g_i T_i
+ * sum_k |Htilde_ik Y_k| (the size of the terms). */
+static void view_colour(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset, uint32_t arr, uint32_t ns,
+                        const float *vmin, const float *vmax, const float *pos, const uint32_t *perm,
+                        const float *view, uint32_t s, double col[3], double mag[3])
+{
+    const float *p = pos + 3 * (uint64_t)perm[s];
+    double d[3], r2 = 0.0;
+    for (int c = 0; c < 3; c++) {
+        d[c] = (double)view[c] - (double)p[c];
+        r2 += d[c] * d[c];
+    }
+    double r = sqrt(r2);
+    for (int c = 0; c < 3; c++) d[c] = r > 0.0 ? d[c] / r : 0.0;
+    double Y[16], H[16][3];
+    ref_sh_basis(d[0], d[1], d[2], Y);
+    slot_coefficients(blocks, fmt, offset, arr, ns, vmin, vmax, s, H);
+    for (int c = 0; c < 3; c++) {
+        col[c] = 0.0;
+        mag[c] = 0.0;
+        for (int k = 0; k < 16; k++) {
+            col[c] += H[k][c] * Y[k];
+            mag[c] += fabs(H[k][c] * Y[k]);
+        }
+    }
+}
+
+EXPORT void ref_blend_tiles(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset, uint32_t arr,
+                            uint32_t n_streams, const float *vmin, const float *vmax, const float *pos,
+                            const uint32_t *perm, const float *view, const float *mu, const float *foot,
+                            const uint32_t *tile_start, const uint32_t *list, uint32_t tiles_x, uint32_t tiles_y,
+                            double *out, double *trans, double *bound)
+{
+    const uint64_t W = 16 * (uint64_t)tiles_x;
+    #pragma omp parallel for schedule(dynamic)
+    for (int64_t t = 0; t < (int64_t)tiles_x * tiles_y; t++) {
+        const uint32_t b0 = tile_start[t], b1 = tile_start[t + 1];
+        const uint64_t tx = (uint64_t)t % tiles_x, ty = (uint64_t)t / tiles_x;
+        /* the colour of each listed primitive does not depend on the pixel */
+        double (*col)[3] = malloc(sizeof(double[3]) * (b1 > b0 ? b1 - b0 : 1));
+        double (*mag)[3] = malloc(sizeof(double[3]) * (b1 > b0 ? b1 - b0 : 1));
+        for (uint32_t e = b0; e < b1; e++)
+            view_colour(blocks, fmt, offset, arr, n_streams, vmin, vmax, pos, perm, view, list[e], col[e - b0],
+                        mag[e - b0]);
+        for (int py = 0; py < 16; py++)
+            for (int px = 0; px < 16; px++) {
+                const double x = (double)(16 * tx + px) + 0.5, y = (double)(16 * ty + py) + 0.5;
+                double a[3] = {0.0, 0.0, 0.0}, bd[3] = {0.0, 0.0, 0.0}, T = 1.0;
+                for (uint32_t e = b0; e < b1; e++) {
+                    const uint32_t i = perm[list[e]];
+                    const float *F = foot + 5 * (uint64_t)i;
+                    const double dx = x - (double)F[0], dy = y - (double)F[1];
+                    const double q = (double)F[2] * dx * dx + 2.0 * (double)F[3] * dx * dy + (double)F[4] * dy * dy;
+                    const double g = exp(-0.5 * q);
+                    for (int c = 0; c < 3; c++) {
+                        a[c] += g * col[e - b0][c] * T;
+                        bd[c] += g * T * mag[e - b0][c];
+                    }
+                    T *= 1.0 - (double)mu[i] * g;
+                }
+                const uint64_t o = (16 * ty + (uint64_t)py) * W + 16 * tx + (uint64_t)px;
+                for (int c = 0; c < 3; c++) {
+                    out[3 * o + c] = a[c];
+                    if (bound) bound[3 * o + c] = bd[c];
+                }
+                if (trans) trans[o] = T;
+            }
+        free(col);
+        free(mag);
     }
 }
 

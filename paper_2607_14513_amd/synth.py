@@ -96,6 +96,51 @@ def make_dirs(v, seed=1):
     return d.astype(np.float32)
 
 
+def make_tiles(pos, view, tiles_x, tiles_y, seed=1, sigma=(1.5, 24.0), margin=32.0):
+    """What a tile rasteriser's front end hands to its colour stage, drawn
+    synthetically: per primitive a projected footprint (pixel-space mean and
+    the conic a, b, c of a 2D Gaussian with standard deviations log-uniform
+    in ``sigma`` px at a uniform rotation; the mean uniform over the image
+    grown by ``margin`` px) and, per 16x16-pixel tile, the primitives whose
+    3-sigma box meets the tile, ordered front to back by the distance of
+    their positions to ``view`` (ties by index).  Returns float32 foot[n][5]
+    (mx, my, a, b, c), uint32 tile_start[tiles + 1], uint32 lst (primitive
+    ids; tile t = ty * tiles_x + tx)."""
+    rng = _rng(seed + 15485863)
+    n = pos.shape[0]
+    W, H = 16 * tiles_x, 16 * tiles_y
+    mx = rng.uniform(-margin, W + margin, n)
+    my = rng.uniform(-margin, H + margin, n)
+    s1 = np.exp(rng.uniform(math.log(sigma[0]), math.log(sigma[1]), n))
+    s2 = np.exp(rng.uniform(math.log(sigma[0]), math.log(sigma[1]), n))
+    th = rng.uniform(0.0, math.pi, n)
+    c, s = np.cos(th), np.sin(th)
+    # covariance R diag(s1^2, s2^2) R^T, conic = its inverse
+    sxx = c * c * s1 * s1 + s * s * s2 * s2
+    syy = s * s * s1 * s1 + c * c * s2 * s2
+    sxy = c * s * (s1 * s1 - s2 * s2)
+    det = sxx * syy - sxy * sxy
+    foot = np.stack([mx, my, syy / det, -sxy / det, sxx / det], 1).astype(np.float32)
+    depth = np.linalg.norm(pos.astype(np.float64) - np.asarray(view, np.float64)[None, :], axis=1)
+    order = np.lexsort((np.arange(n), depth))
+    r = 3.0 * np.maximum(s1, s2)
+    x0 = np.clip(np.floor((mx - r) / 16), 0, tiles_x - 1).astype(np.int64)
+    x1 = np.clip(np.floor((mx + r) / 16), -1, tiles_x - 1).astype(np.int64)
+    y0 = np.clip(np.floor((my - r) / 16), 0, tiles_y - 1).astype(np.int64)
+    y1 = np.clip(np.floor((my + r) / 16), -1, tiles_y - 1).astype(np.int64)
+    on = ~((mx + r < 0) | (my + r < 0) | (mx - r >= W) | (my - r >= H))
+    wx = np.where(on, x1 - x0 + 1, 0)
+    cnt = np.where(on, wx * (y1 - y0 + 1), 0)[order]
+    pr = np.repeat(order, cnt)                     # primitive of each (primitive, tile) entry, front to back
+    local = np.arange(pr.size) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    t = (y0[pr] + local // wx[pr]) * tiles_x + x0[pr] + local % wx[pr]
+    k = np.argsort(t, kind="stable")          # depth order kept within each tile
+    lst = pr[k].astype(np.uint32)
+    tile_start = np.zeros(tiles_x * tiles_y + 1, np.uint32)
+    np.cumsum(np.bincount(t, minlength=tiles_x * tiles_y), out=tile_start[1:])
+    return foot, tile_start, lst
+
+
 def batch_sizes(n_scenes=64, lo=50_000, hi=2_000_000, seed=4):
     """Primitive counts drawn log-uniformly from [lo, hi] (rounded)."""
     rng = _rng(seed)
