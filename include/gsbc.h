@@ -380,6 +380,39 @@ GSBC_API gsbc_status gsbc_decode_eval_view(gsbc_ctx *ctx, const uint8_t *blocks,
                                            const float *pos, const uint32_t *perm, const float *view,
                                            const uint32_t *prim_idx, uint64_t m, float *out);
 
+/* Colour stage of a tile rasteriser (Sec. II: eq. blend written as
+ * eq. preblend with the premultiplied coefficients Htilde = mu H of
+ * eq. premult, which is what the bitstreams hold when gsbc_reorder was given
+ * the opacities).  The image has tiles_x by tiles_y tiles of 16 by 16
+ * pixels; tile t = ty * tiles_x + tx.  For each pixel, with centre
+ * (16 tx + px + 1/2, 16 ty + py + 1/2), the entries i of its tile's list
+ * front to back add
+ *     a += g_i ctilde_i T,   then T *= 1 - mu_i g_i,   T starting at 1,
+ * with ctilde_i = Htilde_i w(f - p_i) the primitive's colour decoded from the
+ * bitstreams and evaluated towards the view position (as
+ * gsbc_decode_eval_view, never written to memory) and
+ * g_i = exp(-(a dx^2 + 2 b dx dy + c dy^2)/2) its footprint at the pixel.
+ * FP32 throughout; no early termination.
+ *   blocks, desc     as gsbc_decode_eval (a coded scene)
+ *   pos, perm        as gsbc_decode_eval_view
+ *   view             host float[3], the view position f
+ *   opacity          device float[n_prims], mu per primitive (input order)
+ *   footprint        device float[n_prims][5]: projected mean x, mean y (pixels)
+ *                    and conic a, b, c (the inverse 2D covariance) per primitive
+ *   tile_start       device uint32[tiles_x * tiles_y + 1]: tile t's entries are
+ *                    list[tile_start[t] .. tile_start[t+1]) (clamped to list_len)
+ *   list, list_len   device uint32[list_len]: sorted-slot ids, each tile's front
+ *                    to back; ids >= n_prims give NaN
+ *   image            device float[16 tiles_y][16 tiles_x][3] out
+ *   transmittance    device float[16 tiles_y][16 tiles_x] out (final T), or NULL
+ * GSBC_E_ARG for NULL pointers, misaligned arrays, an empty image or more
+ * than 2^31 tiles, or a non-finite view position. */
+GSBC_API gsbc_status gsbc_blend_tiles(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_desc *desc,
+                                      const float *pos, const uint32_t *perm, const float *view, const float *opacity,
+                                      const float *footprint, const uint32_t *tile_start, const uint32_t *list,
+                                      uint64_t list_len, uint32_t tiles_x, uint32_t tiles_y, float *image,
+                                      float *transmittance);
+
 /* ---------------------------------------------------------------- container */
 
 /* The durable form of a coded scene: fixed-size blocks in one bitstream per

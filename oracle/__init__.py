@@ -80,7 +80,7 @@ def _load():
             "ref_decode_eval": (None, [P, P, P, u32, u32, P, P, P, u32, P, u64, P, P]),
             "ref_decode_eval_view": (None, [P, P, P, u32, u32, P, P, P, P, P, P, u64, P, P]),
             "ref_degrees": (None, [P, u64, ctypes.c_float, P]),
-            "ref_blend_tiles": (None, [P, P, P, u32, u32, P, P, P, P, P, P, P, P, P, u32, u32, P, P, P]),
+            "ref_blend_tiles": (None, [P, P, P, u32, u32, P, P, P, P, P, P, P, P, P, u32, u32, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(_lib, name)
@@ -476,18 +476,20 @@ def decode_eval_view(payload, off, fmt, vmin, vmax, pos, perm, view, slots, with
 def blend_tiles(payload, off, fmt, vmin, vmax, pos, perm, view, mu, foot, tile_start, lst, tiles_x, tiles_y,
                 arrangement=ARR_BANDS):
     """FP64 colour stage (see ref_blend_tiles): returns (image[H][W][3],
-    transmittance[H][W], bound[H][W][3]) for an image of tiles_x by tiles_y
-    16x16-pixel tiles."""
+    transmittance[H][W], bound[H][W][3], bound_t[H][W][3]) for an image of
+    tiles_x by tiles_y 16x16-pixel tiles."""
     ns = len(fmt)
     fmt, off = _streams16(fmt, off)
     H, W = 16 * int(tiles_y), 16 * int(tiles_x)
     out = np.empty((H, W, 3), np.float64)
     trans = np.empty((H, W), np.float64)
     bound = np.empty((H, W, 3), np.float64)
+    bound_t = np.empty((H, W, 3), np.float64)
     _load().ref_blend_tiles(_p(_c(payload, np.uint8)), _p(_c(fmt, np.uint8)), _p(_c(off, np.uint64)), int(arrangement),
                             ns, _p(_c(vmin, np.float32)), _p(_c(vmax, np.float32)),
                             _p(_c(pos, np.float32).reshape(-1, 3)), _p(_c(perm, np.uint32)),
                             _p(_c(view, np.float32).reshape(3)), _p(_c(mu, np.float32)),
                             _p(_c(foot, np.float32).reshape(-1, 5)), _p(_c(tile_start, np.uint32)),
-                            _p(_c(lst, np.uint32)), int(tiles_x), int(tiles_y), _p(out), _p(trans), _p(bound))
-    return out, trans, bound
+                            _p(_c(lst, np.uint32)), int(tiles_x), int(tiles_y), _p(out), _p(trans), _p(bound),
+                            _p(bound_t))
+    return out, trans, bound, bound_t

@@ -1504,7 +1504,9 @@ EXPORT void ref_decode_eval_view(const uint8_t *blocks, const uint8_t *fmt, cons
  * a, b, c) are per primitive in input order, perm maps a slot to its
  * primitive.  All in FP64 from the FP32 inputs; out[y][x][3] the colour,
  * trans[y][x] the final transmittance, bound[y][x][3] = sum_i g_i T_i
- * sum_k |Htilde_ik Y_k| (the size of the terms). */
+ * sum_k |Htilde_ik Y_k| (the size of the terms) and bound_t[y][x][3] =
+ * sum_i i g_i sum_k |Htilde_ik Y_k| (i from 1: the terms weighted by the
+ * number of transmittance factors before them). */
 static void view_colour(const uint8_t *blocks, const uint8_t *fmt, const uint64_t *offset, uint32_t arr, uint32_t ns,
                         const float *vmin, const float *vmax, const float *pos, const uint32_t *perm,
                         const float *view, uint32_t s, double col[3], double mag[3])
@@ -1534,7 +1536,7 @@ EXPORT void ref_blend_tiles(const uint8_t *blocks, const uint8_t *fmt, const uin
                             uint32_t n_streams, const float *vmin, const float *vmax, const float *pos,
                             const uint32_t *perm, const float *view, const float *mu, const float *foot,
                             const uint32_t *tile_start, const uint32_t *list, uint32_t tiles_x, uint32_t tiles_y,
-                            double *out, double *trans, double *bound)
+                            double *out, double *trans, double *bound, double *bound_t)
 {
     const uint64_t W = 16 * (uint64_t)tiles_x;
     #pragma omp parallel for schedule(dynamic)
@@ -1550,7 +1552,7 @@ EXPORT void ref_blend_tiles(const uint8_t *blocks, const uint8_t *fmt, const uin
         for (int py = 0; py < 16; py++)
             for (int px = 0; px < 16; px++) {
                 const double x = (double)(16 * tx + px) + 0.5, y = (double)(16 * ty + py) + 0.5;
-                double a[3] = {0.0, 0.0, 0.0}, bd[3] = {0.0, 0.0, 0.0}, T = 1.0;
+                double a[3] = {0.0, 0.0, 0.0}, bd[3] = {0.0, 0.0, 0.0}, bt[3] = {0.0, 0.0, 0.0}, T = 1.0;
                 for (uint32_t e = b0; e < b1; e++) {
                     const uint32_t i = perm[list[e]];
                     const float *F = foot + 5 * (uint64_t)i;
@@ -1560,6 +1562,7 @@ EXPORT void ref_blend_tiles(const uint8_t *blocks, const uint8_t *fmt, const uin
                     for (int c = 0; c < 3; c++) {
                         a[c] += g * col[e - b0][c] * T;
                         bd[c] += g * T * mag[e - b0][c];
+                        bt[c] += (double)(e - b0 + 1) * g * mag[e - b0][c];
                     }
                     T *= 1.0 - (double)mu[i] * g;
                 }
@@ -1567,6 +1570,7 @@ EXPORT void ref_blend_tiles(const uint8_t *blocks, const uint8_t *fmt, const uin
                 for (int c = 0; c < 3; c++) {
                     out[3 * o + c] = a[c];
                     if (bound) bound[3 * o + c] = bd[c];
+                    if (bound_t) bound_t[3 * o + c] = bt[c];
                 }
                 if (trans) trans[o] = T;
             }

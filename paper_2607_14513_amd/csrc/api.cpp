@@ -1101,6 +1101,31 @@ gsbc_status gsbc_decode_eval_view(gsbc_ctx *ctx, const uint8_t *blocks, const gs
     return GSBC_OK;
 }
 
+gsbc_status gsbc_blend_tiles(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_stream_desc *desc, const float *pos,
+                             const uint32_t *perm, const float *view, const float *opacity, const float *footprint,
+                             const uint32_t *tile_start, const uint32_t *list, uint64_t list_len, uint32_t tiles_x,
+                             uint32_t tiles_y, float *image, float *transmittance)
+{
+    gsbc_status s = begin(ctx);
+    if (s) return s;
+    ActiveGuard guard(ctx);
+    if (!blocks || !pos || !perm || !view || !opacity || !footprint || !tile_start || !image || (!list && list_len))
+        return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
+    if (reinterpret_cast<uintptr_t>(blocks) & 15) return fail(ctx, GSBC_E_ARG, "blocks must be 16-byte aligned");
+    for (const void *q : {(const void *)pos, (const void *)perm, (const void *)opacity, (const void *)footprint,
+                          (const void *)tile_start, (const void *)list, (const void *)image, (const void *)transmittance})
+        if (reinterpret_cast<uintptr_t>(q) & 3) return fail(ctx, GSBC_E_ARG, "device arrays must be 4-byte aligned");
+    if ((s = check_stream(ctx, desc))) return s;
+    const uint64_t tiles = (uint64_t)tiles_x * tiles_y;
+    if (tiles == 0 || tiles > 0x7FFFFFFFull) return fail(ctx, GSBC_E_ARG, "%u x %u tiles", tiles_x, tiles_y);
+    const float f[3] = {view[0], view[1], view[2]};
+    if (!(isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2]))) return fail(ctx, GSBC_E_ARG, "view position not finite");
+    HIP_TRY(ctx, launch_blend_tiles(blocks, band_args(desc), desc->n_prims, pos, perm, f, opacity, footprint, tile_start,
+                                    list, list_len, tiles_x, tiles_y, image, transmittance, ctx->stream),
+            "blend_tiles launch");
+    return GSBC_OK;
+}
+
 gsbc_status gsbc_profile_enable(gsbc_ctx *ctx, int on)
 {
     gsbc_status s = begin(ctx);

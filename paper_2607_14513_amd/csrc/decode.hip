@@ -405,11 +405,55 @@ __global__ __launch_bounds__(kEvalBlock) __attribute__((amdgpu_waves_per_eu(3)))
     decode_eval_body<8>(blocks, b, prim_idx, m, n_prims, basis, n_dirs, out);
 }
 
-// Colour of each listed slot seen from one view position f (Sec. II,
-// c(f) = H w(f - p)): one lane per slot gathers its primitive's position
-// through perm, takes d = (f - p)/|f - p| (zero when f = p), evaluates the 16
-// basis functions and dots them with the decoded, dequantised texels (FP32,
-// k order).  Out-of-range slot ids give NaN.
+// Colour of slot s seen from view position f (Sec. II, c(f) = H w(f - p)):
+// its primitive's position through perm, d = (f - p)/|f - p| (zero when
+// f = p), the 16 basis functions dotted with the decoded, dequantised texels
+// (FP32, k order).  s must be below the scene's n_prims.
+__device__ __forceinline__ void view_colour(const uint8_t *blocks, const BandArgs &b, uint32_t s, const float *pos,
+                                            const uint32_t *perm, float fx, float fy, float fz, float c[3])
+{
+    const uint64_t pi = perm[s];
+    float x = fx - pos[3 * pi], y = fy - pos[3 * pi + 1], z = fz - pos[3 * pi + 2];
+    const float r = sqrtf(x * x + y * y + z * z);
+    const float inv = r > 0.0f ? 1.0f / r : 0.0f;
+    x *= inv;
+    y *= inv;
+    z *= inv;
+    const float c0 = 0.28209479177387814f, c1 = 0.4886025119029199f;
+    const float c2a = 1.0925484305920792f, c2b = 0.31539156525252005f, c2c = 0.5462742152960396f;
+    const float c3a = 0.5900435899266435f, c3b = 2.890611442640554f, c3c = 0.4570457994644658f;
+    const float c3d = 0.3731763325901154f, c3e = 1.445305721320277f;
+    const float xx = x * x, yy = y * y, zz = z * z;
+    float Y[16];
+    Y[0] = c0;
+    Y[1] = -c1 * y;
+    Y[2] = c1 * z;
+    Y[3] = -c1 * x;
+    Y[4] = c2a * x * y;
+    Y[5] = -c2a * y * z;
+    Y[6] = c2b * (2.0f * zz - xx - yy);
+    Y[7] = -c2a * x * z;
+    Y[8] = c2c * (xx - yy);
+    Y[9] = -c3a * y * (3.0f * xx - yy);
+    Y[10] = c3b * x * y * z;
+    Y[11] = -c3c * y * (4.0f * zz - xx - yy);
+    Y[12] = c3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
+    Y[13] = -c3c * x * (4.0f * zz - xx - yy);
+    Y[14] = c3e * z * (xx - yy);
+    Y[15] = -c3a * x * (xx - 3.0f * yy);
+    uint32_t px[16];
+    slot_texels(blocks, b, s, px);
+    c[0] = c[1] = c[2] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < 16; k++) {
+        if (band_coded(b, k)) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ch++) c[ch] = fmaf(dequant(px[k] >> (8 * ch), b, k), Y[k], c[ch]);
+        }
+    }
+}
+
+// One lane per listed slot; out-of-range slot ids give NaN.
 __global__ __launch_bounds__(256) void k_decode_eval_view(const uint8_t *blocks, BandArgs b, const uint32_t *prim_idx,
                                                           uint64_t m, uint64_t n_prims, const float *pos,
                                                           const uint32_t *perm, float fx, float fy, float fz,
@@ -419,54 +463,85 @@ __global__ __launch_bounds__(256) void k_decode_eval_view(const uint8_t *blocks,
     if (j >= m) return;
     const uint32_t s = prim_idx ? prim_idx[j] : (uint32_t)j;
     float c[3] = {__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
-    if (s < n_prims) {
-        const uint64_t pi = perm[s];
-        float x = fx - pos[3 * pi], y = fy - pos[3 * pi + 1], z = fz - pos[3 * pi + 2];
-        const float r = sqrtf(x * x + y * y + z * z);
-        const float inv = r > 0.0f ? 1.0f / r : 0.0f;
-        x *= inv;
-        y *= inv;
-        z *= inv;
-        const float c0 = 0.28209479177387814f, c1 = 0.4886025119029199f;
-        const float c2a = 1.0925484305920792f, c2b = 0.31539156525252005f, c2c = 0.5462742152960396f;
-        const float c3a = 0.5900435899266435f, c3b = 2.890611442640554f, c3c = 0.4570457994644658f;
-        const float c3d = 0.3731763325901154f, c3e = 1.445305721320277f;
-        const float xx = x * x, yy = y * y, zz = z * z;
-        float Y[16];
-        Y[0] = c0;
-        Y[1] = -c1 * y;
-        Y[2] = c1 * z;
-        Y[3] = -c1 * x;
-        Y[4] = c2a * x * y;
-        Y[5] = -c2a * y * z;
-        Y[6] = c2b * (2.0f * zz - xx - yy);
-        Y[7] = -c2a * x * z;
-        Y[8] = c2c * (xx - yy);
-        Y[9] = -c3a * y * (3.0f * xx - yy);
-        Y[10] = c3b * x * y * z;
-        Y[11] = -c3c * y * (4.0f * zz - xx - yy);
-        Y[12] = c3d * z * (2.0f * zz - 3.0f * xx - 3.0f * yy);
-        Y[13] = -c3c * x * (4.0f * zz - xx - yy);
-        Y[14] = c3e * z * (xx - yy);
-        Y[15] = -c3a * x * (xx - 3.0f * yy);
-        uint32_t px[16];
-        slot_texels(blocks, b, s, px);
-        c[0] = c[1] = c[2] = 0.0f;
-#pragma unroll
-        for (int k = 0; k < 16; k++) {
-            if (band_coded(b, k)) {
-#pragma unroll
-                for (int ch = 0; ch < 3; ch++)
-                    c[ch] = fmaf(dequant(px[k] >> (8 * ch), b, k), Y[k], c[ch]);
-            }
-        }
-    }
+    if (s < n_prims) view_colour(blocks, b, s, pos, perm, fx, fy, fz, c);
     out[3 * j] = c[0];
     out[3 * j + 1] = c[1];
     out[3 * j + 2] = c[2];
 }
 
+// Colour stage of a tile rasteriser (Sec. II, eq. preblend with the
+// premultiplied coefficients of eq. premult), one workgroup per 16x16 tile,
+// one lane per pixel.  The tile's list is taken 256 entries at a time: lane t
+// decodes entry t's colour c~ = Htilde w(f - p) from the bitstreams (no
+// colour buffer in HBM) and stages it in LDS with the primitive's footprint
+// (mean x, mean y, conic a, b, c) and opacity mu; then every pixel walks the
+// staged entries front to back: g = exp(-q/2) at its centre,
+// a += g c~ T, T *= 1 - mu g.  A list entry past n_prims gives NaN colour.
+__global__ __launch_bounds__(256) void k_blend_tiles(const uint8_t *blocks, BandArgs b, uint64_t n_prims,
+                                                     const float *pos, const uint32_t *perm, float fx, float fy,
+                                                     float fz, const float *mu, const float *foot,
+                                                     const uint32_t *tile_start, const uint32_t *list,
+                                                     uint64_t list_len, uint32_t tiles_x, float *image, float *trans)
+{
+    __shared__ float s_par[256][9];   // mean x, mean y, a, b, c, mu, colour r, g, b
+    const uint32_t t = threadIdx.x, tile = blockIdx.x;
+    const uint32_t tx = tile % tiles_x, ty = tile / tiles_x;
+    const float x = (float)(16 * tx + (t & 15u)) + 0.5f, y = (float)(16 * ty + (t >> 4)) + 0.5f;
+    const uint64_t b1 = min((uint64_t)tile_start[tile + 1], list_len);
+    const uint64_t b0 = min((uint64_t)tile_start[tile], b1);
+    float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, T = 1.0f;
+    for (uint64_t base = b0; base < b1; base += 256) {
+        const uint64_t e = base + t;
+        if (e < b1) {
+            const uint32_t s = list[e];
+            float c[3] = {__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
+            uint64_t i = 0;
+            if (s < n_prims) {
+                view_colour(blocks, b, s, pos, perm, fx, fy, fz, c);
+                i = perm[s];
+            }
+#pragma unroll
+            for (int q = 0; q < 5; q++) s_par[t][q] = foot[5 * i + q];
+            s_par[t][5] = mu[i];
+            s_par[t][6] = c[0];
+            s_par[t][7] = c[1];
+            s_par[t][8] = c[2];
+        }
+        __syncthreads();
+        const uint32_t cnt = (uint32_t)(b1 - base < 256 ? b1 - base : 256);
+        for (uint32_t j = 0; j < cnt; j++) {
+            const float dx = x - s_par[j][0], dy = y - s_par[j][1];
+            const float q = fmaf(s_par[j][2] * dx, dx, fmaf(2.0f * s_par[j][3] * dx, dy, s_par[j][4] * dy * dy));
+            const float g = __expf(-0.5f * q);
+            const float w = g * T;
+            a0 = fmaf(w, s_par[j][6], a0);
+            a1 = fmaf(w, s_par[j][7], a1);
+            a2 = fmaf(w, s_par[j][8], a2);
+            T *= 1.0f - s_par[j][5] * g;
+        }
+        __syncthreads();
+    }
+    const uint64_t W = 16 * (uint64_t)tiles_x;
+    const uint64_t o = (16 * (uint64_t)ty + (t >> 4)) * W + 16 * tx + (t & 15u);
+    image[3 * o] = a0;
+    image[3 * o + 1] = a1;
+    image[3 * o + 2] = a2;
+    if (trans) trans[o] = T;
+}
+
 }  // namespace
+
+hipError_t launch_blend_tiles(const uint8_t *blocks, const BandArgs &b, uint64_t n_prims, const float *pos,
+                              const uint32_t *perm, const float view[3], const float *mu, const float *foot,
+                              const uint32_t *tile_start, const uint32_t *list, uint64_t list_len, uint32_t tiles_x,
+                              uint32_t tiles_y, float *image, float *trans, hipStream_t st)
+{
+    const uint64_t tiles = (uint64_t)tiles_x * tiles_y;
+    if (tiles == 0) return hipSuccess;
+    GSBC_LAUNCH("blend_tiles", k_blend_tiles, dim3((uint32_t)tiles), dim3(256), 0, st, blocks, b, n_prims, pos, perm,
+                view[0], view[1], view[2], mu, foot, tile_start, list, list_len, tiles_x, image, trans);
+    return hipGetLastError();
+}
 
 hipError_t launch_decode_eval_view(const uint8_t *blocks, const BandArgs &b, uint64_t n_prims, const float *pos,
                                    const uint32_t *perm, const float view[3], const uint32_t *prim_idx, uint64_t m,

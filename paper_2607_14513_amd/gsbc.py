@@ -22,7 +22,7 @@ N_STREAMS = {ARR_BANDS: 16, ARR_PRIM: 1, ARR_QUAD: 4}
 EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_reserve", "gsbc_arena_info",
             "gsbc_default_params",
             "gsbc_query_sizes", "gsbc_reorder", "gsbc_reorder_degrees", "gsbc_encode", "gsbc_default_batch_tuning",
-            "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_decode_eval_noalloc", "gsbc_decode_eval_view",
+            "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_decode_eval_noalloc", "gsbc_decode_eval_view", "gsbc_blend_tiles",
             "gsbc_save", "gsbc_load",
             "gsbc_profile_enable", "gsbc_profile_read")
 
@@ -106,6 +106,7 @@ def load():
         lib.gsbc_decode_eval.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, u32, P, u64, P]
         lib.gsbc_decode_eval_noalloc.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, u32, P, u64, P]
         lib.gsbc_decode_eval_view.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, P, P, P, u64, P]
+        lib.gsbc_blend_tiles.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, P, P, P, P, P, P, u64, u32, u32, P, P]
         lib.gsbc_save.argtypes = [P, P, ctypes.POINTER(StreamDesc), ctypes.c_char_p]
         lib.gsbc_load.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(StreamDesc), P, u64]
         lib.gsbc_profile_enable.argtypes = [P, ctypes.c_int]
@@ -407,6 +408,41 @@ class Context:
         self._check(load().gsbc_decode_eval_view(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(pos), _ptr(perm), f,
                                                  _ptr(prim_idx), m, _ptr(out)))
         return out
+
+    def blend_tiles(self, blocks, desc, pos, perm, view, opacity, footprint, tile_start, lst, tiles_x, tiles_y,
+                    image=None, transmittance=None, want_transmittance=True):
+        """The colour stage over per-tile front-to-back lists (device tensors:
+        pos float32[N][3], perm int32[n_prims], opacity float32[N],
+        footprint float32[N][5], tile_start int32[tiles + 1], lst int32[L]
+        of sorted-slot ids; view 3 host floats) -> (image float32[H][W][3],
+        transmittance float32[H][W] or None)."""
+        _, _, payload, n = _sizes(desc)
+        _check(blocks, torch.uint8, "blocks", min_numel=payload)
+        _check(pos, torch.float32, "pos")
+        if pos.dim() != 2 or pos.shape[1] != 3 or (n and pos.shape[0] < n):
+            raise ValueError(f"pos has shape {tuple(pos.shape)}, expected (N, 3) with N >= {n}")
+        N = pos.shape[0]
+        _check(perm, torch.int32, "perm", shape=(n,) if n else None)
+        _check(opacity, torch.float32, "opacity", shape=(N,))
+        _check(footprint, torch.float32, "footprint", shape=(N, 5))
+        tiles = int(tiles_x) * int(tiles_y)
+        _check(tile_start, torch.int32, "tile_start", shape=(tiles + 1,))
+        _check(lst, torch.int32, "lst")
+        H, W = 16 * int(tiles_y), 16 * int(tiles_x)
+        if image is None:
+            image = torch.empty((H, W, 3), dtype=torch.float32, device=self.device)
+        _check(image, torch.float32, "image", shape=(H, W, 3))
+        if transmittance is None and want_transmittance:
+            transmittance = torch.empty((H, W), dtype=torch.float32, device=self.device)
+        if transmittance is not None:
+            _check(transmittance, torch.float32, "transmittance", shape=(H, W))
+        _on_device(("blocks", blocks), ("pos", pos), ("perm", perm), ("opacity", opacity), ("footprint", footprint),
+                   ("tile_start", tile_start), ("lst", lst), ("image", image), ("transmittance", transmittance))
+        f = (ctypes.c_float * 3)(*[float(x) for x in view])
+        self._check(load().gsbc_blend_tiles(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(pos), _ptr(perm), f,
+                                            _ptr(opacity), _ptr(footprint), _ptr(tile_start), _ptr(lst), lst.numel(),
+                                            int(tiles_x), int(tiles_y), _ptr(image), _ptr(transmittance)))
+        return image, transmittance
 
     def save(self, path, blocks, desc):
         """Write the coded scene (device blocks + desc) as a container file."""

@@ -41,7 +41,7 @@ def _g(foot, x, y):
 
 def _run(coded, mu, foot, tile_start, lst, tx, ty):
     pos, perm, payload, off, fmt, vmin, vmax = coded
-    return O.blend_tiles(payload, off, fmt, vmin, vmax, pos, perm, VIEW, mu, foot, tile_start, lst, tx, ty)
+    return O.blend_tiles(payload, off, fmt, vmin, vmax, pos, perm, VIEW, mu, foot, tile_start, lst, tx, ty)[:3]
 
 
 def _conic(sx, sy):
