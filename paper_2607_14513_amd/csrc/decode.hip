@@ -474,21 +474,26 @@ __global__ __launch_bounds__(256) void k_decode_eval_view(const uint8_t *blocks,
 // one lane per pixel.  The tile's list is taken 256 entries at a time: lane t
 // decodes entry t's colour c~ = Htilde w(f - p) from the bitstreams (no
 // colour buffer in HBM) and stages it in LDS with the primitive's footprint
-// (mean x, mean y, conic a, b, c) and opacity mu; then every pixel walks the
-// staged entries front to back: g = exp(-q/2) at its centre,
-// a += g c~ T, T *= 1 - mu g.  A list entry past n_prims gives NaN colour.
+// and opacity mu, the conic turned into base-2 exponent coefficients
+// (A, B, C) = -log2(e) (a/2, b, c/2); then every pixel walks the staged
+// entries front to back: g = 2^(A dx^2 + B dx dy + C dy^2) at its centre,
+// a += (g T) c~, T -= (T mu) g.  A list entry past n_prims gives NaN colour.
+// Once every pixel of a wave (or of the tile) has T exactly 0, the remaining
+// entries change nothing (g T = 0 and T stays 0 for finite colours) and are
+// skipped.
 __global__ __launch_bounds__(256) void k_blend_tiles(const uint8_t *blocks, BandArgs b, uint64_t n_prims,
                                                      const float *pos, const uint32_t *perm, float fx, float fy,
                                                      float fz, const float *mu, const float *foot,
                                                      const uint32_t *tile_start, const uint32_t *list,
                                                      uint64_t list_len, uint32_t tiles_x, float *image, float *trans)
 {
-    __shared__ float s_par[256][9];   // mean x, mean y, a, b, c, mu, colour r, g, b
+    __shared__ float s_par[256][9];   // mean x, mean y, A, B, C, mu, colour r, g, b
     const uint32_t t = threadIdx.x, tile = blockIdx.x;
     const uint32_t tx = tile % tiles_x, ty = tile / tiles_x;
     const float x = (float)(16 * tx + (t & 15u)) + 0.5f, y = (float)(16 * ty + (t >> 4)) + 0.5f;
     const uint64_t b1 = min((uint64_t)tile_start[tile + 1], list_len);
     const uint64_t b0 = min((uint64_t)tile_start[tile], b1);
+    constexpr float kLog2e = 1.4426950408889634f;
     float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f, T = 1.0f;
     for (uint64_t base = b0; base < b1; base += 256) {
         const uint64_t e = base + t;
@@ -500,8 +505,11 @@ __global__ __launch_bounds__(256) void k_blend_tiles(const uint8_t *blocks, Band
                 view_colour(blocks, b, s, pos, perm, fx, fy, fz, c);
                 i = perm[s];
             }
-#pragma unroll
-            for (int q = 0; q < 5; q++) s_par[t][q] = foot[5 * i + q];
+            s_par[t][0] = foot[5 * i];
+            s_par[t][1] = foot[5 * i + 1];
+            s_par[t][2] = -0.5f * kLog2e * foot[5 * i + 2];
+            s_par[t][3] = -kLog2e * foot[5 * i + 3];
+            s_par[t][4] = -0.5f * kLog2e * foot[5 * i + 4];
             s_par[t][5] = mu[i];
             s_par[t][6] = c[0];
             s_par[t][7] = c[1];
@@ -509,17 +517,21 @@ __global__ __launch_bounds__(256) void k_blend_tiles(const uint8_t *blocks, Band
         }
         __syncthreads();
         const uint32_t cnt = (uint32_t)(b1 - base < 256 ? b1 - base : 256);
-        for (uint32_t j = 0; j < cnt; j++) {
-            const float dx = x - s_par[j][0], dy = y - s_par[j][1];
-            const float q = fmaf(s_par[j][2] * dx, dx, fmaf(2.0f * s_par[j][3] * dx, dy, s_par[j][4] * dy * dy));
-            const float g = __expf(-0.5f * q);
-            const float w = g * T;
-            a0 = fmaf(w, s_par[j][6], a0);
-            a1 = fmaf(w, s_par[j][7], a1);
-            a2 = fmaf(w, s_par[j][8], a2);
-            T *= 1.0f - s_par[j][5] * g;
+        for (uint32_t j0 = 0; j0 < cnt; j0 += 32) {
+            if (__all(T == 0.0f)) break;   // this wave is done for the chunk
+            const uint32_t j1 = j0 + 32 < cnt ? j0 + 32 : cnt;
+            for (uint32_t j = j0; j < j1; j++) {
+                const float dx = x - s_par[j][0], dy = y - s_par[j][1];
+                const float ex = fmaf(dx, fmaf(s_par[j][2], dx, s_par[j][3] * dy), s_par[j][4] * dy * dy);
+                const float g = __builtin_amdgcn_exp2f(ex);
+                const float w = g * T, m = T * s_par[j][5];
+                a0 = fmaf(w, s_par[j][6], a0);
+                a1 = fmaf(w, s_par[j][7], a1);
+                a2 = fmaf(w, s_par[j][8], a2);
+                T = fmaf(-m, g, T);
+            }
         }
-        __syncthreads();
+        if (__syncthreads_and(T == 0.0f)) break;   // every pixel of the tile is covered
     }
     const uint64_t W = 16 * (uint64_t)tiles_x;
     const uint64_t o = (16 * (uint64_t)ty + (t >> 4)) * W + 16 * tx + (t & 15u);

@@ -96,21 +96,37 @@ def make_dirs(v, seed=1):
     return d.astype(np.float32)
 
 
-def make_tiles(pos, view, tiles_x, tiles_y, seed=1, sigma=(1.5, 24.0), margin=32.0):
+def make_tiles(pos, view, tiles_x, tiles_y, seed=1, sigma=(1.5, 24.0), fov=60.0):
     """What a tile rasteriser's front end hands to its colour stage, drawn
     synthetically: per primitive a projected footprint (pixel-space mean and
-    the conic a, b, c of a 2D Gaussian with standard deviations log-uniform
-    in ``sigma`` px at a uniform rotation; the mean uniform over the image
-    grown by ``margin`` px) and, per 16x16-pixel tile, the primitives whose
-    3-sigma box meets the tile, ordered front to back by the distance of
-    their positions to ``view`` (ties by index).  Returns float32 foot[n][5]
-    (mx, my, a, b, c), uint32 tile_start[tiles + 1], uint32 lst (primitive
-    ids; tile t = ty * tiles_x + tx)."""
+    the conic a, b, c of a 2D Gaussian) and, per 16x16-pixel tile, the
+    primitives whose 3-sigma box meets the tile, ordered front to back by the
+    distance of their positions to ``view`` (ties by index).  The mean is the
+    primitive's position seen by a pinhole camera at ``view`` looking at the
+    scene centre (0.5, 0.5, 0.5) with a ``fov``-degree horizontal field over
+    the image (primitives behind the camera, or whose 3-sigma box misses the
+    image, are in no list), so a tile's primitives come from one region of the
+    scene as a rasteriser's do; the footprint's standard deviations are
+    log-uniform in ``sigma`` px at a uniform rotation.  Returns float32
+    foot[n][5] (mx, my, a, b, c), uint32 tile_start[tiles + 1], uint32 lst
+    (primitive ids; tile t = ty * tiles_x + tx)."""
     rng = _rng(seed + 15485863)
     n = pos.shape[0]
     W, H = 16 * tiles_x, 16 * tiles_y
-    mx = rng.uniform(-margin, W + margin, n)
-    my = rng.uniform(-margin, H + margin, n)
+    f = np.asarray(view, np.float64)
+    fwd = np.array([0.5, 0.5, 0.5]) - f
+    fwd /= np.linalg.norm(fwd)
+    right = np.cross(fwd, [0.0, 1.0, 0.0])
+    right = right / np.linalg.norm(right) if np.linalg.norm(right) > 1e-9 else np.array([1.0, 0.0, 0.0])
+    up = np.cross(right, fwd)
+    rel = pos.astype(np.float64) - f[None, :]
+    z = rel @ fwd
+    focal = 0.5 * W / math.tan(math.radians(fov) / 2)
+    zs = np.where(z > 1e-6, z, 1.0)
+    mx = np.where(z > 1e-6, 0.5 * W + focal * (rel @ right) / zs, -1e9)
+    my = np.where(z > 1e-6, 0.5 * H - focal * (rel @ up) / zs, -1e9)
+    mx = np.clip(mx, -1e7, 1e7)
+    my = np.clip(my, -1e7, 1e7)
     s1 = np.exp(rng.uniform(math.log(sigma[0]), math.log(sigma[1]), n))
     s2 = np.exp(rng.uniform(math.log(sigma[0]), math.log(sigma[1]), n))
     th = rng.uniform(0.0, math.pi, n)

@@ -1,14 +1,16 @@
 """GPU: the colour stage of a tile rasteriser (Sec. II, eqs. blend,
 preblend, premult) through the C ABI against the oracle's FP64 blend.
 
-Bound (FP32 against FP64, per pixel and channel):
+Bound (FP32 against FP64, per pixel and channel, for a list of L entries):
   |a32 - a64| <= 3e-5 * sum_i g_i T_i |c~_i| + 4 * 2^-24 * sum_i i g_i |c~_i|
+                 + (L + 1) * 2^-120
 where |c~_i| = sum_k |Htilde_ik Y_k|.  The first term covers each colour's
 FP32 evaluation (within 1e-5 of its term size, the view decode's bound) and
 the FP32 footprint g (q and exp, within 2e-5 where g matters); the second
 the transmittance, whose i-th factor product carries an absolute error of at
-most about 3 i roundings of 2^-24 (each factor 1 - mu g <= 1).  The final
-transmittance is checked against 3 (L + 1) 2^-24 for a list of L entries."""
+most about 3 i roundings of 2^-24 (each factor 1 - mu g <= 1); the third
+FP32 underflow (g T below 2^-126 flushed, times colours well under 64).
+The final transmittance is checked against 3 (L + 1) 2^-24."""
 import sys
 
 import numpy as np
@@ -48,11 +50,11 @@ def host(t):
 
 def _check(img, T, ref, ts, tx, ty):
     r, rt, b, bt = ref
-    err = np.abs(img.astype(np.float64) - r)
-    lim = 3e-5 * b + 4 * U * bt
-    assert np.all(err <= lim), float((err - lim).max())
     L = np.diff(ts.astype(np.int64)).reshape(ty, tx)
     Lpix = np.repeat(np.repeat(L, 16, 0), 16, 1)
+    err = np.abs(img.astype(np.float64) - r)
+    lim = 3e-5 * b + 4 * U * bt + (Lpix[..., None] + 1) * 2.0 ** -120
+    assert np.all(err <= lim), float((err - lim).max())
     assert np.all(np.abs(T.astype(np.float64) - rt) <= 3 * (Lpix + 1) * U)
 
 
