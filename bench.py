@@ -26,7 +26,8 @@ step time, in Mblocks/s.  Also reported:
                       for every instruction, so it can read slightly above 1);
   roofline_decode_eval  decode + SH evaluation of 3,145,728 primitives at
                       1,024 directions: bytes written+read per launch / time,
-                      against 8 TB/s;
+                      against 8 TB/s; with the view decode and the fused
+                      colour stage (tile blend at 1920x1088) of that scene;
   cpu_baseline        the CPU oracle on a bounded sample of the same step.
 """
 import argparse
@@ -91,21 +92,27 @@ def traffic_bytes(name):
     return profiled(name, "bytes")
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def med_min(ts, scale=1.0, nd=4):
     """Median and minimum of repeated timings (scaled, rounded)."""
     return {"median": round(float(np.median(ts)) * scale, nd), "min": round(float(np.min(ts)) * scale, nd)}
 
 
 def kernel_ms(ctx, name, call, reps):
-    """Device time of kernel `name` in each of `reps` calls (the library's
-    HIP events on its stream), ms."""
+    """Device time of the kernel(s) `name` (one name or a tuple, summed) in
+    each of `reps` calls (the library's HIP events on its stream), ms."""
+    names = (name,) if isinstance(name, str) else tuple(name)
     ctx.profile(True)
     ctx.profile_read()
     ts = []
     for _ in range(reps):
         call()
         k = ctx.profile_read()
-        ts.append(k[name][1] / k[name][0])
+        ts.append(sum(k[nm][1] / k[nm][0] for nm in names))
     ctx.profile(False)
     return ts
 
@@ -197,6 +204,7 @@ def main():
         blocks_per_step = 2 * 16 * nblk
         value = blocks_per_step / (ms_step * 1e-3) / 1e6
 
+        progress(f"timed {args.steps} steps: {ms_step:.3f} ms per step")
         # ---- per-kernel device times of the same step (HIP events the library
         # records on its stream around every launch), read back step by step
         ctx.profile(True)
@@ -241,6 +249,7 @@ def main():
                 valu[name] = {"valu_insts_per_launch": insts, "launch_ms": round(t * 1e3, 4),
                               "issue_busy": round(insts / t / VALU_ISSUE_PEAK, 4)}
 
+        progress("per-kernel times done")
         # ---- whole-format encode rates (every band in one format)
         d7 = d2.copy()
         rates = {}
@@ -271,6 +280,7 @@ def main():
                 "bc7_input_order": band_psnr(tex_id, gsbc.FMT_BC7)}
         del tex_id
 
+        progress("format rates and PSNR done")
         # ---- the arrangements of Table I (Figs. SetupA, SetupB, SetupD) on this
         # scene: PSNR of the decoded texels over all bands and slots, and the
         # coded bytes per primitive
@@ -378,6 +388,7 @@ def main():
             del posg_d, shg_d, permg, texg, tx, bufs, tfull
             torch.cuda.empty_cache()
 
+        progress("arrangements and degree classes done")
         # ---- decode_eval on the 3,145,728-primitive scene at 1,024 directions
         roof_de = None
         if not args.no_large:
@@ -449,7 +460,33 @@ def main():
                         "ms": med_min(t_view), "gslots_s": round(c3["n"] / view_s / 1e9, 3),
                         "bytes": int(dd2.payload_bytes + c3["n"] * (12 + 4 + 12))}
             view_leg["gb_s"] = round(view_leg["bytes"] / view_s / 1e9, 1)
-            del pos3d, p3
+            # the fused colour stage: a 1920 x 1088 image of 16 x 16 tiles whose
+            # front-to-back lists come from projecting the scene from the same
+            # view position (footprints 0.7-6 px); every entry's colour decoded
+            # in the tile's workgroup, nothing per primitive written to memory
+            mu3 = synth.make_opacity(c3["n"], seed=c3["seed"])
+            foot3, ts3, lst3 = synth.make_tiles(pos3, view, 120, 68, seed=c3["seed"], sigma=(0.7, 6.0))
+            slot3 = np.argsort(p3.cpu().numpy().view(np.uint32)).astype(np.int32)
+            mu3d, foot3d = torch.from_numpy(mu3).to(dev), torch.from_numpy(foot3).to(dev)
+            ts3d = torch.from_numpy(ts3.astype(np.int32)).to(dev)
+            lst3d = torch.from_numpy(slot3[lst3]).to(dev)
+            img3, tr3 = ctx.blend_tiles(b3, dd2, pos3d, p3, view, mu3d, foot3d, ts3d, lst3d, 120, 68)
+            t_bl = kernel_ms(ctx, ("tile_order", "blend_tiles"), lambda: ctx.blend_tiles(b3, dd2, pos3d, p3, view, mu3d, foot3d, ts3d,
+                                                                         lst3d, 120, 68, image=img3,
+                                                                         transmittance=tr3), 3)
+            bl_s = float(np.median(t_bl)) * 1e-3
+            entries = int(ts3[-1])
+            colour_leg = {"workload": "1920x1088 image (120x68 tiles of 16x16), 3,145,728 primitives projected from "
+                                      "the view position, footprint sigmas 0.7-6 px, front-to-back tile lists",
+                          "ms": med_min(t_bl), "list_entries": entries,
+                          "max_entries_per_tile": int(np.diff(ts3.astype(np.int64)).max()),
+                          "gentries_s": round(entries / bl_s / 1e9, 3),
+                          "listed_pixel_pairs_gs": round(256 * entries / bl_s / 1e9, 1),
+                          # 18 issue slots per pixel-entry pair at least (footprint 7, exp 4,
+                          # weights and transmittance 4, colour 3); tiles stop at T = 0 exactly,
+                          # so this counts listed pairs, not executed ones
+                          "alu_frac_listed_pairs": round(18 * 256 * entries / bl_s / VALU_PEAK, 4)}
+            del pos3d, p3, img3, tr3, lst3d, ts3d, foot3d, mu3d
             # context: a plain device fill of the same output (write ceiling)
             tf = []
             for i in range(3):
@@ -467,12 +504,16 @@ def main():
                        "traffic": tr_de, "launch_ms": de_s * 1e3, "launch_ms_stats": med_min(t_de),
                        "workload": "3,145,728 primitives x 1,024 directions, 6 bits/texel",
                        "split": split, "plain_fill_gbps": round(fill_gbps, 1),
-                       "fill_ms": med_min(tf, 1e3), "view": view_leg, "encode": large_enc}
+                       "fill_ms": med_min(tf, 1e3), "view": view_leg, "colour_stage": colour_leg,
+                       "encode": large_enc}
             del out3, b3, pos3_d
             torch.cuda.empty_cache()
+        progress("large scene legs done")
         batch = None if args.no_batch else batch_leg(ctx, stream, dev, args.batch_scenes, max(3, args.steps))
         ctx.close()
+    progress("batch leg done")
     served = None if args.no_serve else serve_leg(dev, args.serve_requests)
+    progress("serving leg done")
 
     cpu = None if args.no_cpu else cpu_baseline(pos, sh, dirs, rate)
     line = {

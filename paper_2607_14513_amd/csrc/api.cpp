@@ -1120,8 +1120,10 @@ gsbc_status gsbc_blend_tiles(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_st
     if (tiles == 0 || tiles > 0x7FFFFFFFull) return fail(ctx, GSBC_E_ARG, "%u x %u tiles", tiles_x, tiles_y);
     const float f[3] = {view[0], view[1], view[2]};
     if (!(isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2]))) return fail(ctx, GSBC_E_ARG, "view position not finite");
+    if ((s = ensure_arena(ctx, tiles * sizeof(uint32_t)))) return s;   // the tile schedule
     HIP_TRY(ctx, launch_blend_tiles(blocks, band_args(desc), desc->n_prims, pos, perm, f, opacity, footprint, tile_start,
-                                    list, list_len, tiles_x, tiles_y, image, transmittance, ctx->stream),
+                                    list, list_len, tiles_x, tiles_y, image, transmittance,
+                                    static_cast<uint32_t *>(ctx->arena), ctx->stream),
             "blend_tiles launch");
     return GSBC_OK;
 }

@@ -469,6 +469,37 @@ __global__ __launch_bounds__(256) void k_decode_eval_view(const uint8_t *blocks,
     out[3 * j + 2] = c[2];
 }
 
+// Tiles by decreasing list length (bucketed by floor(log2 L), empty tiles
+// last): one workgroup counts, scans and scatters.  The blend takes tiles
+// in this order so that the longest lists start first instead of ending
+// the launch alone; the order within a bucket does not matter (each tile is
+// computed on its own).
+__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t *tile_start, uint64_t list_len, uint32_t tiles,
+                                                    uint32_t *order)
+{
+    __shared__ uint32_t cnt[33];
+    const uint32_t t = threadIdx.x;
+    if (t < 33) cnt[t] = 0u;
+    __syncthreads();
+    auto key = [&](uint32_t i) {
+        const uint64_t e = min((uint64_t)tile_start[i + 1], list_len), s0 = min((uint64_t)tile_start[i], e);
+        const uint64_t L = e - s0;
+        return L == 0 ? 32u : (uint32_t)__clzll(L) - 32u;   // 31 - floor(log2 L) for L below 2^32
+    };
+    for (uint32_t i = t; i < tiles; i += 1024) atomicAdd(&cnt[key(i)], 1u);
+    __syncthreads();
+    if (t == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < 33; k++) {
+            const uint32_t c = cnt[k];
+            cnt[k] = run;
+            run += c;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = t; i < tiles; i += 1024) order[atomicAdd(&cnt[key(i)], 1u)] = i;
+}
+
 // Colour stage of a tile rasteriser (Sec. II, eq. preblend with the
 // premultiplied coefficients of eq. premult), one workgroup per 16x16 tile,
 // one lane per pixel.  The tile's list is taken 256 entries at a time: lane t
@@ -485,10 +516,11 @@ __global__ __launch_bounds__(256) void k_blend_tiles(const uint8_t *blocks, Band
                                                      const float *pos, const uint32_t *perm, float fx, float fy,
                                                      float fz, const float *mu, const float *foot,
                                                      const uint32_t *tile_start, const uint32_t *list,
-                                                     uint64_t list_len, uint32_t tiles_x, float *image, float *trans)
+                                                     uint64_t list_len, const uint32_t *order, uint32_t tiles_x,
+                                                     float *image, float *trans)
 {
     __shared__ float s_par[256][9];   // mean x, mean y, A, B, C, mu, colour r, g, b
-    const uint32_t t = threadIdx.x, tile = blockIdx.x;
+    const uint32_t t = threadIdx.x, tile = order[blockIdx.x];
     const uint32_t tx = tile % tiles_x, ty = tile / tiles_x;
     const float x = (float)(16 * tx + (t & 15u)) + 0.5f, y = (float)(16 * ty + (t >> 4)) + 0.5f;
     const uint64_t b1 = min((uint64_t)tile_start[tile + 1], list_len);
@@ -546,12 +578,13 @@ __global__ __launch_bounds__(256) void k_blend_tiles(const uint8_t *blocks, Band
 hipError_t launch_blend_tiles(const uint8_t *blocks, const BandArgs &b, uint64_t n_prims, const float *pos,
                               const uint32_t *perm, const float view[3], const float *mu, const float *foot,
                               const uint32_t *tile_start, const uint32_t *list, uint64_t list_len, uint32_t tiles_x,
-                              uint32_t tiles_y, float *image, float *trans, hipStream_t st)
+                              uint32_t tiles_y, float *image, float *trans, uint32_t *order, hipStream_t st)
 {
     const uint64_t tiles = (uint64_t)tiles_x * tiles_y;
     if (tiles == 0) return hipSuccess;
+    GSBC_LAUNCH("tile_order", k_tile_order, dim3(1), dim3(1024), 0, st, tile_start, list_len, (uint32_t)tiles, order);
     GSBC_LAUNCH("blend_tiles", k_blend_tiles, dim3((uint32_t)tiles), dim3(256), 0, st, blocks, b, n_prims, pos, perm,
-                view[0], view[1], view[2], mu, foot, tile_start, list, list_len, tiles_x, image, trans);
+                view[0], view[1], view[2], mu, foot, tile_start, list, list_len, order, tiles_x, image, trans);
     return hipGetLastError();
 }
 
