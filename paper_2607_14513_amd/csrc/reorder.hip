@@ -308,10 +308,16 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
                                                    const uint32_t *gcount, uint64_t *status, uint64_t *zero_status,
                                                    uint64_t status_words, uint32_t *tile_ctr, uint32_t *fault)
 {
+    // 52 KB of LDS, so three workgroups share a CU: at 3,145,728 keys every
+    // tile is resident at once.  The ranking's lane masks and the sorted
+    // keys use the same LDS at different times; the values are not staged:
+    // the sorted position keeps the element's index in the tile and the
+    // value is read back from the input (a cache hit) when it is written.
     __shared__ uint64_t skey[kSortTile];
-    __shared__ uint32_t sval[kSortTile];
+    __shared__ uint16_t sidx[kSortTile];
     __shared__ uint32_t ctr[4][kMaxBins];    // per wave: running digit counts, then the wave's offset in the tile
-    __shared__ uint64_t peer[4][kMaxBins];   // per wave: lanes of one step holding each digit (cleared after use)
+    uint64_t(*peer)[kMaxBins] = reinterpret_cast<uint64_t(*)[kMaxBins]>(skey);   // per wave: lanes of one step
+                                                                                 // holding each digit
     __shared__ uint32_t lstart[kMaxBins];    // first tile-local sorted position of each digit
     __shared__ int32_t gadj[kMaxBins];       // output index of sorted position j of digit d: gadj[d] + j
     __shared__ uint32_t wsum[4][2];
@@ -335,13 +341,11 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
     const uint64_t wbase = t0 + (uint64_t)w * (kSortTile / 4);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
     uint64_t key[kSortKPT];
-    uint32_t val[kSortKPT], rk[kSortKPT];
+    uint32_t rk[kSortKPT];
 #pragma unroll
     for (int it = 0; it < kSortKPT; it++) {
         const uint64_t e = wbase + (uint64_t)it * 64 + lane;
-        const bool ok = e < n;
-        key[it] = ok ? kin[e] : 0ull;
-        val[it] = ok ? (vin ? vin[e] : (uint32_t)e) : 0u;
+        key[it] = e < n ? kin[e] : 0ull;
     }
     // rank of each key among the equal digits before it in its wave: per
     // step, each lane ORs its bit into its digit's LDS mask, reads the mask
@@ -471,7 +475,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
             const uint32_t d = (uint32_t)(key[it] >> shift) & mask;
             const uint32_t lp = lstart[d] + ctr[w][d] + rk[it];
             skey[lp] = key[it];
-            sval[lp] = val[it];
+            sidx[lp] = (uint16_t)(w * (kSortTile / 4) + it * 64 + lane);
         }
     }
     __syncthreads();
@@ -479,9 +483,10 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
     const uint32_t tn = (uint32_t)(n - t0 < (uint64_t)kSortTile ? n - t0 : (uint64_t)kSortTile);
     for (uint32_t j = tid; j < tn; j += 256) {
         const uint64_t k = skey[j];
+        const uint64_t e = t0 + sidx[j];
         const uint32_t o = (uint32_t)(gadj[(uint32_t)(k >> shift) & mask] + (int32_t)j);
         if (kout) kout[o] = k;
-        vout[o] = sval[j];
+        vout[o] = vin ? vin[e] : (uint32_t)e;
     }
 }
 
