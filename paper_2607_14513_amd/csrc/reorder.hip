@@ -137,12 +137,19 @@ __global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4
         take(v3, q + 3 * T);
     }
     for (; q < nq; q += T) take(sh4[q], q);
+    // positions: T is a multiple of 3, so every float this lane reads is on
+    // one axis; four loads in flight, as above
     const int axis = (int)(t % 3);
     float pmin = INFINITY, pmax = -INFINITY;
-    for (uint64_t f = t; f < n * 3; f += T) {
-        float v = pos[f];
-        pmin = fminf(pmin, v);
-        pmax = fmaxf(pmax, v);
+    uint64_t f = t;
+    for (; f + 3 * T < n * 3; f += 4 * T) {
+        const float v0 = pos[f], v1 = pos[f + T], v2 = pos[f + 2 * T], v3 = pos[f + 3 * T];
+        pmin = fminf(fminf(pmin, v0), fminf(v1, fminf(v2, v3)));
+        pmax = fmaxf(fmaxf(pmax, v0), fmaxf(v1, fmaxf(v2, v3)));
+    }
+    for (; f < n * 3; f += T) {
+        pmin = fminf(pmin, pos[f]);
+        pmax = fmaxf(pmax, pos[f]);
     }
     atomicMin(&s_acc[bandA], ord_of(minA));
     atomicMax(&s_acc[16 + bandA], ord_of(maxA));
@@ -213,29 +220,37 @@ __global__ __launch_bounds__(256) void k_keys(const float *pos, const float *dc,
     }
     __syncthreads();
     const uint32_t cmax = (1u << grid_bits) - 1u;
+    // every load of the tile first (the last element stands in past the end),
+    // so the workgroup has them all in flight at once
+    float px[kSortKPT][3], pc[kSortKPT][3], pmu[kSortKPT];
+#pragma unroll
+    for (int it = 0; it < kSortKPT; it++) {
+        const uint64_t i = (uint64_t)blockIdx.x * kSortTile + (uint64_t)it * 256 + threadIdx.x;
+        const uint64_t ic = i < n ? i : n - 1;
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            px[it][a] = pos[ic * 3 + a];
+            pc[it][a] = DEG ? sh[ic * 48 + a] : dc[ic * 3 + a];
+        }
+        pmu[it] = opacity && DEG ? opacity[ic] : 1.0f;
+    }
+#pragma unroll
     for (int it = 0; it < kSortKPT; it++) {
         const uint64_t i = (uint64_t)blockIdx.x * kSortTile + (uint64_t)it * 256 + threadIdx.x;
         if (i >= n) break;
         uint32_t cell[3];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            float t = pos[i * 3 + a] - r->lo[a];
+            float t = px[it][a] - r->lo[a];
             float u = t * r->cell_scale[a];
             uint32_t v = (uint32_t)floorf(u);
             cell[a] = v < cmax ? v : cmax;
         }
-        const float mu = opacity ? opacity[i] : 1.0f;
-        float d0, d1, d2;
-        if (DEG) {
-            d0 = sh[i * 48];
-            d1 = sh[i * 48 + 1];
-            d2 = sh[i * 48 + 2];
-            if (opacity) { d0 = mu * d0; d1 = mu * d1; d2 = mu * d2; }
-        } else {   // already times the opacity
-            d0 = dc[3 * i];
-            d1 = dc[3 * i + 1];
-            d2 = dc[3 * i + 2];
-        }
+        const float mu = pmu[it];
+        // band-0 colour: in the degree variant read here and times the
+        // opacity; otherwise the range pass stored it already multiplied
+        float d0 = pc[it][0], d1 = pc[it][1], d2 = pc[it][2];
+        if (DEG && opacity) { d0 = mu * d0; d1 = mu * d1; d2 = mu * d2; }
         const uint32_t q0 = quant8(d0, r->vmin[0], r->scale[0]);
         const uint32_t q1 = quant8(d1, r->vmin[0], r->scale[0]);
         const uint32_t q2 = quant8(d2, r->vmin[0], r->scale[0]);
@@ -398,6 +413,36 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
     __syncthreads();
     uint32_t lex = lc - (cnt[0] + cnt[1]), gex = gc - (g[0] + g[1]);
     for (int q = 0; q < w; q++) { lex += wsum[q][0]; gex += wsum[q][1]; }
+    const uint32_t lex0 = lex, gex0 = gex;
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        if (2 * tid + h < nbins) lstart[2 * tid + h] = lex;
+        lex += cnt[h];
+    }
+    __syncthreads();
+    // the tile sorted by digit in LDS (stable: waves in order, then rank),
+    // then each thread's share of it, with its values, into registers: all
+    // of this is local and is done before the wait on the earlier tiles
+#pragma unroll
+    for (int it = 0; it < kSortKPT; it++) {
+        if (wbase + (uint64_t)it * 64 + lane < n) {
+            const uint32_t d = (uint32_t)(key[it] >> shift) & mask;
+            const uint32_t lp = lstart[d] + ctr[w][d] + rk[it];
+            skey[lp] = key[it];
+            sidx[lp] = (uint16_t)(w * (kSortTile / 4) + it * 64 + lane);
+        }
+    }
+    __syncthreads();
+    const uint32_t tn = (uint32_t)(n - t0 < (uint64_t)kSortTile ? n - t0 : (uint64_t)kSortTile);
+    uint64_t okey[kSortKPT];
+    uint32_t oval[kSortKPT];
+#pragma unroll
+    for (int m = 0; m < kSortKPT; m++) {
+        const uint32_t j = tid + 256u * m;
+        okey[m] = j < tn ? skey[j] : 0ull;
+        const uint64_t e = t0 + (j < tn ? sidx[j] : 0u);
+        oval[m] = vin ? vin[e] : (uint32_t)e;
+    }
     // Keys of digits 2 tid and 2 tid + 1 in all earlier tiles.  Per digit
     // and step, the words of the next kLookBack earlier tiles are read at
     // once and taken from the nearest back: a partial word adds its count and
@@ -456,37 +501,28 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
             __builtin_amdgcn_s_sleep(1);
         }
     }
+    lex = lex0;
+    gex = gex0;
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const uint32_t d = 2 * tid + h;
         if (d < nbins) {
             lb_store(&status[(uint64_t)tile * kMaxBins + d], kInclusive | (before[h] + cnt[h]));
-            lstart[d] = lex;
             gadj[d] = (int32_t)(gex + before[h]) - (int32_t)lex;
         }
         lex += cnt[h];
         gex += g[h];
     }
     __syncthreads();
-    // the tile sorted by digit in LDS (stable: waves in order, then rank)
-#pragma unroll
-    for (int it = 0; it < kSortKPT; it++) {
-        if (wbase + (uint64_t)it * 64 + lane < n) {
-            const uint32_t d = (uint32_t)(key[it] >> shift) & mask;
-            const uint32_t lp = lstart[d] + ctr[w][d] + rk[it];
-            skey[lp] = key[it];
-            sidx[lp] = (uint16_t)(w * (kSortTile / 4) + it * 64 + lane);
-        }
-    }
-    __syncthreads();
     // each digit's keys leave as one contiguous run
-    const uint32_t tn = (uint32_t)(n - t0 < (uint64_t)kSortTile ? n - t0 : (uint64_t)kSortTile);
-    for (uint32_t j = tid; j < tn; j += 256) {
-        const uint64_t k = skey[j];
-        const uint64_t e = t0 + sidx[j];
-        const uint32_t o = (uint32_t)(gadj[(uint32_t)(k >> shift) & mask] + (int32_t)j);
-        if (kout) kout[o] = k;
-        vout[o] = vin ? vin[e] : (uint32_t)e;
+#pragma unroll
+    for (int m = 0; m < kSortKPT; m++) {
+        const uint32_t j = tid + 256u * m;
+        if (j < tn) {
+            const uint32_t o = (uint32_t)(gadj[(uint32_t)(okey[m] >> shift) & mask] + (int32_t)j);
+            if (kout) kout[o] = okey[m];
+            vout[o] = oval[m];
+        }
     }
 }
 
