@@ -84,7 +84,7 @@ __device__ __forceinline__ uint32_t quant8(float x, float vmin, float s)
 }
 
 // acc layout: [0..15] band min, [16..31] band max, [32..34] pos min, [35..37] pos max.
-// Also clears the sort's digit totals and tile counters (meta, meta_words).
+// Also clears the sort's digit totals (meta, meta_words).
 __global__ __launch_bounds__(256) void k_range_init(uint32_t *acc, uint32_t *meta, uint32_t meta_words)
 {
     const int t = threadIdx.x;
@@ -310,9 +310,13 @@ __device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v)
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One pass of the stable LSD sort over digit (shift, bits).  Tiles are
-// taken in order from tile_ctr, so every earlier tile belongs to a running
-// or finished workgroup, which writes its counts before it waits on anything.
+// One pass of the stable LSD sort over digit (shift, bits).  Tile t is
+// workgroup t: a tile waits only on lower tiles, and the hardware starts a
+// dispatch's workgroups in index order (each XCD its share), so the lowest
+// unfinished tile is always running and every wait ends.  (Taking tile ids
+// from a device counter instead costs one serialised atomic per workgroup,
+// about 8 us per pass at 768 tiles.)  Should a wait not end, the bounded
+// spin below turns it into a reported error, not a hang.
 // vin null: the values are the element indices; kout null: only the values
 // are written (the last pass, into perm).  zero_status (null on the first
 // pass): the look-back words the next pass will use, cleared here.  A tile
@@ -321,7 +325,7 @@ __device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v)
 __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
                                                    uint32_t *vout, uint64_t n, int shift, int bits,
                                                    const uint32_t *gcount, uint64_t *status, uint64_t *zero_status,
-                                                   uint64_t status_words, uint32_t *tile_ctr, uint32_t *fault)
+                                                   uint64_t status_words, uint32_t *fault)
 {
     // 52 KB of LDS, so three workgroups share a CU: at 3,145,728 keys every
     // tile is resident at once.  The ranking's lane masks and the sorted
@@ -336,9 +340,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
     __shared__ uint32_t lstart[kMaxBins];    // first tile-local sorted position of each digit
     __shared__ int32_t gadj[kMaxBins];       // output index of sorted position j of digit d: gadj[d] + j
     __shared__ uint32_t wsum[4][2];
-    __shared__ uint32_t s_tile;
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
-    if (tid == 0) s_tile = atomicAdd(tile_ctr, 1u);
     for (int e = tid; e < 4 * kMaxBins; e += 256) {
         (&ctr[0][0])[e] = 0u;
         (&peer[0][0])[e] = 0ull;
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
         for (uint64_t z = z0 + tid; z < z1; z += 256) zero_status[z] = 0ull;
     }
     __syncthreads();
-    const uint32_t tile = s_tile;
+    const uint32_t tile = blockIdx.x;
     const uint32_t nbins = 1u << bits, mask = nbins - 1u;
     const uint64_t t0 = (uint64_t)tile * kSortTile;
     // wave w holds tile elements [w T/4, (w + 1) T/4), 64 consecutive per step
@@ -534,7 +536,9 @@ __global__ __launch_bounds__(256) void k_gather_pack(const float *sh, const floa
                                                      const RangeRec *r, uint32_t *tex)
 {
     uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= npad) return;
+    // a sort tile that gave up its look-back may leave entries of perm
+    // unwritten: then none of perm is read (the host reports the fault)
+    if (s >= npad || r->sort_fault) return;
     uint32_t src = perm[s < n ? s : n - 1];
     const float4 *p = reinterpret_cast<const float4 *>(sh + (uint64_t)src * 48);
     float f[48];
@@ -712,8 +716,8 @@ struct Layout {
     uint64_t ntiles;
 };
 
-// meta: digit totals [kMaxPasses][kMaxBins], then one tile counter per pass
-constexpr uint32_t kMetaWords = kMaxPasses * kMaxBins + kMaxPasses;
+// meta: digit totals [kMaxPasses][kMaxBins]
+constexpr uint32_t kMetaWords = kMaxPasses * kMaxBins;
 
 Layout layout(uint64_t n)
 {
@@ -792,7 +796,6 @@ void enqueue_keys_and_sort(const float *pos, const float *sh, const float *opaci
     uint64_t *status[2] = {reinterpret_cast<uint64_t *>(s + L.status),
                            reinterpret_cast<uint64_t *>(s + L.status) + L.ntiles * kMaxBins};
     uint32_t *gcount = reinterpret_cast<uint32_t *>(s + L.meta);
-    uint32_t *tile_ctr = gcount + kMaxPasses * kMaxBins;
     uint32_t *fault = const_cast<uint32_t *>(&range_dev->sort_fault);
     const uint64_t words = L.ntiles * kMaxBins;
     const dim3 grid((uint32_t)L.ntiles);
@@ -807,7 +810,7 @@ void enqueue_keys_and_sort(const float *pos, const float *sh, const float *opaci
         const bool last = p == P.passes - 1;
         GSBC_LAUNCH("sort_pass", k_sort_pass, grid, dim3(256), 0, st, kin, vin, last ? nullptr : kout,
                     last ? perm : vout, n, P.shift[p], P.bits[p], gcount + p * kMaxBins, status[p & 1],
-                    p >= 1 ? status[(p + 1) & 1] : nullptr, words, tile_ctr + p, fault);
+                    p >= 1 ? status[(p + 1) & 1] : nullptr, words, fault);
         const uint64_t *kt = kin;
         kin = kout;
         kout = const_cast<uint64_t *>(kt);
