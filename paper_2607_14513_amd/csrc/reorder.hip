@@ -29,6 +29,7 @@ constexpr int kMaxDigitBits = 9;
 constexpr int kMaxBins = 1 << kMaxDigitBits;
 constexpr int kMaxPasses = 7;                  // 56-bit keys (grid 10 bits, degree class) in 9-bit digits
 constexpr int kRangeBlock = 384;               // multiple of 12 and 3
+static_assert(kRangeBlock % 12 == 0, "a block-size run of float4 chunks must hold whole primitives");
 constexpr uint32_t kSpinLimit = 1u << 22;      // look-back polls before a tile gives up (about 0.1 s)
 
 // Digits of each pass, low to high: ceil(bits / 9) passes of near-equal width.
@@ -92,7 +93,16 @@ __global__ __launch_bounds__(256) void k_range_init(uint32_t *acc, uint32_t *met
     for (uint32_t e = t; e < meta_words; e += 256) meta[e] = 0u;
 }
 
-// dc (when not null): each primitive's band-0 colour (times its opacity),
+// Workgroup barrier that orders LDS accesses only: global stores issued
+// before it stay in flight (__syncthreads would wait for them).
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// dc: each primitive's band-0 colour (times its opacity),
 // three floats, for the key pass.
 __global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4, const float *opacity,
                                                                const float *pos, uint64_t n, uint32_t *acc,
@@ -101,55 +111,99 @@ __global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4
     __shared__ uint32_t s_acc[38];
     if (threadIdx.x < 38) s_acc[threadIdx.x] = (threadIdx.x < 16 || (threadIdx.x >= 32 && threadIdx.x < 35)) ? 0xFFFFFFFFu : 0u;
     __syncthreads();
-    const uint64_t T = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // float4 chunk j of a primitive holds floats 4j..4j+3 -> bands (4j+c)/3
-    const int j = (int)(t % 12);
-    const int bandA = (4 * j) / 3, bandB = (4 * j + 3) / 3;
-    float minA = INFINITY, maxA = -INFINITY, minB = INFINITY, maxB = -INFINITY;
+    // each workgroup reads one contiguous span of float4 chunks (a multiple
+    // of the block size, so every chunk a lane reads sits at the same place
+    // in its primitive), four loads in flight per lane
+    constexpr uint64_t B = kRangeBlock;
+    constexpr uint32_t kPrims = (uint32_t)(B / 12);   // primitives per block-size run of chunks
+    // band-0 colours of one step's 4 kPrims primitives, written out by the
+    // whole workgroup at once: a store per lane per primitive would make the
+    // next loads wait on it
+    __shared__ float stage[4 * kPrims * 3];
+    const uint32_t tid = threadIdx.x;
+    // float4 chunk j of a primitive holds floats 4j..4j+3 (bands (4j+c)/3):
+    // extremes kept per position c, folded into bands at the end
+    const int j = (int)(tid % 12);
+    float mn[4], mx[4];
+#pragma unroll
+    for (int c = 0; c < 4; c++) { mn[c] = INFINITY; mx[c] = -INFINITY; }
     const uint64_t nq = n * 12;
-    auto take = [&](float4 v, uint64_t q) {
-        float f[4] = {v.x, v.y, v.z, v.w};
+    auto take = [&](float4 v, uint64_t q) -> float4 {
         if (opacity) {   // H~ = mu H (FP32 products)
             const float mu = opacity[q / 12];
-#pragma unroll
-            for (int c = 0; c < 4; c++) f[c] = mu * f[c];
+            v.x *= mu; v.y *= mu; v.z *= mu; v.w *= mu;
         }
-#pragma unroll
-        for (int c = 0; c < 4; c++) {
-            if ((4 * j + c) / 3 == bandA) { minA = fminf(minA, f[c]); maxA = fmaxf(maxA, f[c]); }
-            else { minB = fminf(minB, f[c]); maxB = fmaxf(maxB, f[c]); }
-        }
-        if (j == 0 && dc) {   // floats 0..2 of the primitive: its band-0 colour
-            float *o = dc + 3 * (q / 12);
-            o[0] = f[0];
-            o[1] = f[1];
-            o[2] = f[2];
-        }
+        mn[0] = fminf(mn[0], v.x); mx[0] = fmaxf(mx[0], v.x);
+        mn[1] = fminf(mn[1], v.y); mx[1] = fmaxf(mx[1], v.y);
+        mn[2] = fminf(mn[2], v.z); mx[2] = fmaxf(mx[2], v.z);
+        mn[3] = fminf(mn[3], v.w); mx[3] = fmaxf(mx[3], v.w);
+        return v;
     };
-    // four loads in flight per lane, then the remainder one at a time
-    uint64_t q = t;
-    for (; q + 3 * T < nq; q += 4 * T) {
-        const float4 v0 = sh4[q], v1 = sh4[q + T], v2 = sh4[q + 2 * T], v3 = sh4[q + 3 * T];
-        take(v0, q);
-        take(v1, q + T);
-        take(v2, q + 2 * T);
-        take(v3, q + 3 * T);
+    {
+        const uint64_t per = ((nq + gridDim.x - 1) / gridDim.x + B - 1) / B * B;
+        const uint64_t q0 = (uint64_t)blockIdx.x * per, q1 = min(nq, q0 + per);
+        const uint64_t steps = q1 > q0 ? (q1 - q0) / (4 * B) : 0;   // whole steps: every lane takes part
+        uint64_t q = q0 + tid;
+        // software-pipelined: the next step's loads are in flight while this
+        // step's colours go out; they are issued after the colours' store, so
+        // waiting on them waits on nothing newer than the store
+        float4 v[4];
+        if (steps)
+#pragma unroll
+            for (int u = 0; u < 4; u++) v[u] = sh4[q + u * B];
+        for (uint64_t k = 0; k < steps; k++, q += 4 * B) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                v[u] = take(v[u], q + u * B);
+                if (j == 0) {
+                    float *o = stage + 3 * (u * kPrims + tid / 12);
+                    o[0] = v[u].x;
+                    o[1] = v[u].y;
+                    o[2] = v[u].z;
+                }
+            }
+            lds_barrier();
+            dc[3 * ((q - tid) / 12) + tid] = stage[tid];   // 4 kPrims primitives x 3 = B floats
+            if (k + 1 < steps)
+#pragma unroll
+                for (int u = 0; u < 4; u++) v[u] = sh4[q + (4 + u) * B];
+            lds_barrier();
+        }
+        for (; q < q1; q += B) {   // the rest of the span, less than one step
+            const float4 v = take(sh4[q], q);
+            if (j == 0) {
+                float *o = dc + 3 * (q / 12);
+                o[0] = v.x;
+                o[1] = v.y;
+                o[2] = v.z;
+            }
+        }
     }
-    for (; q < nq; q += T) take(sh4[q], q);
-    // positions: T is a multiple of 3, so every float this lane reads is on
-    // one axis; four loads in flight, as above
-    const int axis = (int)(t % 3);
+    const int bandA = (4 * j) / 3, bandB = (4 * j + 3) / 3;
+    float minA = INFINITY, maxA = -INFINITY, minB = INFINITY, maxB = -INFINITY;
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+        if ((4 * j + c) / 3 == bandA) { minA = fminf(minA, mn[c]); maxA = fmaxf(maxA, mx[c]); }
+        else { minB = fminf(minB, mn[c]); maxB = fmaxf(maxB, mx[c]); }
+    }
+    // positions, the same way (the block size is a multiple of 3, so every
+    // float a lane reads is on one axis)
+    const int axis = (int)(tid % 3);
     float pmin = INFINITY, pmax = -INFINITY;
-    uint64_t f = t;
-    for (; f + 3 * T < n * 3; f += 4 * T) {
-        const float v0 = pos[f], v1 = pos[f + T], v2 = pos[f + 2 * T], v3 = pos[f + 3 * T];
-        pmin = fminf(fminf(pmin, v0), fminf(v1, fminf(v2, v3)));
-        pmax = fmaxf(fmaxf(pmax, v0), fmaxf(v1, fmaxf(v2, v3)));
-    }
-    for (; f < n * 3; f += T) {
-        pmin = fminf(pmin, pos[f]);
-        pmax = fmaxf(pmax, pos[f]);
+    {
+        const uint64_t np = n * 3;
+        const uint64_t per = ((np + gridDim.x - 1) / gridDim.x + B - 1) / B * B;
+        const uint64_t f0 = (uint64_t)blockIdx.x * per, f1 = min(np, f0 + per);
+        uint64_t f = f0 + tid;
+        for (; f + 3 * B < f1; f += 4 * B) {
+            const float v0 = pos[f], v1 = pos[f + B], v2 = pos[f + 2 * B], v3 = pos[f + 3 * B];
+            pmin = fminf(fminf(pmin, v0), fminf(v1, fminf(v2, v3)));
+            pmax = fmaxf(fmaxf(pmax, v0), fmaxf(v1, fmaxf(v2, v3)));
+        }
+        for (; f < f1; f += B) {
+            pmin = fminf(pmin, pos[f]);
+            pmax = fmaxf(pmax, pos[f]);
+        }
     }
     atomicMin(&s_acc[bandA], ord_of(minA));
     atomicMax(&s_acc[16 + bandA], ord_of(maxA));
