@@ -465,7 +465,6 @@ gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, const
     HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, range, sizeof(RangeRec), hipMemcpyDeviceToHost, ctx->stream), "range read-back");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "reorder");
     const RangeRec *r = static_cast<const RangeRec *>(ctx->pinned);
-    if (p.order != 1 && r->sort_fault) return fail(ctx, GSBC_E_DEVICE, "reorder: a sort tile's look-back timed out");
     memset(desc, 0, sizeof *desc);
     for (int k = 0; k < 16; k++) { desc->vmin[k] = r->vmin[k]; desc->vmax[k] = r->vmax[k]; }
     desc->n_prims = n;
@@ -518,7 +517,6 @@ gsbc_status gsbc_reorder_degrees(gsbc_ctx *ctx, const float *pos, const float *s
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "degree sort");
     RangeRec r;
     memcpy(&r, stage, sizeof r);
-    if (r.sort_fault) return fail(ctx, GSBC_E_DEVICE, "reorder_degrees: a sort tile's look-back timed out");
     uint32_t c32[4];
     memcpy(c32, stage + 512, sizeof c32);
     DegreeLayout lay;

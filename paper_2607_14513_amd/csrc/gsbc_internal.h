@@ -68,7 +68,6 @@ struct RangeRec {
     float scale[16];            // 255 / (vmax - vmin), 0 for a constant band
     float lo[3], hi[3];         // position bounding box
     float cell_scale[3];        // 2^g / (hi - lo), 0 for a flat axis
-    uint32_t sort_fault;        // nonzero: a sort tile's look-back gave up (set on the device)
 };
 
 // ---- reorder (reorder.hip)

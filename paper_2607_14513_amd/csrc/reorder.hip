@@ -6,13 +6,14 @@
 //            integer atomics on an order-preserving encoding of the floats;
 //   keys     (Morton cell of the position) << 24 | RGB bit interleave of the
 //            quantised band-0 colour (Sec. III-C, Fig. Bit4Scan);
-//   sort     stable LSD radix sort, one launch per digit of 8 or 9 bits:
-//            each workgroup takes the next 4,096-key tile, ranks it stably
-//            (per-wave LDS lane masks of equal digits, waves in order), finds the tile's place among
-//            all earlier tiles by decoupled look-back on per-tile digit
-//            counts, sorts the tile in LDS and writes each digit's keys as
-//            one contiguous run; the digit totals of every pass come from
-//            one histogram taken while the keys are made;
+//   sort     stable LSD radix sort over digits of 8 or 9 bits, reduce then
+//            scan: per pass, each 4,096-key tile's digit counts, their
+//            exclusive scan over tiles per digit, then the scatter, where
+//            each workgroup ranks its tile stably (per-wave LDS lane masks
+//            of equal digits, waves in order), sorts it in LDS and writes
+//            each digit's keys as one contiguous run; the digit totals of
+//            every pass and the first pass's tile counts come from the
+//            histogram taken while the keys are made;
 //   pack     gather each slot's 48 coefficients, quantise, and write band k
 //            of slot s to texel zigzag(s % 16) of block s / 16 (Fig. SetupD,
 //            Fig. ZigZagScan).
@@ -30,7 +31,6 @@ constexpr int kMaxBins = 1 << kMaxDigitBits;
 constexpr int kMaxPasses = 7;                  // 56-bit keys (grid 10 bits, degree class) in 9-bit digits
 constexpr int kRangeBlock = 384;               // multiple of 12 and 3
 static_assert(kRangeBlock % 12 == 0, "a block-size run of float4 chunks must hold whole primitives");
-constexpr uint32_t kSpinLimit = 1u << 22;      // look-back polls before a tile gives up (about 0.1 s)
 
 // Digits of each pass, low to high: ceil(bits / 9) passes of near-equal width.
 struct SortPlan {
@@ -241,7 +241,6 @@ __global__ void k_range_final(const uint32_t *acc, const uint32_t *cov, uint32_t
         float range = hi - lo;
         r->scale[k] = range > 0.0f ? 255.0f / range : 0.0f;
     }
-    if (k == 0) r->sort_fault = 0u;
     if (k < 3) {
         float lo = canon_zero(float_of(acc[32 + k])), hi = canon_zero(float_of(acc[35 + k]));
         r->lo[k] = lo;
@@ -254,24 +253,20 @@ __global__ void k_range_final(const uint32_t *acc, const uint32_t *cov, uint32_t
 // Keys, 4,096 per workgroup: (Morton cell << 24) | colour interleave, and
 // the digit counts of every sort pass.  DEG: also the degree class (the
 // largest SH degree with a coefficient above tau in magnitude, 0 if none)
-// above the cell and colour fields, and the class counts.  The workgroups
-// also clear the sort's look-back words (status, status_words).
+// above the cell and colour fields, and the class counts.  A workgroup's
+// keys are the first sort pass's tile: its counts of that pass's digit go
+// to tcount[digit][tile].
 template <bool DEG>
 __global__ __launch_bounds__(256) void k_keys(const float *pos, const float *dc, const float *sh,
                                               const float *opacity, uint64_t n, uint32_t grid_bits,
                                               const RangeRec *r, SortPlan plan, uint64_t *keys, uint32_t *gcount,
-                                              uint64_t *status, uint64_t status_words, float tau,
+                                              uint32_t *tcount, uint32_t ntiles, float tau,
                                               uint32_t *class_count)
 {
     __shared__ uint32_t hist[kMaxPasses][kMaxBins];
     __shared__ uint32_t cls[4];
     for (int e = threadIdx.x; e < kMaxPasses * kMaxBins; e += 256) (&hist[0][0])[e] = 0u;
     if (DEG && threadIdx.x < 4) cls[threadIdx.x] = 0u;
-    {
-        const uint64_t per = (status_words + gridDim.x - 1) / gridDim.x;
-        const uint64_t z0 = (uint64_t)blockIdx.x * per, z1 = min(status_words, z0 + per);
-        for (uint64_t z = z0 + threadIdx.x; z < z1; z += 256) status[z] = 0ull;
-    }
     __syncthreads();
     const uint32_t cmax = (1u << grid_bits) - 1u;
     // every load of the tile first (the last element stands in past the end),
@@ -340,52 +335,101 @@ __global__ __launch_bounds__(256) void k_keys(const float *pos, const float *dc,
         if (p < plan.passes)
             for (int d = threadIdx.x; d < (1 << plan.bits[p]); d += 256)
                 if (hist[p][d]) atomicAdd(&gcount[p * kMaxBins + d], hist[p][d]);
+    for (int d = threadIdx.x; d < (1 << plan.bits[0]); d += 256) tcount[(uint64_t)d * ntiles + blockIdx.x] = hist[0][d];
     if (DEG && threadIdx.x < 4 && cls[threadIdx.x]) atomicAdd(&class_count[threadIdx.x], cls[threadIdx.x]);
 }
 
-// Look-back words of (tile t, digit d): 0 = not yet written; else bits
-// 62..63 = 1 (partial: the count over tiles t - span .. t) or 2 (inclusive:
-// the count over tiles 0 .. t), bits 32..61 = span, low 32 bits = count.
-// A tile writes its own count first (span 0), then wider partial sums as
-// its look-back gathers them, then its inclusive count; a later tile that
-// reads a partial word jumps past the span, so the sums spread to later
-// tiles in a logarithmic number of steps even when every tile starts at
-// once.  Each word carries all it says, so its device-scope loads and stores
-// need no ordering (acquire loads would invalidate the cache on every poll).
-constexpr uint64_t kPartial = 1ull << 62, kInclusive = 2ull << 62;
-constexpr int kLookBack = 1;   // earlier tiles' words read per look-back step and digit (wider windows measured slower)
+// The sort is reduce-then-scan, three steps per pass: each tile's digit
+// counts (for the first pass, from the key kernel), an exclusive scan of
+// the counts over tiles for every digit, offset by the digit's start in the
+// output, then the scatter.  No tile ever waits on another, so any number
+// of tiles may run at once or in any order.  Counts and offsets are stored
+// [digit][tile].
 
-__device__ __forceinline__ uint64_t lb_load(const uint64_t *p)
+// Digit counts of one tile of 4,096 keys (passes after the first).
+__global__ __launch_bounds__(256) void k_tile_hist(const uint64_t *kin, uint64_t n, int shift, int bits,
+                                                   uint32_t ntiles, uint32_t *tcount)
 {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void lb_store(uint64_t *p, uint64_t v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __shared__ uint32_t h[kMaxBins];
+    const uint32_t tid = threadIdx.x, nbins = 1u << bits, mask = nbins - 1u;
+    h[tid] = 0u;
+    h[tid + 256] = 0u;
+    const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
+    uint64_t key[kSortKPT];
+#pragma unroll
+    for (int it = 0; it < kSortKPT; it++) {
+        const uint64_t e = t0 + (uint64_t)it * 256 + tid;
+        key[it] = e < n ? kin[e] : 0ull;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kSortKPT; it++)
+        if (t0 + (uint64_t)it * 256 + tid < n) atomicAdd(&h[(uint32_t)(key[it] >> shift) & mask], 1u);
+    __syncthreads();
+    for (uint32_t d = tid; d < nbins; d += 256) tcount[(uint64_t)d * ntiles + blockIdx.x] = h[d];
 }
 
-// One pass of the stable LSD sort over digit (shift, bits).  Tile t is
-// workgroup t: a tile waits only on lower tiles, and the hardware starts a
-// dispatch's workgroups in index order (each XCD its share), so the lowest
-// unfinished tile is always running and every wait ends.  (Taking tile ids
-// from a device counter instead costs one serialised atomic per workgroup,
-// about 8 us per pass at 768 tiles.)  Should a wait not end, the bounded
-// spin below turns it into a reported error, not a hang.
-// vin null: the values are the element indices; kout null: only the values
-// are written (the last pass, into perm).  zero_status (null on the first
-// pass): the look-back words the next pass will use, cleared here.  A tile
-// whose look-back finds no count within kSpinLimit polls sets *fault and
-// goes on (wrong order, no hang); the host reports it.
+// Workgroup d: toff[d][t] = (keys of digits below d) + (keys of digit d in
+// tiles before t), from the pass's digit totals and the tile counts.  Each
+// thread scans kScanPer consecutive tiles per round.
+constexpr int kScanPer = 4;
+__global__ __launch_bounds__(256) void k_tile_scan(const uint32_t *tcount, const uint32_t *gcount, uint32_t ntiles,
+                                                   uint32_t *toff)
+{
+    __shared__ uint32_t wsum[4];
+    __shared__ uint32_t s_base;
+    const uint32_t d = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    // keys of the lower digits: a block sum over gcount[0 .. d)
+    uint32_t b = 0;
+    for (uint32_t e = tid; e < d; e += 256) b += gcount[e];
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) b += __shfl_xor(b, o);
+    if (lane == 0) wsum[w] = b;
+    __syncthreads();
+    if (tid == 0) s_base = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    __syncthreads();
+    uint32_t carry = s_base;
+    const uint32_t *c = tcount + (uint64_t)d * ntiles;
+    uint32_t *out = toff + (uint64_t)d * ntiles;
+    for (uint32_t r0 = 0; r0 < ntiles; r0 += 256 * kScanPer) {
+        const uint32_t t = r0 + tid * kScanPer;
+        uint32_t v[kScanPer], sum = 0;
+#pragma unroll
+        for (int i = 0; i < kScanPer; i++) {
+            v[i] = t + i < ntiles ? c[t + i] : 0u;
+            sum += v[i];
+        }
+        uint32_t inc = sum;   // inclusive scan of the per-thread sums over the wave
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t x = __shfl_up(inc, o);
+            if (lane >= (uint32_t)o) inc += x;
+        }
+        __syncthreads();   // wsum of the previous round has been read
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t ex = carry + inc - sum;
+        for (uint32_t q = 0; q < w; q++) ex += wsum[q];
+#pragma unroll
+        for (int i = 0; i < kScanPer; i++) {
+            if (t + i < ntiles) out[t + i] = ex;
+            ex += v[i];
+        }
+        carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    }
+}
+
+// One pass of the stable LSD sort over digit (shift, bits): the scatter of
+// tile blockIdx.x, given toff.  vin null: the values are the element
+// indices; kout null: only the values are written (the last pass, into perm).
 __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
                                                    uint32_t *vout, uint64_t n, int shift, int bits,
-                                                   const uint32_t *gcount, uint64_t *status, uint64_t *zero_status,
-                                                   uint64_t status_words, uint32_t *fault)
+                                                   const uint32_t *toff, uint32_t ntiles)
 {
-    // 52 KB of LDS, so three workgroups share a CU: at 3,145,728 keys every
-    // tile is resident at once.  The ranking's lane masks and the sorted
-    // keys use the same LDS at different times; the values are not staged:
-    // the sorted position keeps the element's index in the tile and the
-    // value is read back from the input (a cache hit) when it is written.
+    // 52 KB of LDS, so three workgroups share a CU.  The ranking's lane
+    // masks and the sorted keys use the same LDS at different times; the
+    // values are not staged: the sorted position keeps the element's index
+    // in the tile and the value is read back from the input (a cache hit).
     __shared__ uint64_t skey[kSortTile];
     __shared__ uint16_t sidx[kSortTile];
     __shared__ uint32_t ctr[4][kMaxBins];    // per wave: running digit counts, then the wave's offset in the tile
@@ -393,21 +437,23 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
                                                                                  // holding each digit
     __shared__ uint32_t lstart[kMaxBins];    // first tile-local sorted position of each digit
     __shared__ int32_t gadj[kMaxBins];       // output index of sorted position j of digit d: gadj[d] + j
-    __shared__ uint32_t wsum[4][2];
+    __shared__ uint32_t wsum[4];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
     for (int e = tid; e < 4 * kMaxBins; e += 256) {
         (&ctr[0][0])[e] = 0u;
         (&peer[0][0])[e] = 0ull;
     }
-    if (zero_status) {
-        const uint64_t per = (status_words + gridDim.x - 1) / gridDim.x;
-        const uint64_t z0 = (uint64_t)blockIdx.x * per, z1 = min(status_words, z0 + per);
-        for (uint64_t z = z0 + tid; z < z1; z += 256) zero_status[z] = 0ull;
-    }
     __syncthreads();
     const uint32_t tile = blockIdx.x;
     const uint32_t nbins = 1u << bits, mask = nbins - 1u;
     const uint64_t t0 = (uint64_t)tile * kSortTile;
+    // this tile's output offsets, in flight during the ranking
+    uint32_t off[2];
+#pragma unroll
+    for (int h = 0; h < 2; h++) {
+        const uint32_t d = 2 * tid + h;
+        off[h] = d < nbins ? toff[(uint64_t)d * ntiles + tile] : 0u;
+    }
     // wave w holds tile elements [w T/4, (w + 1) T/4), 64 consecutive per step
     const uint64_t wbase = t0 + (uint64_t)w * (kSortTile / 4);
     const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
@@ -441,8 +487,8 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
     }
     __syncthreads();
     // thread tid: digits 2 tid and 2 tid + 1.  Wave offsets within the tile,
-    // the tile's counts (published at once), tile-local and global prefixes.
-    uint32_t cnt[2], g[2];
+    // the tile's counts, their prefix over the digits (the local start)
+    uint32_t cnt[2];
 #pragma unroll
     for (int h = 0; h < 2; h++) {
         const uint32_t d = 2 * tid + h;
@@ -454,31 +500,30 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
                 ctr[q][d] = c;
                 c += x;
             }
-            if (tile > 0) lb_store(&status[(uint64_t)tile * kMaxBins + d], kPartial | c);
         }
         cnt[h] = c;
-        g[h] = d < nbins ? gcount[d] : 0u;
     }
-    uint32_t lc = cnt[0] + cnt[1], gc = g[0] + g[1];
+    uint32_t lc = cnt[0] + cnt[1];
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t a = __shfl_up(lc, o), b = __shfl_up(gc, o);
-        if (lane >= o) { lc += a; gc += b; }
+        const uint32_t a = __shfl_up(lc, o);
+        if (lane >= o) lc += a;
     }
-    if (lane == 63) { wsum[w][0] = lc; wsum[w][1] = gc; }
+    if (lane == 63) wsum[w] = lc;
     __syncthreads();
-    uint32_t lex = lc - (cnt[0] + cnt[1]), gex = gc - (g[0] + g[1]);
-    for (int q = 0; q < w; q++) { lex += wsum[q][0]; gex += wsum[q][1]; }
-    const uint32_t lex0 = lex, gex0 = gex;
+    uint32_t lex = lc - (cnt[0] + cnt[1]);
+    for (int q = 0; q < w; q++) lex += wsum[q];
 #pragma unroll
     for (int h = 0; h < 2; h++) {
-        if (2 * tid + h < nbins) lstart[2 * tid + h] = lex;
+        const uint32_t d = 2 * tid + h;
+        if (d < nbins) {
+            lstart[d] = lex;
+            gadj[d] = (int32_t)off[h] - (int32_t)lex;
+        }
         lex += cnt[h];
     }
     __syncthreads();
-    // the tile sorted by digit in LDS (stable: waves in order, then rank),
-    // then each thread's share of it, with its values, into registers: all
-    // of this is local and is done before the wait on the earlier tiles
+    // the tile sorted by digit in LDS (stable: waves in order, then rank)
 #pragma unroll
     for (int it = 0; it < kSortKPT; it++) {
         if (wbase + (uint64_t)it * 64 + lane < n) {
@@ -489,96 +534,14 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
         }
     }
     __syncthreads();
-    const uint32_t tn = (uint32_t)(n - t0 < (uint64_t)kSortTile ? n - t0 : (uint64_t)kSortTile);
-    uint64_t okey[kSortKPT];
-    uint32_t oval[kSortKPT];
-#pragma unroll
-    for (int m = 0; m < kSortKPT; m++) {
-        const uint32_t j = tid + 256u * m;
-        okey[m] = j < tn ? skey[j] : 0ull;
-        const uint64_t e = t0 + (j < tn ? sidx[j] : 0u);
-        oval[m] = vin ? vin[e] : (uint32_t)e;
-    }
-    // Keys of digits 2 tid and 2 tid + 1 in all earlier tiles.  Per digit
-    // and step, the words of the next kLookBack earlier tiles are read at
-    // once and taken from the nearest back: a partial word adds its count and
-    // skips its span, an inclusive word ends the walk, an unwritten one is
-    // read again at the next step.  After each step the sum so far is
-    // published as this tile's partial word.
-    uint32_t before[2] = {0u, 0u};
-    int64_t q[2];
-    bool live[2];
-#pragma unroll
-    for (int h = 0; h < 2; h++) {
-        q[h] = (int64_t)tile - 1;
-        live[h] = 2 * tid + h < nbins && tile > 0;
-    }
-    uint32_t spins = 0;
-    while (live[0] || live[1]) {
-        uint64_t sw[2][kLookBack];
-#pragma unroll
-        for (int h = 0; h < 2; h++)
-#pragma unroll
-            for (int i = 0; i < kLookBack; i++)
-                sw[h][i] = live[h] && q[h] - i >= 0 ? lb_load(&status[(uint64_t)(q[h] - i) * kMaxBins + 2 * tid + h])
-                                                    : kInclusive;
-        bool stalled = false;
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            if (!live[h]) continue;
-            int64_t nq = q[h];   // next tile whose word is needed
-            bool done = false, stop = false;
-#pragma unroll
-            for (int i = 0; i < kLookBack; i++) {
-                if (done || stop || q[h] - i != nq) continue;
-                const uint64_t x = sw[h][i];
-                if (x == 0) { stop = true; continue; }
-                before[h] += (uint32_t)x;
-                if (x & kInclusive) { done = true; continue; }
-                nq = q[h] - i - 1 - (int64_t)((x >> 32) & 0x3FFFFFFFu);
-            }
-            const uint32_t d = 2 * tid + h;
-            if (done) {
-                live[h] = false;
-            } else {
-                if (nq < q[h])
-                    lb_store(&status[(uint64_t)tile * kMaxBins + d],
-                             kPartial | (uint64_t)(tile - 1 - nq) << 32 | (before[h] + cnt[h]));
-                else
-                    stalled = true;
-                q[h] = nq;
-            }
-        }
-        if (stalled) {
-            if (++spins > kSpinLimit) {
-                atomicOr(fault, 1u);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-        }
-    }
-    lex = lex0;
-    gex = gex0;
-#pragma unroll
-    for (int h = 0; h < 2; h++) {
-        const uint32_t d = 2 * tid + h;
-        if (d < nbins) {
-            lb_store(&status[(uint64_t)tile * kMaxBins + d], kInclusive | (before[h] + cnt[h]));
-            gadj[d] = (int32_t)(gex + before[h]) - (int32_t)lex;
-        }
-        lex += cnt[h];
-        gex += g[h];
-    }
-    __syncthreads();
     // each digit's keys leave as one contiguous run
-#pragma unroll
-    for (int m = 0; m < kSortKPT; m++) {
-        const uint32_t j = tid + 256u * m;
-        if (j < tn) {
-            const uint32_t o = (uint32_t)(gadj[(uint32_t)(okey[m] >> shift) & mask] + (int32_t)j);
-            if (kout) kout[o] = okey[m];
-            vout[o] = oval[m];
-        }
+    const uint32_t tn = (uint32_t)(n - t0 < (uint64_t)kSortTile ? n - t0 : (uint64_t)kSortTile);
+    for (uint32_t j = tid; j < tn; j += 256) {
+        const uint64_t k = skey[j];
+        const uint64_t e = t0 + sidx[j];
+        const uint32_t o = (uint32_t)(gadj[(uint32_t)(k >> shift) & mask] + (int32_t)j);
+        if (kout) kout[o] = k;
+        vout[o] = vin ? vin[e] : (uint32_t)e;
     }
 }
 
@@ -590,9 +553,7 @@ __global__ __launch_bounds__(256) void k_gather_pack(const float *sh, const floa
                                                      const RangeRec *r, uint32_t *tex)
 {
     uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // a sort tile that gave up its look-back may leave entries of perm
-    // unwritten: then none of perm is read (the host reports the fault)
-    if (s >= npad || r->sort_fault) return;
+    if (s >= npad) return;
     uint32_t src = perm[s < n ? s : n - 1];
     const float4 *p = reinterpret_cast<const float4 *>(sh + (uint64_t)src * 48);
     float f[48];
@@ -766,7 +727,7 @@ __global__ __launch_bounds__(256) void k_pack_degrees(const float *sh, const flo
 }
 
 struct Layout {
-    size_t acc, keys_a, keys_b, vals_a, vals_b, dc, status, meta, cov_state, cov_part, bytes;
+    size_t acc, keys_a, keys_b, vals_a, vals_b, dc, tcount, toff, meta, cov_state, cov_part, bytes;
     uint64_t ntiles;
 };
 
@@ -785,7 +746,8 @@ Layout layout(uint64_t n)
     L.vals_a = o; o += al(n * 4);
     L.vals_b = o; o += al(n * 4);
     L.dc = o; o += al(n * 12);
-    L.status = o; o += al(2 * L.ntiles * kMaxBins * 8);   // two look-back arrays, used by alternate passes
+    L.tcount = o; o += al(L.ntiles * kMaxBins * 4);   // [digit][tile] counts of the current pass
+    L.toff = o; o += al(L.ntiles * kMaxBins * 4);     // [digit][tile] output offsets
     L.meta = o; o += al(kMetaWords * 4);
     L.cov_state = o; o += al(32 * 4);
     L.cov_part = o; o += al((size_t)kCovWG * 4096 * 4);
@@ -836,9 +798,10 @@ void enqueue_range(const float *pos, const float *sh, const float *opacity, uint
     GSBC_LAUNCH("range_final", k_range_final, dim3(1), dim3(64), 0, st, acc, cov, grid_bits, range_dev);
 }
 
-// The keys in keys_a: their digit totals and the cleared look-back words
-// (the key pass), then one stable pass per digit; the last pass writes the
-// values (the original indices) to perm.
+// The keys in keys_a with their digit totals and the first pass's tile
+// counts (the key pass), then per pass: the tile counts (after the first),
+// the offsets, the scatter; the last pass writes the values (the original
+// indices) to perm.
 template <bool DEG>
 void enqueue_keys_and_sort(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
                            float tau, const Layout &L, char *s, const RangeRec *range_dev, uint32_t *class_count,
@@ -847,24 +810,26 @@ void enqueue_keys_and_sort(const float *pos, const float *sh, const float *opaci
     const SortPlan P = plan_sort((DEG ? 26 : 24) + 3 * (int)grid_bits);
     uint64_t *ka = reinterpret_cast<uint64_t *>(s + L.keys_a), *kb = reinterpret_cast<uint64_t *>(s + L.keys_b);
     uint32_t *va = reinterpret_cast<uint32_t *>(s + L.vals_a), *vb = reinterpret_cast<uint32_t *>(s + L.vals_b);
-    uint64_t *status[2] = {reinterpret_cast<uint64_t *>(s + L.status),
-                           reinterpret_cast<uint64_t *>(s + L.status) + L.ntiles * kMaxBins};
+    uint32_t *tcount = reinterpret_cast<uint32_t *>(s + L.tcount), *toff = reinterpret_cast<uint32_t *>(s + L.toff);
     uint32_t *gcount = reinterpret_cast<uint32_t *>(s + L.meta);
-    uint32_t *fault = const_cast<uint32_t *>(&range_dev->sort_fault);
-    const uint64_t words = L.ntiles * kMaxBins;
-    const dim3 grid((uint32_t)L.ntiles);
+    const uint32_t ntiles = (uint32_t)L.ntiles;
+    const dim3 grid(ntiles);
     GSBC_LAUNCH(DEG ? "keys_degree" : "keys", k_keys<DEG>, grid, dim3(256), 0, st, pos,
                 reinterpret_cast<const float *>(s + L.dc), sh, opacity, n, grid_bits, range_dev, P, ka, gcount,
-                status[0], 2 * words, tau, class_count);
+                tcount, ntiles, tau, class_count);
     const uint64_t *kin = ka;
     uint64_t *kout = kb;
     const uint32_t *vin = nullptr;
     uint32_t *vout = va;
     for (int p = 0; p < P.passes; p++) {
         const bool last = p == P.passes - 1;
+        if (p > 0)
+            GSBC_LAUNCH("tile_hist", k_tile_hist, grid, dim3(256), 0, st, kin, n, P.shift[p], P.bits[p], ntiles,
+                        tcount);
+        GSBC_LAUNCH("tile_scan", k_tile_scan, dim3(1u << P.bits[p]), dim3(256), 0, st, tcount,
+                    gcount + p * kMaxBins, ntiles, toff);
         GSBC_LAUNCH("sort_pass", k_sort_pass, grid, dim3(256), 0, st, kin, vin, last ? nullptr : kout,
-                    last ? perm : vout, n, P.shift[p], P.bits[p], gcount + p * kMaxBins, status[p & 1],
-                    p >= 1 ? status[(p + 1) & 1] : nullptr, words, fault);
+                    last ? perm : vout, n, P.shift[p], P.bits[p], toff, ntiles);
         const uint64_t *kt = kin;
         kin = kout;
         kout = const_cast<uint64_t *>(kt);
