@@ -51,6 +51,17 @@ __device__ __forceinline__ void band_add(unsigned long long *sums, uint32_t band
         ::gsbc::trace_end(st);                                             \
     } while (0)
 
+// Workgroup b of a grid of G, as the hardware deals them to the 8 XCDs
+// (b mod 8), mapped to a logical block so that each XCD takes one
+// contiguous range of blocks in order: neighbouring blocks then share that
+// XCD's L2 (rows gathered near each other, partial lines written by two
+// neighbours).  A bijection on 0..G-1 for any G.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t b, uint32_t G)
+{
+    const uint32_t x = b & 7u, q = G >> 3, r = G & 7u;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // Per-band stream description passed to kernels by value.
 struct BandArgs {
     uint64_t offset[16];   // byte offset of each stream in the payload

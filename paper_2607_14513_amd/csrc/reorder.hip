@@ -29,8 +29,9 @@ constexpr int kSortTile = 256 * kSortKPT;      // keys per tile (one workgroup)
 constexpr int kMaxDigitBits = 9;
 constexpr int kMaxBins = 1 << kMaxDigitBits;
 constexpr int kMaxPasses = 7;                  // 56-bit keys (grid 10 bits, degree class) in 9-bit digits
-constexpr int kRangeBlock = 384;               // multiple of 12 and 3
-static_assert(kRangeBlock % 12 == 0, "a block-size run of float4 chunks must hold whole primitives");
+constexpr int kRangeBlock = 384;               // coverage histogram block: a multiple of 12 and 3
+constexpr int kMinMaxBlock = 768;              // min/max pass block (measured faster than 384 or 192)
+static_assert(kRangeBlock % 12 == 0 && kMinMaxBlock % 12 == 0, "a block-size run of float4 chunks must hold whole primitives");
 
 // Digits of each pass, low to high: ceil(bits / 9) passes of near-equal width.
 struct SortPlan {
@@ -93,131 +94,125 @@ __global__ __launch_bounds__(256) void k_range_init(uint32_t *acc, uint32_t *met
     for (uint32_t e = t; e < meta_words; e += 256) meta[e] = 0u;
 }
 
-// Workgroup barrier that orders LDS accesses only: global stores issued
-// before it stay in flight (__syncthreads would wait for them).
-__device__ __forceinline__ void lds_barrier()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
-// dc: each primitive's band-0 colour (times its opacity),
-// three floats, for the key pass.
-__global__ __launch_bounds__(kRangeBlock) void k_range_partial(const float4 *sh4, const float *opacity,
-                                                               const float *pos, uint64_t n, uint32_t *acc,
-                                                               float *dc)
+// dc: each primitive's band-0 colour (times its opacity), three floats,
+// for the key pass.  Every wave streams one contiguous run of primitives
+// (a multiple of kStepPrims = 32), a step at a time: the step's 384 float4
+// chunks (six loads per lane) and 96 position floats (two), all in flight
+// together, with no workgroup barrier.  Chunk u * 64 + lane of a step sits
+// at place (lane + 4u) mod 12 of its primitive, one of three places per
+// lane, whose extremes are kept apart and folded into bands at the end;
+// position float x of a step is on axis x mod 3.  The step's band-0 colours
+// go through the wave's own LDS and leave as two contiguous stores, issued
+// before the next step's loads (so waiting on those never waits on a newer
+// store).
+constexpr uint32_t kStepPrims = 32, kStepChunks = kStepPrims * 12, kStepLoads = kStepChunks / 64;
+static_assert(kStepChunks % 64 == 0 && kMinMaxBlock % 64 == 0, "whole loads per lane and step");
+__global__ __launch_bounds__(kMinMaxBlock) void k_range_partial(const float4 *sh4, const float *opacity,
+                                                                const float *pos, uint64_t n, uint32_t *acc,
+                                                                float *dc)
 {
     __shared__ uint32_t s_acc[38];
-    if (threadIdx.x < 38) s_acc[threadIdx.x] = (threadIdx.x < 16 || (threadIdx.x >= 32 && threadIdx.x < 35)) ? 0xFFFFFFFFu : 0u;
+    __shared__ float stage[kMinMaxBlock / 64][kStepPrims * 3];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid < 38) s_acc[tid] = (tid < 16 || (tid >= 32 && tid < 35)) ? 0xFFFFFFFFu : 0u;
     __syncthreads();
-    // each workgroup reads one contiguous span of float4 chunks (a multiple
-    // of the block size, so every chunk a lane reads sits at the same place
-    // in its primitive), four loads in flight per lane
-    constexpr uint64_t B = kRangeBlock;
-    constexpr uint32_t kPrims = (uint32_t)(B / 12);   // primitives per block-size run of chunks
-    // band-0 colours of one step's 4 kPrims primitives, written out by the
-    // whole workgroup at once: a store per lane per primitive would make the
-    // next loads wait on it
-    __shared__ float stage[4 * kPrims * 3];
-    const uint32_t tid = threadIdx.x;
-    // float4 chunk j of a primitive holds floats 4j..4j+3 (bands (4j+c)/3):
-    // extremes kept per position c, folded into bands at the end
-    const int j = (int)(tid % 12);
-    float mn[4], mx[4];
+    const uint64_t waves = (uint64_t)gridDim.x * (kMinMaxBlock / 64), wg = (uint64_t)blockIdx.x * (kMinMaxBlock / 64) + wv;
+    float mn[3][4], mx[3][4];
 #pragma unroll
-    for (int c = 0; c < 4; c++) { mn[c] = INFINITY; mx[c] = -INFINITY; }
-    const uint64_t nq = n * 12;
-    auto take = [&](float4 v, uint64_t q) -> float4 {
+    for (int k = 0; k < 3; k++)
+#pragma unroll
+        for (int c = 0; c < 4; c++) { mn[k][c] = INFINITY; mx[k][c] = -INFINITY; }
+    auto take = [&](float4 &v, int k, uint64_t q) {
         if (opacity) {   // H~ = mu H (FP32 products)
             const float mu = opacity[q / 12];
             v.x *= mu; v.y *= mu; v.z *= mu; v.w *= mu;
         }
-        mn[0] = fminf(mn[0], v.x); mx[0] = fmaxf(mx[0], v.x);
-        mn[1] = fminf(mn[1], v.y); mx[1] = fmaxf(mx[1], v.y);
-        mn[2] = fminf(mn[2], v.z); mx[2] = fmaxf(mx[2], v.z);
-        mn[3] = fminf(mn[3], v.w); mx[3] = fmaxf(mx[3], v.w);
-        return v;
+        mn[k][0] = fminf(mn[k][0], v.x); mx[k][0] = fmaxf(mx[k][0], v.x);
+        mn[k][1] = fminf(mn[k][1], v.y); mx[k][1] = fmaxf(mx[k][1], v.y);
+        mn[k][2] = fminf(mn[k][2], v.z); mx[k][2] = fmaxf(mx[k][2], v.z);
+        mn[k][3] = fminf(mn[k][3], v.w); mx[k][3] = fmaxf(mx[k][3], v.w);
     };
+    float pmn[3], pmx[3];   // positions: extremes of axis (lane + k) mod 3
+#pragma unroll
+    for (int k = 0; k < 3; k++) { pmn[k] = INFINITY; pmx[k] = -INFINITY; }
+    auto take_pos = [&](float a, int k) {
+        pmn[k] = fminf(pmn[k], a);
+        pmx[k] = fmaxf(pmx[k], a);
+    };
+    float *st = stage[wv];
     {
-        const uint64_t per = ((nq + gridDim.x - 1) / gridDim.x + B - 1) / B * B;
-        const uint64_t q0 = (uint64_t)blockIdx.x * per, q1 = min(nq, q0 + per);
-        const uint64_t steps = q1 > q0 ? (q1 - q0) / (4 * B) : 0;   // whole steps: every lane takes part
-        uint64_t q = q0 + tid;
-        // software-pipelined: the next step's loads are in flight while this
-        // step's colours go out; they are issued after the colours' store, so
-        // waiting on them waits on nothing newer than the store
-        float4 v[4];
-        if (steps)
+        const uint64_t nq = n * 12;
+        const uint64_t span = ((nq + waves - 1) / waves + kStepChunks - 1) / kStepChunks * kStepChunks;
+        const uint64_t q0 = wg * span, q1 = min(nq, q0 + span);
+        const uint64_t steps = q1 > q0 ? (q1 - q0) / kStepChunks : 0;
+        uint64_t q = q0;   // first chunk of the step
+        for (uint64_t k = 0; k < steps; k++, q += kStepChunks) {
+            float4 v[kStepLoads];
 #pragma unroll
-            for (int u = 0; u < 4; u++) v[u] = sh4[q + u * B];
-        for (uint64_t k = 0; k < steps; k++, q += 4 * B) {
+            for (int u = 0; u < (int)kStepLoads; u++) v[u] = sh4[q + u * 64 + lane];
+            const float *ps = pos + q / 4;   // the step's positions: floats 3 (q / 12) ..
+            const bool two = lane < kStepPrims * 3 - 64;   // lanes with a second position float
+            const float a0 = ps[lane], a1 = ps[two ? 64 + lane : lane];
+            take_pos(a0, 0);                             // axis lane mod 3
+            take_pos(two ? a1 : __builtin_nanf(""), 1);  // axis (lane + 1) mod 3; NaN leaves fminf/fmaxf as they are
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                v[u] = take(v[u], q + u * B);
-                if (j == 0) {
-                    float *o = stage + 3 * (u * kPrims + tid / 12);
-                    o[0] = v[u].x;
-                    o[1] = v[u].y;
-                    o[2] = v[u].z;
+            for (int u = 0; u < (int)kStepLoads; u++) {
+                take(v[u], u % 3, q + u * 64 + lane);
+                const uint32_t c = u * 64 + lane;   // chunk within the step
+                if (c % 12 == 0) {
+                    st[c / 12 * 3] = v[u].x;
+                    st[c / 12 * 3 + 1] = v[u].y;
+                    st[c / 12 * 3 + 2] = v[u].z;
                 }
             }
-            lds_barrier();
-            dc[3 * ((q - tid) / 12) + tid] = stage[tid];   // 4 kPrims primitives x 3 = B floats
-            if (k + 1 < steps)
-#pragma unroll
-                for (int u = 0; u < 4; u++) v[u] = sh4[q + (4 + u) * B];
-            lds_barrier();
+            float *o = dc + q / 12 * 3;   // the step's 32 colours: 96 contiguous floats
+            o[lane] = st[lane];
+            if (lane < kStepPrims * 3 - 64) o[64 + lane] = st[64 + lane];
         }
-        for (; q < q1; q += B) {   // the rest of the span, less than one step
-            const float4 v = take(sh4[q], q);
-            if (j == 0) {
-                float *o = dc + 3 * (q / 12);
-                o[0] = v.x;
-                o[1] = v.y;
-                o[2] = v.z;
+        // the rest of the run, less than one step
+        const uint32_t rest = (uint32_t)(q1 > q ? (q1 - q) / 12 : 0);   // primitives
+#pragma unroll
+        for (int u = 0; u < 2; u++)
+            if (u * 64 + lane < rest * 3) take_pos(pos[q / 4 + u * 64 + lane], u);
+#pragma unroll
+        for (int u = 0; u < (int)kStepLoads; u++) {
+            const uint64_t qq = q + u * 64 + lane;
+            if (qq < q1) {
+                float4 v = sh4[qq];
+                take(v, u % 3, qq);
+                if ((u * 64 + lane) % 12 == 0) {
+                    float *o = dc + qq / 12 * 3;
+                    o[0] = v.x;
+                    o[1] = v.y;
+                    o[2] = v.z;
+                }
             }
         }
     }
-    const int bandA = (4 * j) / 3, bandB = (4 * j + 3) / 3;
-    float minA = INFINITY, maxA = -INFINITY, minB = INFINITY, maxB = -INFINITY;
+    // fold: place j = (lane + 4k) mod 12 holds floats 4j..4j+3 (bands (4j+c)/3)
 #pragma unroll
-    for (int c = 0; c < 4; c++) {
-        if ((4 * j + c) / 3 == bandA) { minA = fminf(minA, mn[c]); maxA = fmaxf(maxA, mx[c]); }
-        else { minB = fminf(minB, mn[c]); maxB = fmaxf(maxB, mx[c]); }
-    }
-    // positions, the same way (the block size is a multiple of 3, so every
-    // float a lane reads is on one axis)
-    const int axis = (int)(tid % 3);
-    float pmin = INFINITY, pmax = -INFINITY;
-    {
-        const uint64_t np = n * 3;
-        const uint64_t per = ((np + gridDim.x - 1) / gridDim.x + B - 1) / B * B;
-        const uint64_t f0 = (uint64_t)blockIdx.x * per, f1 = min(np, f0 + per);
-        uint64_t f = f0 + tid;
-        for (; f + 3 * B < f1; f += 4 * B) {
-            const float v0 = pos[f], v1 = pos[f + B], v2 = pos[f + 2 * B], v3 = pos[f + 3 * B];
-            pmin = fminf(fminf(pmin, v0), fminf(v1, fminf(v2, v3)));
-            pmax = fmaxf(fmaxf(pmax, v0), fmaxf(v1, fmaxf(v2, v3)));
+    for (int k = 0; k < 3; k++) {
+        const int j = (int)((lane + 4 * k) % 12), bandA = (4 * j) / 3, bandB = (4 * j + 3) / 3;
+        float minA = INFINITY, maxA = -INFINITY, minB = INFINITY, maxB = -INFINITY;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            if ((4 * j + c) / 3 == bandA) { minA = fminf(minA, mn[k][c]); maxA = fmaxf(maxA, mx[k][c]); }
+            else { minB = fminf(minB, mn[k][c]); maxB = fmaxf(maxB, mx[k][c]); }
         }
-        for (; f < f1; f += B) {
-            pmin = fminf(pmin, pos[f]);
-            pmax = fmaxf(pmax, pos[f]);
+        atomicMin(&s_acc[bandA], ord_of(minA));
+        atomicMax(&s_acc[16 + bandA], ord_of(maxA));
+        if (bandB != bandA) {
+            atomicMin(&s_acc[bandB], ord_of(minB));
+            atomicMax(&s_acc[16 + bandB], ord_of(maxB));
         }
+        const int axis = (int)((lane + k) % 3);
+        atomicMin(&s_acc[32 + axis], ord_of(pmn[k]));
+        atomicMax(&s_acc[35 + axis], ord_of(pmx[k]));
     }
-    atomicMin(&s_acc[bandA], ord_of(minA));
-    atomicMax(&s_acc[16 + bandA], ord_of(maxA));
-    if (bandB != bandA) {
-        atomicMin(&s_acc[bandB], ord_of(minB));
-        atomicMax(&s_acc[16 + bandB], ord_of(maxB));
-    }
-    atomicMin(&s_acc[32 + axis], ord_of(pmin));
-    atomicMax(&s_acc[35 + axis], ord_of(pmax));
     __syncthreads();
-    if (threadIdx.x < 38) {
-        int i = threadIdx.x;
-        if (i < 16 || (i >= 32 && i < 35)) atomicMin(&acc[i], s_acc[i]);
-        else atomicMax(&acc[i], s_acc[i]);
+    if (tid < 38) {
+        if (tid < 16 || (tid >= 32 && tid < 35)) atomicMin(&acc[tid], s_acc[tid]);
+        else atomicMax(&acc[tid], s_acc[tid]);
     }
 }
 
@@ -255,26 +250,31 @@ __global__ void k_range_final(const uint32_t *acc, const uint32_t *cov, uint32_t
 // largest SH degree with a coefficient above tau in magnitude, 0 if none)
 // above the cell and colour fields, and the class counts.  A workgroup's
 // keys are the first sort pass's tile: its counts of that pass's digit go
-// to tcount[digit][tile].
+// to tcount[digit][tile].  idx_bits > 0: each word is key << idx_bits | i
+// (the sort then carries the index in the key word).
+// 512 threads, 8 keys each: more waves per CU hide the loads behind the
+// key arithmetic better than 256 x 16
+constexpr int kKeysThreads = 512, kKeysKPT = kSortTile / kKeysThreads;
 template <bool DEG>
-__global__ __launch_bounds__(256) void k_keys(const float *pos, const float *dc, const float *sh,
+__global__ __launch_bounds__(kKeysThreads) void k_keys(const float *pos, const float *dc, const float *sh,
                                               const float *opacity, uint64_t n, uint32_t grid_bits,
                                               const RangeRec *r, SortPlan plan, uint64_t *keys, uint32_t *gcount,
-                                              uint32_t *tcount, uint32_t ntiles, float tau,
+                                              uint32_t *tcount, uint32_t ntiles, uint32_t idx_bits, float tau,
                                               uint32_t *class_count)
 {
     __shared__ uint32_t hist[kMaxPasses][kMaxBins];
     __shared__ uint32_t cls[4];
-    for (int e = threadIdx.x; e < kMaxPasses * kMaxBins; e += 256) (&hist[0][0])[e] = 0u;
+    for (int e = threadIdx.x; e < kMaxPasses * kMaxBins; e += kKeysThreads) (&hist[0][0])[e] = 0u;
     if (DEG && threadIdx.x < 4) cls[threadIdx.x] = 0u;
     __syncthreads();
     const uint32_t cmax = (1u << grid_bits) - 1u;
+    const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
     // every load of the tile first (the last element stands in past the end),
     // so the workgroup has them all in flight at once
-    float px[kSortKPT][3], pc[kSortKPT][3], pmu[kSortKPT];
+    float px[kKeysKPT][3], pc[kKeysKPT][3], pmu[kKeysKPT];
 #pragma unroll
-    for (int it = 0; it < kSortKPT; it++) {
-        const uint64_t i = (uint64_t)blockIdx.x * kSortTile + (uint64_t)it * 256 + threadIdx.x;
+    for (int it = 0; it < kKeysKPT; it++) {
+        const uint64_t i = (uint64_t)tile * kSortTile + (uint64_t)it * kKeysThreads + threadIdx.x;
         const uint64_t ic = i < n ? i : n - 1;
 #pragma unroll
         for (int a = 0; a < 3; a++) {
@@ -284,8 +284,8 @@ __global__ __launch_bounds__(256) void k_keys(const float *pos, const float *dc,
         pmu[it] = opacity && DEG ? opacity[ic] : 1.0f;
     }
 #pragma unroll
-    for (int it = 0; it < kSortKPT; it++) {
-        const uint64_t i = (uint64_t)blockIdx.x * kSortTile + (uint64_t)it * 256 + threadIdx.x;
+    for (int it = 0; it < kKeysKPT; it++) {
+        const uint64_t i = (uint64_t)tile * kSortTile + (uint64_t)it * kKeysThreads + threadIdx.x;
         if (i >= n) break;
         uint32_t cell[3];
 #pragma unroll
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_keys(const float *pos, const float *dc,
             key |= (uint64_t)L << (24 + 3 * grid_bits);
             atomicAdd(&cls[L], 1u);
         }
-        keys[i] = key;
+        keys[i] = idx_bits ? key << idx_bits | i : key;
 #pragma unroll
         for (int p = 0; p < kMaxPasses; p++)
             if (p < plan.passes) atomicAdd(&hist[p][(uint32_t)(key >> plan.shift[p]) & ((1u << plan.bits[p]) - 1u)], 1u);
@@ -333,9 +333,9 @@ __global__ __launch_bounds__(256) void k_keys(const float *pos, const float *dc,
 #pragma unroll
     for (int p = 0; p < kMaxPasses; p++)
         if (p < plan.passes)
-            for (int d = threadIdx.x; d < (1 << plan.bits[p]); d += 256)
+            for (int d = threadIdx.x; d < (1 << plan.bits[p]); d += kKeysThreads)
                 if (hist[p][d]) atomicAdd(&gcount[p * kMaxBins + d], hist[p][d]);
-    for (int d = threadIdx.x; d < (1 << plan.bits[0]); d += 256) tcount[(uint64_t)d * ntiles + blockIdx.x] = hist[0][d];
+    for (int d = threadIdx.x; d < (1 << plan.bits[0]); d += kKeysThreads) tcount[(uint64_t)d * ntiles + tile] = hist[0][d];
     if (DEG && threadIdx.x < 4 && cls[threadIdx.x]) atomicAdd(&class_count[threadIdx.x], cls[threadIdx.x]);
 }
 
@@ -354,7 +354,8 @@ __global__ __launch_bounds__(256) void k_tile_hist(const uint64_t *kin, uint64_t
     const uint32_t tid = threadIdx.x, nbins = 1u << bits, mask = nbins - 1u;
     h[tid] = 0u;
     h[tid + 256] = 0u;
-    const uint64_t t0 = (uint64_t)blockIdx.x * kSortTile;
+    const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
+    const uint64_t t0 = (uint64_t)tile * kSortTile;
     uint64_t key[kSortKPT];
 #pragma unroll
     for (int it = 0; it < kSortKPT; it++) {
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(256) void k_tile_hist(const uint64_t *kin, uint64_t
     for (int it = 0; it < kSortKPT; it++)
         if (t0 + (uint64_t)it * 256 + tid < n) atomicAdd(&h[(uint32_t)(key[it] >> shift) & mask], 1u);
     __syncthreads();
-    for (uint32_t d = tid; d < nbins; d += 256) tcount[(uint64_t)d * ntiles + blockIdx.x] = h[d];
+    for (uint32_t d = tid; d < nbins; d += 256) tcount[(uint64_t)d * ntiles + tile] = h[d];
 }
 
 // Workgroup d: toff[d][t] = (keys of digits below d) + (keys of digit d in
@@ -379,6 +380,12 @@ __global__ __launch_bounds__(256) void k_tile_scan(const uint32_t *tcount, const
     __shared__ uint32_t wsum[4];
     __shared__ uint32_t s_base;
     const uint32_t d = blockIdx.x, tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    const uint32_t *c = tcount + (uint64_t)d * ntiles;
+    uint32_t *out = toff + (uint64_t)d * ntiles;
+    // the first round's counts are read together with the digit totals
+    uint32_t v[kScanPer];
+#pragma unroll
+    for (int i = 0; i < kScanPer; i++) v[i] = tid * kScanPer + i < ntiles ? c[tid * kScanPer + i] : 0u;
     // keys of the lower digits: a block sum over gcount[0 .. d)
     uint32_t b = 0;
     for (uint32_t e = tid; e < d; e += 256) b += gcount[e];
@@ -389,16 +396,14 @@ __global__ __launch_bounds__(256) void k_tile_scan(const uint32_t *tcount, const
     if (tid == 0) s_base = wsum[0] + wsum[1] + wsum[2] + wsum[3];
     __syncthreads();
     uint32_t carry = s_base;
-    const uint32_t *c = tcount + (uint64_t)d * ntiles;
-    uint32_t *out = toff + (uint64_t)d * ntiles;
     for (uint32_t r0 = 0; r0 < ntiles; r0 += 256 * kScanPer) {
         const uint32_t t = r0 + tid * kScanPer;
-        uint32_t v[kScanPer], sum = 0;
+        if (r0 > 0)
 #pragma unroll
-        for (int i = 0; i < kScanPer; i++) {
-            v[i] = t + i < ntiles ? c[t + i] : 0u;
-            sum += v[i];
-        }
+            for (int i = 0; i < kScanPer; i++) v[i] = t + i < ntiles ? c[t + i] : 0u;
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < kScanPer; i++) sum += v[i];
         uint32_t inc = sum;   // inclusive scan of the per-thread sums over the wave
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -420,18 +425,21 @@ __global__ __launch_bounds__(256) void k_tile_scan(const uint32_t *tcount, const
 }
 
 // One pass of the stable LSD sort over digit (shift, bits): the scatter of
-// tile blockIdx.x, given toff.  vin null: the values are the element
-// indices; kout null: only the values are written (the last pass, into perm).
+// tile blockIdx.x, given toff.  PACKED: the words hold the element index in
+// their low idx_bits bits (vin unused); else vin holds the values (null: the
+// element indices).  kout null: only the values (the indices) are written,
+// to vout (the last pass, into perm).
+template <bool PACKED>
 __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
                                                    uint32_t *vout, uint64_t n, int shift, int bits,
-                                                   const uint32_t *toff, uint32_t ntiles)
+                                                   const uint32_t *toff, uint32_t ntiles, uint32_t idx_bits)
 {
     // 52 KB of LDS, so three workgroups share a CU.  The ranking's lane
     // masks and the sorted keys use the same LDS at different times; the
     // values are not staged: the sorted position keeps the element's index
     // in the tile and the value is read back from the input (a cache hit).
     __shared__ uint64_t skey[kSortTile];
-    __shared__ uint16_t sidx[kSortTile];
+    __shared__ uint16_t sidx[PACKED ? 1 : kSortTile];
     __shared__ uint32_t ctr[4][kMaxBins];    // per wave: running digit counts, then the wave's offset in the tile
     uint64_t(*peer)[kMaxBins] = reinterpret_cast<uint64_t(*)[kMaxBins]>(skey);   // per wave: lanes of one step
                                                                                  // holding each digit
@@ -444,7 +452,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
         (&peer[0][0])[e] = 0ull;
     }
     __syncthreads();
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t nbins = 1u << bits, mask = nbins - 1u;
     const uint64_t t0 = (uint64_t)tile * kSortTile;
     // this tile's output offsets, in flight during the ranking
@@ -530,18 +538,24 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
             const uint32_t d = (uint32_t)(key[it] >> shift) & mask;
             const uint32_t lp = lstart[d] + ctr[w][d] + rk[it];
             skey[lp] = key[it];
-            sidx[lp] = (uint16_t)(w * (kSortTile / 4) + it * 64 + lane);
+            if (!PACKED) sidx[lp] = (uint16_t)(w * (kSortTile / 4) + it * 64 + lane);
         }
     }
     __syncthreads();
     // each digit's keys leave as one contiguous run
     const uint32_t tn = (uint32_t)(n - t0 < (uint64_t)kSortTile ? n - t0 : (uint64_t)kSortTile);
+    const uint64_t imask = (1ull << idx_bits) - 1ull;
     for (uint32_t j = tid; j < tn; j += 256) {
         const uint64_t k = skey[j];
-        const uint64_t e = t0 + sidx[j];
         const uint32_t o = (uint32_t)(gadj[(uint32_t)(k >> shift) & mask] + (int32_t)j);
-        if (kout) kout[o] = k;
-        vout[o] = vin ? vin[e] : (uint32_t)e;
+        if (PACKED) {
+            if (kout) kout[o] = k;
+            else vout[o] = (uint32_t)(k & imask);
+        } else {
+            const uint64_t e = t0 + sidx[j];
+            if (kout) kout[o] = k;
+            vout[o] = vin ? vin[e] : (uint32_t)e;
+        }
     }
 }
 
@@ -552,7 +566,7 @@ __global__ __launch_bounds__(256) void k_gather_pack(const float *sh, const floa
                                                      uint64_t n, uint64_t npad, uint32_t arrangement,
                                                      const RangeRec *r, uint32_t *tex)
 {
-    uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t s = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= npad) return;
     uint32_t src = perm[s < n ? s : n - 1];
     const float4 *p = reinterpret_cast<const float4 *>(sh + (uint64_t)src * 48);
@@ -776,10 +790,9 @@ void enqueue_range(const float *pos, const float *sh, const float *opacity, uint
     GSBC_LAUNCH("range_init", k_range_init, dim3(1), dim3(256), 0, st, acc, reinterpret_cast<uint32_t *>(s + L.meta),
                 kMetaWords);
     uint64_t want = (n * 12 + kRangeBlock - 1) / kRangeBlock;
-    // at most 1,024 workgroups: fewer block-level merges into the 38 global
-    // minima and maxima (measured faster at one million primitives, the same at three)
-    uint32_t nb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 1024);
-    GSBC_LAUNCH("range_partial", k_range_partial, dim3(nb), dim3(kRangeBlock), 0, st,
+    // at most 512 workgroups of 768 (two per CU, each one contiguous span)
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>((n * 12 + kMinMaxBlock - 1) / kMinMaxBlock, 1), 512);
+    GSBC_LAUNCH("range_partial", k_range_partial, dim3(nb), dim3(kMinMaxBlock), 0, st,
                        reinterpret_cast<const float4 *>(sh), opacity, pos, n, acc, reinterpret_cast<float *>(s + L.dc));
     uint32_t *cov = nullptr;
     if (quantiser == 1) {
@@ -807,29 +820,39 @@ void enqueue_keys_and_sort(const float *pos, const float *sh, const float *opaci
                            float tau, const Layout &L, char *s, const RangeRec *range_dev, uint32_t *class_count,
                            uint32_t *perm, hipStream_t st)
 {
-    const SortPlan P = plan_sort((DEG ? 26 : 24) + 3 * (int)grid_bits);
+    const int key_bits = (DEG ? 26 : 24) + 3 * (int)grid_bits;
+    const SortPlan P = plan_sort(key_bits);
+    // the index rides in the low bits of the key word when both fit in 64
+    uint32_t idx_bits = 1;
+    while (idx_bits < 32 && (1ull << idx_bits) < n) idx_bits++;
+    const bool packed = key_bits + (int)idx_bits <= 64;
+    const uint32_t ib = packed ? idx_bits : 0u;
     uint64_t *ka = reinterpret_cast<uint64_t *>(s + L.keys_a), *kb = reinterpret_cast<uint64_t *>(s + L.keys_b);
     uint32_t *va = reinterpret_cast<uint32_t *>(s + L.vals_a), *vb = reinterpret_cast<uint32_t *>(s + L.vals_b);
     uint32_t *tcount = reinterpret_cast<uint32_t *>(s + L.tcount), *toff = reinterpret_cast<uint32_t *>(s + L.toff);
     uint32_t *gcount = reinterpret_cast<uint32_t *>(s + L.meta);
     const uint32_t ntiles = (uint32_t)L.ntiles;
     const dim3 grid(ntiles);
-    GSBC_LAUNCH(DEG ? "keys_degree" : "keys", k_keys<DEG>, grid, dim3(256), 0, st, pos,
+    GSBC_LAUNCH(DEG ? "keys_degree" : "keys", k_keys<DEG>, grid, dim3(kKeysThreads), 0, st, pos,
                 reinterpret_cast<const float *>(s + L.dc), sh, opacity, n, grid_bits, range_dev, P, ka, gcount,
-                tcount, ntiles, tau, class_count);
+                tcount, ntiles, ib, tau, class_count);
     const uint64_t *kin = ka;
     uint64_t *kout = kb;
     const uint32_t *vin = nullptr;
     uint32_t *vout = va;
     for (int p = 0; p < P.passes; p++) {
         const bool last = p == P.passes - 1;
+        const int shift = P.shift[p] + (int)ib;
         if (p > 0)
-            GSBC_LAUNCH("tile_hist", k_tile_hist, grid, dim3(256), 0, st, kin, n, P.shift[p], P.bits[p], ntiles,
-                        tcount);
+            GSBC_LAUNCH("tile_hist", k_tile_hist, grid, dim3(256), 0, st, kin, n, shift, P.bits[p], ntiles, tcount);
         GSBC_LAUNCH("tile_scan", k_tile_scan, dim3(1u << P.bits[p]), dim3(256), 0, st, tcount,
                     gcount + p * kMaxBins, ntiles, toff);
-        GSBC_LAUNCH("sort_pass", k_sort_pass, grid, dim3(256), 0, st, kin, vin, last ? nullptr : kout,
-                    last ? perm : vout, n, P.shift[p], P.bits[p], toff, ntiles);
+        if (packed)
+            GSBC_LAUNCH("sort_pass", k_sort_pass<true>, grid, dim3(256), 0, st, kin, nullptr, last ? nullptr : kout,
+                        last ? perm : nullptr, n, shift, P.bits[p], toff, ntiles, ib);
+        else
+            GSBC_LAUNCH("sort_pass", k_sort_pass<false>, grid, dim3(256), 0, st, kin, vin, last ? nullptr : kout,
+                        last ? perm : vout, n, shift, P.bits[p], toff, ntiles, 0u);
         const uint64_t *kt = kin;
         kin = kout;
         kout = const_cast<uint64_t *>(kt);
