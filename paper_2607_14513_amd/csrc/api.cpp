@@ -4,6 +4,8 @@
 #include "../../include/gsbc.h"
 #include "gsbc_internal.h"
 
+#include <cstddef>
+
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
@@ -63,6 +65,7 @@ constexpr size_t kOff1Off = 1280;                // 16 x u64
 constexpr size_t kOff7Off = 1408;                // 16 x u64
 constexpr size_t kClassOff = 1536;               // 4 x u32 degree-class counts
 constexpr size_t kSmallBytes = 2048;
+static_assert(sizeof(gsbc::RangeRec) <= kSelOff, "RangeRec must fit before RateSel (and before the class counts read back beside it)");
 
 std::atomic<long> g_alloc_count{0};
 
@@ -366,6 +369,14 @@ gsbc_status gsbc_create(gsbc_ctx **out, int device, void *hip_stream)
         ctx->own_stream = true;
     }
     if (hipMalloc(&ctx->small, kSmallBytes) != hipSuccess) return bail(GSBC_E_NOMEM);
+    {   // the range extremes start neutral: minima all ones, maxima zero
+        uint32_t acc0[38];
+        for (int i = 0; i < 38; i++) acc0[i] = (i < 16 || (i >= 32 && i < 35)) ? 0xFFFFFFFFu : 0u;
+        if (hipMemset(ctx->small, 0, kSmallBytes) != hipSuccess ||
+            hipMemcpy(static_cast<char *>(ctx->small) + kRangeOff + offsetof(RangeRec, acc), acc0, sizeof acc0,
+                      hipMemcpyHostToDevice) != hipSuccess)
+            return bail(GSBC_E_DEVICE);
+    }
     if (hipHostMalloc(&ctx->pinned, 4096, hipHostMallocDefault) != hipSuccess) return bail(GSBC_E_NOMEM);
     if (upload_bc1_tables(device, ctx->stream) != hipSuccess) return bail(GSBC_E_DEVICE);
     if (upload_bc7_tables(device, ctx->stream) != hipSuccess) return bail(GSBC_E_DEVICE);

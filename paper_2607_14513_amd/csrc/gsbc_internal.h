@@ -79,6 +79,10 @@ struct RangeRec {
     float scale[16];            // 255 / (vmax - vmin), 0 for a constant band
     float lo[3], hi[3];         // position bounding box
     float cell_scale[3];        // 2^g / (hi - lo), 0 for a flat axis
+    // the range pass's running extremes (order-preserving integer encodings:
+    // [0..15] band min, [16..31] band max, [32..34] position min, [35..37]
+    // position max), left at their neutral values between calls
+    uint32_t acc[38];
 };
 
 // ---- reorder (reorder.hip)

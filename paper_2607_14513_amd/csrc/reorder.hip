@@ -85,14 +85,11 @@ __device__ __forceinline__ uint32_t quant8(float x, float vmin, float s)
     return (uint32_t)v;
 }
 
-// acc layout: [0..15] band min, [16..31] band max, [32..34] pos min, [35..37] pos max.
-// Also clears the sort's digit totals (meta, meta_words).
-__global__ __launch_bounds__(256) void k_range_init(uint32_t *acc, uint32_t *meta, uint32_t meta_words)
-{
-    const int t = threadIdx.x;
-    if (t < 38) acc[t] = (t < 16 || (t >= 32 && t < 35)) ? 0xFFFFFFFFu : 0u;
-    for (uint32_t e = t; e < meta_words; e += 256) meta[e] = 0u;
-}
+// acc (RangeRec::acc) layout: [0..15] band min, [16..31] band max, [32..34]
+// pos min, [35..37] pos max.  It is neutral when a call starts (set so when
+// the context is made, and put back by k_range_final once read).
+constexpr int kAccWords = 38;
+__device__ __forceinline__ bool acc_is_min(int i) { return i < 16 || (i >= 32 && i < 35); }
 
 // dc: each primitive's band-0 colour (times its opacity), three floats,
 // for the key pass.  Every wave streams one contiguous run of primitives
@@ -111,10 +108,10 @@ __global__ __launch_bounds__(kMinMaxBlock) void k_range_partial(const float4 *sh
                                                                 const float *pos, uint64_t n, uint32_t *acc,
                                                                 float *dc)
 {
-    __shared__ uint32_t s_acc[38];
+    __shared__ uint32_t s_acc[kAccWords];
     __shared__ float stage[kMinMaxBlock / 64][kStepPrims * 3];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (tid < 38) s_acc[tid] = (tid < 16 || (tid >= 32 && tid < 35)) ? 0xFFFFFFFFu : 0u;
+    if (tid < kAccWords) s_acc[tid] = acc_is_min((int)tid) ? 0xFFFFFFFFu : 0u;
     __syncthreads();
     const uint64_t waves = (uint64_t)gridDim.x * (kMinMaxBlock / 64), wg = (uint64_t)blockIdx.x * (kMinMaxBlock / 64) + wv;
     float mn[3][4], mx[3][4];
@@ -210,8 +207,8 @@ __global__ __launch_bounds__(kMinMaxBlock) void k_range_partial(const float4 *sh
         atomicMax(&s_acc[35 + axis], ord_of(pmx[k]));
     }
     __syncthreads();
-    if (tid < 38) {
-        if (tid < 16 || (tid >= 32 && tid < 35)) atomicMin(&acc[tid], s_acc[tid]);
+    if (tid < kAccWords) {
+        if (acc_is_min((int)tid)) atomicMin(&acc[tid], s_acc[tid]);
         else atomicMax(&acc[tid], s_acc[tid]);
     }
 }
@@ -221,9 +218,19 @@ __device__ __forceinline__ float canon_zero(float x) { return x == 0.0f ? 0.0f :
 
 // cov: null for the min/max range, else the coverage state (prefix[16] =
 // bit pattern of t per band after the last selection pass) for [-t, t].
-__global__ void k_range_final(const uint32_t *acc, const uint32_t *cov, uint32_t grid_bits, RangeRec *r)
+// The range from r->acc, which is then put back to neutral; also clears the
+// sort's digit totals (meta, meta_words) for the key pass that follows.
+__global__ __launch_bounds__(256) void k_range_final(const uint32_t *cov, uint32_t grid_bits, RangeRec *r,
+                                                     uint32_t *meta, uint32_t meta_words)
 {
-    int k = threadIdx.x;
+    __shared__ uint32_t acc[kAccWords];
+    const int k = threadIdx.x;
+    for (uint32_t e = k; e < meta_words; e += 256) meta[e] = 0u;
+    if (k < kAccWords) {
+        acc[k] = r->acc[k];
+        r->acc[k] = acc_is_min(k) ? 0xFFFFFFFFu : 0u;
+    }
+    __syncthreads();
     if (k < 16) {
         float lo = canon_zero(float_of(acc[k])), hi = canon_zero(float_of(acc[16 + k]));
         if (cov) {
@@ -741,7 +748,7 @@ __global__ __launch_bounds__(256) void k_pack_degrees(const float *sh, const flo
 }
 
 struct Layout {
-    size_t acc, keys_a, keys_b, vals_a, vals_b, dc, tcount, toff, meta, cov_state, cov_part, bytes;
+    size_t keys_a, keys_b, vals_a, vals_b, dc, tcount, toff, meta, cov_state, cov_part, bytes;
     uint64_t ntiles;
 };
 
@@ -754,7 +761,6 @@ Layout layout(uint64_t n)
     Layout L;
     L.ntiles = (n + kSortTile - 1) / kSortTile;
     size_t o = 0;
-    L.acc = o; o += al(64 * 4);
     L.keys_a = o; o += al(n * 8);
     L.keys_b = o; o += al(n * 8);
     L.vals_a = o; o += al(n * 4);
@@ -786,14 +792,11 @@ namespace {
 void enqueue_range(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
                    uint32_t quantiser, const Layout &L, char *s, RangeRec *range_dev, hipStream_t st)
 {
-    uint32_t *acc = reinterpret_cast<uint32_t *>(s + L.acc);
-    GSBC_LAUNCH("range_init", k_range_init, dim3(1), dim3(256), 0, st, acc, reinterpret_cast<uint32_t *>(s + L.meta),
-                kMetaWords);
     uint64_t want = (n * 12 + kRangeBlock - 1) / kRangeBlock;
     // at most 512 workgroups of 768 (two per CU, each one contiguous span)
     const uint32_t nb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>((n * 12 + kMinMaxBlock - 1) / kMinMaxBlock, 1), 512);
     GSBC_LAUNCH("range_partial", k_range_partial, dim3(nb), dim3(kMinMaxBlock), 0, st,
-                       reinterpret_cast<const float4 *>(sh), opacity, pos, n, acc, reinterpret_cast<float *>(s + L.dc));
+                       reinterpret_cast<const float4 *>(sh), opacity, pos, n, range_dev->acc, reinterpret_cast<float *>(s + L.dc));
     uint32_t *cov = nullptr;
     if (quantiser == 1) {
         cov = reinterpret_cast<uint32_t *>(s + L.cov_state);
@@ -808,7 +811,8 @@ void enqueue_range(const float *pos, const float *sh, const float *opacity, uint
             GSBC_LAUNCH("cov_select", k_cov_select, dim3(16), dim3(256), 0, st, part, ncw, pass, cov);
         }
     }
-    GSBC_LAUNCH("range_final", k_range_final, dim3(1), dim3(64), 0, st, acc, cov, grid_bits, range_dev);
+    GSBC_LAUNCH("range_final", k_range_final, dim3(1), dim3(256), 0, st, cov, grid_bits, range_dev,
+                reinterpret_cast<uint32_t *>(s + L.meta), kMetaWords);
 }
 
 // The keys in keys_a with their digit totals and the first pass's tile
