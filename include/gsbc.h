@@ -180,13 +180,25 @@ GSBC_API gsbc_status gsbc_query_sizes(uint64_t n, uint32_t n_dirs, uint64_t *tex
  *           arrangement assigns (GSBC_ARR_*; n_pad * 64 bytes in every
  *           arrangement); slots past n repeat slot n-1
  *   desc    host, out: vmin, vmax, n_prims, n_pad, blocks_per_stream,
- *           arrangement, n_streams filled
+ *           arrangement, n_streams filled; the call waits for the stream to
+ *           read the ranges back.  NULL: the call only enqueues the work and
+ *           returns (perm and textures are ready when the stream gets
+ *           there); gsbc_reorder_desc fills the desc later.
  * Keys: (Morton cell of the position on a 2^g grid over the bounding box) << 24
  * | interleaved bits of the band-0 quantised R,G,B (R highest in each triple);
  * stable ascending sort.  Inputs must be finite. */
 GSBC_API gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, const float *opacity,
                          uint64_t n, const gsbc_params *params, uint32_t *perm, uint8_t *textures,
                          gsbc_stream_desc *desc);
+
+/* The desc of the last gsbc_reorder on this context (as that call fills it
+ * when given a desc): waits for the stream, then reads the ranges back.
+ * For callers that enqueue the reorder without waiting (desc NULL) and need
+ * the ranges later, e.g. after queueing other work.
+ *   desc  host, out
+ * GSBC_E_ARG when no gsbc_reorder has run on the context since it was made
+ * or since a gsbc_reorder_degrees (which reuses the range record). */
+GSBC_API gsbc_status gsbc_reorder_desc(gsbc_ctx *ctx, gsbc_stream_desc *desc);
 
 /* Variable number of bands (Sec. IV-B: primitives whose higher-order SH are
  * zero, or small enough to count as zero, go to bitstreams with fewer

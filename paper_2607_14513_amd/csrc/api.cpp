@@ -29,6 +29,10 @@ struct gsbc_ctx {
     uint64_t arena_growths = 0;
     void *small = nullptr;          // fixed device block: range, selection, SSE sums, offsets
     void *pinned = nullptr;         // host staging for read-backs
+    // the last gsbc_reorder (for gsbc_reorder_desc): its n and params
+    bool reordered = false;
+    uint64_t last_n = 0;
+    gsbc_params last_p{};
     char err[512] = {0};
     // gsbc_encode_batch: the last plan (device tables + captured graph)
     hipStream_t side = nullptr;      // second stream for BC1 beside BC7
@@ -451,13 +455,37 @@ gsbc_status gsbc_arena_info(const gsbc_ctx *ctx, uint64_t *bytes, uint64_t *grow
     return GSBC_OK;
 }
 
+namespace {
+
+// Wait for the stream, then desc from the range record of the last
+// gsbc_reorder and its n and params.
+gsbc_status read_reorder_desc(gsbc_ctx *ctx, gsbc_stream_desc *desc)
+{
+    const RangeRec *range = reinterpret_cast<const RangeRec *>(small_ptr(ctx, kRangeOff));
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, range, sizeof(RangeRec), hipMemcpyDeviceToHost, ctx->stream), "range read-back");
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "reorder");
+    const RangeRec *r = static_cast<const RangeRec *>(ctx->pinned);
+    const gsbc_params &p = ctx->last_p;
+    const uint64_t n = ctx->last_n;
+    memset(desc, 0, sizeof *desc);
+    for (int k = 0; k < 16; k++) { desc->vmin[k] = r->vmin[k]; desc->vmax[k] = r->vmax[k]; }
+    desc->n_prims = n;
+    desc->n_pad = pad16(n);
+    desc->arrangement = p.arrangement;
+    desc->n_streams = streams_of(p.arrangement);
+    desc->blocks_per_stream = desc->n_pad / desc->n_streams;
+    return GSBC_OK;
+}
+
+}  // namespace
+
 gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, const float *opacity, uint64_t n,
                          const gsbc_params *params, uint32_t *perm, uint8_t *textures, gsbc_stream_desc *desc)
 {
     gsbc_status s = begin(ctx);
     if (s) return s;
     ActiveGuard guard(ctx);
-    if (!pos || !sh || !perm || !textures || !desc) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
+    if (!pos || !sh || !perm || !textures) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
     if (n == 0 || n > 0x7FFFFFFFull) return fail(ctx, GSBC_E_ARG, "n = %llu not in 1..2^31-1", (unsigned long long)n);
     if ((reinterpret_cast<uintptr_t>(sh) & 15) || (reinterpret_cast<uintptr_t>(textures) & 15) ||
         (reinterpret_cast<uintptr_t>(pos) & 3) || (reinterpret_cast<uintptr_t>(perm) & 3) ||
@@ -470,20 +498,24 @@ gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, const
                     (unsigned long long)n);
     if ((s = ensure_arena(ctx, reorder_scratch_bytes(n, p.grid_bits)))) return s;
     RangeRec *range = reinterpret_cast<RangeRec *>(small_ptr(ctx, kRangeOff));
+    ctx->reordered = false;
     HIP_TRY(ctx, launch_reorder(pos, sh, opacity, n, p.grid_bits, p.quantiser, p.order == 1, p.arrangement, perm,
                                  textures, ctx->arena, range, ctx->stream),
             "reorder launch");
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, range, sizeof(RangeRec), hipMemcpyDeviceToHost, ctx->stream), "range read-back");
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "reorder");
-    const RangeRec *r = static_cast<const RangeRec *>(ctx->pinned);
-    memset(desc, 0, sizeof *desc);
-    for (int k = 0; k < 16; k++) { desc->vmin[k] = r->vmin[k]; desc->vmax[k] = r->vmax[k]; }
-    desc->n_prims = n;
-    desc->n_pad = pad16(n);
-    desc->arrangement = p.arrangement;
-    desc->n_streams = streams_of(p.arrangement);
-    desc->blocks_per_stream = desc->n_pad / desc->n_streams;
-    return GSBC_OK;
+    ctx->reordered = true;
+    ctx->last_n = n;
+    ctx->last_p = p;
+    return desc ? read_reorder_desc(ctx, desc) : GSBC_OK;
+}
+
+gsbc_status gsbc_reorder_desc(gsbc_ctx *ctx, gsbc_stream_desc *desc)
+{
+    gsbc_status s = begin(ctx);
+    if (s) return s;
+    ActiveGuard guard(ctx);
+    if (!desc) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
+    if (!ctx->reordered) return fail(ctx, GSBC_E_ARG, "no gsbc_reorder on this context since the last range use");
+    return read_reorder_desc(ctx, desc);
 }
 
 gsbc_status gsbc_reorder_degrees(gsbc_ctx *ctx, const float *pos, const float *sh, const float *opacity, uint64_t n,
@@ -519,6 +551,7 @@ gsbc_status gsbc_reorder_degrees(gsbc_ctx *ctx, const float *pos, const float *s
     if ((s = ensure_arena(ctx, reorder_scratch_bytes(n, p.grid_bits)))) return s;
     RangeRec *range = reinterpret_cast<RangeRec *>(small_ptr(ctx, kRangeOff));
     uint32_t *cls = reinterpret_cast<uint32_t *>(small_ptr(ctx, kClassOff));
+    ctx->reordered = false;   // the range record is this call's now
     HIP_TRY(ctx, launch_degree_sort(pos, sh, opacity, n, p.grid_bits, p.quantiser, tau, perm, ctx->arena, range, cls,
                                     ctx->stream), "degree sort launch");
     char *stage = static_cast<char *>(ctx->pinned);

@@ -92,7 +92,7 @@ constexpr int kAccWords = 38;
 __device__ __forceinline__ bool acc_is_min(int i) { return i < 16 || (i >= 32 && i < 35); }
 
 // dc: each primitive's band-0 colour (times its opacity), three floats,
-// for the key pass.  Every wave streams one contiguous run of primitives
+// for the key pass.  Workgroup 0 also clears the sort's digit totals.  Every wave streams one contiguous run of primitives
 // (a multiple of kStepPrims = 32), a step at a time: the step's 384 float4
 // chunks (six loads per lane) and 96 position floats (two), all in flight
 // together, with no workgroup barrier.  Chunk u * 64 + lane of a step sits
@@ -106,12 +106,14 @@ constexpr uint32_t kStepPrims = 32, kStepChunks = kStepPrims * 12, kStepLoads = 
 static_assert(kStepChunks % 64 == 0 && kMinMaxBlock % 64 == 0, "whole loads per lane and step");
 __global__ __launch_bounds__(kMinMaxBlock) void k_range_partial(const float4 *sh4, const float *opacity,
                                                                 const float *pos, uint64_t n, uint32_t *acc,
-                                                                float *dc)
+                                                                float *dc, uint32_t *meta, uint32_t meta_words)
 {
     __shared__ uint32_t s_acc[kAccWords];
     __shared__ float stage[kMinMaxBlock / 64][kStepPrims * 3];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid < kAccWords) s_acc[tid] = acc_is_min((int)tid) ? 0xFFFFFFFFu : 0u;
+    if (blockIdx.x == 0)   // the sort's digit totals, for the key pass that follows
+        for (uint32_t e = tid; e < meta_words; e += kMinMaxBlock) meta[e] = 0u;
     __syncthreads();
     const uint64_t waves = (uint64_t)gridDim.x * (kMinMaxBlock / 64), wg = (uint64_t)blockIdx.x * (kMinMaxBlock / 64) + wv;
     float mn[3][4], mx[3][4];
@@ -216,40 +218,57 @@ __global__ __launch_bounds__(kMinMaxBlock) void k_range_partial(const float4 *sh
 // Signed zero: the range endpoints are values, stored as +0 when zero.
 __device__ __forceinline__ float canon_zero(float x) { return x == 0.0f ? 0.0f : x; }
 
-// cov: null for the min/max range, else the coverage state (prefix[16] =
-// bit pattern of t per band after the last selection pass) for [-t, t].
-// The range from r->acc, which is then put back to neutral; also clears the
-// sort's digit totals (meta, meta_words) for the key pass that follows.
-__global__ __launch_bounds__(256) void k_range_final(const uint32_t *cov, uint32_t grid_bits, RangeRec *r,
-                                                     uint32_t *meta, uint32_t meta_words)
+// The range record's fields from the extremes acc: lane k < 16 band k,
+// lane k < 3 also axis k.  cov: null for the min/max range, else the
+// coverage state (prefix[16] = bit pattern of t per band after the last
+// selection pass) for [-t, t].
+__device__ __forceinline__ void band_range(const uint32_t *acc, int k, float &lo, float &hi, float &scale)
+{
+    lo = canon_zero(float_of(acc[k]));
+    hi = canon_zero(float_of(acc[16 + k]));
+    const float range = hi - lo;
+    scale = range > 0.0f ? 255.0f / range : 0.0f;
+}
+__device__ __forceinline__ void axis_range(const uint32_t *acc, int a, uint32_t grid_bits, float &lo, float &hi,
+                                           float &cell_scale)
+{
+    lo = canon_zero(float_of(acc[32 + a]));
+    hi = canon_zero(float_of(acc[35 + a]));
+    const float ext = hi - lo;
+    cell_scale = ext > 0.0f ? (float)(1u << grid_bits) / ext : 0.0f;
+}
+__device__ void finish_range(const uint32_t *acc, const uint32_t *cov, uint32_t grid_bits, RangeRec *r, int k)
+{
+    if (k < 16) {
+        float lo, hi, scale;
+        band_range(acc, k, lo, hi, scale);
+        if (cov) {
+            const float t = __uint_as_float(cov[k]);
+            lo = canon_zero(-t);
+            hi = t;
+            const float range = hi - lo;
+            scale = range > 0.0f ? 255.0f / range : 0.0f;
+        }
+        r->vmin[k] = lo;
+        r->vmax[k] = hi;
+        r->scale[k] = scale;
+    }
+    if (k < 3) axis_range(acc, k, grid_bits, r->lo[k], r->hi[k], r->cell_scale[k]);
+}
+
+// The range record from r->acc (and cov), then r->acc back to neutral; for
+// calls whose key pass does not finish the range itself (an identity order,
+// or the coverage range).
+__global__ __launch_bounds__(64) void k_range_final(const uint32_t *cov, uint32_t grid_bits, RangeRec *r)
 {
     __shared__ uint32_t acc[kAccWords];
     const int k = threadIdx.x;
-    for (uint32_t e = k; e < meta_words; e += 256) meta[e] = 0u;
     if (k < kAccWords) {
         acc[k] = r->acc[k];
         r->acc[k] = acc_is_min(k) ? 0xFFFFFFFFu : 0u;
     }
     __syncthreads();
-    if (k < 16) {
-        float lo = canon_zero(float_of(acc[k])), hi = canon_zero(float_of(acc[16 + k]));
-        if (cov) {
-            const float t = __uint_as_float(cov[k]);
-            lo = canon_zero(-t);
-            hi = t;
-        }
-        r->vmin[k] = lo;
-        r->vmax[k] = hi;
-        float range = hi - lo;
-        r->scale[k] = range > 0.0f ? 255.0f / range : 0.0f;
-    }
-    if (k < 3) {
-        float lo = canon_zero(float_of(acc[32 + k])), hi = canon_zero(float_of(acc[35 + k]));
-        r->lo[k] = lo;
-        r->hi[k] = hi;
-        float ext = hi - lo;
-        r->cell_scale[k] = ext > 0.0f ? (float)(1u << grid_bits) / ext : 0.0f;
-    }
+    finish_range(acc, cov, grid_bits, r, k);
 }
 
 // Keys, 4,096 per workgroup: (Morton cell << 24) | colour interleave, and
@@ -265,14 +284,30 @@ constexpr int kKeysThreads = 512, kKeysKPT = kSortTile / kKeysThreads;
 template <bool DEG>
 __global__ __launch_bounds__(kKeysThreads) void k_keys(const float *pos, const float *dc, const float *sh,
                                               const float *opacity, uint64_t n, uint32_t grid_bits,
-                                              const RangeRec *r, SortPlan plan, uint64_t *keys, uint32_t *gcount,
-                                              uint32_t *tcount, uint32_t ntiles, uint32_t idx_bits, float tau,
-                                              uint32_t *class_count)
+                                              RangeRec *r, bool self_range, SortPlan plan, uint64_t *keys,
+                                              uint32_t *gcount, uint32_t *tcount, uint32_t ntiles, uint32_t idx_bits,
+                                              float tau, uint32_t *class_count)
 {
     __shared__ uint32_t hist[kMaxPasses][kMaxBins];
     __shared__ uint32_t cls[4];
     for (int e = threadIdx.x; e < kMaxPasses * kMaxBins; e += kKeysThreads) (&hist[0][0])[e] = 0u;
     if (DEG && threadIdx.x < 4) cls[threadIdx.x] = 0u;
+    // the ranges this pass needs (band 0, the three axes): self_range, from
+    // the range pass's extremes (workgroup 0 also fills the whole record);
+    // else from the record
+    float vmin0, scale0, lo[3], cell_scale[3];
+    if (self_range) {
+        float hi;
+        band_range(r->acc, 0, vmin0, hi, scale0);
+#pragma unroll
+        for (int a = 0; a < 3; a++) axis_range(r->acc, a, grid_bits, lo[a], hi, cell_scale[a]);
+        if (blockIdx.x == 0 && threadIdx.x < 16) finish_range(r->acc, nullptr, grid_bits, r, (int)threadIdx.x);
+    } else {
+        vmin0 = r->vmin[0];
+        scale0 = r->scale[0];
+#pragma unroll
+        for (int a = 0; a < 3; a++) { lo[a] = r->lo[a]; cell_scale[a] = r->cell_scale[a]; }
+    }
     __syncthreads();
     const uint32_t cmax = (1u << grid_bits) - 1u;
     const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
@@ -297,8 +332,8 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(const float *pos, const f
         uint32_t cell[3];
 #pragma unroll
         for (int a = 0; a < 3; a++) {
-            float t = px[it][a] - r->lo[a];
-            float u = t * r->cell_scale[a];
+            float t = px[it][a] - lo[a];
+            float u = t * cell_scale[a];
             uint32_t v = (uint32_t)floorf(u);
             cell[a] = v < cmax ? v : cmax;
         }
@@ -307,9 +342,9 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(const float *pos, const f
         // opacity; otherwise the range pass stored it already multiplied
         float d0 = pc[it][0], d1 = pc[it][1], d2 = pc[it][2];
         if (DEG && opacity) { d0 = mu * d0; d1 = mu * d1; d2 = mu * d2; }
-        const uint32_t q0 = quant8(d0, r->vmin[0], r->scale[0]);
-        const uint32_t q1 = quant8(d1, r->vmin[0], r->scale[0]);
-        const uint32_t q2 = quant8(d2, r->vmin[0], r->scale[0]);
+        const uint32_t q0 = quant8(d0, vmin0, scale0);
+        const uint32_t q1 = quant8(d1, vmin0, scale0);
+        const uint32_t q2 = quant8(d2, vmin0, scale0);
         const uint64_t chunk = spread3(cell[0]) | (spread3(cell[1]) << 1) | (spread3(cell[2]) << 2);
         const uint32_t colour = (spread3(q0) << 2) | (spread3(q1) << 1) | spread3(q2);
         uint64_t key = (chunk << 24) | colour;
@@ -435,11 +470,13 @@ __global__ __launch_bounds__(256) void k_tile_scan(const uint32_t *tcount, const
 // tile blockIdx.x, given toff.  PACKED: the words hold the element index in
 // their low idx_bits bits (vin unused); else vin holds the values (null: the
 // element indices).  kout null: only the values (the indices) are written,
-// to vout (the last pass, into perm).
+// to vout (the last pass, into perm).  reset (the first pass): the range
+// extremes to put back to neutral, the key pass having read them.
 template <bool PACKED>
 __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const uint32_t *vin, uint64_t *kout,
                                                    uint32_t *vout, uint64_t n, int shift, int bits,
-                                                   const uint32_t *toff, uint32_t ntiles, uint32_t idx_bits)
+                                                   const uint32_t *toff, uint32_t ntiles, uint32_t idx_bits,
+                                                   RangeRec *reset)
 {
     // 52 KB of LDS, so three workgroups share a CU.  The ranking's lane
     // masks and the sorted keys use the same LDS at different times; the
@@ -454,6 +491,8 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
     __shared__ int32_t gadj[kMaxBins];       // output index of sorted position j of digit d: gadj[d] + j
     __shared__ uint32_t wsum[4];
     const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    if (reset && blockIdx.x == 0 && tid < kAccWords)   // the key pass has read the extremes: back to neutral
+        reset->acc[tid] = acc_is_min(tid) ? 0xFFFFFFFFu : 0u;
     for (int e = tid; e < 4 * kMaxBins; e += 256) {
         (&ctr[0][0])[e] = 0u;
         (&peer[0][0])[e] = 0ull;
@@ -789,14 +828,18 @@ __global__ void k_iota(uint32_t *perm, uint64_t n)
 namespace {
 
 // Range prologue: min/max (and the coverage range when asked) into range_dev.
+// keys_finish: the key pass will fill the range record (and put the extremes
+// back) itself, so no finishing launch is needed unless the coverage range
+// replaces the band ranges.
 void enqueue_range(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
-                   uint32_t quantiser, const Layout &L, char *s, RangeRec *range_dev, hipStream_t st)
+                   uint32_t quantiser, bool keys_finish, const Layout &L, char *s, RangeRec *range_dev, hipStream_t st)
 {
     uint64_t want = (n * 12 + kRangeBlock - 1) / kRangeBlock;
     // at most 512 workgroups of 768 (two per CU, each one contiguous span)
     const uint32_t nb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>((n * 12 + kMinMaxBlock - 1) / kMinMaxBlock, 1), 512);
     GSBC_LAUNCH("range_partial", k_range_partial, dim3(nb), dim3(kMinMaxBlock), 0, st,
-                       reinterpret_cast<const float4 *>(sh), opacity, pos, n, range_dev->acc, reinterpret_cast<float *>(s + L.dc));
+                       reinterpret_cast<const float4 *>(sh), opacity, pos, n, range_dev->acc, reinterpret_cast<float *>(s + L.dc),
+                reinterpret_cast<uint32_t *>(s + L.meta), kMetaWords);
     uint32_t *cov = nullptr;
     if (quantiser == 1) {
         cov = reinterpret_cast<uint32_t *>(s + L.cov_state);
@@ -811,8 +854,8 @@ void enqueue_range(const float *pos, const float *sh, const float *opacity, uint
             GSBC_LAUNCH("cov_select", k_cov_select, dim3(16), dim3(256), 0, st, part, ncw, pass, cov);
         }
     }
-    GSBC_LAUNCH("range_final", k_range_final, dim3(1), dim3(256), 0, st, cov, grid_bits, range_dev,
-                reinterpret_cast<uint32_t *>(s + L.meta), kMetaWords);
+    if (quantiser == 1 || !keys_finish)
+        GSBC_LAUNCH("range_final", k_range_final, dim3(1), dim3(64), 0, st, cov, grid_bits, range_dev);
 }
 
 // The keys in keys_a with their digit totals and the first pass's tile
@@ -821,8 +864,8 @@ void enqueue_range(const float *pos, const float *sh, const float *opacity, uint
 // indices) to perm.
 template <bool DEG>
 void enqueue_keys_and_sort(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
-                           float tau, const Layout &L, char *s, const RangeRec *range_dev, uint32_t *class_count,
-                           uint32_t *perm, hipStream_t st)
+                           float tau, bool self_range, const Layout &L, char *s, RangeRec *range_dev,
+                           uint32_t *class_count, uint32_t *perm, hipStream_t st)
 {
     const int key_bits = (DEG ? 26 : 24) + 3 * (int)grid_bits;
     const SortPlan P = plan_sort(key_bits);
@@ -838,8 +881,8 @@ void enqueue_keys_and_sort(const float *pos, const float *sh, const float *opaci
     const uint32_t ntiles = (uint32_t)L.ntiles;
     const dim3 grid(ntiles);
     GSBC_LAUNCH(DEG ? "keys_degree" : "keys", k_keys<DEG>, grid, dim3(kKeysThreads), 0, st, pos,
-                reinterpret_cast<const float *>(s + L.dc), sh, opacity, n, grid_bits, range_dev, P, ka, gcount,
-                tcount, ntiles, ib, tau, class_count);
+                reinterpret_cast<const float *>(s + L.dc), sh, opacity, n, grid_bits, range_dev, self_range, P, ka,
+                gcount, tcount, ntiles, ib, tau, class_count);
     const uint64_t *kin = ka;
     uint64_t *kout = kb;
     const uint32_t *vin = nullptr;
@@ -853,10 +896,10 @@ void enqueue_keys_and_sort(const float *pos, const float *sh, const float *opaci
                     gcount + p * kMaxBins, ntiles, toff);
         if (packed)
             GSBC_LAUNCH("sort_pass", k_sort_pass<true>, grid, dim3(256), 0, st, kin, nullptr, last ? nullptr : kout,
-                        last ? perm : nullptr, n, shift, P.bits[p], toff, ntiles, ib);
+                        last ? perm : nullptr, n, shift, P.bits[p], toff, ntiles, ib, p == 0 ? range_dev : nullptr);
         else
             GSBC_LAUNCH("sort_pass", k_sort_pass<false>, grid, dim3(256), 0, st, kin, vin, last ? nullptr : kout,
-                        last ? perm : vout, n, shift, P.bits[p], toff, ntiles, 0u);
+                        last ? perm : vout, n, shift, P.bits[p], toff, ntiles, 0u, p == 0 ? range_dev : nullptr);
         const uint64_t *kt = kin;
         kin = kout;
         kout = const_cast<uint64_t *>(kt);
@@ -873,11 +916,12 @@ hipError_t launch_reorder(const float *pos, const float *sh, const float *opacit
 {
     Layout L = layout(n);
     char *s = static_cast<char *>(scratch);
-    enqueue_range(pos, sh, opacity, n, grid_bits, quantiser, L, s, range_dev, st);
+    enqueue_range(pos, sh, opacity, n, grid_bits, quantiser, !identity, L, s, range_dev, st);
     if (identity) {
         GSBC_LAUNCH("iota", k_iota, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, perm, n);
     } else {
-        enqueue_keys_and_sort<false>(pos, sh, opacity, n, grid_bits, 0.0f, L, s, range_dev, nullptr, perm, st);
+        enqueue_keys_and_sort<false>(pos, sh, opacity, n, grid_bits, 0.0f, quantiser != 1, L, s, range_dev, nullptr,
+                                     perm, st);
     }
     const uint64_t npad = (n + 15) / 16 * 16;
     GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0, st,
@@ -891,9 +935,10 @@ hipError_t launch_degree_sort(const float *pos, const float *sh, const float *op
 {
     Layout L = layout(n);
     char *s = static_cast<char *>(scratch);
-    enqueue_range(pos, sh, opacity, n, grid_bits, quantiser, L, s, range_dev, st);
+    enqueue_range(pos, sh, opacity, n, grid_bits, quantiser, true, L, s, range_dev, st);
     GSBC_LAUNCH("fill_count", k_zero4, dim3(1), dim3(64), 0, st, class_count);
-    enqueue_keys_and_sort<true>(pos, sh, opacity, n, grid_bits, tau, L, s, range_dev, class_count, perm, st);
+    enqueue_keys_and_sort<true>(pos, sh, opacity, n, grid_bits, tau, quantiser != 1, L, s, range_dev, class_count,
+                                perm, st);
     return hipGetLastError();
 }
 

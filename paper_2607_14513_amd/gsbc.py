@@ -21,7 +21,7 @@ N_STREAMS = {ARR_BANDS: 16, ARR_PRIM: 1, ARR_QUAD: 4}
 
 EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_reserve", "gsbc_arena_info",
             "gsbc_default_params",
-            "gsbc_query_sizes", "gsbc_reorder", "gsbc_reorder_degrees", "gsbc_encode", "gsbc_default_batch_tuning",
+            "gsbc_query_sizes", "gsbc_reorder", "gsbc_reorder_desc", "gsbc_reorder_degrees", "gsbc_encode", "gsbc_default_batch_tuning",
             "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_decode_eval_noalloc", "gsbc_decode_eval_view", "gsbc_blend_tiles",
             "gsbc_save", "gsbc_load",
             "gsbc_profile_enable", "gsbc_profile_read")
@@ -94,6 +94,7 @@ def load():
         lib.gsbc_default_params.restype = None
         lib.gsbc_query_sizes.argtypes = [u64, u32, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u64)]
         lib.gsbc_reorder.argtypes = [P, P, P, P, u64, ctypes.POINTER(Params), P, P, ctypes.POINTER(StreamDesc)]
+        lib.gsbc_reorder_desc.argtypes = [P, ctypes.POINTER(StreamDesc)]
         lib.gsbc_reorder_degrees.argtypes = [P, P, P, P, u64, ctypes.c_float, ctypes.POINTER(Params), P, P, u64,
                                              ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(StreamDesc)]
         lib.gsbc_encode.argtypes = [P, P, ctypes.POINTER(StreamDesc), ctypes.c_int, ctypes.c_double,
@@ -278,9 +279,10 @@ class Context:
         return out
 
     # ------------------------------------------------------------- calls
-    def reorder(self, pos, sh, params=None, out=None, opacity=None):
+    def reorder(self, pos, sh, params=None, out=None, opacity=None, want_desc=True):
         """pos float32[n][3], sh float32[n][16][3], opacity float32[n] or None
-        on the device -> (perm uint32-as-int32[n], textures uint8[16][nblk][16][4], desc)."""
+        on the device -> (perm uint32-as-int32[n], textures uint8[16][nblk][16][4], desc).
+        want_desc False: only enqueue (no wait; desc None, see reorder_desc)."""
         _check(pos, torch.float32, "pos")
         n = pos.shape[0] if pos.dim() == 2 else -1
         _check(pos, torch.float32, "pos", shape=(n, 3))
@@ -298,11 +300,17 @@ class Context:
             _check(perm, torch.int32, "perm", shape=(n,))
             _check(tex, torch.uint8, "textures", min_numel=npad * 64)
         _on_device(("pos", pos), ("sh", sh), ("opacity", opacity), ("perm", perm), ("textures", tex))
-        desc = StreamDesc()
+        desc = StreamDesc() if want_desc else None
         self._check(load().gsbc_reorder(self._h, _ptr(pos), _ptr(sh),
                                         _ptr(opacity) if opacity is not None else None, n, ctypes.byref(p), _ptr(perm),
-                                        _ptr(tex), ctypes.byref(desc)))
+                                        _ptr(tex), ctypes.byref(desc) if want_desc else None))
         return perm, tex, desc
+
+    def reorder_desc(self):
+        """The desc of the last reorder (waits for the stream)."""
+        desc = StreamDesc()
+        self._check(load().gsbc_reorder_desc(self._h, ctypes.byref(desc)))
+        return desc
 
     def reorder_degrees(self, pos, sh, tau=0.0, params=None, opacity=None):
         """Degree classes (variable number of bands).  Returns (perm int32[n],

@@ -714,3 +714,48 @@ def test_injected_scratch_allocation_failure():
     from paper_2607_14513_amd import gsbc
     assert f"STATUS {gsbc.E_NOMEM}" in r.stdout, r.stdout
     assert "RECOVERED 1000" in r.stdout, r.stdout
+
+
+@pytest.mark.parametrize("n,seed", [(17, 41), (70_001, 42)])
+def test_reorder_async_desc(G, n, seed):
+    """desc None: the reorder is only enqueued; reorder_desc fills the same
+    desc afterwards.  Ranges stay right over a run of calls whose range
+    record is finished by different launches (key pass, identity order,
+    coverage range, degree classes)."""
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(n, seed=seed)
+    rperm, rtex, rvmin, rvmax = O.reorder(pos, sh)
+    pd, sd = dev(pos), dev(sh)
+    say("reorder async", n)
+    perm, tex, d = ctx.reorder(pd, sd, want_desc=False)
+    assert d is None
+    d = ctx.reorder_desc()
+    assert np.array_equal(d.ranges()[0].view(np.uint32), rvmin.view(np.uint32))
+    assert np.array_equal(d.ranges()[1].view(np.uint32), rvmax.view(np.uint32))
+    assert np.array_equal(host(perm).view(np.uint32), rperm)
+    assert np.array_equal(host(tex), rtex)
+    assert d.n_prims == n and d.n_pad == (n + 15) // 16 * 16
+    # other calls in between, then the same scene again
+    pos2, sh2 = synth.make_scene(999, seed=seed + 100)
+    ctx.reorder(dev(pos2), dev(sh2), params=gsbc.default_params(order=1))
+    ctx.reorder(dev(pos2), dev(sh2), params=gsbc.default_params(quantiser=1))
+    ctx.reorder_degrees(dev(pos2), dev(sh2))
+    with pytest.raises(gsbc.GsbcError) as e:
+        ctx.reorder_desc()                  # the degree classes took the range record
+    assert e.value.status == gsbc.E_ARG
+    perm, tex, d = ctx.reorder(pd, sd)
+    assert np.array_equal(d.ranges()[0].view(np.uint32), rvmin.view(np.uint32))
+    assert np.array_equal(d.ranges()[1].view(np.uint32), rvmax.view(np.uint32))
+    assert np.array_equal(host(perm).view(np.uint32), rperm)
+    assert np.array_equal(host(tex), rtex)
+
+
+def test_reorder_desc_needs_a_reorder(G):
+    gsbc, _ = G
+    ctx = gsbc.Context(0)
+    try:
+        with pytest.raises(gsbc.GsbcError) as e:
+            ctx.reorder_desc()
+        assert e.value.status == gsbc.E_ARG
+    finally:
+        ctx.close()
