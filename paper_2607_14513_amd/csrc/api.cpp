@@ -458,11 +458,14 @@ gsbc_status gsbc_arena_info(const gsbc_ctx *ctx, uint64_t *bytes, uint64_t *grow
 namespace {
 
 // Wait for the stream, then desc from the range record of the last
-// gsbc_reorder and its n and params.
-gsbc_status read_reorder_desc(gsbc_ctx *ctx, gsbc_stream_desc *desc)
+// gsbc_reorder and its n and params (staged: that call's last kernel has
+// already copied the record to the pinned block).
+gsbc_status read_reorder_desc(gsbc_ctx *ctx, gsbc_stream_desc *desc, bool staged)
 {
     const RangeRec *range = reinterpret_cast<const RangeRec *>(small_ptr(ctx, kRangeOff));
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, range, sizeof(RangeRec), hipMemcpyDeviceToHost, ctx->stream), "range read-back");
+    if (!staged)
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->pinned, range, sizeof(RangeRec), hipMemcpyDeviceToHost, ctx->stream),
+                "range read-back");
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream), "reorder");
     const RangeRec *r = static_cast<const RangeRec *>(ctx->pinned);
     const gsbc_params &p = ctx->last_p;
@@ -499,13 +502,16 @@ gsbc_status gsbc_reorder(gsbc_ctx *ctx, const float *pos, const float *sh, const
     if ((s = ensure_arena(ctx, reorder_scratch_bytes(n, p.grid_bits)))) return s;
     RangeRec *range = reinterpret_cast<RangeRec *>(small_ptr(ctx, kRangeOff));
     ctx->reordered = false;
+    // with a desc, the last kernel also writes the range record to the pinned
+    // staging block, so only a wait is left
     HIP_TRY(ctx, launch_reorder(pos, sh, opacity, n, p.grid_bits, p.quantiser, p.order == 1, p.arrangement, perm,
-                                 textures, ctx->arena, range, ctx->stream),
+                                 textures, ctx->arena, range, desc ? static_cast<RangeRec *>(ctx->pinned) : nullptr,
+                                 ctx->stream),
             "reorder launch");
     ctx->reordered = true;
     ctx->last_n = n;
     ctx->last_p = p;
-    return desc ? read_reorder_desc(ctx, desc) : GSBC_OK;
+    return desc ? read_reorder_desc(ctx, desc, true) : GSBC_OK;
 }
 
 gsbc_status gsbc_reorder_desc(gsbc_ctx *ctx, gsbc_stream_desc *desc)
@@ -515,7 +521,7 @@ gsbc_status gsbc_reorder_desc(gsbc_ctx *ctx, gsbc_stream_desc *desc)
     ActiveGuard guard(ctx);
     if (!desc) return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
     if (!ctx->reordered) return fail(ctx, GSBC_E_ARG, "no gsbc_reorder on this context since the last range use");
-    return read_reorder_desc(ctx, desc);
+    return read_reorder_desc(ctx, desc, false);
 }
 
 gsbc_status gsbc_reorder_degrees(gsbc_ctx *ctx, const float *pos, const float *sh, const float *opacity, uint64_t n,

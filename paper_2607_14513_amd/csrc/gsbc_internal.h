@@ -94,7 +94,7 @@ size_t reorder_scratch_bytes(uint64_t n, uint32_t grid_bits);
 // per block, 2 four primitives per four blocks).
 hipError_t launch_reorder(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
                           uint32_t quantiser, bool identity, uint32_t arrangement, uint32_t *perm, uint8_t *textures,
-                          void *scratch, RangeRec *range_dev, hipStream_t st);
+                          void *scratch, RangeRec *range_dev, RangeRec *host_range, hipStream_t st);
 
 // Variable number of bands: class L (SH degree L, (L+1)^2 bands) owns dense
 // slots [slot_start[L], slot_start[L+1]) of perm and padded slots

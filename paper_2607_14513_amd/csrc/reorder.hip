@@ -608,10 +608,16 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *kin, const ui
 // One thread per slot s < npad: quantise its 16 band vectors and place them
 // by the arrangement (0: stream k, block s/16, texel zigzag(s%16); 1: block
 // s, texel k; 2: stream k/4, block s/4, texel 4 (s%4) + k%4).
+// host_range (host memory the device can write, or null): workgroup 0 also
+// copies the range record there, so a caller waiting for the stream needs
+// no separate read-back.
 __global__ __launch_bounds__(256) void k_gather_pack(const float *sh, const float *opacity, const uint32_t *perm,
                                                      uint64_t n, uint64_t npad, uint32_t arrangement,
-                                                     const RangeRec *r, uint32_t *tex)
+                                                     const RangeRec *r, uint32_t *tex, RangeRec *host_range)
 {
+    static_assert(sizeof(RangeRec) % 4 == 0 && sizeof(RangeRec) / 4 <= 256, "one word per thread");
+    if (host_range && blockIdx.x == 0 && threadIdx.x < sizeof(RangeRec) / 4)
+        reinterpret_cast<uint32_t *>(host_range)[threadIdx.x] = reinterpret_cast<const uint32_t *>(r)[threadIdx.x];
     uint64_t s = (uint64_t)xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (s >= npad) return;
     uint32_t src = perm[s < n ? s : n - 1];
@@ -912,7 +918,7 @@ void enqueue_keys_and_sort(const float *pos, const float *sh, const float *opaci
 
 hipError_t launch_reorder(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
                           uint32_t quantiser, bool identity, uint32_t arrangement, uint32_t *perm, uint8_t *textures,
-                          void *scratch, RangeRec *range_dev, hipStream_t st)
+                          void *scratch, RangeRec *range_dev, RangeRec *host_range, hipStream_t st)
 {
     Layout L = layout(n);
     char *s = static_cast<char *>(scratch);
@@ -925,7 +931,8 @@ hipError_t launch_reorder(const float *pos, const float *sh, const float *opacit
     }
     const uint64_t npad = (n + 15) / 16 * 16;
     GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0, st,
-                       sh, opacity, perm, n, npad, arrangement, range_dev, reinterpret_cast<uint32_t *>(textures));
+                       sh, opacity, perm, n, npad, arrangement, range_dev, reinterpret_cast<uint32_t *>(textures),
+                       host_range);
     return hipGetLastError();
 }
 
