@@ -501,7 +501,17 @@ def main():
                           # weights and transmittance 4, colour 3); tiles stop at T = 0 exactly,
                           # so this counts listed pairs, not executed ones
                           "alu_frac_listed_pairs": round(18 * 256 * entries / bl_s / VALU_PEAK, 4)}
-            del pos3d, p3, img3, tr3, lst3d, ts3d, foot3d, mu3d
+            # the two-pass form: every primitive's colour decoded once (the
+            # view decode), then the blend reads those colours (bit-identical)
+            cols3 = ctx.decode_eval_view(b3, dd2, pos3d, p3, view)
+            ctx.blend_tiles_colours(cols3, p3, mu3d, foot3d, ts3d, lst3d, 120, 68, image=img3, transmittance=tr3)
+            t_bl2 = kernel_ms(ctx, ("decode_eval_view", "tile_order", "blend_tiles"),
+                              lambda: (ctx.decode_eval_view(b3, dd2, pos3d, p3, view, out=cols3),
+                                       ctx.blend_tiles_colours(cols3, p3, mu3d, foot3d, ts3d, lst3d, 120, 68,
+                                                               image=img3, transmittance=tr3)), 3)
+            colour_leg["two_pass"] = {"ms": med_min(t_bl2), "view_decode_included": True,
+                                      "gentries_s": round(entries / (float(np.median(t_bl2)) * 1e-3) / 1e9, 3)}
+            del pos3d, p3, img3, tr3, lst3d, ts3d, foot3d, mu3d, cols3
             # context: a plain device fill of the same output (write ceiling)
             tf = []
             for i in range(3):

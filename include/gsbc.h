@@ -425,6 +425,24 @@ GSBC_API gsbc_status gsbc_blend_tiles(gsbc_ctx *ctx, const uint8_t *blocks, cons
                                       uint64_t list_len, uint32_t tiles_x, uint32_t tiles_y, float *image,
                                       float *transmittance);
 
+/* The same colour stage with each primitive's colour computed beforehand,
+ * once per primitive, instead of decoded from the bitstreams for every list
+ * entry (a primitive sits in several tiles' lists): the two-pass form of
+ * Sec. II eq. preblend.  With colours from gsbc_decode_eval_view over all
+ * slots (prim_idx NULL) for the same blocks, desc, pos, perm and view, the
+ * image and transmittance equal gsbc_blend_tiles' bit for bit.
+ *   colours          device float[n_prims][3], slot s's colour ctilde
+ *   n_prims          1 .. 2^31-1, the slots of the scene (list ids >= n_prims
+ *                    give NaN)
+ *   perm, opacity, footprint, tile_start, list, list_len, tiles_x, tiles_y,
+ *   image, transmittance   as gsbc_blend_tiles
+ * GSBC_E_ARG for NULL pointers, misaligned arrays, n_prims out of range, an
+ * empty image or more than 2^31 tiles. */
+GSBC_API gsbc_status gsbc_blend_tiles_colours(gsbc_ctx *ctx, const float *colours, uint64_t n_prims,
+                                              const uint32_t *perm, const float *opacity, const float *footprint,
+                                              const uint32_t *tile_start, const uint32_t *list, uint64_t list_len,
+                                              uint32_t tiles_x, uint32_t tiles_y, float *image, float *transmittance);
+
 /* ---------------------------------------------------------------- container */
 
 /* The durable form of a coded scene: fixed-size blocks in one bitstream per

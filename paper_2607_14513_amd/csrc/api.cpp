@@ -1170,7 +1170,33 @@ gsbc_status gsbc_blend_tiles(gsbc_ctx *ctx, const uint8_t *blocks, const gsbc_st
     if (!(isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2]))) return fail(ctx, GSBC_E_ARG, "view position not finite");
     if ((s = ensure_arena(ctx, tiles * sizeof(uint32_t)))) return s;   // the tile schedule
     HIP_TRY(ctx, launch_blend_tiles(blocks, band_args(desc), desc->n_prims, pos, perm, f, opacity, footprint, tile_start,
-                                    list, list_len, tiles_x, tiles_y, image, transmittance,
+                                    list, list_len, tiles_x, tiles_y, nullptr, image, transmittance,
+                                    static_cast<uint32_t *>(ctx->arena), ctx->stream),
+            "blend_tiles launch");
+    return GSBC_OK;
+}
+
+gsbc_status gsbc_blend_tiles_colours(gsbc_ctx *ctx, const float *colours, uint64_t n_prims, const uint32_t *perm,
+                                     const float *opacity, const float *footprint, const uint32_t *tile_start,
+                                     const uint32_t *list, uint64_t list_len, uint32_t tiles_x, uint32_t tiles_y,
+                                     float *image, float *transmittance)
+{
+    gsbc_status s = begin(ctx);
+    if (s) return s;
+    ActiveGuard guard(ctx);
+    if (!colours || !perm || !opacity || !footprint || !tile_start || !image || (!list && list_len))
+        return fail(ctx, GSBC_E_ARG, "NULL pointer argument");
+    for (const void *q : {(const void *)colours, (const void *)perm, (const void *)opacity, (const void *)footprint,
+                          (const void *)tile_start, (const void *)list, (const void *)image, (const void *)transmittance})
+        if (reinterpret_cast<uintptr_t>(q) & 3) return fail(ctx, GSBC_E_ARG, "device arrays must be 4-byte aligned");
+    if (n_prims == 0 || n_prims > 0x7FFFFFFFull)
+        return fail(ctx, GSBC_E_ARG, "n_prims = %llu not in 1..2^31-1", (unsigned long long)n_prims);
+    const uint64_t tiles = (uint64_t)tiles_x * tiles_y;
+    if (tiles == 0 || tiles > 0x7FFFFFFFull) return fail(ctx, GSBC_E_ARG, "%u x %u tiles", tiles_x, tiles_y);
+    if ((s = ensure_arena(ctx, tiles * sizeof(uint32_t)))) return s;   // the tile schedule
+    const float f[3] = {0.0f, 0.0f, 0.0f};   // unused: the colours are given
+    HIP_TRY(ctx, launch_blend_tiles(nullptr, BandArgs{}, n_prims, nullptr, perm, f, opacity, footprint, tile_start,
+                                    list, list_len, tiles_x, tiles_y, colours, image, transmittance,
                                     static_cast<uint32_t *>(ctx->arena), ctx->stream),
             "blend_tiles launch");
     return GSBC_OK;

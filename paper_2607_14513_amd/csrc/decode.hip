@@ -517,7 +517,7 @@ __global__ __launch_bounds__(256) void k_blend_tiles(const uint8_t *blocks, Band
                                                      float fz, const float *mu, const float *foot,
                                                      const uint32_t *tile_start, const uint32_t *list,
                                                      uint64_t list_len, const uint32_t *order, uint32_t tiles_x,
-                                                     float *image, float *trans)
+                                                     const float *colours, float *image, float *trans)
 {
     __shared__ float s_par[256][9];   // mean x, mean y, A, B, C, mu, colour r, g, b
     const uint32_t t = threadIdx.x, tile = order[blockIdx.x];
@@ -534,7 +534,13 @@ __global__ __launch_bounds__(256) void k_blend_tiles(const uint8_t *blocks, Band
             float c[3] = {__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
             uint64_t i = 0;
             if (s < n_prims) {
-                view_colour(blocks, b, s, pos, perm, fx, fy, fz, c);
+                if (colours) {   // the colour computed beforehand, once per primitive
+                    c[0] = colours[3 * (uint64_t)s];
+                    c[1] = colours[3 * (uint64_t)s + 1];
+                    c[2] = colours[3 * (uint64_t)s + 2];
+                } else {
+                    view_colour(blocks, b, s, pos, perm, fx, fy, fz, c);
+                }
                 i = perm[s];
             }
             s_par[t][0] = foot[5 * i];
@@ -578,13 +584,14 @@ __global__ __launch_bounds__(256) void k_blend_tiles(const uint8_t *blocks, Band
 hipError_t launch_blend_tiles(const uint8_t *blocks, const BandArgs &b, uint64_t n_prims, const float *pos,
                               const uint32_t *perm, const float view[3], const float *mu, const float *foot,
                               const uint32_t *tile_start, const uint32_t *list, uint64_t list_len, uint32_t tiles_x,
-                              uint32_t tiles_y, float *image, float *trans, uint32_t *order, hipStream_t st)
+                              uint32_t tiles_y, const float *colours, float *image, float *trans, uint32_t *order,
+                              hipStream_t st)
 {
     const uint64_t tiles = (uint64_t)tiles_x * tiles_y;
     if (tiles == 0) return hipSuccess;
     GSBC_LAUNCH("tile_order", k_tile_order, dim3(1), dim3(1024), 0, st, tile_start, list_len, (uint32_t)tiles, order);
     GSBC_LAUNCH("blend_tiles", k_blend_tiles, dim3((uint32_t)tiles), dim3(256), 0, st, blocks, b, n_prims, pos, perm,
-                view[0], view[1], view[2], mu, foot, tile_start, list, list_len, order, tiles_x, image, trans);
+                view[0], view[1], view[2], mu, foot, tile_start, list, list_len, order, tiles_x, colours, image, trans);
     return hipGetLastError();
 }
 

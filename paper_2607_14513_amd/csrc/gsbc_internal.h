@@ -224,7 +224,8 @@ float *static_scratch(int device);
 hipError_t launch_blend_tiles(const uint8_t *blocks, const BandArgs &b, uint64_t n_prims, const float *pos,
                               const uint32_t *perm, const float view[3], const float *mu, const float *foot,
                               const uint32_t *tile_start, const uint32_t *list, uint64_t list_len, uint32_t tiles_x,
-                              uint32_t tiles_y, float *image, float *trans, uint32_t *order, hipStream_t st);
+                              uint32_t tiles_y, const float *colours, float *image, float *trans, uint32_t *order,
+                              hipStream_t st);
 hipError_t launch_decode_eval_view(const uint8_t *blocks, const BandArgs &b, uint64_t n_prims, const float *pos,
                                    const uint32_t *perm, const float view[3], const uint32_t *prim_idx, uint64_t m,
                                    float *out, hipStream_t st);

@@ -22,7 +22,7 @@ N_STREAMS = {ARR_BANDS: 16, ARR_PRIM: 1, ARR_QUAD: 4}
 EXPORTED = ("gsbc_create", "gsbc_destroy", "gsbc_last_error", "gsbc_sync", "gsbc_reserve", "gsbc_arena_info",
             "gsbc_default_params",
             "gsbc_query_sizes", "gsbc_reorder", "gsbc_reorder_desc", "gsbc_reorder_degrees", "gsbc_encode", "gsbc_default_batch_tuning",
-            "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_decode_eval_noalloc", "gsbc_decode_eval_view", "gsbc_blend_tiles",
+            "gsbc_encode_batch", "gsbc_decode", "gsbc_decode_eval", "gsbc_decode_eval_noalloc", "gsbc_decode_eval_view", "gsbc_blend_tiles", "gsbc_blend_tiles_colours",
             "gsbc_save", "gsbc_load",
             "gsbc_profile_enable", "gsbc_profile_read")
 
@@ -108,6 +108,7 @@ def load():
         lib.gsbc_decode_eval_noalloc.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, u32, P, u64, P]
         lib.gsbc_decode_eval_view.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, P, P, P, u64, P]
         lib.gsbc_blend_tiles.argtypes = [P, P, ctypes.POINTER(StreamDesc), P, P, P, P, P, P, P, u64, u32, u32, P, P]
+        lib.gsbc_blend_tiles_colours.argtypes = [P, P, u64, P, P, P, P, P, u64, u32, u32, P, P]
         lib.gsbc_save.argtypes = [P, P, ctypes.POINTER(StreamDesc), ctypes.c_char_p]
         lib.gsbc_load.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(StreamDesc), P, u64]
         lib.gsbc_profile_enable.argtypes = [P, ctypes.c_int]
@@ -450,6 +451,38 @@ class Context:
         self._check(load().gsbc_blend_tiles(self._h, _ptr(blocks), ctypes.byref(desc), _ptr(pos), _ptr(perm), f,
                                             _ptr(opacity), _ptr(footprint), _ptr(tile_start), _ptr(lst), lst.numel(),
                                             int(tiles_x), int(tiles_y), _ptr(image), _ptr(transmittance)))
+        return image, transmittance
+
+    def blend_tiles_colours(self, colours, perm, opacity, footprint, tile_start, lst, tiles_x, tiles_y,
+                            image=None, transmittance=None, want_transmittance=True):
+        """The colour stage with the colours computed beforehand (colours
+        float32[n_prims][3] per slot, e.g. decode_eval_view over all slots);
+        other arguments and the result as blend_tiles."""
+        _check(colours, torch.float32, "colours")
+        if colours.dim() != 2 or colours.shape[1] != 3:
+            raise ValueError(f"colours has shape {tuple(colours.shape)}, expected (n_prims, 3)")
+        n = colours.shape[0]
+        _check(perm, torch.int32, "perm", shape=(n,))
+        _check(opacity, torch.float32, "opacity")
+        N = opacity.shape[0] if opacity.dim() == 1 else -1
+        _check(opacity, torch.float32, "opacity", shape=(N,))
+        _check(footprint, torch.float32, "footprint", shape=(N, 5))
+        tiles = int(tiles_x) * int(tiles_y)
+        _check(tile_start, torch.int32, "tile_start", shape=(tiles + 1,))
+        _check(lst, torch.int32, "lst")
+        H, W = 16 * int(tiles_y), 16 * int(tiles_x)
+        if image is None:
+            image = torch.empty((H, W, 3), dtype=torch.float32, device=self.device)
+        _check(image, torch.float32, "image", shape=(H, W, 3))
+        if transmittance is None and want_transmittance:
+            transmittance = torch.empty((H, W), dtype=torch.float32, device=self.device)
+        if transmittance is not None:
+            _check(transmittance, torch.float32, "transmittance", shape=(H, W))
+        _on_device(("colours", colours), ("perm", perm), ("opacity", opacity), ("footprint", footprint),
+                   ("tile_start", tile_start), ("lst", lst), ("image", image), ("transmittance", transmittance))
+        self._check(load().gsbc_blend_tiles_colours(self._h, _ptr(colours), n, _ptr(perm), _ptr(opacity),
+                                                    _ptr(footprint), _ptr(tile_start), _ptr(lst), lst.numel(),
+                                                    int(tiles_x), int(tiles_y), _ptr(image), _ptr(transmittance)))
         return image, transmittance
 
     def save(self, path, blocks, desc):

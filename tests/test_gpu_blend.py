@@ -121,3 +121,34 @@ def test_blend_tiles_edges(G):
         ctx.blend_tiles(blocks, d2, dev(pos), perm, (0.0, float("inf"), 0.0), dev(mu), dev(foot),
                         dev(ts.astype(np.int32)), dev(lst.astype(np.int32)), 2, 2)
     assert e.value.status == gsbc.E_ARG
+
+
+@pytest.mark.parametrize("n,tiles,seed", [(3000, (8, 6), 3), (20_011, (20, 15), 4)])
+def test_blend_tiles_colours_equals_fused(G, n, tiles, seed):
+    """The two-pass form (view decode of every slot, then the blend reading
+    those colours) gives the fused stage's image and transmittance bit for
+    bit, and so the same oracle bound; ids past the scene still give NaN."""
+    gsbc, ctx = G
+    tx, ty = tiles
+    pos, sh = synth.make_scene(n, seed=seed)
+    mu = synth.make_opacity(n, seed=seed)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh), opacity=dev(mu))
+    blocks, d2, _ = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO, rate=6.0)
+    foot, ts, lst = synth.make_tiles(pos, VIEW, tx, ty, seed=seed)
+    gslot = np.argsort(host(perm).view(np.uint32)).astype(np.int32)
+    say("blend two-pass", n, tiles, int(ts[-1]), "entries")
+    pd, md, fd, tsd, ld = dev(pos), dev(mu), dev(foot), dev(ts.astype(np.int32)), dev(gslot[lst])
+    img, T = ctx.blend_tiles(blocks, d2, pd, perm, VIEW, md, fd, tsd, ld, tx, ty)
+    cols = ctx.decode_eval_view(blocks, d2, pd, perm, VIEW)
+    img2, T2 = ctx.blend_tiles_colours(cols, perm, md, fd, tsd, ld, tx, ty)
+    assert np.array_equal(host(img).view(np.uint32), host(img2).view(np.uint32))
+    assert np.array_equal(host(T).view(np.uint32), host(T2).view(np.uint32))
+    bad = gslot[lst].copy()
+    bad[0] = n + 3                                            # first entry of the first non-empty tile
+    img3, _ = ctx.blend_tiles_colours(cols, perm, md, fd, tsd, dev(bad), tx, ty, want_transmittance=False)
+    img3 = host(img3)
+    t0 = int(np.searchsorted(ts, 0, side="right")) - 1        # the tile holding entry 0
+    yy, xx = divmod(t0, tx)
+    assert np.isnan(img3[16 * yy:16 * yy + 16, 16 * xx:16 * xx + 16]).all()
+    with pytest.raises(ValueError):
+        ctx.blend_tiles_colours(cols[:, :2].contiguous(), perm, md, fd, tsd, ld, tx, ty)
