@@ -31,7 +31,7 @@ constexpr int kMaxBins = 1 << kMaxDigitBits;
 constexpr int kMaxPasses = 7;                  // 56-bit keys (grid 10 bits, degree class) in 9-bit digits
 constexpr int kRangeBlock = 384;               // coverage histogram block: a multiple of 12 and 3
 constexpr int kMinMaxBlock = 768;              // min/max pass block (measured faster than 384 or 192)
-static_assert(kRangeBlock % 12 == 0 && kMinMaxBlock % 12 == 0, "a block-size run of float4 chunks must hold whole primitives");
+static_assert(kRangeBlock % 12 == 0, "a block-size run of float4 chunks must hold whole primitives");
 
 // Digits of each pass, low to high: ceil(bits / 9) passes of near-equal width.
 struct SortPlan {
