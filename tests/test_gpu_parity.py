@@ -77,7 +77,8 @@ def test_decode_random_blocks(G, fmt):
 
 
 # ---------------------------------------------------------------- reorder
-@pytest.mark.parametrize("n,seed", [(1, 3), (15, 4), (17, 5), (1007, 6), (65_536, 1)])
+@pytest.mark.parametrize("n,seed", [(1, 3), (15, 4), (17, 5), (1007, 6), (4096, 7), (4097, 8), (8191, 9),
+                                    (65_536, 1)])
 def test_reorder_bit_exact(G, n, seed):
     gsbc, ctx = G
     pos, sh = synth.make_scene(n, seed=seed)
@@ -98,6 +99,19 @@ def test_reorder_grid_bits(G, g):
     pos, sh = synth.make_scene(5000, seed=20 + g)
     perm, tex, d = ctx.reorder(dev(pos), dev(sh), params=gsbc.default_params(grid_bits=g))
     rperm, rtex, _, _ = O.reorder(pos, sh, grid_bits=g)
+    assert np.array_equal(host(perm).view(np.uint32), rperm)
+    assert np.array_equal(host(tex), rtex)
+
+
+@pytest.mark.parametrize("n", [1024, 1025])
+def test_reorder_packed_word_boundary(G, n):
+    """At grid_bits 10 the key has 54 bits: up to 1,024 primitives the index
+    rides in the key word (10 bits), from 1,025 it needs 11 and the sort
+    carries separate values; both orders equal the oracle's."""
+    gsbc, ctx = G
+    pos, sh = synth.make_scene(n, seed=n)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh), params=gsbc.default_params(grid_bits=10))
+    rperm, rtex, _, _ = O.reorder(pos, sh, grid_bits=10)
     assert np.array_equal(host(perm).view(np.uint32), rperm)
     assert np.array_equal(host(tex), rtex)
 
