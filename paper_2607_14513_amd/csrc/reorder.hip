@@ -92,8 +92,9 @@ constexpr int kAccWords = 38;
 __device__ __forceinline__ bool acc_is_min(int i) { return i < 16 || (i >= 32 && i < 35); }
 
 // dc: each primitive's band-0 colour (times its opacity), three floats,
-// for the key pass.  Workgroup 0 also clears the sort's digit totals.  Every wave streams one contiguous run of primitives
-// (a multiple of kStepPrims = 32), a step at a time: the step's 384 float4
+// for the key pass.  Workgroup 0 also clears the sort's digit totals.
+// Every wave streams one contiguous run of primitives (a multiple of
+// kStepPrims = 32), a step at a time: the step's 384 float4
 // chunks (six loads per lane) and 96 position floats (two), all in flight
 // together, with no workgroup barrier.  Chunk u * 64 + lane of a step sits
 // at place (lane + 4u) mod 12 of its primitive, one of three places per
