@@ -102,15 +102,21 @@ __device__ __forceinline__ bool acc_is_min(int i) { return i < 16 || (i >= 32 &&
 // position float x of a step is on axis x mod 3.  The step's band-0 colours
 // go through the wave's own LDS and leave as two contiguous stores, issued
 // before the next step's loads (so waiting on those never waits on a newer
-// store).
+// store).  DEG: also deg, each primitive's degree class: the
+// largest SH degree l in 1..3 with a coefficient (after the opacity) above
+// tau in magnitude in a band of degree l, else 0; per chunk a 3-bit mask of
+// the degrees it shows, combined per primitive through the same LDS.
 constexpr uint32_t kStepPrims = 32, kStepChunks = kStepPrims * 12, kStepLoads = kStepChunks / 64;
 static_assert(kStepChunks % 64 == 0 && kMinMaxBlock % 64 == 0, "whole loads per lane and step");
+template <bool DEG>
 __global__ __launch_bounds__(kMinMaxBlock) void k_range_partial(const float4 *sh4, const float *opacity,
                                                                 const float *pos, uint64_t n, uint32_t *acc,
-                                                                float *dc, uint32_t *meta, uint32_t meta_words)
+                                                                float *dc, uint32_t *meta, uint32_t meta_words,
+                                                                float tau, uint8_t *deg)
 {
     __shared__ uint32_t s_acc[kAccWords];
     __shared__ float stage[kMinMaxBlock / 64][kStepPrims * 3];
+    __shared__ uint8_t s_deg[DEG ? kMinMaxBlock / 64 : 1][kStepChunks];   // degree masks of the step's chunks
     const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     if (tid < kAccWords) s_acc[tid] = acc_is_min((int)tid) ? 0xFFFFFFFFu : 0u;
     if (blockIdx.x == 0)   // the sort's digit totals, for the key pass that follows
@@ -140,6 +146,27 @@ __global__ __launch_bounds__(kMinMaxBlock) void k_range_partial(const float4 *sh
         pmx[k] = fmaxf(pmx[k], a);
     };
     float *st = stage[wv];
+    uint8_t *sd = s_deg[DEG ? wv : 0];
+    // degrees (bits l - 1) shown by chunk place j's four floats 4j..4j+3
+    auto degree_mask = [&](const float4 &v, int j) {
+        const float f[4] = {v.x, v.y, v.z, v.w};
+        uint32_t m = 0;
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const int band = (4 * j + c) / 3, l = band >= 9 ? 3 : band >= 4 ? 2 : band >= 1 ? 1 : 0;
+            if (l && fabsf(f[c]) > tau) m |= 1u << (l - 1);
+        }
+        return m;
+    };
+    // lanes m < count: the class of the step's primitive m from its 12 chunks' masks
+    auto store_degrees = [&](uint64_t prim0, uint32_t count) {
+        if (lane < count) {
+            uint32_t m = 0;
+#pragma unroll
+            for (int i = 0; i < 12; i++) m |= sd[12 * lane + i];
+            deg[prim0 + lane] = (uint8_t)(m ? 32 - __clz(m) : 0);
+        }
+    };
     {
         const uint64_t nq = n * 12;
         const uint64_t span = ((nq + waves - 1) / waves + kStepChunks - 1) / kStepChunks * kStepChunks;
@@ -159,6 +186,7 @@ __global__ __launch_bounds__(kMinMaxBlock) void k_range_partial(const float4 *sh
             for (int u = 0; u < (int)kStepLoads; u++) {
                 take(v[u], u % 3, q + u * 64 + lane);
                 const uint32_t c = u * 64 + lane;   // chunk within the step
+                if (DEG) sd[c] = (uint8_t)degree_mask(v[u], (int)((lane + 4 * (u % 3)) % 12));
                 if (c % 12 == 0) {
                     st[c / 12 * 3] = v[u].x;
                     st[c / 12 * 3 + 1] = v[u].y;
@@ -168,6 +196,7 @@ __global__ __launch_bounds__(kMinMaxBlock) void k_range_partial(const float4 *sh
             float *o = dc + q / 12 * 3;   // the step's 32 colours: 96 contiguous floats
             o[lane] = st[lane];
             if (lane < kStepPrims * 3 - 64) o[64 + lane] = st[64 + lane];
+            if (DEG) store_degrees(q / 12, kStepPrims);
         }
         // the rest of the run, less than one step
         const uint32_t rest = (uint32_t)(q1 > q ? (q1 - q) / 12 : 0);   // primitives
@@ -180,6 +209,7 @@ __global__ __launch_bounds__(kMinMaxBlock) void k_range_partial(const float4 *sh
             if (qq < q1) {
                 float4 v = sh4[qq];
                 take(v, u % 3, qq);
+                if (DEG) sd[u * 64 + lane] = (uint8_t)degree_mask(v, (int)((lane + 4 * (u % 3)) % 12));
                 if ((u * 64 + lane) % 12 == 0) {
                     float *o = dc + qq / 12 * 3;
                     o[0] = v.x;
@@ -188,6 +218,7 @@ __global__ __launch_bounds__(kMinMaxBlock) void k_range_partial(const float4 *sh
                 }
             }
         }
+        if (DEG) store_degrees(q / 12, rest);
     }
     // fold: place j = (lane + 4k) mod 12 holds floats 4j..4j+3 (bands (4j+c)/3)
 #pragma unroll
@@ -273,9 +304,9 @@ __global__ __launch_bounds__(64) void k_range_final(const uint32_t *cov, uint32_
 }
 
 // Keys, 4,096 per workgroup: (Morton cell << 24) | colour interleave, and
-// the digit counts of every sort pass.  DEG: also the degree class (the
-// largest SH degree with a coefficient above tau in magnitude, 0 if none)
-// above the cell and colour fields, and the class counts.  A workgroup's
+// the digit counts of every sort pass.  DEG: also the degree class (from
+// the range pass's deg bytes) above the cell and colour fields, and the
+// class counts.  A workgroup's
 // keys are the first sort pass's tile: its counts of that pass's digit go
 // to tcount[digit][tile].  idx_bits > 0: each word is key << idx_bits | i
 // (the sort then carries the index in the key word).
@@ -283,11 +314,11 @@ __global__ __launch_bounds__(64) void k_range_final(const uint32_t *cov, uint32_
 // key arithmetic better than 256 x 16
 constexpr int kKeysThreads = 512, kKeysKPT = kSortTile / kKeysThreads;
 template <bool DEG>
-__global__ __launch_bounds__(kKeysThreads) void k_keys(const float *pos, const float *dc, const float *sh,
-                                              const float *opacity, uint64_t n, uint32_t grid_bits,
+__global__ __launch_bounds__(kKeysThreads) void k_keys(const float *pos, const float *dc, const uint8_t *deg,
+                                              uint64_t n, uint32_t grid_bits,
                                               RangeRec *r, bool self_range, SortPlan plan, uint64_t *keys,
                                               uint32_t *gcount, uint32_t *tcount, uint32_t ntiles, uint32_t idx_bits,
-                                              float tau, uint32_t *class_count)
+                                              uint32_t *class_count)
 {
     __shared__ uint32_t hist[kMaxPasses][kMaxBins];
     __shared__ uint32_t cls[4];
@@ -314,7 +345,8 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(const float *pos, const f
     const uint32_t tile = xcd_block(blockIdx.x, gridDim.x);
     // every load of the tile first (the last element stands in past the end),
     // so the workgroup has them all in flight at once
-    float px[kKeysKPT][3], pc[kKeysKPT][3], pmu[kKeysKPT];
+    float px[kKeysKPT][3], pc[kKeysKPT][3];
+    uint32_t pl[kKeysKPT];
 #pragma unroll
     for (int it = 0; it < kKeysKPT; it++) {
         const uint64_t i = (uint64_t)tile * kSortTile + (uint64_t)it * kKeysThreads + threadIdx.x;
@@ -322,9 +354,9 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(const float *pos, const f
 #pragma unroll
         for (int a = 0; a < 3; a++) {
             px[it][a] = pos[ic * 3 + a];
-            pc[it][a] = DEG ? sh[ic * 48 + a] : dc[ic * 3 + a];
+            pc[it][a] = dc[ic * 3 + a];
         }
-        pmu[it] = opacity && DEG ? opacity[ic] : 1.0f;
+        pl[it] = DEG ? deg[ic] : 0u;
     }
 #pragma unroll
     for (int it = 0; it < kKeysKPT; it++) {
@@ -338,32 +370,16 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys(const float *pos, const f
             uint32_t v = (uint32_t)floorf(u);
             cell[a] = v < cmax ? v : cmax;
         }
-        const float mu = pmu[it];
-        // band-0 colour: in the degree variant read here and times the
-        // opacity; otherwise the range pass stored it already multiplied
-        float d0 = pc[it][0], d1 = pc[it][1], d2 = pc[it][2];
-        if (DEG && opacity) { d0 = mu * d0; d1 = mu * d1; d2 = mu * d2; }
+        // band-0 colour, as the range pass stored it (times the opacity)
+        const float d0 = pc[it][0], d1 = pc[it][1], d2 = pc[it][2];
         const uint32_t q0 = quant8(d0, vmin0, scale0);
         const uint32_t q1 = quant8(d1, vmin0, scale0);
         const uint32_t q2 = quant8(d2, vmin0, scale0);
         const uint64_t chunk = spread3(cell[0]) | (spread3(cell[1]) << 1) | (spread3(cell[2]) << 2);
         const uint32_t colour = (spread3(q0) << 2) | (spread3(q1) << 1) | spread3(q2);
         uint64_t key = (chunk << 24) | colour;
-        if (DEG) {
-            const float4 *p4 = reinterpret_cast<const float4 *>(sh + i * 48);
-            float f[48];
-#pragma unroll
-            for (int c = 0; c < 12; c++) {
-                const float4 v = p4[c];
-                f[4 * c] = v.x; f[4 * c + 1] = v.y; f[4 * c + 2] = v.z; f[4 * c + 3] = v.w;
-            }
-            uint32_t L = 0;
-#pragma unroll
-            for (int e = 3; e < 48; e++) {       // bands 1..15; band k has degree floor(sqrt(k))
-                const int k = e / 3, l = k >= 9 ? 3 : k >= 4 ? 2 : 1;
-                const float x = opacity ? mu * f[e] : f[e];
-                if (fabsf(x) > tau) L = L > (uint32_t)l ? L : (uint32_t)l;
-            }
+        if (DEG) {   // the degree class the range pass found
+            const uint32_t L = pl[it];
             key |= (uint64_t)L << (24 + 3 * grid_bits);
             atomicAdd(&cls[L], 1u);
         }
@@ -794,7 +810,7 @@ __global__ __launch_bounds__(256) void k_pack_degrees(const float *sh, const flo
 }
 
 struct Layout {
-    size_t keys_a, keys_b, vals_a, vals_b, dc, tcount, toff, meta, cov_state, cov_part, bytes;
+    size_t keys_a, keys_b, vals_a, vals_b, dc, deg, tcount, toff, meta, cov_state, cov_part, bytes;
     uint64_t ntiles;
 };
 
@@ -812,6 +828,7 @@ Layout layout(uint64_t n)
     L.vals_a = o; o += al(n * 4);
     L.vals_b = o; o += al(n * 4);
     L.dc = o; o += al(n * 12);
+    L.deg = o; o += al(n);   // degree classes (the degree-class reorder)
     L.tcount = o; o += al(L.ntiles * kMaxBins * 4);   // [digit][tile] counts of the current pass
     L.toff = o; o += al(L.ntiles * kMaxBins * 4);     // [digit][tile] output offsets
     L.meta = o; o += al(kMetaWords * 4);
@@ -838,15 +855,25 @@ namespace {
 // keys_finish: the key pass will fill the range record (and put the extremes
 // back) itself, so no finishing launch is needed unless the coverage range
 // replaces the band ranges.
+// deg_tau >= 0: also each primitive's degree class (threshold deg_tau) into
+// the arena's deg bytes, for the degree-class key pass.
 void enqueue_range(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
-                   uint32_t quantiser, bool keys_finish, const Layout &L, char *s, RangeRec *range_dev, hipStream_t st)
+                   uint32_t quantiser, bool keys_finish, float deg_tau, const Layout &L, char *s, RangeRec *range_dev,
+                   hipStream_t st)
 {
     uint64_t want = (n * 12 + kRangeBlock - 1) / kRangeBlock;
     // at most 512 workgroups of 768 (two per CU, each one contiguous span)
     const uint32_t nb = (uint32_t)std::min<uint64_t>(std::max<uint64_t>((n * 12 + kMinMaxBlock - 1) / kMinMaxBlock, 1), 512);
-    GSBC_LAUNCH("range_partial", k_range_partial, dim3(nb), dim3(kMinMaxBlock), 0, st,
-                       reinterpret_cast<const float4 *>(sh), opacity, pos, n, range_dev->acc, reinterpret_cast<float *>(s + L.dc),
-                reinterpret_cast<uint32_t *>(s + L.meta), kMetaWords);
+    if (deg_tau >= 0.0f)
+        GSBC_LAUNCH("range_partial", k_range_partial<true>, dim3(nb), dim3(kMinMaxBlock), 0, st,
+                    reinterpret_cast<const float4 *>(sh), opacity, pos, n, range_dev->acc,
+                    reinterpret_cast<float *>(s + L.dc), reinterpret_cast<uint32_t *>(s + L.meta), kMetaWords, deg_tau,
+                    reinterpret_cast<uint8_t *>(s + L.deg));
+    else
+        GSBC_LAUNCH("range_partial", k_range_partial<false>, dim3(nb), dim3(kMinMaxBlock), 0, st,
+                    reinterpret_cast<const float4 *>(sh), opacity, pos, n, range_dev->acc,
+                    reinterpret_cast<float *>(s + L.dc), reinterpret_cast<uint32_t *>(s + L.meta), kMetaWords, 0.0f,
+                    nullptr);
     uint32_t *cov = nullptr;
     if (quantiser == 1) {
         cov = reinterpret_cast<uint32_t *>(s + L.cov_state);
@@ -870,9 +897,8 @@ void enqueue_range(const float *pos, const float *sh, const float *opacity, uint
 // the offsets, the scatter; the last pass writes the values (the original
 // indices) to perm.
 template <bool DEG>
-void enqueue_keys_and_sort(const float *pos, const float *sh, const float *opacity, uint64_t n, uint32_t grid_bits,
-                           float tau, bool self_range, const Layout &L, char *s, RangeRec *range_dev,
-                           uint32_t *class_count, uint32_t *perm, hipStream_t st)
+void enqueue_keys_and_sort(const float *pos, uint64_t n, uint32_t grid_bits, bool self_range, const Layout &L, char *s,
+                           RangeRec *range_dev, uint32_t *class_count, uint32_t *perm, hipStream_t st)
 {
     const int key_bits = (DEG ? 26 : 24) + 3 * (int)grid_bits;
     const SortPlan P = plan_sort(key_bits);
@@ -888,8 +914,8 @@ void enqueue_keys_and_sort(const float *pos, const float *sh, const float *opaci
     const uint32_t ntiles = (uint32_t)L.ntiles;
     const dim3 grid(ntiles);
     GSBC_LAUNCH(DEG ? "keys_degree" : "keys", k_keys<DEG>, grid, dim3(kKeysThreads), 0, st, pos,
-                reinterpret_cast<const float *>(s + L.dc), sh, opacity, n, grid_bits, range_dev, self_range, P, ka,
-                gcount, tcount, ntiles, ib, tau, class_count);
+                reinterpret_cast<const float *>(s + L.dc), reinterpret_cast<const uint8_t *>(s + L.deg), n, grid_bits,
+                range_dev, self_range, P, ka, gcount, tcount, ntiles, ib, class_count);
     const uint64_t *kin = ka;
     uint64_t *kout = kb;
     const uint32_t *vin = nullptr;
@@ -923,12 +949,11 @@ hipError_t launch_reorder(const float *pos, const float *sh, const float *opacit
 {
     Layout L = layout(n);
     char *s = static_cast<char *>(scratch);
-    enqueue_range(pos, sh, opacity, n, grid_bits, quantiser, !identity, L, s, range_dev, st);
+    enqueue_range(pos, sh, opacity, n, grid_bits, quantiser, !identity, -1.0f, L, s, range_dev, st);
     if (identity) {
         GSBC_LAUNCH("iota", k_iota, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, perm, n);
     } else {
-        enqueue_keys_and_sort<false>(pos, sh, opacity, n, grid_bits, 0.0f, quantiser != 1, L, s, range_dev, nullptr,
-                                     perm, st);
+        enqueue_keys_and_sort<false>(pos, n, grid_bits, quantiser != 1, L, s, range_dev, nullptr, perm, st);
     }
     const uint64_t npad = (n + 15) / 16 * 16;
     GSBC_LAUNCH("gather_pack", k_gather_pack, dim3((uint32_t)((npad + 255) / 256)), dim3(256), 0, st,
@@ -943,10 +968,9 @@ hipError_t launch_degree_sort(const float *pos, const float *sh, const float *op
 {
     Layout L = layout(n);
     char *s = static_cast<char *>(scratch);
-    enqueue_range(pos, sh, opacity, n, grid_bits, quantiser, true, L, s, range_dev, st);
+    enqueue_range(pos, sh, opacity, n, grid_bits, quantiser, true, tau, L, s, range_dev, st);
     GSBC_LAUNCH("fill_count", k_zero4, dim3(1), dim3(64), 0, st, class_count);
-    enqueue_keys_and_sort<true>(pos, sh, opacity, n, grid_bits, tau, quantiser != 1, L, s, range_dev, class_count,
-                                perm, st);
+    enqueue_keys_and_sort<true>(pos, n, grid_bits, quantiser != 1, L, s, range_dev, class_count, perm, st);
     return hipGetLastError();
 }
 
