@@ -457,7 +457,8 @@ class Context:
                             image=None, transmittance=None, want_transmittance=True):
         """The colour stage with the colours computed beforehand (colours
         float32[n_prims][3] per slot, e.g. decode_eval_view over all slots);
-        other arguments and the result as blend_tiles."""
+        other arguments and the result as blend_tiles (perm from reorder:
+        every value below N, the length of opacity and footprint)."""
         _check(colours, torch.float32, "colours")
         if colours.dim() != 2 or colours.shape[1] != 3:
             raise ValueError(f"colours has shape {tuple(colours.shape)}, expected (n_prims, 3)")
