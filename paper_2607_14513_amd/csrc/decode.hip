@@ -519,7 +519,10 @@ __global__ __launch_bounds__(256) void k_blend_tiles(const uint8_t *blocks, Band
                                                      uint64_t list_len, const uint32_t *order, uint32_t tiles_x,
                                                      const float *colours, float *image, float *trans)
 {
-    __shared__ float s_par[256][9];   // mean x, mean y, A, B, C, mu, colour r, g, b
+    // per staged entry: mean x, mean y, A, B | C, mu, colour r, g | colour b
+    // (rows of 12 floats: three 16-byte LDS reads per entry, all lanes
+    // reading the same row)
+    __shared__ __align__(16) float s_par[256][12];
     const uint32_t t = threadIdx.x, tile = order[blockIdx.x];
     const uint32_t tx = tile % tiles_x, ty = tile / tiles_x;
     const float x = (float)(16 * tx + (t & 15u)) + 0.5f, y = (float)(16 * ty + (t >> 4)) + 0.5f;
@@ -558,14 +561,19 @@ __global__ __launch_bounds__(256) void k_blend_tiles(const uint8_t *blocks, Band
         for (uint32_t j0 = 0; j0 < cnt; j0 += 32) {
             if (__all(T == 0.0f)) break;   // this wave is done for the chunk
             const uint32_t j1 = j0 + 32 < cnt ? j0 + 32 : cnt;
+            // four entries' reads in flight at once
+#pragma unroll 4
             for (uint32_t j = j0; j < j1; j++) {
-                const float dx = x - s_par[j][0], dy = y - s_par[j][1];
-                const float ex = fmaf(dx, fmaf(s_par[j][2], dx, s_par[j][3] * dy), s_par[j][4] * dy * dy);
+                const float4 pa = *reinterpret_cast<const float4 *>(&s_par[j][0]);
+                const float4 pb = *reinterpret_cast<const float4 *>(&s_par[j][4]);
+                const float4 pc = *reinterpret_cast<const float4 *>(&s_par[j][8]);
+                const float dx = x - pa.x, dy = y - pa.y;
+                const float ex = fmaf(dx, fmaf(pa.z, dx, pa.w * dy), pb.x * dy * dy);
                 const float g = __builtin_amdgcn_exp2f(ex);
-                const float w = g * T, m = T * s_par[j][5];
-                a0 = fmaf(w, s_par[j][6], a0);
-                a1 = fmaf(w, s_par[j][7], a1);
-                a2 = fmaf(w, s_par[j][8], a2);
+                const float w = g * T, m = T * pb.y;
+                a0 = fmaf(w, pb.z, a0);
+                a1 = fmaf(w, pb.w, a1);
+                a2 = fmaf(w, pc.x, a2);
                 T = fmaf(-m, g, T);
             }
         }
