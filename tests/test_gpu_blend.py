@@ -152,3 +152,77 @@ def test_blend_tiles_colours_equals_fused(G, n, tiles, seed):
     assert np.isnan(img3[16 * yy:16 * yy + 16, 16 * xx:16 * xx + 16]).all()
     with pytest.raises(ValueError):
         ctx.blend_tiles_colours(cols[:, :2].contiguous(), perm, md, fd, tsd, ld, tx, ty)
+
+
+def test_blend_tiles_full_size_sampled(G):
+    """The colour stage at the size the bench times it: the 3,145,728-
+    primitive scene (256 clusters), a 1920 x 1088 image of 120 x 68 tiles
+    whose lists come from projecting the scene from one view position
+    (footprint sigmas 0.7-6 px, 16.6 M entries), 6 bits/texel (band 0 and
+    seven other bands BC7, the rest BC1).  The fused and two-pass forms give
+    the same bits over the whole image; seven tiles (lists of 300 to 8,000
+    entries, several LDS chunks each, plus one short list) against the FP64
+    oracle on oracle-encoded blocks, the other tiles' lists left empty on
+    the oracle side."""
+    gsbc, ctx = G
+    c = synth.CONFIGS["large"]
+    n, tx, ty = c["n"], 120, 68
+    view = np.array([0.5, 0.5, 2.5], np.float32)
+    pos, sh = synth.make_scene(n, c["clusters"], c["comps"], c["seed"])
+    mu = synth.make_opacity(n, seed=c["seed"])
+    fmt = np.array([7, 7, 1, 7, 1, 7, 1, 7, 1, 7, 1, 7, 1, 1, 7, 1], np.uint8)
+    assert 8 * (fmt == 7).sum() + 4 * (fmt == 1).sum() == 6 * 16
+    say("blend full size: reorder + encode")
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    for k in range(16):
+        d.format[k] = int(fmt[k])
+    blocks, d2, _ = ctx.encode(tex, d, fmt=gsbc.FMT_BANDS)
+    del tex
+    foot, ts, lst = synth.make_tiles(pos, view, tx, ty, seed=c["seed"], sigma=(0.7, 6.0))
+    gperm = host(perm).view(np.uint32)
+    gslot = np.argsort(gperm).astype(np.int32)
+    pd, md, fd, tsd, ld = dev(pos), dev(mu), dev(foot), dev(ts.astype(np.int32)), dev(gslot[lst])
+    say("blend full size:", int(ts[-1]), "entries")
+    img, T = ctx.blend_tiles(blocks, d2, pd, perm, view, md, fd, tsd, ld, tx, ty)
+    cols = ctx.decode_eval_view(blocks, d2, pd, perm, view)
+    img2, T2 = ctx.blend_tiles_colours(cols, perm, md, fd, tsd, ld, tx, ty)
+    img, T = host(img), host(T)
+    assert np.array_equal(img.view(np.uint32), host(img2).view(np.uint32))
+    assert np.array_equal(T.view(np.uint32), host(T2).view(np.uint32))
+    del img2, T2, cols
+    assert np.isfinite(img).all() and ((T >= 0) & (T <= 1)).all()
+
+    rperm, rtex, vmin, vmax = O.reorder(pos, sh)
+    assert np.array_equal(gperm, rperm)
+    assert np.array_equal(d2.ranges()[0].view(np.uint32), vmin.view(np.uint32))
+    L = np.diff(ts.astype(np.int64))
+    rng = np.random.default_rng(11)
+    pick = list(rng.choice(np.flatnonzero((L >= 300) & (L <= 2500)), 5, replace=False))
+    pick.append(int(rng.choice(np.flatnonzero((L >= 6000) & (L <= 8000)))))
+    pick.append(int(rng.choice(np.flatnonzero((L >= 1) & (L < 256)))))
+    pick = np.array(sorted(set(int(t) for t in pick)))
+    # the picked tiles' lists, as slots of a payload holding only their blocks
+    rslot = np.argsort(rperm).astype(np.uint32)
+    prims = np.concatenate([lst[ts[t]:ts[t + 1]] for t in pick])
+    slots = rslot[prims]
+    need = np.unique(slots)
+    blk = np.unique(need // 16)
+    say("blend full size: oracle encode of", blk.size, "blocks per band")
+    payload, off, _ = O.encode(rtex[:, blk], fmt)
+    renum = (16 * np.searchsorted(blk, need // 16) + need % 16).astype(np.uint32)
+    perm_o = np.zeros(16 * blk.size, np.uint32)
+    perm_o[renum] = rperm[need]
+    lst_o = renum[np.searchsorted(need, slots)]
+    ts_o = np.zeros(tx * ty + 1, np.int64)
+    cnt = np.zeros(tx * ty, np.int64)
+    cnt[pick] = L[pick]
+    ts_o[1:] = np.cumsum(cnt)
+    r, rt, b, bt = O.blend_tiles(payload, off, fmt, vmin, vmax, pos, perm_o, view, mu, foot, ts_o.astype(np.uint32),
+                                 lst_o, tx, ty)
+    for t in pick:
+        yy, xx = divmod(int(t), tx)
+        sl = (slice(16 * yy, 16 * yy + 16), slice(16 * xx, 16 * xx + 16))
+        err = np.abs(img[sl].astype(np.float64) - r[sl])
+        lim = 3e-5 * b[sl] + 4 * U * bt[sl] + (L[t] + 1) * 2.0 ** -120
+        assert np.all(err <= lim), (int(t), int(L[t]), float((err - lim).max()))
+        assert np.all(np.abs(T[sl].astype(np.float64) - rt[sl]) <= 3 * (L[t] + 1) * U), int(t)
