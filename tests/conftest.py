@@ -47,3 +47,32 @@ def load_golden(name):
                 exp[int(i)] = tuple(int(x) for x in v.split(","))
             out.append((fmt, bytes.fromhex(hexb), exp))
     return out
+
+
+def oracle_blend_tiles_subset(rtex, fmt, vmin, vmax, pos, rperm, view, mu, foot, tile_start, lst, pick,
+                              tiles_x, tiles_y):
+    """The oracle's FP64 colour stage on the tiles in ``pick`` only, with a
+    payload encoded from just the blocks their lists reach (a scene too
+    large for the oracle to encode whole).  ``lst`` holds primitive ids in
+    input order, ``rperm`` is the oracle's slot -> primitive order; every
+    other tile's list is left empty.  Returns what ``O.blend_tiles`` does
+    (image, transmittance and their bounds); only the picked tiles carry the
+    scene's values.  Also returns the number of blocks encoded per band."""
+    import oracle as O
+    ts = np.asarray(tile_start, np.int64)
+    pick = np.unique(np.asarray(pick, np.int64))         # the lists in tile order
+    L = np.diff(ts)
+    rslot = np.argsort(rperm).astype(np.uint32)
+    slots = rslot[np.concatenate([lst[ts[t]:ts[t + 1]] for t in pick])]
+    need = np.unique(slots)
+    blk = np.unique(need // 16)
+    payload, off, _ = O.encode(rtex[:, blk], fmt)
+    renum = (16 * np.searchsorted(blk, need // 16) + need % 16).astype(np.uint32)
+    perm_o = np.zeros(16 * blk.size, np.uint32)
+    perm_o[renum] = rperm[need]
+    cnt = np.zeros(tiles_x * tiles_y, np.int64)
+    cnt[pick] = L[pick]
+    ts_o = np.concatenate([[0], np.cumsum(cnt)]).astype(np.uint32)
+    lst_o = renum[np.searchsorted(need, slots)]
+    return O.blend_tiles(payload, off, fmt, vmin, vmax, pos, perm_o, view, mu, foot, ts_o, lst_o, tiles_x,
+                         tiles_y), blk.size

@@ -17,6 +17,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from conftest import oracle_blend_tiles_subset
 from paper_2607_14513_amd import synth
 
 torch = pytest.importorskip("torch")
@@ -200,25 +201,11 @@ def test_blend_tiles_full_size_sampled(G):
     pick = list(rng.choice(np.flatnonzero((L >= 300) & (L <= 2500)), 5, replace=False))
     pick.append(int(rng.choice(np.flatnonzero((L >= 6000) & (L <= 8000)))))
     pick.append(int(rng.choice(np.flatnonzero((L >= 1) & (L < 256)))))
-    pick = np.array(sorted(set(int(t) for t in pick)))
-    # the picked tiles' lists, as slots of a payload holding only their blocks
-    rslot = np.argsort(rperm).astype(np.uint32)
-    prims = np.concatenate([lst[ts[t]:ts[t + 1]] for t in pick])
-    slots = rslot[prims]
-    need = np.unique(slots)
-    blk = np.unique(need // 16)
-    say("blend full size: oracle encode of", blk.size, "blocks per band")
-    payload, off, _ = O.encode(rtex[:, blk], fmt)
-    renum = (16 * np.searchsorted(blk, need // 16) + need % 16).astype(np.uint32)
-    perm_o = np.zeros(16 * blk.size, np.uint32)
-    perm_o[renum] = rperm[need]
-    lst_o = renum[np.searchsorted(need, slots)]
-    ts_o = np.zeros(tx * ty + 1, np.int64)
-    cnt = np.zeros(tx * ty, np.int64)
-    cnt[pick] = L[pick]
-    ts_o[1:] = np.cumsum(cnt)
-    r, rt, b, bt = O.blend_tiles(payload, off, fmt, vmin, vmax, pos, perm_o, view, mu, foot, ts_o.astype(np.uint32),
-                                 lst_o, tx, ty)
+    pick = np.unique(pick)
+    say("blend full size: oracle on tiles", pick.tolist())
+    (r, rt, b, bt), nblk = oracle_blend_tiles_subset(rtex, fmt, vmin, vmax, pos, rperm, view, mu, foot, ts, lst, pick,
+                                                     tx, ty)
+    say("blend full size: oracle encoded", nblk, "blocks per band")
     for t in pick:
         yy, xx = divmod(int(t), tx)
         sl = (slice(16 * yy, 16 * yy + 16), slice(16 * xx, 16 * xx + 16))

@@ -154,3 +154,33 @@ def test_order_matters_with_opacity():
     a1, _, _ = _run(coded, mu, foot, ts, slot_of[[0, 1]], 1, 1)
     a2, _, _ = _run(coded, mu, foot, ts, slot_of[[1, 0]], 1, 1)
     assert np.abs(a1 - a2).max() > 1e-4
+
+
+def test_blend_on_tile_subset_equals_whole_payload():
+    """The full-size GPU test runs the oracle on a few tiles with a payload
+    of just their blocks: on a scene small enough to encode whole, those
+    tiles come out identical (every bit of image, transmittance and bounds)
+    to the blend over the whole payload, and the other tiles stay empty."""
+    from conftest import oracle_blend_tiles_subset
+    n, tx, ty = 20_011, 20, 15
+    view = np.array([0.5, 0.5, 2.5], np.float32)
+    pos, sh = synth.make_scene(n, seed=4)
+    mu = synth.make_opacity(n, seed=4)
+    fmt = np.array([7, 7, 1, 7, 1, 7, 1, 7, 1, 7, 1, 7, 1, 1, 7, 1], np.uint8)
+    foot, ts, lst = synth.make_tiles(pos, view, tx, ty, seed=4, sigma=(0.7, 6.0))
+    rperm, rtex, vmin, vmax = O.reorder(pos, sh)
+    payload, off, _ = O.encode(rtex, fmt)
+    whole = O.blend_tiles(payload, off, fmt, vmin, vmax, pos, rperm, view, mu, foot, ts,
+                          np.argsort(rperm).astype(np.uint32)[lst], tx, ty)
+    L = np.diff(ts.astype(np.int64))
+    pick = np.random.default_rng(1).choice(np.flatnonzero(L > 0), 6, replace=False)[::-1]   # any order
+    sub, nblk = oracle_blend_tiles_subset(rtex, fmt, vmin, vmax, pos, rperm, view, mu, foot, ts, lst, pick, tx, ty)
+    assert nblk < rtex.shape[1]
+    for t in range(tx * ty):
+        yy, xx = divmod(t, tx)
+        sl = (slice(16 * yy, 16 * yy + 16), slice(16 * xx, 16 * xx + 16))
+        if t in pick:
+            for a, b in zip(whole, sub):
+                assert np.array_equal(a[sl], b[sl]), t
+        else:
+            assert not sub[0][sl].any() and (sub[1][sl] == 1.0).all(), t
