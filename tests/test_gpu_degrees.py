@@ -121,6 +121,59 @@ def test_classes_encode_batch_and_decode(G):
         assert np.array_equal(host(blocks[i])[:rpay.size], rpay), i
 
 
+def test_degrees_full_size_sampled(G):
+    """The degree-class workload at the size the bench times it: 1,048,576
+    primitives (32 clusters, 64-component DC mixture) whose SH degrees are
+    drawn as 35/20/15/30 %.  Class counts, the class-major permutation, the
+    ranges and every class's textures bit-exact against the oracle; the
+    classes coded band 0 BC7 + the rest BC1 in one batch equal the same
+    classes coded one by one, and 256 blocks of every kept band of every
+    class (first and last included) equal the oracle's encoder."""
+    gsbc, ctx = G
+    c = synth.CONFIGS["mid"]
+    pos, sh = synth.make_scene(c["n"], c["clusters"], c["comps"], c["seed"] + 100, degree_mix=MIX)
+    say("degrees full size: reorder")
+    perm, counts, tex, descs = ctx.reorder_degrees(dev(pos), dev(sh))
+    rperm, rcounts, rtex, vmin, vmax = O.reorder_degrees(pos, sh, 0.0)
+    assert counts == rcounts.tolist() and all(counts)
+    assert np.array_equal(host(perm).view(np.uint32), rperm)
+    texs, dl, single = [], [], []
+    for L in range(4):
+        nb = (L + 1) ** 2
+        d = descs[L]
+        assert np.array_equal(d.ranges()[0].view(np.uint32), vmin.view(np.uint32))
+        assert np.array_equal(d.ranges()[1].view(np.uint32), vmax.view(np.uint32))
+        assert np.array_equal(host(tex[L]), rtex[L]), L
+        fmt = [7] + [1] * (nb - 1)
+        for k, f in enumerate(fmt):
+            d.format[k] = f
+        say("degrees full size: class", L, counts[L])
+        blocks, d2, _ = ctx.encode(tex[L], d, fmt=gsbc.FMT_BANDS)
+        hb = host(blocks)
+        nblk = d2.blocks_per_stream
+        for k, f in enumerate(fmt):
+            pick = _sample_blocks(nblk, 256, 40 * L + k)
+            bs = 16 if f == 7 else 8
+            stream = hb[int(d2.offsets()[k]):int(d2.offsets()[k]) + nblk * bs].reshape(nblk, bs)
+            ref = O.bc7_encode(rtex[L][k][pick])[0] if f == 7 else O.bc1_encode(rtex[L][k][pick])[0]
+            assert np.array_equal(stream[pick], ref), (L, k)
+        texs.append(tex[L])
+        dl.append(d)
+        single.append(hb[:d2.payload_bytes])
+    say("degrees full size: batch")
+    outs = [torch.zeros(p.size + 64, dtype=torch.uint8, device="cuda") for p in single]
+    ctx.encode_batch(texs, dl, outs)
+    for L, p in enumerate(single):
+        assert np.array_equal(host(outs[L])[:p.size], p), L
+
+
+def _sample_blocks(nblk, count, seed):
+    """count distinct block indices of a stream, its first and last included."""
+    rng = np.random.default_rng(seed)
+    inner = 1 + rng.choice(max(nblk - 2, 0), min(max(nblk - 2, 0), count - 2), replace=False)
+    return np.unique(np.concatenate([[0, nblk - 1], inner]))
+
+
 def test_degree_errors(G):
     gsbc, ctx = G
     pos, sh = synth.make_scene(100, seed=10)
