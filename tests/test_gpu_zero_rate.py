@@ -92,6 +92,55 @@ def test_auto_zero_bit_exact(G, scene, rate):
         assert (want == 3).any() and (want != 3).sum() > 1
 
 
+def test_auto_zero_full_size_sampled(G):
+    """The 0-bit option at 1,048,576 primitives (32 clusters, 64-component DC
+    mixture), 3.25 bits/texel.  The choice rests on each band's SSE in both
+    formats and its code histogram: each format's SSE totals equal the
+    GPU's decode of that format's whole payload and the totals AUTO_ZERO
+    reports, the formats equal the oracle's selector applied to those totals
+    and to the oracle's histograms of the oracle's textures, the budget is
+    met exactly, and 256 blocks of every coded band (first and last
+    included) equal the oracle's encoder in the chosen format."""
+    gsbc, ctx = G
+    c = synth.CONFIGS["mid"]
+    rate = 3.25
+    pos, sh = synth.make_scene(c["n"], c["clusters"], c["comps"], c["seed"])
+    say("auto zero full size")
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh))
+    blocks, d2, sse = ctx.encode(tex, d, fmt=gsbc.FMT_AUTO_ZERO, rate=rate, want_sse=True)
+    _, rtex, vmin, vmax = O.reorder(pos, sh)
+    assert np.array_equal(host(tex), rtex)
+    nblk = rtex.shape[1]
+    totals = []
+    for fi, f in enumerate((1, 7)):
+        ball, dall, sall = ctx.encode(tex, d, fmt=f, want_sse=True)
+        dec = ctx.decode(ball, dall)
+        del ball
+        diff = dec[..., :3].to(torch.int64) - tex[..., :3].to(torch.int64)
+        err = (diff * diff).sum(dim=(1, 2, 3)).cpu().numpy()
+        del dec, diff
+        assert np.array_equal(err, sall[fi]), f
+        k0 = 1 if f == 1 else 0                  # band 0 is always BC7: no BC1 total for it
+        assert np.array_equal(sse[fi][k0:], sall[fi][k0:]), f
+        totals.append(sall[fi].astype(np.int64))
+    want = O.rate_select_zero(totals[0], totals[1], O.band_hist(rtex), vmin, vmax, rate, 16)
+    f0 = d2.formats()
+    assert want is not None and np.array_equal(f0, want), (f0, want)
+    assert (f0 == 3).any() and (f0 == 1).any() and (f0 == 7).sum() > 1
+    off, total = O.stream_layout(want, nblk)
+    assert np.array_equal(d2.offsets(), off) and d2.payload_bytes == total
+    assert sum({7: 128, 1: 64, 3: 0}[int(f)] * nblk for f in want) == rate * 16 * nblk * 16
+    hb = host(blocks)
+    for k in range(16):
+        if f0[k] == 3:
+            continue
+        pick = np.unique(np.concatenate([[0, nblk - 1], np.random.default_rng(60 + k).choice(nblk, 254, replace=False)]))
+        bs = 8 if f0[k] == 1 else 16
+        stream = hb[int(off[k]):int(off[k]) + nblk * bs].reshape(nblk, bs)
+        ref = O.bc1_encode(rtex[k][pick])[0] if f0[k] == 1 else O.bc7_encode(rtex[k][pick])[0]
+        assert np.array_equal(stream[pick], ref), f"band {k} format {f0[k]}"
+
+
 def test_zero_streams_decode_to_zero(G, scene):
     """Formats set by the caller with some bands given no bits: blocks,
     texels, colours (all slots, 9 directions), the view colour, the
