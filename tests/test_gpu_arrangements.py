@@ -93,6 +93,41 @@ def test_encode_arrangement_bit_exact(G, arr, which, n):
     assert np.array_equal(host(ctx.decode(blocks, d2)), O.decode_stream(rpay, roff, fmt, rtex.shape[1]))
 
 
+@pytest.mark.parametrize("arr,order", [(1, 0), (2, 0), (2, 1)])
+def test_arrangement_full_size_sampled(G, arr, order):
+    """At the size the bench codes the arrangements (1,048,576 primitives, 32
+    clusters, 64-component DC mixture; sorted and input order): permutation
+    and every stream's texture bit-exact against the oracle's packer, then
+    the first format set coded and 256 blocks of every stream (first and
+    last included) equal to the oracle's encoder."""
+    gsbc, ctx = G
+    c = synth.CONFIGS["mid"]
+    pos, sh = synth.make_scene(c["n"], c["clusters"], c["comps"], c["seed"])
+    say("arrangement full size", arr, order)
+    perm, tex, d = ctx.reorder(dev(pos), dev(sh), params=gsbc.default_params(arrangement=arr, order=order))
+    if order == 0:
+        rperm, rtex, _, _ = O.reorder(pos, sh, arrangement=arr)
+    else:
+        rvmin, rvmax = O.band_range(sh)
+        rperm = np.arange(c["n"], dtype=np.uint32)
+        rtex = O.pack(O.quantise(sh, rvmin, rvmax), rperm, arr)
+    assert np.array_equal(host(perm).view(np.uint32), rperm)
+    assert np.array_equal(host(tex), rtex)
+    fmt = np.array(FMTS[arr][0], np.uint8)
+    for k, f in enumerate(fmt):
+        d.format[k] = int(f)
+    blocks, d2, _ = ctx.encode(tex, d, fmt=gsbc.FMT_BANDS)
+    hb = host(blocks)
+    nblk = d2.blocks_per_stream
+    for k, f in enumerate(fmt):
+        rng = np.random.default_rng(70 + 8 * arr + k)
+        pick = np.unique(np.concatenate([[0, nblk - 1], rng.choice(nblk, 254, replace=False)]))
+        bs = 16 if f == 7 else 8
+        stream = hb[int(d2.offsets()[k]):int(d2.offsets()[k]) + nblk * bs].reshape(nblk, bs)
+        ref = O.bc7_encode(rtex[k][pick])[0] if f == 7 else O.bc1_encode(rtex[k][pick])[0]
+        assert np.array_equal(stream[pick], ref), (arr, k)
+
+
 @pytest.mark.parametrize("arr", [1, 2])
 def test_whole_format_and_auto(G, arr):
     gsbc, ctx = G
