@@ -44,6 +44,25 @@ __host__ __device__ constexpr int bc7_weight(int n, int i)
     return (128 * i + ((1 << n) - 1)) / (2 * ((1 << n) - 1));
 }
 
+// The same weights for n and i known only at run time (the decoders): the
+// table bytes, little end first, taken by one 64-bit shift instead of a
+// division by 2 (2^n - 1).
+__host__ __device__ constexpr int bc7_weight_packed(int n, int i)
+{
+    const uint64_t lo = n == 2 ? 0x402B1500ull : n == 3 ? 0x40372E251B120900ull : 0x1E1A15110D090400ull;
+    const uint64_t hi = 0x403C37332F2B2622ull;   // n = 4, indices 8..15
+    return (int)(((i < 8 ? lo : hi) >> (8 * (i & 7))) & 255u);
+}
+
+__host__ __device__ constexpr bool bc7_weights_packed_ok()
+{
+    for (int n = 2; n <= 4; n++)
+        for (int i = 0; i < (1 << n); i++)
+            if (bc7_weight_packed(n, i) != bc7_weight(n, i)) return false;
+    return true;
+}
+static_assert(bc7_weights_packed_ok(), "packed BC7 weight tables");
+
 __host__ __device__ constexpr int interp64(int e0, int e1, int w)
 {
     return ((64 - w) * e0 + w * e1 + 32) >> 6;
@@ -178,12 +197,14 @@ struct Blk128 {
     uint64_t lo, hi;
 };
 
+// Bits pos .. pos + n - 1 of the block (0 <= pos < 128, 1 <= n <= 31):
+// a funnel shift of the two halves, without branches (positions differ
+// from lane to lane).  (hi << 1) << (63 - p) is hi << (64 - p), zero at p = 0.
 __device__ inline uint32_t get_field(const Blk128 &b, int pos, int n)
 {
-    uint64_t v;
-    if (pos >= 64) v = b.hi >> (pos - 64);
-    else if (pos + n <= 64) v = b.lo >> pos;
-    else v = (b.lo >> pos) | (b.hi << (64 - pos));
+    const int p = pos & 63;
+    const uint64_t below = (b.lo >> p) | ((b.hi << 1) << (63 - p));
+    const uint64_t v = pos >= 64 ? b.hi >> p : below;
     return (uint32_t)v & ((1u << n) - 1u);
 }
 
@@ -279,7 +300,7 @@ __device__ inline uint32_t bc7_texel(const Blk128 &b, int i, const Lut &lut)
         if (sel == 0) { ai = i2; an = md.ib2; }
         else { ci = i2; cn = md.ib2; ai = i1; an = md.ib; }
     }
-    int wc = bc7_weight(cn, ci), wa = bc7_weight(an, ai);
+    int wc = bc7_weight_packed(cn, ci), wa = bc7_weight_packed(an, ai);
     int px[4];
     for (int c = 0; c < 3; c++) px[c] = interp64(e0[c], e1[c], wc);
     px[3] = interp64(e0[3], e1[3], wa);
