@@ -25,8 +25,9 @@ __device__ __forceinline__ uint32_t zigzag_texel(uint32_t j)
     return 4 * y + x;
 }
 
+template <class Lut = Bc7ConstLut>
 __device__ __forceinline__ uint32_t band_texel(const uint8_t *blocks, const BandArgs &b, int k,
-                                               uint64_t blk, int texel)
+                                               uint64_t blk, int texel, const Lut &lut = Lut{})
 {
     if (b.format[k] == GSBC_FMT_NONE) return 0u;   // a stream given 0 bits stores no blocks
     const uint8_t *base = blocks + b.offset[k];
@@ -36,7 +37,7 @@ __device__ __forceinline__ uint32_t band_texel(const uint8_t *blocks, const Band
     }
     ulonglong2 w = *reinterpret_cast<const ulonglong2 *>(base + blk * 16);
     Blk128 q{w.x, w.y};
-    return bc7_texel(q, texel);
+    return bc7_texel(q, texel, lut);
 }
 
 // The band texels of slot s, each found through the arrangement:
@@ -46,15 +47,17 @@ __device__ __forceinline__ uint32_t band_texel(const uint8_t *blocks, const Band
 // the n_streams streams: one stream is Fig. SetupC, bands 0..3).
 // One load per block, each decoded as it arrives (the fewest memory
 // instructions, for gathers that issue little else):
-template <int ARR>
-__device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16])
+template <int ARR, class Lut>
+__device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16],
+                                                const Lut &lut)
 {
 #pragma unroll
     for (int k = 0; k < 16; k++) {
-        if (ARR == 1) px[k] = band_texel(blocks, b, 0, s, k);
+        if (ARR == 1) px[k] = band_texel(blocks, b, 0, s, k, lut);
         else if (ARR == 2) px[k] = (uint32_t)(k >> 2) < b.n_streams
-                                       ? band_texel(blocks, b, k >> 2, s >> 2, 4 * (int)(s & 3u) + (k & 3)) : 0u;
-        else px[k] = (uint32_t)k < b.n_streams ? band_texel(blocks, b, k, s >> 4, (int)zigzag_texel(s & 15u)) : 0u;
+                                       ? band_texel(blocks, b, k >> 2, s >> 2, 4 * (int)(s & 3u) + (k & 3), lut) : 0u;
+        else px[k] = (uint32_t)k < b.n_streams ? band_texel(blocks, b, k, s >> 4, (int)zigzag_texel(s & 15u), lut)
+                                               : 0u;
     }
 }
 
@@ -62,8 +65,8 @@ __device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const Ban
 // 8-byte BC1 block loads its one half twice), so that the loads share one
 // wait, and the BC7 tables read through `lut`:
 template <int ARR, class Lut>
-__device__ __forceinline__ void slot_texels_arr(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16],
-                                                const Lut &lut)
+__device__ __forceinline__ void slot_texels_arr_batched(const uint8_t *blocks, const BandArgs &b, uint32_t s,
+                                                        uint32_t px[16], const Lut &lut)
 {
     uint2 lo[16], hi[16];
 #pragma unroll
@@ -119,13 +122,9 @@ __device__ __forceinline__ bool band_coded(const BandArgs &b, int k)
     return (uint32_t)k < kept_bands(b) && !(b.arrangement == 0 && b.format[k] == GSBC_FMT_NONE);
 }
 
-__device__ __forceinline__ void slot_texels(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16])
-{
-    if (b.arrangement == 1) slot_texels_arr<1>(blocks, b, s, px);
-    else if (b.arrangement == 2) slot_texels_arr<2>(blocks, b, s, px);
-    else slot_texels_arr<0>(blocks, b, s, px);
-}
-
+// The BC7 tables come through lut: Bc7ConstLut (constant memory) or
+// Bc7PackedLut (the workgroup's LDS copy, whose lookups wait on LDS
+// instead of on a second memory round trip after the block's).
 template <class Lut>
 __device__ __forceinline__ void slot_texels(const uint8_t *blocks, const BandArgs &b, uint32_t s, uint32_t px[16],
                                             const Lut &lut)
@@ -133,6 +132,15 @@ __device__ __forceinline__ void slot_texels(const uint8_t *blocks, const BandArg
     if (b.arrangement == 1) slot_texels_arr<1>(blocks, b, s, px, lut);
     else if (b.arrangement == 2) slot_texels_arr<2>(blocks, b, s, px, lut);
     else slot_texels_arr<0>(blocks, b, s, px, lut);
+}
+
+template <class Lut>
+__device__ __forceinline__ void slot_texels_batched(const uint8_t *blocks, const BandArgs &b, uint32_t s,
+                                                    uint32_t px[16], const Lut &lut)
+{
+    if (b.arrangement == 1) slot_texels_arr_batched<1>(blocks, b, s, px, lut);
+    else if (b.arrangement == 2) slot_texels_arr_batched<2>(blocks, b, s, px, lut);
+    else slot_texels_arr_batched<0>(blocks, b, s, px, lut);
 }
 
 __global__ __launch_bounds__(256) void k_decode(const uint8_t *blocks, BandArgs b, uint64_t nblk,
@@ -229,7 +237,7 @@ __device__ __forceinline__ void decode_eval_body(const uint8_t *blocks, const Ba
         if (j < m) {
             if (s < n_prims) {
                 uint32_t px[16];
-                slot_texels(blocks, b, s, px, Bc7PackedLut{lutw});
+                slot_texels_batched(blocks, b, s, px, Bc7PackedLut{lutw});
 #pragma unroll
                 for (int k = 0; k < 16; k++) {
                     const bool kept = band_coded(b, k);
@@ -409,8 +417,10 @@ __global__ __launch_bounds__(kEvalBlock) __attribute__((amdgpu_waves_per_eu(3)))
 // its primitive's position through perm, d = (f - p)/|f - p| (zero when
 // f = p), the 16 basis functions dotted with the decoded, dequantised texels
 // (FP32, k order).  s must be below the scene's n_prims.
+template <class Lut>
 __device__ __forceinline__ void view_colour(const uint8_t *blocks, const BandArgs &b, uint32_t s, const float *pos,
-                                            const uint32_t *perm, float fx, float fy, float fz, float c[3])
+                                            const uint32_t *perm, float fx, float fy, float fz, float c[3],
+                                            const Lut &lut)
 {
     const uint64_t pi = perm[s];
     float x = fx - pos[3 * pi], y = fy - pos[3 * pi + 1], z = fz - pos[3 * pi + 2];
@@ -442,7 +452,7 @@ __device__ __forceinline__ void view_colour(const uint8_t *blocks, const BandArg
     Y[14] = c3e * z * (xx - yy);
     Y[15] = -c3a * x * (xx - 3.0f * yy);
     uint32_t px[16];
-    slot_texels(blocks, b, s, px);
+    slot_texels(blocks, b, s, px, lut);
     c[0] = c[1] = c[2] = 0.0f;
 #pragma unroll
     for (int k = 0; k < 16; k++) {
@@ -453,17 +463,22 @@ __device__ __forceinline__ void view_colour(const uint8_t *blocks, const BandArg
     }
 }
 
-// One lane per listed slot; out-of-range slot ids give NaN.
+// One lane per listed slot; out-of-range slot ids give NaN.  The BC7
+// tables are read from the workgroup's LDS copy (the colour stage keeps
+// them in constant memory: there the LDS copy measured slower).
 __global__ __launch_bounds__(256) void k_decode_eval_view(const uint8_t *blocks, BandArgs b, const uint32_t *prim_idx,
                                                           uint64_t m, uint64_t n_prims, const float *pos,
                                                           const uint32_t *perm, float fx, float fy, float fz,
                                                           float *out)
 {
+    __shared__ uint32_t s_lut[kBc7LutWords];
+    if (threadIdx.x < kBc7LutWords) s_lut[threadIdx.x] = bc7_lut_word(threadIdx.x);
+    __syncthreads();
     const uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x;
     if (j >= m) return;
     const uint32_t s = prim_idx ? prim_idx[j] : (uint32_t)j;
     float c[3] = {__builtin_nanf(""), __builtin_nanf(""), __builtin_nanf("")};
-    if (s < n_prims) view_colour(blocks, b, s, pos, perm, fx, fy, fz, c);
+    if (s < n_prims) view_colour(blocks, b, s, pos, perm, fx, fy, fz, c, Bc7PackedLut{s_lut});
     out[3 * j] = c[0];
     out[3 * j + 1] = c[1];
     out[3 * j + 2] = c[2];
@@ -542,7 +557,7 @@ __global__ __launch_bounds__(256) void k_blend_tiles(const uint8_t *blocks, Band
                     c[1] = colours[3 * (uint64_t)s + 1];
                     c[2] = colours[3 * (uint64_t)s + 2];
                 } else {
-                    view_colour(blocks, b, s, pos, perm, fx, fy, fz, c);
+                    view_colour(blocks, b, s, pos, perm, fx, fy, fz, c, Bc7ConstLut{});
                 }
                 i = perm[s];
             }
