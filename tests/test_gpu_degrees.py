@@ -44,7 +44,9 @@ MIX = (0.35, 0.2, 0.15, 0.3)
 @pytest.mark.parametrize("n,seed,mix,small,tau,pre", [
     (1, 1, MIX, 0.0, 0.0, False), (17, 2, MIX, 0.0, 0.0, False), (4101, 3, MIX, 0.0, 0.0, False),
     (4101, 4, MIX, 1e-4, 1e-4, False), (4101, 5, MIX, 1e-4, 0.0, False), (20_000, 6, (0.5, 0.0, 0.5, 0.0), 0.0, 0.0, False),
-    (65_536, 7, MIX, 1e-4, 1e-4, True), (3000, 8, None, 0.0, 0.0, False)])
+    (65_536, 7, MIX, 1e-4, 1e-4, True), (3000, 8, None, 0.0, 0.0, False),
+    # SH rows past 256 MiB: the range pass streams them (non-temporal loads)
+    (1_500_000, 13, MIX, 1e-4, 1e-4, False)])
 def test_reorder_degrees_bit_exact(G, n, seed, mix, small, tau, pre):
     gsbc, ctx = G
     pos, sh = synth.make_scene(n, seed=seed, degree_mix=mix, small=small)
