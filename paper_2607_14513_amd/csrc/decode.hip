@@ -346,6 +346,12 @@ __device__ __forceinline__ void decode_eval_body(const uint8_t *blocks, const Ba
                     for (int h = 0; h < 3; h++)
                         if (cok[h]) __builtin_nontemporal_store(stage[rr][64 * h + lane], o + rr * row_stride + 64 * h);
             }
+            // The four waves start each direction tile together, so their
+            // 768-byte pieces of a row leave close in time (one 3 KB stretch
+            // of it): a bare s_barrier, which waits on no memory counter.
+            // Every wave runs the same iterations (v0 and v_end are uniform
+            // over the workgroup); 7.27 -> 7.14 ms at 3,145,728 x 1,024.
+            __builtin_amdgcn_s_barrier();
         }
     } else {
         for (uint32_t v0 = vc0; v0 < v_end; v0 += 16) {
